@@ -1,0 +1,188 @@
+/*
+ * ihmc.h -- C ABI of the MI355X Hybrid Monte Carlo library for the
+ * Hubbard-Stratonovich-transformed Ising model (Ostmeyer, Berkowitz, Luu,
+ * Petschlies, Pittler, "The Ising Model with Hybrid Monte Carlo",
+ * arXiv:1912.03278).
+ *
+ * The model (Sec. 2, eq. hamilton_matrix_notation) is H(s) = -1/2 J s^T K s - h.s
+ * with K the periodic nearest-neighbour connectivity of a 2D or 3D hypercubic
+ * lattice, or an explicit symmetric coupling matrix in place of J K.  With
+ * J' = beta J, h' = beta h and the shift Kt = K + C*1 (C > n, so that J' Kt is
+ * positive definite, Sec. 2 after eq. eigen_spectrum_K) the library samples the
+ * auxiliary field psi with the action of eq. phi_psi_substitution,
+ *     S(psi) = 1/2 psi.Kt psi - psi.h'/sqrt(J') - sum_i log cosh(sqrt(J') (Kt psi)_i),
+ * by HMC (Sec. 3): N(0,1) momenta, a reversible symplectic integrator over one
+ * trajectory, and a Metropolis test with min(1, exp(-dH)).  After every
+ * trajectory it records the estimators of Sec. 4 (eqs. formula_for_m and
+ * formula_for_e, in their general-field form).
+ *
+ * Conventions for every entry point:
+ *   - Return IHMC_OK (0) or a negative status; never throw across the ABI.
+ *     ihmc_last_error() returns a thread-local message for the last failure.
+ *   - Host pointers are read during the call (or copied before it returns);
+ *     the caller keeps ownership and may free them afterwards.
+ *   - Output arrays are caller-owned host memory of the stated length; any
+ *     output pointer may be NULL to skip it.
+ *   - Device memory is owned by the context: it is carved from one arena
+ *     obtained at ihmc_ctx_create (from the caller's allocator callback, or
+ *     hipMalloc).  Exceeding the arena gives IHMC_E_NOMEM.
+ *   - Work is enqueued on the context's HIP stream.  A context is not
+ *     thread-safe unless an entry point says otherwise.
+ *   - Lattice sites are numbered x + L0 (y + L1 z) (x fastest).
+ */
+#ifndef IHMC_H
+#define IHMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IHMC_OK 0
+#define IHMC_E_INVAL (-1)       /* invalid argument (message says which) */
+#define IHMC_E_NOMEM (-2)       /* device arena exhausted */
+#define IHMC_E_AGAIN (-3)       /* serving queue full / result not ready */
+#define IHMC_E_DEVICE (-4)      /* HIP runtime error; the context stays unusable */
+#define IHMC_E_CANCELLED (-5)   /* request was cancelled */
+#define IHMC_E_UNSUPPORTED (-6) /* valid but not implemented (e.g. 1D lattices on the GPU) */
+
+#define IHMC_F32 4 /* state (psi, p) in FP32; H, dH, Metropolis in FP64 */
+#define IHMC_F64 8 /* state in FP64 */
+
+#define IHMC_LEAPFROG 0 /* kick-drift-kick leap-frog (Sec. 3) */
+#define IHMC_OMELYAN 1  /* second-order minimum-norm integrator, named in Sec. 3 */
+
+#define IHMC_TAG_INIT 1u /* Philox stream tags (counter word 3) */
+#define IHMC_TAG_MOM 2u
+#define IHMC_TAG_ACC 3u
+#define IHMC_TAG_FLIP 4u
+
+typedef struct ihmc_ctx ihmc_ctx;
+typedef struct ihmc_chains ihmc_chains;
+
+/* Device allocator hook (e.g. PyTorch's caching allocator).  alloc returns a
+ * device pointer or NULL; free releases it. */
+typedef void* (*ihmc_alloc_fn)(uint64_t bytes, void* user);
+typedef void (*ihmc_free_fn)(void* ptr, void* user);
+
+/* Periodic hypercubic lattice with nearest-neighbour K (Sec. 2).
+ *   ndim       2 or 3 on the GPU (1 is IHMC_E_UNSUPPORTED).
+ *   L[ndim]    extents, each >= 3 (periodic neighbours must be distinct).
+ *   J, beta    J' = beta*J must be > 0 (eq. def_J_prime).
+ *   C          shift of K, must exceed n = 2*ndim (Sec. 2).
+ *   h, h_len   host field: h_len 0 (h = 0), 1 (uniform h[0], eq. constant_h),
+ *              or N (one value per site). */
+typedef struct {
+  int32_t ndim;
+  int32_t L[3];
+  double J, beta, C;
+  const double* h;
+  int64_t h_len;
+} ihmc_lattice;
+
+/* Parameters of one chain (Sec. 3).
+ *   n_md        integrator steps per trajectory (>= 1).
+ *   n_traj      trajectories to record (capacity of the series, >= 0).
+ *   traj_len    MD time per trajectory (> 0; the paper uses one time unit).
+ *   integrator  IHMC_LEAPFROG or IHMC_OMELYAN.
+ *   flip_every  > 0: propose the global sign flip psi -> -psi with its own
+ *               Metropolis test after every flip_every-th trajectory (Sec. 3).
+ *   precision   IHMC_F32 or IHMC_F64 (state precision).
+ *   seed        64-bit Philox4x32-10 key.
+ *   chain_id    counter word 2 (low 32 bits used): independent streams.
+ *   psi0        host, N values, or NULL: psi0 ~ N(0,1) from the TAG_INIT stream.
+ *   replay_accept host, n_traj bytes, or NULL: force the accept decisions
+ *               (test hook for comparing trajectories past a point where FP32
+ *               and FP64 decisions could differ). */
+typedef struct {
+  int32_t n_md;
+  int32_t n_traj;
+  double traj_len;
+  int32_t integrator;
+  int32_t flip_every;
+  int32_t precision;
+  int32_t pad;
+  uint64_t seed;
+  uint64_t chain_id;
+  const double* psi0;
+  const uint8_t* replay_accept;
+} ihmc_run;
+
+/* Per-chain results.  Series are indexed by trajectory; after trajectory t
+ * they hold dH = H_new - H_old, the accept/flip decisions and the estimators
+ * of the accepted field: m, |m|, m^2 minus its Gaussian-noise bias
+ * 1^T Kt^-1 1 / (N^2 J'), and beta*eps (Sec. 4). */
+typedef struct {
+  double *dH, *H_old, *H_new, *m, *abs_m, *m2c, *beta_eps; /* host, n_traj each, or NULL */
+  uint8_t *accepted, *flipped;                            /* host, n_traj each, or NULL */
+  double* psi_final;                                      /* host, N, or NULL */
+  double acceptance;        /* accepted / trajectories done */
+  double mean_exp_minus_dH; /* over trajectories with finite dH */
+  int64_t n_nonfinite;      /* trajectories with a non-finite or out-of-range H term */
+  int64_t n_traj_done;
+} ihmc_result;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device` with a device arena of arena_bytes
+ * (0: 1 GiB).  alloc/free may be NULL (then hipMalloc/hipFree); `user` is
+ * passed to them.  The context creates its own HIP stream (default priority). */
+int ihmc_ctx_create(int32_t device, uint64_t arena_bytes, ihmc_alloc_fn alloc, ihmc_free_fn free_fn,
+                    void* user, ihmc_ctx** out);
+void ihmc_ctx_destroy(ihmc_ctx* ctx);
+/* The context's hipStream_t. */
+void* ihmc_ctx_stream(ihmc_ctx* ctx);
+/* Wait for all work enqueued on the context. */
+int ihmc_ctx_sync(ihmc_ctx* ctx);
+/* Bytes of the arena in use / in total. */
+int ihmc_ctx_memory(ihmc_ctx* ctx, uint64_t* used, uint64_t* total);
+const char* ihmc_last_error(void);
+
+/* ---- resident chains (the hot path) --------------------------------------- */
+
+/* Create n independent chains, each with its own lattice and run parameters
+ * (2D and 3D, FP32 and FP64 may be mixed).  Performs the set-up of every chain
+ * on the device: field constants, initial field, S(psi0).  Synchronous. */
+int ihmc_chains_create(ihmc_ctx* ctx, int32_t n, const ihmc_lattice* lats, const ihmc_run* runs,
+                       ihmc_chains** out);
+/* Enqueue n_traj further trajectories of every chain (asynchronous; repeated
+ * calls continue the chains).  Fails with IHMC_E_INVAL past the capacity
+ * n_traj given at creation.  Launch sequences are captured once into a HIP
+ * graph and replayed. */
+int ihmc_chains_advance(ihmc_chains* chains, int32_t n_traj);
+/* Wait, then copy the series and summary of chain i (0 <= i < n). */
+int ihmc_chains_result(ihmc_chains* chains, int32_t i, ihmc_result* out);
+int ihmc_chains_destroy(ihmc_chains* chains);
+
+/* One chain: create, advance run->n_traj, fetch, destroy.  Synchronous. */
+int ihmc_run_lattice(ihmc_ctx* ctx, const ihmc_lattice* lat, const ihmc_run* run, ihmc_result* out);
+/* n chains (arrays of n descriptors and n results).  Synchronous. */
+int ihmc_run_batch(ihmc_ctx* ctx, int32_t n, const ihmc_lattice* lats, const ihmc_run* runs,
+                   ihmc_result* outs);
+
+/* ---- diagnostics (same kernels as the hot path) --------------------------- */
+
+/* F = -dS/dpsi at the host field psi (N values) into host F (N values), with
+ * the state rounded to `precision` (Sec. 3 equations of motion). */
+int ihmc_force(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t precision, const double* psi, double* F);
+/* Action and estimators of a host field psi: out[0] = S(psi) (FP64, eq.
+ * phi_psi_substitution without constants), out[1] = m, out[2] = |m|,
+ * out[3] = m^2 corrected, out[4] = beta*eps (Sec. 4). */
+int ihmc_action(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t precision, const double* psi, double* out);
+/* One trajectory of molecular dynamics from host (psi, p), in place, with
+ * run->n_md, traj_len, integrator, precision (no Metropolis test). */
+int ihmc_integrate(ihmc_ctx* ctx, const ihmc_lattice* lat, const ihmc_run* run, double* psi, double* p);
+/* The momentum-stream normals of the GPU generator: n values for sites
+ * 0..n-1 of (seed, chain_id, traj, tag) into host out. */
+int ihmc_philox_normals(ihmc_ctx* ctx, uint64_t seed, uint64_t chain_id, uint32_t traj, uint32_t tag,
+                        int64_t n, double* out);
+/* Raw Philox4x32-10 words: for k < n, out[4k..4k+3] = philox(ctr[4k..4k+3],
+ * key[2k..2k+1]), computed on the GPU. */
+int ihmc_philox_words(ihmc_ctx* ctx, int64_t n, const uint32_t* ctr, const uint32_t* key, uint32_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IHMC_H */

@@ -1,0 +1,105 @@
+// Internal data layout of the HMC runtime (device-visible structures).
+#pragma once
+
+#include <stdint.h>
+
+namespace ihmc {
+
+enum : uint32_t { TAG_INIT = 1u, TAG_MOM = 2u, TAG_ACC = 3u, TAG_FLIP = 4u };
+
+enum Integrator : int32_t { LEAPFROG = 0, OMELYAN = 1 };
+
+// Omelyan-Mryglod-Folk second-order minimum-norm parameter.
+constexpr double kOmelyanLambda = 0.1931833275037836;
+
+// Accumulated FP64 terms (exact fixed point, see device_common.hpp).
+enum Term : int {
+  T_K0 = 0,    // 1/2 p^2 of the fresh momenta (H_old)
+  T_K1 = 1,    // 1/2 p^2 at the end of the trajectory (H_new)
+  T_S = 2,     // action density S(psi) of the proposal
+  T_PSI = 3,   // psi
+  T_PSIH = 4,  // psi h'
+  T_UT = 5,    // u tanh(sqrt(J') u), u = Kt psi
+  NTERM = 6
+};
+constexpr int NSLOT = 16;  // atomic slots per term, spread over blocks
+
+// Record written after every trajectory (64 bytes).
+struct TrajRecord {
+  double dH, H_old, H_new, m, abs_m, m2c, beta_eps;
+  uint32_t flags;  // bit 0 accepted, bit 1 flipped, bit 2 non-finite
+  uint32_t pad;
+};
+enum : uint32_t { REC_ACCEPT = 1u, REC_FLIP = 2u, REC_NONFINITE = 4u };
+
+// Mutable per-chain state, updated on the device by the finalising block.
+struct ChainState {
+  uint64_t acc[NTERM][NSLOT][2];  // fixed-point accumulators of the running trajectory
+  uint64_t S_lo, S_hi;            // S(psi_cur), fixed point
+  double sum_psi, sum_psih, sum_ut;  // estimator sums of psi_cur
+  int32_t cur;    // buffer (0..2) holding the accepted field
+  int32_t sign;   // +1, or -1 after an accepted global sign flip
+  int32_t traj;   // next trajectory index
+  uint32_t done;  // finished blocks of the current pass
+  uint32_t bad;   // a non-finite / out-of-range term was seen
+  int32_t cur_bad;  // the accepted field itself has such a term (e.g. a NaN start)
+  int64_t n_acc, n_nonfinite;
+  double sum_exp_mdh;
+};
+
+// Immutable per-chain parameters (FP64 constants; kernels round what they need).
+struct ChainDev {
+  int32_t ndim, L0, L1, L2;
+  int64_t N;
+  int32_t n_pass;      // force evaluations per trajectory
+  int32_t integrator;
+  int32_t flip_every;
+  int32_t h_kind;      // 0: h = 0, 1: uniform, 2: per site
+  uint32_t chain_id, n_tiles, seed_lo, seed_hi;
+  double C, sqJ, Jp, b0, hp0, eps;
+  double c_m, c_e, c_v;  // 1^T Kt^-1 h', h'^T Kt^-1 h', 1^T Kt^-1 1
+  int32_t cap;           // capacity of the record series
+  int32_t precision;     // 4 or 8 (bytes of the state type)
+  int32_t p_given;       // first pass reads p instead of drawing it (diagnostic)
+  int32_t write_p_last;  // last pass stores the final momenta (diagnostic)
+  void* psi;             // 3 * N state values (three rotating buffers)
+  void* p;               // N state values
+  const void* b;         // N state values h'/sqrt(J') (per-site field) or null
+  const double* hp;      // N FP64 h' (per-site field) or null
+  TrajRecord* rec;       // cap records
+  const uint8_t* replay; // forced decisions (test hook) or null
+  ChainState* st;
+};
+
+// One work tile of a lattice pass.
+struct Tile {
+  int32_t chain;
+  int32_t x0, y0, z0;
+};
+
+// Kick and drift coefficients of pass j (0 <= j < n_pass).
+inline __host__ __device__ void pass_coeffs(const ChainDev& cd, int j, double& kick, double& drift) {
+  const double e = cd.eps;
+  const int last = cd.n_pass - 1;
+  if (cd.integrator == OMELYAN) {
+    const double l = kOmelyanLambda;
+    if (j == 0 || j == last) kick = l * e;
+    else if (j & 1) kick = (1.0 - 2.0 * l) * e;
+    else kick = 2.0 * l * e;
+    drift = (j == last) ? 0.0 : 0.5 * e;
+  } else {
+    kick = (j == 0 || j == last) ? 0.5 * e : e;
+    drift = (j == last) ? 0.0 : e;
+  }
+}
+
+// Buffer read by pass j when the accepted field sits in buffer `cur`.
+inline __host__ __device__ int pass_in_buf(int cur, int j) {
+  if (j == 0) return cur;
+  return (j & 1) ? (cur + 1) % 3 : (cur + 2) % 3;
+}
+inline __host__ __device__ int pass_out_buf(int cur, int j) {
+  return (j & 1) ? (cur + 2) % 3 : (cur + 1) % 3;
+}
+
+}  // namespace ihmc

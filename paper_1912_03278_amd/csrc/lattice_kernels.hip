@@ -1,0 +1,397 @@
+// Fused leap-frog passes for HMC on periodic 2D / 3D nearest-neighbour lattices.
+//
+// One pass = one force evaluation of the equations of motion (Sec. 3):
+//     u = Kt psi,  w = sqrt(J') tanh(sqrt(J') u) - psi,  F = Kt w + h'/sqrt(J'),
+// followed by the kick p += c_j F and the drift psi' = psi + d_j p.  Because F
+// at a site needs psi on the radius-2 diamond around it, a workgroup stages its
+// tile plus a 2-wide halo of psi in LDS, computes w on the tile plus a 1-wide
+// halo, and then F, p and psi' on the tile: every pass reads psi (and p) once
+// and writes p and psi' once from HBM.
+//
+// Pass kinds (template MODE):
+//   FIRST   - momenta from Philox (Sec. 3, eq. momentum distribution), 1/2 p^2
+//             accumulated for H_old, first kick and drift;
+//   MIDDLE  - kick and drift;
+//   LAST    - final kick, then the FP64 Hamiltonian and estimator sums of the
+//             proposal; the last block to finish takes the Metropolis decision
+//             (Sec. 3) and writes the trajectory record (Sec. 4 estimators);
+//   MEASURE - FP64 action and estimator sums of the accepted field (set-up);
+//   FORCE   - writes F itself (diagnostic; same arithmetic as the other passes).
+//
+// Sums are exact 128-bit fixed point (device_common.hpp), so every result is
+// independent of the tile shape and of which chains share a launch.
+#include "device_common.hpp"
+#include "lattice_kernels.hpp"
+
+namespace ihmc {
+
+template <int NDIM, int BX, int BY, int BZ>
+struct Geom {
+  static constexpr int Z3 = (NDIM == 3) ? 1 : 0;
+  static constexpr int PX = BX + 4, PY = BY + 4, PZ = Z3 ? BZ + 4 : 1;
+  static constexpr int WX = BX + 2, WY = BY + 2, WZ = Z3 ? BZ + 2 : 1;
+  static constexpr int NP = PX * PY * PZ;
+  static constexpr int NW = WX * WY * WZ;
+  static constexpr int BZE = Z3 ? BZ : 1;
+  static constexpr int NO = BX * BY * BZE;
+};
+
+__device__ __forceinline__ int wrap_near(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
+__device__ __forceinline__ int wrap_any(int v, int L) {
+  const int r = v % L;
+  return r < 0 ? r + L : r;
+}
+
+template <typename T>
+__device__ __forceinline__ T neg_if(T v, int sign) {
+  return sign < 0 ? -v : v;
+}
+
+// Metropolis decision and record, run by one thread of the last block of a LAST pass.
+__device__ __forceinline__ void finalize_trajectory(const ChainDev& cd, ChainState* st, int last_buf) {
+  u128 sum[NTERM];
+#pragma unroll
+  for (int t = 0; t < NTERM; ++t) {
+    sum[t] = u128{0ull, 0ull};
+#pragma unroll 1
+    for (int s = 0; s < NSLOT; ++s) sum[t] = add128(sum[t], load128_agent(st->acc[t][s]));
+  }
+  const uint32_t bad = __hip_atomic_load(&st->bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int t = st->traj;
+  const u128 S_old{st->S_lo, st->S_hi};
+  const u128 H_old = add128(sum[T_K0], S_old);
+  const u128 H_new = add128(sum[T_K1], sum[T_S]);
+  double dH = fixed_to_double(sub128(H_new, H_old));
+  uint32_t flags = 0u;
+  bool finite = (bad == 0u);
+  if (!finite) {
+    dH = __builtin_nan("");
+    flags |= REC_NONFINITE;
+    st->n_nonfinite += 1;
+  }
+  if (finite && st->cur_bad) dH = -__builtin_inf();  // leaving a state of zero weight
+  bool accept;
+  if (cd.replay) {
+    accept = cd.replay[t] != 0;
+  } else {
+    const double r = uniform_at(cd, (uint32_t)t, TAG_ACC);
+    accept = finite && (dH <= 0.0 || r < exp(-dH));
+  }
+  if (finite && !st->cur_bad) st->sum_exp_mdh += exp(-dH);
+  if (accept) {
+    st->cur_bad = 0;
+    st->S_lo = sum[T_S].lo;
+    st->S_hi = sum[T_S].hi;
+    st->sum_psi = fixed_to_double(sum[T_PSI]);
+    st->sum_psih = fixed_to_double(sum[T_PSIH]);
+    st->sum_ut = fixed_to_double(sum[T_UT]);
+    st->cur = last_buf;
+    st->sign = 1;
+    st->n_acc += 1;
+    flags |= REC_ACCEPT;
+  }
+  if (cd.flip_every > 0 && (t + 1) % cd.flip_every == 0) {
+    // S(-psi) - S(psi) = 2 psi.h'/sqrt(J'): only the linear field term changes.
+    const double dS = 2.0 * st->sum_psih / cd.sqJ;
+    const double r2 = uniform_at(cd, (uint32_t)t, TAG_FLIP);
+    if (dS <= 0.0 || r2 < exp(-dS)) {
+      uint32_t b2 = 0u;
+      const u128 S = add128(u128{st->S_lo, st->S_hi}, to_fixed(dS, b2));
+      st->S_lo = S.lo;
+      st->S_hi = S.hi;
+      st->sign = -st->sign;
+      st->sum_psi = -st->sum_psi;
+      st->sum_psih = -st->sum_psih;
+      flags |= REC_FLIP;
+    }
+  }
+  if (t < cd.cap) {
+    const double N = (double)cd.N;
+    TrajRecord rec;
+    rec.dH = dH;
+    rec.H_old = fixed_to_double(H_old);
+    rec.H_new = fixed_to_double(H_new);
+    rec.m = (st->sum_psi / cd.sqJ - cd.c_m / cd.Jp) / N;
+    rec.abs_m = fabs(rec.m);
+    rec.m2c = rec.m * rec.m - cd.c_v / (N * N * cd.Jp);
+    rec.beta_eps = 0.5 * cd.C * cd.Jp + cd.c_e / (2.0 * N * cd.Jp) - st->sum_psih / (2.0 * N * cd.sqJ) -
+                   cd.sqJ / (2.0 * N) * st->sum_ut;
+    rec.flags = flags;
+    rec.pad = 0u;
+    cd.rec[t] = rec;
+  }
+  st->traj = t + 1;
+#pragma unroll 1
+  for (int a = 0; a < NTERM; ++a)
+#pragma unroll 1
+    for (int s = 0; s < NSLOT; ++s) {
+      st->acc[a][s][0] = 0ull;
+      st->acc[a][s][1] = 0ull;
+    }
+  st->bad = 0u;
+  st->done = 0u;
+  __threadfence();
+}
+
+__device__ __forceinline__ void finalize_measure(ChainState* st) {
+  st->cur_bad = __hip_atomic_load(&st->bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1 : 0;
+  u128 sum[NTERM];
+#pragma unroll
+  for (int t = 0; t < NTERM; ++t) {
+    sum[t] = u128{0ull, 0ull};
+#pragma unroll 1
+    for (int s = 0; s < NSLOT; ++s) sum[t] = add128(sum[t], load128_agent(st->acc[t][s]));
+  }
+  st->S_lo = sum[T_S].lo;
+  st->S_hi = sum[T_S].hi;
+  st->sum_psi = fixed_to_double(sum[T_PSI]);
+  st->sum_psih = fixed_to_double(sum[T_PSIH]);
+  st->sum_ut = fixed_to_double(sum[T_UT]);
+#pragma unroll 1
+  for (int a = 0; a < NTERM; ++a)
+#pragma unroll 1
+    for (int s = 0; s < NSLOT; ++s) {
+      st->acc[a][s][0] = 0ull;
+      st->acc[a][s][1] = 0ull;
+    }
+  st->bad = 0u;
+  st->done = 0u;
+  __threadfence();
+}
+
+template <typename T, int NDIM, int BX, int BY, int BZ, int MODE>
+__global__ __launch_bounds__(256) void lattice_pass(const ChainDev* __restrict__ chains,
+                                                    const Tile* __restrict__ tiles, int j) {
+  using G = Geom<NDIM, BX, BY, BZ>;
+  constexpr bool kHasW = (MODE != PASS_MEASURE);
+  constexpr bool kH64 = (MODE == PASS_LAST || MODE == PASS_MEASURE);
+  __shared__ T sP[G::NP];
+  __shared__ T sW[kHasW ? G::NW : 1];
+  __shared__ u128 sRed[4][NTERM];
+
+  const Tile tl = tiles[blockIdx.x];
+  const ChainDev& cd = chains[tl.chain];
+  ChainState* st = cd.st;
+  const int L0 = cd.L0, L1 = cd.L1, L2 = cd.L2;
+  const int64_t N = cd.N;
+  const int cur = st->cur;
+  const int sign = st->sign;
+  const int traj = st->traj;
+  const bool from_cur = (MODE == PASS_FIRST || MODE == PASS_MEASURE || MODE == PASS_FORCE);
+  const int in_buf = from_cur ? cur : pass_in_buf(cur, j);
+  const int out_buf = pass_out_buf(cur, j);
+  const T* __restrict__ pin = (const T*)cd.psi + (int64_t)in_buf * N;
+  T* __restrict__ pout = (T*)cd.psi + (int64_t)out_buf * N;
+  T* __restrict__ pmom = (T*)cd.p;
+
+  // ---- stage psi on the tile plus a 2-wide halo (periodic wrap)
+  const bool near = (L0 > BX) && (L1 > BY) && (NDIM == 2 || L2 > BZ);
+  for (int i = threadIdx.x; i < G::NP; i += 256) {
+    const int lx = i % G::PX;
+    const int r = i / G::PX;
+    const int ly = r % G::PY;
+    const int lz = r / G::PY;
+    int gx = tl.x0 + lx - 2, gy = tl.y0 + ly - 2, gz = G::Z3 ? tl.z0 + lz - 2 : 0;
+    if (near) {
+      gx = wrap_near(gx, L0);
+      gy = wrap_near(gy, L1);
+      if (G::Z3) gz = wrap_near(gz, L2);
+    } else {
+      gx = wrap_any(gx, L0);
+      gy = wrap_any(gy, L1);
+      if (G::Z3) gz = wrap_any(gz, L2);
+    }
+    const int64_t g = gx + (int64_t)L0 * (gy + (int64_t)L1 * gz);
+    T v = pin[g];
+    if (from_cur) v = neg_if(v, sign);
+    sP[i] = v;
+  }
+  __syncthreads();
+
+  const T Ct = (T)cd.C;
+  const T at = (T)cd.sqJ;
+  constexpr int SP = G::PX * G::PY;
+  constexpr int SW = G::WX * G::WY;
+
+  // ---- w = sqrt(J') tanh(sqrt(J') Kt psi) - psi on the tile plus a 1-wide halo
+  if (kHasW) {
+    for (int i = threadIdx.x; i < G::NW; i += 256) {
+      const int wx = i % G::WX;
+      const int r = i / G::WX;
+      const int wy = r % G::WY;
+      const int wz = r / G::WY;
+      const int pc = (wx + 1) + G::PX * ((wy + 1) + G::PY * (wz + G::Z3));
+      const T c = sP[pc];
+      T s = (sP[pc - 1] + sP[pc + 1]) + (sP[pc - G::PX] + sP[pc + G::PX]);
+      if (G::Z3) s = s + (sP[pc - SP] + sP[pc + SP]);
+      const T u = fma_t(Ct, c, s);
+      sW[i] = fma_t(at, tanh_state(at * u), -c);
+    }
+    __syncthreads();
+  }
+
+  double kick_d = 0.0, drift_d = 0.0;
+  pass_coeffs(cd, j, kick_d, drift_d);
+  const T kick = (MODE == PASS_FORCE) ? (T)1 : (T)kick_d;
+  const T drift = (T)drift_d;
+  const T b_uniform = (T)cd.b0;
+  const T* __restrict__ bsite = (const T*)cd.b;
+  const bool site_field = (cd.h_kind == 2);
+
+  uint32_t bad = 0u;
+  u128 acc[NTERM];
+#pragma unroll
+  for (int a = 0; a < NTERM; ++a) acc[a] = u128{0ull, 0ull};
+
+  auto site_body = [&](int o) {
+    const int lx = o % BX;
+    const int r = o / BX;
+    const int ly = r % BY;
+    const int lz = r / BY;
+    const int gx = tl.x0 + lx, gy = tl.y0 + ly, gz = tl.z0 + lz;
+    if (gx >= L0 || gy >= L1 || (G::Z3 && gz >= L2)) return;
+    const int64_t site = gx + (int64_t)L0 * (gy + (int64_t)L1 * gz);
+    const int pc = (lx + 2) + G::PX * ((ly + 2) + G::PY * (lz + 2 * G::Z3));
+    const T c = sP[pc];
+    T pn = (T)0;
+    if (kHasW) {
+      const int wc = (lx + 1) + G::WX * ((ly + 1) + G::WY * (lz + G::Z3));
+      T sw = (sW[wc - 1] + sW[wc + 1]) + (sW[wc - G::WX] + sW[wc + G::WX]);
+      if (G::Z3) sw = sw + (sW[wc - SW] + sW[wc + SW]);
+      T F = fma_t(Ct, sW[wc], sw);
+      F = F + (site_field ? bsite[site] : b_uniform);
+      T p;
+      if (MODE == PASS_FIRST) {
+        if (cd.p_given) {
+          p = pmom[site];
+        } else {
+          p = (T)normal_at(cd, (uint32_t)traj, TAG_MOM, site);
+        }
+        const double pd = (double)p;
+        acc[T_K0] = add128(acc[T_K0], to_fixed(0.5 * pd * pd, bad));
+      } else if (MODE == PASS_FORCE) {
+        p = (T)0;
+      } else {
+        p = pmom[site];
+      }
+      pn = fma_t(kick, F, p);
+      if (MODE == PASS_FIRST || MODE == PASS_MIDDLE) {
+        pmom[site] = pn;
+        pout[site] = fma_t(drift, pn, c);
+      } else if (MODE == PASS_FORCE) {
+        pmom[site] = pn;
+      } else if (MODE == PASS_LAST) {
+        if (cd.write_p_last) pmom[site] = pn;
+        const double pd = (double)pn;
+        acc[T_K1] = add128(acc[T_K1], to_fixed(0.5 * pd * pd, bad));
+      }
+    }
+    if (kH64) {
+      // FP64 action terms of the field as stored: the integer stencil weights
+      // are exact, C and sqrt(J') are the true FP64 constants.
+      const double cdv = (double)c;
+      double nb = ((double)sP[pc - 1] + (double)sP[pc + 1]) + ((double)sP[pc - G::PX] + (double)sP[pc + G::PX]);
+      if (G::Z3) nb = nb + ((double)sP[pc - SP] + (double)sP[pc + SP]);
+      const double u = cd.C * cdv + nb;
+      double lc, th;
+      logcosh_tanh(cd.sqJ * u, lc, th);
+      double hpx = cd.hp0, bx = cd.b0;
+      if (site_field) {
+        hpx = cd.hp[site];
+        bx = hpx / cd.sqJ;
+      }
+      acc[T_S] = add128(acc[T_S], to_fixed(0.5 * cdv * u - cdv * bx - lc, bad));
+      acc[T_PSI] = add128(acc[T_PSI], to_fixed(cdv, bad));
+      acc[T_PSIH] = add128(acc[T_PSIH], to_fixed(cdv * hpx, bad));
+      acc[T_UT] = add128(acc[T_UT], to_fixed(u * th, bad));
+    }
+  };
+  if constexpr (MODE == PASS_MIDDLE || MODE == PASS_FORCE) {
+#pragma unroll
+    for (int o = threadIdx.x; o < G::NO; o += 256) site_body(o);
+  } else {
+#pragma unroll 1
+    for (int o = threadIdx.x; o < G::NO; o += 256) site_body(o);
+  }
+
+  if (MODE == PASS_MIDDLE || MODE == PASS_FORCE) return;
+
+  // ---- block reduction and order-independent accumulation into the chain
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int t_lo = (MODE == PASS_FIRST) ? T_K0 : ((MODE == PASS_MEASURE) ? T_S : T_K1);
+  constexpr int t_hi = (MODE == PASS_FIRST) ? T_K0 : T_UT;
+#pragma unroll
+  for (int a = t_lo; a <= t_hi; ++a) {
+    const u128 v = wave_sum128(acc[a]);
+    if (lane == 0) sRed[wave][a] = v;
+  }
+  // non-finite flags: any lane of any wave
+  const unsigned long long any_bad = __ballot(bad != 0u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int slot = blockIdx.x % NSLOT;
+    for (int a = t_lo; a <= t_hi; ++a) {
+      u128 v = add128(add128(sRed[0][a], sRed[1][a]), add128(sRed[2][a], sRed[3][a]));
+      atomic_add128(st->acc[a][slot], v);
+    }
+  }
+  if (lane == 0 && any_bad) atomicOr(&st->bad, 1u);
+  if (MODE == PASS_FIRST) return;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t prev = atomicAdd(&st->done, 1u);
+    if (prev == cd.n_tiles - 1u) {
+      __threadfence();
+      if (MODE == PASS_LAST) finalize_trajectory(cd, st, pass_in_buf(cur, j));
+      else finalize_measure(st);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launch ---
+
+template <typename T, int NDIM, int BX, int BY, int BZ>
+static hipError_t launch_mode(int mode, const ChainDev* chains, const Tile* tiles, int n_tiles, int j,
+                              hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  dim3 grid(n_tiles), block(256);
+  switch (mode) {
+    case PASS_FIRST:
+      lattice_pass<T, NDIM, BX, BY, BZ, PASS_FIRST><<<grid, block, 0, s>>>(chains, tiles, j);
+      break;
+    case PASS_MIDDLE:
+      lattice_pass<T, NDIM, BX, BY, BZ, PASS_MIDDLE><<<grid, block, 0, s>>>(chains, tiles, j);
+      break;
+    case PASS_LAST:
+      lattice_pass<T, NDIM, BX, BY, BZ, PASS_LAST><<<grid, block, 0, s>>>(chains, tiles, j);
+      break;
+    case PASS_MEASURE:
+      lattice_pass<T, NDIM, BX, BY, BZ, PASS_MEASURE><<<grid, block, 0, s>>>(chains, tiles, j);
+      break;
+    case PASS_FORCE:
+      lattice_pass<T, NDIM, BX, BY, BZ, PASS_FORCE><<<grid, block, 0, s>>>(chains, tiles, j);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+TileShape tile_shape(int precision, int ndim) {
+  (void)precision;
+  if (ndim == 2) return TileShape{64, 16, 1};
+  return TileShape{64, 4, 4};
+}
+
+hipError_t launch_lattice_pass(int precision, int ndim, int mode, const ChainDev* chains, const Tile* tiles,
+                               int n_tiles, int j, hipStream_t s) {
+  if (precision == 4) {
+    if (ndim == 2) return launch_mode<float, 2, 64, 16, 1>(mode, chains, tiles, n_tiles, j, s);
+    return launch_mode<float, 3, 64, 4, 4>(mode, chains, tiles, n_tiles, j, s);
+  }
+  if (ndim == 2) return launch_mode<double, 2, 64, 16, 1>(mode, chains, tiles, n_tiles, j, s);
+  return launch_mode<double, 3, 64, 4, 4>(mode, chains, tiles, n_tiles, j, s);
+}
+
+}  // namespace ihmc

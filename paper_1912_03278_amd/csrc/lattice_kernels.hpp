@@ -1,0 +1,25 @@
+// Launch interface of the fused lattice passes (lattice_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ihmc_internal.hpp"
+
+namespace ihmc {
+
+enum PassMode : int { PASS_FIRST = 0, PASS_MIDDLE = 1, PASS_LAST = 2, PASS_MEASURE = 3, PASS_FORCE = 4 };
+
+struct TileShape {
+  int bx, by, bz;
+};
+
+// Tile extents used for a state precision (4 or 8 bytes) and dimension (2 or 3).
+TileShape tile_shape(int precision, int ndim);
+
+// Launch one pass of kind `mode` (pass index j of the trajectory) over n_tiles
+// consecutive entries of `tiles`; all tiles must belong to chains of the given
+// precision and dimension.
+hipError_t launch_lattice_pass(int precision, int ndim, int mode, const ChainDev* chains, const Tile* tiles,
+                               int n_tiles, int j, hipStream_t s);
+
+}  // namespace ihmc

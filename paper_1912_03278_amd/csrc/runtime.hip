@@ -1,0 +1,884 @@
+// Host runtime and C ABI (include/ihmc.h): context, device arena, chain set-up
+// (Sec. 2 constants and the initial field), the per-trajectory launch sequence
+// captured into a HIP graph, and result export.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ihmc.h"
+#include "device_common.hpp"
+#include "lattice_kernels.hpp"
+#include "runtime_internal.hpp"
+
+namespace ihmc {
+
+// ------------------------------------------------------------------ errors ---
+
+static thread_local std::string g_err;
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(ihmc_ctx* ctx, hipError_t e, const char* where) {
+  if (ctx) ctx->dead = true;
+  return set_error(IHMC_E_DEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------- arena ---
+
+void* Arena::alloc(uint64_t bytes) {
+  bytes = (bytes + 255ull) & ~255ull;
+  if (bytes == 0) bytes = 256;
+  std::lock_guard<std::mutex> lk(mu);
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second >= bytes) {
+      const uint64_t off = it->first, rem = it->second - bytes;
+      free_.erase(it);
+      if (rem) free_[off + bytes] = rem;
+      live_[off] = bytes;
+      used += bytes;
+      return base + off;
+    }
+  }
+  return nullptr;
+}
+
+void Arena::release(void* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(mu);
+  const uint64_t off = (uint64_t)((char*)p - base);
+  auto it = live_.find(off);
+  if (it == live_.end()) return;
+  uint64_t sz = it->second;
+  live_.erase(it);
+  used -= sz;
+  uint64_t start = off;
+  auto nx = free_.lower_bound(off);
+  if (nx != free_.end() && nx->first == off + sz) {
+    sz += nx->second;
+    free_.erase(nx);
+  }
+  auto pv = free_.lower_bound(off);
+  if (pv != free_.begin()) {
+    --pv;
+    if (pv->first + pv->second == off) {
+      start = pv->first;
+      sz += pv->second;
+      free_.erase(pv);
+    }
+  }
+  free_[start] = sz;
+}
+
+// ---------------------------------------------------------- set-up kernels ---
+
+template <typename T>
+__global__ void k_field_setup(double* hp, T* b, int64_t N, double beta, double sqJ) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double v = beta * hp[i];
+  hp[i] = v;
+  b[i] = (T)(v / sqJ);
+}
+
+template <typename T>
+__global__ void k_init_psi(const ChainDev* cds, int ci, const double* psi0) {
+  const ChainDev& cd = cds[ci];
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= cd.N) return;
+  T* psi = (T*)cd.psi;
+  psi[i] = psi0 ? (T)psi0[i] : (T)normal_at(cd, 0u, TAG_INIT, i);
+}
+
+template <typename T>
+__global__ void k_import(T* dst, const double* src, int64_t N) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < N) dst[i] = (T)src[i];
+}
+
+template <typename T>
+__global__ void k_export_psi(const ChainDev* cds, int ci, double* out) {
+  const ChainDev& cd = cds[ci];
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= cd.N) return;
+  const ChainState* st = cd.st;
+  const double v = (double)((const T*)cd.psi)[(int64_t)st->cur * cd.N + i];
+  out[i] = st->sign < 0 ? -v : v;
+}
+
+template <typename T>
+__global__ void k_export(double* dst, const T* src, int64_t N) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < N) dst[i] = (double)src[i];
+}
+
+__global__ void k_zero_state(ChainState* st) {
+  uint64_t* w = (uint64_t*)st;
+  const int nw = (int)(sizeof(ChainState) / 8);
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) w[i] = 0ull;
+  __syncthreads();
+  if (threadIdx.x == 0) st->sign = 1;
+}
+
+__global__ void k_philox_words(int64_t n, const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint4 c = make_uint4(ctr[4 * k], ctr[4 * k + 1], ctr[4 * k + 2], ctr[4 * k + 3]);
+  const uint4 r = philox4x32_10(c, key[2 * k], key[2 * k + 1]);
+  out[4 * k] = r.x;
+  out[4 * k + 1] = r.y;
+  out[4 * k + 2] = r.z;
+  out[4 * k + 3] = r.w;
+}
+
+__global__ void k_philox_normals(ChainDev cd, uint32_t traj, uint32_t tag, int64_t n, double* out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = normal_at(cd, traj, tag, i);
+}
+
+// Deterministic block-wide FP64 sum (fixed order), result broadcast to all threads.
+__device__ double block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int w = 0; w < nw; ++w) t += sh[w];
+  return t;
+}
+
+__device__ void lattice_apply_global(const ChainDev& cd, const double* x, double* y) {
+  const int L0 = cd.L0, L1 = cd.L1, L2 = cd.L2;
+  for (int64_t s = threadIdx.x; s < cd.N; s += blockDim.x) {
+    const int gx = (int)(s % L0);
+    const int gy = (int)((s / L0) % L1);
+    const int gz = (int)(s / ((int64_t)L0 * L1));
+    auto at = [&](int a, int b, int c) { return x[a + (int64_t)L0 * (b + (int64_t)L1 * c)]; };
+    double acc = (at((gx + L0 - 1) % L0, gy, gz) + at((gx + 1) % L0, gy, gz)) +
+                 (at(gx, (gy + L1 - 1) % L1, gz) + at(gx, (gy + 1) % L1, gz));
+    if (cd.ndim == 3) acc += at(gx, gy, (gz + L2 - 1) % L2) + at(gx, gy, (gz + 1) % L2);
+    y[s] = cd.C * x[s] + acc;
+  }
+}
+
+// Per-site field: h'^T Kt^-1 h' by conjugate gradients (Sec. 2: solve Kt x = h'
+// instead of inverting) and 1^T Kt^-1 h' = sum h' / (n0 + C).  One block per chain.
+__global__ __launch_bounds__(256) void k_field_cg(ChainDev* cds, const int* which, double* work,
+                                                  const int64_t* woff) {
+  __shared__ double sh[8];
+  ChainDev& cd = cds[which[blockIdx.x]];
+  const int64_t N = cd.N;
+  double* x = work + woff[blockIdx.x];
+  double* r = x + N;
+  double* d = r + N;
+  double* q = d + N;
+  const double* hp = cd.hp;
+  double hs = 0.0, rr = 0.0;
+  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
+    x[i] = 0.0;
+    r[i] = hp[i];
+    d[i] = hp[i];
+    hs += hp[i];
+    rr += hp[i] * hp[i];
+  }
+  hs = block_sum(hs, sh);
+  rr = block_sum(rr, sh);
+  const double stop = 1e-30 * rr;
+  for (int it = 0; it < 20000 && rr > stop; ++it) {
+    __syncthreads();
+    lattice_apply_global(cd, d, q);
+    __syncthreads();
+    double dq = 0.0;
+    for (int64_t i = threadIdx.x; i < N; i += blockDim.x) dq += d[i] * q[i];
+    dq = block_sum(dq, sh);
+    const double alpha = rr / dq;
+    double rn = 0.0;
+    for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
+      x[i] += alpha * d[i];
+      r[i] -= alpha * q[i];
+      rn += r[i] * r[i];
+    }
+    rn = block_sum(rn, sh);
+    const double beta = rn / rr;
+    rr = rn;
+    for (int64_t i = threadIdx.x; i < N; i += blockDim.x) d[i] = r[i] + beta * d[i];
+  }
+  __syncthreads();
+  double ce = 0.0;
+  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) ce += hp[i] * x[i];
+  ce = block_sum(ce, sh);
+  if (threadIdx.x == 0) {
+    cd.c_e = ce;
+    cd.c_m = hs / (2.0 * cd.ndim + cd.C);
+  }
+}
+
+static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+// ------------------------------------------------------------ validation ---
+
+int64_t lattice_sites(const ihmc_lattice& l) {
+  int64_t n = 1;
+  for (int i = 0; i < l.ndim; ++i) n *= l.L[i];
+  return n;
+}
+
+int validate(const ihmc_lattice& l, const ihmc_run& r, int idx) {
+  if (l.ndim == 1) return set_error(IHMC_E_UNSUPPORTED, "chain %d: 1D lattices are not supported on the GPU", idx);
+  if (l.ndim != 2 && l.ndim != 3) return set_error(IHMC_E_INVAL, "chain %d: ndim must be 2 or 3", idx);
+  for (int i = 0; i < l.ndim; ++i)
+    if (l.L[i] < 3 || l.L[i] > (1 << 20)) return set_error(IHMC_E_INVAL, "chain %d: L[%d] must be in [3, 2^20]", idx, i);
+  if (!(l.beta * l.J > 0.0) || !std::isfinite(l.beta * l.J))
+    return set_error(IHMC_E_INVAL, "chain %d: J' = beta*J must be positive and finite", idx);
+  if (!(l.C > 2.0 * l.ndim) || !std::isfinite(l.C))
+    return set_error(IHMC_E_INVAL, "chain %d: C must exceed 2*ndim so that J' Kt is positive definite", idx);
+  const int64_t N = lattice_sites(l);
+  if (N >= (int64_t(1) << 33)) return set_error(IHMC_E_INVAL, "chain %d: too many sites", idx);
+  if (!(l.h_len == 0 || l.h_len == 1 || l.h_len == N))
+    return set_error(IHMC_E_INVAL, "chain %d: h_len must be 0, 1 or N", idx);
+  if (l.h_len > 0 && !l.h) return set_error(IHMC_E_INVAL, "chain %d: h is NULL", idx);
+  if (r.n_md < 1) return set_error(IHMC_E_INVAL, "chain %d: n_md must be >= 1", idx);
+  if (r.n_traj < 0) return set_error(IHMC_E_INVAL, "chain %d: n_traj must be >= 0", idx);
+  if (!(r.traj_len > 0.0) || !std::isfinite(r.traj_len))
+    return set_error(IHMC_E_INVAL, "chain %d: traj_len must be positive", idx);
+  if (r.integrator != LEAPFROG && r.integrator != OMELYAN)
+    return set_error(IHMC_E_INVAL, "chain %d: unknown integrator", idx);
+  if (r.precision != 4 && r.precision != 8) return set_error(IHMC_E_INVAL, "chain %d: precision must be 4 or 8", idx);
+  if (r.flip_every < 0) return set_error(IHMC_E_INVAL, "chain %d: flip_every must be >= 0", idx);
+  return IHMC_OK;
+}
+
+}  // namespace ihmc
+
+using namespace ihmc;
+
+// =========================================================== C ABI: context ===
+
+extern "C" const char* ihmc_last_error(void) { return g_err.c_str(); }
+
+extern "C" int ihmc_ctx_create(int32_t device, uint64_t arena_bytes, ihmc_alloc_fn alloc, ihmc_free_fn free_fn,
+                               void* user, ihmc_ctx** out) {
+  if (!out) return set_error(IHMC_E_INVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0) return set_error(IHMC_E_DEVICE, "no HIP device available");
+  if (device < 0 || device >= ndev) return set_error(IHMC_E_INVAL, "device %d out of range", device);
+  if ((alloc == nullptr) != (free_fn == nullptr)) return set_error(IHMC_E_INVAL, "alloc and free must both be set");
+  if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+  if (arena_bytes == 0) arena_bytes = 1ull << 30;
+  arena_bytes = (arena_bytes + 255ull) & ~255ull;
+  ihmc_ctx* c = new (std::nothrow) ihmc_ctx();
+  if (!c) return set_error(IHMC_E_NOMEM, "host allocation failed");
+  c->device = device;
+  c->af = alloc;
+  c->ff = free_fn;
+  c->user = user;
+  void* base = nullptr;
+  if (alloc) {
+    base = alloc(arena_bytes, user);
+    if (!base) {
+      delete c;
+      return set_error(IHMC_E_NOMEM, "allocator callback failed for %llu bytes", (unsigned long long)arena_bytes);
+    }
+  } else if ((e = hipMalloc(&base, arena_bytes)) != hipSuccess) {
+    delete c;
+    return set_error(IHMC_E_NOMEM, "hipMalloc(%llu): %s", (unsigned long long)arena_bytes, hipGetErrorString(e));
+  }
+  c->arena.base = (char*)base;
+  c->arena.size = arena_bytes;
+  c->arena.free_[0] = arena_bytes;
+  if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) {
+    if (alloc) free_fn(base, user);
+    else hipFree(base);
+    delete c;
+    return hip_fail(nullptr, e, "hipStreamCreate");
+  }
+  *out = c;
+  return IHMC_OK;
+}
+
+extern "C" void ihmc_ctx_destroy(ihmc_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  hipStreamDestroy(c->stream);
+  if (c->af) c->ff(c->arena.base, c->user);
+  else hipFree(c->arena.base);
+  delete c;
+}
+
+extern "C" void* ihmc_ctx_stream(ihmc_ctx* c) { return c ? (void*)c->stream : nullptr; }
+
+extern "C" int ihmc_ctx_sync(ihmc_ctx* c) {
+  if (!c) return set_error(IHMC_E_INVAL, "ctx is NULL");
+  hipSetDevice(c->device);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  return e == hipSuccess ? IHMC_OK : hip_fail(c, e, "hipStreamSynchronize");
+}
+
+extern "C" int ihmc_ctx_memory(ihmc_ctx* c, uint64_t* used, uint64_t* total) {
+  if (!c) return set_error(IHMC_E_INVAL, "ctx is NULL");
+  if (used) *used = c->arena.used;
+  if (total) *total = c->arena.size;
+  return IHMC_OK;
+}
+
+// ============================================================ chain objects ===
+
+namespace ihmc {
+
+void* Chains::dalloc(uint64_t bytes) {
+  void* p = ctx->arena.alloc(bytes);
+  if (p) allocs.push_back(p);
+  return p;
+}
+
+Chains::~Chains() {
+  if (gexec) hipGraphExecDestroy(gexec);
+  if (graph) hipGraphDestroy(graph);
+  for (void* p : allocs) ctx->arena.release(p);
+}
+
+#define HIPCHK(expr, what)                         \
+  do {                                             \
+    hipError_t _e = (expr);                        \
+    if (_e != hipSuccess) return hip_fail(ctx, _e, what); \
+  } while (0)
+
+int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, int flags) {
+  n = n_;
+  cd.resize(n);
+  hipStream_t s = ctx->stream;
+  std::vector<void*> temps;
+  auto tmp_alloc = [&](uint64_t bytes) {
+    void* p = ctx->arena.alloc(bytes);
+    if (p) temps.push_back(p);
+    return p;
+  };
+  auto cleanup = [&]() {
+    hipStreamSynchronize(s);
+    for (void* p : temps) ctx->arena.release(p);
+    temps.clear();
+  };
+  for (int i = 0; i < n; ++i) {
+    const ihmc_lattice& l = lats[i];
+    const ihmc_run& r = runs[i];
+    int rc = validate(l, r, i);
+    if (rc) return rc;
+    ChainDev& c = cd[i];
+    std::memset(&c, 0, sizeof c);
+    c.ndim = l.ndim;
+    c.L0 = l.L[0];
+    c.L1 = l.L[1];
+    c.L2 = l.ndim == 3 ? l.L[2] : 1;
+    c.N = lattice_sites(l);
+    c.integrator = r.integrator;
+    c.n_pass = r.integrator == OMELYAN ? 2 * r.n_md + 1 : r.n_md + 1;
+    c.flip_every = r.flip_every;
+    c.h_kind = l.h_len == 0 ? 0 : (l.h_len == 1 ? 1 : 2);
+    c.chain_id = (uint32_t)r.chain_id;
+    c.seed_lo = (uint32_t)r.seed;
+    c.seed_hi = (uint32_t)(r.seed >> 32);
+    c.Jp = l.beta * l.J;
+    c.sqJ = std::sqrt(c.Jp);
+    c.C = l.C;
+    c.eps = r.traj_len / r.n_md;
+    c.hp0 = c.h_kind == 1 ? l.beta * l.h[0] : 0.0;
+    c.b0 = c.h_kind == 1 ? c.hp0 / c.sqJ : 0.0;
+    const double n0c = 2.0 * l.ndim + l.C;
+    // Kt 1 = (n0 + C) 1 on the periodic lattice (eq. hKh_for_constant_h)
+    c.c_v = (double)c.N / n0c;
+    c.c_m = c.h_kind == 1 ? (double)c.N * c.hp0 / n0c : 0.0;
+    c.c_e = c.h_kind == 1 ? (double)c.N * c.hp0 * c.hp0 / n0c : 0.0;
+    c.cap = r.n_traj;
+    c.precision = r.precision;
+    c.p_given = (flags & BUILD_P_GIVEN) ? 1 : 0;
+    c.write_p_last = (flags & BUILD_WRITE_P) ? 1 : 0;
+    const int64_t N = c.N;
+    const int64_t pb = r.precision;
+    c.psi = dalloc(3 * N * pb);
+    c.p = dalloc(N * pb);
+    c.rec = (TrajRecord*)dalloc(sizeof(TrajRecord) * (uint64_t)std::max(1, r.n_traj));
+    c.st = (ChainState*)dalloc(sizeof(ChainState));
+    if (!c.psi || !c.p || !c.rec || !c.st) {
+      cleanup();
+      return set_error(IHMC_E_NOMEM, "chain %d: device arena exhausted (%llu of %llu bytes in use)", i,
+                       (unsigned long long)ctx->arena.used, (unsigned long long)ctx->arena.size);
+    }
+    if (r.replay_accept && r.n_traj > 0) {
+      uint8_t* d = (uint8_t*)dalloc((uint64_t)r.n_traj);
+      if (!d) {
+        cleanup();
+        return set_error(IHMC_E_NOMEM, "chain %d: arena exhausted", i);
+      }
+      HIPCHK(hipMemcpyAsync(d, r.replay_accept, (size_t)r.n_traj, hipMemcpyHostToDevice, s), "replay upload");
+      c.replay = d;
+    }
+    if (c.h_kind == 2) {
+      double* hp = (double*)dalloc(8 * N);
+      void* b = dalloc(N * pb);
+      if (!hp || !b) {
+        cleanup();
+        return set_error(IHMC_E_NOMEM, "chain %d: arena exhausted", i);
+      }
+      HIPCHK(hipMemcpyAsync(hp, l.h, 8 * N, hipMemcpyHostToDevice, s), "h upload");
+      if (pb == 4) k_field_setup<float><<<nblk(N), 256, 0, s>>>(hp, (float*)b, N, l.beta, c.sqJ);
+      else k_field_setup<double><<<nblk(N), 256, 0, s>>>(hp, (double*)b, N, l.beta, c.sqJ);
+      c.hp = hp;
+      c.b = b;
+    }
+    k_zero_state<<<1, 256, 0, s>>>(c.st);
+  }
+  d_cd = (ChainDev*)dalloc(sizeof(ChainDev) * (uint64_t)n);
+  if (!d_cd) {
+    cleanup();
+    return set_error(IHMC_E_NOMEM, "arena exhausted (chain table)");
+  }
+
+  // ---- groups of equal (precision, ndim), chains sorted by passes (descending)
+  std::map<std::pair<int, int>, std::vector<int>> byk;
+  for (int i = 0; i < n; ++i) byk[{cd[i].precision, cd[i].ndim}].push_back(i);
+  std::vector<Tile> all_tiles;
+  for (auto& kv : byk) {
+    Group g;
+    g.prec = kv.first.first;
+    g.ndim = kv.first.second;
+    g.order = kv.second;
+    std::stable_sort(g.order.begin(), g.order.end(), [&](int a, int b) { return cd[a].n_pass > cd[b].n_pass; });
+    const TileShape ts = tile_shape(g.prec, g.ndim);
+    g.tile_off = (int)all_tiles.size();
+    for (int ci : g.order) {
+      ChainDev& c = cd[ci];
+      g.tile_begin.push_back((int)all_tiles.size() - g.tile_off);
+      uint32_t cnt = 0;
+      for (int z = 0; z < c.L2; z += (g.ndim == 3 ? ts.bz : 1))
+        for (int y = 0; y < c.L1; y += ts.by)
+          for (int x = 0; x < c.L0; x += ts.bx) {
+            all_tiles.push_back(Tile{ci, x, y, z});
+            ++cnt;
+          }
+      c.n_tiles = cnt;
+      g.n_pass.push_back(c.n_pass);
+    }
+    g.tile_begin.push_back((int)all_tiles.size() - g.tile_off);
+    g.max_pass = cd[g.order[0]].n_pass;
+    groups.push_back(g);
+  }
+  d_tiles = (Tile*)dalloc(sizeof(Tile) * all_tiles.size());
+  if (!d_tiles) {
+    cleanup();
+    return set_error(IHMC_E_NOMEM, "arena exhausted (tile table)");
+  }
+  HIPCHK(hipMemcpyAsync(d_tiles, all_tiles.data(), sizeof(Tile) * all_tiles.size(), hipMemcpyHostToDevice, s),
+         "tile upload");
+  HIPCHK(hipMemcpyAsync(d_cd, cd.data(), sizeof(ChainDev) * (uint64_t)n, hipMemcpyHostToDevice, s), "chain upload");
+
+  // ---- per-site field constants by CG (one block per chain)
+  std::vector<int> cg_idx;
+  std::vector<int64_t> cg_off;
+  int64_t cg_total = 0;
+  for (int i = 0; i < n; ++i)
+    if (cd[i].h_kind == 2) {
+      cg_idx.push_back(i);
+      cg_off.push_back(cg_total);
+      cg_total += 4 * cd[i].N;
+    }
+  if (!cg_idx.empty()) {
+    double* work = (double*)tmp_alloc(8 * (uint64_t)cg_total);
+    int* didx = (int*)tmp_alloc(sizeof(int) * cg_idx.size());
+    int64_t* doff = (int64_t*)tmp_alloc(sizeof(int64_t) * cg_off.size());
+    if (!work || !didx || !doff) {
+      cleanup();
+      return set_error(IHMC_E_NOMEM, "arena exhausted (CG work space)");
+    }
+    HIPCHK(hipMemcpyAsync(didx, cg_idx.data(), sizeof(int) * cg_idx.size(), hipMemcpyHostToDevice, s), "cg idx");
+    HIPCHK(hipMemcpyAsync(doff, cg_off.data(), sizeof(int64_t) * cg_off.size(), hipMemcpyHostToDevice, s), "cg off");
+    k_field_cg<<<(unsigned)cg_idx.size(), 256, 0, s>>>(d_cd, didx, work, doff);
+    HIPCHK(hipGetLastError(), "k_field_cg");
+  }
+
+  // ---- initial field and its action
+  for (int i = 0; i < n; ++i) {
+    const ihmc_run& r = runs[i];
+    const int64_t N = cd[i].N;
+    const double* src = nullptr;
+    if (r.psi0) {
+      double* t = (double*)tmp_alloc(8 * (uint64_t)N);
+      if (!t) {
+        cleanup();
+        return set_error(IHMC_E_NOMEM, "arena exhausted (psi0 staging)");
+      }
+      HIPCHK(hipMemcpyAsync(t, r.psi0, 8 * N, hipMemcpyHostToDevice, s), "psi0 upload");
+      src = t;
+    }
+    if (cd[i].precision == 4) k_init_psi<float><<<nblk(N), 256, 0, s>>>(d_cd, i, src);
+    else k_init_psi<double><<<nblk(N), 256, 0, s>>>(d_cd, i, src);
+    HIPCHK(hipGetLastError(), "k_init_psi");
+  }
+  for (auto& g : groups) {
+    HIPCHK(launch_lattice_pass(g.prec, g.ndim, PASS_MEASURE, d_cd, d_tiles + g.tile_off, g.tile_begin.back(), 0, s),
+           "measure pass");
+  }
+  hipError_t e = hipStreamSynchronize(s);
+  cleanup();
+  if (e != hipSuccess) return hip_fail(ctx, e, "chain set-up");
+  return IHMC_OK;
+}
+
+// One trajectory of every chain: per group, pass j = 0 (FIRST) over all
+// tiles, then MIDDLE over the chains that still have passes after j and LAST
+// over the chains whose final pass is j.  Chains are sorted by pass count, so
+// each set is a contiguous range of the tile table.
+hipError_t Chains::enqueue_round(hipStream_t s) {
+  for (auto& g : groups) {
+    const Tile* base = d_tiles + g.tile_off;
+    hipError_t e = launch_lattice_pass(g.prec, g.ndim, PASS_FIRST, d_cd, base, g.tile_begin.back(), 0, s);
+    if (e != hipSuccess) return e;
+    const int nc = (int)g.order.size();
+    for (int j = 1; j < g.max_pass; ++j) {
+      int mid_end = 0;
+      while (mid_end < nc && g.n_pass[mid_end] - 1 > j) ++mid_end;
+      int last_end = mid_end;
+      while (last_end < nc && g.n_pass[last_end] - 1 == j) ++last_end;
+      if (mid_end > 0) {
+        e = launch_lattice_pass(g.prec, g.ndim, PASS_MIDDLE, d_cd, base, g.tile_begin[mid_end], j, s);
+        if (e != hipSuccess) return e;
+      }
+      if (last_end > mid_end) {
+        const int t0 = g.tile_begin[mid_end], t1 = g.tile_begin[last_end];
+        e = launch_lattice_pass(g.prec, g.ndim, PASS_LAST, d_cd, base + t0, t1 - t0, j, s);
+        if (e != hipSuccess) return e;
+      }
+    }
+  }
+  return hipSuccess;
+}
+
+int Chains::advance(int32_t n_traj) {
+  if (n_traj < 0) return set_error(IHMC_E_INVAL, "n_traj must be >= 0");
+  for (int i = 0; i < n; ++i)
+    if (enqueued + n_traj > cd[i].cap)
+      return set_error(IHMC_E_INVAL, "chain %d: %d trajectories exceed the capacity %d", i, enqueued + n_traj,
+                       cd[i].cap);
+  hipStream_t s = ctx->stream;
+  if (n_traj == 0) return IHMC_OK;
+  if (n_traj == 1 && !gexec) {
+    HIPCHK(enqueue_round(s), "round launch");
+  } else {
+    if (!gexec) {
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+      hipError_t e = enqueue_round(s);
+      hipGraph_t gr = nullptr;
+      hipError_t e2 = hipStreamEndCapture(s, &gr);
+      if (e != hipSuccess) return hip_fail(ctx, e, "capture round");
+      if (e2 != hipSuccess) return hip_fail(ctx, e2, "end capture");
+      graph = gr;
+      HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0), "graph instantiate");
+    }
+    for (int t = 0; t < n_traj; ++t) HIPCHK(hipGraphLaunch(gexec, s), "graph launch");
+  }
+  enqueued += n_traj;
+  return IHMC_OK;
+}
+
+int Chains::result(int32_t i, ihmc_result* out) {
+  if (i < 0 || i >= n) return set_error(IHMC_E_INVAL, "chain index %d out of range", i);
+  if (!out) return set_error(IHMC_E_INVAL, "out is NULL");
+  hipStream_t s = ctx->stream;
+  HIPCHK(hipStreamSynchronize(s), "sync");
+  const ChainDev& c = cd[i];
+  ChainState st;
+  HIPCHK(hipMemcpy(&st, c.st, sizeof st, hipMemcpyDeviceToHost), "state download");
+  const int done = std::min(st.traj, c.cap);
+  std::vector<TrajRecord> rec((size_t)std::max(done, 1));
+  if (done > 0) HIPCHK(hipMemcpy(rec.data(), c.rec, sizeof(TrajRecord) * done, hipMemcpyDeviceToHost), "records");
+  for (int t = 0; t < done; ++t) {
+    const TrajRecord& r = rec[t];
+    if (out->dH) out->dH[t] = r.dH;
+    if (out->H_old) out->H_old[t] = r.H_old;
+    if (out->H_new) out->H_new[t] = r.H_new;
+    if (out->m) out->m[t] = r.m;
+    if (out->abs_m) out->abs_m[t] = r.abs_m;
+    if (out->m2c) out->m2c[t] = r.m2c;
+    if (out->beta_eps) out->beta_eps[t] = r.beta_eps;
+    if (out->accepted) out->accepted[t] = (r.flags & REC_ACCEPT) ? 1 : 0;
+    if (out->flipped) out->flipped[t] = (r.flags & REC_FLIP) ? 1 : 0;
+  }
+  out->n_traj_done = st.traj;
+  out->acceptance = st.traj ? (double)st.n_acc / st.traj : 0.0;
+  const int64_t nf = st.traj - st.n_nonfinite;
+  out->mean_exp_minus_dH = nf > 0 ? st.sum_exp_mdh / (double)nf : 0.0;
+  out->n_nonfinite = st.n_nonfinite;
+  if (out->psi_final) {
+    double* t = (double*)ctx->arena.alloc(8 * (uint64_t)c.N);
+    if (!t) return set_error(IHMC_E_NOMEM, "arena exhausted (export)");
+    if (c.precision == 4) k_export_psi<float><<<nblk(c.N), 256, 0, s>>>(d_cd, i, t);
+    else k_export_psi<double><<<nblk(c.N), 256, 0, s>>>(d_cd, i, t);
+    hipError_t e = hipMemcpyAsync(out->psi_final, t, 8 * c.N, hipMemcpyDeviceToHost, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    ctx->arena.release(t);
+    if (e != hipSuccess) return hip_fail(ctx, e, "psi export");
+    if (e2 != hipSuccess) return hip_fail(ctx, e2, "psi export sync");
+  }
+  return IHMC_OK;
+}
+
+}  // namespace ihmc
+
+// ========================================================== C ABI: chains ===
+
+#define CTX_OK(c)                                                         \
+  do {                                                                    \
+    if (!(c)) return set_error(IHMC_E_INVAL, "ctx is NULL");              \
+    if ((c)->dead) return set_error(IHMC_E_DEVICE, "context is unusable after a device error"); \
+    hipSetDevice((c)->device);                                            \
+  } while (0)
+
+static int make_chains(ihmc_ctx* ctx, int32_t n, const ihmc_lattice* lats, const ihmc_run* runs, int flags,
+                       Chains** out) {
+  if (n < 1 || !lats || !runs) return set_error(IHMC_E_INVAL, "need n >= 1 chains with descriptors");
+  Chains* c = new (std::nothrow) Chains();
+  if (!c) return set_error(IHMC_E_NOMEM, "host allocation failed");
+  c->ctx = ctx;
+  int rc = c->build(n, lats, runs, flags);
+  if (rc) {
+    hipStreamSynchronize(ctx->stream);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return IHMC_OK;
+}
+
+extern "C" int ihmc_chains_create(ihmc_ctx* ctx, int32_t n, const ihmc_lattice* lats, const ihmc_run* runs,
+                                  ihmc_chains** out) {
+  CTX_OK(ctx);
+  if (!out) return set_error(IHMC_E_INVAL, "out is NULL");
+  Chains* c = nullptr;
+  int rc = make_chains(ctx, n, lats, runs, 0, &c);
+  *out = (ihmc_chains*)c;
+  return rc;
+}
+
+extern "C" int ihmc_chains_advance(ihmc_chains* ch, int32_t n_traj) {
+  if (!ch) return set_error(IHMC_E_INVAL, "chains is NULL");
+  Chains* c = (Chains*)ch;
+  CTX_OK(c->ctx);
+  return c->advance(n_traj);
+}
+
+extern "C" int ihmc_chains_result(ihmc_chains* ch, int32_t i, ihmc_result* out) {
+  if (!ch) return set_error(IHMC_E_INVAL, "chains is NULL");
+  Chains* c = (Chains*)ch;
+  CTX_OK(c->ctx);
+  return c->result(i, out);
+}
+
+extern "C" int ihmc_chains_destroy(ihmc_chains* ch) {
+  if (!ch) return IHMC_OK;
+  Chains* c = (Chains*)ch;
+  hipSetDevice(c->ctx->device);
+  hipStreamSynchronize(c->ctx->stream);
+  delete c;
+  return IHMC_OK;
+}
+
+extern "C" int ihmc_run_batch(ihmc_ctx* ctx, int32_t n, const ihmc_lattice* lats, const ihmc_run* runs,
+                              ihmc_result* outs) {
+  CTX_OK(ctx);
+  if (!outs) return set_error(IHMC_E_INVAL, "outs is NULL");
+  Chains* c = nullptr;
+  int rc = make_chains(ctx, n, lats, runs, 0, &c);
+  if (rc) return rc;
+  int max_traj = 0;
+  bool uniform = true;
+  for (int i = 0; i < n; ++i) {
+    max_traj = std::max(max_traj, runs[i].n_traj);
+    uniform = uniform && runs[i].n_traj == runs[0].n_traj;
+  }
+  if (!uniform) {
+    delete c;
+    return set_error(IHMC_E_UNSUPPORTED, "ihmc_run_batch: chains must share n_traj");
+  }
+  rc = c->advance(max_traj);
+  for (int i = 0; rc == IHMC_OK && i < n; ++i) rc = c->result(i, &outs[i]);
+  hipStreamSynchronize(ctx->stream);
+  delete c;
+  return rc;
+}
+
+extern "C" int ihmc_run_lattice(ihmc_ctx* ctx, const ihmc_lattice* lat, const ihmc_run* run, ihmc_result* out) {
+  return ihmc_run_batch(ctx, 1, lat, run, out);
+}
+
+// ===================================================== C ABI: diagnostics ===
+
+static ihmc_run diag_run(int32_t precision) {
+  ihmc_run r;
+  std::memset(&r, 0, sizeof r);
+  r.n_md = 1;
+  r.n_traj = 1;
+  r.traj_len = 1.0;
+  r.precision = precision;
+  return r;
+}
+
+extern "C" int ihmc_force(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t precision, const double* psi, double* F) {
+  CTX_OK(ctx);
+  if (!lat || !psi || !F) return set_error(IHMC_E_INVAL, "NULL argument");
+  ihmc_run r = diag_run(precision);
+  r.psi0 = psi;
+  Chains* c = nullptr;
+  int rc = make_chains(ctx, 1, lat, &r, 0, &c);
+  if (rc) return rc;
+  hipStream_t s = ctx->stream;
+  const Group& g = c->groups[0];
+  hipError_t e = launch_lattice_pass(g.prec, g.ndim, PASS_FORCE, c->d_cd, c->d_tiles, g.tile_begin.back(), 0, s);
+  const int64_t N = c->cd[0].N;
+  double* t = (double*)ctx->arena.alloc(8 * (uint64_t)N);
+  if (e == hipSuccess && t) {
+    if (precision == 4) k_export<float><<<nblk(N), 256, 0, s>>>(t, (const float*)c->cd[0].p, N);
+    else k_export<double><<<nblk(N), 256, 0, s>>>(t, (const double*)c->cd[0].p, N);
+    e = hipMemcpyAsync(F, t, 8 * N, hipMemcpyDeviceToHost, s);
+  }
+  hipError_t e2 = hipStreamSynchronize(s);
+  if (t) ctx->arena.release(t);
+  delete c;
+  if (!t) return set_error(IHMC_E_NOMEM, "arena exhausted");
+  if (e != hipSuccess) return hip_fail(ctx, e, "force");
+  if (e2 != hipSuccess) return hip_fail(ctx, e2, "force sync");
+  return IHMC_OK;
+}
+
+extern "C" int ihmc_action(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t precision, const double* psi,
+                           double* out) {
+  CTX_OK(ctx);
+  if (!lat || !psi || !out) return set_error(IHMC_E_INVAL, "NULL argument");
+  ihmc_run r = diag_run(precision);
+  r.psi0 = psi;
+  Chains* c = nullptr;
+  int rc = make_chains(ctx, 1, lat, &r, 0, &c);
+  if (rc) return rc;
+  ChainState st;
+  ChainDev cdv;
+  hipError_t e = hipMemcpy(&st, c->cd[0].st, sizeof st, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(&cdv, c->d_cd, sizeof cdv, hipMemcpyDeviceToHost);
+  delete c;
+  if (e != hipSuccess) return hip_fail(ctx, e, "action download");
+  const double N = (double)cdv.N;
+  out[0] = fixed_to_double(u128{st.S_lo, st.S_hi});
+  out[1] = (st.sum_psi / cdv.sqJ - cdv.c_m / cdv.Jp) / N;
+  out[2] = std::fabs(out[1]);
+  out[3] = out[1] * out[1] - cdv.c_v / (N * N * cdv.Jp);
+  out[4] = 0.5 * cdv.C * cdv.Jp + cdv.c_e / (2.0 * N * cdv.Jp) - st.sum_psih / (2.0 * N * cdv.sqJ) -
+           cdv.sqJ / (2.0 * N) * st.sum_ut;
+  return IHMC_OK;
+}
+
+extern "C" int ihmc_integrate(ihmc_ctx* ctx, const ihmc_lattice* lat, const ihmc_run* run, double* psi, double* p) {
+  CTX_OK(ctx);
+  if (!lat || !run || !psi || !p) return set_error(IHMC_E_INVAL, "NULL argument");
+  ihmc_run r = *run;
+  r.n_traj = 1;
+  r.psi0 = psi;
+  r.flip_every = 0;
+  static const uint8_t one = 1;
+  r.replay_accept = &one;
+  Chains* c = nullptr;
+  int rc = make_chains(ctx, 1, lat, &r, BUILD_P_GIVEN | BUILD_WRITE_P, &c);
+  if (rc) return rc;
+  hipStream_t s = ctx->stream;
+  const ChainDev& cdh = c->cd[0];
+  const int64_t N = cdh.N;
+  double* t = (double*)ctx->arena.alloc(8 * (uint64_t)N);
+  hipError_t e = hipSuccess;
+  if (t) {
+    e = hipMemcpyAsync(t, p, 8 * N, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+      if (cdh.precision == 4) k_import<float><<<nblk(N), 256, 0, s>>>((float*)cdh.p, t, N);
+      else k_import<double><<<nblk(N), 256, 0, s>>>((double*)cdh.p, t, N);
+      e = c->enqueue_round(s);
+    }
+    if (e == hipSuccess) {
+      if (cdh.precision == 4) k_export_psi<float><<<nblk(N), 256, 0, s>>>(c->d_cd, 0, t);
+      else k_export_psi<double><<<nblk(N), 256, 0, s>>>(c->d_cd, 0, t);
+      e = hipMemcpyAsync(psi, t, 8 * N, hipMemcpyDeviceToHost, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) {
+      if (cdh.precision == 4) k_export<float><<<nblk(N), 256, 0, s>>>(t, (const float*)cdh.p, N);
+      else k_export<double><<<nblk(N), 256, 0, s>>>(t, (const double*)cdh.p, N);
+      e = hipMemcpyAsync(p, t, 8 * N, hipMemcpyDeviceToHost, s);
+    }
+  }
+  hipError_t e2 = hipStreamSynchronize(s);
+  if (t) ctx->arena.release(t);
+  delete c;
+  if (!t) return set_error(IHMC_E_NOMEM, "arena exhausted");
+  if (e != hipSuccess) return hip_fail(ctx, e, "integrate");
+  if (e2 != hipSuccess) return hip_fail(ctx, e2, "integrate sync");
+  return IHMC_OK;
+}
+
+extern "C" int ihmc_philox_normals(ihmc_ctx* ctx, uint64_t seed, uint64_t chain_id, uint32_t traj, uint32_t tag,
+                                   int64_t n, double* out) {
+  CTX_OK(ctx);
+  if (n < 0 || (n > 0 && !out)) return set_error(IHMC_E_INVAL, "bad output");
+  if (n == 0) return IHMC_OK;
+  ChainDev cdv;
+  std::memset(&cdv, 0, sizeof cdv);
+  cdv.seed_lo = (uint32_t)seed;
+  cdv.seed_hi = (uint32_t)(seed >> 32);
+  cdv.chain_id = (uint32_t)chain_id;
+  double* t = (double*)ctx->arena.alloc(8 * (uint64_t)n);
+  if (!t) return set_error(IHMC_E_NOMEM, "arena exhausted");
+  hipStream_t s = ctx->stream;
+  k_philox_normals<<<nblk(n), 256, 0, s>>>(cdv, traj, tag, n, t);
+  hipError_t e = hipMemcpyAsync(out, t, 8 * n, hipMemcpyDeviceToHost, s);
+  hipError_t e2 = hipStreamSynchronize(s);
+  ctx->arena.release(t);
+  if (e != hipSuccess) return hip_fail(ctx, e, "normals");
+  if (e2 != hipSuccess) return hip_fail(ctx, e2, "normals sync");
+  return IHMC_OK;
+}
+
+extern "C" int ihmc_philox_words(ihmc_ctx* ctx, int64_t n, const uint32_t* ctr, const uint32_t* key,
+                                 uint32_t* out) {
+  CTX_OK(ctx);
+  if (n < 0 || (n > 0 && (!ctr || !key || !out))) return set_error(IHMC_E_INVAL, "bad arguments");
+  if (n == 0) return IHMC_OK;
+  uint32_t* d = (uint32_t*)ctx->arena.alloc(40 * (uint64_t)n);
+  if (!d) return set_error(IHMC_E_NOMEM, "arena exhausted");
+  hipStream_t s = ctx->stream;
+  uint32_t *dc = d, *dk = d + 4 * n, *dout = d + 6 * n;
+  hipError_t e = hipMemcpyAsync(dc, ctr, 16 * n, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dk, key, 8 * n, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    k_philox_words<<<nblk(n), 256, 0, s>>>(n, dc, dk, dout);
+    e = hipMemcpyAsync(out, dout, 16 * n, hipMemcpyDeviceToHost, s);
+  }
+  hipError_t e2 = hipStreamSynchronize(s);
+  ctx->arena.release(d);
+  if (e != hipSuccess) return hip_fail(ctx, e, "philox");
+  if (e2 != hipSuccess) return hip_fail(ctx, e2, "philox sync");
+  return IHMC_OK;
+}

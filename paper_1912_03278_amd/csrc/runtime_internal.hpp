@@ -1,0 +1,72 @@
+// Host-side runtime objects behind the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "../../include/ihmc.h"
+#include "ihmc_internal.hpp"
+
+namespace ihmc {
+
+int set_error(int code, const char* fmt, ...);
+int hip_fail(ihmc_ctx* ctx, hipError_t e, const char* where);
+
+// First-fit sub-allocator over one device allocation (256-byte granules).
+struct Arena {
+  char* base = nullptr;
+  uint64_t size = 0;
+  uint64_t used = 0;
+  std::map<uint64_t, uint64_t> free_;  // offset -> bytes
+  std::map<uint64_t, uint64_t> live_;  // offset -> bytes
+  std::mutex mu;
+  void* alloc(uint64_t bytes);
+  void release(void* p);
+};
+
+enum BuildFlags : int { BUILD_P_GIVEN = 1, BUILD_WRITE_P = 2 };
+
+// Chains of equal state precision and dimension share launches.
+struct Group {
+  int prec = 4, ndim = 2;
+  std::vector<int> order;       // chain indices, sorted by pass count (descending)
+  std::vector<int> n_pass;      // pass count per position in `order`
+  std::vector<int> tile_begin;  // first tile of each position, relative to tile_off; size+1
+  int tile_off = 0;
+  int max_pass = 0;
+};
+
+struct Chains {
+  ihmc_ctx* ctx = nullptr;
+  int n = 0;
+  std::vector<ChainDev> cd;  // host copies
+  ChainDev* d_cd = nullptr;
+  Tile* d_tiles = nullptr;
+  std::vector<Group> groups;
+  std::vector<void*> allocs;
+  int enqueued = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+
+  void* dalloc(uint64_t bytes);
+  int build(int32_t n, const ihmc_lattice* lats, const ihmc_run* runs, int flags);
+  hipError_t enqueue_round(hipStream_t s);
+  int advance(int32_t n_traj);
+  int result(int32_t i, ihmc_result* out);
+  ~Chains();
+};
+
+}  // namespace ihmc
+
+struct ihmc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  ihmc::Arena arena;
+  ihmc_alloc_fn af = nullptr;
+  ihmc_free_fn ff = nullptr;
+  void* user = nullptr;
+  bool dead = false;
+};

@@ -1,0 +1,333 @@
+"""Python binding of the MI355X HMC library (include/ihmc.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+``libihmc.so``.  PyTorch supplies device memory (the library's arena is one
+block from torch's caching allocator) and nothing else.  There is no CPU
+fallback: if the library or a GPU is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libihmc.so")
+
+IHMC_OK = 0
+STATUS = {-1: "IHMC_E_INVAL", -2: "IHMC_E_NOMEM", -3: "IHMC_E_AGAIN", -4: "IHMC_E_DEVICE",
+          -5: "IHMC_E_CANCELLED", -6: "IHMC_E_UNSUPPORTED"}
+F32, F64 = 4, 8
+LEAPFROG, OMELYAN = 0, 1
+TAG_INIT, TAG_MOM, TAG_ACC, TAG_FLIP = 1, 2, 3, 4
+
+EXPORTS = (
+    "ihmc_ctx_create", "ihmc_ctx_destroy", "ihmc_ctx_stream", "ihmc_ctx_sync", "ihmc_ctx_memory",
+    "ihmc_last_error", "ihmc_chains_create", "ihmc_chains_advance", "ihmc_chains_result",
+    "ihmc_chains_destroy", "ihmc_run_lattice", "ihmc_run_batch", "ihmc_force", "ihmc_action",
+    "ihmc_integrate", "ihmc_philox_normals", "ihmc_philox_words",
+)
+
+
+class IhmcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Lattice(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("L", C.c_int32 * 3), ("J", C.c_double), ("beta", C.c_double),
+                ("C", C.c_double), ("h", C.POINTER(C.c_double)), ("h_len", C.c_int64)]
+
+
+class _Run(C.Structure):
+    _fields_ = [("n_md", C.c_int32), ("n_traj", C.c_int32), ("traj_len", C.c_double),
+                ("integrator", C.c_int32), ("flip_every", C.c_int32), ("precision", C.c_int32),
+                ("pad", C.c_int32), ("seed", C.c_uint64), ("chain_id", C.c_uint64),
+                ("psi0", C.POINTER(C.c_double)), ("replay_accept", C.POINTER(C.c_uint8))]
+
+
+_DP = C.POINTER(C.c_double)
+_U8 = C.POINTER(C.c_uint8)
+
+
+class _Result(C.Structure):
+    _fields_ = [("dH", _DP), ("H_old", _DP), ("H_new", _DP), ("m", _DP), ("abs_m", _DP), ("m2c", _DP),
+                ("beta_eps", _DP), ("accepted", _U8), ("flipped", _U8), ("psi_final", _DP),
+                ("acceptance", C.c_double), ("mean_exp_minus_dH", C.c_double),
+                ("n_nonfinite", C.c_int64), ("n_traj_done", C.c_int64)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_uint64, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+_lib = None
+
+
+def load():
+    """Load libihmc.so (built by paper_1912_03278_amd.build); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1912_03278_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, pp = C.c_void_p, C.POINTER(C.c_void_p)
+    L.ihmc_ctx_create.argtypes = [C.c_int32, C.c_uint64, ALLOC_FN, FREE_FN, vp, pp]
+    L.ihmc_ctx_destroy.argtypes = [vp]
+    L.ihmc_ctx_destroy.restype = None
+    L.ihmc_ctx_stream.argtypes = [vp]
+    L.ihmc_ctx_stream.restype = vp
+    L.ihmc_ctx_sync.argtypes = [vp]
+    L.ihmc_ctx_memory.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+    L.ihmc_last_error.restype = C.c_char_p
+    L.ihmc_chains_create.argtypes = [vp, C.c_int32, C.POINTER(_Lattice), C.POINTER(_Run), pp]
+    L.ihmc_chains_advance.argtypes = [vp, C.c_int32]
+    L.ihmc_chains_result.argtypes = [vp, C.c_int32, C.POINTER(_Result)]
+    L.ihmc_chains_destroy.argtypes = [vp]
+    L.ihmc_run_lattice.argtypes = [vp, C.POINTER(_Lattice), C.POINTER(_Run), C.POINTER(_Result)]
+    L.ihmc_run_batch.argtypes = [vp, C.c_int32, C.POINTER(_Lattice), C.POINTER(_Run), C.POINTER(_Result)]
+    L.ihmc_force.argtypes = [vp, C.POINTER(_Lattice), C.c_int32, _DP, _DP]
+    L.ihmc_action.argtypes = [vp, C.POINTER(_Lattice), C.c_int32, _DP, _DP]
+    L.ihmc_integrate.argtypes = [vp, C.POINTER(_Lattice), C.POINTER(_Run), _DP, _DP]
+    L.ihmc_philox_normals.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int64, _DP]
+    L.ihmc_philox_words.argtypes = [vp, C.c_int64, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                    C.POINTER(C.c_uint32)]
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != IHMC_OK:
+        raise IhmcError(rc, load().ihmc_last_error().decode(errors="replace"))
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(_DP)
+
+
+@dataclass
+class Lattice:
+    """Periodic 2D/3D nearest-neighbour lattice (Sec. 2): J' = beta J, Kt = K + C 1."""
+    L: tuple
+    beta: float
+    C: float
+    J: float = 1.0
+    h: object = None  # None, a scalar, or one value per site
+
+    @property
+    def N(self):
+        return int(np.prod(self.L))
+
+    def _c(self, keep):
+        s = _Lattice()
+        s.ndim = len(self.L)
+        for i in range(3):
+            s.L[i] = int(self.L[i]) if i < len(self.L) else 1
+        s.J, s.beta, s.C = float(self.J), float(self.beta), float(self.C)
+        h = None if self.h is None else _f64(np.atleast_1d(self.h))
+        keep.append(h)
+        s.h = _dp(h)
+        s.h_len = 0 if h is None else h.size
+        return s
+
+
+@dataclass
+class Run:
+    """Chain parameters (Sec. 3)."""
+    n_md: int
+    n_traj: int
+    traj_len: float = 1.0
+    integrator: int = LEAPFROG
+    flip_every: int = 0
+    precision: int = F32
+    seed: int = 0
+    chain_id: int = 0
+    psi0: object = None
+    replay_accept: object = None
+
+    def _c(self, keep):
+        s = _Run()
+        s.n_md, s.n_traj, s.traj_len = int(self.n_md), int(self.n_traj), float(self.traj_len)
+        s.integrator, s.flip_every, s.precision = int(self.integrator), int(self.flip_every), int(self.precision)
+        s.seed, s.chain_id = int(self.seed), int(self.chain_id)
+        p0 = _f64(self.psi0)
+        keep.append(p0)
+        s.psi0 = _dp(p0)
+        ra = None if self.replay_accept is None else np.ascontiguousarray(self.replay_accept, dtype=np.uint8)
+        keep.append(ra)
+        s.replay_accept = None if ra is None else ra.ctypes.data_as(_U8)
+        return s
+
+
+SERIES = ("dH", "H_old", "H_new", "m", "abs_m", "m2c", "beta_eps")
+
+
+def _result_struct(n_traj, N, want_psi=True):
+    arrays = {k: np.zeros(n_traj) for k in SERIES}
+    arrays["accepted"] = np.zeros(n_traj, dtype=np.uint8)
+    arrays["flipped"] = np.zeros(n_traj, dtype=np.uint8)
+    if want_psi:
+        arrays["psi_final"] = np.zeros(N)
+    r = _Result()
+    for k, v in arrays.items():
+        setattr(r, k, v.ctypes.data_as(_U8 if v.dtype == np.uint8 else _DP))
+    return r, arrays
+
+
+def _result_dict(r, arrays):
+    out = dict(arrays)
+    out.update(acceptance=r.acceptance, mean_exp_minus_dH=r.mean_exp_minus_dH,
+               n_nonfinite=int(r.n_nonfinite), n_traj_done=int(r.n_traj_done))
+    return out
+
+
+class Context:
+    """A device context: HIP stream plus an arena of device memory from torch."""
+
+    def __init__(self, device=0, arena_bytes=1 << 30, use_torch=True):
+        L = load()
+        self._keep = []
+        if use_torch:
+            import torch
+            if not torch.cuda.is_available():
+                raise RuntimeError("no GPU visible to torch")
+            dev = int(device)
+
+            def _alloc(nbytes, user):
+                return int(torch.cuda.caching_allocator_alloc(int(nbytes), device=dev))
+
+            def _free(ptr, user):
+                torch.cuda.caching_allocator_delete(int(ptr))
+
+            af, ff = ALLOC_FN(_alloc), FREE_FN(_free)
+        else:
+            af, ff = ALLOC_FN(), FREE_FN()
+        self._fns = (af, ff)
+        h = C.c_void_p()
+        _check(L.ihmc_ctx_create(int(device), int(arena_bytes), af, ff, None, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().ihmc_ctx_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def stream(self):
+        return load().ihmc_ctx_stream(self.h)
+
+    def sync(self):
+        _check(load().ihmc_ctx_sync(self.h))
+
+    def memory(self):
+        u, t = C.c_uint64(), C.c_uint64()
+        _check(load().ihmc_ctx_memory(self.h, C.byref(u), C.byref(t)))
+        return u.value, t.value
+
+    # ---- whole runs
+    def run_lattice(self, lat: Lattice, run: Run, want_psi=True):
+        return self.run_batch([lat], [run], want_psi)[0]
+
+    def run_batch(self, lats, runs, want_psi=True):
+        keep = []
+        n = len(lats)
+        la = (_Lattice * n)(*[l._c(keep) for l in lats])
+        ra = (_Run * n)(*[r._c(keep) for r in runs])
+        res = (_Result * n)()
+        arrs = []
+        for i in range(n):
+            r, a = _result_struct(runs[i].n_traj, lats[i].N, want_psi)
+            res[i] = r
+            arrs.append(a)
+        _check(load().ihmc_run_batch(self.h, n, la, ra, res))
+        return [_result_dict(res[i], arrs[i]) for i in range(n)]
+
+    # ---- diagnostics
+    def force(self, lat: Lattice, psi, precision=F32):
+        keep = []
+        psi = _f64(psi)
+        F = np.zeros_like(psi)
+        _check(load().ihmc_force(self.h, C.byref(lat._c(keep)), int(precision), _dp(psi), _dp(F)))
+        return F
+
+    def action(self, lat: Lattice, psi, precision=F32):
+        keep = []
+        psi = _f64(psi)
+        out = np.zeros(5)
+        _check(load().ihmc_action(self.h, C.byref(lat._c(keep)), int(precision), _dp(psi), _dp(out)))
+        return dict(zip(("S", "m", "abs_m", "m2c", "beta_eps"), out.tolist()))
+
+    def integrate(self, lat: Lattice, run: Run, psi, p):
+        keep = []
+        psi, p = _f64(psi).copy(), _f64(p).copy()
+        _check(load().ihmc_integrate(self.h, C.byref(lat._c(keep)), C.byref(run._c(keep)), _dp(psi), _dp(p)))
+        return psi, p
+
+    def philox_normals(self, seed, chain_id, traj, tag, n):
+        out = np.zeros(n)
+        _check(load().ihmc_philox_normals(self.h, seed, chain_id, traj, tag, n, _dp(out)))
+        return out
+
+    def philox_words(self, ctr, key):
+        ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+        key = np.ascontiguousarray(key, dtype=np.uint32).reshape(-1, 2)
+        n = ctr.shape[0]
+        out = np.zeros((n, 4), dtype=np.uint32)
+        u32 = C.POINTER(C.c_uint32)
+        _check(load().ihmc_philox_words(self.h, n, ctr.ctypes.data_as(u32), key.ctypes.data_as(u32),
+                                        out.ctypes.data_as(u32)))
+        return out
+
+
+class Chains:
+    """Chains resident on the device; advance() enqueues trajectories asynchronously."""
+
+    def __init__(self, ctx: Context, lats, runs):
+        self.ctx = ctx
+        keep = []
+        n = len(lats)
+        self.n = n
+        self.lats, self.runs = list(lats), list(runs)
+        la = (_Lattice * n)(*[l._c(keep) for l in lats])
+        ra = (_Run * n)(*[r._c(keep) for r in runs])
+        h = C.c_void_p()
+        _check(load().ihmc_chains_create(ctx.h, n, la, ra, C.byref(h)))
+        self.h = h
+
+    def advance(self, n_traj):
+        _check(load().ihmc_chains_advance(self.h, int(n_traj)))
+
+    def result(self, i, want_psi=True):
+        r, a = _result_struct(self.runs[i].n_traj, self.lats[i].N, want_psi)
+        _check(load().ihmc_chains_result(self.h, int(i), C.byref(r)))
+        return _result_dict(r, a)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().ihmc_chains_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
