@@ -71,6 +71,12 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
+    # PyTorch ships its own HIP runtime under the same soname; loading torch first
+    # makes the library bind to that one runtime instead of a second copy.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1912_03278_amd.build`")
     L = C.CDLL(LIB_PATH)
