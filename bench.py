@@ -1,0 +1,163 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the fused lattice HMC path on one MI355X.
+
+Workload (default, "large"): two single large chains, FP32 state with FP64
+Hamiltonian reductions, J = 1, h = 0, 20 leap-frog steps per unit trajectory:
+  * 2D 1024 x 1024 torus at beta_c = ln(1 + sqrt 2)/2, C = 4.1;
+  * 3D 128^3 torus at beta = 0.2216544, C = 6.1.
+Seeded Gaussian initial fields (Philox).  One step = one HMC trajectory of both
+chains (21 fused passes each, Metropolis on the device); the metric is
+site-MD-steps/s = (sites x MD steps) per second over the timed steps.
+
+Besides the throughput line it reports the roofline of the dominant kernel (the
+fused middle pass: 16 bytes of state per site, HIP-event timed on the library's
+stream) and the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+BYTES_MIDDLE_F32 = 16  # read psi, read p, write p, write psi' (FP32), h = 0
+
+
+def large_workload():
+    from paper_1912_03278_amd import inputs
+    return inputs.large()
+
+
+def cpu_baseline(chains):
+    """The FP64 oracle, single-threaded, one trajectory of each chain."""
+    import oracle
+    t_total, work = 0.0, 0
+    for w in chains:
+        lat = oracle.Lattice(w["L"], beta=w["beta"], C=w["C"])
+        t0 = time.perf_counter()
+        oracle.run(lat, 1, w["n_md"], seed=w["seed"], chain_id=w["chain_id"])
+        t_total += time.perf_counter() - t0
+        work += int(math.prod(w["L"])) * w["n_md"]
+    return dict(value=work / t_total, unit="site-MD-steps/s", cores=1, kind="oracle",
+                sample="one trajectory (20 MD steps) of the 1024^2 and the 128^3 chain, FP64, "
+                       f"{t_total:.1f} s on one host core")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--timing-reps", type=int, default=100)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; the multi-GPU sharding is described in "
+              "DESIGN.md and is not implemented", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1912_03278_amd import ihmc
+
+    ws = large_workload()
+    K, W = args.steps, args.warmup
+    ctx = ihmc.Context(device=0, arena_bytes=1 << 30)
+    lats = [ihmc.Lattice(w["L"], beta=w["beta"], C=w["C"]) for w in ws]
+    runs = [ihmc.Run(n_md=w["n_md"], n_traj=W + K, precision=ihmc.F32, seed=w["seed"], chain_id=w["chain_id"])
+            for w in ws]
+    chains = ihmc.Chains(ctx, lats, runs)
+    print(f"bench: chains ready ({', '.join('x'.join(map(str, w['L'])) for w in ws)})", file=sys.stderr, flush=True)
+    chains.advance(W)
+    ctx.sync()
+    print(f"bench: warmup {W} trajectories done", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    ctx.sync()
+    t0 = time.perf_counter()
+    chains.advance(K)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dt = t1 - t0
+    site_steps = sum(int(math.prod(w["L"])) * w["n_md"] for w in ws)
+    value = K * site_steps / dt
+    print(f"bench: timed {K} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+
+    per = []
+    for i, w in enumerate(ws):
+        r = chains.result(i, want_psi=False)
+        per.append(dict(lattice="x".join(map(str, w["L"])), beta=w["beta"], acceptance=round(r["acceptance"], 4),
+                        n_traj_done=r["n_traj_done"], n_nonfinite=r["n_nonfinite"],
+                        mean_beta_eps_last=float(r["beta_eps"][-1])))
+
+    # ---- roofline of the dominant kernel: HIP-event timing of each fused pass kind
+    kern = []
+    for g in range(chains.groups()):
+        mid = chains.time_pass(g, mode=1, reps=args.timing_reps)
+        first = chains.time_pass(g, mode=0, reps=max(10, args.timing_reps // 5))
+        n_md = ws[g]["n_md"]  # groups are ordered (precision, ndim): 2D then 3D, one chain each
+        kern.append(dict(ndim=mid["ndim"], sites=mid["sites"], middle_us=mid["us"], first_us=first["us"],
+                         middle_share_us=(n_md - 1) * mid["us"]))
+    dom = max(kern, key=lambda k: k["middle_share_us"])
+    bytes_per_launch = BYTES_MIDDLE_F32 * dom["sites"]
+    achieved = bytes_per_launch / (dom["middle_us"] * 1e-6) / 1e9
+    for k in kern:
+        k["middle_GBs"] = round(BYTES_MIDDLE_F32 * k["sites"] / (k["middle_us"] * 1e-6) / 1e9, 1)
+        k["middle_us"] = round(k["middle_us"], 3)
+        k["first_us"] = round(k["first_us"], 3)
+        del k["middle_share_us"]
+
+    line = {
+        "metric": "site-MD-steps/s",
+        "value": value,
+        "unit": "site-MD-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1000.0 * dt / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "single large chains: 2D 1024^2 at beta_c=0.4406868 (C=4.1) and 3D 128^3 at "
+                        "beta=0.2216544 (C=6.1), J=1, h=0, 20 leap-frog steps per unit trajectory, FP32 "
+                        "state, FP64 H/dH/Metropolis; one step = one trajectory of both chains",
+            "sites": sum(int(math.prod(w["L"])) for w in ws),
+            "md_steps_per_trajectory": ws[0]["n_md"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": f"fused middle pass, {dom['ndim']}D",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "bytes_per_launch": bytes_per_launch,
+            "avg_launch_us": round(dom["middle_us"], 3),
+        },
+        "kernels": kern,
+        "chains": per,
+    }
+    chains.close()
+    ctx.close()
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle on a one-trajectory sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(ws)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -71,7 +71,7 @@ __device__ __forceinline__ void finalize_trajectory(const ChainDev& cd, ChainSta
   }
   if (finite && st->cur_bad) dH = -__builtin_inf();  // leaving a state of zero weight
   bool accept;
-  if (cd.replay) {
+  if (cd.replay && t < cd.cap) {
     accept = cd.replay[t] != 0;
   } else {
     const double r = uniform_at(cd, (uint32_t)t, TAG_ACC);

@@ -882,3 +882,48 @@ extern "C" int ihmc_philox_words(ihmc_ctx* ctx, int64_t n, const uint32_t* ctr, 
   if (e2 != hipSuccess) return hip_fail(ctx, e2, "philox sync");
   return IHMC_OK;
 }
+
+// ======================================================== C ABI: measurement ===
+
+extern "C" int ihmc_chains_groups(ihmc_chains* ch, int32_t* n_groups) {
+  if (!ch || !n_groups) return set_error(IHMC_E_INVAL, "NULL argument");
+  *n_groups = (int32_t)((Chains*)ch)->groups.size();
+  return IHMC_OK;
+}
+
+extern "C" int ihmc_chains_time_pass(ihmc_chains* ch, int32_t group, int32_t mode, int32_t reps, double* avg_us,
+                                     int64_t* sites, int32_t* ndim, int32_t* precision) {
+  if (!ch) return set_error(IHMC_E_INVAL, "chains is NULL");
+  Chains* c = (Chains*)ch;
+  ihmc_ctx* ctx = c->ctx;
+  CTX_OK(ctx);
+  if (group < 0 || group >= (int32_t)c->groups.size()) return set_error(IHMC_E_INVAL, "group out of range");
+  if (mode != PASS_FIRST && mode != PASS_MIDDLE) return set_error(IHMC_E_INVAL, "only FIRST and MIDDLE passes can be timed");
+  if (reps < 1) return set_error(IHMC_E_INVAL, "reps must be >= 1");
+  const Group& g = c->groups[group];
+  for (int ci : g.order)
+    if (mode == PASS_MIDDLE && c->cd[ci].n_pass < 3)
+      return set_error(IHMC_E_INVAL, "chain %d has no middle pass", ci);
+  int64_t nsite = 0;
+  for (int ci : g.order) nsite += c->cd[ci].N;
+  hipStream_t s = ctx->stream;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0), "event");
+  HIPCHK(hipEventCreate(&e1), "event");
+  hipError_t e = launch_lattice_pass(g.prec, g.ndim, mode, c->d_cd, c->d_tiles + g.tile_off, g.tile_begin.back(), 1, s);
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  for (int r = 0; e == hipSuccess && r < reps; ++r)
+    e = launch_lattice_pass(g.prec, g.ndim, mode, c->d_cd, c->d_tiles + g.tile_off, g.tile_begin.back(), 1, s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(ctx, e, "time pass");
+  if (avg_us) *avg_us = 1000.0 * ms / reps;
+  if (sites) *sites = nsite;
+  if (ndim) *ndim = g.ndim;
+  if (precision) *precision = g.prec;
+  return IHMC_OK;
+}

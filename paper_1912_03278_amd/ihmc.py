@@ -27,7 +27,8 @@ EXPORTS = (
     "ihmc_ctx_create", "ihmc_ctx_destroy", "ihmc_ctx_stream", "ihmc_ctx_sync", "ihmc_ctx_memory",
     "ihmc_last_error", "ihmc_chains_create", "ihmc_chains_advance", "ihmc_chains_result",
     "ihmc_chains_destroy", "ihmc_run_lattice", "ihmc_run_batch", "ihmc_force", "ihmc_action",
-    "ihmc_integrate", "ihmc_philox_normals", "ihmc_philox_words",
+    "ihmc_integrate", "ihmc_philox_normals", "ihmc_philox_words", "ihmc_chains_groups",
+    "ihmc_chains_time_pass",
 )
 
 
@@ -101,6 +102,9 @@ def load():
     L.ihmc_philox_normals.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int64, _DP]
     L.ihmc_philox_words.argtypes = [vp, C.c_int64, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
                                     C.POINTER(C.c_uint32)]
+    L.ihmc_chains_groups.argtypes = [vp, C.POINTER(C.c_int32)]
+    L.ihmc_chains_time_pass.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     _lib = L
     return L
 
@@ -326,6 +330,18 @@ class Chains:
         r, a = _result_struct(self.runs[i].n_traj, self.lats[i].N, want_psi)
         _check(load().ihmc_chains_result(self.h, int(i), C.byref(r)))
         return _result_dict(r, a)
+
+    def groups(self):
+        n = C.c_int32()
+        _check(load().ihmc_chains_groups(self.h, C.byref(n)))
+        return n.value
+
+    def time_pass(self, group, mode=1, reps=50):
+        """Mean duration (us) of one fused pass launch of a group, timed with HIP events."""
+        us, sites, nd, pr = C.c_double(), C.c_int64(), C.c_int32(), C.c_int32()
+        _check(load().ihmc_chains_time_pass(self.h, int(group), int(mode), int(reps), C.byref(us),
+                                            C.byref(sites), C.byref(nd), C.byref(pr)))
+        return dict(us=us.value, sites=sites.value, ndim=nd.value, precision=pr.value)
 
     def close(self):
         if getattr(self, "h", None):
