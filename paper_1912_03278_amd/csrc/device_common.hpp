@@ -52,6 +52,35 @@ __device__ __forceinline__ double normal_at(const ChainDev& cd, uint32_t traj, u
   return (site & 1) ? r * sin(th) : r * cos(th);
 }
 
+// Both normals of pair i.  FP64 state: FP64 Box-Muller (matches an FP64
+// reference to a few ulp).  FP32 state: the same 53-bit uniforms, Box-Muller
+// in FP32 (sqrt(-2 log u1) and sincospi(2 u2)), accurate to about 2 FP32 ulp.
+template <typename T>
+__device__ __forceinline__ void normal_pair(const ChainDev& cd, uint32_t traj, uint32_t tag, int64_t pair,
+                                            T& z0, T& z1);
+template <>
+__device__ __forceinline__ void normal_pair<double>(const ChainDev& cd, uint32_t traj, uint32_t tag,
+                                                    int64_t pair, double& z0, double& z1) {
+  const uint4 w = draw(cd, (uint32_t)pair, traj, tag);
+  const double u1 = unit53(w.x, w.y), u2 = unit53(w.z, w.w);
+  const double r = sqrt(-2.0 * log(u1));
+  const double th = 6.283185307179586 * u2;
+  z0 = r * cos(th);
+  z1 = r * sin(th);
+}
+template <>
+__device__ __forceinline__ void normal_pair<float>(const ChainDev& cd, uint32_t traj, uint32_t tag,
+                                                   int64_t pair, float& z0, float& z1) {
+  const uint4 w = draw(cd, (uint32_t)pair, traj, tag);
+  const float u1 = (float)unit53(w.x, w.y);
+  const float u2 = (float)unit53(w.z, w.w);
+  const float r = sqrtf(-2.0f * logf(u1));
+  float sn, cs;
+  sincospif(2.0f * u2, &sn, &cs);
+  z0 = r * cs;
+  z1 = r * sn;
+}
+
 __device__ __forceinline__ double uniform_at(const ChainDev& cd, uint32_t traj, uint32_t tag) {
   const uint4 w = draw(cd, 0u, traj, tag);
   return unit53(w.x, w.y);
@@ -120,10 +149,28 @@ __device__ __forceinline__ u128 wave_sum128(u128 v) {
 // Order-independent 128-bit atomic accumulation from two 64-bit atomics: the
 // number of carries out of the low word equals floor(sum of low words / 2^64)
 // whatever the order, so the high word ends up exact.
+// Both RMWs return, so the caller can wait for them to be performed before it
+// publishes completion (see publish_done).
 __device__ __forceinline__ void atomic_add128(uint64_t* slot, u128 v) {
-  const unsigned long long old = atomicAdd((unsigned long long*)&slot[0], (unsigned long long)v.lo);
+  const uint64_t old = __hip_atomic_fetch_add(&slot[0], v.lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const uint64_t carry = (old + v.lo < old) ? 1ull : 0ull;
-  atomicAdd((unsigned long long*)&slot[1], (unsigned long long)(v.hi + carry));
+  (void)__hip_atomic_fetch_add(&slot[1], v.hi + carry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store128_agent(uint64_t* slot, u128 v) {
+  __hip_atomic_store(&slot[0], v.lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&slot[1], v.hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Count one finished block of a chain and tell whether it was the last one.
+// The accumulators are only ever touched by device-scope atomics, so ordering
+// needs no cache write-back: the caller's atomics are made to complete
+// (workgroup-scope release = wait for this wave's outstanding memory
+// operations) before the counter increments.
+__device__ __forceinline__ bool publish_done(uint32_t* done, uint32_t n_blocks) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  const uint32_t prev = __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return prev == n_blocks - 1u;
 }
 
 __device__ __forceinline__ u128 load128_agent(const uint64_t* slot) {

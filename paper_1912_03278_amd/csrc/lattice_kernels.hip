@@ -47,16 +47,10 @@ __device__ __forceinline__ T neg_if(T v, int sign) {
   return sign < 0 ? -v : v;
 }
 
-// Metropolis decision and record, run by one thread of the last block of a LAST pass.
-__device__ __forceinline__ void finalize_trajectory(const ChainDev& cd, ChainState* st, int last_buf) {
-  u128 sum[NTERM];
-#pragma unroll
-  for (int t = 0; t < NTERM; ++t) {
-    sum[t] = u128{0ull, 0ull};
-#pragma unroll 1
-    for (int s = 0; s < NSLOT; ++s) sum[t] = add128(sum[t], load128_agent(st->acc[t][s]));
-  }
-  const uint32_t bad = __hip_atomic_load(&st->bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Metropolis decision and record, run by one thread of the last block of a LAST
+// pass once the block has gathered the chain's accumulators (`sum`, `bad`).
+__device__ __forceinline__ void finalize_trajectory(const ChainDev& cd, ChainState* st, int last_buf,
+                                                    const u128* sum, uint32_t bad) {
   const int t = st->traj;
   const u128 S_old{st->S_lo, st->S_hi};
   const u128 H_old = add128(sum[T_K0], S_old);
@@ -121,42 +115,50 @@ __device__ __forceinline__ void finalize_trajectory(const ChainDev& cd, ChainSta
     cd.rec[t] = rec;
   }
   st->traj = t + 1;
-#pragma unroll 1
-  for (int a = 0; a < NTERM; ++a)
-#pragma unroll 1
-    for (int s = 0; s < NSLOT; ++s) {
-      st->acc[a][s][0] = 0ull;
-      st->acc[a][s][1] = 0ull;
-    }
-  st->bad = 0u;
-  st->done = 0u;
-  __threadfence();
+  __hip_atomic_store(&st->bad, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&st->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void finalize_measure(ChainState* st) {
-  st->cur_bad = __hip_atomic_load(&st->bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1 : 0;
-  u128 sum[NTERM];
-#pragma unroll
-  for (int t = 0; t < NTERM; ++t) {
-    sum[t] = u128{0ull, 0ull};
-#pragma unroll 1
-    for (int s = 0; s < NSLOT; ++s) sum[t] = add128(sum[t], load128_agent(st->acc[t][s]));
-  }
+__device__ __forceinline__ void finalize_measure(ChainState* st, const u128* sum, uint32_t bad) {
+  st->cur_bad = bad ? 1 : 0;
   st->S_lo = sum[T_S].lo;
   st->S_hi = sum[T_S].hi;
   st->sum_psi = fixed_to_double(sum[T_PSI]);
   st->sum_psih = fixed_to_double(sum[T_PSIH]);
   st->sum_ut = fixed_to_double(sum[T_UT]);
+  __hip_atomic_store(&st->bad, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&st->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Last-block epilogue shared by every kernel that closes a trajectory or a
+// measurement: gather the NTERM x NSLOT accumulators with one load per thread,
+// clear them for the next trajectory, and let thread 0 finish.
+template <bool kTraj>
+__device__ __forceinline__ void close_chain(const ChainDev& cd, ChainState* st, int last_buf) {
+  __shared__ u128 sAcc[NTERM][NSLOT];
+  __shared__ uint32_t sBad;
+  const int k = threadIdx.x;
+  if (k < NTERM * NSLOT) {
+    const int a = k / NSLOT, sl = k % NSLOT;
+    sAcc[a][sl] = load128_agent(st->acc[a][sl]);
+  }
+  if (k == 0) sBad = __hip_atomic_load(&st->bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  if (k < NTERM * NSLOT) {
+    const int a = k / NSLOT, sl = k % NSLOT;
+    store128_agent(st->acc[a][sl], u128{0ull, 0ull});
+  }
+  if (k == 0) {
+    u128 sum[NTERM];
+#pragma unroll
+    for (int a = 0; a < NTERM; ++a) {
+      sum[a] = u128{0ull, 0ull};
 #pragma unroll 1
-  for (int a = 0; a < NTERM; ++a)
-#pragma unroll 1
-    for (int s = 0; s < NSLOT; ++s) {
-      st->acc[a][s][0] = 0ull;
-      st->acc[a][s][1] = 0ull;
+      for (int sl = 0; sl < NSLOT; ++sl) sum[a] = add128(sum[a], sAcc[a][sl]);
     }
-  st->bad = 0u;
-  st->done = 0u;
-  __threadfence();
+    if (kTraj) finalize_trajectory(cd, st, last_buf, sum, sBad);
+    else finalize_measure(st, sum, sBad);
+  }
 }
 
 template <typename T, int NDIM, int BX, int BY, int BZ, int MODE>
@@ -230,6 +232,30 @@ __global__ __launch_bounds__(256) void lattice_pass(const ChainDev* __restrict__
     __syncthreads();
   }
 
+  // Momenta of the first pass: one Philox draw feeds the two sites of a pair.
+  // With an even row length a pair never straddles a row, so the tile draws
+  // each pair once and stages both normals in LDS.
+  constexpr bool kMom = (MODE == PASS_FIRST);
+  __shared__ T sMom[kMom ? G::NO : 1];
+  const bool pair_rows = ((L0 & 1) == 0);
+  if (kMom && !cd.p_given && pair_rows) {
+    for (int q = threadIdx.x; q < G::NO / 2; q += 256) {
+      const int o = 2 * q;
+      const int lx = o % BX;
+      const int r = o / BX;
+      const int ly = r % BY;
+      const int lz = r / BY;
+      const int gx = tl.x0 + lx, gy = tl.y0 + ly, gz = tl.z0 + lz;
+      if (gx >= L0 || gy >= L1 || (G::Z3 && gz >= L2)) continue;
+      const int64_t site = gx + (int64_t)L0 * (gy + (int64_t)L1 * gz);
+      T z0, z1;
+      normal_pair<T>(cd, (uint32_t)traj, TAG_MOM, site >> 1, z0, z1);
+      sMom[o] = z0;
+      sMom[o + 1] = z1;
+    }
+    __syncthreads();
+  }
+
   double kick_d = 0.0, drift_d = 0.0;
   pass_coeffs(cd, j, kick_d, drift_d);
   const T kick = (MODE == PASS_FORCE) ? (T)1 : (T)kick_d;
@@ -264,8 +290,12 @@ __global__ __launch_bounds__(256) void lattice_pass(const ChainDev* __restrict__
       if (MODE == PASS_FIRST) {
         if (cd.p_given) {
           p = pmom[site];
+        } else if (pair_rows) {
+          p = sMom[o];
         } else {
-          p = (T)normal_at(cd, (uint32_t)traj, TAG_MOM, site);
+          T z0, z1;
+          normal_pair<T>(cd, (uint32_t)traj, TAG_MOM, site >> 1, z0, z1);
+          p = (site & 1) ? z1 : z0;
         }
         const double pd = (double)p;
         acc[T_K0] = add128(acc[T_K0], to_fixed(0.5 * pd * pd, bad));
@@ -326,7 +356,10 @@ __global__ __launch_bounds__(256) void lattice_pass(const ChainDev* __restrict__
     if (lane == 0) sRed[wave][a] = v;
   }
   // non-finite flags: any lane of any wave
+  __shared__ uint32_t sBadW[4];
   const unsigned long long any_bad = __ballot(bad != 0u);
+  if (lane == 0) sBadW[wave] = any_bad ? 1u : 0u;
+  __shared__ int sLast;
   __syncthreads();
   if (threadIdx.x == 0) {
     const int slot = blockIdx.x % NSLOT;
@@ -334,19 +367,14 @@ __global__ __launch_bounds__(256) void lattice_pass(const ChainDev* __restrict__
       u128 v = add128(add128(sRed[0][a], sRed[1][a]), add128(sRed[2][a], sRed[3][a]));
       atomic_add128(st->acc[a][slot], v);
     }
+    if (sBadW[0] | sBadW[1] | sBadW[2] | sBadW[3])
+      (void)__hip_atomic_fetch_or(&st->bad, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (MODE != PASS_FIRST) sLast = publish_done(&st->done, cd.n_tiles) ? 1 : 0;
   }
-  if (lane == 0 && any_bad) atomicOr(&st->bad, 1u);
   if (MODE == PASS_FIRST) return;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t prev = atomicAdd(&st->done, 1u);
-    if (prev == cd.n_tiles - 1u) {
-      __threadfence();
-      if (MODE == PASS_LAST) finalize_trajectory(cd, st, pass_in_buf(cur, j));
-      else finalize_measure(st);
-    }
-  }
+  if (!sLast) return;
+  close_chain<MODE == PASS_LAST>(cd, st, pass_in_buf(cur, j));
 }
 
 // ------------------------------------------------------------------ launch ---
