@@ -214,7 +214,10 @@ class Context:
                 return int(torch.cuda.caching_allocator_alloc(int(nbytes), device=dev))
 
             def _free(ptr, user):
-                torch.cuda.caching_allocator_delete(int(ptr))
+                # at interpreter shutdown torch may already be torn down
+                tc = getattr(torch, "cuda", None)
+                if tc is not None:
+                    tc.caching_allocator_delete(int(ptr))
 
             af, ff = ALLOC_FN(_alloc), FREE_FN(_free)
         else:
