@@ -648,19 +648,30 @@ static hipError_t launch_mode(int mode, const ChainDev* chains, const Tile* tile
 #define IHMC_3D_ZR 4
 #endif
 
-TileShape tile_shape(int precision, int ndim) {
+int tile_class(int ndim, int L0) {
+  if (ndim == 2) return L0 < 48 ? 1 : 0;
+  return 0;
+}
+
+TileShape tile_shape(int precision, int ndim, int cls) {
   (void)precision;
-  if (ndim == 2) return TileShape{64, 16, 1};
+  if (ndim == 2) return cls == 1 ? TileShape{16, 16, 1} : TileShape{64, 16, 1};
   return TileShape{IHMC_3D_BX, IHMC_3D_BY, IHMC_3D_ZR};
 }
 
-hipError_t launch_lattice_pass(int precision, int ndim, int mode, const ChainDev* chains, const Tile* tiles,
-                               int n_tiles, int j, hipStream_t s) {
+hipError_t launch_lattice_pass(int precision, int ndim, int cls, int mode, const ChainDev* chains,
+                               const Tile* tiles, int n_tiles, int j, hipStream_t s) {
   if (precision == 4) {
-    if (ndim == 2) return launch_mode<float, 2, 64, 16, 1>(mode, chains, tiles, n_tiles, j, s);
+    if (ndim == 2) {
+      if (cls == 1) return launch_mode<float, 2, 16, 16, 1>(mode, chains, tiles, n_tiles, j, s);
+      return launch_mode<float, 2, 64, 16, 1>(mode, chains, tiles, n_tiles, j, s);
+    }
     return launch_mode3s<float, IHMC_3D_BX, IHMC_3D_BY, IHMC_3D_ZR>(mode, chains, tiles, n_tiles, j, s);
   }
-  if (ndim == 2) return launch_mode<double, 2, 64, 16, 1>(mode, chains, tiles, n_tiles, j, s);
+  if (ndim == 2) {
+    if (cls == 1) return launch_mode<double, 2, 16, 16, 1>(mode, chains, tiles, n_tiles, j, s);
+    return launch_mode<double, 2, 64, 16, 1>(mode, chains, tiles, n_tiles, j, s);
+  }
   return launch_mode3s<double, IHMC_3D_BX, IHMC_3D_BY, IHMC_3D_ZR>(mode, chains, tiles, n_tiles, j, s);
 }
 

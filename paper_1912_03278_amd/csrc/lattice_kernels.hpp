@@ -13,13 +13,17 @@ struct TileShape {
   int bx, by, bz;
 };
 
-// Tile extents used for a state precision (4 or 8 bytes) and dimension (2 or 3).
-TileShape tile_shape(int precision, int ndim);
+// Tile-shape class of a lattice (small 2D lattices use smaller tiles).
+int tile_class(int ndim, int L0);
+
+// Tile extents used for a state precision (4 or 8 bytes), dimension (2 or 3)
+// and tile class.
+TileShape tile_shape(int precision, int ndim, int cls);
 
 // Launch one pass of kind `mode` (pass index j of the trajectory) over n_tiles
 // consecutive entries of `tiles`; all tiles must belong to chains of the given
-// precision and dimension.
-hipError_t launch_lattice_pass(int precision, int ndim, int mode, const ChainDev* chains, const Tile* tiles,
-                               int n_tiles, int j, hipStream_t s);
+// precision, dimension and tile class.
+hipError_t launch_lattice_pass(int precision, int ndim, int cls, int mode, const ChainDev* chains,
+                               const Tile* tiles, int n_tiles, int j, hipStream_t s);
 
 }  // namespace ihmc

@@ -12,6 +12,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/ihmc.h"
@@ -455,16 +456,18 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
   }
 
   // ---- groups of equal (precision, ndim), chains sorted by passes (descending)
-  std::map<std::pair<int, int>, std::vector<int>> byk;
-  for (int i = 0; i < n; ++i) byk[{cd[i].precision, cd[i].ndim}].push_back(i);
+  std::map<std::tuple<int, int, int>, std::vector<int>> byk;
+  for (int i = 0; i < n; ++i)
+    byk[std::make_tuple(cd[i].precision, cd[i].ndim, tile_class(cd[i].ndim, cd[i].L0))].push_back(i);
   std::vector<Tile> all_tiles;
   for (auto& kv : byk) {
     Group g;
-    g.prec = kv.first.first;
-    g.ndim = kv.first.second;
+    g.prec = std::get<0>(kv.first);
+    g.ndim = std::get<1>(kv.first);
+    g.cls = std::get<2>(kv.first);
     g.order = kv.second;
     std::stable_sort(g.order.begin(), g.order.end(), [&](int a, int b) { return cd[a].n_pass > cd[b].n_pass; });
-    const TileShape ts = tile_shape(g.prec, g.ndim);
+    const TileShape ts = tile_shape(g.prec, g.ndim, g.cls);
     g.tile_off = (int)all_tiles.size();
     for (int ci : g.order) {
       ChainDev& c = cd[ci];
@@ -535,7 +538,7 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
     HIPCHK(hipGetLastError(), "k_init_psi");
   }
   for (auto& g : groups) {
-    HIPCHK(launch_lattice_pass(g.prec, g.ndim, PASS_MEASURE, d_cd, d_tiles + g.tile_off, g.tile_begin.back(), 0, s),
+    HIPCHK(launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_MEASURE, d_cd, d_tiles + g.tile_off, g.tile_begin.back(), 0, s),
            "measure pass");
   }
   hipError_t e = hipStreamSynchronize(s);
@@ -551,7 +554,7 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
 hipError_t Chains::enqueue_round(hipStream_t s) {
   for (auto& g : groups) {
     const Tile* base = d_tiles + g.tile_off;
-    hipError_t e = launch_lattice_pass(g.prec, g.ndim, PASS_FIRST, d_cd, base, g.tile_begin.back(), 0, s);
+    hipError_t e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_FIRST, d_cd, base, g.tile_begin.back(), 0, s);
     if (e != hipSuccess) return e;
     const int nc = (int)g.order.size();
     for (int j = 1; j < g.max_pass; ++j) {
@@ -560,12 +563,12 @@ hipError_t Chains::enqueue_round(hipStream_t s) {
       int last_end = mid_end;
       while (last_end < nc && g.n_pass[last_end] - 1 == j) ++last_end;
       if (mid_end > 0) {
-        e = launch_lattice_pass(g.prec, g.ndim, PASS_MIDDLE, d_cd, base, g.tile_begin[mid_end], j, s);
+        e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_MIDDLE, d_cd, base, g.tile_begin[mid_end], j, s);
         if (e != hipSuccess) return e;
       }
       if (last_end > mid_end) {
         const int t0 = g.tile_begin[mid_end], t1 = g.tile_begin[last_end];
-        e = launch_lattice_pass(g.prec, g.ndim, PASS_LAST, d_cd, base + t0, t1 - t0, j, s);
+        e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_LAST, d_cd, base + t0, t1 - t0, j, s);
         if (e != hipSuccess) return e;
       }
     }
@@ -752,7 +755,7 @@ extern "C" int ihmc_force(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t precis
   if (rc) return rc;
   hipStream_t s = ctx->stream;
   const Group& g = c->groups[0];
-  hipError_t e = launch_lattice_pass(g.prec, g.ndim, PASS_FORCE, c->d_cd, c->d_tiles, g.tile_begin.back(), 0, s);
+  hipError_t e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_FORCE, c->d_cd, c->d_tiles, g.tile_begin.back(), 0, s);
   const int64_t N = c->cd[0].N;
   double* t = (double*)ctx->arena.alloc(8 * (uint64_t)N);
   if (e == hipSuccess && t) {
@@ -910,10 +913,10 @@ extern "C" int ihmc_chains_time_pass(ihmc_chains* ch, int32_t group, int32_t mod
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0), "event");
   HIPCHK(hipEventCreate(&e1), "event");
-  hipError_t e = launch_lattice_pass(g.prec, g.ndim, mode, c->d_cd, c->d_tiles + g.tile_off, g.tile_begin.back(), 1, s);
+  hipError_t e = launch_lattice_pass(g.prec, g.ndim, g.cls, mode, c->d_cd, c->d_tiles + g.tile_off, g.tile_begin.back(), 1, s);
   if (e == hipSuccess) e = hipEventRecord(e0, s);
   for (int r = 0; e == hipSuccess && r < reps; ++r)
-    e = launch_lattice_pass(g.prec, g.ndim, mode, c->d_cd, c->d_tiles + g.tile_off, g.tile_begin.back(), 1, s);
+    e = launch_lattice_pass(g.prec, g.ndim, g.cls, mode, c->d_cd, c->d_tiles + g.tile_off, g.tile_begin.back(), 1, s);
   if (e == hipSuccess) e = hipEventRecord(e1, s);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float ms = 0.f;

@@ -31,7 +31,7 @@ enum BuildFlags : int { BUILD_P_GIVEN = 1, BUILD_WRITE_P = 2 };
 
 // Chains of equal state precision and dimension share launches.
 struct Group {
-  int prec = 4, ndim = 2;
+  int prec = 4, ndim = 2, cls = 0;
   std::vector<int> order;       // chain indices, sorted by pass count (descending)
   std::vector<int> n_pass;      // pass count per position in `order`
   std::vector<int> tile_begin;  // first tile of each position, relative to tile_off; size+1
