@@ -121,8 +121,8 @@ def bench_batched(args):
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_launch": 20 * dom["sites"], "avg_launch_us": dom["middle_us"]},
         "kernels": kern,
-        "plain": {"chains": len(sample), "value": plain_work / plain_time, "unit": "site-MD-steps/s",
-                  "bitwise_equal_to_batched": identical},
+        "plain": {"chains": len(sample), "value": (plain_work / plain_time) if plain_time > 0 else None,
+                  "unit": "site-MD-steps/s", "bitwise_equal_to_batched": identical if sample else None},
         "acceptance_sample_mean": float(np.mean(acc)),
         "setup_s": round(t_setup, 2),
         "cpu_baseline": None,

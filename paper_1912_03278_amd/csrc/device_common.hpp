@@ -54,7 +54,7 @@ __device__ __forceinline__ double normal_at(const ChainDev& cd, uint32_t traj, u
 
 // Both normals of pair i.  FP64 state: FP64 Box-Muller (matches an FP64
 // reference to a few ulp).  FP32 state: the same 53-bit uniforms, Box-Muller
-// in FP32 (sqrt(-2 log u1) and sincospi(2 u2)), accurate to about 2 FP32 ulp.
+// in FP32 with the hardware log2 / sin / cos (absolute error ~1e-6).
 template <typename T>
 __device__ __forceinline__ void normal_pair(const ChainDev& cd, uint32_t traj, uint32_t tag, int64_t pair,
                                             T& z0, T& z1);
@@ -74,11 +74,11 @@ __device__ __forceinline__ void normal_pair<float>(const ChainDev& cd, uint32_t 
   const uint4 w = draw(cd, (uint32_t)pair, traj, tag);
   const float u1 = (float)unit53(w.x, w.y);
   const float u2 = (float)unit53(w.z, w.w);
-  const float r = sqrtf(-2.0f * logf(u1));
-  float sn, cs;
-  sincospif(2.0f * u2, &sn, &cs);
-  z0 = r * cs;
-  z1 = r * sn;
+  // -2 ln u1 = -2 ln2 log2(u1); the hardware sine/cosine take revolutions,
+  // so sin(2 pi u2) needs no range reduction for u2 in (0, 1)
+  const float r = __builtin_sqrtf(-1.38629436111989061f * __builtin_amdgcn_logf(u1));
+  z0 = r * __builtin_amdgcn_cosf(u2);
+  z1 = r * __builtin_amdgcn_sinf(u2);
 }
 
 __device__ __forceinline__ double uniform_at(const ChainDev& cd, uint32_t traj, uint32_t tag) {
@@ -108,24 +108,33 @@ __host__ __device__ __forceinline__ u128 neg128(u128 a) {
 
 __host__ __device__ __forceinline__ u128 sub128(u128 a, u128 b) { return add128(a, neg128(b)); }
 
-// Magnitude limit of one term; larger or non-finite terms set `bad`.
-constexpr double kFixedLimit = 268435456.0;  // 2^28
 
-// round(x * 2^64) as a signed 128-bit integer.  |x| < 2^28: the integer part
-// goes to `hi`, the fraction times 2^64 (exact: a power-of-two scaling of an
-// exactly computed fraction) to `lo`.
+// round(x * 2^64) (ties away from zero) as a signed 128-bit integer, from the
+// bit pattern: |x| = m 2^e with a 53-bit integer m, so |x| 2^64 = m 2^(e+64)
+// is m shifted left or right.  |x| < 2^28 keeps any sum of up to 2^34 terms
+// inside the 128-bit range; larger or non-finite terms set `bad`.
 __device__ __forceinline__ u128 to_fixed(double x, uint32_t& bad) {
-  const double ax = fabs(x);
-  if (!(ax < kFixedLimit)) {
-    bad = 1u;
-    return u128{0ull, 0ull};
-  }
-  const double ip = floor(ax);
-  const double fr = (ax - ip) * 18446744073709551616.0;
+  // branch-free: every case is computed and selected, so the conversions of a
+  // wave never split into divergent paths
+  const uint64_t bits = (uint64_t)__double_as_longlong(x);
+  const int ex = (int)((bits >> 52) & 0x7ffu);
+  const bool too_big = (ex >= 1023 + 28);  // |x| >= 2^28, inf or nan
+  bad |= too_big ? 1u : 0u;
+  const uint64_t m = (ex == 0 || too_big) ? 0ull : ((bits & 0x000fffffffffffffull) | 0x0010000000000000ull);
+  const int sh = ex - 1011;  // |x| 2^64 = m 2^sh, sh <= 39
+  const int k = -sh;
+  const uint64_t left_lo = m << (sh & 63);
+  const uint64_t left_hi = m >> ((64 - sh) & 63);
+  const uint64_t rnd = 1ull << ((k - 1) & 63);
+  const uint64_t right = (m + rnd) >> (k & 63);
   u128 r;
-  r.hi = (uint64_t)ip;
-  r.lo = (uint64_t)rint(fr);
-  return x < 0.0 ? neg128(r) : r;
+  r.lo = (sh >= 0) ? left_lo : ((k < 64) ? right : 0ull);
+  r.hi = (sh > 0) ? left_hi : 0ull;
+  const u128 n = neg128(r);
+  const bool neg = (bits >> 63) != 0ull;
+  r.lo = neg ? n.lo : r.lo;
+  r.hi = neg ? n.hi : r.hi;
+  return r;
 }
 
 __host__ __device__ __forceinline__ double fixed_to_double(u128 v) {
@@ -146,20 +155,37 @@ __device__ __forceinline__ u128 wave_sum128(u128 v) {
   return v;
 }
 
-// Order-independent 128-bit atomic accumulation from two 64-bit atomics: the
-// number of carries out of the low word equals floor(sum of low words / 2^64)
-// whatever the order, so the high word ends up exact.
-// Both RMWs return, so the caller can wait for them to be performed before it
-// publishes completion (see publish_done).
-__device__ __forceinline__ void atomic_add128(uint64_t* slot, u128 v) {
-  const uint64_t old = __hip_atomic_fetch_add(&slot[0], v.lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const uint64_t carry = (old + v.lo < old) ? 1ull : 0ull;
-  (void)__hip_atomic_fetch_add(&slot[1], v.hi + carry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Order-independent accumulation of 128-bit values with plain 64-bit atomic
+// adds: a value is split into three limbs of 42 bits, V = l0 + l1 2^42 + l2 2^84
+// with l0, l1 in [0, 2^42) and l2 = V >> 84 (arithmetic).  Each limb goes to its
+// own 64-bit word, so no carry has to travel between words while blocks add
+// (a word absorbs 2^22 additions), every add is fire-and-forget, and the words
+// are recombined exactly when the sum is read.
+__device__ __forceinline__ void atomic_add_limbs(uint64_t* slot, u128 v) {
+  const uint64_t m42 = (1ull << 42) - 1ull;
+  const uint64_t l0 = v.lo & m42;
+  const uint64_t l1 = ((v.lo >> 42) | (v.hi << 22)) & m42;
+  const uint64_t l2 = (uint64_t)((int64_t)v.hi >> 20);
+  __hip_atomic_fetch_add(&slot[0], l0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_add(&slot[1], l1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_add(&slot[2], l2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void store128_agent(uint64_t* slot, u128 v) {
-  __hip_atomic_store(&slot[0], v.lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(&slot[1], v.hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ u128 load_limbs_agent(const uint64_t* slot) {
+  const uint64_t l0 = __hip_atomic_load(&slot[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint64_t l1 = __hip_atomic_load(&slot[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint64_t l2 = __hip_atomic_load(&slot[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // V = l0 + l1 2^42 + l2 2^84 (l0, l1 non-negative sums, l2 a signed sum)
+  u128 r{l0, 0ull};
+  r = add128(r, u128{l1 << 42, l1 >> 22});
+  r = add128(r, u128{0ull, l2 << 20});
+  return r;
+}
+
+__device__ __forceinline__ void clear_limbs_agent(uint64_t* slot) {
+  __hip_atomic_store(&slot[0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&slot[1], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&slot[2], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Count one finished block of a chain and tell whether it was the last one.
@@ -173,12 +199,6 @@ __device__ __forceinline__ bool publish_done(uint32_t* done, uint32_t n_blocks) 
   return prev == n_blocks - 1u;
 }
 
-__device__ __forceinline__ u128 load128_agent(const uint64_t* slot) {
-  u128 r;
-  r.lo = __hip_atomic_load(&slot[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  r.hi = __hip_atomic_load(&slot[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return r;
-}
 
 // ------------------------------------------------------------- functions ---
 
@@ -194,11 +214,61 @@ __device__ __forceinline__ float tanh_state(float x) {
 
 __device__ __forceinline__ double tanh_state(double x) { return tanh(x); }
 
-// log cosh(y) = |y| + log1p(e^{-2|y|}) - ln 2 and tanh(y), sharing one exponential.
+// log cosh(y) = |y| + log1p(e) - ln 2 and tanh(y) = sign(y) (1 - e)/(1 + e)
+// with e = exp(-2|y|) in [0, 1], in FP64:
+//   exp: Cody-Waite reduction x = k ln2 + r, |r| <= ln2/2, Taylor polynomial of
+//        degree 13 (truncation < 5e-18), then 2^k;
+//   log1p(e) = 2 atanh(s), s = e/(2+e) (e <= sqrt2 - 1) or
+//        ln 2 + 2 atanh((e-1)/(e+3)) (e > sqrt2 - 1), so |s| <= 0.1716 and the
+//        odd series to s^23 is below 1e-18 relative.
+// Agrees with correctly rounded log cosh / tanh to a few ulp.
+__device__ __forceinline__ double exp_nonpos(double x) {
+  const bool under = (x < -745.0);
+  x = under ? 0.0 : x;
+  const double k = rint(x * 1.4426950408889634);
+  double r = __builtin_fma(-k, 6.93147180369123816490e-01, x);
+  r = __builtin_fma(-k, 1.90821492927058770002e-10, r);
+  double p = 1.6059043836821614e-10;  // 1/13!
+  p = __builtin_fma(p, r, 2.0876756987868099e-09);
+  p = __builtin_fma(p, r, 2.5052108385441720e-08);
+  p = __builtin_fma(p, r, 2.7557319223985893e-07);
+  p = __builtin_fma(p, r, 2.7557319223985888e-06);
+  p = __builtin_fma(p, r, 2.4801587301587302e-05);
+  p = __builtin_fma(p, r, 1.9841269841269841e-04);
+  p = __builtin_fma(p, r, 1.3888888888888889e-03);
+  p = __builtin_fma(p, r, 8.3333333333333332e-03);
+  p = __builtin_fma(p, r, 4.1666666666666664e-02);
+  p = __builtin_fma(p, r, 1.6666666666666666e-01);
+  p = __builtin_fma(p, r, 0.5);
+  p = __builtin_fma(p, r, 1.0);
+  p = __builtin_fma(p, r, 1.0);
+  return under ? 0.0 : ldexp(p, (int)k);
+}
+
+__device__ __forceinline__ double log1p_unit(double e) {
+  const bool hi = (e > 0.41421356237309503);
+  const double s = (hi ? e - 1.0 : e) / (hi ? e + 3.0 : 2.0 + e);
+  const double off = hi ? 0.6931471805599453 : 0.0;
+  const double z = s * s;
+  double q = 1.0 / 23.0;
+  q = __builtin_fma(q, z, 1.0 / 21.0);
+  q = __builtin_fma(q, z, 1.0 / 19.0);
+  q = __builtin_fma(q, z, 1.0 / 17.0);
+  q = __builtin_fma(q, z, 1.0 / 15.0);
+  q = __builtin_fma(q, z, 1.0 / 13.0);
+  q = __builtin_fma(q, z, 1.0 / 11.0);
+  q = __builtin_fma(q, z, 1.0 / 9.0);
+  q = __builtin_fma(q, z, 1.0 / 7.0);
+  q = __builtin_fma(q, z, 1.0 / 5.0);
+  q = __builtin_fma(q, z, 1.0 / 3.0);
+  q = q * z;  // atanh(s)/s - 1
+  return off + 2.0 * __builtin_fma(s, q, s);
+}
+
 __device__ __forceinline__ void logcosh_tanh(double y, double& lc, double& t) {
   const double a = fabs(y);
-  const double e = exp(-2.0 * a);
-  lc = a + log1p(e) - 0.6931471805599453;
+  const double e = exp_nonpos(-2.0 * a);
+  lc = (a - 0.6931471805599453) + log1p_unit(e);
   t = copysign((1.0 - e) / (1.0 + e), y);
 }
 

@@ -34,7 +34,7 @@ enum : uint32_t { REC_ACCEPT = 1u, REC_FLIP = 2u, REC_NONFINITE = 4u };
 
 // Mutable per-chain state, updated on the device by the finalising block.
 struct ChainState {
-  uint64_t acc[NTERM][NSLOT][2];  // fixed-point accumulators of the running trajectory
+  uint64_t acc[NTERM][NSLOT][3];  // fixed-point accumulators (42-bit limbs) of the running trajectory
   uint64_t S_lo, S_hi;            // S(psi_cur), fixed point
   double sum_psi, sum_psih, sum_ut;  // estimator sums of psi_cur
   int32_t cur;    // buffer (0..2) holding the accepted field
@@ -50,7 +50,10 @@ struct ChainState {
 // Immutable per-chain parameters (FP64 constants; kernels round what they need).
 struct ChainDev {
   int32_t ndim, L0, L1, L2;
-  int64_t N;
+  int64_t N;             // lattice sites
+  int32_t pitch;         // row pitch of the stored fields (L0 rounded up to 4)
+  int32_t pad0;
+  int64_t NP;            // stored elements per field: pitch * L1 * L2
   int32_t n_pass;      // force evaluations per trajectory
   int32_t integrator;
   int32_t flip_every;
@@ -62,14 +65,20 @@ struct ChainDev {
   int32_t precision;     // 4 or 8 (bytes of the state type)
   int32_t p_given;       // first pass reads p instead of drawing it (diagnostic)
   int32_t write_p_last;  // last pass stores the final momenta (diagnostic)
-  void* psi;             // 3 * N state values (three rotating buffers)
-  void* p;               // N state values
-  const void* b;         // N state values h'/sqrt(J') (per-site field) or null
-  const double* hp;      // N FP64 h' (per-site field) or null
+  void* psi;             // 3 * NP state values (three rotating buffers)
+  void* p;               // NP state values
+  const void* b;         // NP state values h'/sqrt(J') (per-site field) or null
+  const double* hp;      // NP FP64 h' (per-site field) or null
   TrajRecord* rec;       // cap records
   const uint8_t* replay; // forced decisions (test hook) or null
   ChainState* st;
 };
+
+// Stored index of logical site i = x + L0 (y + L1 z).
+inline __host__ __device__ int64_t stored_index(const ChainDev& cd, int64_t i) {
+  const int64_t x = i % cd.L0, r = i / cd.L0;
+  return x + (int64_t)cd.pitch * r;
+}
 
 // One work tile of a lattice pass.
 struct Tile {

@@ -2,39 +2,31 @@
 //
 // One pass = one force evaluation of the equations of motion (Sec. 3):
 //     u = Kt psi,  w = sqrt(J') tanh(sqrt(J') u) - psi,  F = Kt w + h'/sqrt(J'),
-// followed by the kick p += c_j F and the drift psi' = psi + d_j p.  Because F
-// at a site needs psi on the radius-2 diamond around it, a workgroup stages its
-// tile plus a 2-wide halo of psi in LDS, computes w on the tile plus a 1-wide
-// halo, and then F, p and psi' on the tile: every pass reads psi (and p) once
-// and writes p and psi' once from HBM.
+// followed by the kick p += c_j F and the drift psi' = psi + d_j p.  F at a
+// site needs psi on the radius-2 diamond around it, so a workgroup stages psi
+// on its tile plus a 2-wide halo in LDS, computes w on the tile plus a 1-wide
+// halo, and then F, p and psi' on the tile: every pass reads psi, p (and the
+// per-site field) once and writes p and psi' once.
 //
 // Pass kinds (template MODE):
 //   FIRST   - momenta from Philox (Sec. 3, eq. momentum distribution), 1/2 p^2
 //             accumulated for H_old, first kick and drift;
 //   MIDDLE  - kick and drift;
 //   LAST    - final kick, then the FP64 Hamiltonian and estimator sums of the
-//             proposal; the last block to finish takes the Metropolis decision
-//             (Sec. 3) and writes the trajectory record (Sec. 4 estimators);
+//             proposal; the block that finishes last takes the Metropolis
+//             decision (Sec. 3) and writes the trajectory record;
 //   MEASURE - FP64 action and estimator sums of the accepted field (set-up);
 //   FORCE   - writes F itself (diagnostic; same arithmetic as the other passes).
 //
-// Sums are exact 128-bit fixed point (device_common.hpp), so every result is
-// independent of the tile shape and of which chains share a launch.
+// Memory layout: rows padded to `pitch` (a multiple of 4 elements), so a thread
+// of the 2D kernel moves its four sites with 16-byte vector accesses.  Sums are
+// exact 128-bit fixed point (device_common.hpp): results do not depend on the
+// tile shape or on which chains share a launch.
+#include "chain_epilogue.hpp"
 #include "device_common.hpp"
 #include "lattice_kernels.hpp"
 
 namespace ihmc {
-
-template <int NDIM, int BX, int BY, int BZ>
-struct Geom {
-  static constexpr int Z3 = (NDIM == 3) ? 1 : 0;
-  static constexpr int PX = BX + 4, PY = BY + 4, PZ = Z3 ? BZ + 4 : 1;
-  static constexpr int WX = BX + 2, WY = BY + 2, WZ = Z3 ? BZ + 2 : 1;
-  static constexpr int NP = PX * PY * PZ;
-  static constexpr int NW = WX * WY * WZ;
-  static constexpr int BZE = Z3 ? BZ : 1;
-  static constexpr int NO = BX * BY * BZE;
-};
 
 __device__ __forceinline__ int wrap_near(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
 __device__ __forceinline__ int wrap_any(int v, int L) {
@@ -47,246 +39,182 @@ __device__ __forceinline__ T neg_if(T v, int sign) {
   return sign < 0 ? -v : v;
 }
 
-// Metropolis decision and record, run by one thread of the last block of a LAST
-// pass once the block has gathered the chain's accumulators (`sum`, `bad`).
-__device__ __forceinline__ void finalize_trajectory(const ChainDev& cd, ChainState* st, int last_buf,
-                                                    const u128* sum, uint32_t bad) {
-  const int t = st->traj;
-  const u128 S_old{st->S_lo, st->S_hi};
-  const u128 H_old = add128(sum[T_K0], S_old);
-  const u128 H_new = add128(sum[T_K1], sum[T_S]);
-  double dH = fixed_to_double(sub128(H_new, H_old));
-  uint32_t flags = 0u;
-  bool finite = (bad == 0u);
-  if (!finite) {
-    dH = __builtin_nan("");
-    flags |= REC_NONFINITE;
-    st->n_nonfinite += 1;
-  }
-  if (finite && st->cur_bad) dH = -__builtin_inf();  // leaving a state of zero weight
-  bool accept;
-  if (cd.replay && t < cd.cap) {
-    accept = cd.replay[t] != 0;
-  } else {
-    const double r = uniform_at(cd, (uint32_t)t, TAG_ACC);
-    accept = finite && (dH <= 0.0 || r < exp(-dH));
-  }
-  if (finite && !st->cur_bad) st->sum_exp_mdh += exp(-dH);
-  if (accept) {
-    st->cur_bad = 0;
-    st->S_lo = sum[T_S].lo;
-    st->S_hi = sum[T_S].hi;
-    st->sum_psi = fixed_to_double(sum[T_PSI]);
-    st->sum_psih = fixed_to_double(sum[T_PSIH]);
-    st->sum_ut = fixed_to_double(sum[T_UT]);
-    st->cur = last_buf;
-    st->sign = 1;
-    st->n_acc += 1;
-    flags |= REC_ACCEPT;
-  }
-  if (cd.flip_every > 0 && (t + 1) % cd.flip_every == 0) {
-    // S(-psi) - S(psi) = 2 psi.h'/sqrt(J'): only the linear field term changes.
-    const double dS = 2.0 * st->sum_psih / cd.sqJ;
-    const double r2 = uniform_at(cd, (uint32_t)t, TAG_FLIP);
-    if (dS <= 0.0 || r2 < exp(-dS)) {
-      uint32_t b2 = 0u;
-      const u128 S = add128(u128{st->S_lo, st->S_hi}, to_fixed(dS, b2));
-      st->S_lo = S.lo;
-      st->S_hi = S.hi;
-      st->sign = -st->sign;
-      st->sum_psi = -st->sum_psi;
-      st->sum_psih = -st->sum_psih;
-      flags |= REC_FLIP;
-    }
-  }
-  if (t < cd.cap) {
-    const double N = (double)cd.N;
-    TrajRecord rec;
-    rec.dH = dH;
-    rec.H_old = fixed_to_double(H_old);
-    rec.H_new = fixed_to_double(H_new);
-    rec.m = (st->sum_psi / cd.sqJ - cd.c_m / cd.Jp) / N;
-    rec.abs_m = fabs(rec.m);
-    rec.m2c = rec.m * rec.m - cd.c_v / (N * N * cd.Jp);
-    rec.beta_eps = 0.5 * cd.C * cd.Jp + cd.c_e / (2.0 * N * cd.Jp) - st->sum_psih / (2.0 * N * cd.sqJ) -
-                   cd.sqJ / (2.0 * N) * st->sum_ut;
-    rec.flags = flags;
-    rec.pad = 0u;
-    cd.rec[t] = rec;
-  }
-  st->traj = t + 1;
-  __hip_atomic_store(&st->bad, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(&st->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Four consecutive state values (16 bytes for FP32, 32 bytes for FP64).
+template <typename T>
+__device__ __forceinline__ void ld4(const T* __restrict__ p, T (&v)[4]);
+template <>
+__device__ __forceinline__ void ld4<float>(const float* __restrict__ p, float (&v)[4]) {
+  const float4 q = *reinterpret_cast<const float4*>(p);
+  v[0] = q.x;
+  v[1] = q.y;
+  v[2] = q.z;
+  v[3] = q.w;
+}
+template <>
+__device__ __forceinline__ void ld4<double>(const double* __restrict__ p, double (&v)[4]) {
+  const double2 a = reinterpret_cast<const double2*>(p)[0];
+  const double2 b = reinterpret_cast<const double2*>(p)[1];
+  v[0] = a.x;
+  v[1] = a.y;
+  v[2] = b.x;
+  v[3] = b.y;
+}
+template <typename T>
+__device__ __forceinline__ void st4(T* __restrict__ p, const T (&v)[4]);
+template <>
+__device__ __forceinline__ void st4<float>(float* __restrict__ p, const float (&v)[4]) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+template <>
+__device__ __forceinline__ void st4<double>(double* __restrict__ p, const double (&v)[4]) {
+  reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
+  reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
 }
 
-__device__ __forceinline__ void finalize_measure(ChainState* st, const u128* sum, uint32_t bad) {
-  st->cur_bad = bad ? 1 : 0;
-  st->S_lo = sum[T_S].lo;
-  st->S_hi = sum[T_S].hi;
-  st->sum_psi = fixed_to_double(sum[T_PSI]);
-  st->sum_psih = fixed_to_double(sum[T_PSIH]);
-  st->sum_ut = fixed_to_double(sum[T_UT]);
-  __hip_atomic_store(&st->bad, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(&st->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// FP64 action and estimator terms of one site of the stored field: the integer
+// stencil weights are exact, C and sqrt(J') are the true FP64 constants.
+//   h[0]  S-density   1/2 psi u - psi h'/sqrt(J') - log cosh(sqrt(J') u)
+//   h[1]  psi
+//   h[2]  psi h'
+//   h[3]  u tanh(sqrt(J') u)
+// `act` = the site belongs to the lattice (a quad may reach into the row
+// padding, a column into the plane padding): inactive sites give exact zeros.
+__device__ __forceinline__ void h_terms(const ChainDev& cd, double v, double nb, int64_t idx, bool act,
+                                        double (&h)[4]) {
+  const double u = cd.C * v + nb;
+  double lc, th;
+  logcosh_tanh(cd.sqJ * u, lc, th);
+  double hpx = cd.hp0, bx = cd.b0;
+  if (cd.h_kind == 2) {
+    hpx = cd.hp[idx];
+    bx = hpx / cd.sqJ;
+  }
+  h[0] = act ? 0.5 * v * u - v * bx - lc : 0.0;
+  h[1] = act ? v : 0.0;
+  h[2] = act ? v * hpx : 0.0;
+  h[3] = act ? u * th : 0.0;
 }
 
-// Last-block epilogue shared by every kernel that closes a trajectory or a
-// measurement: gather the NTERM x NSLOT accumulators with one load per thread,
-// clear them for the next trajectory, and let thread 0 finish.
-template <bool kTraj>
-__device__ __forceinline__ void close_chain(const ChainDev& cd, ChainState* st, int last_buf) {
-  __shared__ u128 sAcc[NTERM][NSLOT];
-  __shared__ uint32_t sBad;
-  const int k = threadIdx.x;
-  if (k < NTERM * NSLOT) {
-    const int a = k / NSLOT, sl = k % NSLOT;
-    sAcc[a][sl] = load128_agent(st->acc[a][sl]);
-  }
-  if (k == 0) sBad = __hip_atomic_load(&st->bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  if (k < NTERM * NSLOT) {
-    const int a = k / NSLOT, sl = k % NSLOT;
-    store128_agent(st->acc[a][sl], u128{0ull, 0ull});
-  }
-  if (k == 0) {
-    u128 sum[NTERM];
-#pragma unroll
-    for (int a = 0; a < NTERM; ++a) {
-      sum[a] = u128{0ull, 0ull};
-#pragma unroll 1
-      for (int sl = 0; sl < NSLOT; ++sl) sum[a] = add128(sum[a], sAcc[a][sl]);
-    }
-    if (kTraj) finalize_trajectory(cd, st, last_buf, sum, sBad);
-    else finalize_measure(st, sum, sBad);
-  }
+// Site terms are summed per quad of four x-aligned sites (x = 4q .. 4q+3) as
+// (t0 + t1) + (t2 + t3) in FP64 and converted to fixed point once per quad.
+// Quads are the same in every tiling, so the totals stay tile-independent.
+__device__ __forceinline__ double quad_sum(double t0, double t1, double t2, double t3) {
+  return (t0 + t1) + (t2 + t3);
 }
 
-// Block reduction of the per-thread fixed-point sums, order-independent
-// accumulation into the chain, and the last block's epilogue.
-template <int MODE>
-__device__ __forceinline__ void block_accumulate(const ChainDev& cd, ChainState* st, const u128* acc,
-                                                 uint32_t bad, u128 (*sRed)[NTERM], int cur, int j) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  constexpr int t_lo = (MODE == PASS_FIRST) ? T_K0 : ((MODE == PASS_MEASURE) ? T_S : T_K1);
-  constexpr int t_hi = (MODE == PASS_FIRST) ? T_K0 : T_UT;
-#pragma unroll
-  for (int a = t_lo; a <= t_hi; ++a) {
-    const u128 v = wave_sum128(acc[a]);
-    if (lane == 0) sRed[wave][a] = v;
-  }
-  // non-finite flags: any lane of any wave
-  __shared__ uint32_t sBadW[4];
-  const unsigned long long any_bad = __ballot(bad != 0u);
-  if (lane == 0) sBadW[wave] = any_bad ? 1u : 0u;
-  __shared__ int sLast;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int slot = blockIdx.x % NSLOT;
-    for (int a = t_lo; a <= t_hi; ++a) {
-      u128 v = add128(add128(sRed[0][a], sRed[1][a]), add128(sRed[2][a], sRed[3][a]));
-      atomic_add128(st->acc[a][slot], v);
-    }
-    if (sBadW[0] | sBadW[1] | sBadW[2] | sBadW[3])
-      (void)__hip_atomic_fetch_or(&st->bad, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (MODE != PASS_FIRST) sLast = publish_done(&st->done, cd.n_tiles) ? 1 : 0;
-  }
-  if (MODE == PASS_FIRST) return;
-  __syncthreads();
-  if (!sLast) return;
-  close_chain<MODE == PASS_LAST>(cd, st, pass_in_buf(cur, j));
+// The same quad sum across four consecutive lanes holding x = 4q .. 4q+3
+// (FP addition is commutative, so every lane of the quad forms the identical
+// value; lane 4q keeps it, the other three return zero).
+__device__ __forceinline__ double quad_sum_lanes(double t) {
+  t = t + __shfl_xor(t, 1, 64);
+  t = t + __shfl_xor(t, 2, 64);
+  return ((threadIdx.x & 3) == 0) ? t : 0.0;
 }
 
-template <typename T, int NDIM, int BX, int BY, int BZ, int MODE>
-__global__ __launch_bounds__(256) void lattice_pass(const ChainDev* __restrict__ chains,
-                                                    const Tile* __restrict__ tiles, int j) {
-  using G = Geom<NDIM, BX, BY, BZ>;
+// --------------------------------------------------------------------- 2D ---
+//
+// Tile BX x BY, one thread per quad of four consecutive x (NT = BX/4 * BY).
+// LDS rows have pitch RP = BX + 8 with lattice x at index x - x0 + 4, so the
+// psi halo [x0-2, x0+BX+2) sits inside one 16-byte aligned row and global and
+// LDS traffic moves in aligned quads.  p and the per-site field are fetched
+// before the LDS phases so their latency overlaps the stencil work.
+template <typename T, int BX, int BY, int MODE>
+__global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __restrict__ chains,
+                                                              const Tile* __restrict__ tiles, int j) {
+  constexpr int QX = BX / 4;
+  constexpr int NT = QX * BY;
+  constexpr int NWAVE = (NT + 63) / 64;
+  constexpr int RP = BX + 8;
+  constexpr int PR = BY + 4;
+  constexpr int WR = BY + 2;
+  constexpr int NWS = (BX + 2) * WR;
+  constexpr int NCH = RP / 4;  // 16-byte chunks per staged row
   constexpr bool kHasW = (MODE != PASS_MEASURE);
   constexpr bool kH64 = (MODE == PASS_LAST || MODE == PASS_MEASURE);
-  __shared__ T sP[G::NP];
-  __shared__ T sW[kHasW ? G::NW : 1];
-  __shared__ u128 sRed[4][NTERM];
+  static_assert(BX % 4 == 0 && NT % 64 == 0, "tile shape");
+  __shared__ __align__(16) T sP[PR * RP];
+  __shared__ __align__(16) T sW[kHasW ? WR * RP : 4];
 
   const Tile tl = tiles[blockIdx.x];
   const ChainDev& cd = chains[tl.chain];
   ChainState* st = cd.st;
-  const int L0 = cd.L0, L1 = cd.L1, L2 = cd.L2;
-  const int64_t N = cd.N;
+  const int L0 = cd.L0, L1 = cd.L1, pitch = cd.pitch;
+  const int64_t NP = cd.NP;
   const int cur = st->cur;
   const int sign = st->sign;
   const int traj = st->traj;
   const bool from_cur = (MODE == PASS_FIRST || MODE == PASS_MEASURE || MODE == PASS_FORCE);
   const int in_buf = from_cur ? cur : pass_in_buf(cur, j);
   const int out_buf = pass_out_buf(cur, j);
-  const T* __restrict__ pin = (const T*)cd.psi + (int64_t)in_buf * N;
-  T* __restrict__ pout = (T*)cd.psi + (int64_t)out_buf * N;
+  const T* __restrict__ pin = (const T*)cd.psi + (int64_t)in_buf * NP;
+  T* __restrict__ pout = (T*)cd.psi + (int64_t)out_buf * NP;
   T* __restrict__ pmom = (T*)cd.p;
+  const bool site_field = (cd.h_kind == 2);
 
-  // ---- stage psi on the tile plus a 2-wide halo (periodic wrap)
-  const bool near = (L0 > BX) && (L1 > BY) && (NDIM == 2 || L2 > BZ);
-  for (int i = threadIdx.x; i < G::NP; i += 256) {
-    const int lx = i % G::PX;
-    const int r = i / G::PX;
-    const int ly = r % G::PY;
-    const int lz = r / G::PY;
-    int gx = tl.x0 + lx - 2, gy = tl.y0 + ly - 2, gz = G::Z3 ? tl.z0 + lz - 2 : 0;
-    if (near) {
-      gx = wrap_near(gx, L0);
-      gy = wrap_near(gy, L1);
-      if (G::Z3) gz = wrap_near(gz, L2);
+  const int t = threadIdx.x;
+  const int qx = t % QX, qy = t / QX;
+  const int gx = tl.x0 + 4 * qx, gy = tl.y0 + qy;
+  const bool quad_ok = (gx < L0) && (gy < L1);  // the quad's first site is a lattice site
+  const int64_t base = gx + (int64_t)pitch * gy;  // gx + 3 < pitch when quad_ok
+
+  // ---- prefetch p and the field of the quad
+  T pq[4] = {(T)0, (T)0, (T)0, (T)0};
+  T bq[4];
+  const T b_uniform = (T)cd.b0;
+  bq[0] = bq[1] = bq[2] = bq[3] = b_uniform;
+  if (quad_ok) {
+    if (MODE == PASS_MIDDLE || MODE == PASS_LAST || (MODE == PASS_FIRST && cd.p_given)) ld4<T>(pmom + base, pq);
+    if (kHasW && site_field) ld4<T>((const T*)cd.b + base, bq);
+  }
+
+  // ---- stage psi on the tile plus its halo, in aligned 4-element chunks:
+  // a chunk inside [0, L0) is one vector load, a chunk crossing the periodic
+  // wrap (or the row end) is gathered element by element.
+  const bool rows_near = (L1 > BY);
+  for (int i = t; i < PR * NCH; i += NT) {
+    const int r = i / NCH, c = i % NCH;
+    const int yy = rows_near ? wrap_near(tl.y0 + r - 2, L1) : wrap_any(tl.y0 + r - 2, L1);
+    const T* row = pin + (int64_t)pitch * yy;
+    const int x = tl.x0 - 4 + 4 * c;
+    T v[4];
+    if (x >= 0 && x + 4 <= L0) {
+      ld4<T>(row + x, v);
     } else {
-      gx = wrap_any(gx, L0);
-      gy = wrap_any(gy, L1);
-      if (G::Z3) gz = wrap_any(gz, L2);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = row[wrap_any(x + e, L0)];
     }
-    const int64_t g = gx + (int64_t)L0 * (gy + (int64_t)L1 * gz);
-    T v = pin[g];
-    if (from_cur) v = neg_if(v, sign);
-    sP[i] = v;
+    if (from_cur) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = neg_if(v[e], sign);
+    }
+    st4<T>(sP + r * RP + 4 * c, v);
   }
   __syncthreads();
 
   const T Ct = (T)cd.C;
   const T at = (T)cd.sqJ;
-  constexpr int SP = G::PX * G::PY;
-  constexpr int SW = G::WX * G::WY;
 
-  // ---- w = sqrt(J') tanh(sqrt(J') Kt psi) - psi on the tile plus a 1-wide halo
+  // ---- w on the rows y in [-1, BY], in quads over x in [-4, BX+4): the
+  // outermost quads hold unused values (their stencil reaches past the staged
+  // halo) but keep every LDS access aligned
   if (kHasW) {
-    for (int i = threadIdx.x; i < G::NW; i += 256) {
-      const int wx = i % G::WX;
-      const int r = i / G::WX;
-      const int wy = r % G::WY;
-      const int wz = r / G::WY;
-      const int pc = (wx + 1) + G::PX * ((wy + 1) + G::PY * (wz + G::Z3));
-      const T c = sP[pc];
-      T s = (sP[pc - 1] + sP[pc + 1]) + (sP[pc - G::PX] + sP[pc + G::PX]);
-      if (G::Z3) s = s + (sP[pc - SP] + sP[pc + SP]);
-      const T u = fma_t(Ct, c, s);
-      sW[i] = fma_t(at, tanh_state(at * u), -c);
-    }
-    __syncthreads();
-  }
-
-  // Momenta of the first pass: one Philox draw feeds the two sites of a pair.
-  // With an even row length a pair never straddles a row, so the tile draws
-  // each pair once and stages both normals in LDS.
-  constexpr bool kMom = (MODE == PASS_FIRST);
-  __shared__ T sMom[kMom ? G::NO : 1];
-  const bool pair_rows = ((L0 & 1) == 0);
-  if (kMom && !cd.p_given && pair_rows) {
-    for (int q = threadIdx.x; q < G::NO / 2; q += 256) {
-      const int o = 2 * q;
-      const int lx = o % BX;
-      const int r = o / BX;
-      const int ly = r % BY;
-      const int lz = r / BY;
-      const int gx = tl.x0 + lx, gy = tl.y0 + ly, gz = tl.z0 + lz;
-      if (gx >= L0 || gy >= L1 || (G::Z3 && gz >= L2)) continue;
-      const int64_t site = gx + (int64_t)L0 * (gy + (int64_t)L1 * gz);
-      T z0, z1;
-      normal_pair<T>(cd, (uint32_t)traj, TAG_MOM, site >> 1, z0, z1);
-      sMom[o] = z0;
-      sMom[o + 1] = z1;
+    for (int i = t; i < WR * NCH; i += NT) {
+      const int wy = i / NCH, c = i % NCH;
+      const int pc = (wy + 1) * RP + 4 * c;  // psi at (x = -4 + 4c, y = wy - 1)
+      T cv[4], up[4], dn[4], w[4];
+      ld4<T>(sP + pc, cv);
+      ld4<T>(sP + pc - RP, up);
+      ld4<T>(sP + pc + RP, dn);
+      const T lft = sP[pc - 1], rgt = sP[pc + 4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const T xm = (e == 0) ? lft : cv[e - 1];
+        const T xp = (e == 3) ? rgt : cv[e + 1];
+        const T s = (xm + xp) + (up[e] + dn[e]);
+        const T u = fma_t(Ct, cv[e], s);
+        w[e] = fma_t(at, tanh_state(at * u), -cv[e]);
+      }
+      st4<T>(sW + wy * RP + 4 * c, w);
     }
     __syncthreads();
   }
@@ -295,100 +223,92 @@ __global__ __launch_bounds__(256) void lattice_pass(const ChainDev* __restrict__
   pass_coeffs(cd, j, kick_d, drift_d);
   const T kick = (MODE == PASS_FORCE) ? (T)1 : (T)kick_d;
   const T drift = (T)drift_d;
-  const T b_uniform = (T)cd.b0;
-  const T* __restrict__ bsite = (const T*)cd.b;
-  const bool site_field = (cd.h_kind == 2);
 
   uint32_t bad = 0u;
   u128 acc[NTERM];
 #pragma unroll
   for (int a = 0; a < NTERM; ++a) acc[a] = u128{0ull, 0ull};
 
-  auto site_body = [&](int o) {
-    const int lx = o % BX;
-    const int r = o / BX;
-    const int ly = r % BY;
-    const int lz = r / BY;
-    const int gx = tl.x0 + lx, gy = tl.y0 + ly, gz = tl.z0 + lz;
-    if (gx >= L0 || gy >= L1 || (G::Z3 && gz >= L2)) return;
-    const int64_t site = gx + (int64_t)L0 * (gy + (int64_t)L1 * gz);
-    const int pc = (lx + 2) + G::PX * ((ly + 2) + G::PY * (lz + 2 * G::Z3));
-    const T c = sP[pc];
-    T pn = (T)0;
-    if (kHasW) {
-      const int wc = (lx + 1) + G::WX * ((ly + 1) + G::WY * (lz + G::Z3));
-      T sw = (sW[wc - 1] + sW[wc + 1]) + (sW[wc - G::WX] + sW[wc + G::WX]);
-      if (G::Z3) sw = sw + (sW[wc - SW] + sW[wc + SW]);
-      T F = fma_t(Ct, sW[wc], sw);
-      F = F + (site_field ? bsite[site] : b_uniform);
-      T p;
-      if (MODE == PASS_FIRST) {
-        if (cd.p_given) {
-          p = pmom[site];
-        } else if (pair_rows) {
-          p = sMom[o];
-        } else {
-          T z0, z1;
-          normal_pair<T>(cd, (uint32_t)traj, TAG_MOM, site >> 1, z0, z1);
-          p = (site & 1) ? z1 : z0;
-        }
-        const double pd = (double)p;
-        acc[T_K0] = add128(acc[T_K0], to_fixed(0.5 * pd * pd, bad));
-      } else if (MODE == PASS_FORCE) {
-        p = (T)0;
+  if (quad_ok) {
+    // momenta of the first pass: one Philox draw per site pair; with an even
+    // row length a pair never straddles a row
+    if (MODE == PASS_FIRST && !cd.p_given) {
+      const int64_t s0 = gx + (int64_t)L0 * gy;  // logical site of the quad's first element
+      if ((L0 & 1) == 0) {
+        normal_pair<T>(cd, (uint32_t)traj, TAG_MOM, s0 >> 1, pq[0], pq[1]);
+        normal_pair<T>(cd, (uint32_t)traj, TAG_MOM, (s0 >> 1) + 1, pq[2], pq[3]);
       } else {
-        p = pmom[site];
-      }
-      pn = fma_t(kick, F, p);
-      if (MODE == PASS_FIRST || MODE == PASS_MIDDLE) {
-        pmom[site] = pn;
-        pout[site] = fma_t(drift, pn, c);
-      } else if (MODE == PASS_FORCE) {
-        pmom[site] = pn;
-      } else if (MODE == PASS_LAST) {
-        if (cd.write_p_last) pmom[site] = pn;
-        const double pd = (double)pn;
-        acc[T_K1] = add128(acc[T_K1], to_fixed(0.5 * pd * pd, bad));
-      }
-    }
-    if (kH64) {
-      // FP64 action terms of the field as stored: the integer stencil weights
-      // are exact, C and sqrt(J') are the true FP64 constants.
-      const double cdv = (double)c;
-      double nb = ((double)sP[pc - 1] + (double)sP[pc + 1]) + ((double)sP[pc - G::PX] + (double)sP[pc + G::PX]);
-      if (G::Z3) nb = nb + ((double)sP[pc - SP] + (double)sP[pc + SP]);
-      const double u = cd.C * cdv + nb;
-      double lc, th;
-      logcosh_tanh(cd.sqJ * u, lc, th);
-      double hpx = cd.hp0, bx = cd.b0;
-      if (site_field) {
-        hpx = cd.hp[site];
-        bx = hpx / cd.sqJ;
-      }
-      acc[T_S] = add128(acc[T_S], to_fixed(0.5 * cdv * u - cdv * bx - lc, bad));
-      acc[T_PSI] = add128(acc[T_PSI], to_fixed(cdv, bad));
-      acc[T_PSIH] = add128(acc[T_PSIH], to_fixed(cdv * hpx, bad));
-      acc[T_UT] = add128(acc[T_UT], to_fixed(u * th, bad));
-    }
-  };
-  if constexpr (MODE == PASS_MIDDLE || MODE == PASS_FORCE) {
 #pragma unroll
-    for (int o = threadIdx.x; o < G::NO; o += 256) site_body(o);
-  } else {
-#pragma unroll 1
-    for (int o = threadIdx.x; o < G::NO; o += 256) site_body(o);
+        for (int e = 0; e < 4; ++e) {
+          T z0, z1;
+          normal_pair<T>(cd, (uint32_t)traj, TAG_MOM, (s0 + e) >> 1, z0, z1);
+          pq[e] = ((s0 + e) & 1) ? z1 : z0;
+        }
+      }
+    }
+    T pn[4], pv[4];
+    const int pc0 = (qy + 2) * RP + 4 * qx + 4;  // psi of the quad's first site
+    const int wc0 = (qy + 1) * RP + 4 * qx + 4;  // w of the quad's first site
+    T cv[4];
+    ld4<T>(sP + pc0, cv);
+    T wcv[4], wup[4], wdn[4];
+    if (kHasW) {
+      ld4<T>(sW + wc0, wcv);
+      ld4<T>(sW + wc0 - RP, wup);
+      ld4<T>(sW + wc0 + RP, wdn);
+    }
+    double kin[4];
+    double ht[4][4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const bool act = (gx + e < L0);
+      const T c = cv[e];
+      pv[e] = c;
+      pn[e] = pq[e];
+      kin[e] = 0.0;
+      if (kHasW) {
+        const T wm = (e == 0) ? sW[wc0 - 1] : wcv[e - 1];
+        const T wp = (e == 3) ? sW[wc0 + 4] : wcv[e + 1];
+        const T sw = (wm + wp) + (wup[e] + wdn[e]);
+        const T F = fma_t(Ct, wcv[e], sw) + bq[e];
+        pn[e] = fma_t(kick, F, (MODE == PASS_FORCE) ? (T)0 : pq[e]);
+        pv[e] = fma_t(drift, pn[e], c);
+        const double pd = (double)((MODE == PASS_FIRST) ? pq[e] : pn[e]);
+        kin[e] = act ? 0.5 * pd * pd : 0.0;
+      }
+      if (kH64) {
+        const int pc = pc0 + e;
+        const double nb = ((double)sP[pc - 1] + (double)sP[pc + 1]) + ((double)sP[pc - RP] + (double)sP[pc + RP]);
+        h_terms(cd, (double)c, nb, base + e, act, ht[e]);
+      }
+    }
+    if (MODE == PASS_FIRST)
+      acc[T_K0] = add128(acc[T_K0], to_fixed(quad_sum(kin[0], kin[1], kin[2], kin[3]), bad));
+    if (MODE == PASS_LAST)
+      acc[T_K1] = add128(acc[T_K1], to_fixed(quad_sum(kin[0], kin[1], kin[2], kin[3]), bad));
+    if (kH64) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        acc[T_S + a] = add128(acc[T_S + a], to_fixed(quad_sum(ht[0][a], ht[1][a], ht[2][a], ht[3][a]), bad));
+    }
+    if (MODE == PASS_FIRST || MODE == PASS_MIDDLE) {
+      st4<T>(pmom + base, pn);
+      st4<T>(pout + base, pv);
+    } else if (MODE == PASS_FORCE || (MODE == PASS_LAST && cd.write_p_last)) {
+      st4<T>(pmom + base, pn);
+    }
   }
 
   if (MODE == PASS_MIDDLE || MODE == PASS_FORCE) return;
-  block_accumulate<MODE>(cd, st, acc, bad, sRed, cur, j);
+  block_accumulate<MODE, NWAVE>(cd, st, acc, bad, cur, j, blockIdx.x % NSLOT);
 }
 
-
-// 3D passes as a 2.5D stream: a block owns a BX x BY column of the xy plane
-// and walks z over [z0, z0 + ZR).  A ring of five psi planes (2-wide xy halo)
-// and three w planes (1-wide halo) stays in LDS, so each psi value is read
-// from memory (ZR + 4) / ZR times and each w is computed (BX+2)(BY+2)/(BX BY)
-// times, instead of staging a full 3D halo box per tile.  Step z computes
+// --------------------------------------------------------------------- 3D ---
+//
+// A 2.5D stream: a block owns a BX x BY column of the xy plane and walks z
+// over [z0, z0 + ZR).  A ring of five psi planes (2-wide xy halo) and three w
+// planes (1-wide halo) stays in LDS, so each psi value is read (ZR + 4) / ZR
+// times and each w computed (BX+2)(BY+2)/(BX BY) times.  Step z computes
 // w(z+1) and the update of plane z while the loads of plane z+3 are in flight.
 template <typename T, int BX, int BY, int ZR, int MODE>
 __global__ __launch_bounds__(256) void lattice_pass3s(const ChainDev* __restrict__ chains,
@@ -400,22 +320,21 @@ __global__ __launch_bounds__(256) void lattice_pass3s(const ChainDev* __restrict
   constexpr bool kH64 = (MODE == PASS_LAST || MODE == PASS_MEASURE);
   __shared__ T sP[5][PP];
   __shared__ T sW[kHasW ? 3 : 1][kHasW ? WP : 1];
-  __shared__ u128 sRed[4][NTERM];
 
   const Tile tl = tiles[blockIdx.x];
   const ChainDev& cd = chains[tl.chain];
   ChainState* st = cd.st;
-  const int L0 = cd.L0, L1 = cd.L1, L2 = cd.L2;
-  const int64_t N = cd.N;
-  const int64_t plane = (int64_t)L0 * L1;
+  const int L0 = cd.L0, L1 = cd.L1, L2 = cd.L2, pitch = cd.pitch;
+  const int64_t NP = cd.NP;
+  const int64_t plane = (int64_t)pitch * L1;
   const int cur = st->cur;
   const int sign = st->sign;
   const int traj = st->traj;
   const bool from_cur = (MODE == PASS_FIRST || MODE == PASS_MEASURE || MODE == PASS_FORCE);
   const int in_buf = from_cur ? cur : pass_in_buf(cur, j);
   const int out_buf = pass_out_buf(cur, j);
-  const T* __restrict__ pin = (const T*)cd.psi + (int64_t)in_buf * N;
-  T* __restrict__ pout = (T*)cd.psi + (int64_t)out_buf * N;
+  const T* __restrict__ pin = (const T*)cd.psi + (int64_t)in_buf * NP;
+  T* __restrict__ pout = (T*)cd.psi + (int64_t)out_buf * NP;
   T* __restrict__ pmom = (T*)cd.p;
   const int z_end = min(tl.z0 + ZR, L2);
   const bool near_xy = (L0 > BX) && (L1 > BY);
@@ -432,14 +351,10 @@ __global__ __launch_bounds__(256) void lattice_pass3s(const ChainDev* __restrict
 
   // Plane z (any integer in [z0-2, z_end+2]) of psi: fetch_plane issues the
   // global loads into registers, store_plane moves them to ring slot
-  // (z - z0 + 2) % 5.  Splitting the two lets the loads of plane z+3 overlap
-  // the compute of plane z.
+  // (z - z0 + 2) % 5.
   constexpr int NPRE = (PP + 255) / 256;
-  auto fetch_plane = [&](int z, T (&pre)[NPRE]) {
-    int gz = z;
-    if (gz < 0) gz += L2;
-    else if (gz >= L2) gz -= L2;
-    if (gz < 0 || gz >= L2) gz = wrap_any(z, L2);
+  auto fetch_plane = [&](int z, T(&pre)[NPRE]) {
+    const int gz = wrap_any(z, L2);
     const T* src = pin + (int64_t)gz * plane;
 #pragma unroll
     for (int k = 0; k < NPRE; ++k) {
@@ -454,13 +369,13 @@ __global__ __launch_bounds__(256) void lattice_pass3s(const ChainDev* __restrict
           gx = wrap_any(gx, L0);
           gy = wrap_any(gy, L1);
         }
-        T v = src[gx + (int64_t)L0 * gy];
+        T v = src[gx + (int64_t)pitch * gy];
         if (from_cur) v = neg_if(v, sign);
         pre[k] = v;
       }
     }
   };
-  auto store_plane = [&](int z, const T (&pre)[NPRE]) {
+  auto store_plane = [&](int z, const T(&pre)[NPRE]) {
     T* dst = sP[(z - tl.z0 + 2) % 5];
 #pragma unroll
     for (int k = 0; k < NPRE; ++k) {
@@ -517,63 +432,61 @@ __global__ __launch_bounds__(256) void lattice_pass3s(const ChainDev* __restrict
     const T* __restrict__ wm = sW[kHasW ? (z - 1 - tl.z0 + 3) % 3 : 0];
     const T* __restrict__ wc = sW[kHasW ? (z - tl.z0 + 3) % 3 : 0];
     const T* __restrict__ wp = sW[kHasW ? (z + 1 - tl.z0 + 3) % 3 : 0];
+    static_assert(BX % 4 == 0 && NO % 256 == 0, "3D tile shape");
+#pragma unroll 1
     for (int o = threadIdx.x; o < NO; o += 256) {
       const int lx = o % BX, ly = o / BX;
       const int gx = tl.x0 + lx, gy = tl.y0 + ly;
-      if (gx >= L0 || gy >= L1) continue;
-      const int64_t site = gx + (int64_t)L0 * (gy + (int64_t)L1 * z);
+      const bool act = (gx < L0) && (gy < L1);
+      const int64_t idx = gx + (int64_t)pitch * gy + plane * z;
       const int c = (lx + 2) + PX * (ly + 2);
       const T v = pc[c];
-      if (kHasW) {
+      double kin = 0.0;
+      if (kHasW && act) {
         const int q = (lx + 1) + WX * (ly + 1);
         T sw = (wc[q - 1] + wc[q + 1]) + (wc[q - WX] + wc[q + WX]);
         sw = sw + (wm[q] + wp[q]);
         T F = fma_t(Ct, wc[q], sw);
-        F = F + (site_field ? bsite[site] : b_uniform);
+        F = F + (site_field ? bsite[idx] : b_uniform);
         T p;
         if (MODE == PASS_FIRST) {
           if (cd.p_given) {
-            p = pmom[site];
+            p = pmom[idx];
           } else {
+            const int64_t site = gx + (int64_t)L0 * (gy + (int64_t)L1 * z);
             T z0, z1;
             normal_pair<T>(cd, (uint32_t)traj, TAG_MOM, site >> 1, z0, z1);
             p = (site & 1) ? z1 : z0;
           }
           const double pd = (double)p;
-          acc[T_K0] = add128(acc[T_K0], to_fixed(0.5 * pd * pd, bad));
+          kin = 0.5 * pd * pd;
         } else if (MODE == PASS_FORCE) {
           p = (T)0;
         } else {
-          p = pmom[site];
+          p = pmom[idx];
         }
         const T pn = fma_t(kick, F, p);
         if (MODE == PASS_FIRST || MODE == PASS_MIDDLE) {
-          pmom[site] = pn;
-          pout[site] = fma_t(drift, pn, v);
+          pmom[idx] = pn;
+          pout[idx] = fma_t(drift, pn, v);
         } else if (MODE == PASS_FORCE) {
-          pmom[site] = pn;
+          pmom[idx] = pn;
         } else if (MODE == PASS_LAST) {
-          if (cd.write_p_last) pmom[site] = pn;
+          if (cd.write_p_last) pmom[idx] = pn;
           const double pd = (double)pn;
-          acc[T_K1] = add128(acc[T_K1], to_fixed(0.5 * pd * pd, bad));
+          kin = 0.5 * pd * pd;
         }
       }
+      // every lane reaches the quad sums (the shuffles need the whole wave)
+      if (MODE == PASS_FIRST) acc[T_K0] = add128(acc[T_K0], to_fixed(quad_sum_lanes(kin), bad));
+      if (MODE == PASS_LAST) acc[T_K1] = add128(acc[T_K1], to_fixed(quad_sum_lanes(kin), bad));
       if (kH64) {
-        const double cdv = (double)v;
+        double ht[4];
         double nb = ((double)pc[c - 1] + (double)pc[c + 1]) + ((double)pc[c - PX] + (double)pc[c + PX]);
         nb = nb + ((double)pm[c] + (double)pp[c]);
-        const double u = cd.C * cdv + nb;
-        double lc, th;
-        logcosh_tanh(cd.sqJ * u, lc, th);
-        double hpx = cd.hp0, bx = cd.b0;
-        if (site_field) {
-          hpx = cd.hp[site];
-          bx = hpx / cd.sqJ;
-        }
-        acc[T_S] = add128(acc[T_S], to_fixed(0.5 * cdv * u - cdv * bx - lc, bad));
-        acc[T_PSI] = add128(acc[T_PSI], to_fixed(cdv, bad));
-        acc[T_PSIH] = add128(acc[T_PSIH], to_fixed(cdv * hpx, bad));
-        acc[T_UT] = add128(acc[T_UT], to_fixed(u * th, bad));
+        h_terms(cd, (double)v, nb, act ? idx : 0, act, ht);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) acc[T_S + a] = add128(acc[T_S + a], to_fixed(quad_sum_lanes(ht[a]), bad));
       }
     }
     // plane z+3 replaces plane z-2, which no later step reads
@@ -582,10 +495,37 @@ __global__ __launch_bounds__(256) void lattice_pass3s(const ChainDev* __restrict
   }
 
   if (MODE == PASS_MIDDLE || MODE == PASS_FORCE) return;
-  block_accumulate<MODE>(cd, st, acc, bad, sRed, cur, j);
+  block_accumulate<MODE, 4>(cd, st, acc, bad, cur, j, blockIdx.x % NSLOT);
 }
 
 // ------------------------------------------------------------------ launch ---
+
+template <typename T, int BX, int BY>
+static hipError_t launch_mode2v(int mode, const ChainDev* chains, const Tile* tiles, int n_tiles, int j,
+                                hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  dim3 grid(n_tiles), block(BX / 4 * BY);
+  switch (mode) {
+    case PASS_FIRST:
+      lattice_pass2v<T, BX, BY, PASS_FIRST><<<grid, block, 0, s>>>(chains, tiles, j);
+      break;
+    case PASS_MIDDLE:
+      lattice_pass2v<T, BX, BY, PASS_MIDDLE><<<grid, block, 0, s>>>(chains, tiles, j);
+      break;
+    case PASS_LAST:
+      lattice_pass2v<T, BX, BY, PASS_LAST><<<grid, block, 0, s>>>(chains, tiles, j);
+      break;
+    case PASS_MEASURE:
+      lattice_pass2v<T, BX, BY, PASS_MEASURE><<<grid, block, 0, s>>>(chains, tiles, j);
+      break;
+    case PASS_FORCE:
+      lattice_pass2v<T, BX, BY, PASS_FORCE><<<grid, block, 0, s>>>(chains, tiles, j);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 template <typename T, int BX, int BY, int ZR>
 static hipError_t launch_mode3s(int mode, const ChainDev* chains, const Tile* tiles, int n_tiles, int j,
@@ -614,34 +554,13 @@ static hipError_t launch_mode3s(int mode, const ChainDev* chains, const Tile* ti
   return hipGetLastError();
 }
 
-template <typename T, int NDIM, int BX, int BY, int BZ>
-static hipError_t launch_mode(int mode, const ChainDev* chains, const Tile* tiles, int n_tiles, int j,
-                              hipStream_t s) {
-  if (n_tiles <= 0) return hipSuccess;
-  dim3 grid(n_tiles), block(256);
-  switch (mode) {
-    case PASS_FIRST:
-      lattice_pass<T, NDIM, BX, BY, BZ, PASS_FIRST><<<grid, block, 0, s>>>(chains, tiles, j);
-      break;
-    case PASS_MIDDLE:
-      lattice_pass<T, NDIM, BX, BY, BZ, PASS_MIDDLE><<<grid, block, 0, s>>>(chains, tiles, j);
-      break;
-    case PASS_LAST:
-      lattice_pass<T, NDIM, BX, BY, BZ, PASS_LAST><<<grid, block, 0, s>>>(chains, tiles, j);
-      break;
-    case PASS_MEASURE:
-      lattice_pass<T, NDIM, BX, BY, BZ, PASS_MEASURE><<<grid, block, 0, s>>>(chains, tiles, j);
-      break;
-    case PASS_FORCE:
-      lattice_pass<T, NDIM, BX, BY, BZ, PASS_FORCE><<<grid, block, 0, s>>>(chains, tiles, j);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-// 3D column tiles: BX x BY in the plane, streamed over ZR planes.
+// 2D tiles: 64 x 16 (256 threads) for rows of 48 sites or more, 16 x 16
+// (64 threads) for small lattices.  3D column tiles: BX x BY in the plane,
+// streamed over ZR planes.
+#ifndef IHMC_2D_BX
+#define IHMC_2D_BX 64
+#define IHMC_2D_BY 16
+#endif
 #ifndef IHMC_3D_BX
 #define IHMC_3D_BX 32
 #define IHMC_3D_BY 8
@@ -655,7 +574,7 @@ int tile_class(int ndim, int L0) {
 
 TileShape tile_shape(int precision, int ndim, int cls) {
   (void)precision;
-  if (ndim == 2) return cls == 1 ? TileShape{16, 16, 1} : TileShape{64, 16, 1};
+  if (ndim == 2) return cls == 1 ? TileShape{16, 16, 1} : TileShape{IHMC_2D_BX, IHMC_2D_BY, 1};
   return TileShape{IHMC_3D_BX, IHMC_3D_BY, IHMC_3D_ZR};
 }
 
@@ -663,14 +582,14 @@ hipError_t launch_lattice_pass(int precision, int ndim, int cls, int mode, const
                                const Tile* tiles, int n_tiles, int j, hipStream_t s) {
   if (precision == 4) {
     if (ndim == 2) {
-      if (cls == 1) return launch_mode<float, 2, 16, 16, 1>(mode, chains, tiles, n_tiles, j, s);
-      return launch_mode<float, 2, 64, 16, 1>(mode, chains, tiles, n_tiles, j, s);
+      if (cls == 1) return launch_mode2v<float, 16, 16>(mode, chains, tiles, n_tiles, j, s);
+      return launch_mode2v<float, IHMC_2D_BX, IHMC_2D_BY>(mode, chains, tiles, n_tiles, j, s);
     }
     return launch_mode3s<float, IHMC_3D_BX, IHMC_3D_BY, IHMC_3D_ZR>(mode, chains, tiles, n_tiles, j, s);
   }
   if (ndim == 2) {
-    if (cls == 1) return launch_mode<double, 2, 16, 16, 1>(mode, chains, tiles, n_tiles, j, s);
-    return launch_mode<double, 2, 64, 16, 1>(mode, chains, tiles, n_tiles, j, s);
+    if (cls == 1) return launch_mode2v<double, 16, 16>(mode, chains, tiles, n_tiles, j, s);
+    return launch_mode2v<double, IHMC_2D_BX, IHMC_2D_BY>(mode, chains, tiles, n_tiles, j, s);
   }
   return launch_mode3s<double, IHMC_3D_BX, IHMC_3D_BY, IHMC_3D_ZR>(mode, chains, tiles, n_tiles, j, s);
 }

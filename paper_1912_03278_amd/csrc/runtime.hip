@@ -89,13 +89,16 @@ void Arena::release(void* p) {
 
 // ---------------------------------------------------------- set-up kernels ---
 
+// h' = beta h (FP64) and h'/sqrt(J') (state precision) at the stored indices.
 template <typename T>
-__global__ void k_field_setup(double* hp, T* b, int64_t N, double beta, double sqJ) {
+__global__ void k_field_setup(const ChainDev* cds, int ci, const double* h, double beta) {
+  const ChainDev& cd = cds[ci];
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const double v = beta * hp[i];
-  hp[i] = v;
-  b[i] = (T)(v / sqJ);
+  if (i >= cd.N) return;
+  const int64_t k = stored_index(cd, i);
+  const double hp = beta * h[i];
+  ((double*)cd.hp)[k] = hp;
+  ((T*)cd.b)[k] = (T)(hp / cd.sqJ);
 }
 
 template <typename T>
@@ -104,13 +107,15 @@ __global__ void k_init_psi(const ChainDev* cds, int ci, const double* psi0) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= cd.N) return;
   T* psi = (T*)cd.psi;
-  psi[i] = psi0 ? (T)psi0[i] : (T)normal_at(cd, 0u, TAG_INIT, i);
+  psi[stored_index(cd, i)] = psi0 ? (T)psi0[i] : (T)normal_at(cd, 0u, TAG_INIT, i);
 }
 
+// Logical <-> stored layout of one field (p or F).
 template <typename T>
-__global__ void k_import(T* dst, const double* src, int64_t N) {
+__global__ void k_import(const ChainDev* cds, int ci, T* dst, const double* src) {
+  const ChainDev& cd = cds[ci];
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < N) dst[i] = (T)src[i];
+  if (i < cd.N) dst[stored_index(cd, i)] = (T)src[i];
 }
 
 template <typename T>
@@ -119,14 +124,15 @@ __global__ void k_export_psi(const ChainDev* cds, int ci, double* out) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= cd.N) return;
   const ChainState* st = cd.st;
-  const double v = (double)((const T*)cd.psi)[(int64_t)st->cur * cd.N + i];
+  const double v = (double)((const T*)cd.psi)[(int64_t)st->cur * cd.NP + stored_index(cd, i)];
   out[i] = st->sign < 0 ? -v : v;
 }
 
 template <typename T>
-__global__ void k_export(double* dst, const T* src, int64_t N) {
+__global__ void k_export(const ChainDev* cds, int ci, double* dst, const T* src) {
+  const ChainDev& cd = cds[ci];
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < N) dst[i] = (double)src[i];
+  if (i < cd.N) dst[i] = (double)src[stored_index(cd, i)];
 }
 
 __global__ void k_zero_state(ChainState* st) {
@@ -191,14 +197,15 @@ __global__ __launch_bounds__(256) void k_field_cg(ChainDev* cds, const int* whic
   double* r = x + N;
   double* d = r + N;
   double* q = d + N;
-  const double* hp = cd.hp;
+  const double* hp = cd.hp;  // stored layout; the CG vectors use the logical one
   double hs = 0.0, rr = 0.0;
   for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
+    const double v = hp[stored_index(cd, i)];
     x[i] = 0.0;
-    r[i] = hp[i];
-    d[i] = hp[i];
-    hs += hp[i];
-    rr += hp[i] * hp[i];
+    r[i] = v;
+    d[i] = v;
+    hs += v;
+    rr += v * v;
   }
   hs = block_sum(hs, sh);
   rr = block_sum(rr, sh);
@@ -224,7 +231,7 @@ __global__ __launch_bounds__(256) void k_field_cg(ChainDev* cds, const int* whic
   }
   __syncthreads();
   double ce = 0.0;
-  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) ce += hp[i] * x[i];
+  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) ce += hp[stored_index(cd, i)] * x[i];
   ce = block_sum(ce, sh);
   if (threadIdx.x == 0) {
     cd.c_e = ce;
@@ -356,6 +363,8 @@ void* Chains::dalloc(uint64_t bytes) {
 Chains::~Chains() {
   if (gexec) hipGraphExecDestroy(gexec);
   if (graph) hipGraphDestroy(graph);
+  for (hipEvent_t ev : events) hipEventDestroy(ev);
+  for (hipStream_t st : side) hipStreamDestroy(st);
   for (void* p : allocs) ctx->arena.release(p);
 }
 
@@ -392,6 +401,8 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
     c.L1 = l.L[1];
     c.L2 = l.ndim == 3 ? l.L[2] : 1;
     c.N = lattice_sites(l);
+    c.pitch = (c.L0 + 3) & ~3;
+    c.NP = (int64_t)c.pitch * c.L1 * c.L2;
     c.integrator = r.integrator;
     c.n_pass = r.integrator == OMELYAN ? 2 * r.n_md + 1 : r.n_md + 1;
     c.flip_every = r.flip_every;
@@ -414,10 +425,10 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
     c.precision = r.precision;
     c.p_given = (flags & BUILD_P_GIVEN) ? 1 : 0;
     c.write_p_last = (flags & BUILD_WRITE_P) ? 1 : 0;
-    const int64_t N = c.N;
+    const int64_t N = c.N, NP = c.NP;
     const int64_t pb = r.precision;
-    c.psi = dalloc(3 * N * pb);
-    c.p = dalloc(N * pb);
+    c.psi = dalloc(3 * NP * pb);
+    c.p = dalloc(NP * pb);
     c.rec = (TrajRecord*)dalloc(sizeof(TrajRecord) * (uint64_t)std::max(1, r.n_traj));
     c.st = (ChainState*)dalloc(sizeof(ChainState));
     if (!c.psi || !c.p || !c.rec || !c.st) {
@@ -435,17 +446,12 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
       c.replay = d;
     }
     if (c.h_kind == 2) {
-      double* hp = (double*)dalloc(8 * N);
-      void* b = dalloc(N * pb);
-      if (!hp || !b) {
+      c.hp = (double*)dalloc(8 * NP);
+      c.b = dalloc(NP * pb);
+      if (!c.hp || !c.b) {
         cleanup();
         return set_error(IHMC_E_NOMEM, "chain %d: arena exhausted", i);
       }
-      HIPCHK(hipMemcpyAsync(hp, l.h, 8 * N, hipMemcpyHostToDevice, s), "h upload");
-      if (pb == 4) k_field_setup<float><<<nblk(N), 256, 0, s>>>(hp, (float*)b, N, l.beta, c.sqJ);
-      else k_field_setup<double><<<nblk(N), 256, 0, s>>>(hp, (double*)b, N, l.beta, c.sqJ);
-      c.hp = hp;
-      c.b = b;
     }
     k_zero_state<<<1, 256, 0, s>>>(c.st);
   }
@@ -486,6 +492,21 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
     g.max_pass = cd[g.order[0]].n_pass;
     groups.push_back(g);
   }
+  // streams and events of the per-round fork/join (default priority)
+  {
+    size_t n_ev = 1;
+    for (auto& g : groups) n_ev += (size_t)g.max_pass + 2;
+    for (size_t k = 0; k < 2 * groups.size(); ++k) {
+      hipStream_t st = nullptr;
+      HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "side stream");
+      side.push_back(st);
+    }
+    for (size_t k = 0; k < n_ev; ++k) {
+      hipEvent_t ev = nullptr;
+      HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
+      events.push_back(ev);
+    }
+  }
   d_tiles = (Tile*)dalloc(sizeof(Tile) * all_tiles.size());
   if (!d_tiles) {
     cleanup();
@@ -494,6 +515,21 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
   HIPCHK(hipMemcpyAsync(d_tiles, all_tiles.data(), sizeof(Tile) * all_tiles.size(), hipMemcpyHostToDevice, s),
          "tile upload");
   HIPCHK(hipMemcpyAsync(d_cd, cd.data(), sizeof(ChainDev) * (uint64_t)n, hipMemcpyHostToDevice, s), "chain upload");
+
+  // ---- per-site fields into the stored layout
+  for (int i = 0; i < n; ++i) {
+    if (cd[i].h_kind != 2) continue;
+    const int64_t N = cd[i].N;
+    double* t = (double*)tmp_alloc(8 * (uint64_t)N);
+    if (!t) {
+      cleanup();
+      return set_error(IHMC_E_NOMEM, "arena exhausted (field staging)");
+    }
+    HIPCHK(hipMemcpyAsync(t, lats[i].h, 8 * N, hipMemcpyHostToDevice, s), "h upload");
+    if (cd[i].precision == 4) k_field_setup<float><<<nblk(N), 256, 0, s>>>(d_cd, i, t, lats[i].beta);
+    else k_field_setup<double><<<nblk(N), 256, 0, s>>>(d_cd, i, t, lats[i].beta);
+    HIPCHK(hipGetLastError(), "k_field_setup");
+  }
 
   // ---- per-site field constants by CG (one block per chain)
   std::vector<int> cg_idx;
@@ -547,14 +583,26 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
   return IHMC_OK;
 }
 
-// One trajectory of every chain: per group, pass j = 0 (FIRST) over all
+// One trajectory of every chain.  Per group: pass j = 0 (FIRST) over all
 // tiles, then MIDDLE over the chains that still have passes after j and LAST
 // over the chains whose final pass is j.  Chains are sorted by pass count, so
-// each set is a contiguous range of the tile table.
+// each set is a contiguous range of the tile table.  Groups run on streams of
+// their own, and the LAST launches of a group on a second stream: LAST(j) only
+// waits for launch j-1 of its group, so it overlaps MIDDLE(j) of the other
+// chains.  Captured once, the fork/join structure becomes graph edges.
 hipError_t Chains::enqueue_round(hipStream_t s) {
-  for (auto& g : groups) {
+  hipError_t e;
+  int ev = 0;
+  auto next_event = [&]() { return events[ev++]; };
+  hipEvent_t fork = next_event();
+  if ((e = hipEventRecord(fork, s)) != hipSuccess) return e;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const Group& g = groups[gi];
+    hipStream_t gs = side[2 * gi], ls = side[2 * gi + 1];
+    if ((e = hipStreamWaitEvent(gs, fork, 0)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(ls, fork, 0)) != hipSuccess) return e;
     const Tile* base = d_tiles + g.tile_off;
-    hipError_t e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_FIRST, d_cd, base, g.tile_begin.back(), 0, s);
+    e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_FIRST, d_cd, base, g.tile_begin.back(), 0, gs);
     if (e != hipSuccess) return e;
     const int nc = (int)g.order.size();
     for (int j = 1; j < g.max_pass; ++j) {
@@ -562,16 +610,24 @@ hipError_t Chains::enqueue_round(hipStream_t s) {
       while (mid_end < nc && g.n_pass[mid_end] - 1 > j) ++mid_end;
       int last_end = mid_end;
       while (last_end < nc && g.n_pass[last_end] - 1 == j) ++last_end;
-      if (mid_end > 0) {
-        e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_MIDDLE, d_cd, base, g.tile_begin[mid_end], j, s);
+      if (last_end > mid_end) {
+        hipEvent_t after_prev = next_event();
+        if ((e = hipEventRecord(after_prev, gs)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(ls, after_prev, 0)) != hipSuccess) return e;
+        const int t0 = g.tile_begin[mid_end], t1 = g.tile_begin[last_end];
+        e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_LAST, d_cd, base + t0, t1 - t0, j, ls);
         if (e != hipSuccess) return e;
       }
-      if (last_end > mid_end) {
-        const int t0 = g.tile_begin[mid_end], t1 = g.tile_begin[last_end];
-        e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_LAST, d_cd, base + t0, t1 - t0, j, s);
+      if (mid_end > 0) {
+        e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_MIDDLE, d_cd, base, g.tile_begin[mid_end], j, gs);
         if (e != hipSuccess) return e;
       }
     }
+    hipEvent_t j1 = next_event(), j2 = next_event();
+    if ((e = hipEventRecord(j1, gs)) != hipSuccess) return e;
+    if ((e = hipEventRecord(j2, ls)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, j1, 0)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, j2, 0)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -759,8 +815,8 @@ extern "C" int ihmc_force(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t precis
   const int64_t N = c->cd[0].N;
   double* t = (double*)ctx->arena.alloc(8 * (uint64_t)N);
   if (e == hipSuccess && t) {
-    if (precision == 4) k_export<float><<<nblk(N), 256, 0, s>>>(t, (const float*)c->cd[0].p, N);
-    else k_export<double><<<nblk(N), 256, 0, s>>>(t, (const double*)c->cd[0].p, N);
+    if (precision == 4) k_export<float><<<nblk(N), 256, 0, s>>>(c->d_cd, 0, t, (const float*)c->cd[0].p);
+    else k_export<double><<<nblk(N), 256, 0, s>>>(c->d_cd, 0, t, (const double*)c->cd[0].p);
     e = hipMemcpyAsync(F, t, 8 * N, hipMemcpyDeviceToHost, s);
   }
   hipError_t e2 = hipStreamSynchronize(s);
@@ -817,8 +873,8 @@ extern "C" int ihmc_integrate(ihmc_ctx* ctx, const ihmc_lattice* lat, const ihmc
   if (t) {
     e = hipMemcpyAsync(t, p, 8 * N, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
-      if (cdh.precision == 4) k_import<float><<<nblk(N), 256, 0, s>>>((float*)cdh.p, t, N);
-      else k_import<double><<<nblk(N), 256, 0, s>>>((double*)cdh.p, t, N);
+      if (cdh.precision == 4) k_import<float><<<nblk(N), 256, 0, s>>>(c->d_cd, 0, (float*)cdh.p, t);
+      else k_import<double><<<nblk(N), 256, 0, s>>>(c->d_cd, 0, (double*)cdh.p, t);
       e = c->enqueue_round(s);
     }
     if (e == hipSuccess) {
@@ -828,8 +884,8 @@ extern "C" int ihmc_integrate(ihmc_ctx* ctx, const ihmc_lattice* lat, const ihmc
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess) {
-      if (cdh.precision == 4) k_export<float><<<nblk(N), 256, 0, s>>>(t, (const float*)cdh.p, N);
-      else k_export<double><<<nblk(N), 256, 0, s>>>(t, (const double*)cdh.p, N);
+      if (cdh.precision == 4) k_export<float><<<nblk(N), 256, 0, s>>>(c->d_cd, 0, t, (const float*)cdh.p);
+      else k_export<double><<<nblk(N), 256, 0, s>>>(c->d_cd, 0, t, (const double*)cdh.p);
       e = hipMemcpyAsync(p, t, 8 * N, hipMemcpyDeviceToHost, s);
     }
   }

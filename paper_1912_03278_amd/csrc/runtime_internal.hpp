@@ -47,6 +47,8 @@ struct Chains {
   Tile* d_tiles = nullptr;
   std::vector<Group> groups;
   std::vector<void*> allocs;
+  std::vector<hipStream_t> side;   // two per group: passes, and LAST passes
+  std::vector<hipEvent_t> events;  // fork/join points of one round
   int enqueued = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;

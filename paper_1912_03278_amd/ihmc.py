@@ -14,7 +14,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libihmc.so")
+LIB_PATH = os.environ.get("IHMC_LIB", os.path.join(HERE, "libihmc.so"))
 
 IHMC_OK = 0
 STATUS = {-1: "IHMC_E_INVAL", -2: "IHMC_E_NOMEM", -3: "IHMC_E_AGAIN", -4: "IHMC_E_DEVICE",
