@@ -84,7 +84,7 @@ def bench_batched(args):
     # plain form: a sample of chains, each alone, same parameters; bitwise comparison
     rng = np.random.default_rng(0)
     sample = sorted(rng.choice(len(ws), size=min(args.plain_sample, len(ws)), replace=False).tolist())
-    plain_time, plain_work, identical = 0.0, 0, True
+    plain_time, plain_work, identical, mismatch = 0.0, 0, True, []
     for i in sample:
         alone = ihmc.Chains(ctx, [lats[i]], [ihmc.Run(n_md=ws[i]["n_md"], n_traj=W + K, precision=ihmc.F32,
                                                       seed=ws[i]["seed"], chain_id=ws[i]["chain_id"])])
@@ -97,7 +97,10 @@ def bench_batched(args):
         plain_work += K * int(math.prod(ws[i]["L"])) * ws[i]["n_md"]
         a = alone.result(0, want_psi=False)
         b = chains.result(i, want_psi=False)
-        identical &= bool(np.array_equal(a["dH"], b["dH"]) and np.array_equal(a["beta_eps"], b["beta_eps"]))
+        same = bool(np.array_equal(a["dH"], b["dH"]) and np.array_equal(a["beta_eps"], b["beta_eps"]))
+        if not same:
+            mismatch.append(i)
+        identical &= same
         alone.close()
     acc = [chains.result(i, want_psi=False)["acceptance"] for i in range(0, len(ws), max(1, len(ws) // 64))]
 
@@ -108,6 +111,8 @@ def bench_batched(args):
                          middle_GBs=round(20 * mid["sites"] / (mid["us"] * 1e-6) / 1e9, 1)))
     dom = max(kern, key=lambda k: k["middle_us"])
     achieved = 20 * dom["sites"] / (dom["middle_us"] * 1e-6) / 1e9
+    copy_bytes = 512 << 20
+    copy_gbs = 2 * copy_bytes / (ctx.copy_bandwidth(copy_bytes, reps=10) * 1e-6) / 1e9
     line = {
         "metric": "site-MD-steps/s", "value": value, "unit": "site-MD-steps/s", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": 1000.0 * dt / K, "higher_is_better": True, "scaling": "weak",
@@ -119,10 +124,12 @@ def bench_batched(args):
         "roofline": {"bound": "hbm", "kernel": "fused middle pass, 2D, per-site field (large-tile group)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "bytes_per_launch": 20 * dom["sites"], "avg_launch_us": dom["middle_us"]},
+                     "bytes_per_launch": 20 * dom["sites"], "avg_launch_us": dom["middle_us"],
+                     "copy_kernel_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "kernels": kern,
         "plain": {"chains": len(sample), "value": (plain_work / plain_time) if plain_time > 0 else None,
-                  "unit": "site-MD-steps/s", "bitwise_equal_to_batched": identical if sample else None},
+                  "unit": "site-MD-steps/s", "bitwise_equal_to_batched": identical if sample else None,
+                  "mismatched_chains": mismatch},
         "acceptance_sample_mean": float(np.mean(acc)),
         "setup_s": round(t_setup, 2),
         "cpu_baseline": None,
@@ -160,7 +167,7 @@ def main():
 
     ws = large_workload()
     K, W = args.steps, args.warmup
-    ctx = ihmc.Context(device=0, arena_bytes=1 << 30)
+    ctx = ihmc.Context(device=0, arena_bytes=2 << 30)
     lats = [ihmc.Lattice(w["L"], beta=w["beta"], C=w["C"]) for w in ws]
     runs = [ihmc.Run(n_md=w["n_md"], n_traj=W + K, precision=ihmc.F32, seed=w["seed"], chain_id=w["chain_id"])
             for w in ws]
@@ -206,6 +213,9 @@ def main():
         k["first_us"] = round(k["first_us"], 3)
         del k["middle_share_us"]
 
+    copy_bytes = 512 << 20
+    copy_us = ctx.copy_bandwidth(copy_bytes, reps=10)
+    copy_gbs = 2 * copy_bytes / (copy_us * 1e-6) / 1e9
     line = {
         "metric": "site-MD-steps/s",
         "value": value,
@@ -236,6 +246,8 @@ def main():
             "traffic": None,
             "bytes_per_launch": bytes_per_launch,
             "avg_launch_us": round(dom["middle_us"], 3),
+            "copy_kernel_GBs": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4),
         },
         "kernels": kern,
         "chains": per,

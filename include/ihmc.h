@@ -195,6 +195,12 @@ int ihmc_chains_groups(ihmc_chains* chains, int32_t* n_groups);
 int ihmc_chains_time_pass(ihmc_chains* chains, int32_t group, int32_t mode, int32_t reps, double* avg_us,
                           int64_t* sites, int32_t* ndim, int32_t* precision);
 
+/* Copy `bytes` (>= 4096) between two arena buffers with a plain 16-byte-vector
+ * streaming kernel, `reps` times after one warm-up, timed with HIP events on
+ * the context stream; returns the mean microseconds per copy (read + write
+ * traffic = 2 * bytes).  The achievable-bandwidth reference of the roofline. */
+int ihmc_copy_bandwidth(ihmc_ctx* ctx, uint64_t bytes, int32_t reps, double* avg_us);
+
 #ifdef __cplusplus
 }
 #endif

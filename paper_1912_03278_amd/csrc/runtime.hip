@@ -986,3 +986,50 @@ extern "C" int ihmc_chains_time_pass(ihmc_chains* ch, int32_t group, int32_t mod
   if (precision) *precision = g.prec;
   return IHMC_OK;
 }
+
+// Plain streaming copy (16-byte vectors, grid-stride): the achievable-bandwidth
+// reference for the roofline and the calibration of the memory counters.
+__global__ __launch_bounds__(256) void k_copy_stream(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                     int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+extern "C" int ihmc_copy_bandwidth(ihmc_ctx* ctx, uint64_t bytes, int32_t reps, double* avg_us) {
+  CTX_OK(ctx);
+  if (bytes < 4096 || reps < 1) return set_error(IHMC_E_INVAL, "need bytes >= 4096 and reps >= 1");
+  bytes &= ~(uint64_t)15;
+  void* a = ctx->arena.alloc(bytes);
+  void* b = ctx->arena.alloc(bytes);
+  if (!a || !b) {
+    ctx->arena.release(a);
+    ctx->arena.release(b);
+    return set_error(IHMC_E_NOMEM, "arena exhausted (copy buffers)");
+  }
+  hipStream_t s = ctx->stream;
+  const int64_t n = (int64_t)(bytes / 16);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0), "event");
+  HIPCHK(hipEventCreate(&e1), "event");
+  const unsigned grid = 256 * 16;
+  hipError_t e = hipMemsetAsync(a, 0, bytes, s);
+  if (e == hipSuccess) {
+    k_copy_stream<<<grid, 256, 0, s>>>((const float4*)a, (float4*)b, n);
+    e = hipEventRecord(e0, s);
+  }
+  for (int r = 0; e == hipSuccess && r < reps; ++r) {
+    k_copy_stream<<<grid, 256, 0, s>>>((const float4*)a, (float4*)b, n);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  ctx->arena.release(a);
+  ctx->arena.release(b);
+  if (e != hipSuccess) return hip_fail(ctx, e, "copy bandwidth");
+  if (avg_us) *avg_us = 1000.0 * ms / reps;
+  return IHMC_OK;
+}

@@ -28,7 +28,7 @@ EXPORTS = (
     "ihmc_last_error", "ihmc_chains_create", "ihmc_chains_advance", "ihmc_chains_result",
     "ihmc_chains_destroy", "ihmc_run_lattice", "ihmc_run_batch", "ihmc_force", "ihmc_action",
     "ihmc_integrate", "ihmc_philox_normals", "ihmc_philox_words", "ihmc_chains_groups",
-    "ihmc_chains_time_pass",
+    "ihmc_chains_time_pass", "ihmc_copy_bandwidth",
 )
 
 
@@ -105,6 +105,7 @@ def load():
     L.ihmc_chains_groups.argtypes = [vp, C.POINTER(C.c_int32)]
     L.ihmc_chains_time_pass.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                         C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.ihmc_copy_bandwidth.argtypes = [vp, C.c_uint64, C.c_int32, C.POINTER(C.c_double)]
     _lib = L
     return L
 
@@ -294,6 +295,12 @@ class Context:
         psi, p = _f64(psi).copy(), _f64(p).copy()
         _check(load().ihmc_integrate(self.h, C.byref(lat._c(keep)), C.byref(run._c(keep)), _dp(psi), _dp(p)))
         return psi, p
+
+    def copy_bandwidth(self, nbytes, reps=20):
+        """Mean microseconds of one plain device copy of nbytes (2 * nbytes of traffic)."""
+        us = C.c_double()
+        _check(load().ihmc_copy_bandwidth(self.h, int(nbytes), int(reps), C.byref(us)))
+        return us.value
 
     def philox_normals(self, seed, chain_id, traj, tag, n):
         out = np.zeros(n)

@@ -58,3 +58,46 @@ def test_sampled_chains_bitwise_equal_alone(full_batch):
         b = ch.result(i)
         for k in ("dH", "H_old", "beta_eps", "m", "psi_final"):
             assert np.array_equal(alone[k], b[k]), (i, k)
+
+
+def _batched_run(ctx, ws, n_traj):
+    from paper_1912_03278_amd import ihmc
+    lats = [ihmc.Lattice(w["L"], beta=w["beta"], C=w["C"], h=w["h"]) for w in ws]
+    runs = [ihmc.Run(n_md=w["n_md"], n_traj=n_traj, precision=ihmc.F32, seed=w["seed"], chain_id=w["chain_id"])
+            for w in ws]
+    ch = ihmc.Chains(ctx, lats, runs)
+    ch.advance(n_traj)
+    return ch, lats, runs
+
+
+def test_batched_rerun_is_bitwise_deterministic():
+    """Natural accept decisions over several trajectories: two runs of the full
+    batch agree bit for bit (a race between concurrent launches would show here)."""
+    from paper_1912_03278_amd import ihmc, inputs
+    ctx = ihmc.Context(arena_bytes=6 << 30)
+    ws = inputs.batched()
+    a, _, _ = _batched_run(ctx, ws, 6)
+    ra = [a.result(i, want_psi=False)["dH"] for i in range(0, len(ws), 97)]
+    a.close()
+    b, _, _ = _batched_run(ctx, ws, 6)
+    rb = [b.result(i, want_psi=False)["dH"] for i in range(0, len(ws), 97)]
+    b.close()
+    ctx.close()
+    bad = [k for k, (x, y) in enumerate(zip(ra, rb)) if not np.array_equal(x, y)]
+    assert not bad, bad
+
+
+def test_batched_equals_alone_natural_decisions():
+    from paper_1912_03278_amd import ihmc, inputs
+    ctx = ihmc.Context(arena_bytes=6 << 30)
+    ws = inputs.batched()
+    ch, lats, runs = _batched_run(ctx, ws, 6)
+    diffs = []
+    for i in (0, 1, 2, 500, 1234, 4095):
+        alone = ctx.run_lattice(lats[i], runs[i], want_psi=False)
+        b = ch.result(i, want_psi=False)
+        if not (np.array_equal(alone["dH"], b["dH"]) and np.array_equal(alone["beta_eps"], b["beta_eps"])):
+            diffs.append((i, ws[i]["L"], ws[i]["n_md"], alone["dH"].tolist(), b["dH"].tolist()))
+    ch.close()
+    ctx.close()
+    assert not diffs, diffs
