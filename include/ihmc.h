@@ -60,6 +60,7 @@ extern "C" {
 
 typedef struct ihmc_ctx ihmc_ctx;
 typedef struct ihmc_chains ihmc_chains;
+typedef struct ihmc_dense_chains ihmc_dense_chains;
 
 /* Device allocator hook (e.g. PyTorch's caching allocator).  alloc returns a
  * device pointer or NULL; free releases it. */
@@ -80,6 +81,27 @@ typedef struct {
   const double* h;
   int64_t h_len;
 } ihmc_lattice;
+
+/* Explicit coupling matrix in place of the lattice's J K (Sec. 2 allows any
+ * symmetric coupling; App. A's infinite-range model is one instance).
+ *   N          sites, >= 1.
+ *   K          host, N x N, row-major, symmetric, finite (checked).  The
+ *              model's couplings are J * K.
+ *   J, beta    J' = beta*J must be > 0.
+ *   C          shift of K.  C >= 0: used as given, rejected when the lowest
+ *              Ritz value theta of K gives theta + C <= 0 (K + C*1 then is
+ *              certainly not positive definite).  C < 0: chosen as
+ *              -(theta - |r|) + 0.1 from FP64 Lanczos (theta the lowest Ritz
+ *              value, |r| its residual norm, so theta - |r| bounds the lowest
+ *              eigenvalue from below once theta has converged to it).
+ *   h, h_len   as for the lattice: 0, 1 (uniform) or N values. */
+typedef struct {
+  int64_t N;
+  const double* K;
+  double J, beta, C;
+  const double* h;
+  int64_t h_len;
+} ihmc_dense;
 
 /* Parameters of one chain (Sec. 3).
  *   n_md        integrator steps per trajectory (>= 1).
@@ -160,6 +182,52 @@ int ihmc_run_lattice(ihmc_ctx* ctx, const ihmc_lattice* lat, const ihmc_run* run
 /* n chains (arrays of n descriptors and n results).  Synchronous. */
 int ihmc_run_batch(ihmc_ctx* ctx, int32_t n, const ihmc_lattice* lats, const ihmc_run* runs,
                    ihmc_result* outs);
+
+/* ---- dense couplings (many chains of one model) ---------------------------- */
+
+/* Create n chains of one dense model (runs[i] gives each chain's seed,
+ * chain_id, psi0, replay and capacity; n_md, traj_len, integrator and
+ * flip_every must agree across the chains, and precision must be IHMC_F32).
+ * The fields of all chains form one N x n matrix, so both K~ applications of
+ * a force evaluation are matrix products on the MFMA units.  `products`
+ * selects their precision: 6 (K and the FP32 operand each held as three BF16
+ * limbs, all limb products of order <= 2, ~FP32 accuracy; the default when 0)
+ * or 3 (two limbs each, products of order <= 1, ~2^-16 relative).  The
+ * Hamiltonian uses an FP64 product of the stored field with the FP64 K.
+ * Set-up (synchronous): K's limbs, Lanczos for C (see ihmc_dense), CG solves
+ * for the estimator constants 1^T Kt^-1 1, 1^T Kt^-1 h', h'^T Kt^-1 h', the
+ * initial fields and S(psi0). */
+int ihmc_dense_create(ihmc_ctx* ctx, const ihmc_dense* model, int32_t n, const ihmc_run* runs, int32_t products,
+                      ihmc_dense_chains** out);
+/* Enqueue n_traj trajectories of every chain (asynchronous, graph-replayed). */
+int ihmc_dense_advance(ihmc_dense_chains* chains, int32_t n_traj);
+/* Wait, then copy chain i's series and summary, as ihmc_chains_result. */
+int ihmc_dense_result(ihmc_dense_chains* chains, int32_t i, ihmc_result* out);
+/* The shift in use and the Lanczos estimate: out[0] = C, out[1] = theta,
+ * out[2] = |r|, out[3] = Lanczos steps, out[4] = CG iterations (largest of
+ * the solves). */
+int ihmc_dense_info(ihmc_dense_chains* chains, double* out);
+/* Time one of the dense launches `reps` times after a warm-up, with HIP
+ * events on the context stream: what = 0 the BF16-limb GEMM of one K~
+ * application over all chains, 1 the FP64 GEMM of the Hamiltonian, 2 a whole
+ * force evaluation (two GEMMs and their epilogues).  Returns microseconds per
+ * launch and the GEMM dimensions (m = padded sites, n = padded chains,
+ * k = padded sites) and split-K factor of the BF16 GEMM.  Overwrites the
+ * momenta: call only when the results are no longer needed. */
+int ihmc_dense_time(ihmc_dense_chains* chains, int32_t what, int32_t reps, double* avg_us, int64_t* mnk_s);
+int ihmc_dense_destroy(ihmc_dense_chains* chains);
+/* n chains of one dense model: create, advance, fetch n results, destroy. */
+int ihmc_run_dense(ihmc_ctx* ctx, const ihmc_dense* model, int32_t n, const ihmc_run* runs, int32_t products,
+                   ihmc_result* outs);
+/* Forces of n host fields (psi: n x N, row-major) through the dense GEMM path
+ * into host F (n x N). */
+int ihmc_dense_force(ihmc_ctx* ctx, const ihmc_dense* model, int32_t n, const double* psi, int32_t products,
+                     double* F);
+/* Lowest eigenvalue of a symmetric N x N host matrix K by FP64 Lanczos with
+ * full reorthogonalisation on the device: theta (lowest Ritz value, an upper
+ * bound), resid (|r| of its Ritz pair; theta - resid is a lower bound once
+ * theta has converged to the lowest eigenvalue) and the steps taken. */
+int ihmc_min_eig(ihmc_ctx* ctx, const double* K, int64_t N, double* theta, double* resid, int32_t* steps);
 
 /* ---- diagnostics (same kernels as the hot path) --------------------------- */
 

@@ -161,4 +161,42 @@ __device__ __forceinline__ void block_accumulate(const ChainDev& cd, ChainState*
   close_chain<MODE == PASS_LAST>(cd, st, pass_in_buf(cur, j));
 }
 
+
+// Terms of four x-aligned sites held by four consecutive lanes, summed as
+// (t0 + t1) + (t2 + t3) in FP64 (FP addition is commutative, so every lane of
+// the quad forms the identical value; lane 4q keeps it, the other three give 0).
+__device__ __forceinline__ double quad_sum_lanes(double t) {
+  t = t + __shfl_xor(t, 1, 64);
+  t = t + __shfl_xor(t, 2, 64);
+  return ((threadIdx.x & 3) == 0) ? t : 0.0;
+}
+
+// Block reduction of the terms [a_lo, a_hi] and their accumulation into the
+// chain, without counting the block as finished (used where another kernel
+// closes the trajectory).
+template <int NW>
+__device__ __forceinline__ void block_add_terms(ChainState* st, const u128* acc, uint32_t bad, int a_lo, int a_hi,
+                                                int slot) {
+  __shared__ u128 sRedA[NW][NTERM];
+  __shared__ uint32_t sBadA[NW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int a = a_lo; a <= a_hi; ++a) {
+    const u128 v = wave_sum128(acc[a]);
+    if (lane == 0) sRedA[wave][a] = v;
+  }
+  const unsigned long long any_bad = __ballot(bad != 0u);
+  if (lane == 0) sBadA[wave] = any_bad ? 1u : 0u;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int a = a_lo; a <= a_hi; ++a) {
+      u128 v = sRedA[0][a];
+      for (int w = 1; w < NW; ++w) v = add128(v, sRedA[w][a]);
+      atomic_add_limbs(st->acc[a][slot], v);
+    }
+    uint32_t anyb = 0u;
+    for (int w = 0; w < NW; ++w) anyb |= sBadA[w];
+    if (anyb) (void)__hip_atomic_fetch_or(&st->bad, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 }  // namespace ihmc

@@ -102,15 +102,6 @@ __device__ __forceinline__ double quad_sum(double t0, double t1, double t2, doub
   return (t0 + t1) + (t2 + t3);
 }
 
-// The same quad sum across four consecutive lanes holding x = 4q .. 4q+3
-// (FP addition is commutative, so every lane of the quad forms the identical
-// value; lane 4q keeps it, the other three return zero).
-__device__ __forceinline__ double quad_sum_lanes(double t) {
-  t = t + __shfl_xor(t, 1, 64);
-  t = t + __shfl_xor(t, 2, 64);
-  return ((threadIdx.x & 3) == 0) ? t : 0.0;
-}
-
 // --------------------------------------------------------------------- 2D ---
 //
 // Tile BX x BY, one thread per quad of four consecutive x (NT = BX/4 * BY).

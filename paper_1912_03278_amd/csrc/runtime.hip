@@ -368,11 +368,7 @@ Chains::~Chains() {
   for (void* p : allocs) ctx->arena.release(p);
 }
 
-#define HIPCHK(expr, what)                         \
-  do {                                             \
-    hipError_t _e = (expr);                        \
-    if (_e != hipSuccess) return hip_fail(ctx, _e, what); \
-  } while (0)
+
 
 int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, int flags) {
   n = n_;
@@ -661,10 +657,15 @@ int Chains::advance(int32_t n_traj) {
 
 int Chains::result(int32_t i, ihmc_result* out) {
   if (i < 0 || i >= n) return set_error(IHMC_E_INVAL, "chain index %d out of range", i);
+  return result_from_device(ctx, cd[i], d_cd, i, out);
+}
+
+// Series and summary of chain ci of a device chain table (shared by the lattice
+// and dense runtimes).
+int result_from_device(ihmc_ctx* ctx, const ChainDev& c, const ChainDev* d_cd, int ci, ihmc_result* out) {
   if (!out) return set_error(IHMC_E_INVAL, "out is NULL");
   hipStream_t s = ctx->stream;
   HIPCHK(hipStreamSynchronize(s), "sync");
-  const ChainDev& c = cd[i];
   ChainState st;
   HIPCHK(hipMemcpy(&st, c.st, sizeof st, hipMemcpyDeviceToHost), "state download");
   const int done = std::min(st.traj, c.cap);
@@ -690,9 +691,8 @@ int Chains::result(int32_t i, ihmc_result* out) {
   if (out->psi_final) {
     double* t = (double*)ctx->arena.alloc(8 * (uint64_t)c.N);
     if (!t) return set_error(IHMC_E_NOMEM, "arena exhausted (export)");
-    if (c.precision == 4) k_export_psi<float><<<nblk(c.N), 256, 0, s>>>(d_cd, i, t);
-    else k_export_psi<double><<<nblk(c.N), 256, 0, s>>>(d_cd, i, t);
-    hipError_t e = hipMemcpyAsync(out->psi_final, t, 8 * c.N, hipMemcpyDeviceToHost, s);
+    hipError_t e0 = launch_export_psi(d_cd, ci, t, c.N, c.precision, s);
+    hipError_t e = e0 == hipSuccess ? hipMemcpyAsync(out->psi_final, t, 8 * c.N, hipMemcpyDeviceToHost, s) : e0;
     hipError_t e2 = hipStreamSynchronize(s);
     ctx->arena.release(t);
     if (e != hipSuccess) return hip_fail(ctx, e, "psi export");
@@ -705,12 +705,7 @@ int Chains::result(int32_t i, ihmc_result* out) {
 
 // ========================================================== C ABI: chains ===
 
-#define CTX_OK(c)                                                         \
-  do {                                                                    \
-    if (!(c)) return set_error(IHMC_E_INVAL, "ctx is NULL");              \
-    if ((c)->dead) return set_error(IHMC_E_DEVICE, "context is unusable after a device error"); \
-    hipSetDevice((c)->device);                                            \
-  } while (0)
+
 
 static int make_chains(ihmc_ctx* ctx, int32_t n, const ihmc_lattice* lats, const ihmc_run* runs, int flags,
                        Chains** out) {
@@ -1033,3 +1028,26 @@ extern "C" int ihmc_copy_bandwidth(ihmc_ctx* ctx, uint64_t bytes, int32_t reps, 
   if (avg_us) *avg_us = 1000.0 * ms / reps;
   return IHMC_OK;
 }
+
+namespace ihmc {
+hipError_t launch_init_psi(const ChainDev* d_cd, int ci, const double* psi0, int64_t N, int precision, hipStream_t s) {
+  if (precision == 4) k_init_psi<float><<<nblk(N), 256, 0, s>>>(d_cd, ci, psi0);
+  else k_init_psi<double><<<nblk(N), 256, 0, s>>>(d_cd, ci, psi0);
+  return hipGetLastError();
+}
+hipError_t launch_zero_state(ChainState* st, hipStream_t s) {
+  k_zero_state<<<1, 256, 0, s>>>(st);
+  return hipGetLastError();
+}
+hipError_t launch_export_psi(const ChainDev* d_cd, int ci, double* out, int64_t N, int precision, hipStream_t s) {
+  if (precision == 4) k_export_psi<float><<<nblk(N), 256, 0, s>>>(d_cd, ci, out);
+  else k_export_psi<double><<<nblk(N), 256, 0, s>>>(d_cd, ci, out);
+  return hipGetLastError();
+}
+hipError_t launch_export_field(const ChainDev* d_cd, int ci, double* out, const void* src, int64_t N, int precision,
+                               hipStream_t s) {
+  if (precision == 4) k_export<float><<<nblk(N), 256, 0, s>>>(d_cd, ci, out, (const float*)src);
+  else k_export<double><<<nblk(N), 256, 0, s>>>(d_cd, ci, out, (const double*)src);
+  return hipGetLastError();
+}
+}  // namespace ihmc

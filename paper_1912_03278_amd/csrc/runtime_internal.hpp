@@ -15,6 +15,14 @@ namespace ihmc {
 int set_error(int code, const char* fmt, ...);
 int hip_fail(ihmc_ctx* ctx, hipError_t e, const char* where);
 
+// Set-up launchers shared by the lattice and dense runtimes (runtime.hip).
+hipError_t launch_init_psi(const ChainDev* d_cd, int ci, const double* psi0, int64_t N, int precision, hipStream_t s);
+hipError_t launch_zero_state(ChainState* st, hipStream_t s);
+hipError_t launch_export_psi(const ChainDev* d_cd, int ci, double* out, int64_t N, int precision, hipStream_t s);
+hipError_t launch_export_field(const ChainDev* d_cd, int ci, double* out, const void* src, int64_t N, int precision,
+                               hipStream_t s);
+int result_from_device(ihmc_ctx* ctx, const ChainDev& c, const ChainDev* d_cd, int ci, ihmc_result* out);
+
 // First-fit sub-allocator over one device allocation (256-byte granules).
 struct Arena {
   char* base = nullptr;
@@ -62,6 +70,19 @@ struct Chains {
 };
 
 }  // namespace ihmc
+
+#define HIPCHK(expr, what)                                \
+  do {                                                    \
+    hipError_t _e = (expr);                               \
+    if (_e != hipSuccess) return hip_fail(ctx, _e, what); \
+  } while (0)
+
+#define CTX_OK(c)                                                                             \
+  do {                                                                                        \
+    if (!(c)) return set_error(IHMC_E_INVAL, "ctx is NULL");                                  \
+    if ((c)->dead) return set_error(IHMC_E_DEVICE, "context is unusable after a device error"); \
+    hipSetDevice((c)->device);                                                                \
+  } while (0)
 
 struct ihmc_ctx {
   int device = 0;

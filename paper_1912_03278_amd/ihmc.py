@@ -28,7 +28,9 @@ EXPORTS = (
     "ihmc_last_error", "ihmc_chains_create", "ihmc_chains_advance", "ihmc_chains_result",
     "ihmc_chains_destroy", "ihmc_run_lattice", "ihmc_run_batch", "ihmc_force", "ihmc_action",
     "ihmc_integrate", "ihmc_philox_normals", "ihmc_philox_words", "ihmc_chains_groups",
-    "ihmc_chains_time_pass", "ihmc_copy_bandwidth",
+    "ihmc_chains_time_pass", "ihmc_copy_bandwidth", "ihmc_dense_create", "ihmc_dense_advance",
+    "ihmc_dense_result", "ihmc_dense_info", "ihmc_dense_time", "ihmc_dense_destroy", "ihmc_run_dense",
+    "ihmc_dense_force", "ihmc_min_eig",
 )
 
 
@@ -40,6 +42,11 @@ class IhmcError(RuntimeError):
 
 class _Lattice(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("L", C.c_int32 * 3), ("J", C.c_double), ("beta", C.c_double),
+                ("C", C.c_double), ("h", C.POINTER(C.c_double)), ("h_len", C.c_int64)]
+
+
+class _Dense(C.Structure):
+    _fields_ = [("N", C.c_int64), ("K", C.POINTER(C.c_double)), ("J", C.c_double), ("beta", C.c_double),
                 ("C", C.c_double), ("h", C.POINTER(C.c_double)), ("h_len", C.c_int64)]
 
 
@@ -106,6 +113,16 @@ def load():
     L.ihmc_chains_time_pass.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                         C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.ihmc_copy_bandwidth.argtypes = [vp, C.c_uint64, C.c_int32, C.POINTER(C.c_double)]
+    L.ihmc_dense_create.argtypes = [vp, C.POINTER(_Dense), C.c_int32, C.POINTER(_Run), C.c_int32, pp]
+    L.ihmc_dense_advance.argtypes = [vp, C.c_int32]
+    L.ihmc_dense_result.argtypes = [vp, C.c_int32, C.POINTER(_Result)]
+    L.ihmc_dense_info.argtypes = [vp, _DP]
+    L.ihmc_dense_time.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.ihmc_dense_destroy.argtypes = [vp]
+    L.ihmc_run_dense.argtypes = [vp, C.POINTER(_Dense), C.c_int32, C.POINTER(_Run), C.c_int32,
+                                 C.POINTER(_Result)]
+    L.ihmc_dense_force.argtypes = [vp, C.POINTER(_Dense), C.c_int32, _DP, C.c_int32, _DP]
+    L.ihmc_min_eig.argtypes = [vp, _DP, C.c_int64, _DP, _DP, C.POINTER(C.c_int32)]
     _lib = L
     return L
 
@@ -141,6 +158,38 @@ class Lattice:
         s.ndim = len(self.L)
         for i in range(3):
             s.L[i] = int(self.L[i]) if i < len(self.L) else 1
+        s.J, s.beta, s.C = float(self.J), float(self.beta), float(self.C)
+        h = None if self.h is None else _f64(np.atleast_1d(self.h))
+        keep.append(h)
+        s.h = _dp(h)
+        s.h_len = 0 if h is None else h.size
+        return s
+
+
+@dataclass
+class Dense:
+    """Explicit symmetric coupling matrix K (the model's couplings are J K), Kt = K + C 1.
+    C < 0 selects the shift from the lowest Ritz value of K (FP64 Lanczos)."""
+    K: object
+    beta: float
+    C: float = -1.0
+    J: float = 1.0
+    h: object = None  # None, a scalar, or one value per site
+
+    def __post_init__(self):
+        self.K = np.ascontiguousarray(self.K, dtype=np.float64)
+        if self.K.ndim != 2 or self.K.shape[0] != self.K.shape[1]:
+            raise ValueError("K must be a square matrix")
+
+    @property
+    def N(self):
+        return int(self.K.shape[0])
+
+    def _c(self, keep):
+        s = _Dense()
+        s.N = self.N
+        keep.append(self.K)
+        s.K = _dp(self.K)
         s.J, s.beta, s.C = float(self.J), float(self.beta), float(self.C)
         h = None if self.h is None else _f64(np.atleast_1d(self.h))
         keep.append(h)
@@ -296,6 +345,35 @@ class Context:
         _check(load().ihmc_integrate(self.h, C.byref(lat._c(keep)), C.byref(run._c(keep)), _dp(psi), _dp(p)))
         return psi, p
 
+    def run_dense(self, model: Dense, runs, products=6, want_psi=True):
+        keep = []
+        n = len(runs)
+        ra = (_Run * n)(*[r._c(keep) for r in runs])
+        res = (_Result * n)()
+        arrs = []
+        for i in range(n):
+            r, a = _result_struct(runs[i].n_traj, model.N, want_psi)
+            res[i] = r
+            arrs.append(a)
+        _check(load().ihmc_run_dense(self.h, C.byref(model._c(keep)), n, ra, int(products), res))
+        return [_result_dict(res[i], arrs[i]) for i in range(n)]
+
+    def dense_force(self, model: Dense, psi, products=6):
+        """Forces of the rows of psi (n x N) through the GEMM path."""
+        keep = []
+        psi = np.atleast_2d(_f64(psi))
+        F = np.zeros_like(psi)
+        _check(load().ihmc_dense_force(self.h, C.byref(model._c(keep)), psi.shape[0], _dp(psi), int(products),
+                                       _dp(F)))
+        return F
+
+    def min_eig(self, K):
+        """(theta, |r|, steps): lowest Ritz value of K by FP64 Lanczos and its residual norm."""
+        K = np.ascontiguousarray(K, dtype=np.float64)
+        th, rs, st = C.c_double(), C.c_double(), C.c_int32()
+        _check(load().ihmc_min_eig(self.h, _dp(K), K.shape[0], C.byref(th), C.byref(rs), C.byref(st)))
+        return th.value, rs.value, st.value
+
     def copy_bandwidth(self, nbytes, reps=20):
         """Mean microseconds of one plain device copy of nbytes (2 * nbytes of traffic)."""
         us = C.c_double()
@@ -356,6 +434,52 @@ class Chains:
     def close(self):
         if getattr(self, "h", None):
             load().ihmc_chains_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DenseChains:
+    """Chains of one dense model, resident on the device; both K~ applications of
+    every force evaluation run as GEMMs over all chains."""
+
+    def __init__(self, ctx: Context, model: Dense, runs, products=6):
+        self.ctx, self.model, self.runs = ctx, model, list(runs)
+        keep = []
+        n = len(runs)
+        self.n = n
+        ra = (_Run * n)(*[r._c(keep) for r in runs])
+        h = C.c_void_p()
+        _check(load().ihmc_dense_create(ctx.h, C.byref(model._c(keep)), n, ra, int(products), C.byref(h)))
+        self.h = h
+
+    def advance(self, n_traj):
+        _check(load().ihmc_dense_advance(self.h, int(n_traj)))
+
+    def result(self, i, want_psi=True):
+        r, a = _result_struct(self.runs[i].n_traj, self.model.N, want_psi)
+        _check(load().ihmc_dense_result(self.h, int(i), C.byref(r)))
+        return _result_dict(r, a)
+
+    def info(self):
+        out = np.zeros(5)
+        _check(load().ihmc_dense_info(self.h, _dp(out)))
+        return dict(C=out[0], theta=out[1], resid=out[2], lanczos_steps=int(out[3]), cg_iters=int(out[4]))
+
+    def time(self, what=0, reps=20):
+        """Mean microseconds of one launch: 0 BF16-limb GEMM, 1 FP64 GEMM, 2 whole force evaluation."""
+        us = C.c_double()
+        mnk = (C.c_int64 * 4)()
+        _check(load().ihmc_dense_time(self.h, int(what), int(reps), C.byref(us), mnk))
+        return dict(us=us.value, m=mnk[0], n=mnk[1], k=mnk[2], split_k=mnk[3])
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().ihmc_dense_destroy(self.h)
             self.h = None
 
     def __del__(self):
