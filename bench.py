@@ -28,6 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 matrix
 BYTES_MIDDLE_F32 = 16  # read psi, read p, write p, write psi' (FP32), h = 0
 
 
@@ -139,13 +141,172 @@ def bench_batched(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_dense(args):
+    """256 chains of one dense all-to-all model (N = 4096, K_ij ~ N(0, 1/N), h = 0,
+    beta = 1, C from Lanczos), 16 leap-frog steps per trajectory; one step = one
+    trajectory of every chain.  Both K~ applications of a force evaluation are
+    4096 x 4096 by 4096 x 256 GEMMs on the MFMA units (six BF16 limb products)."""
+    import numpy as np
+    import torch
+    from paper_1912_03278_amd import ihmc, inputs
+
+    w = inputs.dense()
+    K, W = args.steps, args.warmup
+    N, B, n_md = w["K"].shape[0], w["n_chains"], w["n_md"]
+    ctx = ihmc.Context(device=0, arena_bytes=2 << 30)
+    runs = [ihmc.Run(n_md=n_md, n_traj=W + K, precision=ihmc.F32, seed=w["seed"], chain_id=i) for i in range(B)]
+    t0 = time.perf_counter()
+    chains = ihmc.DenseChains(ctx, ihmc.Dense(w["K"], beta=w["beta"]), runs, products=args.products)
+    t_setup = time.perf_counter() - t0
+    info = chains.info()
+    print(f"bench: dense chains ready in {t_setup:.2f} s (C = {info['C']:.6f}, Lanczos {info['lanczos_steps']} "
+          f"steps, CG {info['cg_iters']} steps)", file=sys.stderr, flush=True)
+    chains.advance(W)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chains.advance(K)
+    ctx.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = K * N * B * n_md / dt
+    print(f"bench: timed {K} trajectories of {B} chains in {dt:.3f} s", file=sys.stderr, flush=True)
+    res = [chains.result(i, want_psi=False) for i in range(B)]
+    acc = float(np.mean([r["acceptance"] for r in res]))
+    be = float(np.mean([r["beta_eps"][-1] for r in res]))
+
+    g = chains.time(0, reps=args.timing_reps)
+    f64 = chains.time(1, reps=max(5, args.timing_reps // 4))
+    force = chains.time(2, reps=max(5, args.timing_reps // 4))
+    m, n, k = g["m"], g["n"], g["k"]
+    executed = args.products * 2.0 * m * n * k  # BF16 MFMA flops one launch executes (padded shape)
+    useful = 2.0 * N * N * B  # one K~ application of every chain, FP32-equivalent
+    achieved = executed / (g["us"] * 1e-6) / 1e12
+    line = {
+        "metric": "site-MD-steps/s", "value": value, "unit": "site-MD-steps/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": 1000.0 * dt / K, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16x%d->f32 (FP32 state, FP64 H)" % args.products, "data": "synthetic",
+        "config": {"workload": f"dense all-to-all: N={N}, K_ij ~ N(0,1/N) symmetric, zero diagonal, h=0, beta=1, "
+                               f"C=|lambda_min|+0.1 by FP64 Lanczos, {B} chains, {n_md} leap-frog steps per "
+                               "trajectory; one step = one trajectory of every chain",
+                   "sites": N, "chains": B, "md_steps_per_trajectory": n_md, "limb_products": args.products,
+                   "C": info["C"]},
+        "roofline": {"bound": "mfma", "kernel": "BF16-limb split-K GEMM (one K~ application of all chains)",
+                     "achieved": round(achieved, 1), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": None,
+                     "flops_per_launch": executed, "avg_launch_us": round(g["us"], 2),
+                     "gemm_mnk": [m, n, k], "split_k": g["split_k"],
+                     "useful_fp32_equiv_TFLOPs": round(useful / (g["us"] * 1e-6) / 1e12, 1)},
+        "kernels": {"gemm_bf16_us": round(g["us"], 2), "gemm_f64_us": round(f64["us"], 2),
+                    "gemm_f64_TFLOPs": round(2.0 * m * B * k / (f64["us"] * 1e-6) / 1e12, 1),
+                    "gemm_f64_frac": round(2.0 * m * B * k / (f64["us"] * 1e-6) / 1e12 / FP64_PEAK_TFLOPS, 4),
+                    "force_evaluation_us": round(force["us"], 2)},
+        "acceptance_mean": acc, "beta_eps_last_mean": be, "setup_s": round(t_setup, 2),
+        "lanczos": {"theta": info["theta"], "resid": info["resid"], "steps": info["lanczos_steps"]},
+    }
+    chains.close()
+    ctx.close()
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        import oracle
+        t_cpu, work = 0.0, 0
+        for i in range(2):
+            t1 = time.perf_counter()
+            oracle.run(oracle.Dense(w["K"], beta=w["beta"], C=info["C"]), 2, n_md, seed=w["seed"], chain_id=i)
+            t_cpu += time.perf_counter() - t1
+            work += 2 * N * n_md
+        line["cpu_baseline"] = dict(value=work / t_cpu, unit="site-MD-steps/s", cores=1, kind="oracle",
+                                    sample=f"2 chains x 2 trajectories of the N={N} dense model, FP64, set-up "
+                                           f"(CG constants) included, {t_cpu:.1f} s on one host core")
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+def bench_serving(args):
+    """Open-loop Poisson arrivals of lattice requests (2D or 3D, uneven size,
+    beta, field and length) into the continuous-batching server; reports the
+    completed site-MD-steps/s and the p50/p99 request latency."""
+    import threading
+
+    import numpy as np
+    from paper_1912_03278_amd import ihmc, inputs
+
+    reqs = inputs.serving(rate=args.rate, duration=args.serve_duration)
+    ctx = ihmc.Context(device=0, arena_bytes=12 << 30)
+    sv = ihmc.Server(ctx, budget_bytes=10 << 30, max_active=2048)
+    tickets = [None] * len(reqs)
+    work = [int(math.prod(r["L"])) * r["n_md"] * r["n_traj"] for r in reqs]
+    t_start = time.perf_counter()
+
+    def submitter():
+        for k, r in enumerate(reqs):
+            delay = t_start + r["t"] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            lat = ihmc.Lattice(r["L"], beta=r["beta"], C=r["C"], h=r["h"])
+            tickets[k] = sv.submit(lat, ihmc.Run(n_md=r["n_md"], n_traj=r["n_traj"], precision=ihmc.F32,
+                                                 seed=r["seed"], chain_id=r["chain_id"]))
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    done, lat_s, next_report = {}, [], time.perf_counter() + 10
+    deadline = t_start + args.serve_duration + args.drain
+    while len(done) < len(reqs) and time.perf_counter() < deadline:
+        for k, t in enumerate(tickets):
+            if t is None or k in done:
+                continue
+            if sv.poll(t) >= ihmc.REQ_DONE:
+                r = sv.fetch(t, want_psi=False)
+                done[k] = r
+                lat_s.append(r["t_done"] - r["t_submit"])
+        if time.perf_counter() > next_report:
+            st = sv.stats()
+            print(f"bench: t={time.perf_counter() - t_start:.0f}s done {len(done)}/{len(reqs)} "
+                  f"resident {st['resident']:.0f} queued {st['queued']:.0f}", file=sys.stderr, flush=True)
+            next_report += 10
+        time.sleep(0.002)
+    th.join()
+    t_end = time.perf_counter()
+    st = sv.stats()
+    incomplete = [k for k in range(len(reqs)) if k not in done]
+    sv.close()
+    ctx.close()
+    completed_work = sum(work[k] for k in done)
+    elapsed = t_end - t_start
+    lat = np.array(lat_s) if lat_s else np.array([float("nan")])
+    line = {
+        "metric": "site-MD-steps/s", "value": completed_work / elapsed, "unit": "site-MD-steps/s", "n_gpus": 1,
+        "steps": len(done), "warmup": 0, "ms_per_step": 1000.0 * elapsed / max(1, len(done)),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"serving: Poisson arrivals {args.rate:g}/s for {args.serve_duration:g} s; 2D or 3D "
+                               "(p = 1/2), L U{16..128} (2D) / U{16..64} (3D), beta U[0.2,0.6], uniform h "
+                               "U[0,0.1], C = 2d + 0.1, 50-1000 trajectories of 10-30 leap-frog steps, FP32 state, "
+                               "FP64 H; one step = one completed request",
+                   "requests": len(reqs), "offered_site_md_steps_per_s": sum(work) / args.serve_duration},
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "mean": float(lat.mean()), "max": float(lat.max())},
+        "completed": len(done), "incomplete": len(incomplete), "elapsed_s": elapsed,
+        "server": {"rounds": st["rounds"], "busy_s": st["busy_s"], "max_resident": st["max_resident"],
+                   "site_md_steps_in_rounds": st["site_md_steps"],
+                   "rate_while_busy": st["site_md_steps"] / st["busy_s"] if st["busy_s"] > 0 else None},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="large", choices=["large", "batched"],
-                    help="large (default): the 1024^2 + 128^3 single chains; batched: 4096 uneven chains")
+    ap.add_argument("--workload", default="large", choices=["large", "batched", "dense", "serving"],
+                    help="large (default): the 1024^2 + 128^3 single chains; batched: 4096 uneven chains; "
+                         "dense: 256 chains of an N=4096 all-to-all model; serving: Poisson request arrivals")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
+    ap.add_argument("--serve-duration", type=float, default=60.0, help="serving: seconds of arrivals")
+    ap.add_argument("--drain", type=float, default=120.0, help="serving: seconds allowed after the last arrival")
+    ap.add_argument("--products", type=int, default=6, choices=[3, 6], help="dense: BF16 limb products")
     ap.add_argument("--chains", type=int, default=4096, help="batched: number of chains")
     ap.add_argument("--plain-sample", type=int, default=16, help="batched: chains rerun alone")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
@@ -159,6 +320,12 @@ def main():
         args.steps = 10 if args.steps is None else args.steps
         args.warmup = 2 if args.warmup is None else args.warmup
         return bench_batched(args)
+    if args.workload == "serving":
+        return bench_serving(args)
+    if args.workload == "dense":
+        args.steps = 100 if args.steps is None else args.steps
+        args.warmup = 5 if args.warmup is None else args.warmup
+        return bench_dense(args)
     args.steps = 200 if args.steps is None else args.steps
     args.warmup = 20 if args.warmup is None else args.warmup
 

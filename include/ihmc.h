@@ -61,6 +61,7 @@ extern "C" {
 typedef struct ihmc_ctx ihmc_ctx;
 typedef struct ihmc_chains ihmc_chains;
 typedef struct ihmc_dense_chains ihmc_dense_chains;
+typedef struct ihmc_server ihmc_server;
 
 /* Device allocator hook (e.g. PyTorch's caching allocator).  alloc returns a
  * device pointer or NULL; free releases it. */
@@ -228,6 +229,52 @@ int ihmc_dense_force(ihmc_ctx* ctx, const ihmc_dense* model, int32_t n, const do
  * bound), resid (|r| of its Ritz pair; theta - resid is a lower bound once
  * theta has converged to the lowest eigenvalue) and the steps taken. */
 int ihmc_min_eig(ihmc_ctx* ctx, const double* K, int64_t N, double* theta, double* resid, int32_t* steps);
+
+/* ---- serving (continuous batching of lattice requests) --------------------- */
+
+#define IHMC_REQ_QUEUED 0
+#define IHMC_REQ_RUNNING 1
+#define IHMC_REQ_DONE 2
+#define IHMC_REQ_CANCELLED 3
+#define IHMC_REQ_FAILED 4
+
+/* Start a server on the context: a scheduler thread with its own HIP streams.
+ * Before every round it admits queued requests in arrival order while their
+ * device footprint fits budget_bytes (0: half the arena) and one of max_active
+ * chain slots (0: 1024) is free; a round advances every resident chain by one
+ * trajectory (the fused lattice passes of all resident chains share the
+ * launches); a chain that reached its n_traj is retired: results are copied to
+ * host memory and its device memory and slot go to the next request.  Results
+ * are bit-identical to the same request run alone (ihmc_run_lattice). */
+int ihmc_server_create(ihmc_ctx* ctx, uint64_t budget_bytes, int32_t max_active, ihmc_server** out);
+/* Stop: queued requests are cancelled, running ones are retired as cancelled,
+ * the scheduler is joined and every unfetched request is released. */
+int ihmc_server_destroy(ihmc_server* server);
+/* Queue one request (lattice and run as for ihmc_run_lattice; h, psi0 and
+ * replay_accept are copied before the call returns).  Thread-safe.  Errors:
+ * IHMC_E_INVAL (invalid parameters), IHMC_E_NOMEM (footprint above the
+ * budget), IHMC_E_AGAIN (queue full), IHMC_E_DEVICE (server stopped by a
+ * device error). */
+int ihmc_submit(ihmc_server* server, const ihmc_lattice* lat, const ihmc_run* run, uint64_t* ticket);
+/* State of a request (IHMC_REQ_*).  Thread-safe. */
+int ihmc_poll(ihmc_server* server, uint64_t ticket, int32_t* state);
+/* Block until the request has finished (done, cancelled or failed) or
+ * timeout_s seconds have passed; returns its state.  Thread-safe. */
+int ihmc_wait(ihmc_server* server, uint64_t ticket, double timeout_s, int32_t* state);
+/* Copy a finished request's results into `out` (as ihmc_chains_result; the
+ * series hold n_traj values) and release it; the ticket is invalid afterwards.
+ * times (3 doubles, or NULL): submission, admission and completion, in seconds
+ * since the server started.  IHMC_E_AGAIN while the request is still queued or
+ * running, IHMC_E_CANCELLED for a cancelled one (the trajectories done before
+ * the cancellation are still copied).  Thread-safe. */
+int ihmc_fetch(ihmc_server* server, uint64_t ticket, ihmc_result* out, double* times);
+/* Cancel a request: a queued one at once, a running one at the next round
+ * boundary.  Thread-safe. */
+int ihmc_cancel(ihmc_server* server, uint64_t ticket);
+/* out[10]: rounds, seconds spent in rounds, site-MD-steps done, largest
+ * number of resident chains, completed requests, queued now, resident now,
+ * seconds since start, device bytes held, budget. */
+int ihmc_server_stats(ihmc_server* server, double* out);
 
 /* ---- diagnostics (same kernels as the hot path) --------------------------- */
 

@@ -12,11 +12,15 @@
 // in the epilogues, so the diagonal never consumes BF16 precision.  The
 // Hamiltonian uses an FP64 GEMM of the stored FP32 field with the FP64 K.
 //
-// Layouts (row-major, chain-major for the B x N operands):
-//   K limbs   [L][Np][Np]  (site i, column k)
-//   X limbs   [L][Bp][Np]  (chain b, site k)
+// Layouts:
+//   K limbs   [L] x tiled (Np x Np), rows = sites i, columns = k
+//   X limbs   [L] x tiled (Bp x Np), rows = chains b, columns = sites k
 //   partials  [S][Bp][Np]  FP32 (split-K slices, summed in fixed order)
-// Np, Bp are N and B padded to multiples of 128; padding is zero.
+// "Tiled" stores each 128-row x 32-column block contiguously (8 KiB of BF16,
+// rows of 64 bytes), blocks ordered row-block major: one k-step of a GEMM
+// workgroup then reads one contiguous block per limb and operand, in whole
+// cache lines.  Np is N padded to a multiple of 256, Bp is B padded to a
+// multiple of 128; padding is zero.
 #include "chain_epilogue.hpp"
 #include "dense_kernels.hpp"
 #include "device_common.hpp"
@@ -24,6 +28,11 @@
 namespace ihmc {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Offset of element (row, k) of a tiled operand with Np columns.
+__host__ __device__ __forceinline__ int64_t tiled(int64_t row, int64_t k, int64_t Np) {
+  return (((row >> 7) * (Np >> 5) + (k >> 5)) << 12) + ((row & 127) << 5) + (k & 31);
+}
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -46,9 +55,10 @@ __global__ void k_dense_split_K(const double* __restrict__ K, int64_t N, int64_t
   const double x = (i < N && k < N) ? K[i * N + k] : 0.0;
   __bf16 a, b, c;
   split3(x, a, b, c);
-  Kl[idx] = a;
-  Kl[Np * Np + idx] = b;
-  Kl[2 * Np * Np + idx] = c;
+  const int64_t o = tiled(i, k, Np);
+  Kl[o] = a;
+  Kl[Np * Np + o] = b;
+  Kl[2 * Np * Np + o] = c;
 }
 
 // Padded FP64 copy of K for the Hamiltonian GEMM and the set-up solvers.
@@ -237,70 +247,85 @@ __global__ void k_dense_fill(double* __restrict__ x, int64_t N, int64_t Np, doub
 // ---------------------------------------------------------- split-K MFMA GEMM ---
 //
 // part[s][b][i] = sum_{k in slice s} sum_{(a, c) in products} Kl[a][i][k] * Xl[c][b][k]
-// Workgroup tile 128 sites x 128 chains, k-step 32, four waves of 64 x 64 (4 x 4
-// MFMA 16x16x32 tiles).  Operand tiles for all limbs are staged in LDS; rows are
-// padded to 40 elements to spread LDS banks.
-constexpr int GBM = 128, GBN = 128, GBK = 32, GPAD = 40;
+// Workgroup tile 128 sites x 128 chains, k-step 32, eight waves (two per SIMD)
+// of 32 sites x 64 chains (2 x 4 MFMA 16x16x32 tiles).  Operand tiles of all
+// limbs are staged in LDS, double buffered: the global loads of k-step t+1 are
+// issued into registers before the MFMAs of step t and written to the other
+// LDS buffer after them, so one barrier per k-step separates the two.  LDS rows
+// are padded to 40 elements, which makes the fragment reads conflict-free.
+constexpr int GBM = 128, GBN = 128, GBK = 32, GPAD = 40, GTHREADS = 512;
 
 template <int NL, int NPROD>
-__global__ __launch_bounds__(256) void k_dense_gemm_bf16(const __bf16* __restrict__ Kl, const __bf16* __restrict__ Xl,
-                                                         float* __restrict__ part, int64_t Np, int64_t Bp,
-                                                         int64_t kslice) {
-  __shared__ __align__(16) __bf16 sA[NL][GBM][GPAD];
-  __shared__ __align__(16) __bf16 sB[NL][GBN][GPAD];
+__global__ __launch_bounds__(GTHREADS) void k_dense_gemm_bf16(const __bf16* __restrict__ Kl,
+                                                              const __bf16* __restrict__ Xl, float* __restrict__ part,
+                                                              int64_t Np, int64_t Bp, int64_t kslice) {
+  __shared__ __align__(16) __bf16 sA[2][NL][GBM][GPAD];
+  __shared__ __align__(16) __bf16 sB[2][NL][GBN][GPAD];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t i0 = (int64_t)blockIdx.x * GBM, b0 = (int64_t)blockIdx.y * GBN;
-  const int64_t k_begin = (int64_t)blockIdx.z * kslice, k_end = k_begin + kslice;
-  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;  // wave's sub-tile
+  const int64_t k_begin = (int64_t)blockIdx.z * kslice;
+  const int nk = (int)(kslice / GBK);
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 64;  // wave's sub-tile
   // limb pairs (a, c) with a + c <= 2 (NPROD = 6) or <= 1 (NPROD = 3)
   constexpr int PA[6] = {0, 0, 1, 0, 1, 2};
   constexpr int PC[6] = {0, 1, 0, 2, 1, 0};
-
-  f32x4 acc[4][4];
+  // staging: a 128 x 32 block is 512 chunks of 8 elements, contiguous in the
+  // tiled layout; thread t moves chunk t (row t/4, k offset 8 (t%4)) per limb
+  const int srow = t >> 2, skc = (t & 3) * 8;
+  const __bf16* gA = Kl + tiled(i0, k_begin, Np) + t * 8;
+  const __bf16* gB = Xl + tiled(b0, k_begin, Np) + t * 8;
+  const int64_t lA = Np * Np, lB = Bp * Np;
+  bf16x8 ra[NL], rb[NL];
+  auto gload = [&](int64_t koff) {
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+    for (int l = 0; l < NL; ++l) {
+      ra[l] = *reinterpret_cast<const bf16x8*>(gA + l * lA + koff);
+      rb[l] = *reinterpret_cast<const bf16x8*>(gB + l * lB + koff);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      *reinterpret_cast<bf16x8*>(&sA[buf][l][srow][skc]) = ra[l];
+      *reinterpret_cast<bf16x8*>(&sB[buf][l][srow][skc]) = rb[l];
+    }
+  };
+
+  f32x4 acc[2][4];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int64_t k0 = k_begin; k0 < k_end; k0 += GBK) {
-    // stage: per limb, GBM rows x 32 k = 512 chunks of 8 elements (16 bytes)
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((int64_t)(kt + 1) << 12);  // next 128 x 32 block of the same row block
+    bf16x8 fa[NL][2], fb[NL][4];
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int ch = t + 256 * q;  // 0..511
-        const int row = ch >> 2, kc = (ch & 3) * 8;
-        const bf16x8 va =
-            *reinterpret_cast<const bf16x8*>(Kl + (int64_t)l * Np * Np + (i0 + row) * Np + k0 + kc);
-        *reinterpret_cast<bf16x8*>(&sA[l][row][kc]) = va;
-        const bf16x8 vb =
-            *reinterpret_cast<const bf16x8*>(Xl + (int64_t)l * Bp * Np + (b0 + row) * Np + k0 + kc);
-        *reinterpret_cast<bf16x8*>(&sB[l][row][kc]) = vb;
-      }
+      for (int r = 0; r < 2; ++r) fa[l][r] = *reinterpret_cast<const bf16x8*>(&sA[buf][l][wr + 16 * r + fr][fk]);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) fb[l][c] = *reinterpret_cast<const bf16x8*>(&sB[buf][l][wc + 16 * c + fr][fk]);
     }
-    __syncthreads();
-    const int fr = lane & 15, fk = (lane >> 4) * 8;
-    bf16x8 fa[NL][4], fb[NL][4];
-#pragma unroll
-    for (int l = 0; l < NL; ++l)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        fa[l][r] = *reinterpret_cast<const bf16x8*>(&sA[l][wr + 16 * r + fr][fk]);
-        fb[l][r] = *reinterpret_cast<const bf16x8*>(&sB[l][wc + 16 * r + fr][fk]);
-      }
 #pragma unroll
     for (int p = 0; p < NPROD; ++p)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c)
           acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[PA[p]][r], fb[PC[p]][c], acc[r][c], 0, 0, 0);
+    if (kt + 1 < nk) lstore(buf ^ 1);
     __syncthreads();
   }
   // D layout of the 16x16 MFMA: lane -> column (chain) lane % 16, rows 4 (lane / 16) + e
   float* out = part + (int64_t)blockIdx.z * Bp * Np;
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int64_t b = b0 + wc + 16 * c + (lane & 15);
@@ -312,15 +337,18 @@ __global__ __launch_bounds__(256) void k_dense_gemm_bf16(const __bf16* __restric
 // ------------------------------------------------------------- FP64 MFMA GEMM ---
 //
 // U64[b][i] = sum_k K64[i][k] psi[b][k] with psi the stored FP32 fields (exact in
-// FP64).  Tile 64 sites x 64 chains, k-step 16, four waves of 32 x 32 (2 x 2
-// MFMA 16x16x4 FP64 tiles).
+// FP64).  Tile 64 sites x 64 chains, k-step 32, four waves of 32 x 32 (2 x 2
+// MFMA 16x16x4 FP64 tiles); LDS double buffered with register prefetch of the
+// next k-step, as in the BF16 GEMM.
 // The field of chain b is read through its state: the accepted field (with its
 // sign) for a measurement, else the buffer holding the proposal after pass j.
+constexpr int DBK = 32, DPAD = 33;
+
 __global__ __launch_bounds__(256) void k_dense_gemm_f64(const double* __restrict__ K64,
                                                         const ChainDev* __restrict__ chains, int j, int measure,
                                                         double* __restrict__ U64, int64_t Np, int B) {
-  __shared__ double sA[64][17];
-  __shared__ double sB[64][17];
+  __shared__ double sA[2][64][DPAD];
+  __shared__ double sB[2][64][DPAD];
   __shared__ const float* sX[64];
   __shared__ float sS[64];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -341,35 +369,67 @@ __global__ __launch_bounds__(256) void k_dense_gemm_f64(const double* __restrict
     sS[t] = sg;
   }
   __syncthreads();
+  // staging: A = 64 rows x 32 doubles as 1024 double2 chunks (4 per thread),
+  // B = 64 rows x 32 floats as 512 float4 chunks (2 per thread)
+  double2 ra[4];
+  float4 rb[2];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ch = t + 256 * q, row = ch >> 4, c2 = (ch & 15) * 2;
+      ra[q] = *reinterpret_cast<const double2*>(K64 + (i0 + row) * Np + k0 + c2);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int ch = t + 256 * q, row = ch >> 3, c4 = (ch & 7) * 4;
+      const float* x = sX[row];
+      rb[q] = x ? *reinterpret_cast<const float4*>(x + k0 + c4) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ch = t + 256 * q, row = ch >> 4, c2 = (ch & 15) * 2;
+      sA[buf][row][c2] = ra[q].x;
+      sA[buf][row][c2 + 1] = ra[q].y;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int ch = t + 256 * q, row = ch >> 3, c4 = (ch & 7) * 4;
+      const float sg = sS[row];
+      sB[buf][row][c4] = (double)(sg * rb[q].x);
+      sB[buf][row][c4 + 1] = (double)(sg * rb[q].y);
+      sB[buf][row][c4 + 2] = (double)(sg * rb[q].z);
+      sB[buf][row][c4 + 3] = (double)(sg * rb[q].w);
+    }
+  };
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   f64x4 acc[2][2];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int c = 0; c < 2; ++c) acc[r][c] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t k0 = 0; k0 < Np; k0 += 16) {
+  const int nk = (int)(Np / DBK);
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((int64_t)(kt + 1) * DBK);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + 256 * q;  // 0..1023
-      const int row = e >> 4, kk = e & 15;
-      sA[row][kk] = K64[(i0 + row) * Np + k0 + kk];
-      const float* x = sX[row];
-      sB[row][kk] = x ? (double)(sS[row] * x[k0 + kk]) : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < 16; ks += 4) {
+    for (int ks = 0; ks < DBK; ks += 4) {
       const int fr = lane & 15, fk = ks + (lane >> 4);
       double fa[2], fb[2];
 #pragma unroll
-      for (int r = 0; r < 2; ++r) fa[r] = sA[wr + 16 * r + fr][fk];
+      for (int r = 0; r < 2; ++r) fa[r] = sA[buf][wr + 16 * r + fr][fk];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) fb[c] = sB[wc + 16 * c + fr][fk];
+      for (int c = 0; c < 2; ++c) fb[c] = sB[buf][wc + 16 * c + fr][fk];
 #pragma unroll
       for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int c = 0; c < 2; ++c) acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[r], fb[c], acc[r][c], 0, 0, 0);
     }
+    if (kt + 1 < nk) lstore(buf ^ 1);
     __syncthreads();
   }
   // D layout of the FP64 16x16 MFMA: lane -> column lane % 16, rows lane / 16 + 4 e
@@ -421,7 +481,7 @@ __global__ void k_dense_prep(const ChainDev* __restrict__ chains, int B, int64_t
   }
   __bf16 a, c, d;
   split_f32(v, a, c, d);
-  const int64_t o = (int64_t)b * Np + i;
+  const int64_t o = tiled(b, i, Np);
   Xl[o] = a;
   Xl[Bp * Np + o] = c;
   Xl[2 * Bp * Np + o] = d;
@@ -450,9 +510,10 @@ __global__ void k_dense_epi_w(const ChainDev* __restrict__ chains, int B, int64_
   W32[o] = w;
   __bf16 l0, l1, l2;
   split_f32(w, l0, l1, l2);
-  Wl[o] = l0;
-  Wl[Bp * Np + o] = l1;
-  Wl[2 * Bp * Np + o] = l2;
+  const int64_t ot = tiled(b, i, Np);
+  Wl[ot] = l0;
+  Wl[Bp * Np + ot] = l1;
+  Wl[2 * Bp * Np + ot] = l2;
 }
 
 // After F = K W: F += C w + h'/sqrt(J'); kick p, drift psi (not on the last pass),
@@ -512,9 +573,10 @@ __global__ __launch_bounds__(256) void k_dense_epi_f(const ChainDev* __restrict_
   if (MODE == PASS_FIRST || MODE == PASS_MIDDLE) {
     __bf16 l0, l1, l2;
     split_f32(psi_new, l0, l1, l2);
-    Xl[o] = l0;
-    Xl[Bp * Np + o] = l1;
-    Xl[2 * Bp * Np + o] = l2;
+    const int64_t ot = tiled(b, i, Np);
+    Xl[ot] = l0;
+    Xl[Bp * Np + ot] = l1;
+    Xl[2 * Bp * Np + ot] = l2;
   }
   if (MODE == PASS_FIRST || MODE == PASS_LAST) {
     uint32_t bad = 0u;
@@ -625,8 +687,8 @@ hipError_t dense_gemm_bf16(int nprod, const __bf16* Kl, const __bf16* Xl, float*
                            hipStream_t s) {
   dim3 grid((unsigned)(Np / GBM), (unsigned)(Bp / GBN), (unsigned)S);
   const int64_t kslice = Np / S;
-  if (nprod == 6) k_dense_gemm_bf16<3, 6><<<grid, 256, 0, s>>>(Kl, Xl, part, Np, Bp, kslice);
-  else k_dense_gemm_bf16<2, 3><<<grid, 256, 0, s>>>(Kl, Xl, part, Np, Bp, kslice);
+  if (nprod == 6) k_dense_gemm_bf16<3, 6><<<grid, GTHREADS, 0, s>>>(Kl, Xl, part, Np, Bp, kslice);
+  else k_dense_gemm_bf16<2, 3><<<grid, GTHREADS, 0, s>>>(Kl, Xl, part, Np, Bp, kslice);
   return hipGetLastError();
 }
 

@@ -24,7 +24,10 @@ static inline int64_t round_up(int64_t a, int64_t m) { return (a + m - 1) / m * 
 
 // Lowest eigenvalue of the symmetric tridiagonal T (diagonal a[0..m), off-
 // diagonal b[0..m-1)) by Sturm-count bisection, and the last component of its
-// normalised eigenvector (from the LDL^T factors of T - theta 1).
+// normalised eigenvector by inverse iteration with the LDL^T factors of the
+// positive definite T - sigma 1, sigma just below theta.  (Back-substitution
+// from the top-down factors of T - theta 1 alone is unreliable exactly when the
+// Ritz pair has converged, i.e. when that last component is tiny.)
 static void tridiag_min(const std::vector<double>& a, const std::vector<double>& b, int m, double* theta,
                         double* last) {
   double lo = a[0], hi = a[0];
@@ -50,20 +53,25 @@ static void tridiag_min(const std::vector<double>& a, const std::vector<double>&
     if (count_below(mid) >= 1) hi = mid;
     else lo = mid;
   }
-  const double th = lo;  // no eigenvalue below lo: T - lo 1 is positive semi-definite
-  // Null vector of T - th 1 from its LDL^T factors: s_{m-1} = 1, s_i = -l_i s_{i+1}.
-  std::vector<double> d(m), s(m);
-  d[0] = a[0] - th;
-  for (int i = 1; i < m; ++i) d[i] = (a[i] - th) - b[i - 1] * b[i - 1] / (d[i - 1] != 0.0 ? d[i - 1] : 1e-300);
-  s[m - 1] = 1.0;
-  double nrm = 1.0;
-  for (int i = m - 2; i >= 0; --i) {
-    const double l = b[i] / (d[i] != 0.0 ? d[i] : 1e-300);
-    s[i] = -l * s[i + 1];
-    nrm += s[i] * s[i];
+  const double th = lo;  // no eigenvalue below lo
+  const double sigma = th - 1e-9 * (std::fabs(th) + 1.0);
+  std::vector<double> d(m), l(m > 1 ? m - 1 : 1), x(m, 1.0);
+  d[0] = a[0] - sigma;
+  for (int i = 1; i < m; ++i) {
+    l[i - 1] = b[i - 1] / d[i - 1];
+    d[i] = (a[i] - sigma) - l[i - 1] * b[i - 1];
+  }
+  for (int it = 0; it < 3; ++it) {
+    for (int i = 1; i < m; ++i) x[i] -= l[i - 1] * x[i - 1];  // L y = x
+    for (int i = 0; i < m; ++i) x[i] /= d[i];                 // D z = y
+    for (int i = m - 2; i >= 0; --i) x[i] -= l[i] * x[i + 1];  // L^T s = z
+    double nrm = 0.0;
+    for (int i = 0; i < m; ++i) nrm += x[i] * x[i];
+    nrm = std::sqrt(nrm);
+    for (int i = 0; i < m; ++i) x[i] /= nrm;
   }
   *theta = th;
-  *last = 1.0 / std::sqrt(nrm);
+  *last = std::fabs(x[m - 1]);
 }
 
 // FP64 Lanczos on the padded device matrix K64 (zero shift), with full

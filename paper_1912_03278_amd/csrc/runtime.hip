@@ -241,6 +241,87 @@ __global__ __launch_bounds__(256) void k_field_cg(ChainDev* cds, const int* whic
 
 static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
+// Descriptor of one lattice chain (no device memory yet).
+void describe_chain(const ihmc_lattice& l, const ihmc_run& r, int flags, ChainDev& c) {
+  std::memset(&c, 0, sizeof c);
+  c.ndim = l.ndim;
+  c.L0 = l.L[0];
+  c.L1 = l.L[1];
+  c.L2 = l.ndim == 3 ? l.L[2] : 1;
+  c.N = lattice_sites(l);
+  c.pitch = (c.L0 + 3) & ~3;
+  c.NP = (int64_t)c.pitch * c.L1 * c.L2;
+  c.integrator = r.integrator;
+  c.n_pass = r.integrator == OMELYAN ? 2 * r.n_md + 1 : r.n_md + 1;
+  c.flip_every = r.flip_every;
+  c.h_kind = l.h_len == 0 ? 0 : (l.h_len == 1 ? 1 : 2);
+  c.chain_id = (uint32_t)r.chain_id;
+  c.seed_lo = (uint32_t)r.seed;
+  c.seed_hi = (uint32_t)(r.seed >> 32);
+  c.Jp = l.beta * l.J;
+  c.sqJ = std::sqrt(c.Jp);
+  c.C = l.C;
+  c.eps = r.traj_len / r.n_md;
+  c.hp0 = c.h_kind == 1 ? l.beta * l.h[0] : 0.0;
+  c.b0 = c.h_kind == 1 ? c.hp0 / c.sqJ : 0.0;
+  const double n0c = 2.0 * l.ndim + l.C;
+  // Kt 1 = (n0 + C) 1 on the periodic lattice (eq. hKh_for_constant_h)
+  c.c_v = (double)c.N / n0c;
+  c.c_m = c.h_kind == 1 ? (double)c.N * c.hp0 / n0c : 0.0;
+  c.c_e = c.h_kind == 1 ? (double)c.N * c.hp0 * c.hp0 / n0c : 0.0;
+  c.cap = r.n_traj;
+  c.precision = r.precision;
+  c.p_given = (flags & BUILD_P_GIVEN) ? 1 : 0;
+  c.write_p_last = (flags & BUILD_WRITE_P) ? 1 : 0;
+  c.n_tiles = chain_tile_count(c);
+}
+
+// Tiles of one chain in the tile shape of its launch group.
+uint32_t chain_tile_count(const ChainDev& c) {
+  const TileShape ts = tile_shape(c.precision, c.ndim, tile_class(c.ndim, c.L0));
+  const uint32_t nz = c.ndim == 3 ? (uint32_t)((c.L2 + ts.bz - 1) / ts.bz) : 1u;
+  return nz * (uint32_t)((c.L1 + ts.by - 1) / ts.by) * (uint32_t)((c.L0 + ts.bx - 1) / ts.bx);
+}
+
+// Launch groups of equal (precision, ndim, tile class) over the chains
+// `members` (indices into cd), each sorted by pass count (descending), and
+// their tiles appended to `tiles` (group tile offsets relative to its start).
+void plan_groups(const std::vector<ChainDev>& cd, const std::vector<int>& members, std::vector<Group>& groups,
+                 std::vector<Tile>& tiles) {
+  const int base = (int)tiles.size();
+  std::map<std::tuple<int, int, int>, std::vector<int>> byk;
+  for (int i : members)
+    byk[std::make_tuple(cd[i].precision, cd[i].ndim, tile_class(cd[i].ndim, cd[i].L0))].push_back(i);
+  for (auto& kv : byk) {
+    Group g;
+    g.prec = std::get<0>(kv.first);
+    g.ndim = std::get<1>(kv.first);
+    g.cls = std::get<2>(kv.first);
+    g.order = kv.second;
+    std::stable_sort(g.order.begin(), g.order.end(), [&](int a, int b) { return cd[a].n_pass > cd[b].n_pass; });
+    const TileShape ts = tile_shape(g.prec, g.ndim, g.cls);
+    g.tile_off = (int)tiles.size() - base;
+    for (int ci : g.order) {
+      const ChainDev& c = cd[ci];
+      g.tile_begin.push_back((int)tiles.size() - base - g.tile_off);
+      for (int z = 0; z < c.L2; z += (g.ndim == 3 ? ts.bz : 1))
+        for (int y = 0; y < c.L1; y += ts.by)
+          for (int x = 0; x < c.L0; x += ts.bx) tiles.push_back(Tile{ci, x, y, z});
+      g.n_pass.push_back(c.n_pass);
+    }
+    g.tile_begin.push_back((int)tiles.size() - base - g.tile_off);
+    g.max_pass = cd[g.order[0]].n_pass;
+    groups.push_back(g);
+  }
+}
+
+// Events one round of the plan needs.
+size_t round_events(const std::vector<Group>& groups) {
+  size_t n = 1;
+  for (auto& g : groups) n += (size_t)g.max_pass + 2;
+  return n;
+}
+
 // ------------------------------------------------------------ validation ---
 
 int64_t lattice_sites(const ihmc_lattice& l) {
@@ -391,36 +472,7 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
     int rc = validate(l, r, i);
     if (rc) return rc;
     ChainDev& c = cd[i];
-    std::memset(&c, 0, sizeof c);
-    c.ndim = l.ndim;
-    c.L0 = l.L[0];
-    c.L1 = l.L[1];
-    c.L2 = l.ndim == 3 ? l.L[2] : 1;
-    c.N = lattice_sites(l);
-    c.pitch = (c.L0 + 3) & ~3;
-    c.NP = (int64_t)c.pitch * c.L1 * c.L2;
-    c.integrator = r.integrator;
-    c.n_pass = r.integrator == OMELYAN ? 2 * r.n_md + 1 : r.n_md + 1;
-    c.flip_every = r.flip_every;
-    c.h_kind = l.h_len == 0 ? 0 : (l.h_len == 1 ? 1 : 2);
-    c.chain_id = (uint32_t)r.chain_id;
-    c.seed_lo = (uint32_t)r.seed;
-    c.seed_hi = (uint32_t)(r.seed >> 32);
-    c.Jp = l.beta * l.J;
-    c.sqJ = std::sqrt(c.Jp);
-    c.C = l.C;
-    c.eps = r.traj_len / r.n_md;
-    c.hp0 = c.h_kind == 1 ? l.beta * l.h[0] : 0.0;
-    c.b0 = c.h_kind == 1 ? c.hp0 / c.sqJ : 0.0;
-    const double n0c = 2.0 * l.ndim + l.C;
-    // Kt 1 = (n0 + C) 1 on the periodic lattice (eq. hKh_for_constant_h)
-    c.c_v = (double)c.N / n0c;
-    c.c_m = c.h_kind == 1 ? (double)c.N * c.hp0 / n0c : 0.0;
-    c.c_e = c.h_kind == 1 ? (double)c.N * c.hp0 * c.hp0 / n0c : 0.0;
-    c.cap = r.n_traj;
-    c.precision = r.precision;
-    c.p_given = (flags & BUILD_P_GIVEN) ? 1 : 0;
-    c.write_p_last = (flags & BUILD_WRITE_P) ? 1 : 0;
+    describe_chain(l, r, flags, c);
     const int64_t N = c.N, NP = c.NP;
     const int64_t pb = r.precision;
     c.psi = dalloc(3 * NP * pb);
@@ -457,41 +509,16 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
     return set_error(IHMC_E_NOMEM, "arena exhausted (chain table)");
   }
 
-  // ---- groups of equal (precision, ndim), chains sorted by passes (descending)
-  std::map<std::tuple<int, int, int>, std::vector<int>> byk;
-  for (int i = 0; i < n; ++i)
-    byk[std::make_tuple(cd[i].precision, cd[i].ndim, tile_class(cd[i].ndim, cd[i].L0))].push_back(i);
+  // ---- groups of equal (precision, ndim, tile class), chains sorted by passes (descending)
   std::vector<Tile> all_tiles;
-  for (auto& kv : byk) {
-    Group g;
-    g.prec = std::get<0>(kv.first);
-    g.ndim = std::get<1>(kv.first);
-    g.cls = std::get<2>(kv.first);
-    g.order = kv.second;
-    std::stable_sort(g.order.begin(), g.order.end(), [&](int a, int b) { return cd[a].n_pass > cd[b].n_pass; });
-    const TileShape ts = tile_shape(g.prec, g.ndim, g.cls);
-    g.tile_off = (int)all_tiles.size();
-    for (int ci : g.order) {
-      ChainDev& c = cd[ci];
-      g.tile_begin.push_back((int)all_tiles.size() - g.tile_off);
-      uint32_t cnt = 0;
-      for (int z = 0; z < c.L2; z += (g.ndim == 3 ? ts.bz : 1))
-        for (int y = 0; y < c.L1; y += ts.by)
-          for (int x = 0; x < c.L0; x += ts.bx) {
-            all_tiles.push_back(Tile{ci, x, y, z});
-            ++cnt;
-          }
-      c.n_tiles = cnt;
-      g.n_pass.push_back(c.n_pass);
-    }
-    g.tile_begin.push_back((int)all_tiles.size() - g.tile_off);
-    g.max_pass = cd[g.order[0]].n_pass;
-    groups.push_back(g);
+  {
+    std::vector<int> members(n);
+    for (int i = 0; i < n; ++i) members[i] = i;
+    plan_groups(cd, members, groups, all_tiles);
   }
   // streams and events of the per-round fork/join (default priority)
   {
-    size_t n_ev = 1;
-    for (auto& g : groups) n_ev += (size_t)g.max_pass + 2;
+    const size_t n_ev = round_events(groups);
     for (size_t k = 0; k < 2 * groups.size(); ++k) {
       hipStream_t st = nullptr;
       HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "side stream");
@@ -586,7 +613,9 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
 // their own, and the LAST launches of a group on a second stream: LAST(j) only
 // waits for launch j-1 of its group, so it overlaps MIDDLE(j) of the other
 // chains.  Captured once, the fork/join structure becomes graph edges.
-hipError_t Chains::enqueue_round(hipStream_t s) {
+hipError_t enqueue_round_plan(const std::vector<Group>& groups, const Tile* d_tiles, const ChainDev* d_cd,
+                              const std::vector<hipStream_t>& side, const std::vector<hipEvent_t>& events,
+                              hipStream_t s) {
   hipError_t e;
   int ev = 0;
   auto next_event = [&]() { return events[ev++]; };
@@ -627,6 +656,8 @@ hipError_t Chains::enqueue_round(hipStream_t s) {
   }
   return hipSuccess;
 }
+
+hipError_t Chains::enqueue_round(hipStream_t s) { return enqueue_round_plan(groups, d_tiles, d_cd, side, events, s); }
 
 int Chains::advance(int32_t n_traj) {
   if (n_traj < 0) return set_error(IHMC_E_INVAL, "n_traj must be >= 0");
@@ -1034,6 +1065,25 @@ hipError_t launch_init_psi(const ChainDev* d_cd, int ci, const double* psi0, int
   if (precision == 4) k_init_psi<float><<<nblk(N), 256, 0, s>>>(d_cd, ci, psi0);
   else k_init_psi<double><<<nblk(N), 256, 0, s>>>(d_cd, ci, psi0);
   return hipGetLastError();
+}
+hipError_t launch_field_setup(const ChainDev* d_cd, int ci, const double* h, double beta, int64_t N, int precision,
+                              hipStream_t s) {
+  if (precision == 4) k_field_setup<float><<<nblk(N), 256, 0, s>>>(d_cd, ci, h, beta);
+  else k_field_setup<double><<<nblk(N), 256, 0, s>>>(d_cd, ci, h, beta);
+  return hipGetLastError();
+}
+hipError_t launch_field_cg(ChainDev* d_cd, const int* which, int n, double* work, const int64_t* woff,
+                           hipStream_t s) {
+  if (n > 0) k_field_cg<<<(unsigned)n, 256, 0, s>>>(d_cd, which, work, woff);
+  return hipGetLastError();
+}
+hipError_t launch_measure(const std::vector<Group>& groups, const Tile* d_tiles, const ChainDev* d_cd, hipStream_t s) {
+  for (auto& g : groups) {
+    hipError_t e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_MEASURE, d_cd, d_tiles + g.tile_off,
+                                       g.tile_begin.back(), 0, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 hipError_t launch_zero_state(ChainState* st, hipStream_t s) {
   k_zero_state<<<1, 256, 0, s>>>(st);

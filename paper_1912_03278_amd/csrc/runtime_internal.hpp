@@ -47,6 +47,29 @@ struct Group {
   int max_pass = 0;
 };
 
+// Chain descriptors, launch plans and rounds shared by the resident chain sets
+// and the serving loop (runtime.hip).
+int validate(const ihmc_lattice& l, const ihmc_run& r, int idx);
+int64_t lattice_sites(const ihmc_lattice& l);
+void describe_chain(const ihmc_lattice& l, const ihmc_run& r, int flags, ChainDev& c);
+uint32_t chain_tile_count(const ChainDev& c);
+void plan_groups(const std::vector<ChainDev>& cd, const std::vector<int>& members, std::vector<Group>& groups,
+                 std::vector<Tile>& tiles);
+size_t round_events(const std::vector<Group>& groups);
+// One trajectory of every chain of the plan: FIRST over all tiles of a group,
+// then MIDDLE / LAST per pass index; groups on side streams (two per group).
+hipError_t enqueue_round_plan(const std::vector<Group>& groups, const Tile* d_tiles, const ChainDev* d_cd,
+                              const std::vector<hipStream_t>& side, const std::vector<hipEvent_t>& events,
+                              hipStream_t s);
+// Per-site field of chain ci into its stored layout (h: device, logical order).
+hipError_t launch_field_setup(const ChainDev* d_cd, int ci, const double* h, double beta, int64_t N, int precision,
+                              hipStream_t s);
+// h'^T Kt^-1 h' and 1^T Kt^-1 h' of the chains `which` (device int array, n
+// entries) by CG, one block per chain; work: 4 N doubles per chain at woff.
+hipError_t launch_field_cg(ChainDev* d_cd, const int* which, int n, double* work, const int64_t* woff,
+                           hipStream_t s);
+hipError_t launch_measure(const std::vector<Group>& groups, const Tile* d_tiles, const ChainDev* d_cd, hipStream_t s);
+
 struct Chains {
   ihmc_ctx* ctx = nullptr;
   int n = 0;

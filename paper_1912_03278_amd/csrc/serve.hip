@@ -1,0 +1,619 @@
+// Serving loop: continuous batching of HMC requests.
+//
+// Requests (one lattice chain each) are submitted asynchronously.  A scheduler
+// thread owns the device side: before every round it admits queued requests,
+// in arrival order, while their device footprint fits the server's HBM budget
+// and a chain slot is free, sets them up (initial field, S(psi0)), then advances
+// every resident chain by one trajectory with the fused lattice passes, and
+// retires the chains that reached their trajectory count: their series, state
+// and final field are copied to host memory, their device memory and slot are
+// released, and the next queued requests take their place.  Chain state stays
+// on the device between rounds.  A chain's arithmetic depends only on its own
+// parameters (fixed-point sums, per-site work independent of the tile and of
+// the other chains in a launch), so a served result is bit-identical to the
+// same request run alone.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "lattice_kernels.hpp"
+#include "runtime_internal.hpp"
+
+using namespace ihmc;
+
+namespace ihmc {
+
+enum ReqState : int32_t { REQ_QUEUED = 0, REQ_RUNNING = 1, REQ_DONE = 2, REQ_CANCELLED = 3, REQ_FAILED = 4 };
+
+struct Request {
+  uint64_t ticket = 0;
+  int32_t state = REQ_QUEUED;
+  ihmc_lattice lat{};
+  ihmc_run run{};
+  std::vector<double> h, psi0;
+  std::vector<uint8_t> replay;
+  uint64_t need = 0;  // device bytes while resident
+  int slot = -1;
+  ChainDev cd{};
+  std::vector<void*> dev;  // arena blocks
+  int rounds = 0;
+  bool cancel = false;
+  std::vector<TrajRecord> rec;
+  ChainState st{};
+  std::vector<double> psi;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  int err_code = 0;
+  std::string error;
+};
+
+static inline uint64_t r256(uint64_t b) { return (b + 255ull) & ~255ull; }
+
+// Device bytes a request holds while resident (state, records, field arrays,
+// and its share of the tile table), plus its set-up staging.
+static uint64_t request_bytes(const ihmc_lattice& l, const ihmc_run& r) {
+  const int64_t N = lattice_sites(l);
+  const int64_t pitch = (l.L[0] + 3) & ~3;
+  const int64_t NP = pitch * (N / l.L[0]);
+  const uint64_t pb = (uint64_t)r.precision;
+  uint64_t b = r256(3 * NP * pb) + r256(NP * pb) + r256(sizeof(TrajRecord) * (uint64_t)std::max(1, r.n_traj)) +
+               r256(sizeof(ChainState)) + r256(8 * (uint64_t)N);
+  if (r.replay_accept) b += r256((uint64_t)r.n_traj);
+  if (l.h_len == N && N > 1) b += r256(8 * NP) + r256(NP * pb) + r256(8 * 4 * (uint64_t)N) + r256(8 * (uint64_t)N);
+  b += r256(sizeof(Tile) * ((uint64_t)N / 64 + 16));
+  return b;
+}
+
+}  // namespace ihmc
+
+struct ihmc_server {
+  ihmc_ctx* ctx = nullptr;
+  uint64_t budget = 0;
+  int max_active = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::thread th;
+  bool stop = false;
+  std::deque<Request*> queue;
+  std::vector<Request*> active;
+  std::map<uint64_t, Request*> reqs;
+  uint64_t next_ticket = 1, used = 0;
+  // device side (scheduler thread only)
+  hipStream_t s = nullptr;
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> events;
+  ChainDev* d_cd = nullptr;
+  std::vector<ChainDev> cd_host;  // slot table
+  std::vector<int> free_slots;
+  Tile* d_tiles = nullptr;
+  Tile* h_tiles = nullptr;  // pinned staging of the tile table
+  size_t tile_cap = 0;
+  double* d_export = nullptr;
+  int64_t export_cap = 0;
+  // statistics
+  std::chrono::steady_clock::time_point t0;
+  int64_t rounds = 0, completed = 0;
+  double busy_s = 0.0, site_steps = 0.0;
+  int max_seen = 0;
+  bool dead = false;
+  std::string dead_msg;
+
+  double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+  void loop();
+  bool admit_setup(std::vector<Request*>& fresh);
+  bool run_round();
+  void retire(Request* r, int32_t final_state);
+  void fail_all(const char* what, hipError_t e);
+  bool ensure_tiles(size_t n);
+  bool ensure_streams(size_t n_groups, size_t n_events);
+};
+
+void ihmc_server::fail_all(const char* what, hipError_t e) {
+  std::lock_guard<std::mutex> lk(mu);
+  dead = true;
+  dead_msg = std::string(what) + ": " + hipGetErrorString(e);
+  ctx->dead = true;
+  for (Request* r : active) {
+    r->state = REQ_FAILED;
+    r->err_code = IHMC_E_DEVICE;
+    r->error = dead_msg;
+  }
+  active.clear();
+  for (Request* r : queue) {
+    r->state = REQ_FAILED;
+    r->err_code = IHMC_E_DEVICE;
+    r->error = dead_msg;
+  }
+  queue.clear();
+  cv_done.notify_all();
+}
+
+bool ihmc_server::ensure_tiles(size_t n) {
+  if (n <= tile_cap) return true;
+  const size_t cap = std::max<size_t>(n, 2 * tile_cap);
+  if (d_tiles) ctx->arena.release(d_tiles);
+  if (h_tiles) hipHostFree(h_tiles);
+  d_tiles = nullptr;
+  h_tiles = nullptr;
+  tile_cap = 0;
+  d_tiles = (Tile*)ctx->arena.alloc(sizeof(Tile) * cap);
+  if (!d_tiles) return false;
+  if (hipHostMalloc((void**)&h_tiles, sizeof(Tile) * cap, 0) != hipSuccess) {
+    h_tiles = nullptr;
+    ctx->arena.release(d_tiles);
+    d_tiles = nullptr;
+    return false;
+  }
+  tile_cap = cap;
+  return true;
+}
+
+bool ihmc_server::ensure_streams(size_t n_groups, size_t n_events) {
+  while (side.size() < 2 * n_groups) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return false;
+    side.push_back(st);
+  }
+  while (events.size() < n_events) {
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return false;
+    events.push_back(ev);
+  }
+  return true;
+}
+
+// Copy a finished (or cancelled) chain's results to host memory and release
+// its device memory and slot.  Scheduler thread; the stream is idle.
+void ihmc_server::retire(Request* r, int32_t final_state) {
+  const ChainDev& c = cd_host[r->slot];
+  hipError_t e = hipMemcpyAsync(&r->st, c.st, sizeof(ChainState), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  const int done = std::min(r->st.traj, c.cap);
+  if (e == hipSuccess && done > 0) {
+    r->rec.resize(done);
+    e = hipMemcpyAsync(r->rec.data(), c.rec, sizeof(TrajRecord) * done, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
+  if (e == hipSuccess) {
+    if (c.N > export_cap) {
+      if (d_export) ctx->arena.release(d_export);
+      d_export = (double*)ctx->arena.alloc(8 * (uint64_t)c.N);
+      export_cap = d_export ? c.N : 0;
+    }
+    if (d_export) {
+      r->psi.resize(c.N);
+      e = launch_export_psi(d_cd, r->slot, d_export, c.N, c.precision, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(r->psi.data(), d_export, 8 * c.N, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+  }
+  for (void* p : r->dev) ctx->arena.release(p);
+  r->dev.clear();
+  std::lock_guard<std::mutex> lk(mu);
+  free_slots.push_back(r->slot);
+  used -= r->need;
+  r->t_done = now();
+  if (e != hipSuccess) {
+    r->state = REQ_FAILED;
+    r->err_code = IHMC_E_DEVICE;
+    r->error = std::string("result copy: ") + hipGetErrorString(e);
+  } else {
+    r->state = final_state;
+    if (final_state == REQ_DONE) ++completed;
+  }
+  cv_done.notify_all();
+}
+
+// Device set-up of newly admitted requests: memory, descriptor upload, initial
+// field, per-site field constants, and the measurement of S(psi0).
+bool ihmc_server::admit_setup(std::vector<Request*>& fresh) {
+  std::vector<void*> temps;
+  auto tmp = [&](uint64_t b) {
+    void* p = ctx->arena.alloc(b);
+    if (p) temps.push_back(p);
+    return p;
+  };
+  std::vector<Request*> ok;
+  std::vector<int> cg_slots;
+  std::vector<int64_t> cg_off;
+  int64_t cg_total = 0;
+  hipError_t e = hipSuccess;
+  for (Request* r : fresh) {
+    ChainDev& c = r->cd;
+    describe_chain(r->lat, r->run, 0, c);
+    const uint64_t pb = (uint64_t)c.precision;
+    auto dal = [&](uint64_t b) {
+      void* p = ctx->arena.alloc(b);
+      if (p) r->dev.push_back(p);
+      return p;
+    };
+    c.psi = dal(3 * c.NP * pb);
+    c.p = dal(c.NP * pb);
+    c.rec = (TrajRecord*)dal(sizeof(TrajRecord) * (uint64_t)std::max(1, r->run.n_traj));
+    c.st = (ChainState*)dal(sizeof(ChainState));
+    bool good = c.psi && c.p && c.rec && c.st;
+    if (good && !r->replay.empty()) {
+      uint8_t* d = (uint8_t*)dal(r->replay.size());
+      good = d != nullptr;
+      if (good) e = hipMemcpyAsync(d, r->replay.data(), r->replay.size(), hipMemcpyHostToDevice, s);
+      c.replay = d;
+    }
+    if (good && c.h_kind == 2) {
+      c.hp = (double*)dal(8 * (uint64_t)c.NP);
+      c.b = dal((uint64_t)c.NP * pb);
+      good = c.hp && c.b;
+    }
+    if (!good || e != hipSuccess) {
+      for (void* p : r->dev) ctx->arena.release(p);
+      r->dev.clear();
+      std::lock_guard<std::mutex> lk(mu);
+      used -= r->need;
+      free_slots.push_back(r->slot);
+      r->state = REQ_FAILED;
+      r->err_code = e != hipSuccess ? IHMC_E_DEVICE : IHMC_E_NOMEM;
+      r->error = e != hipSuccess ? "replay upload failed" : "device arena exhausted at admission";
+      r->t_done = now();
+      cv_done.notify_all();
+      if (e != hipSuccess) break;
+      continue;
+    }
+    cd_host[r->slot] = c;
+    e = hipMemcpyAsync(d_cd + r->slot, &cd_host[r->slot], sizeof(ChainDev), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_zero_state(c.st, s);
+    if (e == hipSuccess && c.h_kind == 2) {
+      double* t = (double*)tmp(8 * (uint64_t)c.N);
+      if (!t) e = hipErrorOutOfMemory;
+      if (e == hipSuccess) e = hipMemcpyAsync(t, r->h.data(), 8 * c.N, hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = launch_field_setup(d_cd, r->slot, t, r->lat.beta, c.N, c.precision, s);
+      cg_slots.push_back(r->slot);
+      cg_off.push_back(cg_total);
+      cg_total += 4 * c.N;
+    }
+    if (e == hipSuccess) {
+      const double* src = nullptr;
+      if (!r->psi0.empty()) {
+        double* t = (double*)tmp(8 * (uint64_t)c.N);
+        if (!t) e = hipErrorOutOfMemory;
+        if (e == hipSuccess) e = hipMemcpyAsync(t, r->psi0.data(), 8 * c.N, hipMemcpyHostToDevice, s);
+        src = t;
+      }
+      if (e == hipSuccess) e = launch_init_psi(d_cd, r->slot, src, c.N, c.precision, s);
+    }
+    if (e != hipSuccess) break;
+    ok.push_back(r);
+  }
+  if (e == hipSuccess && !cg_slots.empty()) {
+    double* work = (double*)tmp(8 * (uint64_t)cg_total);
+    int* which = (int*)tmp(sizeof(int) * cg_slots.size());
+    int64_t* woff = (int64_t*)tmp(sizeof(int64_t) * cg_off.size());
+    if (!work || !which || !woff) e = hipErrorOutOfMemory;
+    if (e == hipSuccess) e = hipMemcpyAsync(which, cg_slots.data(), sizeof(int) * cg_slots.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(woff, cg_off.data(), sizeof(int64_t) * cg_off.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_field_cg(d_cd, which, (int)cg_slots.size(), work, woff, s);
+  }
+  if (e == hipSuccess && !ok.empty()) {
+    std::vector<int> slots;
+    for (Request* r : ok) slots.push_back(r->slot);
+    std::vector<Group> g;
+    std::vector<Tile> tiles;
+    plan_groups(cd_host, slots, g, tiles);
+    if (!ensure_tiles(tiles.size())) {
+      e = hipErrorOutOfMemory;
+    } else {
+      std::memcpy(h_tiles, tiles.data(), sizeof(Tile) * tiles.size());
+      e = hipMemcpyAsync(d_tiles, h_tiles, sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = launch_measure(g, d_tiles, d_cd, s);
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  for (void* p : temps) ctx->arena.release(p);
+  if (e != hipSuccess) {
+    {
+      // requests of this batch are in neither the queue nor the active set yet
+      std::lock_guard<std::mutex> lk(mu);
+      for (Request* r : fresh)
+        if (r->state == REQ_QUEUED) {
+          for (void* p : r->dev) ctx->arena.release(p);
+          r->dev.clear();
+          r->state = REQ_FAILED;
+          r->err_code = IHMC_E_DEVICE;
+          r->error = "request set-up failed";
+        }
+    }
+    fail_all("request set-up", e);
+    return false;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  for (Request* r : ok) {
+    r->state = REQ_RUNNING;
+    active.push_back(r);
+  }
+  max_seen = std::max(max_seen, (int)active.size());
+  return true;
+}
+
+// One trajectory of every resident chain that has trajectories left.
+bool ihmc_server::run_round() {
+  std::vector<int> slots;
+  double work = 0.0;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (Request* r : active)
+      if (!r->cancel && r->rounds < r->run.n_traj) {
+        slots.push_back(r->slot);
+        work += (double)r->cd.N * r->run.n_md;
+      }
+  }
+  if (slots.empty()) return true;
+  std::vector<Group> g;
+  std::vector<Tile> tiles;
+  plan_groups(cd_host, slots, g, tiles);
+  const auto t_start = std::chrono::steady_clock::now();
+  hipError_t e = hipSuccess;
+  if (!ensure_tiles(tiles.size()) || !ensure_streams(g.size(), round_events(g))) e = hipErrorOutOfMemory;
+  if (e == hipSuccess) {
+    std::memcpy(h_tiles, tiles.data(), sizeof(Tile) * tiles.size());
+    e = hipMemcpyAsync(d_tiles, h_tiles, sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, s);
+  }
+  if (e == hipSuccess) e = enqueue_round_plan(g, d_tiles, d_cd, side, events, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    fail_all("round", e);
+    return false;
+  }
+  const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  std::lock_guard<std::mutex> lk(mu);
+  ++rounds;
+  busy_s += dt;
+  site_steps += work;
+  for (Request* r : active)
+    if (!r->cancel && r->rounds < r->run.n_traj) ++r->rounds;
+  return true;
+}
+
+void ihmc_server::loop() {
+  hipSetDevice(ctx->device);
+  for (;;) {
+    std::vector<Request*> fresh, finished;
+    bool quit = false;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      if (dead) return;
+      if (stop) {
+        for (Request* r : active) r->cancel = true;
+        quit = true;
+      }
+      for (Request* r : active)
+        if (r->cancel || r->rounds >= r->run.n_traj) finished.push_back(r);
+    }
+    for (Request* r : finished) {
+      retire(r, r->cancel ? REQ_CANCELLED : REQ_DONE);
+      std::lock_guard<std::mutex> lk(mu);
+      active.erase(std::find(active.begin(), active.end(), r));
+    }
+    if (quit) return;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      while (!queue.empty() && !free_slots.empty()) {
+        Request* r = queue.front();
+        if (used + r->need > budget && !(active.empty() && fresh.empty())) break;
+        queue.pop_front();
+        r->slot = free_slots.back();
+        free_slots.pop_back();
+        used += r->need;
+        r->t_admit = now();
+        fresh.push_back(r);
+      }
+      if (active.empty() && fresh.empty()) {
+        cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+        continue;
+      }
+    }
+    if (!fresh.empty() && !admit_setup(fresh)) return;
+    if (!run_round()) return;
+  }
+}
+
+// ============================================================ C ABI: serving ===
+
+extern "C" int ihmc_server_create(ihmc_ctx* ctx, uint64_t budget_bytes, int32_t max_active, ihmc_server** out) {
+  CTX_OK(ctx);
+  if (!out) return set_error(IHMC_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (max_active <= 0) max_active = 1024;
+  if (budget_bytes == 0 || budget_bytes > ctx->arena.size) budget_bytes = ctx->arena.size / 2;
+  ihmc_server* sv = new (std::nothrow) ihmc_server();
+  if (!sv) return set_error(IHMC_E_NOMEM, "host allocation failed");
+  sv->ctx = ctx;
+  sv->budget = budget_bytes;
+  sv->max_active = max_active;
+  sv->t0 = std::chrono::steady_clock::now();
+  sv->cd_host.resize(max_active);
+  for (int i = max_active - 1; i >= 0; --i) sv->free_slots.push_back(i);
+  sv->d_cd = (ChainDev*)ctx->arena.alloc(sizeof(ChainDev) * (uint64_t)max_active);
+  hipError_t e = sv->d_cd ? hipStreamCreateWithFlags(&sv->s, hipStreamNonBlocking) : hipErrorOutOfMemory;
+  if (e != hipSuccess) {
+    if (sv->d_cd) ctx->arena.release(sv->d_cd);
+    delete sv;
+    return e == hipErrorOutOfMemory ? set_error(IHMC_E_NOMEM, "arena exhausted (slot table)")
+                                    : hip_fail(ctx, e, "server stream");
+  }
+  sv->th = std::thread([sv] { sv->loop(); });
+  *out = sv;
+  return IHMC_OK;
+}
+
+extern "C" int ihmc_server_destroy(ihmc_server* sv) {
+  if (!sv) return IHMC_OK;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+    for (Request* r : sv->queue) r->state = REQ_CANCELLED;
+    sv->queue.clear();
+  }
+  sv->cv_work.notify_all();
+  if (sv->th.joinable()) sv->th.join();
+  hipSetDevice(sv->ctx->device);
+  if (sv->s) hipStreamSynchronize(sv->s);
+  for (Request* r : sv->active)
+    for (void* p : r->dev) sv->ctx->arena.release(p);
+  for (auto& kv : sv->reqs) delete kv.second;
+  for (hipEvent_t ev : sv->events) hipEventDestroy(ev);
+  for (hipStream_t st : sv->side) hipStreamDestroy(st);
+  if (sv->s) hipStreamDestroy(sv->s);
+  if (sv->d_tiles) sv->ctx->arena.release(sv->d_tiles);
+  if (sv->h_tiles) hipHostFree(sv->h_tiles);
+  if (sv->d_export) sv->ctx->arena.release(sv->d_export);
+  if (sv->d_cd) sv->ctx->arena.release(sv->d_cd);
+  delete sv;
+  return IHMC_OK;
+}
+
+extern "C" int ihmc_submit(ihmc_server* sv, const ihmc_lattice* lat, const ihmc_run* run, uint64_t* ticket) {
+  if (!sv || !lat || !run || !ticket) return set_error(IHMC_E_INVAL, "NULL argument");
+  int rc = validate(*lat, *run, 0);
+  if (rc) return rc;
+  Request* r = new (std::nothrow) Request();
+  if (!r) return set_error(IHMC_E_NOMEM, "host allocation failed");
+  r->lat = *lat;
+  r->run = *run;
+  const int64_t N = lattice_sites(*lat);
+  if (lat->h_len > 0) r->h.assign(lat->h, lat->h + lat->h_len);
+  r->lat.h = r->h.empty() ? nullptr : r->h.data();
+  if (run->psi0) r->psi0.assign(run->psi0, run->psi0 + N);
+  if (run->replay_accept && run->n_traj > 0) r->replay.assign(run->replay_accept, run->replay_accept + run->n_traj);
+  r->run.psi0 = nullptr;
+  r->run.replay_accept = r->replay.empty() ? nullptr : r->replay.data();
+  r->need = request_bytes(r->lat, r->run);
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (sv->dead) {
+    delete r;
+    return set_error(IHMC_E_DEVICE, "server stopped after a device error: %s", sv->dead_msg.c_str());
+  }
+  if (sv->stop) {
+    delete r;
+    return set_error(IHMC_E_CANCELLED, "server is shutting down");
+  }
+  if (r->need > sv->budget) {
+    const unsigned long long need = r->need, budget = sv->budget;
+    delete r;
+    return set_error(IHMC_E_NOMEM, "request needs %llu device bytes, the server budget is %llu", need, budget);
+  }
+  if (sv->queue.size() >= (size_t)1 << 20) {
+    delete r;
+    return set_error(IHMC_E_AGAIN, "serving queue full");
+  }
+  r->ticket = sv->next_ticket++;
+  r->t_submit = sv->now();
+  sv->reqs[r->ticket] = r;
+  sv->queue.push_back(r);
+  *ticket = r->ticket;
+  sv->cv_work.notify_one();
+  return IHMC_OK;
+}
+
+extern "C" int ihmc_poll(ihmc_server* sv, uint64_t ticket, int32_t* state) {
+  if (!sv || !state) return set_error(IHMC_E_INVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return set_error(IHMC_E_INVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  *state = it->second->state;
+  return IHMC_OK;
+}
+
+extern "C" int ihmc_wait(ihmc_server* sv, uint64_t ticket, double timeout_s, int32_t* state) {
+  if (!sv || !state) return set_error(IHMC_E_INVAL, "NULL argument");
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return set_error(IHMC_E_INVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  Request* r = it->second;
+  sv->cv_done.wait_for(lk, std::chrono::duration<double>(std::max(0.0, timeout_s)),
+                       [&] { return r->state >= REQ_DONE; });
+  *state = r->state;
+  return IHMC_OK;
+}
+
+extern "C" int ihmc_fetch(ihmc_server* sv, uint64_t ticket, ihmc_result* out, double* times) {
+  if (!sv || !out) return set_error(IHMC_E_INVAL, "NULL argument");
+  Request* r = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end()) return set_error(IHMC_E_INVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    r = it->second;
+    if (r->state < REQ_DONE) return set_error(IHMC_E_AGAIN, "request %llu is not finished", (unsigned long long)ticket);
+    sv->reqs.erase(it);
+  }
+  if (times) {
+    times[0] = r->t_submit;
+    times[1] = r->t_admit;
+    times[2] = r->t_done;
+  }
+  int rc = IHMC_OK;
+  if (r->state == REQ_CANCELLED) rc = set_error(IHMC_E_CANCELLED, "request %llu was cancelled", (unsigned long long)ticket);
+  else if (r->state == REQ_FAILED) rc = set_error(r->err_code ? r->err_code : IHMC_E_DEVICE, "%s", r->error.c_str());
+  const int done = (int)r->rec.size();
+  for (int t = 0; t < done; ++t) {
+    const TrajRecord& q = r->rec[t];
+    if (out->dH) out->dH[t] = q.dH;
+    if (out->H_old) out->H_old[t] = q.H_old;
+    if (out->H_new) out->H_new[t] = q.H_new;
+    if (out->m) out->m[t] = q.m;
+    if (out->abs_m) out->abs_m[t] = q.abs_m;
+    if (out->m2c) out->m2c[t] = q.m2c;
+    if (out->beta_eps) out->beta_eps[t] = q.beta_eps;
+    if (out->accepted) out->accepted[t] = (q.flags & REC_ACCEPT) ? 1 : 0;
+    if (out->flipped) out->flipped[t] = (q.flags & REC_FLIP) ? 1 : 0;
+  }
+  out->n_traj_done = r->st.traj;
+  out->acceptance = r->st.traj ? (double)r->st.n_acc / r->st.traj : 0.0;
+  const int64_t nf = r->st.traj - r->st.n_nonfinite;
+  out->mean_exp_minus_dH = nf > 0 ? r->st.sum_exp_mdh / (double)nf : 0.0;
+  out->n_nonfinite = r->st.n_nonfinite;
+  if (out->psi_final && !r->psi.empty()) std::memcpy(out->psi_final, r->psi.data(), 8 * r->psi.size());
+  delete r;
+  return rc;
+}
+
+extern "C" int ihmc_cancel(ihmc_server* sv, uint64_t ticket) {
+  if (!sv) return set_error(IHMC_E_INVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return set_error(IHMC_E_INVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  Request* r = it->second;
+  auto q = std::find(sv->queue.begin(), sv->queue.end(), r);
+  if (r->state == REQ_QUEUED && q != sv->queue.end()) {
+    sv->queue.erase(q);
+    r->state = REQ_CANCELLED;
+    r->t_done = sv->now();
+    sv->cv_done.notify_all();
+  } else if (r->state <= REQ_RUNNING) {
+    r->cancel = true;  // admitted (or being set up): retired at the next round boundary
+  }
+  return IHMC_OK;
+}
+
+extern "C" int ihmc_server_stats(ihmc_server* sv, double* out) {
+  if (!sv || !out) return set_error(IHMC_E_INVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  out[0] = (double)sv->rounds;
+  out[1] = sv->busy_s;
+  out[2] = sv->site_steps;
+  out[3] = sv->max_seen;
+  out[4] = (double)sv->completed;
+  out[5] = (double)sv->queue.size();
+  out[6] = (double)sv->active.size();
+  out[7] = sv->now();
+  out[8] = (double)sv->used;
+  out[9] = (double)sv->budget;
+  return IHMC_OK;
+}

@@ -30,8 +30,10 @@ EXPORTS = (
     "ihmc_integrate", "ihmc_philox_normals", "ihmc_philox_words", "ihmc_chains_groups",
     "ihmc_chains_time_pass", "ihmc_copy_bandwidth", "ihmc_dense_create", "ihmc_dense_advance",
     "ihmc_dense_result", "ihmc_dense_info", "ihmc_dense_time", "ihmc_dense_destroy", "ihmc_run_dense",
-    "ihmc_dense_force", "ihmc_min_eig",
+    "ihmc_dense_force", "ihmc_min_eig", "ihmc_server_create", "ihmc_server_destroy", "ihmc_submit",
+    "ihmc_poll", "ihmc_wait", "ihmc_fetch", "ihmc_cancel", "ihmc_server_stats",
 )
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED, REQ_FAILED = 0, 1, 2, 3, 4
 
 
 class IhmcError(RuntimeError):
@@ -123,6 +125,14 @@ def load():
                                  C.POINTER(_Result)]
     L.ihmc_dense_force.argtypes = [vp, C.POINTER(_Dense), C.c_int32, _DP, C.c_int32, _DP]
     L.ihmc_min_eig.argtypes = [vp, _DP, C.c_int64, _DP, _DP, C.POINTER(C.c_int32)]
+    L.ihmc_server_create.argtypes = [vp, C.c_uint64, C.c_int32, pp]
+    L.ihmc_server_destroy.argtypes = [vp]
+    L.ihmc_submit.argtypes = [vp, C.POINTER(_Lattice), C.POINTER(_Run), C.POINTER(C.c_uint64)]
+    L.ihmc_poll.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int32)]
+    L.ihmc_wait.argtypes = [vp, C.c_uint64, C.c_double, C.POINTER(C.c_int32)]
+    L.ihmc_fetch.argtypes = [vp, C.c_uint64, C.POINTER(_Result), _DP]
+    L.ihmc_cancel.argtypes = [vp, C.c_uint64]
+    L.ihmc_server_stats.argtypes = [vp, _DP]
     _lib = L
     return L
 
@@ -480,6 +490,70 @@ class DenseChains:
     def close(self):
         if getattr(self, "h", None):
             load().ihmc_dense_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server: submit() queues a lattice request, the
+    library's scheduler thread admits it by HBM budget and advances all
+    resident chains together; fetch() returns the results and timings."""
+
+    STATS = ("rounds", "busy_s", "site_md_steps", "max_resident", "completed", "queued", "resident",
+             "uptime_s", "bytes_held", "budget")
+
+    def __init__(self, ctx: Context, budget_bytes=0, max_active=0):
+        self.ctx = ctx
+        h = C.c_void_p()
+        _check(load().ihmc_server_create(ctx.h, int(budget_bytes), int(max_active), C.byref(h)))
+        self.h = h
+        self._meta = {}
+
+    def submit(self, lat: Lattice, run: Run):
+        keep = []
+        t = C.c_uint64()
+        _check(load().ihmc_submit(self.h, C.byref(lat._c(keep)), C.byref(run._c(keep)), C.byref(t)))
+        self._meta[t.value] = (run.n_traj, lat.N)
+        return t.value
+
+    def poll(self, ticket):
+        st = C.c_int32()
+        _check(load().ihmc_poll(self.h, int(ticket), C.byref(st)))
+        return st.value
+
+    def wait(self, ticket, timeout=60.0):
+        st = C.c_int32()
+        _check(load().ihmc_wait(self.h, int(ticket), float(timeout), C.byref(st)))
+        return st.value
+
+    def fetch(self, ticket, want_psi=True):
+        n_traj, N = self._meta[ticket]
+        r, a = _result_struct(n_traj, N, want_psi)
+        times = np.zeros(3)
+        rc = load().ihmc_fetch(self.h, int(ticket), C.byref(r), _dp(times))
+        if rc == IHMC_OK or rc == -5:
+            self._meta.pop(ticket, None)
+        _check(rc)
+        out = _result_dict(r, a)
+        out.update(t_submit=times[0], t_admit=times[1], t_done=times[2])
+        return out
+
+    def cancel(self, ticket):
+        _check(load().ihmc_cancel(self.h, int(ticket)))
+
+    def stats(self):
+        out = np.zeros(10)
+        _check(load().ihmc_server_stats(self.h, _dp(out)))
+        return dict(zip(self.STATS, out.tolist()))
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().ihmc_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

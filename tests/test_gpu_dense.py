@@ -43,6 +43,9 @@ def test_min_eig_against_eigvalsh(ctx, N):
     th, res, steps = ctx.min_eig(K)
     assert th - res - 1e-12 <= lam <= th + 1e-12, (th, res, lam)
     assert abs(th - lam) < 1e-8, (th, lam, steps)
+    # the residual bound is tight once the Ritz pair has converged
+    assert res < 1e-8 * (abs(lam) + 1), (res, steps)
+    assert steps <= max(N, 1) and (N < 300 or steps < 400), steps
 
 
 def test_min_eig_infinite_range(ctx):
@@ -156,6 +159,7 @@ def test_advance_in_pieces_and_auto_shift(ctx):
     ch = ihmc.DenseChains(ctx, ihmc.Dense(K, beta=0.9), runs)
     info = ch.info()
     assert info["theta"] - info["resid"] <= lam + 1e-12 and abs(info["C"] - (-lam + 0.1)) < 1e-8
+    assert info["resid"] < 1e-8
     ch.advance(1)
     ch.advance(2)
     ch.advance(4)
