@@ -368,9 +368,10 @@ def main():
     for g in range(chains.groups()):
         mid = chains.time_pass(g, mode=1, reps=args.timing_reps)
         first = chains.time_pass(g, mode=0, reps=max(10, args.timing_reps // 5))
+        last = chains.time_pass(g, mode=2, reps=max(10, args.timing_reps // 5))
         n_md = ws[g]["n_md"]  # groups are ordered (precision, ndim): 2D then 3D, one chain each
         kern.append(dict(ndim=mid["ndim"], sites=mid["sites"], middle_us=mid["us"], first_us=first["us"],
-                         middle_share_us=(n_md - 1) * mid["us"]))
+                         last_us=last["us"], middle_share_us=(n_md - 1) * mid["us"]))
     dom = max(kern, key=lambda k: k["middle_share_us"])
     bytes_per_launch = BYTES_MIDDLE_F32 * dom["sites"]
     achieved = bytes_per_launch / (dom["middle_us"] * 1e-6) / 1e9
@@ -378,6 +379,7 @@ def main():
         k["middle_GBs"] = round(BYTES_MIDDLE_F32 * k["sites"] / (k["middle_us"] * 1e-6) / 1e9, 1)
         k["middle_us"] = round(k["middle_us"], 3)
         k["first_us"] = round(k["first_us"], 3)
+        k["last_us"] = round(k["last_us"], 3)
         del k["middle_share_us"]
 
     copy_bytes = 512 << 20

@@ -301,12 +301,13 @@ int ihmc_philox_words(ihmc_ctx* ctx, int64_t n, const uint32_t* ctr, const uint3
 /* Number of launch groups of a chain set (chains of equal precision and
  * dimension share launches; groups are ordered by (precision, ndim)). */
 int ihmc_chains_groups(ihmc_chains* chains, int32_t* n_groups);
-/* Time the fused pass kind `mode` (0 = first, 1 = middle) of launch group
- * `group`: one warm-up launch, then `reps` launches bracketed by HIP events
- * on the context stream.  Returns the mean duration per launch in
+/* Time the fused pass kind `mode` (0 = first, 1 = middle, 2 = last) of launch
+ * group `group`: one warm-up launch, then `reps` launches bracketed by HIP
+ * events on the context stream.  Returns the mean duration per launch in
  * microseconds and the lattice sites one launch covers.  The repeated passes
- * overwrite the chains' momenta and field buffers: call it only when the
- * chains' results have been fetched or are no longer needed. */
+ * overwrite the chains' momenta and field buffers (and a last pass closes a
+ * trajectory of every chain in the group): call it only when the chains'
+ * results have been fetched or are no longer needed. */
 int ihmc_chains_time_pass(ihmc_chains* chains, int32_t group, int32_t mode, int32_t reps, double* avg_us,
                           int64_t* sites, int32_t* ndim, int32_t* precision);
 

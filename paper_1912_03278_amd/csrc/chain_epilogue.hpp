@@ -1,6 +1,6 @@
-// Trajectory epilogue shared by the lattice kernels: block reduction of the
-// exact fixed-point sums, accumulation into the chain, and the work of the
-// block that finishes last -- the Metropolis test of Sec. 3 on
+// Trajectory epilogue shared by the lattice and dense kernels: block reduction
+// of the exact fixed-point sums, their store into per-tile entries, and the
+// work of the block that finishes last -- the Metropolis test of Sec. 3 on
 // dH = H_new - H_old in FP64 (exact integer difference of the fixed-point
 // Hamiltonians), the optional global sign flip, and the Sec. 4 estimators.
 #pragma once
@@ -93,74 +93,145 @@ __device__ __forceinline__ void finalize_measure(ChainState* st, const u128* sum
   __hip_atomic_store(&st->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Last-block epilogue shared by every kernel that closes a trajectory or a
-// measurement: gather the NTERM x NSLOT accumulators with one load per thread,
-// clear them for the next trajectory, and let thread 0 finish.
-template <bool kTraj>
-__device__ __forceinline__ void close_chain(const ChainDev& cd, ChainState* st, int last_buf) {
-  __shared__ u128 sAcc[NTERM][NSLOT];
-  __shared__ uint32_t sBad;
-  for (int k = threadIdx.x; k < NTERM * NSLOT; k += blockDim.x) {
-    const int a = k / NSLOT, sl = k % NSLOT;
-    sAcc[a][sl] = load_limbs_agent(st->acc[a][sl]);
-  }
-  if (threadIdx.x == 0) sBad = __hip_atomic_load(&st->bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  for (int k = threadIdx.x; k < NTERM * NSLOT; k += blockDim.x) {
-    const int a = k / NSLOT, sl = k % NSLOT;
-    clear_limbs_agent(st->acc[a][sl]);
-  }
-  if (threadIdx.x == 0) {
-    u128 sum[NTERM];
-#pragma unroll
-    for (int a = 0; a < NTERM; ++a) {
-      sum[a] = u128{0ull, 0ull};
-#pragma unroll 1
-      for (int sl = 0; sl < NSLOT; ++sl) sum[a] = add128(sum[a], sAcc[a][sl]);
-    }
-    if (kTraj) finalize_trajectory(cd, st, last_buf, sum, sBad);
-    else finalize_measure(st, sum, sBad);
-  }
+// ------------------------------------------------------- partial sums ---
+//
+// Every block of a pass that contributes FP64 terms stores its exact
+// fixed-point block sums in its own entries of the chain's partial table
+// (part[tile][NPART] of 128-bit values; the last entry holds non-finite flags
+// as 32-bit words: 0 the momenta of the first pass, 1 the final momenta, 2 the
+// action terms).  Stores and loads of the table are agent-scope (coherent across
+// the XCDs' L2 caches); a full wait for outstanding memory operations precedes
+// every counter increment, so a closer that sees the final count also sees every
+// entry counted.  Tiles are counted in groups of PGROUP: the block that completes
+// a group sums the group's entries (integer sums: exact, in any order), and the
+// block that completes the last group closes the chain.  No two blocks ever add
+// into the same memory, so large chains do not serialise on a few cache lines.
+
+__device__ __forceinline__ uint64_t* part_entry(uint64_t* base, int64_t idx, int a) {
+  return base + (idx * NPART + a) * 2;
+}
+__device__ __forceinline__ void store_u128_agent(uint64_t* p, u128 v) {
+  __hip_atomic_store(&p[0], v.lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&p[1], v.hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ u128 load_u128_agent(const uint64_t* p) {
+  return u128{__hip_atomic_load(&p[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+              __hip_atomic_load(&p[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
+}
+__device__ __forceinline__ void store_flag_agent(uint64_t* entry, int word, uint32_t v) {
+  __hip_atomic_store((uint32_t*)entry + word, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t load_flag_agent(const uint64_t* entry, int word) {
+  return __hip_atomic_load((const uint32_t*)entry + word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Count one finished unit at `counter`; true for the unit that completes `n`.
+__device__ __forceinline__ bool count_done(uint32_t* counter, uint32_t n) {
+  __builtin_amdgcn_s_waitcnt(0);  // the entries stored above have completed
+  const uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return prev == n - 1u;
 }
 
-// Block reduction of the per-thread fixed-point sums, order-independent
-// accumulation into the chain, and the last block's epilogue.  NW = waves per
-// block; `slot` spreads blocks over the NSLOT atomic slots of every term.
-template <int MODE, int NW>
-__device__ __forceinline__ void block_accumulate(const ChainDev& cd, ChainState* st, const u128* acc,
-                                                 uint32_t bad, int cur, int j, int slot) {
-  __shared__ u128 sRed[NW][NTERM];
+// Sums over `count` consecutive entries of terms [a_lo, a_hi] and the OR of
+// the flag words in `wmask`: one wave per term, lanes striding over entries.
+// Results in sum[] / *flags (LDS) for thread 0 after the closing barrier.
+template <int NW>
+__device__ __forceinline__ void gather_entries(const uint64_t* base, int count, int a_lo, int a_hi, uint32_t wmask,
+                                               u128* sum, uint32_t* flags) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  constexpr int t_lo = (MODE == PASS_FIRST) ? T_K0 : ((MODE == PASS_MEASURE) ? T_S : T_K1);
-  constexpr int t_hi = (MODE == PASS_FIRST) ? T_K0 : T_UT;
-#pragma unroll
-  for (int a = t_lo; a <= t_hi; ++a) {
-    const u128 v = wave_sum128(acc[a]);
-    if (lane == 0) sRed[wave][a] = v;
+  for (int a = a_lo + wave; a <= a_hi; a += NW) {
+    u128 v{0ull, 0ull};
+    for (int i = lane; i < count; i += 64) v = add128(v, load_u128_agent(part_entry((uint64_t*)base, i, a)));
+    v = wave_sum128(v);
+    if (lane == 0) sum[a] = v;
   }
-  // non-finite flags: any lane of any wave
-  __shared__ uint32_t sBadW[NW];
+  if (wave == NW - 1) {
+    uint32_t f = 0u;
+    for (int i = lane; i < count; i += 64) {
+      const uint64_t* e = part_entry((uint64_t*)base, i, NTERM);
+#pragma unroll
+      for (int w = 0; w < 3; ++w)
+        if (wmask & (1u << w)) f |= load_flag_agent(e, w);
+    }
+    const unsigned long long any = __ballot(f != 0u);
+    if (lane == 0) *flags = any ? 1u : 0u;
+  }
+  __syncthreads();
+}
+
+// Flag words a pass stores, by kind of contribution.
+enum : int { CONTRIB_FIRST = 0, CONTRIB_FINAL_KIN = 1, CONTRIB_ACTION = 2, CONTRIB_LAST = 3 };
+
+// Block reduction of the per-thread fixed-point sums of terms [a_lo, a_hi] and
+// their store into the chain's entries of tile `tix`; flag words per `kind`.
+template <int NW>
+__device__ __forceinline__ void block_store_terms(const ChainDev& cd, const u128* acc, uint32_t bad, int a_lo,
+                                                  int a_hi, int kind, int tix) {
+  __shared__ u128 sRedA[NW][NTERM];
+  __shared__ uint32_t sBadA[NW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < NTERM; ++a) {
+    if (a < a_lo || a > a_hi) continue;
+    const u128 v = wave_sum128(acc[a]);
+    if (lane == 0) sRedA[wave][a] = v;
+  }
   const unsigned long long any_bad = __ballot(bad != 0u);
-  if (lane == 0) sBadW[wave] = any_bad ? 1u : 0u;
-  __shared__ int sLast;
+  if (lane == 0) sBadA[wave] = any_bad ? 1u : 0u;
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int a = t_lo; a <= t_hi; ++a) {
-      u128 v = sRed[0][a];
-      for (int w = 1; w < NW; ++w) v = add128(v, sRed[w][a]);
-      atomic_add_limbs(st->acc[a][slot], v);
+    uint64_t* base = cd.part;
+    for (int a = a_lo; a <= a_hi; ++a) {
+      u128 v = sRedA[0][a];
+      for (int w = 1; w < NW; ++w) v = add128(v, sRedA[w][a]);
+      store_u128_agent(part_entry(base, tix, a), v);
     }
     uint32_t anyb = 0u;
-    for (int w = 0; w < NW; ++w) anyb |= sBadW[w];
-    if (anyb) (void)__hip_atomic_fetch_or(&st->bad, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (MODE != PASS_FIRST) sLast = publish_done(&st->done, cd.n_tiles) ? 1 : 0;
+    for (int w = 0; w < NW; ++w) anyb |= sBadA[w];
+    uint64_t* fe = part_entry(base, tix, NTERM);
+    if (kind == CONTRIB_FIRST) store_flag_agent(fe, 0, anyb);
+    if (kind == CONTRIB_FINAL_KIN || kind == CONTRIB_LAST) store_flag_agent(fe, 1, anyb);
+    if (kind == CONTRIB_ACTION || kind == CONTRIB_LAST) store_flag_agent(fe, 2, anyb);
   }
-  if (MODE == PASS_FIRST) return;
-  __syncthreads();
-  if (!sLast) return;
-  close_chain<MODE == PASS_LAST>(cd, st, pass_in_buf(cur, j));
 }
 
+// After block_store_terms of a closing pass (LAST or MEASURE): count the tile,
+// and in the block completing its group / the chain, sum the entries and run
+// the Metropolis step (kTraj) or the measurement of the accepted field.
+template <bool kTraj, int NW>
+__device__ __forceinline__ void block_close(const ChainDev& cd, ChainState* st, int last_buf, int tix) {
+  __shared__ u128 sSum[NTERM];
+  __shared__ uint32_t sFlag, sLast;
+  const int a_lo = kTraj ? T_K0 : T_S;
+  const uint32_t wmask = kTraj ? 7u : 4u;
+  const int g = tix / PGROUP;
+  const int ng = (int)((cd.n_tiles + PGROUP - 1) / PGROUP);
+  const int gs = min(PGROUP, (int)cd.n_tiles - g * PGROUP);
+  if (threadIdx.x == 0) sLast = count_done(&cd.gcnt[g], (uint32_t)gs) ? 1u : 0u;
+  __syncthreads();
+  if (!sLast) return;
+  // this block completed group g
+  gather_entries<NW>(cd.part + (int64_t)g * PGROUP * NPART * 2, gs, a_lo, T_UT, wmask, sSum, &sFlag);
+  if (ng > 1) {
+    if (threadIdx.x == 0) {
+      __hip_atomic_store(&cd.gcnt[g], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int a = a_lo; a <= T_UT; ++a) store_u128_agent(part_entry(cd.gsum, g, a), sSum[a]);
+      store_flag_agent(part_entry(cd.gsum, g, NTERM), 0, sFlag);
+      sLast = count_done(&st->done, (uint32_t)ng) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!sLast) return;
+    // this block completed the chain: sum the group sums (flags in word 0)
+    gather_entries<NW>(cd.gsum, ng, a_lo, T_UT, 1u, sSum, &sFlag);
+  }
+  if (threadIdx.x == 0) {
+    if (ng == 1) __hip_atomic_store(&cd.gcnt[g], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    u128 sum[NTERM];
+#pragma unroll
+    for (int a = 0; a < NTERM; ++a) sum[a] = (a >= a_lo) ? sSum[a] : u128{0ull, 0ull};
+    if (kTraj) finalize_trajectory(cd, st, last_buf, sum, sFlag);
+    else finalize_measure(st, sum, sFlag);
+  }
+}
 
 // Terms of four x-aligned sites held by four consecutive lanes, summed as
 // (t0 + t1) + (t2 + t3) in FP64 (FP addition is commutative, so every lane of
@@ -171,32 +242,18 @@ __device__ __forceinline__ double quad_sum_lanes(double t) {
   return ((threadIdx.x & 3) == 0) ? t : 0.0;
 }
 
-// Block reduction of the terms [a_lo, a_hi] and their accumulation into the
-// chain, without counting the block as finished (used where another kernel
-// closes the trajectory).
-template <int NW>
-__device__ __forceinline__ void block_add_terms(ChainState* st, const u128* acc, uint32_t bad, int a_lo, int a_hi,
-                                                int slot) {
-  __shared__ u128 sRedA[NW][NTERM];
-  __shared__ uint32_t sBadA[NW];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int a = a_lo; a <= a_hi; ++a) {
-    const u128 v = wave_sum128(acc[a]);
-    if (lane == 0) sRedA[wave][a] = v;
-  }
-  const unsigned long long any_bad = __ballot(bad != 0u);
-  if (lane == 0) sBadA[wave] = any_bad ? 1u : 0u;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int a = a_lo; a <= a_hi; ++a) {
-      u128 v = sRedA[0][a];
-      for (int w = 1; w < NW; ++w) v = add128(v, sRedA[w][a]);
-      atomic_add_limbs(st->acc[a][slot], v);
-    }
-    uint32_t anyb = 0u;
-    for (int w = 0; w < NW; ++w) anyb |= sBadA[w];
-    if (anyb) (void)__hip_atomic_fetch_or(&st->bad, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+// Epilogue of a lattice pass: store the block's terms (FIRST: kinetic energy of
+// the fresh momenta; LAST: final kinetic energy and the action terms; MEASURE:
+// the action terms) and close the chain where this block completes it.
+template <int MODE, int NW>
+__device__ __forceinline__ void block_accumulate(const ChainDev& cd, ChainState* st, const u128* acc, uint32_t bad,
+                                                 int cur, int j, int tix) {
+  constexpr int t_lo = (MODE == PASS_FIRST) ? T_K0 : ((MODE == PASS_MEASURE) ? T_S : T_K1);
+  constexpr int t_hi = (MODE == PASS_FIRST) ? T_K0 : T_UT;
+  constexpr int kind = (MODE == PASS_FIRST) ? CONTRIB_FIRST : ((MODE == PASS_MEASURE) ? CONTRIB_ACTION : CONTRIB_LAST);
+  block_store_terms<NW>(cd, acc, bad, t_lo, t_hi, kind, tix);
+  if (MODE == PASS_FIRST) return;
+  block_close<MODE == PASS_LAST, NW>(cd, st, pass_in_buf(cur, j), tix);
 }
 
 }  // namespace ihmc

@@ -583,9 +583,9 @@ __global__ __launch_bounds__(256) void k_dense_epi_f(const ChainDev* __restrict_
     u128 acc[NTERM];
 #pragma unroll
     for (int a = 0; a < NTERM; ++a) acc[a] = u128{0ull, 0ull};
-    acc[MODE == PASS_FIRST ? T_K0 : T_K1] = to_fixed(quad_sum_lanes(kin), bad);
-    block_add_terms<4>(st, acc, bad, MODE == PASS_FIRST ? T_K0 : T_K1, MODE == PASS_FIRST ? T_K0 : T_K1,
-                       blockIdx.x % NSLOT);
+    constexpr int a = (MODE == PASS_FIRST) ? T_K0 : T_K1;
+    acc[a] = to_fixed(quad_sum_lanes(kin), bad);
+    block_store_terms<4>(cd, acc, bad, a, a, MODE == PASS_FIRST ? CONTRIB_FIRST : CONTRIB_FINAL_KIN, blockIdx.x);
   }
 }
 
@@ -625,7 +625,9 @@ __global__ __launch_bounds__(256) void k_dense_h(const ChainDev* __restrict__ ch
   for (int a = 0; a < NTERM; ++a) acc[a] = u128{0ull, 0ull};
 #pragma unroll
   for (int a = 0; a < 4; ++a) acc[T_S + a] = to_fixed(quad_sum_lanes(h[a]), bad);
-  block_accumulate<MODE, 4>(cd, st, acc, bad, cur, j, blockIdx.x % NSLOT);
+  // the final kinetic energy was stored by the last force epilogue
+  block_store_terms<4>(cd, acc, bad, T_S, T_UT, CONTRIB_ACTION, blockIdx.x);
+  block_close<MODE == PASS_LAST, 4>(cd, st, MODE == PASS_LAST ? pass_in_buf(cur, j) : cur, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ launch ---

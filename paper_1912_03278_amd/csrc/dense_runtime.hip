@@ -357,9 +357,11 @@ int DenseChains::build(const ihmc_dense& md, int32_t n, const ihmc_run* runs, in
     c.p = dalloc(4 * (uint64_t)Np);
     c.rec = (TrajRecord*)dalloc(sizeof(TrajRecord) * (uint64_t)std::max(1, r.n_traj));
     c.st = (ChainState*)dalloc(sizeof(ChainState));
+    void* pblk = dalloc(partials_bytes(c.n_tiles));
     c.b = bfield;
     c.hp = hp;
-    if (!c.psi || !c.p || !c.rec || !c.st) return nomem("chain state");
+    if (!c.psi || !c.p || !c.rec || !c.st || !pblk) return nomem("chain state");
+    HIPCHK(setup_partials(c, pblk, s), "partials");
     HIPCHK(hipMemsetAsync(c.psi, 0, 4 * 3 * (size_t)Np, s), "clear psi");
     HIPCHK(hipMemsetAsync(c.p, 0, 4 * (size_t)Np, s), "clear p");
     if (r.replay_accept && r.n_traj > 0) {

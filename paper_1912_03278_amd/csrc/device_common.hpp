@@ -155,51 +155,6 @@ __device__ __forceinline__ u128 wave_sum128(u128 v) {
   return v;
 }
 
-// Order-independent accumulation of 128-bit values with plain 64-bit atomic
-// adds: a value is split into three limbs of 42 bits, V = l0 + l1 2^42 + l2 2^84
-// with l0, l1 in [0, 2^42) and l2 = V >> 84 (arithmetic).  Each limb goes to its
-// own 64-bit word, so no carry has to travel between words while blocks add
-// (a word absorbs 2^22 additions), every add is fire-and-forget, and the words
-// are recombined exactly when the sum is read.
-__device__ __forceinline__ void atomic_add_limbs(uint64_t* slot, u128 v) {
-  const uint64_t m42 = (1ull << 42) - 1ull;
-  const uint64_t l0 = v.lo & m42;
-  const uint64_t l1 = ((v.lo >> 42) | (v.hi << 22)) & m42;
-  const uint64_t l2 = (uint64_t)((int64_t)v.hi >> 20);
-  __hip_atomic_fetch_add(&slot[0], l0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_fetch_add(&slot[1], l1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_fetch_add(&slot[2], l2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ u128 load_limbs_agent(const uint64_t* slot) {
-  const uint64_t l0 = __hip_atomic_load(&slot[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const uint64_t l1 = __hip_atomic_load(&slot[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const uint64_t l2 = __hip_atomic_load(&slot[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  // V = l0 + l1 2^42 + l2 2^84 (l0, l1 non-negative sums, l2 a signed sum)
-  u128 r{l0, 0ull};
-  r = add128(r, u128{l1 << 42, l1 >> 22});
-  r = add128(r, u128{0ull, l2 << 20});
-  return r;
-}
-
-__device__ __forceinline__ void clear_limbs_agent(uint64_t* slot) {
-  __hip_atomic_store(&slot[0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(&slot[1], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(&slot[2], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Count one finished block of a chain and tell whether it was the last one.
-// The accumulators are only ever touched by device-scope atomics, so ordering
-// needs no cache write-back: the caller's atomics are made to complete
-// (workgroup-scope release = wait for this wave's outstanding memory
-// operations) before the counter increments.
-__device__ __forceinline__ bool publish_done(uint32_t* done, uint32_t n_blocks) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  const uint32_t prev = __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return prev == n_blocks - 1u;
-}
-
-
 // ------------------------------------------------------------- functions ---
 
 // tanh in FP32: tanh|x| = 1 - 2 / (1 + e^{2|x|}) with the hardware base-2

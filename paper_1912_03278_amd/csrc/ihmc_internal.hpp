@@ -22,7 +22,8 @@ enum Term : int {
   T_UT = 5,    // u tanh(sqrt(J') u), u = Kt psi
   NTERM = 6
 };
-constexpr int NSLOT = 16;  // atomic slots per term, spread over blocks
+constexpr int NPART = NTERM + 1;  // entries per tile of the partial-sum table (terms + flag words)
+constexpr int PGROUP = 64;        // tiles per group of the two-level close
 
 // Record written after every trajectory (64 bytes).
 struct TrajRecord {
@@ -34,14 +35,13 @@ enum : uint32_t { REC_ACCEPT = 1u, REC_FLIP = 2u, REC_NONFINITE = 4u };
 
 // Mutable per-chain state, updated on the device by the finalising block.
 struct ChainState {
-  uint64_t acc[NTERM][NSLOT][3];  // fixed-point accumulators (42-bit limbs) of the running trajectory
   uint64_t S_lo, S_hi;            // S(psi_cur), fixed point
   double sum_psi, sum_psih, sum_ut;  // estimator sums of psi_cur
   int32_t cur;    // buffer (0..2) holding the accepted field
   int32_t sign;   // +1, or -1 after an accepted global sign flip
   int32_t traj;   // next trajectory index
-  uint32_t done;  // finished blocks of the current pass
-  uint32_t bad;   // a non-finite / out-of-range term was seen
+  uint32_t done;  // finished tile groups of the closing pass
+  uint32_t bad;   // unused (kept for layout stability of the record fields)
   int32_t cur_bad;  // the accepted field itself has such a term (e.g. a NaN start)
   int64_t n_acc, n_nonfinite;
   double sum_exp_mdh;
@@ -72,7 +72,17 @@ struct ChainDev {
   TrajRecord* rec;       // cap records
   const uint8_t* replay; // forced decisions (test hook) or null
   ChainState* st;
+  uint64_t* part;   // n_tiles x NPART fixed-point entries (block sums of the current trajectory)
+  uint64_t* gsum;   // ceil(n_tiles / PGROUP) x NPART group sums
+  uint32_t* gcnt;   // ceil(n_tiles / PGROUP) tile counters, zero between passes
 };
+
+// Bytes of a chain's partial-sum table, group sums and group counters.
+inline __host__ __device__ uint64_t partials_bytes(uint32_t n_tiles) {
+  const uint64_t ng = (n_tiles + PGROUP - 1) / PGROUP;
+  return ((uint64_t)n_tiles * NPART * 16 + 255) / 256 * 256 + (ng * NPART * 16 + 255) / 256 * 256 +
+         (ng * 4 + 255) / 256 * 256;
+}
 
 // Stored index of logical site i = x + L0 (y + L1 z).
 inline __host__ __device__ int64_t stored_index(const ChainDev& cd, int64_t i) {

@@ -102,6 +102,23 @@ __device__ __forceinline__ double quad_sum(double t0, double t1, double t2, doub
   return (t0 + t1) + (t2 + t3);
 }
 
+// Workgroups are dealt to the eight XCDs round-robin (block b runs on XCD b % 8),
+// each XCD with its own L2.  Neighbouring tiles read the same halo cache lines,
+// so each XCD takes a contiguous range of the tile table: block b works on tile
+// xcd_tile(b, n), a bijection of [0, n).
+#ifndef IHMC_XCD_REMAP
+#define IHMC_XCD_REMAP 1
+#endif
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+#if IHMC_XCD_REMAP
+  const int q = n >> 3, r = n & 7, k = b & 7, m = b >> 3;
+  return k * q + (k < r ? k : r) + m;
+#else
+  (void)n;
+  return b;
+#endif
+}
+
 // --------------------------------------------------------------------- 2D ---
 //
 // Tile BX x BY, one thread per quad of four consecutive x (NT = BX/4 * BY).
@@ -111,7 +128,7 @@ __device__ __forceinline__ double quad_sum(double t0, double t1, double t2, doub
 // before the LDS phases so their latency overlaps the stencil work.
 template <typename T, int BX, int BY, int MODE>
 __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __restrict__ chains,
-                                                              const Tile* __restrict__ tiles, int j) {
+                                                              const Tile* __restrict__ tiles, int n_tiles, int j) {
   constexpr int QX = BX / 4;
   constexpr int NT = QX * BY;
   constexpr int NWAVE = (NT + 63) / 64;
@@ -126,7 +143,7 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
   __shared__ __align__(16) T sP[PR * RP];
   __shared__ __align__(16) T sW[kHasW ? WR * RP : 4];
 
-  const Tile tl = tiles[blockIdx.x];
+  const Tile tl = tiles[xcd_tile(blockIdx.x, n_tiles)];
   const ChainDev& cd = chains[tl.chain];
   ChainState* st = cd.st;
   const int L0 = cd.L0, L1 = cd.L1, pitch = cd.pitch;
@@ -291,7 +308,8 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
   }
 
   if (MODE == PASS_MIDDLE || MODE == PASS_FORCE) return;
-  block_accumulate<MODE, NWAVE>(cd, st, acc, bad, cur, j, blockIdx.x % NSLOT);
+  const int tix = (tl.y0 / BY) * ((L0 + BX - 1) / BX) + tl.x0 / BX;  // tile index within the chain
+  block_accumulate<MODE, NWAVE>(cd, st, acc, bad, cur, j, tix);
 }
 
 // --------------------------------------------------------------------- 3D ---
@@ -303,7 +321,7 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
 // w(z+1) and the update of plane z while the loads of plane z+3 are in flight.
 template <typename T, int BX, int BY, int ZR, int MODE>
 __global__ __launch_bounds__(256) void lattice_pass3s(const ChainDev* __restrict__ chains,
-                                                      const Tile* __restrict__ tiles, int j) {
+                                                      const Tile* __restrict__ tiles, int n_tiles, int j) {
   constexpr int PX = BX + 4, PY = BY + 4, PP = PX * PY;
   constexpr int WX = BX + 2, WY = BY + 2, WP = WX * WY;
   constexpr int NO = BX * BY;
@@ -312,7 +330,7 @@ __global__ __launch_bounds__(256) void lattice_pass3s(const ChainDev* __restrict
   __shared__ T sP[5][PP];
   __shared__ T sW[kHasW ? 3 : 1][kHasW ? WP : 1];
 
-  const Tile tl = tiles[blockIdx.x];
+  const Tile tl = tiles[xcd_tile(blockIdx.x, n_tiles)];
   const ChainDev& cd = chains[tl.chain];
   ChainState* st = cd.st;
   const int L0 = cd.L0, L1 = cd.L1, L2 = cd.L2, pitch = cd.pitch;
@@ -486,7 +504,8 @@ __global__ __launch_bounds__(256) void lattice_pass3s(const ChainDev* __restrict
   }
 
   if (MODE == PASS_MIDDLE || MODE == PASS_FORCE) return;
-  block_accumulate<MODE, 4>(cd, st, acc, bad, cur, j, blockIdx.x % NSLOT);
+  const int tix = ((tl.z0 / ZR) * ((L1 + BY - 1) / BY) + tl.y0 / BY) * ((L0 + BX - 1) / BX) + tl.x0 / BX;
+  block_accumulate<MODE, 4>(cd, st, acc, bad, cur, j, tix);
 }
 
 // ------------------------------------------------------------------ launch ---
@@ -498,19 +517,19 @@ static hipError_t launch_mode2v(int mode, const ChainDev* chains, const Tile* ti
   dim3 grid(n_tiles), block(BX / 4 * BY);
   switch (mode) {
     case PASS_FIRST:
-      lattice_pass2v<T, BX, BY, PASS_FIRST><<<grid, block, 0, s>>>(chains, tiles, j);
+      lattice_pass2v<T, BX, BY, PASS_FIRST><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
       break;
     case PASS_MIDDLE:
-      lattice_pass2v<T, BX, BY, PASS_MIDDLE><<<grid, block, 0, s>>>(chains, tiles, j);
+      lattice_pass2v<T, BX, BY, PASS_MIDDLE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
       break;
     case PASS_LAST:
-      lattice_pass2v<T, BX, BY, PASS_LAST><<<grid, block, 0, s>>>(chains, tiles, j);
+      lattice_pass2v<T, BX, BY, PASS_LAST><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
       break;
     case PASS_MEASURE:
-      lattice_pass2v<T, BX, BY, PASS_MEASURE><<<grid, block, 0, s>>>(chains, tiles, j);
+      lattice_pass2v<T, BX, BY, PASS_MEASURE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
       break;
     case PASS_FORCE:
-      lattice_pass2v<T, BX, BY, PASS_FORCE><<<grid, block, 0, s>>>(chains, tiles, j);
+      lattice_pass2v<T, BX, BY, PASS_FORCE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
       break;
     default:
       return hipErrorInvalidValue;
@@ -525,19 +544,19 @@ static hipError_t launch_mode3s(int mode, const ChainDev* chains, const Tile* ti
   dim3 grid(n_tiles), block(256);
   switch (mode) {
     case PASS_FIRST:
-      lattice_pass3s<T, BX, BY, ZR, PASS_FIRST><<<grid, block, 0, s>>>(chains, tiles, j);
+      lattice_pass3s<T, BX, BY, ZR, PASS_FIRST><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
       break;
     case PASS_MIDDLE:
-      lattice_pass3s<T, BX, BY, ZR, PASS_MIDDLE><<<grid, block, 0, s>>>(chains, tiles, j);
+      lattice_pass3s<T, BX, BY, ZR, PASS_MIDDLE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
       break;
     case PASS_LAST:
-      lattice_pass3s<T, BX, BY, ZR, PASS_LAST><<<grid, block, 0, s>>>(chains, tiles, j);
+      lattice_pass3s<T, BX, BY, ZR, PASS_LAST><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
       break;
     case PASS_MEASURE:
-      lattice_pass3s<T, BX, BY, ZR, PASS_MEASURE><<<grid, block, 0, s>>>(chains, tiles, j);
+      lattice_pass3s<T, BX, BY, ZR, PASS_MEASURE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
       break;
     case PASS_FORCE:
-      lattice_pass3s<T, BX, BY, ZR, PASS_FORCE><<<grid, block, 0, s>>>(chains, tiles, j);
+      lattice_pass3s<T, BX, BY, ZR, PASS_FORCE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
       break;
     default:
       return hipErrorInvalidValue;

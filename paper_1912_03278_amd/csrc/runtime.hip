@@ -479,7 +479,9 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
     c.p = dalloc(NP * pb);
     c.rec = (TrajRecord*)dalloc(sizeof(TrajRecord) * (uint64_t)std::max(1, r.n_traj));
     c.st = (ChainState*)dalloc(sizeof(ChainState));
-    if (!c.psi || !c.p || !c.rec || !c.st) {
+    void* pblk = dalloc(partials_bytes(c.n_tiles));
+    if (pblk) HIPCHK(setup_partials(c, pblk, s), "partials");
+    if (!c.psi || !c.p || !c.rec || !c.st || !pblk) {
       cleanup();
       return set_error(IHMC_E_NOMEM, "chain %d: device arena exhausted (%llu of %llu bytes in use)", i,
                        (unsigned long long)ctx->arena.used, (unsigned long long)ctx->arena.size);
@@ -983,7 +985,8 @@ extern "C" int ihmc_chains_time_pass(ihmc_chains* ch, int32_t group, int32_t mod
   ihmc_ctx* ctx = c->ctx;
   CTX_OK(ctx);
   if (group < 0 || group >= (int32_t)c->groups.size()) return set_error(IHMC_E_INVAL, "group out of range");
-  if (mode != PASS_FIRST && mode != PASS_MIDDLE) return set_error(IHMC_E_INVAL, "only FIRST and MIDDLE passes can be timed");
+  if (mode != PASS_FIRST && mode != PASS_MIDDLE && mode != PASS_LAST)
+    return set_error(IHMC_E_INVAL, "only FIRST, MIDDLE and LAST passes can be timed");
   if (reps < 1) return set_error(IHMC_E_INVAL, "reps must be >= 1");
   const Group& g = c->groups[group];
   for (int ci : g.order)
@@ -1084,6 +1087,16 @@ hipError_t launch_measure(const std::vector<Group>& groups, const Tile* d_tiles,
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+hipError_t setup_partials(ChainDev& c, void* block, hipStream_t s) {
+  char* b = (char*)block;
+  const uint64_t ng = (c.n_tiles + PGROUP - 1) / PGROUP;
+  c.part = (uint64_t*)b;
+  b += ((uint64_t)c.n_tiles * NPART * 16 + 255) / 256 * 256;
+  c.gsum = (uint64_t*)b;
+  b += (ng * NPART * 16 + 255) / 256 * 256;
+  c.gcnt = (uint32_t*)b;
+  return hipMemsetAsync(c.gcnt, 0, 4 * ng, s);
 }
 hipError_t launch_zero_state(ChainState* st, hipStream_t s) {
   k_zero_state<<<1, 256, 0, s>>>(st);

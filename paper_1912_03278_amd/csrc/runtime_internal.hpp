@@ -18,6 +18,9 @@ int hip_fail(ihmc_ctx* ctx, hipError_t e, const char* where);
 // Set-up launchers shared by the lattice and dense runtimes (runtime.hip).
 hipError_t launch_init_psi(const ChainDev* d_cd, int ci, const double* psi0, int64_t N, int precision, hipStream_t s);
 hipError_t launch_zero_state(ChainState* st, hipStream_t s);
+// Point c.part / c.gsum / c.gcnt into `block` (partials_bytes(c.n_tiles) bytes)
+// and clear the group counters.
+hipError_t setup_partials(ChainDev& c, void* block, hipStream_t s);
 hipError_t launch_export_psi(const ChainDev* d_cd, int ci, double* out, int64_t N, int precision, hipStream_t s);
 hipError_t launch_export_field(const ChainDev* d_cd, int ci, double* out, const void* src, int64_t N, int precision,
                                hipStream_t s);

@@ -69,7 +69,9 @@ static uint64_t request_bytes(const ihmc_lattice& l, const ihmc_run& r) {
                r256(sizeof(ChainState)) + r256(8 * (uint64_t)N);
   if (r.replay_accept) b += r256((uint64_t)r.n_traj);
   if (l.h_len == N && N > 1) b += r256(8 * NP) + r256(NP * pb) + r256(8 * 4 * (uint64_t)N) + r256(8 * (uint64_t)N);
-  b += r256(sizeof(Tile) * ((uint64_t)N / 64 + 16));
+  ChainDev c;
+  describe_chain(l, r, 0, c);
+  b += r256(sizeof(Tile) * (uint64_t)c.n_tiles) + partials_bytes(c.n_tiles);
   return b;
 }
 
@@ -240,7 +242,9 @@ bool ihmc_server::admit_setup(std::vector<Request*>& fresh) {
     c.p = dal(c.NP * pb);
     c.rec = (TrajRecord*)dal(sizeof(TrajRecord) * (uint64_t)std::max(1, r->run.n_traj));
     c.st = (ChainState*)dal(sizeof(ChainState));
-    bool good = c.psi && c.p && c.rec && c.st;
+    void* pblk = dal(partials_bytes(c.n_tiles));
+    bool good = c.psi && c.p && c.rec && c.st && pblk;
+    if (good) e = setup_partials(c, pblk, s);
     if (good && !r->replay.empty()) {
       uint8_t* d = (uint8_t*)dal(r->replay.size());
       good = d != nullptr;
