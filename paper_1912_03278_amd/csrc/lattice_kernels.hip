@@ -409,10 +409,14 @@ __global__ __launch_bounds__(256) void lattice_pass3s(const ChainDev* __restrict
     }
   };
 
+  // FP64 sums of the thread's column over the tile's planes (in z order); the
+  // column sums of four x-aligned columns form a quad that is converted to
+  // fixed point once, after the plane loop.  Tiles are aligned ZR-plane slabs,
+  // so the grouping is the same in every tiling.
   uint32_t bad = 0u;
-  u128 acc[NTERM];
+  double hs[NTERM];
 #pragma unroll
-  for (int a = 0; a < NTERM; ++a) acc[a] = u128{0ull, 0ull};
+  for (int a = 0; a < NTERM; ++a) hs[a] = 0.0;
 
   // prologue: psi planes z0-2 .. z0+2 in LDS, w planes z0-1, z0
   {
@@ -486,16 +490,15 @@ __global__ __launch_bounds__(256) void lattice_pass3s(const ChainDev* __restrict
           kin = 0.5 * pd * pd;
         }
       }
-      // every lane reaches the quad sums (the shuffles need the whole wave)
-      if (MODE == PASS_FIRST) acc[T_K0] = add128(acc[T_K0], to_fixed(quad_sum_lanes(kin), bad));
-      if (MODE == PASS_LAST) acc[T_K1] = add128(acc[T_K1], to_fixed(quad_sum_lanes(kin), bad));
+      if (MODE == PASS_FIRST) hs[T_K0] = hs[T_K0] + kin;
+      if (MODE == PASS_LAST) hs[T_K1] = hs[T_K1] + kin;
       if (kH64) {
         double ht[4];
         double nb = ((double)pc[c - 1] + (double)pc[c + 1]) + ((double)pc[c - PX] + (double)pc[c + PX]);
         nb = nb + ((double)pm[c] + (double)pp[c]);
         h_terms(cd, (double)v, nb, act ? idx : 0, act, ht);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) acc[T_S + a] = add128(acc[T_S + a], to_fixed(quad_sum_lanes(ht[a]), bad));
+        for (int a = 0; a < 4; ++a) hs[T_S + a] = hs[T_S + a] + ht[a];
       }
     }
     // plane z+3 replaces plane z-2, which no later step reads
@@ -504,6 +507,16 @@ __global__ __launch_bounds__(256) void lattice_pass3s(const ChainDev* __restrict
   }
 
   if (MODE == PASS_MIDDLE || MODE == PASS_FORCE) return;
+  // every lane reaches the quad sums (the shuffles need the whole wave)
+  u128 acc[NTERM];
+#pragma unroll
+  for (int a = 0; a < NTERM; ++a) acc[a] = u128{0ull, 0ull};
+  if (MODE == PASS_FIRST) acc[T_K0] = to_fixed(quad_sum_lanes(hs[T_K0]), bad);
+  if (MODE == PASS_LAST) acc[T_K1] = to_fixed(quad_sum_lanes(hs[T_K1]), bad);
+  if (kH64) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) acc[T_S + a] = to_fixed(quad_sum_lanes(hs[T_S + a]), bad);
+  }
   const int tix = ((tl.z0 / ZR) * ((L1 + BY - 1) / BY) + tl.y0 / BY) * ((L0 + BX - 1) / BX) + tl.x0 / BX;
   block_accumulate<MODE, 4>(cd, st, acc, bad, cur, j, tix);
 }
