@@ -53,6 +53,84 @@ def cpu_baseline(chains):
                        f"{t_total:.1f} s on one host core")
 
 
+def streaming_point(args, copy_gbs):
+    """Labelled extra point: one 2D 8192^2 chain (about 1 GiB of state, far beyond
+    the 256 MB Infinity Cache), beta_c, h = 0, n_md = 20, FP32: the fused middle
+    pass against the HBM peak on a single chain."""
+    import torch
+    from paper_1912_03278_amd import ihmc, inputs
+    L = 8192
+    ctx = ihmc.Context(device=0, arena_bytes=3 << 30)
+    lat = ihmc.Lattice((L, L), beta=inputs.BETA_C_2D, C=4.1)
+    ch = ihmc.Chains(ctx, [lat], [ihmc.Run(n_md=20, n_traj=8, precision=ihmc.F32, seed=2, chain_id=2)])
+    ch.advance(1)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ch.advance(4)
+    ctx.sync()
+    dt = time.perf_counter() - t0
+    acc = ch.result(0, want_psi=False)["acceptance"]
+    mid = ch.time_pass(0, mode=1, reps=max(5, args.timing_reps // 5))
+    ch.close()
+    ctx.close()
+    gbs = BYTES_MIDDLE_F32 * mid["sites"] / (mid["us"] * 1e-6) / 1e9
+    print(f"bench: streaming point 8192^2 middle pass {mid['us']:.1f} us = {gbs:.0f} GB/s", file=sys.stderr,
+          flush=True)
+    return {"label": "extra point, not the configured workload: one 2D 8192^2 chain at beta_c, FP32, n_md=20",
+            "site_md_steps_per_s": 4 * L * L * 20 / dt, "acceptance": acc,
+            "middle_pass_us": round(mid["us"], 2), "bytes_per_launch": BYTES_MIDDLE_F32 * mid["sites"],
+            "achieved_GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "frac_of_copy": round(gbs / copy_gbs, 4)}
+
+
+def bench_small(args):
+    """One 2D 8x8 chain in FP64 (beta = 0.40, C = 4.1, n_md = 10, h = 0): the
+    correctness configuration.  With 64 sites every pass is pure launch latency;
+    the CPU oracle on the same chain is reported beside it."""
+    import numpy as np
+    import torch
+    from paper_1912_03278_amd import ihmc, inputs
+    w = inputs.small()
+    K, W = args.steps, args.warmup
+    ctx = ihmc.Context(device=0, arena_bytes=64 << 20)
+    lat = ihmc.Lattice(w["L"], beta=w["beta"], C=w["C"])
+    ch = ihmc.Chains(ctx, [lat], [ihmc.Run(n_md=w["n_md"], n_traj=W + K, precision=ihmc.F64, seed=w["seed"])])
+    ch.advance(W)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ch.advance(K)
+    ctx.sync()
+    dt = time.perf_counter() - t0
+    r = ch.result(0, want_psi=False)
+    ch.close()
+    ctx.close()
+    N = int(math.prod(w["L"]))
+    line = {
+        "metric": "site-MD-steps/s", "value": K * N * w["n_md"] / dt, "unit": "site-MD-steps/s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": 1000.0 * dt / K, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "small: one 2D 8x8 chain, beta=0.40, C=4.1, h=0, n_md=10, FP64 state; one step = "
+                               "one trajectory (latency-bound by construction)", "sites": N},
+        "observables": {"beta_eps_mean": float(np.mean(r["beta_eps"][W:])), "m2c_mean": float(np.mean(r["m2c"][W:])),
+                        "acceptance": r["acceptance"],
+                        "exact_beta_eps": -0.4889282573, "exact_m2": 0.4320990786},
+        "roofline": None,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        t1 = time.perf_counter()
+        oracle.run(oracle.Lattice(w["L"], beta=w["beta"], C=w["C"]), W + K, w["n_md"], seed=w["seed"])
+        t_cpu = time.perf_counter() - t1
+        line["cpu_baseline"] = dict(value=(W + K) * N * w["n_md"] / t_cpu, unit="site-MD-steps/s", cores=1,
+                                    kind="oracle", sample=f"the same chain, {W + K} trajectories, FP64, "
+                                                          f"{t_cpu:.2f} s on one host core")
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
 def bench_batched(args):
     """4096 independent 2D tori of uneven size, beta, per-site field and step count,
     advanced together (one step = one trajectory of every chain), against the same
@@ -300,7 +378,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="large", choices=["large", "batched", "dense", "serving"],
+    ap.add_argument("--workload", default="large", choices=["large", "batched", "dense", "serving", "small"],
                     help="large (default): the 1024^2 + 128^3 single chains; batched: 4096 uneven chains; "
                          "dense: 256 chains of an N=4096 all-to-all model; serving: Poisson request arrivals")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
@@ -310,6 +388,7 @@ def main():
     ap.add_argument("--chains", type=int, default=4096, help="batched: number of chains")
     ap.add_argument("--plain-sample", type=int, default=16, help="batched: chains rerun alone")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--no-streaming-point", action="store_true", help="large: skip the extra 8192^2 point")
     ap.add_argument("--timing-reps", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -322,6 +401,10 @@ def main():
         return bench_batched(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "small":
+        args.steps = 2000 if args.steps is None else args.steps
+        args.warmup = 200 if args.warmup is None else args.warmup
+        return bench_small(args)
     if args.workload == "dense":
         args.steps = 100 if args.steps is None else args.steps
         args.warmup = 5 if args.warmup is None else args.warmup
@@ -423,6 +506,8 @@ def main():
     }
     chains.close()
     ctx.close()
+    if not args.no_streaming_point:
+        line["extra_streaming_point"] = streaming_point(args, copy_gbs)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a one-trajectory sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(ws)

@@ -432,10 +432,28 @@ __global__ __launch_bounds__(256) void lattice_pass3s(const ChainDev* __restrict
     compute_w(tl.z0);
   }
 
+  // Each thread owns one column (lx, ly) of the tile; its momentum and field
+  // values are loaded one plane ahead, so their latency overlaps the w planes
+  // and the barrier of the step before.
+  static_assert(NO == 256, "one column per thread");
+  const int lx = threadIdx.x % BX, ly = threadIdx.x / BX;
+  const int gx = tl.x0 + lx, gy = tl.y0 + ly;
+  const bool act = (gx < L0) && (gy < L1);
+  const int64_t col = gx + (int64_t)pitch * gy;
+  constexpr bool kLoadP = (MODE == PASS_MIDDLE || MODE == PASS_LAST || MODE == PASS_FIRST);
+  const bool load_p = kLoadP && act && (MODE != PASS_FIRST || cd.p_given);
+  const bool load_b = kHasW && act && site_field;
+  T p_next = (T)0, b_next = b_uniform;
+  if (load_p) p_next = pmom[col + plane * tl.z0];
+  if (load_b) b_next = bsite[col + plane * tl.z0];
+
   for (int z = tl.z0; z < z_end; ++z) {
     // w(z+1) needs psi planes z .. z+2 (in LDS); plane z+3 is fetched meanwhile
     T pre[NPRE];
     const bool more = (z + 1 < z_end);
+    const T p_here = p_next, b_here = b_next;
+    if (more && load_p) p_next = pmom[col + plane * (z + 1)];
+    if (more && load_b) b_next = bsite[col + plane * (z + 1)];
     if (more) fetch_plane(z + 3, pre);
     if (kHasW) compute_w(z + 1);
     __syncthreads();
@@ -445,13 +463,9 @@ __global__ __launch_bounds__(256) void lattice_pass3s(const ChainDev* __restrict
     const T* __restrict__ wm = sW[kHasW ? (z - 1 - tl.z0 + 3) % 3 : 0];
     const T* __restrict__ wc = sW[kHasW ? (z - tl.z0 + 3) % 3 : 0];
     const T* __restrict__ wp = sW[kHasW ? (z + 1 - tl.z0 + 3) % 3 : 0];
-    static_assert(BX % 4 == 0 && NO % 256 == 0, "3D tile shape");
-#pragma unroll 1
-    for (int o = threadIdx.x; o < NO; o += 256) {
-      const int lx = o % BX, ly = o / BX;
-      const int gx = tl.x0 + lx, gy = tl.y0 + ly;
-      const bool act = (gx < L0) && (gy < L1);
-      const int64_t idx = gx + (int64_t)pitch * gy + plane * z;
+    static_assert(BX % 4 == 0, "3D tile shape");
+    {
+      const int64_t idx = col + plane * z;
       const int c = (lx + 2) + PX * (ly + 2);
       const T v = pc[c];
       double kin = 0.0;
@@ -460,11 +474,11 @@ __global__ __launch_bounds__(256) void lattice_pass3s(const ChainDev* __restrict
         T sw = (wc[q - 1] + wc[q + 1]) + (wc[q - WX] + wc[q + WX]);
         sw = sw + (wm[q] + wp[q]);
         T F = fma_t(Ct, wc[q], sw);
-        F = F + (site_field ? bsite[idx] : b_uniform);
+        F = F + b_here;
         T p;
         if (MODE == PASS_FIRST) {
           if (cd.p_given) {
-            p = pmom[idx];
+            p = p_here;
           } else {
             const int64_t site = gx + (int64_t)L0 * (gy + (int64_t)L1 * z);
             T z0, z1;
@@ -476,7 +490,7 @@ __global__ __launch_bounds__(256) void lattice_pass3s(const ChainDev* __restrict
         } else if (MODE == PASS_FORCE) {
           p = (T)0;
         } else {
-          p = pmom[idx];
+          p = p_here;
         }
         const T pn = fma_t(kick, F, p);
         if (MODE == PASS_FIRST || MODE == PASS_MIDDLE) {
