@@ -233,9 +233,9 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
   const T drift = (T)drift_d;
 
   uint32_t bad = 0u;
-  u128 acc[NTERM];
+  double qs[NTERM];  // FP64 sums of the thread's quad (0 without one)
 #pragma unroll
-  for (int a = 0; a < NTERM; ++a) acc[a] = u128{0ull, 0ull};
+  for (int a = 0; a < NTERM; ++a) qs[a] = 0.0;
 
   if (quad_ok) {
     // momenta of the first pass: one Philox draw per site pair; with an even
@@ -290,14 +290,11 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
         h_terms(cd, (double)c, nb, base + e, act, ht[e]);
       }
     }
-    if (MODE == PASS_FIRST)
-      acc[T_K0] = add128(acc[T_K0], to_fixed(quad_sum(kin[0], kin[1], kin[2], kin[3]), bad));
-    if (MODE == PASS_LAST)
-      acc[T_K1] = add128(acc[T_K1], to_fixed(quad_sum(kin[0], kin[1], kin[2], kin[3]), bad));
+    if (MODE == PASS_FIRST) qs[T_K0] = quad_sum(kin[0], kin[1], kin[2], kin[3]);
+    if (MODE == PASS_LAST) qs[T_K1] = quad_sum(kin[0], kin[1], kin[2], kin[3]);
     if (kH64) {
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
-        acc[T_S + a] = add128(acc[T_S + a], to_fixed(quad_sum(ht[0][a], ht[1][a], ht[2][a], ht[3][a]), bad));
+      for (int a = 0; a < 4; ++a) qs[T_S + a] = quad_sum(ht[0][a], ht[1][a], ht[2][a], ht[3][a]);
     }
     if (MODE == PASS_FIRST || MODE == PASS_MIDDLE) {
       st4<T>(pmom + base, pn);
@@ -308,6 +305,15 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
   }
 
   if (MODE == PASS_MIDDLE || MODE == PASS_FORCE) return;
+  u128 acc[NTERM];
+#pragma unroll
+  for (int a = 0; a < NTERM; ++a) acc[a] = u128{0ull, 0ull};
+  if (MODE == PASS_FIRST) acc[T_K0] = to_fixed(qs[T_K0], bad);
+  if (MODE == PASS_LAST) acc[T_K1] = to_fixed(qs[T_K1], bad);
+  if (kH64) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) acc[T_S + a] = to_fixed(qs[T_S + a], bad);
+  }
   const int tix = (tl.y0 / BY) * ((L0 + BX - 1) / BX) + tl.x0 / BX;  // tile index within the chain
   block_accumulate<MODE, NWAVE>(cd, st, acc, bad, cur, j, tix);
 }
@@ -591,9 +597,10 @@ static hipError_t launch_mode3s(int mode, const ChainDev* chains, const Tile* ti
   return hipGetLastError();
 }
 
-// 2D tiles: 64 x 16 (256 threads) for rows of 48 sites or more, 16 x 16
-// (64 threads) for small lattices.  3D column tiles: BX x BY in the plane,
-// streamed over ZR planes.
+// 2D tiles: 64 x 16 (256 threads) for rows of 48 sites or more, 32 x 32 (256
+// threads) where that wastes less of the last tile of a row, 16 x 16 (64
+// threads) for small lattices.  3D column tiles: 32 x 8 (or 16 x 16 by the same
+// rule) in the plane, streamed over ZR planes.
 #ifndef IHMC_2D_BX
 #define IHMC_2D_BX 64
 #define IHMC_2D_BY 16
@@ -604,14 +611,26 @@ static hipError_t launch_mode3s(int mode, const ChainDev* chains, const Tile* ti
 #define IHMC_3D_ZR 4
 #endif
 
+// Tile classes: the narrower tile wherever it leaves fewer idle threads in the
+// last tile of a row (row lengths just above a multiple of the wide tile).
 int tile_class(int ndim, int L0) {
-  if (ndim == 2) return L0 < 48 ? 1 : 0;
-  return 0;
+  if (ndim == 2) {
+    if (L0 < 48) return 1;
+    const int r = L0 % 64;
+    return (r >= 1 && r <= 32) ? 2 : 0;
+  }
+  const int r = L0 % 32;
+  return (r >= 1 && r <= 16) ? 1 : 0;
 }
 
 TileShape tile_shape(int precision, int ndim, int cls) {
   (void)precision;
-  if (ndim == 2) return cls == 1 ? TileShape{16, 16, 1} : TileShape{IHMC_2D_BX, IHMC_2D_BY, 1};
+  if (ndim == 2) {
+    if (cls == 1) return TileShape{16, 16, 1};
+    if (cls == 2) return TileShape{32, 32, 1};
+    return TileShape{IHMC_2D_BX, IHMC_2D_BY, 1};
+  }
+  if (cls == 1) return TileShape{16, 16, IHMC_3D_ZR};
   return TileShape{IHMC_3D_BX, IHMC_3D_BY, IHMC_3D_ZR};
 }
 
@@ -620,14 +639,18 @@ hipError_t launch_lattice_pass(int precision, int ndim, int cls, int mode, const
   if (precision == 4) {
     if (ndim == 2) {
       if (cls == 1) return launch_mode2v<float, 16, 16>(mode, chains, tiles, n_tiles, j, s);
+      if (cls == 2) return launch_mode2v<float, 32, 32>(mode, chains, tiles, n_tiles, j, s);
       return launch_mode2v<float, IHMC_2D_BX, IHMC_2D_BY>(mode, chains, tiles, n_tiles, j, s);
     }
+    if (cls == 1) return launch_mode3s<float, 16, 16, IHMC_3D_ZR>(mode, chains, tiles, n_tiles, j, s);
     return launch_mode3s<float, IHMC_3D_BX, IHMC_3D_BY, IHMC_3D_ZR>(mode, chains, tiles, n_tiles, j, s);
   }
   if (ndim == 2) {
     if (cls == 1) return launch_mode2v<double, 16, 16>(mode, chains, tiles, n_tiles, j, s);
+    if (cls == 2) return launch_mode2v<double, 32, 32>(mode, chains, tiles, n_tiles, j, s);
     return launch_mode2v<double, IHMC_2D_BX, IHMC_2D_BY>(mode, chains, tiles, n_tiles, j, s);
   }
+  if (cls == 1) return launch_mode3s<double, 16, 16, IHMC_3D_ZR>(mode, chains, tiles, n_tiles, j, s);
   return launch_mode3s<double, IHMC_3D_BX, IHMC_3D_BY, IHMC_3D_ZR>(mode, chains, tiles, n_tiles, j, s);
 }
 
