@@ -33,6 +33,41 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 matrix
 BYTES_MIDDLE_F32 = 16  # read psi, read p, write p, write psi' (FP32), h = 0
 
 
+# HBM traffic per launch of each workload's roofline kernel, from two rocprofv3
+# --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, median over the full
+# launches), scaled by what the same counters read for the plain copy kernel of
+# known size: FETCH_SIZE x 2, WRITE_SIZE x 1.  Each entry records a digest of the
+# kernel sources it was measured on; when the sources differ, the field is null.
+KERNEL_SOURCES = ("lattice_kernels.hip", "lattice_kernels.hpp", "chain_epilogue.hpp", "device_common.hpp",
+                  "ihmc_internal.hpp", "dense_kernels.hip", "dense_kernels.hpp")
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+TRAFFIC = {
+    "large_2d_middle": {"sources": "b7d2d3d1e9d8d4b2", "fetch_kib": 4199.0, "write_kib": 8192.0},
+    "large_3d_middle": {"sources": "b7d2d3d1e9d8d4b2", "fetch_kib": 9319.0, "write_kib": 16384.0},
+    "stream_2d_middle": {"sources": "b7d2d3d1e9d8d4b2", "fetch_kib": 263704.1, "write_kib": 524288.0},
+    "batched_middle": {"sources": "b7d2d3d1e9d8d4b2", "fetch_kib": 155782.8, "write_kib": 207496.4},
+    "dense_gemm_bf16": {"sources": "b7d2d3d1e9d8d4b2", "fetch_kib": 73754.5, "write_kib": 16384.0},
+}
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1912_03278_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_bytes(key):
+    """Measured HBM bytes per launch of the roofline kernel, or None if the
+    kernel sources changed since the counters were taken."""
+    t = TRAFFIC.get(key)
+    if not t or t["sources"] != kernel_digest():
+        return None
+    return int(1024 * (FETCH_SCALE * t["fetch_kib"] + WRITE_SCALE * t["write_kib"]))
+
+
 def large_workload():
     from paper_1912_03278_amd import inputs
     return inputs.large()
@@ -80,6 +115,7 @@ def streaming_point(args, copy_gbs):
     return {"label": "extra point, not the configured workload: one 2D 8192^2 chain at beta_c, FP32, n_md=20",
             "site_md_steps_per_s": 4 * L * L * 20 / dt, "acceptance": acc,
             "middle_pass_us": round(mid["us"], 2), "bytes_per_launch": BYTES_MIDDLE_F32 * mid["sites"],
+            "traffic": traffic_bytes("stream_2d_middle"),
             "achieved_GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
             "frac_of_copy": round(gbs / copy_gbs, 4)}
 
@@ -184,12 +220,16 @@ def bench_batched(args):
         alone.close()
     acc = [chains.result(i, want_psi=False)["acceptance"] for i in range(0, len(ws), max(1, len(ws) // 64))]
 
+    # launch groups are ordered by (precision, dimension, tile class); every chain
+    # here is FP32 2D, so the groups are the 64x16, 16x16 and 32x32 tile classes
+    tile_names = ["64x16", "16x16", "32x32"]
     kern = []
     for g in range(chains.groups()):
         mid = chains.time_pass(g, mode=1, reps=args.timing_reps)
-        kern.append(dict(ndim=mid["ndim"], sites=mid["sites"], middle_us=round(mid["us"], 2),
+        kern.append(dict(ndim=mid["ndim"], tiles=tile_names[g] if g < 3 else "?", sites=mid["sites"],
+                         middle_us=round(mid["us"], 2),
                          middle_GBs=round(20 * mid["sites"] / (mid["us"] * 1e-6) / 1e9, 1)))
-    dom = max(kern, key=lambda k: k["middle_us"])
+    dom = kern[0]  # the 64x16 group: the most sites
     achieved = 20 * dom["sites"] / (dom["middle_us"] * 1e-6) / 1e9
     copy_bytes = 512 << 20
     copy_gbs = 2 * copy_bytes / (ctx.copy_bandwidth(copy_bytes, reps=10) * 1e-6) / 1e9
@@ -201,9 +241,9 @@ def bench_batched(args):
                                "h_x ~ N(0,0.05^2) per site, n_md U{8..32}, C=4.1, FP32 state, FP64 H; "
                                "one step = one trajectory of every chain",
                    "chains": len(ws), "sites": sum(int(math.prod(w["L"])) for w in ws)},
-        "roofline": {"bound": "hbm", "kernel": "fused middle pass, 2D, per-site field (large-tile group)",
+        "roofline": {"bound": "hbm", "kernel": "fused middle pass, 2D, per-site field, 64x16-tile group (all chains)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_bytes("batched_middle"),
                      "bytes_per_launch": 20 * dom["sites"], "avg_launch_us": dom["middle_us"],
                      "copy_kernel_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "kernels": kern,
@@ -271,7 +311,7 @@ def bench_dense(args):
                    "C": info["C"]},
         "roofline": {"bound": "mfma", "kernel": "BF16-limb split-K GEMM (one K~ application of all chains)",
                      "achieved": round(achieved, 1), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": traffic_bytes("dense_gemm_bf16"),
                      "flops_per_launch": executed, "avg_launch_us": round(g["us"], 2),
                      "gemm_mnk": [m, n, k], "split_k": g["split_k"],
                      "useful_fp32_equiv_TFLOPs": round(useful / (g["us"] * 1e-6) / 1e12, 1)},
@@ -495,7 +535,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic_bytes("large_3d_middle" if dom["ndim"] == 3 else "large_2d_middle"),
             "bytes_per_launch": bytes_per_launch,
             "avg_launch_us": round(dom["middle_us"], 3),
             "copy_kernel_GBs": round(copy_gbs, 1),
