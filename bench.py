@@ -45,7 +45,8 @@ TRAFFIC = {
     "large_2d_middle": {"sources": "b7d2d3d1e9d8d4b2", "fetch_kib": 4199.0, "write_kib": 8192.0},
     "large_3d_middle": {"sources": "b7d2d3d1e9d8d4b2", "fetch_kib": 9319.0, "write_kib": 16384.0},
     "stream_2d_middle": {"sources": "b7d2d3d1e9d8d4b2", "fetch_kib": 263704.1, "write_kib": 524288.0},
-    "batched_middle": {"sources": "b7d2d3d1e9d8d4b2", "fetch_kib": 155782.8, "write_kib": 207496.4},
+    "batched_middle": {"sources": "b7d2d3d1e9d8d4b2", "sites": 26151867, "fetch_kib": 155782.8,
+                       "write_kib": 207496.4},
     "dense_gemm_bf16": {"sources": "b7d2d3d1e9d8d4b2", "fetch_kib": 73754.5, "write_kib": 16384.0},
 }
 
@@ -59,11 +60,14 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
-def traffic_bytes(key):
+def traffic_bytes(key, sites=None):
     """Measured HBM bytes per launch of the roofline kernel, or None if the
-    kernel sources changed since the counters were taken."""
+    kernel sources (or the sites that launch covers) changed since the counters
+    were taken."""
     t = TRAFFIC.get(key)
     if not t or t["sources"] != kernel_digest():
+        return None
+    if sites is not None and t.get("sites") not in (None, sites):
         return None
     return int(1024 * (FETCH_SCALE * t["fetch_kib"] + WRITE_SCALE * t["write_kib"]))
 
@@ -71,6 +75,34 @@ def traffic_bytes(key):
 def large_workload():
     from paper_1912_03278_amd import inputs
     return inputs.large()
+
+
+def tune_tiles(ctx, lats, args, sites=0):
+    """Autotune the tile class of every distinct lattice shape (unless --tiles rule)
+    at the workload's resident working set; returns a summary for the JSON line."""
+    if args.tiles == "rule":
+        return {"tile_classes": "built-in rule"}
+    t0 = time.perf_counter()
+    n = ctx.tune(lats, sites=sites)
+    dt = time.perf_counter() - t0
+    print(f"bench: tile classes tuned for {n} shapes in {dt:.1f} s", file=sys.stderr, flush=True)
+    return {"tile_classes": "autotuned", "tuned_shapes": n, "tune_s": round(dt, 2)}
+
+
+def group_rows(chains, reps, modes=(1,)):
+    """Per launch group: tile shape, sites and HIP-event time of the pass kinds."""
+    from paper_1912_03278_amd import ihmc
+    rows = []
+    for g in range(chains.groups()):
+        info = chains.group_info(g)
+        shape = ihmc.tile_shape(info["ndim"], info["cls"])
+        row = dict(ndim=info["ndim"], tiles="x".join(map(str, shape if info["ndim"] == 3 else shape[:2])),
+                   chains=info["chains"], sites=info["sites"])
+        for m in modes:
+            name = ("first_us", "middle_us", "last_us")[m]
+            row[name] = chains.time_pass(g, mode=m, reps=reps if m == 1 else max(10, reps // 5))["us"]
+        rows.append(row)
+    return rows
 
 
 def cpu_baseline(chains):
@@ -181,6 +213,7 @@ def bench_batched(args):
     lats = [ihmc.Lattice(w["L"], beta=w["beta"], C=w["C"], h=w["h"]) for w in ws]
     runs = [ihmc.Run(n_md=w["n_md"], n_traj=W + K, precision=ihmc.F32, seed=w["seed"], chain_id=w["chain_id"])
             for w in ws]
+    tiles = tune_tiles(ctx, lats, args)
     t0 = time.perf_counter()
     chains = ihmc.Chains(ctx, lats, runs)
     t_setup = time.perf_counter() - t0
@@ -220,16 +253,12 @@ def bench_batched(args):
         alone.close()
     acc = [chains.result(i, want_psi=False)["acceptance"] for i in range(0, len(ws), max(1, len(ws) // 64))]
 
-    # launch groups are ordered by (precision, dimension, tile class); every chain
-    # here is FP32 2D, so the groups are the 64x16, 16x16 and 32x32 tile classes
-    tile_names = ["64x16", "16x16", "32x32"]
-    kern = []
-    for g in range(chains.groups()):
-        mid = chains.time_pass(g, mode=1, reps=args.timing_reps)
-        kern.append(dict(ndim=mid["ndim"], tiles=tile_names[g] if g < 3 else "?", sites=mid["sites"],
-                         middle_us=round(mid["us"], 2),
-                         middle_GBs=round(20 * mid["sites"] / (mid["us"] * 1e-6) / 1e9, 1)))
-    dom = kern[0]  # the 64x16 group: the most sites
+    # one launch group per tile class in use (all chains are FP32 2D)
+    kern = group_rows(chains, args.timing_reps)
+    for k in kern:
+        k["middle_GBs"] = round(20 * k["sites"] / (k["middle_us"] * 1e-6) / 1e9, 1)
+        k["middle_us"] = round(k["middle_us"], 2)
+    dom = max(kern, key=lambda k: k["sites"])
     achieved = 20 * dom["sites"] / (dom["middle_us"] * 1e-6) / 1e9
     copy_bytes = 512 << 20
     copy_gbs = 2 * copy_bytes / (ctx.copy_bandwidth(copy_bytes, reps=10) * 1e-6) / 1e9
@@ -240,10 +269,12 @@ def bench_batched(args):
         "config": {"workload": f"batched: {len(ws)} 2D tori, L log-uniform [16,256], beta U[0.30,0.55], "
                                "h_x ~ N(0,0.05^2) per site, n_md U{8..32}, C=4.1, FP32 state, FP64 H; "
                                "one step = one trajectory of every chain",
-                   "chains": len(ws), "sites": sum(int(math.prod(w["L"])) for w in ws)},
-        "roofline": {"bound": "hbm", "kernel": "fused middle pass, 2D, per-site field, 64x16-tile group (all chains)",
+                   "chains": len(ws), "sites": sum(int(math.prod(w["L"])) for w in ws), **tiles},
+        "roofline": {"bound": "hbm", "kernel": f"fused middle pass, 2D, per-site field, {dom['tiles']}-tile group "
+                                               f"({dom['chains']} chains)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_bytes("batched_middle"),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_bytes("batched_middle", sites=dom["sites"]),
                      "bytes_per_launch": 20 * dom["sites"], "avg_launch_us": dom["middle_us"],
                      "copy_kernel_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "kernels": kern,
@@ -352,6 +383,14 @@ def bench_serving(args):
 
     reqs = inputs.serving(rate=args.rate, duration=args.serve_duration)
     ctx = ihmc.Context(device=0, arena_bytes=12 << 30)
+    # tile classes of every request shape, chosen before the first arrival
+    shapes = {}
+    for r in reqs:
+        shapes.setdefault((tuple(r["L"]), r["h"] is not None and np.size(r["h"]) > 1),
+                          ihmc.Lattice(r["L"], beta=r["beta"], C=r["C"], h=r["h"]))
+    # the working set they are tuned for: the resident set at this load, about a
+    # thousand requests of ~47k sites on average
+    tiles = tune_tiles(ctx, list(shapes.values()), args, sites=1 << 25)
     sv = ihmc.Server(ctx, budget_bytes=10 << 30, max_active=2048)
     tickets = [None] * len(reqs)
     work = [int(math.prod(r["L"])) * r["n_md"] * r["n_traj"] for r in reqs]
@@ -401,7 +440,8 @@ def bench_serving(args):
                                "(p = 1/2), L U{16..128} (2D) / U{16..64} (3D), beta U[0.2,0.6], uniform h "
                                "U[0,0.1], C = 2d + 0.1, 50-1000 trajectories of 10-30 leap-frog steps, FP32 state, "
                                "FP64 H; one step = one completed request",
-                   "requests": len(reqs), "offered_site_md_steps_per_s": sum(work) / args.serve_duration},
+                   "requests": len(reqs), "offered_site_md_steps_per_s": sum(work) / args.serve_duration,
+                   **tiles},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "mean": float(lat.mean()), "max": float(lat.max())},
         "completed": len(done), "incomplete": len(incomplete), "elapsed_s": elapsed,
@@ -430,6 +470,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-streaming-point", action="store_true", help="large: skip the extra 8192^2 point")
     ap.add_argument("--timing-reps", type=int, default=100)
+    ap.add_argument("--tiles", default="tuned", choices=["tuned", "rule"],
+                    help="tile classes: autotuned per lattice shape before the run (default), or the built-in rule")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU sharding is described in "
@@ -461,6 +503,7 @@ def main():
     lats = [ihmc.Lattice(w["L"], beta=w["beta"], C=w["C"]) for w in ws]
     runs = [ihmc.Run(n_md=w["n_md"], n_traj=W + K, precision=ihmc.F32, seed=w["seed"], chain_id=w["chain_id"])
             for w in ws]
+    tiles = tune_tiles(ctx, lats, args)
     chains = ihmc.Chains(ctx, lats, runs)
     print(f"bench: chains ready ({', '.join('x'.join(map(str, w['L'])) for w in ws)})", file=sys.stderr, flush=True)
     chains.advance(W)
@@ -487,14 +530,10 @@ def main():
                         mean_beta_eps_last=float(r["beta_eps"][-1])))
 
     # ---- roofline of the dominant kernel: HIP-event timing of each fused pass kind
-    kern = []
-    for g in range(chains.groups()):
-        mid = chains.time_pass(g, mode=1, reps=args.timing_reps)
-        first = chains.time_pass(g, mode=0, reps=max(10, args.timing_reps // 5))
-        last = chains.time_pass(g, mode=2, reps=max(10, args.timing_reps // 5))
-        n_md = ws[g]["n_md"]  # groups are ordered (precision, ndim): 2D then 3D, one chain each
-        kern.append(dict(ndim=mid["ndim"], sites=mid["sites"], middle_us=mid["us"], first_us=first["us"],
-                         last_us=last["us"], middle_share_us=(n_md - 1) * mid["us"]))
+    # groups are ordered (precision, ndim, tile class): the 2D chain, then the 3D one
+    kern = group_rows(chains, args.timing_reps, modes=(1, 0, 2))
+    for g, k in enumerate(kern):
+        k["middle_share_us"] = (ws[g]["n_md"] - 1) * k["middle_us"]
     dom = max(kern, key=lambda k: k["middle_share_us"])
     bytes_per_launch = BYTES_MIDDLE_F32 * dom["sites"]
     achieved = bytes_per_launch / (dom["middle_us"] * 1e-6) / 1e9
@@ -527,6 +566,7 @@ def main():
                         "state, FP64 H/dH/Metropolis; one step = one trajectory of both chains",
             "sites": sum(int(math.prod(w["L"])) for w in ws),
             "md_steps_per_trajectory": ws[0]["n_md"],
+            **tiles,
         },
         "roofline": {
             "bound": "hbm",

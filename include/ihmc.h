@@ -298,9 +298,13 @@ int ihmc_philox_words(ihmc_ctx* ctx, int64_t n, const uint32_t* ctr, const uint3
 
 /* ---- measurement ----------------------------------------------------------- */
 
-/* Number of launch groups of a chain set (chains of equal precision and
- * dimension share launches; groups are ordered by (precision, ndim)). */
+/* Number of launch groups of a chain set (chains of equal precision,
+ * dimension and tile class share launches; groups are ordered by (precision,
+ * ndim, tile class)). */
 int ihmc_chains_groups(ihmc_chains* chains, int32_t* n_groups);
+/* Launch group `group` (0 <= group < n_groups): out[0..5] = state precision,
+ * ndim, tile class (see ihmc_tile_shape), chains, lattice sites, tiles. */
+int ihmc_chains_group_info(ihmc_chains* chains, int32_t group, int64_t* out);
 /* Time the fused pass kind `mode` (0 = first, 1 = middle, 2 = last) of launch
  * group `group`: one warm-up launch, then `reps` launches bracketed by HIP
  * events on the context stream.  Returns the mean duration per launch in
@@ -316,6 +320,64 @@ int ihmc_chains_time_pass(ihmc_chains* chains, int32_t group, int32_t mode, int3
  * the context stream; returns the mean microseconds per copy (read + write
  * traffic = 2 * bytes).  The achievable-bandwidth reference of the roofline. */
 int ihmc_copy_bandwidth(ihmc_ctx* ctx, uint64_t bytes, int32_t reps, double* avg_us);
+
+/* ---- tile autotuner ---------------------------------------------------------- */
+
+/* A lattice pass covers its chain in tiles of one of a few shapes, the tile
+ * classes: in 2D 0 = 64 x 16, 1 = 16 x 16, 2 = 32 x 32 sites; in 3D columns of
+ * 0 = 32 x 8 or 1 = 16 x 16 sites in the plane, four planes deep.  The class
+ * changes speed only: every class gives bitwise the same trajectories, since
+ * all sums are formed per x-aligned quad of sites and per four-plane column
+ * and then added in exact fixed point.  A chain takes its class when it is
+ * created (ihmc_chains_create, ihmc_run_*, ihmc_submit) from its context's
+ * table, keyed by (precision, ndim, L, per-site field or not), and without a
+ * table entry from a built-in rule (narrower tiles where a row ends just past a
+ * multiple of the wide tile).  When the environment variable IHMC_TUNE_CACHE
+ * names a file, ihmc_ctx_create loads the table from it if it exists (failing
+ * with IHMC_E_INVAL if it is malformed) and ihmc_tune saves the table there. */
+#define IHMC_TUNE_RULE 0     /* no entry: the built-in rule */
+#define IHMC_TUNE_MEASURED 1 /* chosen by ihmc_tune */
+#define IHMC_TUNE_PINNED 2   /* set by ihmc_tune_pin; ihmc_tune leaves it */
+#define IHMC_TUNE_FORCE 1    /* ihmc_tune flag: measure keys that have a measured entry again */
+
+/* Tile extent of class cls in dimension ndim: out[0..2] = sites in x, y and
+ * planes in z (1 in 2D); IHMC_E_INVAL for an unknown class.  *n_classes (if
+ * not NULL) = number of classes of ndim (out may be NULL to ask only that). */
+int ihmc_tile_shape(int32_t ndim, int32_t cls, int32_t* out, int32_t* n_classes);
+/* Autotune: for each distinct key among lats[0..n) (state precision
+ * precision[i]), time the middle pass of every tile class and keep the fastest
+ * in the table (the built-in rule's class stays unless another is over 3 % faster).  A measurement
+ * runs on the context stream over replicas of the lattice with synthetic
+ * fields, about `sites` sites in all (at most 65536 replicas): the working set
+ * the choice is for, since whether the state streams from HBM or stays in the
+ * last-level cache decides which tile is fastest.  sites = 0 takes the total
+ * sites of lats[0..n), repeats included (pass the lattices of the chains that
+ * will run together); the value is clamped to [2^20, 2^26].  Per class, `reps`
+ * launches (0: 10, or 4 above 2^23 sites) after a warm-up, in three rounds
+ * interleaved across the classes, keeping the least mean.  The arena must hold
+ * the replicas (4 state fields, 5 with a per-site field, each replica) for the
+ * duration of one key.  Keys with a measured entry are skipped unless flags has
+ * IHMC_TUNE_FORCE; pinned keys are always skipped.  Synchronous; *n_measured
+ * (may be NULL) = keys measured.  Existing chains keep their classes. */
+int ihmc_tune(ihmc_ctx* ctx, int32_t n, const ihmc_lattice* lats, const int32_t* precision, int64_t sites,
+              int32_t reps, int32_t flags, int32_t* n_measured);
+/* The class that chains of (lat, precision) would take on this context, its
+ * source (IHMC_TUNE_*) and, if ns_site is not NULL, ns_site[0..2] = measured
+ * middle-pass nanoseconds per site of each class (NaN where not measured or
+ * the class does not exist). */
+int ihmc_tune_lookup(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t precision, int32_t* cls, int32_t* source,
+                     double* ns_site);
+/* Pin class cls for (lat, precision); cls < 0 removes the entry (the rule
+ * applies again).  IHMC_E_INVAL for a class that does not exist. */
+int ihmc_tune_pin(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t precision, int32_t cls);
+/* Write the table to `path` as JSON / merge the JSON table at `path` into the
+ * context's (entries replace equal keys; IHMC_E_INVAL for a missing, malformed
+ * or out-of-range file, leaving the table unchanged). */
+int ihmc_tune_save(ihmc_ctx* ctx, const char* path);
+int ihmc_tune_load(ihmc_ctx* ctx, const char* path);
+/* Read and check the JSON table at `path` without a context or GPU;
+ * *n_entries (may be NULL) = distinct keys in it. */
+int ihmc_tune_check(const char* path, int32_t* n_entries);
 
 #ifdef __cplusplus
 }

@@ -52,7 +52,7 @@ struct ChainDev {
   int32_t ndim, L0, L1, L2;
   int64_t N;             // lattice sites
   int32_t pitch;         // row pitch of the stored fields (L0 rounded up to 4)
-  int32_t pad0;
+  int32_t tile_cls;      // tile class of the chain's launch group (host-side choice)
   int64_t NP;            // stored elements per field: pitch * L1 * L2
   int32_t n_pass;      // force evaluations per trajectory
   int32_t integrator;

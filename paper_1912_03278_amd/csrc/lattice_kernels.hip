@@ -623,6 +623,8 @@ int tile_class(int ndim, int L0) {
   return (r >= 1 && r <= 16) ? 1 : 0;
 }
 
+int tile_class_count(int ndim) { return ndim == 2 ? 3 : 2; }
+
 TileShape tile_shape(int precision, int ndim, int cls) {
   (void)precision;
   if (ndim == 2) {

@@ -13,8 +13,12 @@ struct TileShape {
   int bx, by, bz;
 };
 
-// Tile-shape class of a lattice (small 2D lattices use smaller tiles).
+// Built-in tile class of a lattice (row length L0): the class that the
+// context uses unless its tuning table has an entry for the lattice.
 int tile_class(int ndim, int L0);
+
+// Number of tile classes of a dimension (2 or 3); classes are 0 .. n-1.
+int tile_class_count(int ndim);
 
 // Tile extents used for a state precision (4 or 8 bytes), dimension (2 or 3)
 // and tile class.

@@ -242,7 +242,7 @@ __global__ __launch_bounds__(256) void k_field_cg(ChainDev* cds, const int* whic
 static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
 // Descriptor of one lattice chain (no device memory yet).
-void describe_chain(const ihmc_lattice& l, const ihmc_run& r, int flags, ChainDev& c) {
+void describe_chain(const ihmc_lattice& l, const ihmc_run& r, int flags, int cls, ChainDev& c) {
   std::memset(&c, 0, sizeof c);
   c.ndim = l.ndim;
   c.L0 = l.L[0];
@@ -273,12 +273,13 @@ void describe_chain(const ihmc_lattice& l, const ihmc_run& r, int flags, ChainDe
   c.precision = r.precision;
   c.p_given = (flags & BUILD_P_GIVEN) ? 1 : 0;
   c.write_p_last = (flags & BUILD_WRITE_P) ? 1 : 0;
+  c.tile_cls = cls;
   c.n_tiles = chain_tile_count(c);
 }
 
 // Tiles of one chain in the tile shape of its launch group.
 uint32_t chain_tile_count(const ChainDev& c) {
-  const TileShape ts = tile_shape(c.precision, c.ndim, tile_class(c.ndim, c.L0));
+  const TileShape ts = tile_shape(c.precision, c.ndim, c.tile_cls);
   const uint32_t nz = c.ndim == 3 ? (uint32_t)((c.L2 + ts.bz - 1) / ts.bz) : 1u;
   return nz * (uint32_t)((c.L1 + ts.by - 1) / ts.by) * (uint32_t)((c.L0 + ts.bx - 1) / ts.bx);
 }
@@ -291,7 +292,7 @@ void plan_groups(const std::vector<ChainDev>& cd, const std::vector<int>& member
   const int base = (int)tiles.size();
   std::map<std::tuple<int, int, int>, std::vector<int>> byk;
   for (int i : members)
-    byk[std::make_tuple(cd[i].precision, cd[i].ndim, tile_class(cd[i].ndim, cd[i].L0))].push_back(i);
+    byk[std::make_tuple(cd[i].precision, cd[i].ndim, cd[i].tile_cls)].push_back(i);
   for (auto& kv : byk) {
     Group g;
     g.prec = std::get<0>(kv.first);
@@ -401,6 +402,18 @@ extern "C" int ihmc_ctx_create(int32_t device, uint64_t arena_bytes, ihmc_alloc_
     delete c;
     return hip_fail(nullptr, e, "hipStreamCreate");
   }
+  // tile classes chosen earlier, when a cache file is named and present
+  const char* cache = std::getenv("IHMC_TUNE_CACHE");
+  if (cache && *cache) {
+    if (FILE* f = std::fopen(cache, "r")) {
+      std::fclose(f);
+      const int rc = tune_load(c->tune, cache);
+      if (rc) {
+        ihmc_ctx_destroy(c);
+        return rc;
+      }
+    }
+  }
   *out = c;
   return IHMC_OK;
 }
@@ -472,7 +485,7 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
     int rc = validate(l, r, i);
     if (rc) return rc;
     ChainDev& c = cd[i];
-    describe_chain(l, r, flags, c);
+    describe_chain(l, r, flags, ctx->tune.class_for(tile_key(l, r.precision)), c);
     const int64_t N = c.N, NP = c.NP;
     const int64_t pb = r.precision;
     c.psi = dalloc(3 * NP * pb);
@@ -975,6 +988,22 @@ extern "C" int ihmc_philox_words(ihmc_ctx* ctx, int64_t n, const uint32_t* ctr, 
 extern "C" int ihmc_chains_groups(ihmc_chains* ch, int32_t* n_groups) {
   if (!ch || !n_groups) return set_error(IHMC_E_INVAL, "NULL argument");
   *n_groups = (int32_t)((Chains*)ch)->groups.size();
+  return IHMC_OK;
+}
+
+extern "C" int ihmc_chains_group_info(ihmc_chains* ch, int32_t group, int64_t* out) {
+  if (!ch || !out) return set_error(IHMC_E_INVAL, "NULL argument");
+  Chains* c = (Chains*)ch;
+  if (group < 0 || group >= (int32_t)c->groups.size()) return set_error(IHMC_E_INVAL, "group out of range");
+  const Group& g = c->groups[group];
+  int64_t sites = 0;
+  for (int ci : g.order) sites += c->cd[ci].N;
+  out[0] = g.prec;
+  out[1] = g.ndim;
+  out[2] = g.cls;
+  out[3] = (int64_t)g.order.size();
+  out[4] = sites;
+  out[5] = g.tile_begin.back();
   return IHMC_OK;
 }
 

@@ -5,6 +5,7 @@
 
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "../../include/ihmc.h"
@@ -40,6 +41,32 @@ struct Arena {
 
 enum BuildFlags : int { BUILD_P_GIVEN = 1, BUILD_WRITE_P = 2 };
 
+// Tile classes of the lattice passes: the built-in rule (lattice_kernels.hip)
+// and the per-shape choices of the autotuner (tune.hip), keyed by what the
+// cost of a pass depends on.
+struct TileKey {
+  int32_t prec, ndim, L0, L1, L2, site_field;
+  bool operator<(const TileKey& o) const {
+    return std::tie(prec, ndim, L0, L1, L2, site_field) < std::tie(o.prec, o.ndim, o.L0, o.L1, o.L2, o.site_field);
+  }
+};
+constexpr int kMaxTileClasses = 3;
+struct TuneEntry {
+  int32_t cls = 0;
+  int32_t source = IHMC_TUNE_RULE;
+  double ns_site[kMaxTileClasses];  // middle-pass ns per site of each class (NaN: not measured)
+};
+struct TuneTable {
+  std::mutex mu;
+  std::map<TileKey, TuneEntry> m;
+  // The table's class for k, else the built-in rule.
+  int class_for(const TileKey& k);
+};
+TileKey tile_key(const ihmc_lattice& l, int precision);
+// JSON form of the table; load merges (entries replace equal keys).
+int tune_save(TuneTable& t, const char* path);
+int tune_load(TuneTable& t, const char* path);
+
 // Chains of equal state precision and dimension share launches.
 struct Group {
   int prec = 4, ndim = 2, cls = 0;
@@ -54,7 +81,8 @@ struct Group {
 // and the serving loop (runtime.hip).
 int validate(const ihmc_lattice& l, const ihmc_run& r, int idx);
 int64_t lattice_sites(const ihmc_lattice& l);
-void describe_chain(const ihmc_lattice& l, const ihmc_run& r, int flags, ChainDev& c);
+// Descriptor of one chain whose passes use tile class `cls` (no device memory).
+void describe_chain(const ihmc_lattice& l, const ihmc_run& r, int flags, int cls, ChainDev& c);
 uint32_t chain_tile_count(const ChainDev& c);
 void plan_groups(const std::vector<ChainDev>& cd, const std::vector<int>& members, std::vector<Group>& groups,
                  std::vector<Tile>& tiles);
@@ -118,4 +146,5 @@ struct ihmc_ctx {
   ihmc_free_fn ff = nullptr;
   void* user = nullptr;
   bool dead = false;
+  ihmc::TuneTable tune;
 };

@@ -43,6 +43,7 @@ struct Request {
   std::vector<double> h, psi0;
   std::vector<uint8_t> replay;
   uint64_t need = 0;  // device bytes while resident
+  int cls = 0;        // tile class, fixed at submission
   int slot = -1;
   ChainDev cd{};
   std::vector<void*> dev;  // arena blocks
@@ -60,7 +61,7 @@ static inline uint64_t r256(uint64_t b) { return (b + 255ull) & ~255ull; }
 
 // Device bytes a request holds while resident (state, records, field arrays,
 // and its share of the tile table), plus its set-up staging.
-static uint64_t request_bytes(const ihmc_lattice& l, const ihmc_run& r) {
+static uint64_t request_bytes(const ihmc_lattice& l, const ihmc_run& r, int cls) {
   const int64_t N = lattice_sites(l);
   const int64_t pitch = (l.L[0] + 3) & ~3;
   const int64_t NP = pitch * (N / l.L[0]);
@@ -70,7 +71,7 @@ static uint64_t request_bytes(const ihmc_lattice& l, const ihmc_run& r) {
   if (r.replay_accept) b += r256((uint64_t)r.n_traj);
   if (l.h_len == N && N > 1) b += r256(8 * NP) + r256(NP * pb) + r256(8 * 4 * (uint64_t)N) + r256(8 * (uint64_t)N);
   ChainDev c;
-  describe_chain(l, r, 0, c);
+  describe_chain(l, r, 0, cls, c);
   b += r256(sizeof(Tile) * (uint64_t)c.n_tiles) + partials_bytes(c.n_tiles);
   return b;
 }
@@ -231,7 +232,7 @@ bool ihmc_server::admit_setup(std::vector<Request*>& fresh) {
   hipError_t e = hipSuccess;
   for (Request* r : fresh) {
     ChainDev& c = r->cd;
-    describe_chain(r->lat, r->run, 0, c);
+    describe_chain(r->lat, r->run, 0, r->cls, c);
     const uint64_t pb = (uint64_t)c.precision;
     auto dal = [&](uint64_t b) {
       void* p = ctx->arena.alloc(b);
@@ -497,7 +498,8 @@ extern "C" int ihmc_submit(ihmc_server* sv, const ihmc_lattice* lat, const ihmc_
   if (run->replay_accept && run->n_traj > 0) r->replay.assign(run->replay_accept, run->replay_accept + run->n_traj);
   r->run.psi0 = nullptr;
   r->run.replay_accept = r->replay.empty() ? nullptr : r->replay.data();
-  r->need = request_bytes(r->lat, r->run);
+  r->cls = sv->ctx->tune.class_for(tile_key(r->lat, r->run.precision));
+  r->need = request_bytes(r->lat, r->run, r->cls);
   std::lock_guard<std::mutex> lk(sv->mu);
   if (sv->dead) {
     delete r;

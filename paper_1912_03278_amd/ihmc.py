@@ -28,11 +28,14 @@ EXPORTS = (
     "ihmc_last_error", "ihmc_chains_create", "ihmc_chains_advance", "ihmc_chains_result",
     "ihmc_chains_destroy", "ihmc_run_lattice", "ihmc_run_batch", "ihmc_force", "ihmc_action",
     "ihmc_integrate", "ihmc_philox_normals", "ihmc_philox_words", "ihmc_chains_groups",
-    "ihmc_chains_time_pass", "ihmc_copy_bandwidth", "ihmc_dense_create", "ihmc_dense_advance",
-    "ihmc_dense_result", "ihmc_dense_info", "ihmc_dense_time", "ihmc_dense_destroy", "ihmc_run_dense",
-    "ihmc_dense_force", "ihmc_min_eig", "ihmc_server_create", "ihmc_server_destroy", "ihmc_submit",
-    "ihmc_poll", "ihmc_wait", "ihmc_fetch", "ihmc_cancel", "ihmc_server_stats",
+    "ihmc_chains_time_pass", "ihmc_chains_group_info", "ihmc_copy_bandwidth", "ihmc_dense_create",
+    "ihmc_dense_advance", "ihmc_dense_result", "ihmc_dense_info", "ihmc_dense_time", "ihmc_dense_destroy",
+    "ihmc_run_dense", "ihmc_dense_force", "ihmc_min_eig", "ihmc_server_create", "ihmc_server_destroy",
+    "ihmc_submit", "ihmc_poll", "ihmc_wait", "ihmc_fetch", "ihmc_cancel", "ihmc_server_stats",
+    "ihmc_tile_shape", "ihmc_tune", "ihmc_tune_lookup", "ihmc_tune_pin", "ihmc_tune_save", "ihmc_tune_load",
+    "ihmc_tune_check",
 )
+TUNE_RULE, TUNE_MEASURED, TUNE_PINNED = 0, 1, 2
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED, REQ_FAILED = 0, 1, 2, 3, 4
 
 
@@ -112,6 +115,7 @@ def load():
     L.ihmc_philox_words.argtypes = [vp, C.c_int64, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
                                     C.POINTER(C.c_uint32)]
     L.ihmc_chains_groups.argtypes = [vp, C.POINTER(C.c_int32)]
+    L.ihmc_chains_group_info.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64)]
     L.ihmc_chains_time_pass.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                         C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.ihmc_copy_bandwidth.argtypes = [vp, C.c_uint64, C.c_int32, C.POINTER(C.c_double)]
@@ -133,6 +137,14 @@ def load():
     L.ihmc_fetch.argtypes = [vp, C.c_uint64, C.POINTER(_Result), _DP]
     L.ihmc_cancel.argtypes = [vp, C.c_uint64]
     L.ihmc_server_stats.argtypes = [vp, _DP]
+    i32p = C.POINTER(C.c_int32)
+    L.ihmc_tile_shape.argtypes = [C.c_int32, C.c_int32, i32p, i32p]
+    L.ihmc_tune.argtypes = [vp, C.c_int32, C.POINTER(_Lattice), i32p, C.c_int64, C.c_int32, C.c_int32, i32p]
+    L.ihmc_tune_lookup.argtypes = [vp, C.POINTER(_Lattice), C.c_int32, i32p, i32p, _DP]
+    L.ihmc_tune_pin.argtypes = [vp, C.POINTER(_Lattice), C.c_int32, C.c_int32]
+    L.ihmc_tune_save.argtypes = [vp, C.c_char_p]
+    L.ihmc_tune_load.argtypes = [vp, C.c_char_p]
+    L.ihmc_tune_check.argtypes = [C.c_char_p, i32p]
     _lib = L
     return L
 
@@ -140,6 +152,26 @@ def load():
 def _check(rc):
     if rc != IHMC_OK:
         raise IhmcError(rc, load().ihmc_last_error().decode(errors="replace"))
+
+
+def tile_shape(ndim, cls):
+    """(x, y, z) extent of tile class `cls` of the lattice passes in dimension ndim."""
+    out = (C.c_int32 * 3)()
+    _check(load().ihmc_tile_shape(int(ndim), int(cls), out, None))
+    return tuple(out)
+
+
+def tile_class_count(ndim):
+    n = C.c_int32()
+    _check(load().ihmc_tile_shape(int(ndim), 0, None, C.byref(n)))
+    return n.value
+
+
+def check_tuning(path):
+    """Parse a saved tile-class table (no GPU needed); returns its number of entries."""
+    n = C.c_int32()
+    _check(load().ihmc_tune_check(os.fsencode(path), C.byref(n)))
+    return n.value
 
 
 def _f64(a):
@@ -316,6 +348,41 @@ class Context:
         _check(load().ihmc_ctx_memory(self.h, C.byref(u), C.byref(t)))
         return u.value, t.value
 
+    # ---- tile autotuner
+    def tune(self, lats, precision=F32, sites=0, reps=0, force=False):
+        """Time every tile class on each distinct lattice shape and keep the fastest
+        for chains created afterwards; returns the number of shapes measured.
+        `sites`: working set of the timed launches (0: the total sites of `lats`)."""
+        keep = []
+        n = len(lats)
+        prec = [precision] * n if isinstance(precision, int) else list(precision)
+        la = (_Lattice * n)(*[l._c(keep) for l in lats])
+        pa = (C.c_int32 * n)(*prec)
+        got = C.c_int32()
+        _check(load().ihmc_tune(self.h, n, la, pa, int(sites), int(reps), 1 if force else 0, C.byref(got)))
+        return got.value
+
+    def tile_class(self, lat: Lattice, precision=F32):
+        """{'cls', 'source', 'ns_per_site'} of the tile class chains of `lat` take here."""
+        keep = []
+        s = lat._c(keep)
+        cls, src = C.c_int32(), C.c_int32()
+        ns = (C.c_double * 3)()
+        _check(load().ihmc_tune_lookup(self.h, C.byref(s), int(precision), C.byref(cls), C.byref(src), ns))
+        return {"cls": cls.value, "source": src.value, "ns_per_site": list(ns)}
+
+    def pin_tile(self, lat: Lattice, cls, precision=F32):
+        """Force tile class `cls` for chains of `lat` (cls < 0: back to the built-in rule)."""
+        keep = []
+        s = lat._c(keep)
+        _check(load().ihmc_tune_pin(self.h, C.byref(s), int(precision), int(cls)))
+
+    def save_tuning(self, path):
+        _check(load().ihmc_tune_save(self.h, os.fsencode(path)))
+
+    def load_tuning(self, path):
+        _check(load().ihmc_tune_load(self.h, os.fsencode(path)))
+
     # ---- whole runs
     def run_lattice(self, lat: Lattice, run: Run, want_psi=True):
         return self.run_batch([lat], [run], want_psi)[0]
@@ -433,6 +500,12 @@ class Chains:
         n = C.c_int32()
         _check(load().ihmc_chains_groups(self.h, C.byref(n)))
         return n.value
+
+    def group_info(self, group):
+        """{'precision', 'ndim', 'cls', 'chains', 'sites', 'tiles'} of a launch group."""
+        out = (C.c_int64 * 6)()
+        _check(load().ihmc_chains_group_info(self.h, int(group), out))
+        return dict(zip(("precision", "ndim", "cls", "chains", "sites", "tiles"), (int(v) for v in out)))
 
     def time_pass(self, group, mode=1, reps=50):
         """Mean duration (us) of one fused pass launch of a group, timed with HIP events."""

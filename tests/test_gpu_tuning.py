@@ -1,0 +1,140 @@
+"""Tile autotuner on the GPU: every tile class gives bitwise the same chains, and
+the tuner measures, stores, pins, saves and reloads its choices."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+SERIES = ("dH", "H_old", "H_new", "m", "abs_m", "m2c", "beta_eps", "accepted", "flipped", "psi_final")
+
+
+@pytest.fixture(scope="module")
+def ih():
+    from paper_1912_03278_amd import ihmc
+    return ihmc
+
+
+def lattices(ih):
+    rng = np.random.default_rng(11)
+    return [
+        (ih.Lattice((20, 20), beta=0.44, C=4.1), ih.F32),
+        (ih.Lattice((37, 45), beta=0.40, C=4.1, h=rng.normal(0, 0.05, 37 * 45)), ih.F32),
+        (ih.Lattice((70, 66), beta=0.44, C=4.1, h=0.02), ih.F32),
+        (ih.Lattice((131, 17), beta=0.35, C=4.3), ih.F32),
+        (ih.Lattice((17, 17, 17), beta=0.22, C=6.1), ih.F32),
+        (ih.Lattice((20, 12, 9), beta=0.25, C=6.1, h=rng.normal(0, 0.05, 20 * 12 * 9)), ih.F32),
+        (ih.Lattice((36, 20), beta=0.44, C=4.1), ih.F64),
+        (ih.Lattice((18, 9, 11), beta=0.22, C=6.1), ih.F64),
+    ]
+
+
+@pytest.mark.parametrize("k", range(8))
+def test_every_tile_class_gives_bitwise_equal_chains(ih, k):
+    lat, prec = lattices(ih)[k]
+    nd = len(lat.L)
+    run = ih.Run(n_md=7, n_traj=6, precision=prec, seed=5 + k, chain_id=k, flip_every=2)
+    with ih.Context(arena_bytes=256 << 20) as ctx:
+        outs = []
+        for cls in range(ih.tile_class_count(nd)):
+            ctx.pin_tile(lat, cls, prec)
+            assert ctx.tile_class(lat, prec)["cls"] == cls
+            assert ctx.tile_class(lat, prec)["source"] == ih.TUNE_PINNED
+            outs.append(ctx.run_lattice(lat, run))
+    ref = outs[0]
+    assert ref["n_traj_done"] == 6 and np.all(np.isfinite(ref["dH"]))
+    for cls, o in enumerate(outs[1:], 1):
+        for key in SERIES:
+            assert np.array_equal(o[key], ref[key]), (lat.L, cls, key)
+
+
+def test_mixed_classes_in_one_batch_equal_alone(ih):
+    """Chains of one shape pinned to different classes cannot share a launch
+    group; a batch mixing classes (several groups) equals each chain alone."""
+    lat_a = ih.Lattice((40, 40), beta=0.44, C=4.1)
+    lat_b = ih.Lattice((40, 41), beta=0.44, C=4.1)
+    lat_c = ih.Lattice((18, 18, 18), beta=0.22, C=6.1)
+    lats = [lat_a, lat_b, lat_c, lat_a]
+    runs = [ih.Run(n_md=5 + i, n_traj=4, seed=30 + i, chain_id=i) for i in range(4)]
+    with ih.Context(arena_bytes=256 << 20) as ctx:
+        ctx.pin_tile(lat_a, 0)
+        ctx.pin_tile(lat_b, 2)
+        ctx.pin_tile(lat_c, 1)
+        ch = ih.Chains(ctx, lats, runs)
+        assert ch.groups() == 3
+        ch.advance(4)
+        got = [ch.result(i) for i in range(4)]
+        ch.close()
+        ctx.pin_tile(lat_a, -1)
+        ctx.pin_tile(lat_b, -1)
+        ctx.pin_tile(lat_c, -1)
+        assert ctx.tile_class(lat_a)["source"] == ih.TUNE_RULE
+        alone = [ctx.run_lattice(l, r) for l, r in zip(lats, runs)]
+    for i in range(4):
+        for key in SERIES:
+            assert np.array_equal(got[i][key], alone[i][key]), (i, key)
+
+
+def test_tune_measures_pins_and_round_trips(ih, tmp_path, monkeypatch):
+    shapes = [ih.Lattice((24, 24), beta=0.44, C=4.1), ih.Lattice((72, 72), beta=0.44, C=4.1, h=0.01),
+              ih.Lattice((20, 20, 20), beta=0.22, C=6.1)]
+    pinned = ih.Lattice((100, 100), beta=0.44, C=4.1)
+    path = tmp_path / "tiles.json"
+    monkeypatch.setenv("IHMC_TUNE_CACHE", str(path))
+    with ih.Context(arena_bytes=1 << 30) as ctx:
+        ctx.pin_tile(pinned, 1)
+        # h = scalar and h absent share a key (only a per-site field changes the pass)
+        assert ctx.tune(shapes + [pinned, ih.Lattice((72, 72), beta=0.3, C=4.5)], reps=3) == 3
+        table = {}
+        for lat in shapes:
+            t = ctx.tile_class(lat)
+            nc = ih.tile_class_count(len(lat.L))
+            assert t["source"] == ih.TUNE_MEASURED
+            assert 0 <= t["cls"] < nc
+            ns = t["ns_per_site"]
+            assert all(0 < ns[c] < 10 for c in range(nc)), ns
+            assert all(math.isnan(ns[c]) for c in range(nc, 3))
+            # the choice is the fastest class, or the built-in one within 3 %
+            assert ns[t["cls"]] <= 1.03 * min(ns[:nc])
+            table[lat.L] = t
+        assert ctx.tile_class(pinned)["cls"] == 1 and ctx.tile_class(pinned)["source"] == ih.TUNE_PINNED
+        # nothing new to measure; force re-measures the measured keys, not the pinned one
+        assert ctx.tune(shapes, reps=3) == 0
+        assert ctx.tune(shapes + [pinned], reps=3, force=True) == 3
+        assert ctx.tile_class(pinned)["source"] == ih.TUNE_PINNED
+        chosen = {lat.L: ctx.tile_class(lat)["cls"] for lat in shapes}
+    # the cache file was written by tune and is read by a new context
+    assert path.exists() and ih.check_tuning(str(path)) == 4
+    with ih.Context(arena_bytes=64 << 20) as ctx2:
+        for lat in shapes:
+            assert ctx2.tile_class(lat)["cls"] == chosen[lat.L]
+            assert ctx2.tile_class(lat)["source"] == ih.TUNE_MEASURED
+        assert ctx2.tile_class(pinned)["source"] == ih.TUNE_PINNED
+    # explicit save / load without the environment variable
+    monkeypatch.delenv("IHMC_TUNE_CACHE")
+    with ih.Context(arena_bytes=64 << 20) as ctx3:
+        assert ctx3.tile_class(shapes[0])["source"] == ih.TUNE_RULE
+        ctx3.load_tuning(str(path))
+        assert ctx3.tile_class(shapes[0])["cls"] == chosen[shapes[0].L]
+        out = tmp_path / "copy.json"
+        ctx3.save_tuning(str(out))
+        assert ih.check_tuning(str(out)) == 4
+
+
+def test_tune_rejects_bad_input(ih, tmp_path, monkeypatch):
+    monkeypatch.delenv("IHMC_TUNE_CACHE", raising=False)
+    with ih.Context(arena_bytes=64 << 20) as ctx:
+        with pytest.raises(ih.IhmcError):
+            ctx.tune([ih.Lattice((16, 16), beta=0.44, C=3.9)])  # C <= 2d
+        with pytest.raises(ih.IhmcError):
+            ctx.pin_tile(ih.Lattice((16, 16), beta=0.44, C=4.1), 3)
+        with pytest.raises(ih.IhmcError):
+            ctx.load_tuning(str(tmp_path / "absent.json"))
+        # a shape whose replicas do not fit the arena fails cleanly and leaves the context usable
+        with pytest.raises(ih.IhmcError) as e:
+            ctx.tune([ih.Lattice((2048, 2048), beta=0.44, C=4.1)])
+        assert e.value.code == -2
+        r = ctx.run_lattice(ih.Lattice((16, 16), beta=0.44, C=4.1), ih.Run(n_md=4, n_traj=2))
+        assert r["n_traj_done"] == 2
