@@ -29,9 +29,13 @@
 namespace ihmc {
 
 __device__ __forceinline__ int wrap_near(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
+// v mod L in [0, L) for |v| < 2^22 (lattice coordinates plus a halo): the
+// quotient from FP32, exact to within one, then corrected in integers.
 __device__ __forceinline__ int wrap_any(int v, int L) {
-  const int r = v % L;
-  return r < 0 ? r + L : r;
+  const int q = (int)floorf((float)v * __builtin_amdgcn_rcpf((float)L));
+  int r = v - q * L;
+  r = r < 0 ? r + L : r;
+  return r >= L ? r - L : r;
 }
 
 template <typename T>
@@ -59,6 +63,88 @@ __device__ __forceinline__ void ld4<double>(const double* __restrict__ p, double
   v[2] = b.x;
   v[3] = b.y;
 }
+// The state arrays that the chain table points to live in global memory.
+// Accessing them through pointers of the global address space lets the
+// compiler use global rather than flat memory instructions: a flat access
+// counts as an LDS access too, so every wait for LDS data would also wait for
+// the global loads still in flight.
+template <class T>
+using gmem = __attribute__((address_space(1))) T;
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef double vd2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ void ld4g(const gmem<T>* p, T (&v)[4]);
+template <>
+__device__ __forceinline__ void ld4g<float>(const gmem<float>* p, float (&v)[4]) {
+  const vf4 q = *(const gmem<vf4>*)p;
+  v[0] = q.x;
+  v[1] = q.y;
+  v[2] = q.z;
+  v[3] = q.w;
+}
+template <>
+__device__ __forceinline__ void ld4g<double>(const gmem<double>* p, double (&v)[4]) {
+  const vd2 a = ((const gmem<vd2>*)p)[0];
+  const vd2 b = ((const gmem<vd2>*)p)[1];
+  v[0] = a.x;
+  v[1] = a.y;
+  v[2] = b.x;
+  v[3] = b.y;
+}
+template <typename T>
+__device__ __forceinline__ void st4g(gmem<T>* p, const T (&v)[4]);
+template <>
+__device__ __forceinline__ void st4g<float>(gmem<float>* p, const float (&v)[4]) {
+  *(gmem<vf4>*)p = vf4{v[0], v[1], v[2], v[3]};
+}
+template <>
+__device__ __forceinline__ void st4g<double>(gmem<double>* p, const double (&v)[4]) {
+  ((gmem<vd2>*)p)[0] = vd2{v[0], v[1]};
+  ((gmem<vd2>*)p)[1] = vd2{v[2], v[3]};
+}
+
+// Where a staging thread finds its 4-element chunk x .. x+3 of every row it
+// loads (x a multiple of 4, at least -4 and, when x_near, below 2 L0 - 4;
+// x_near says every x + e lies within one period of [0, L0)): one aligned
+// vector load at xv, or, for a chunk that straddles the periodic wrap, the
+// four wrapped positions xe.  A wrapped chunk is still one vector load when L0
+// is a multiple of 4.  Worked out once per thread, used for all its rows.
+struct ChunkPos {
+  int xv;
+  bool vec;
+  int xe[4];
+};
+__device__ __forceinline__ ChunkPos chunk_pos(int x, int L0, bool x_near) {
+  ChunkPos cp;
+  const int xs = x_near ? wrap_near(x, L0) : x;
+  cp.vec = xs >= 0 && xs + 4 <= L0 && (xs & 3) == 0;
+  cp.xv = cp.vec ? xs : 0;
+  int xe = x_near ? xs : wrap_any(x, L0);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    cp.xe[e] = xe;
+    xe = (xe + 1 == L0) ? 0 : xe + 1;
+  }
+  return cp;
+}
+
+// Every lane issues the vector load (a gathering lane from the row start, and
+// discards it), so that the compiler keeps it one 16-byte access.
+template <typename T>
+__device__ __forceinline__ void load_chunk(const gmem<T>* row, const ChunkPos& cp, T (&v)[4]) {
+  ld4g<T>(row + cp.xv, v);
+  if (!cp.vec) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = row[cp.xe[e]];
+  }
+}
+
+// Element offset of a row from its index and the row pitch (both non-negative).
+__device__ __forceinline__ uint64_t row_offset(int idx, int64_t stride) {
+  return (uint64_t)(uint32_t)idx * (uint64_t)stride;
+}
+
 template <typename T>
 __device__ __forceinline__ void st4(T* __restrict__ p, const T (&v)[4]);
 template <>
@@ -154,9 +240,9 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
   const bool from_cur = (MODE == PASS_FIRST || MODE == PASS_MEASURE || MODE == PASS_FORCE);
   const int in_buf = from_cur ? cur : pass_in_buf(cur, j);
   const int out_buf = pass_out_buf(cur, j);
-  const T* __restrict__ pin = (const T*)cd.psi + (int64_t)in_buf * NP;
-  T* __restrict__ pout = (T*)cd.psi + (int64_t)out_buf * NP;
-  T* __restrict__ pmom = (T*)cd.p;
+  const gmem<T>* __restrict__ pin = (const gmem<T>*)cd.psi + (int64_t)in_buf * NP;
+  gmem<T>* __restrict__ pout = (gmem<T>*)cd.psi + (int64_t)out_buf * NP;
+  gmem<T>* __restrict__ pmom = (gmem<T>*)cd.p;
   const bool site_field = (cd.h_kind == 2);
 
   const int t = threadIdx.x;
@@ -171,31 +257,43 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
   const T b_uniform = (T)cd.b0;
   bq[0] = bq[1] = bq[2] = bq[3] = b_uniform;
   if (quad_ok) {
-    if (MODE == PASS_MIDDLE || MODE == PASS_LAST || (MODE == PASS_FIRST && cd.p_given)) ld4<T>(pmom + base, pq);
-    if (kHasW && site_field) ld4<T>((const T*)cd.b + base, bq);
+    if (MODE == PASS_MIDDLE || MODE == PASS_LAST || (MODE == PASS_FIRST && cd.p_given)) ld4g<T>(pmom + base, pq);
+    if (kHasW && site_field) ld4g<T>((const gmem<T>*)cd.b + base, bq);
   }
 
   // ---- stage psi on the tile plus its halo, in aligned 4-element chunks:
   // a chunk inside [0, L0) is one vector load, a chunk crossing the periodic
   // wrap (or the row end) is gathered element by element.
-  const bool rows_near = (L1 > BY);
-  for (int i = t; i < PR * NCH; i += NT) {
-    const int r = i / NCH, c = i % NCH;
-    const int yy = rows_near ? wrap_near(tl.y0 + r - 2, L1) : wrap_any(tl.y0 + r - 2, L1);
-    const T* row = pin + (int64_t)pitch * yy;
-    const int x = tl.x0 - 4 + 4 * c;
-    T v[4];
-    if (x >= 0 && x + 4 <= L0) {
-      ld4<T>(row + x, v);
-    } else {
+  // Thread t loads chunk column t % NCH of the rows t / NCH + RG k; all its
+  // loads are issued before its LDS stores.
+  const bool rows_near = (L1 > BY), x_near = (L0 > BX + 2);
+  {
+    constexpr int RG = NT / NCH;
+    constexpr int NRPT = (PR + RG - 1) / RG;
+    const int c = t % NCH, rg = t / NCH;
+    if (rg < RG) {
+      const ChunkPos cp = chunk_pos(tl.x0 - 4 + 4 * c, L0, x_near);
+      T v[NRPT][4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) v[e] = row[wrap_any(x + e, L0)];
-    }
-    if (from_cur) {
+      for (int k = 0; k < NRPT; ++k) {
+        const int r = rg + RG * k;
+        if (r < PR) {
+          const int yy = rows_near ? wrap_near(tl.y0 + r - 2, L1) : wrap_any(tl.y0 + r - 2, L1);
+          load_chunk<T>(pin + row_offset(yy, pitch), cp, v[k]);
+        }
+      }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) v[e] = neg_if(v[e], sign);
+      for (int k = 0; k < NRPT; ++k) {
+        const int r = rg + RG * k;
+        if (r < PR) {
+          if (from_cur) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[k][e] = neg_if(v[k][e], sign);
+          }
+          st4<T>(sP + r * RP + 4 * c, v[k]);
+        }
+      }
     }
-    st4<T>(sP + r * RP + 4 * c, v);
   }
   __syncthreads();
 
@@ -297,10 +395,10 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
       for (int a = 0; a < 4; ++a) qs[T_S + a] = quad_sum(ht[0][a], ht[1][a], ht[2][a], ht[3][a]);
     }
     if (MODE == PASS_FIRST || MODE == PASS_MIDDLE) {
-      st4<T>(pmom + base, pn);
-      st4<T>(pout + base, pv);
+      st4g<T>(pmom + base, pn);
+      st4g<T>(pout + base, pv);
     } else if (MODE == PASS_FORCE || (MODE == PASS_LAST && cd.write_p_last)) {
-      st4<T>(pmom + base, pn);
+      st4g<T>(pmom + base, pn);
     }
   }
 
@@ -318,23 +416,31 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
   block_accumulate<MODE, NWAVE>(cd, st, acc, bad, cur, j, tix);
 }
 
-// --------------------------------------------------------------------- 3D ---
+// ------------------------------------------------------------ 3D, one phase ---
 //
-// A 2.5D stream: a block owns a BX x BY column of the xy plane and walks z
-// over [z0, z0 + ZR).  A ring of five psi planes (2-wide xy halo) and three w
-// planes (1-wide halo) stays in LDS, so each psi value is read (ZR + 4) / ZR
-// times and each w computed (BX+2)(BY+2)/(BX BY) times.  Step z computes
-// w(z+1) and the update of plane z while the loads of plane z+3 are in flight.
+// A block owns a BX x BY x ZR box, one x-y column per thread, ZR sites deep.
+// psi on the box plus its 2-wide halo is staged in LDS in one phase, in
+// aligned 4-element chunks (rows of RP = BX + 8 values with lattice x at
+// x - x0 + 4, as in 2D), so every load of the block is in flight at once; w on
+// the box plus its 1-wide halo follows in quads (the outermost quad of a row is
+// unused), then each thread updates its column plane by plane.  The column's
+// momenta and field values are fetched before the staging.  Sums of the FP64
+// terms follow the same order as in every other tiling: per column over the
+// ZR planes in z order, then per x-aligned quad of columns.
 template <typename T, int BX, int BY, int ZR, int MODE>
-__global__ __launch_bounds__(256) void lattice_pass3s(const ChainDev* __restrict__ chains,
+__global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict__ chains,
                                                       const Tile* __restrict__ tiles, int n_tiles, int j) {
-  constexpr int PX = BX + 4, PY = BY + 4, PP = PX * PY;
-  constexpr int WX = BX + 2, WY = BY + 2, WP = WX * WY;
-  constexpr int NO = BX * BY;
+  constexpr int RP = BX + 8;
+  constexpr int NCH = RP / 4;  // 16-byte chunks per staged row
+  constexpr int PR = BY + 4, PZ = ZR + 4;
+  constexpr int WR = BY + 2, WZ = ZR + 2;
+  constexpr int PPL = PR * RP, WPL = WR * RP;
+  constexpr int NWC = WZ * WR * NCH;  // w chunks
   constexpr bool kHasW = (MODE != PASS_MEASURE);
   constexpr bool kH64 = (MODE == PASS_LAST || MODE == PASS_MEASURE);
-  __shared__ T sP[5][PP];
-  __shared__ T sW[kHasW ? 3 : 1][kHasW ? WP : 1];
+  static_assert(BX * BY == 256 && BX % 4 == 0, "one column per thread");
+  __shared__ __align__(16) T sP[PZ * PPL];
+  __shared__ __align__(16) T sW[kHasW ? WZ * WPL : 4];
 
   const Tile tl = tiles[xcd_tile(blockIdx.x, n_tiles)];
   const ChainDev& cd = chains[tl.chain];
@@ -348,100 +454,15 @@ __global__ __launch_bounds__(256) void lattice_pass3s(const ChainDev* __restrict
   const bool from_cur = (MODE == PASS_FIRST || MODE == PASS_MEASURE || MODE == PASS_FORCE);
   const int in_buf = from_cur ? cur : pass_in_buf(cur, j);
   const int out_buf = pass_out_buf(cur, j);
-  const T* __restrict__ pin = (const T*)cd.psi + (int64_t)in_buf * NP;
-  T* __restrict__ pout = (T*)cd.psi + (int64_t)out_buf * NP;
-  T* __restrict__ pmom = (T*)cd.p;
+  const gmem<T>* __restrict__ pin = (const gmem<T>*)cd.psi + (int64_t)in_buf * NP;
+  gmem<T>* __restrict__ pout = (gmem<T>*)cd.psi + (int64_t)out_buf * NP;
+  gmem<T>* __restrict__ pmom = (gmem<T>*)cd.p;
   const int z_end = min(tl.z0 + ZR, L2);
-  const bool near_xy = (L0 > BX) && (L1 > BY);
-
-  const T Ct = (T)cd.C;
-  const T at = (T)cd.sqJ;
-  double kick_d = 0.0, drift_d = 0.0;
-  pass_coeffs(cd, j, kick_d, drift_d);
-  const T kick = (MODE == PASS_FORCE) ? (T)1 : (T)kick_d;
-  const T drift = (T)drift_d;
   const T b_uniform = (T)cd.b0;
-  const T* __restrict__ bsite = (const T*)cd.b;
+  const gmem<T>* __restrict__ bsite = (const gmem<T>*)cd.b;
   const bool site_field = (cd.h_kind == 2);
 
-  // Plane z (any integer in [z0-2, z_end+2]) of psi: fetch_plane issues the
-  // global loads into registers, store_plane moves them to ring slot
-  // (z - z0 + 2) % 5.
-  constexpr int NPRE = (PP + 255) / 256;
-  auto fetch_plane = [&](int z, T(&pre)[NPRE]) {
-    const int gz = wrap_any(z, L2);
-    const T* src = pin + (int64_t)gz * plane;
-#pragma unroll
-    for (int k = 0; k < NPRE; ++k) {
-      const int i = threadIdx.x + 256 * k;
-      if (i < PP) {
-        const int lx = i % PX, ly = i / PX;
-        int gx = tl.x0 + lx - 2, gy = tl.y0 + ly - 2;
-        if (near_xy) {
-          gx = wrap_near(gx, L0);
-          gy = wrap_near(gy, L1);
-        } else {
-          gx = wrap_any(gx, L0);
-          gy = wrap_any(gy, L1);
-        }
-        T v = src[gx + (int64_t)pitch * gy];
-        if (from_cur) v = neg_if(v, sign);
-        pre[k] = v;
-      }
-    }
-  };
-  auto store_plane = [&](int z, const T(&pre)[NPRE]) {
-    T* dst = sP[(z - tl.z0 + 2) % 5];
-#pragma unroll
-    for (int k = 0; k < NPRE; ++k) {
-      const int i = threadIdx.x + 256 * k;
-      if (i < PP) dst[i] = pre[k];
-    }
-  };
-  // w on plane z from psi planes z-1, z, z+1
-  auto compute_w = [&](int z) {
-    const T* __restrict__ pm = sP[(z - 1 - tl.z0 + 2) % 5];
-    const T* __restrict__ pc = sP[(z - tl.z0 + 2) % 5];
-    const T* __restrict__ pp = sP[(z + 1 - tl.z0 + 2) % 5];
-    T* __restrict__ w = sW[(z - tl.z0 + 3) % 3];
-    for (int i = threadIdx.x; i < WP; i += 256) {
-      const int wx = i % WX, wy = i / WX;
-      const int c = (wx + 1) + PX * (wy + 1);
-      const T v = pc[c];
-      T sum = (pc[c - 1] + pc[c + 1]) + (pc[c - PX] + pc[c + PX]);
-      sum = sum + (pm[c] + pp[c]);
-      const T u = fma_t(Ct, v, sum);
-      w[i] = fma_t(at, tanh_state(at * u), -v);
-    }
-  };
-
-  // FP64 sums of the thread's column over the tile's planes (in z order); the
-  // column sums of four x-aligned columns form a quad that is converted to
-  // fixed point once, after the plane loop.  Tiles are aligned ZR-plane slabs,
-  // so the grouping is the same in every tiling.
-  uint32_t bad = 0u;
-  double hs[NTERM];
-#pragma unroll
-  for (int a = 0; a < NTERM; ++a) hs[a] = 0.0;
-
-  // prologue: psi planes z0-2 .. z0+2 in LDS, w planes z0-1, z0
-  {
-    T pre[5][NPRE];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) fetch_plane(tl.z0 - 2 + q, pre[q]);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) store_plane(tl.z0 - 2 + q, pre[q]);
-  }
-  __syncthreads();
-  if (kHasW) {
-    compute_w(tl.z0 - 1);
-    compute_w(tl.z0);
-  }
-
-  // Each thread owns one column (lx, ly) of the tile; its momentum and field
-  // values are loaded one plane ahead, so their latency overlaps the w planes
-  // and the barrier of the step before.
-  static_assert(NO == 256, "one column per thread");
+  // ---- the column's momenta and field values
   const int lx = threadIdx.x % BX, ly = threadIdx.x / BX;
   const int gx = tl.x0 + lx, gy = tl.y0 + ly;
   const bool act = (gx < L0) && (gy < L1);
@@ -449,81 +470,147 @@ __global__ __launch_bounds__(256) void lattice_pass3s(const ChainDev* __restrict
   constexpr bool kLoadP = (MODE == PASS_MIDDLE || MODE == PASS_LAST || MODE == PASS_FIRST);
   const bool load_p = kLoadP && act && (MODE != PASS_FIRST || cd.p_given);
   const bool load_b = kHasW && act && site_field;
-  T p_next = (T)0, b_next = b_uniform;
-  if (load_p) p_next = pmom[col + plane * tl.z0];
-  if (load_b) b_next = bsite[col + plane * tl.z0];
+  T pcol[ZR], bcol[ZR];
+#pragma unroll
+  for (int k = 0; k < ZR; ++k) {
+    pcol[k] = (T)0;
+    bcol[k] = b_uniform;
+    if (tl.z0 + k < z_end) {
+      if (load_p) pcol[k] = pmom[col + plane * (tl.z0 + k)];
+      if (load_b) bcol[k] = bsite[col + plane * (tl.z0 + k)];
+    }
+  }
 
-  for (int z = tl.z0; z < z_end; ++z) {
-    // w(z+1) needs psi planes z .. z+2 (in LDS); plane z+3 is fetched meanwhile
-    T pre[NPRE];
-    const bool more = (z + 1 < z_end);
-    const T p_here = p_next, b_here = b_next;
-    if (more && load_p) p_next = pmom[col + plane * (z + 1)];
-    if (more && load_b) b_next = bsite[col + plane * (z + 1)];
-    if (more) fetch_plane(z + 3, pre);
-    if (kHasW) compute_w(z + 1);
-    __syncthreads();
-    const T* __restrict__ pm = sP[(z - 1 - tl.z0 + 2) % 5];
-    const T* __restrict__ pc = sP[(z - tl.z0 + 2) % 5];
-    const T* __restrict__ pp = sP[(z + 1 - tl.z0 + 2) % 5];
-    const T* __restrict__ wm = sW[kHasW ? (z - 1 - tl.z0 + 3) % 3 : 0];
-    const T* __restrict__ wc = sW[kHasW ? (z - tl.z0 + 3) % 3 : 0];
-    const T* __restrict__ wp = sW[kHasW ? (z + 1 - tl.z0 + 3) % 3 : 0];
-    static_assert(BX % 4 == 0, "3D tile shape");
-    {
-      const int64_t idx = col + plane * z;
-      const int c = (lx + 2) + PX * (ly + 2);
-      const T v = pc[c];
-      double kin = 0.0;
-      if (kHasW && act) {
-        const int q = (lx + 1) + WX * (ly + 1);
-        T sw = (wc[q - 1] + wc[q + 1]) + (wc[q - WX] + wc[q + WX]);
-        sw = sw + (wm[q] + wp[q]);
-        T F = fma_t(Ct, wc[q], sw);
-        F = F + b_here;
-        T p;
-        if (MODE == PASS_FIRST) {
-          if (cd.p_given) {
-            p = p_here;
-          } else {
-            const int64_t site = gx + (int64_t)L0 * (gy + (int64_t)L1 * z);
-            T z0, z1;
-            normal_pair<T>(cd, (uint32_t)traj, TAG_MOM, site >> 1, z0, z1);
-            p = (site & 1) ? z1 : z0;
-          }
-          const double pd = (double)p;
-          kin = 0.5 * pd * pd;
-        } else if (MODE == PASS_FORCE) {
-          p = (T)0;
-        } else {
-          p = p_here;
-        }
-        const T pn = fma_t(kick, F, p);
-        if (MODE == PASS_FIRST || MODE == PASS_MIDDLE) {
-          pmom[idx] = pn;
-          pout[idx] = fma_t(drift, pn, v);
-        } else if (MODE == PASS_FORCE) {
-          pmom[idx] = pn;
-        } else if (MODE == PASS_LAST) {
-          if (cd.write_p_last) pmom[idx] = pn;
-          const double pd = (double)pn;
-          kin = 0.5 * pd * pd;
+  // ---- stage psi on the box plus its halo: thread t loads chunk column
+  // t % NCH of the staged rows (plane-major) t / NCH + RG k; all its loads are
+  // issued before its LDS stores
+  const bool rows_near = (L1 > BY), planes_near = (L2 > ZR), x_near = (L0 > BX + 2);
+  {
+    constexpr int NROW = PZ * PR;
+    constexpr int RG = 256 / NCH;
+    constexpr int NRPT = (NROW + RG - 1) / RG;
+    const int c = threadIdx.x % NCH, rg = threadIdx.x / NCH;
+    if (rg < RG) {
+      const ChunkPos cp = chunk_pos(tl.x0 - 4 + 4 * c, L0, x_near);
+      T v[NRPT][4];
+#pragma unroll
+      for (int k = 0; k < NRPT; ++k) {
+        const int R = rg + RG * k;
+        if (R < NROW) {
+          const int pz = R / PR, r = R - pz * PR;
+          const int zz = planes_near ? wrap_near(tl.z0 + pz - 2, L2) : wrap_any(tl.z0 + pz - 2, L2);
+          const int yy = rows_near ? wrap_near(tl.y0 + r - 2, L1) : wrap_any(tl.y0 + r - 2, L1);
+          load_chunk<T>(pin + row_offset(zz, plane) + row_offset(yy, pitch), cp, v[k]);
         }
       }
-      if (MODE == PASS_FIRST) hs[T_K0] = hs[T_K0] + kin;
-      if (MODE == PASS_LAST) hs[T_K1] = hs[T_K1] + kin;
-      if (kH64) {
-        double ht[4];
-        double nb = ((double)pc[c - 1] + (double)pc[c + 1]) + ((double)pc[c - PX] + (double)pc[c + PX]);
-        nb = nb + ((double)pm[c] + (double)pp[c]);
-        h_terms(cd, (double)v, nb, act ? idx : 0, act, ht);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) hs[T_S + a] = hs[T_S + a] + ht[a];
+      for (int k = 0; k < NRPT; ++k) {
+        const int R = rg + RG * k;
+        if (R < NROW) {
+          if (from_cur) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[k][e] = neg_if(v[k][e], sign);
+          }
+          st4<T>(sP + R * RP + 4 * c, v[k]);
+        }
       }
     }
-    // plane z+3 replaces plane z-2, which no later step reads
-    if (more) store_plane(z + 3, pre);
+  }
+  __syncthreads();
+
+  const T Ct = (T)cd.C;
+  const T at = (T)cd.sqJ;
+
+  // ---- w on the box plus its 1-wide halo, in quads over x in [-4, BX+4)
+  if (kHasW) {
+    for (int i = threadIdx.x; i < NWC; i += 256) {
+      const int wz = i / (WR * NCH), rem = i - wz * (WR * NCH);
+      const int wy = rem / NCH, c = rem - wy * NCH;
+      const int pc = (wz + 1) * PPL + (wy + 1) * RP + 4 * c;  // psi at (x0 - 4 + 4c, y0 - 1 + wy, z0 - 1 + wz)
+      T cv[4], up[4], dn[4], zm[4], zp[4], w[4];
+      ld4<T>(sP + pc, cv);
+      ld4<T>(sP + pc - RP, up);
+      ld4<T>(sP + pc + RP, dn);
+      ld4<T>(sP + pc - PPL, zm);
+      ld4<T>(sP + pc + PPL, zp);
+      const T lft = sP[pc - 1], rgt = sP[pc + 4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const T xm = (e == 0) ? lft : cv[e - 1];
+        const T xp = (e == 3) ? rgt : cv[e + 1];
+        T sum = (xm + xp) + (up[e] + dn[e]);
+        sum = sum + (zm[e] + zp[e]);
+        const T u = fma_t(Ct, cv[e], sum);
+        w[e] = fma_t(at, tanh_state(at * u), -cv[e]);
+      }
+      st4<T>(sW + wz * WPL + wy * RP + 4 * c, w);
+    }
     __syncthreads();
+  }
+
+  double kick_d = 0.0, drift_d = 0.0;
+  pass_coeffs(cd, j, kick_d, drift_d);
+  const T kick = (MODE == PASS_FORCE) ? (T)1 : (T)kick_d;
+  const T drift = (T)drift_d;
+
+  uint32_t bad = 0u;
+  double hs[NTERM];
+#pragma unroll
+  for (int a = 0; a < NTERM; ++a) hs[a] = 0.0;
+
+#pragma unroll
+  for (int k = 0; k < ZR; ++k) {
+    const int z = tl.z0 + k;
+    if (z >= z_end) break;
+    const int64_t idx = col + plane * z;
+    const int c = (k + 2) * PPL + (ly + 2) * RP + lx + 4;
+    const T v = sP[c];
+    double kin = 0.0;
+    if (kHasW && act) {
+      const int q = (k + 1) * WPL + (ly + 1) * RP + lx + 4;
+      T sw = (sW[q - 1] + sW[q + 1]) + (sW[q - RP] + sW[q + RP]);
+      sw = sw + (sW[q - WPL] + sW[q + WPL]);
+      T F = fma_t(Ct, sW[q], sw);
+      F = F + bcol[k];
+      T p;
+      if (MODE == PASS_FIRST) {
+        if (cd.p_given) {
+          p = pcol[k];
+        } else {
+          const int64_t site = gx + (int64_t)L0 * (gy + (int64_t)L1 * z);
+          T z0, z1;
+          normal_pair<T>(cd, (uint32_t)traj, TAG_MOM, site >> 1, z0, z1);
+          p = (site & 1) ? z1 : z0;
+        }
+        const double pd = (double)p;
+        kin = 0.5 * pd * pd;
+      } else if (MODE == PASS_FORCE) {
+        p = (T)0;
+      } else {
+        p = pcol[k];
+      }
+      const T pn = fma_t(kick, F, p);
+      if (MODE == PASS_FIRST || MODE == PASS_MIDDLE) {
+        pmom[idx] = pn;
+        pout[idx] = fma_t(drift, pn, v);
+      } else if (MODE == PASS_FORCE) {
+        pmom[idx] = pn;
+      } else if (MODE == PASS_LAST) {
+        if (cd.write_p_last) pmom[idx] = pn;
+        const double pd = (double)pn;
+        kin = 0.5 * pd * pd;
+      }
+    }
+    if (MODE == PASS_FIRST) hs[T_K0] = hs[T_K0] + kin;
+    if (MODE == PASS_LAST) hs[T_K1] = hs[T_K1] + kin;
+    if (kH64) {
+      double ht[4];
+      double nb = ((double)sP[c - 1] + (double)sP[c + 1]) + ((double)sP[c - RP] + (double)sP[c + RP]);
+      nb = nb + ((double)sP[c - PPL] + (double)sP[c + PPL]);
+      h_terms(cd, (double)v, nb, act ? idx : 0, act, ht);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) hs[T_S + a] = hs[T_S + a] + ht[a];
+    }
   }
 
   if (MODE == PASS_MIDDLE || MODE == PASS_FORCE) return;
@@ -571,25 +658,25 @@ static hipError_t launch_mode2v(int mode, const ChainDev* chains, const Tile* ti
 }
 
 template <typename T, int BX, int BY, int ZR>
-static hipError_t launch_mode3s(int mode, const ChainDev* chains, const Tile* tiles, int n_tiles, int j,
+static hipError_t launch_mode3t(int mode, const ChainDev* chains, const Tile* tiles, int n_tiles, int j,
                                 hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   dim3 grid(n_tiles), block(256);
   switch (mode) {
     case PASS_FIRST:
-      lattice_pass3s<T, BX, BY, ZR, PASS_FIRST><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
+      lattice_pass3t<T, BX, BY, ZR, PASS_FIRST><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
       break;
     case PASS_MIDDLE:
-      lattice_pass3s<T, BX, BY, ZR, PASS_MIDDLE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
+      lattice_pass3t<T, BX, BY, ZR, PASS_MIDDLE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
       break;
     case PASS_LAST:
-      lattice_pass3s<T, BX, BY, ZR, PASS_LAST><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
+      lattice_pass3t<T, BX, BY, ZR, PASS_LAST><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
       break;
     case PASS_MEASURE:
-      lattice_pass3s<T, BX, BY, ZR, PASS_MEASURE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
+      lattice_pass3t<T, BX, BY, ZR, PASS_MEASURE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
       break;
     case PASS_FORCE:
-      lattice_pass3s<T, BX, BY, ZR, PASS_FORCE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
+      lattice_pass3t<T, BX, BY, ZR, PASS_FORCE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
       break;
     default:
       return hipErrorInvalidValue;
@@ -599,8 +686,8 @@ static hipError_t launch_mode3s(int mode, const ChainDev* chains, const Tile* ti
 
 // 2D tiles: 64 x 16 (256 threads) for rows of 48 sites or more, 32 x 32 (256
 // threads) where that wastes less of the last tile of a row, 16 x 16 (64
-// threads) for small lattices.  3D column tiles: 32 x 8 (or 16 x 16 by the same
-// rule) in the plane, streamed over ZR planes.
+// threads) for small lattices.  3D boxes: 32 x 8 (or 16 x 16 by the same rule)
+// in the plane, ZR planes deep.
 #ifndef IHMC_2D_BX
 #define IHMC_2D_BX 64
 #define IHMC_2D_BY 16
@@ -644,16 +731,16 @@ hipError_t launch_lattice_pass(int precision, int ndim, int cls, int mode, const
       if (cls == 2) return launch_mode2v<float, 32, 32>(mode, chains, tiles, n_tiles, j, s);
       return launch_mode2v<float, IHMC_2D_BX, IHMC_2D_BY>(mode, chains, tiles, n_tiles, j, s);
     }
-    if (cls == 1) return launch_mode3s<float, 16, 16, IHMC_3D_ZR>(mode, chains, tiles, n_tiles, j, s);
-    return launch_mode3s<float, IHMC_3D_BX, IHMC_3D_BY, IHMC_3D_ZR>(mode, chains, tiles, n_tiles, j, s);
+    if (cls == 1) return launch_mode3t<float, 16, 16, IHMC_3D_ZR>(mode, chains, tiles, n_tiles, j, s);
+    return launch_mode3t<float, IHMC_3D_BX, IHMC_3D_BY, IHMC_3D_ZR>(mode, chains, tiles, n_tiles, j, s);
   }
   if (ndim == 2) {
     if (cls == 1) return launch_mode2v<double, 16, 16>(mode, chains, tiles, n_tiles, j, s);
     if (cls == 2) return launch_mode2v<double, 32, 32>(mode, chains, tiles, n_tiles, j, s);
     return launch_mode2v<double, IHMC_2D_BX, IHMC_2D_BY>(mode, chains, tiles, n_tiles, j, s);
   }
-  if (cls == 1) return launch_mode3s<double, 16, 16, IHMC_3D_ZR>(mode, chains, tiles, n_tiles, j, s);
-  return launch_mode3s<double, IHMC_3D_BX, IHMC_3D_BY, IHMC_3D_ZR>(mode, chains, tiles, n_tiles, j, s);
+  if (cls == 1) return launch_mode3t<double, 16, 16, IHMC_3D_ZR>(mode, chains, tiles, n_tiles, j, s);
+  return launch_mode3t<double, IHMC_3D_BX, IHMC_3D_BY, IHMC_3D_ZR>(mode, chains, tiles, n_tiles, j, s);
 }
 
 }  // namespace ihmc
