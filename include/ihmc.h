@@ -324,15 +324,16 @@ int ihmc_copy_bandwidth(ihmc_ctx* ctx, uint64_t bytes, int32_t reps, double* avg
 /* ---- tile autotuner ---------------------------------------------------------- */
 
 /* A lattice pass covers its chain in tiles of one of a few shapes, the tile
- * classes: in 2D 0 = 64 x 16, 1 = 16 x 16, 2 = 32 x 32 sites; in 3D columns of
- * 0 = 32 x 8 or 1 = 16 x 16 sites in the plane, four planes deep.  The class
+ * classes: in 2D 0 = 64 x 16, 1 = 16 x 16, 2 = 32 x 32 sites; in 3D boxes of
+ * 0 = 32 x 8 x 4, 1 = 16 x 16 x 4, 2 = 32 x 8 x 8, 3 = 16 x 16 x 8.  The class
  * changes speed only: every class gives bitwise the same trajectories, since
- * all sums are formed per x-aligned quad of sites and per four-plane column
- * and then added in exact fixed point.  A chain takes its class when it is
+ * all sums are formed per x-aligned quad of sites and per aligned four-plane
+ * column and then added in exact fixed point.  A chain takes its class when it is
  * created (ihmc_chains_create, ihmc_run_*, ihmc_submit) from its context's
  * table, keyed by (precision, ndim, L, per-site field or not), and without a
  * table entry from a built-in rule (narrower tiles where a row ends just past a
- * multiple of the wide tile).  When the environment variable IHMC_TUNE_CACHE
+ * multiple of the wide tile; in 3D eight-plane boxes where L[2] is a multiple
+ * of 8 and L[0] of 4).  When the environment variable IHMC_TUNE_CACHE
  * names a file, ihmc_ctx_create loads the table from it if it exists (failing
  * with IHMC_E_INVAL if it is malformed) and ihmc_tune saves the table there. */
 #define IHMC_TUNE_RULE 0     /* no entry: the built-in rule */
@@ -362,7 +363,7 @@ int ihmc_tile_shape(int32_t ndim, int32_t cls, int32_t* out, int32_t* n_classes)
 int ihmc_tune(ihmc_ctx* ctx, int32_t n, const ihmc_lattice* lats, const int32_t* precision, int64_t sites,
               int32_t reps, int32_t flags, int32_t* n_measured);
 /* The class that chains of (lat, precision) would take on this context, its
- * source (IHMC_TUNE_*) and, if ns_site is not NULL, ns_site[0..2] = measured
+ * source (IHMC_TUNE_*) and, if ns_site is not NULL, ns_site[0..3] = measured
  * middle-pass nanoseconds per site of each class (NaN where not measured or
  * the class does not exist). */
 int ihmc_tune_lookup(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t precision, int32_t* cls, int32_t* source,

@@ -553,77 +553,89 @@ __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict
   const T kick = (MODE == PASS_FORCE) ? (T)1 : (T)kick_d;
   const T drift = (T)drift_d;
 
+  // FP64 terms are summed per column over each aligned 4-plane slab (in z
+  // order), then per x-aligned quad of columns, and converted to fixed point
+  // once per slab and quad: the same grouping for every box depth.
+  static_assert(ZR % 4 == 0, "boxes are whole 4-plane slabs");
+  constexpr bool kAcc = (MODE == PASS_FIRST || MODE == PASS_LAST || MODE == PASS_MEASURE);
   uint32_t bad = 0u;
   double hs[NTERM];
+  u128 acc[NTERM];
 #pragma unroll
-  for (int a = 0; a < NTERM; ++a) hs[a] = 0.0;
+  for (int a = 0; a < NTERM; ++a) {
+    hs[a] = 0.0;
+    acc[a] = u128{0ull, 0ull};
+  }
 
 #pragma unroll
   for (int k = 0; k < ZR; ++k) {
     const int z = tl.z0 + k;
-    if (z >= z_end) break;
-    const int64_t idx = col + plane * z;
-    const int c = (k + 2) * PPL + (ly + 2) * RP + lx + 4;
-    const T v = sP[c];
-    double kin = 0.0;
-    if (kHasW && act) {
-      const int q = (k + 1) * WPL + (ly + 1) * RP + lx + 4;
-      T sw = (sW[q - 1] + sW[q + 1]) + (sW[q - RP] + sW[q + RP]);
-      sw = sw + (sW[q - WPL] + sW[q + WPL]);
-      T F = fma_t(Ct, sW[q], sw);
-      F = F + bcol[k];
-      T p;
-      if (MODE == PASS_FIRST) {
-        if (cd.p_given) {
-          p = pcol[k];
+    if (z < z_end) {
+      const int64_t idx = col + plane * z;
+      const int c = (k + 2) * PPL + (ly + 2) * RP + lx + 4;
+      const T v = sP[c];
+      double kin = 0.0;
+      if (kHasW && act) {
+        const int q = (k + 1) * WPL + (ly + 1) * RP + lx + 4;
+        T sw = (sW[q - 1] + sW[q + 1]) + (sW[q - RP] + sW[q + RP]);
+        sw = sw + (sW[q - WPL] + sW[q + WPL]);
+        T F = fma_t(Ct, sW[q], sw);
+        F = F + bcol[k];
+        T p;
+        if (MODE == PASS_FIRST) {
+          if (cd.p_given) {
+            p = pcol[k];
+          } else {
+            const int64_t site = gx + (int64_t)L0 * (gy + (int64_t)L1 * z);
+            T z0, z1;
+            normal_pair<T>(cd, (uint32_t)traj, TAG_MOM, site >> 1, z0, z1);
+            p = (site & 1) ? z1 : z0;
+          }
+          const double pd = (double)p;
+          kin = 0.5 * pd * pd;
+        } else if (MODE == PASS_FORCE) {
+          p = (T)0;
         } else {
-          const int64_t site = gx + (int64_t)L0 * (gy + (int64_t)L1 * z);
-          T z0, z1;
-          normal_pair<T>(cd, (uint32_t)traj, TAG_MOM, site >> 1, z0, z1);
-          p = (site & 1) ? z1 : z0;
+          p = pcol[k];
         }
-        const double pd = (double)p;
-        kin = 0.5 * pd * pd;
-      } else if (MODE == PASS_FORCE) {
-        p = (T)0;
-      } else {
-        p = pcol[k];
+        const T pn = fma_t(kick, F, p);
+        if (MODE == PASS_FIRST || MODE == PASS_MIDDLE) {
+          pmom[idx] = pn;
+          pout[idx] = fma_t(drift, pn, v);
+        } else if (MODE == PASS_FORCE) {
+          pmom[idx] = pn;
+        } else if (MODE == PASS_LAST) {
+          if (cd.write_p_last) pmom[idx] = pn;
+          const double pd = (double)pn;
+          kin = 0.5 * pd * pd;
+        }
       }
-      const T pn = fma_t(kick, F, p);
-      if (MODE == PASS_FIRST || MODE == PASS_MIDDLE) {
-        pmom[idx] = pn;
-        pout[idx] = fma_t(drift, pn, v);
-      } else if (MODE == PASS_FORCE) {
-        pmom[idx] = pn;
-      } else if (MODE == PASS_LAST) {
-        if (cd.write_p_last) pmom[idx] = pn;
-        const double pd = (double)pn;
-        kin = 0.5 * pd * pd;
+      if (MODE == PASS_FIRST) hs[T_K0] = hs[T_K0] + kin;
+      if (MODE == PASS_LAST) hs[T_K1] = hs[T_K1] + kin;
+      if (kH64) {
+        double ht[4];
+        double nb = ((double)sP[c - 1] + (double)sP[c + 1]) + ((double)sP[c - RP] + (double)sP[c + RP]);
+        nb = nb + ((double)sP[c - PPL] + (double)sP[c + PPL]);
+        h_terms(cd, (double)v, nb, act ? idx : 0, act, ht);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) hs[T_S + a] = hs[T_S + a] + ht[a];
       }
     }
-    if (MODE == PASS_FIRST) hs[T_K0] = hs[T_K0] + kin;
-    if (MODE == PASS_LAST) hs[T_K1] = hs[T_K1] + kin;
-    if (kH64) {
-      double ht[4];
-      double nb = ((double)sP[c - 1] + (double)sP[c + 1]) + ((double)sP[c - RP] + (double)sP[c + RP]);
-      nb = nb + ((double)sP[c - PPL] + (double)sP[c + PPL]);
-      h_terms(cd, (double)v, nb, act ? idx : 0, act, ht);
+    // end of a slab: every lane takes part (the quad sums shuffle across the wave)
+    if (kAcc && (k & 3) == 3) {
 #pragma unroll
-      for (int a = 0; a < 4; ++a) hs[T_S + a] = hs[T_S + a] + ht[a];
+      for (int a = 0; a < NTERM; ++a) {
+        const bool used = (MODE == PASS_FIRST && a == T_K0) || (MODE == PASS_LAST && a == T_K1) ||
+                          (kH64 && a >= T_S && a < T_S + 4);
+        if (used) {
+          acc[a] = add128(acc[a], to_fixed(quad_sum_lanes(hs[a]), bad));
+          hs[a] = 0.0;
+        }
+      }
     }
   }
 
   if (MODE == PASS_MIDDLE || MODE == PASS_FORCE) return;
-  // every lane reaches the quad sums (the shuffles need the whole wave)
-  u128 acc[NTERM];
-#pragma unroll
-  for (int a = 0; a < NTERM; ++a) acc[a] = u128{0ull, 0ull};
-  if (MODE == PASS_FIRST) acc[T_K0] = to_fixed(quad_sum_lanes(hs[T_K0]), bad);
-  if (MODE == PASS_LAST) acc[T_K1] = to_fixed(quad_sum_lanes(hs[T_K1]), bad);
-  if (kH64) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a) acc[T_S + a] = to_fixed(quad_sum_lanes(hs[T_S + a]), bad);
-  }
   const int tix = ((tl.z0 / ZR) * ((L1 + BY - 1) / BY) + tl.y0 / BY) * ((L0 + BX - 1) / BX) + tl.x0 / BX;
   block_accumulate<MODE, 4>(cd, st, acc, bad, cur, j, tix);
 }
@@ -687,30 +699,29 @@ static hipError_t launch_mode3t(int mode, const ChainDev* chains, const Tile* ti
 // 2D tiles: 64 x 16 (256 threads) for rows of 48 sites or more, 32 x 32 (256
 // threads) where that wastes less of the last tile of a row, 16 x 16 (64
 // threads) for small lattices.  3D boxes: 32 x 8 (or 16 x 16 by the same rule)
-// in the plane, ZR planes deep.
+// in the plane, 4 planes deep, or 8 where that adds no padding planes.
 #ifndef IHMC_2D_BX
 #define IHMC_2D_BX 64
 #define IHMC_2D_BY 16
 #endif
-#ifndef IHMC_3D_BX
-#define IHMC_3D_BX 32
-#define IHMC_3D_BY 8
-#define IHMC_3D_ZR 4
-#endif
 
 // Tile classes: the narrower tile wherever it leaves fewer idle threads in the
-// last tile of a row (row lengths just above a multiple of the wide tile).
-int tile_class(int ndim, int L0) {
+// last tile of a row (row lengths just above a multiple of the wide tile); in
+// 3D the 8-plane boxes (fewer halo planes per site) where L2 is a multiple of 8
+// and rows are whole vector chunks (L0 a multiple of 4).
+int tile_class(int ndim, int L0, int L2) {
   if (ndim == 2) {
     if (L0 < 48) return 1;
     const int r = L0 % 64;
     return (r >= 1 && r <= 32) ? 2 : 0;
   }
   const int r = L0 % 32;
-  return (r >= 1 && r <= 16) ? 1 : 0;
+  const int narrow = (r >= 1 && r <= 16) ? 1 : 0;
+  const bool deep = (L2 % 8 == 0) && (L0 % 4 == 0);
+  return narrow + (deep ? 2 : 0);
 }
 
-int tile_class_count(int ndim) { return ndim == 2 ? 3 : 2; }
+int tile_class_count(int ndim) { return ndim == 2 ? 3 : 4; }
 
 TileShape tile_shape(int precision, int ndim, int cls) {
   (void)precision;
@@ -719,8 +730,8 @@ TileShape tile_shape(int precision, int ndim, int cls) {
     if (cls == 2) return TileShape{32, 32, 1};
     return TileShape{IHMC_2D_BX, IHMC_2D_BY, 1};
   }
-  if (cls == 1) return TileShape{16, 16, IHMC_3D_ZR};
-  return TileShape{IHMC_3D_BX, IHMC_3D_BY, IHMC_3D_ZR};
+  const int bz = cls >= 2 ? 8 : 4;
+  return (cls & 1) ? TileShape{16, 16, bz} : TileShape{32, 8, bz};
 }
 
 hipError_t launch_lattice_pass(int precision, int ndim, int cls, int mode, const ChainDev* chains,
@@ -731,16 +742,24 @@ hipError_t launch_lattice_pass(int precision, int ndim, int cls, int mode, const
       if (cls == 2) return launch_mode2v<float, 32, 32>(mode, chains, tiles, n_tiles, j, s);
       return launch_mode2v<float, IHMC_2D_BX, IHMC_2D_BY>(mode, chains, tiles, n_tiles, j, s);
     }
-    if (cls == 1) return launch_mode3t<float, 16, 16, IHMC_3D_ZR>(mode, chains, tiles, n_tiles, j, s);
-    return launch_mode3t<float, IHMC_3D_BX, IHMC_3D_BY, IHMC_3D_ZR>(mode, chains, tiles, n_tiles, j, s);
+    switch (cls) {
+      case 1: return launch_mode3t<float, 16, 16, 4>(mode, chains, tiles, n_tiles, j, s);
+      case 2: return launch_mode3t<float, 32, 8, 8>(mode, chains, tiles, n_tiles, j, s);
+      case 3: return launch_mode3t<float, 16, 16, 8>(mode, chains, tiles, n_tiles, j, s);
+      default: return launch_mode3t<float, 32, 8, 4>(mode, chains, tiles, n_tiles, j, s);
+    }
   }
   if (ndim == 2) {
     if (cls == 1) return launch_mode2v<double, 16, 16>(mode, chains, tiles, n_tiles, j, s);
     if (cls == 2) return launch_mode2v<double, 32, 32>(mode, chains, tiles, n_tiles, j, s);
     return launch_mode2v<double, IHMC_2D_BX, IHMC_2D_BY>(mode, chains, tiles, n_tiles, j, s);
   }
-  if (cls == 1) return launch_mode3t<double, 16, 16, IHMC_3D_ZR>(mode, chains, tiles, n_tiles, j, s);
-  return launch_mode3t<double, IHMC_3D_BX, IHMC_3D_BY, IHMC_3D_ZR>(mode, chains, tiles, n_tiles, j, s);
+  switch (cls) {
+    case 1: return launch_mode3t<double, 16, 16, 4>(mode, chains, tiles, n_tiles, j, s);
+    case 2: return launch_mode3t<double, 32, 8, 8>(mode, chains, tiles, n_tiles, j, s);
+    case 3: return launch_mode3t<double, 16, 16, 8>(mode, chains, tiles, n_tiles, j, s);
+    default: return launch_mode3t<double, 32, 8, 4>(mode, chains, tiles, n_tiles, j, s);
+  }
 }
 
 }  // namespace ihmc

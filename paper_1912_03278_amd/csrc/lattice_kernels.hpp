@@ -13,9 +13,9 @@ struct TileShape {
   int bx, by, bz;
 };
 
-// Built-in tile class of a lattice (row length L0): the class that the
-// context uses unless its tuning table has an entry for the lattice.
-int tile_class(int ndim, int L0);
+// Built-in tile class of a lattice (row length L0, planes L2; L2 = 1 in 2D):
+// the class that the context uses unless its tuning table has an entry for it.
+int tile_class(int ndim, int L0, int L2);
 
 // Number of tile classes of a dimension (2 or 3); classes are 0 .. n-1.
 int tile_class_count(int ndim);

@@ -50,7 +50,7 @@ struct TileKey {
     return std::tie(prec, ndim, L0, L1, L2, site_field) < std::tie(o.prec, o.ndim, o.L0, o.L1, o.L2, o.site_field);
   }
 };
-constexpr int kMaxTileClasses = 3;
+constexpr int kMaxTileClasses = 4;
 struct TuneEntry {
   int32_t cls = 0;
   int32_t source = IHMC_TUNE_RULE;

@@ -39,7 +39,7 @@ TileKey tile_key(const ihmc_lattice& l, int precision) {
 int TuneTable::class_for(const TileKey& k) {
   std::lock_guard<std::mutex> lk(mu);
   auto it = m.find(k);
-  return it != m.end() ? it->second.cls : tile_class(k.ndim, k.L0);
+  return it != m.end() ? it->second.cls : tile_class(k.ndim, k.L0, k.L2);
 }
 
 static bool key_ok(const TileKey& k) {
@@ -202,7 +202,7 @@ static int pick_class(const TileKey& k, const double* ns) {
   int b = 0;
   for (int cls = 1; cls < ncls; ++cls)
     if (ns[cls] < ns[b]) b = cls;
-  const int rule = tile_class(k.ndim, k.L0);
+  const int rule = tile_class(k.ndim, k.L0, k.L2);
   return ns[rule] <= kTuneMargin * ns[b] ? rule : b;
 }
 
@@ -509,7 +509,7 @@ extern "C" int ihmc_tune_lookup(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t 
   std::lock_guard<std::mutex> lk(ctx->tune.mu);
   auto it = ctx->tune.m.find(k);
   if (it == ctx->tune.m.end()) {
-    *cls = tile_class(k.ndim, k.L0);
+    *cls = tile_class(k.ndim, k.L0, k.L2);
     if (source) *source = IHMC_TUNE_RULE;
     if (ns_site)
       for (int c = 0; c < kMaxTileClasses; ++c) ns_site[c] = NAN;

@@ -367,7 +367,7 @@ class Context:
         keep = []
         s = lat._c(keep)
         cls, src = C.c_int32(), C.c_int32()
-        ns = (C.c_double * 3)()
+        ns = (C.c_double * 4)()
         _check(load().ihmc_tune_lookup(self.h, C.byref(s), int(precision), C.byref(cls), C.byref(src), ns))
         return {"cls": cls.value, "source": src.value, "ns_per_site": list(ns)}
 

@@ -95,7 +95,7 @@ def test_tune_measures_pins_and_round_trips(ih, tmp_path, monkeypatch):
             assert 0 <= t["cls"] < nc
             ns = t["ns_per_site"]
             assert all(0 < ns[c] < 10 for c in range(nc)), ns
-            assert all(math.isnan(ns[c]) for c in range(nc, 3))
+            assert all(math.isnan(ns[c]) for c in range(nc, 4))
             # the choice is the fastest class, or the built-in one within 3 %
             assert ns[t["cls"]] <= 1.03 * min(ns[:nc])
             table[lat.L] = t

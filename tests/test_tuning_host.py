@@ -15,10 +15,10 @@ def ih():
 
 
 def test_tile_shapes(ih):
-    assert ih.tile_class_count(2) == 3 and ih.tile_class_count(3) == 2
+    assert ih.tile_class_count(2) == 3 and ih.tile_class_count(3) == 4
     assert [ih.tile_shape(2, c) for c in range(3)] == [(64, 16, 1), (16, 16, 1), (32, 32, 1)]
-    assert [ih.tile_shape(3, c) for c in range(2)] == [(32, 8, 4), (16, 16, 4)]
-    for nd, c in ((2, 3), (3, 2), (2, -1)):
+    assert [ih.tile_shape(3, c) for c in range(4)] == [(32, 8, 4), (16, 16, 4), (32, 8, 8), (16, 16, 8)]
+    for nd, c in ((2, 3), (3, 4), (2, -1)):
         with pytest.raises(ih.IhmcError):
             ih.tile_shape(nd, c)
     with pytest.raises(ih.IhmcError):
@@ -60,7 +60,7 @@ def test_valid_tables(ih, tmp_path):
     json.dumps({"format": "other", "entries": []}),
     json.dumps({"format": "ihmc-tile-classes"}),
     json.dumps(table(entry(**{"class": 3}))),                    # 2D has classes 0..2
-    json.dumps(table(entry(ndim=3, L=[16, 16, 16], **{"class": 2}))),  # 3D has 0..1
+    json.dumps(table(entry(ndim=3, L=[16, 16, 16], **{"class": 4}))),  # 3D has 0..3
     json.dumps(table(entry(L=[2, 64, 1]))),                      # L >= 3
     json.dumps(table(entry(L=[64, 64, 4]))),                     # 2D has L2 = 1
     json.dumps(table(entry(L=[64, 64]))),
