@@ -453,12 +453,73 @@ def bench_serving(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_tau(args):
+    """Critical slowing down measured on the batched engine (Sec. 4): tau_int of
+    |m| against N at the critical coupling in 2D and 3D, with the paper's fits
+    tau = alpha N^(2/d) and a free exponent, and against C - n at N = 15^2 (2D).
+    Every point runs `chains` independent replicas of `steps` unit trajectories
+    (after `warmup` discarded ones) with floor(log N) leap-frog steps, FP32
+    state, all points advanced together as one chain set."""
+    from paper_1912_03278_amd import autocorr as A, ihmc, inputs
+
+    K, W, R = args.steps, args.warmup, args.tau_chains
+    pts2 = [dict(L=(L, L), beta=inputs.BETA_C_2D, C=4.1) for L in (4, 6, 8, 11, 16, 23, 32)]
+    pts3 = [dict(L=(L,) * 3, beta=inputs.BETA_3D, C=6.1) for L in (3, 4, 5, 6, 8, 10)]
+    dcs = (0.05, 0.25, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0)
+    ptsC = [dict(L=(15, 15), beta=inputs.BETA_C_2D, C=4.0 + dc) for dc in dcs]
+    ctx = ihmc.Context(device=0, arena_bytes=6 << 30)
+    pts = pts2 + pts3 + ptsC
+    print(f"bench: tau_int scan, {len(pts)} points x {R} chains x {W + K} trajectories", file=sys.stderr,
+          flush=True)
+    out = A.run_scan(ctx, pts, n_chains=R, n_traj=K, n_therm=W, seed=17)
+    ctx.close()
+    run_s = out[0]["run_s"]
+    work = sum(r["site_md_steps"] for r in out)
+    r2, r3, rC = out[:len(pts2)], out[len(pts2):len(pts2) + len(pts3)], out[len(pts2) + len(pts3):]
+
+    def fits(rows, d):
+        rows = [r for r in rows if r["N"] > 10]
+        N = [r["N"] for r in rows]
+        tau = [r["tau_int"] for r in rows]
+        err = [r["tau_err"] for r in rows]
+        fixed = A.fit_power(N, tau, err, exponent=2.0 / d)
+        free = A.fit_power(N, tau, err)
+        return {"alpha_at_2_over_d": fixed["alpha"], "alpha_err": fixed["alpha_err"],
+                "chi2_dof_at_2_over_d": fixed["chi2_dof"], "free_gamma": free["gamma"],
+                "free_gamma_err": free["gamma_err"], "z": d * free["gamma"], "z_err": d * free["gamma_err"]}
+
+    def rowfmt(rows, key):
+        return [{key: r[key] if key != "C_minus_n" else round(r["C"] - 2 * len(r["L"]), 4), "N": r["N"],
+                 "n_md": r["n_md"], "tau_int": round(r["tau_int"], 4), "tau_err": round(r["tau_err"], 4),
+                 "abs_m": round(r["mean"], 6), "abs_m_err": round(r["err"], 6),
+                 "acceptance": round(r["acceptance"], 4)} for r in rows]
+
+    t0 = rC[0]
+    c_crit = next((round(r["C"] - 4.0, 4) for r in rC[1:]
+                   if r["tau_int"] > t0["tau_int"] + 3 * math.hypot(t0["tau_err"], r["tau_err"])), None)
+    line = {
+        "metric": "site-MD-steps/s", "value": work / run_s, "unit": "site-MD-steps/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": 1000.0 * run_s / (K + W), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"tau_int scans at the critical coupling, h = 0, {R} replicas per point, "
+                               f"{K} trajectories after {W}, n_md = floor(log N): 2D L 4..32 (C = 4.1), "
+                               "3D L 3..10 (C = 6.1), 2D 15^2 with C - n from 0.05 to 4; one step = one "
+                               "trajectory of every chain", "chains": R * len(pts)},
+        "tau_2d": {"points": rowfmt(r2, "L"), "fit": fits(r2, 2)},
+        "tau_3d": {"points": rowfmt(r3, "L"), "fit": fits(r3, 3)},
+        "tau_vs_C": {"points": rowfmt(rC, "C_minus_n"), "first_C_minus_n_above_plateau": c_crit},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="large", choices=["large", "batched", "dense", "serving", "small"],
+    ap.add_argument("--workload", default="large",
+                    choices=["large", "batched", "dense", "serving", "small", "tau"],
                     help="large (default): the 1024^2 + 128^3 single chains; batched: 4096 uneven chains; "
                          "dense: 256 chains of an N=4096 all-to-all model; serving: Poisson request arrivals")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
@@ -470,6 +531,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-streaming-point", action="store_true", help="large: skip the extra 8192^2 point")
     ap.add_argument("--timing-reps", type=int, default=100)
+    ap.add_argument("--tau-chains", type=int, default=128, help="tau: replicas per scan point")
     ap.add_argument("--tiles", default="tuned", choices=["tuned", "rule"],
                     help="tile classes: autotuned per lattice shape before the run (default), or the built-in rule")
     args = ap.parse_args()
@@ -483,6 +545,10 @@ def main():
         return bench_batched(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "tau":
+        args.steps = 8000 if args.steps is None else args.steps
+        args.warmup = 1000 if args.warmup is None else args.warmup
+        return bench_tau(args)
     if args.workload == "small":
         args.steps = 2000 if args.steps is None else args.steps
         args.warmup = 200 if args.warmup is None else args.warmup
