@@ -37,17 +37,21 @@ BYTES_MIDDLE_F32 = 16  # read psi, read p, write p, write psi' (FP32), h = 0
 # --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, median over the full
 # launches), scaled by what the same counters read for the plain copy kernel of
 # known size: FETCH_SIZE x 2, WRITE_SIZE x 1.  Each entry records a digest of the
-# kernel sources it was measured on; when the sources differ, the field is null.
+# kernel sources it was measured on and the tile shape and sites of the launch;
+# when any of them differs, the field is null.
 KERNEL_SOURCES = ("lattice_kernels.hip", "lattice_kernels.hpp", "chain_epilogue.hpp", "device_common.hpp",
                   "ihmc_internal.hpp", "dense_kernels.hip", "dense_kernels.hpp")
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
-    "large_2d_middle": {"sources": "b7d2d3d1e9d8d4b2", "fetch_kib": 4199.0, "write_kib": 8192.0},
-    "large_3d_middle": {"sources": "b7d2d3d1e9d8d4b2", "fetch_kib": 9319.0, "write_kib": 16384.0},
-    "stream_2d_middle": {"sources": "b7d2d3d1e9d8d4b2", "fetch_kib": 263704.1, "write_kib": 524288.0},
-    "batched_middle": {"sources": "b7d2d3d1e9d8d4b2", "sites": 26151867, "fetch_kib": 155782.8,
-                       "write_kib": 207496.4},
-    "dense_gemm_bf16": {"sources": "b7d2d3d1e9d8d4b2", "fetch_kib": 73754.5, "write_kib": 16384.0},
+    "large_2d_middle": {"sources": "e540736aeaf6c97c", "tiles": "64x16", "sites": 1048576,
+                        "fetch_kib": 4206.0, "write_kib": 8192.0},
+    "large_3d_middle": {"sources": "e540736aeaf6c97c", "tiles": "32x8x8", "sites": 2097152,
+                        "fetch_kib": 9295.5, "write_kib": 16384.0},
+    "stream_2d_middle": {"sources": "e540736aeaf6c97c", "tiles": "64x16", "sites": 67108864,
+                         "fetch_kib": 263714.5, "write_kib": 524288.0},
+    "batched_middle": {"sources": "e540736aeaf6c97c", "tiles": "64x16", "sites": 28410923,
+                       "fetch_kib": 169419.9, "write_kib": 224484.9},
+    "dense_gemm_bf16": {"sources": "e540736aeaf6c97c", "fetch_kib": 73754.5, "write_kib": 16384.0},
 }
 
 
@@ -60,14 +64,16 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
-def traffic_bytes(key, sites=None):
+def traffic_bytes(key, sites=None, tiles=None):
     """Measured HBM bytes per launch of the roofline kernel, or None if the
-    kernel sources (or the sites that launch covers) changed since the counters
-    were taken."""
+    kernel sources, or the tile shape or sites of the launch, differ from those
+    the counters were taken on."""
     t = TRAFFIC.get(key)
     if not t or t["sources"] != kernel_digest():
         return None
     if sites is not None and t.get("sites") not in (None, sites):
+        return None
+    if tiles is not None and t.get("tiles") not in (None, tiles):
         return None
     return int(1024 * (FETCH_SCALE * t["fetch_kib"] + WRITE_SCALE * t["write_kib"]))
 
@@ -147,7 +153,7 @@ def streaming_point(args, copy_gbs):
     return {"label": "extra point, not the configured workload: one 2D 8192^2 chain at beta_c, FP32, n_md=20",
             "site_md_steps_per_s": 4 * L * L * 20 / dt, "acceptance": acc,
             "middle_pass_us": round(mid["us"], 2), "bytes_per_launch": BYTES_MIDDLE_F32 * mid["sites"],
-            "traffic": traffic_bytes("stream_2d_middle"),
+            "traffic": traffic_bytes("stream_2d_middle", sites=mid["sites"]),
             "achieved_GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
             "frac_of_copy": round(gbs / copy_gbs, 4)}
 
@@ -274,7 +280,7 @@ def bench_batched(args):
                                                f"({dom['chains']} chains)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_bytes("batched_middle", sites=dom["sites"]),
+                     "traffic": traffic_bytes("batched_middle", sites=dom["sites"], tiles=dom["tiles"]),
                      "bytes_per_launch": 20 * dom["sites"], "avg_launch_us": dom["middle_us"],
                      "copy_kernel_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "kernels": kern,
@@ -641,7 +647,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_bytes("large_3d_middle" if dom["ndim"] == 3 else "large_2d_middle"),
+            "traffic": traffic_bytes("large_3d_middle" if dom["ndim"] == 3 else "large_2d_middle",
+                                     sites=dom["sites"], tiles=dom["tiles"]),
             "bytes_per_launch": bytes_per_launch,
             "avg_launch_us": round(dom["middle_us"], 3),
             "copy_kernel_GBs": round(copy_gbs, 1),
