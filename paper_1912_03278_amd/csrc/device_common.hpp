@@ -163,7 +163,7 @@ __device__ __forceinline__ u128 wave_sum128(u128 v) {
 __device__ __forceinline__ float tanh_state(float x) {
   const float ax = fabsf(x);
   const float e = __builtin_amdgcn_exp2f(ax * 2.88539008177792681f);
-  const float t = 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + e);
+  const float t = fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + e), 1.0f);
   return copysignf(t, x);
 }
 

@@ -435,7 +435,6 @@ __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict
   constexpr int PR = BY + 4, PZ = ZR + 4;
   constexpr int WR = BY + 2, WZ = ZR + 2;
   constexpr int PPL = PR * RP, WPL = WR * RP;
-  constexpr int NWC = WZ * WR * NCH;  // w chunks
   constexpr bool kHasW = (MODE != PASS_MEASURE);
   constexpr bool kH64 = (MODE == PASS_LAST || MODE == PASS_MEASURE);
   static_assert(BX * BY == 256 && BX % 4 == 0, "one column per thread");
@@ -481,37 +480,38 @@ __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict
     }
   }
 
-  // ---- stage psi on the box plus its halo: thread t loads chunk column
-  // t % NCH of the staged rows (plane-major) t / NCH + RG k; all its loads are
-  // issued before its LDS stores
+  // ---- stage psi on the box plus its halo: thread t owns chunk column c of
+  // staged row r (each of the NCH * PR pairs has NH threads) and loads it in a
+  // run of consecutive planes, so the row's wrap and offset are worked out
+  // once; all its loads are issued before its LDS stores
   const bool rows_near = (L1 > BY), planes_near = (L2 > ZR), x_near = (L0 > BX + 2);
   {
-    constexpr int NROW = PZ * PR;
-    constexpr int RG = 256 / NCH;
-    constexpr int NRPT = (NROW + RG - 1) / RG;
-    const int c = threadIdx.x % NCH, rg = threadIdx.x / NCH;
-    if (rg < RG) {
+    constexpr int NPAIR = NCH * PR;
+    constexpr int NH = 256 / NPAIR;
+    constexpr int NPP = (PZ + NH - 1) / NH;  // planes per thread
+    static_assert(NH >= 1, "box row too long for one block");
+    const int pair = threadIdx.x % NPAIR, h = threadIdx.x / NPAIR;
+    if (h < NH) {
+      const int c = pair % NCH, r = pair / NCH;
       const ChunkPos cp = chunk_pos(tl.x0 - 4 + 4 * c, L0, x_near);
-      T v[NRPT][4];
+      const int yy = rows_near ? wrap_near(tl.y0 + r - 2, L1) : wrap_any(tl.y0 + r - 2, L1);
+      const gmem<T>* rowy = pin + row_offset(yy, pitch);
+      const int pz0 = h * NPP;
+      int zz = planes_near ? wrap_near(tl.z0 + pz0 - 2, L2) : wrap_any(tl.z0 + pz0 - 2, L2);
+      T v[NPP][4];
 #pragma unroll
-      for (int k = 0; k < NRPT; ++k) {
-        const int R = rg + RG * k;
-        if (R < NROW) {
-          const int pz = R / PR, r = R - pz * PR;
-          const int zz = planes_near ? wrap_near(tl.z0 + pz - 2, L2) : wrap_any(tl.z0 + pz - 2, L2);
-          const int yy = rows_near ? wrap_near(tl.y0 + r - 2, L1) : wrap_any(tl.y0 + r - 2, L1);
-          load_chunk<T>(pin + row_offset(zz, plane) + row_offset(yy, pitch), cp, v[k]);
-        }
+      for (int k = 0; k < NPP; ++k) {
+        if (pz0 + k < PZ) load_chunk<T>(rowy + row_offset(zz, plane), cp, v[k]);
+        zz = (zz + 1 == L2) ? 0 : zz + 1;
       }
 #pragma unroll
-      for (int k = 0; k < NRPT; ++k) {
-        const int R = rg + RG * k;
-        if (R < NROW) {
+      for (int k = 0; k < NPP; ++k) {
+        if (pz0 + k < PZ) {
           if (from_cur) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) v[k][e] = neg_if(v[k][e], sign);
           }
-          st4<T>(sP + R * RP + 4 * c, v[k]);
+          st4<T>(sP + (pz0 + k) * PPL + r * RP + 4 * c, v[k]);
         }
       }
     }
@@ -521,11 +521,18 @@ __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict
   const T Ct = (T)cd.C;
   const T at = (T)cd.sqJ;
 
-  // ---- w on the box plus its 1-wide halo, in quads over x in [-4, BX+4)
+  // ---- w on the box plus its 1-wide halo, in quads over x in [-4, BX+4):
+  // thread t computes chunk column t % NCH of the w rows t / NCH + RG k
   if (kHasW) {
-    for (int i = threadIdx.x; i < NWC; i += 256) {
-      const int wz = i / (WR * NCH), rem = i - wz * (WR * NCH);
-      const int wy = rem / NCH, c = rem - wy * NCH;
+    constexpr int NWROW = WZ * WR;
+    constexpr int RG = 256 / NCH;
+    constexpr int NIT = (NWROW + RG - 1) / RG;
+    const int c = threadIdx.x % NCH, rg = threadIdx.x / NCH;
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int R = rg + RG * k;
+      if (rg >= RG || R >= NWROW) break;
+      const int wz = R / WR, wy = R - wz * WR;
       const int pc = (wz + 1) * PPL + (wy + 1) * RP + 4 * c;  // psi at (x0 - 4 + 4c, y0 - 1 + wy, z0 - 1 + wz)
       T cv[4], up[4], dn[4], zm[4], zp[4], w[4];
       ld4<T>(sP + pc, cv);
