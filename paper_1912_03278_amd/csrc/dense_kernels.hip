@@ -299,11 +299,16 @@ __global__ __launch_bounds__(GTHREADS) void k_dense_gemm_bf16(const __bf16* __re
 
   gload(0);
   lstore(0);
-  __syncthreads();
+  lds_barrier();
   const int fr = lane & 15, fk = (lane >> 4) * 8;
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
-    if (kt + 1 < nk) gload((int64_t)(kt + 1) << 12);  // next 128 x 32 block of the same row block
+    // next 128 x 32 block of the same row block, issued before this step's MFMAs
+    // and stored after them; unconditional (the last step reloads its own block
+    // into the idle buffer), since the compiler sinks loads that only a branch
+    // uses into that branch, after the MFMAs, exposing their whole latency
+    gload((int64_t)min(kt + 1, nk - 1) << 12);
+    __builtin_amdgcn_sched_barrier(0);
     bf16x8 fa[NL][2], fb[NL][4];
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
@@ -319,8 +324,8 @@ __global__ __launch_bounds__(GTHREADS) void k_dense_gemm_bf16(const __bf16* __re
 #pragma unroll
         for (int c = 0; c < 4; ++c)
           acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[PA[p]][r], fb[PC[p]][c], acc[r][c], 0, 0, 0);
-    if (kt + 1 < nk) lstore(buf ^ 1);
-    __syncthreads();
+    lstore(buf ^ 1);  // unconditional too, or the loads above would sink into its branch
+    lds_barrier();
   }
   // D layout of the 16x16 MFMA: lane -> column (chain) lane % 16, rows 4 (lane / 16) + e
   float* out = part + (int64_t)blockIdx.z * Bp * Np;
@@ -430,7 +435,7 @@ __global__ __launch_bounds__(256) void k_dense_gemm_f64(const double* __restrict
         for (int c = 0; c < 2; ++c) acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[r], fb[c], acc[r][c], 0, 0, 0);
     }
     if (kt + 1 < nk) lstore(buf ^ 1);
-    __syncthreads();
+    lds_barrier();
   }
   // D layout of the FP64 16x16 MFMA: lane -> column lane % 16, rows lane / 16 + 4 e
 #pragma unroll

@@ -155,6 +155,15 @@ __device__ __forceinline__ u128 wave_sum128(u128 v) {
   return v;
 }
 
+// Workgroup barrier that orders LDS accesses only.  The full __syncthreads
+// fence also waits for every global load in flight, which would expose the
+// latency of loads issued early to overlap work across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ------------------------------------------------------------- functions ---
 
 // tanh in FP32: tanh|x| = 1 - 2 / (1 + e^{2|x|}) with the hardware base-2

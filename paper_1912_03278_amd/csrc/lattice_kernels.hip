@@ -295,7 +295,7 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   const T Ct = (T)cd.C;
   const T at = (T)cd.sqJ;
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
       }
       st4<T>(sW + wy * RP + 4 * c, w);
     }
-    __syncthreads();
+    lds_barrier();
   }
 
   double kick_d = 0.0, drift_d = 0.0;
@@ -516,7 +516,7 @@ __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   const T Ct = (T)cd.C;
   const T at = (T)cd.sqJ;
@@ -552,7 +552,7 @@ __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict
       }
       st4<T>(sW + wz * WPL + wy * RP + 4 * c, w);
     }
-    __syncthreads();
+    lds_barrier();
   }
 
   double kick_d = 0.0, drift_d = 0.0;
