@@ -233,6 +233,14 @@ __device__ __forceinline__ void block_close(const ChainDev& cd, ChainState* st, 
   }
 }
 
+// Site terms are summed per quad of four x-aligned sites (x = 4q .. 4q+3; in the dense
+// path, site indices 4q .. 4q+3) as
+// (t0 + t1) + (t2 + t3) in FP64 and converted to fixed point once per quad.
+// Quads are the same in every tiling, so the totals stay tile-independent.
+__device__ __forceinline__ double quad_sum(double t0, double t1, double t2, double t3) {
+  return (t0 + t1) + (t2 + t3);
+}
+
 // Terms of four x-aligned sites held by four consecutive lanes, summed as
 // (t0 + t1) + (t2 + t3) in FP64 (FP addition is commutative, so every lane of
 // the quad forms the identical value; lane 4q keeps it, the other three give 0).

@@ -455,12 +455,6 @@ __global__ __launch_bounds__(256) void k_dense_gemm_f64(const double* __restrict
 // ---------------------------------------------------------------- epilogues ---
 
 // Sum of the split-K partials in slice order.
-__device__ __forceinline__ float sum_parts(const float* __restrict__ part, int S, int64_t plane, int64_t off) {
-  float s = part[off];
-  for (int q = 1; q < S; ++q) s += part[(int64_t)q * plane + off];
-  return s;
-}
-
 // Three BF16 limbs of an FP32 value (exact: 3 x 8 significand bits cover 24).
 __device__ __forceinline__ void split_f32(float x, __bf16& l0, __bf16& l1, __bf16& l2) {
   l0 = (__bf16)x;
@@ -469,170 +463,201 @@ __device__ __forceinline__ void split_f32(float x, __bf16& l0, __bf16& l1, __bf1
   l2 = (__bf16)(r1 - (float)l1);
 }
 
+// The per-site kernels below (set-up limbs, both force epilogues, the FP64 action
+// terms) run one wave per tile of 256 sites of one chain (grid: tiles x chains,
+// so the chain's fields are uniform loads) with four consecutive sites per lane:
+// 16-byte loads and stores of the FP32 fields, 8-byte stores of the limbs (four
+// consecutive sites are contiguous in the tiled layout), and one wave per CU
+// slot instead of four, so that the whole grid is resident at once.  Sites past
+// N (the padding up to Np) carry zeros.
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+constexpr int EPI_SITES = 256, EPI_THREADS = 64;
+
+__device__ __forceinline__ f32x4 ld_f4(const float* p) { return *reinterpret_cast<const f32x4*>(p); }
+__device__ __forceinline__ void st_f4(float* p, f32x4 v) { *reinterpret_cast<f32x4*>(p) = v; }
+
+__device__ __forceinline__ f32x4 sum_parts4(const float* __restrict__ part, int S, int64_t plane, int64_t off) {
+  f32x4 s = ld_f4(part + off);
+  for (int q = 1; q < S; ++q) s = s + ld_f4(part + (int64_t)q * plane + off);
+  return s;
+}
+
+// limbs of four consecutive sites (row b, columns i .. i+3, i % 4 == 0)
+__device__ __forceinline__ void store_limbs4(__bf16* __restrict__ X, int64_t limb_stride, int64_t b, int64_t i,
+                                             int64_t Np, f32x4 v) {
+  bf16x4 l0, l1, l2;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    __bf16 a, c, d;
+    split_f32(v[e], a, c, d);
+    l0[e] = a;
+    l1[e] = c;
+    l2[e] = d;
+  }
+  const int64_t o = tiled(b, i, Np);
+  *reinterpret_cast<bf16x4*>(X + o) = l0;
+  *reinterpret_cast<bf16x4*>(X + limb_stride + o) = l1;
+  *reinterpret_cast<bf16x4*>(X + 2 * limb_stride + o) = l2;
+}
+
 // Start of a trajectory / set-up: limbs of the accepted fields (sign applied).
-// One thread per (chain, site).
-__global__ void k_dense_prep(const ChainDev* __restrict__ chains, int B, int64_t Np, int64_t Bp,
-                             __bf16* __restrict__ Xl) {
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)B * Np) return;
-  const int b = (int)(idx / Np);
-  const int64_t i = idx % Np;
+__global__ __launch_bounds__(EPI_THREADS) void k_dense_prep(const ChainDev* __restrict__ chains, int64_t Np,
+                                                            int64_t Bp, __bf16* __restrict__ Xl) {
+  const int b = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * EPI_SITES + 4 * threadIdx.x;
   const ChainDev& cd = chains[b];
   const ChainState* st = cd.st;
-  float v = 0.f;
+  f32x4 v = {0.f, 0.f, 0.f, 0.f};
   if (i < cd.N) {
-    v = ((const float*)cd.psi)[(int64_t)st->cur * cd.NP + i];
+    v = ld_f4((const float*)cd.psi + (int64_t)st->cur * cd.NP + i);
     if (st->sign < 0) v = -v;
   }
-  __bf16 a, c, d;
-  split_f32(v, a, c, d);
-  const int64_t o = tiled(b, i, Np);
-  Xl[o] = a;
-  Xl[Bp * Np + o] = c;
-  Xl[2 * Bp * Np + o] = d;
+  store_limbs4(Xl, Bp * Np, b, i, Np, v);
 }
 
 // After U = K Psi: w = sqrt(J') tanh(sqrt(J') (U + C psi)) - psi  -> W (FP32 and limbs).
-__global__ void k_dense_epi_w(const ChainDev* __restrict__ chains, int B, int64_t Np, int64_t Bp, int S,
-                              const float* __restrict__ part, int j, float* __restrict__ W32,
-                              __bf16* __restrict__ Wl) {
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)B * Np) return;
-  const int b = (int)(idx / Np);
-  const int64_t i = idx % Np;
+__global__ __launch_bounds__(EPI_THREADS) void k_dense_epi_w(const ChainDev* __restrict__ chains, int64_t Np,
+                                                             int64_t Bp, int S, const float* __restrict__ part, int j,
+                                                             float* __restrict__ W32, __bf16* __restrict__ Wl) {
+  const int b = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * EPI_SITES + 4 * threadIdx.x;
   const ChainDev& cd = chains[b];
   const ChainState* st = cd.st;
   const int64_t o = (int64_t)b * Np + i;
-  float w = 0.f;
+  const f32x4 ku = sum_parts4(part, S, Bp * Np, o);
+  f32x4 w = {0.f, 0.f, 0.f, 0.f};
   if (i < cd.N) {
     const int buf = (j == 0) ? st->cur : pass_in_buf(st->cur, j);
-    float v = ((const float*)cd.psi)[(int64_t)buf * cd.NP + i];
+    f32x4 v = ld_f4((const float*)cd.psi + (int64_t)buf * cd.NP + i);
     if (j == 0 && st->sign < 0) v = -v;
-    const float a = (float)cd.sqJ;
-    const float u = __builtin_fmaf((float)cd.C, v, sum_parts(part, S, Bp * Np, o));
-    w = __builtin_fmaf(a, tanh_state(a * u), -v);
+    const float a = (float)cd.sqJ, C = (float)cd.C;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (i + e < cd.N) {
+        const float u = __builtin_fmaf(C, v[e], ku[e]);
+        w[e] = __builtin_fmaf(a, tanh_state(a * u), -v[e]);
+      }
+    }
   }
-  W32[o] = w;
-  __bf16 l0, l1, l2;
-  split_f32(w, l0, l1, l2);
-  const int64_t ot = tiled(b, i, Np);
-  Wl[ot] = l0;
-  Wl[Bp * Np + ot] = l1;
-  Wl[2 * Bp * Np + ot] = l2;
+  st_f4(W32 + o, w);
+  store_limbs4(Wl, Bp * Np, b, i, Np, w);
 }
 
 // After F = K W: F += C w + h'/sqrt(J'); kick p, drift psi (not on the last pass),
-// new limbs of psi.  Grid: (site blocks of 256) x (chains); the FIRST pass draws
-// the momenta and sums 1/2 p^2, the LAST pass sums 1/2 p^2 of the final momenta.
+// new limbs of psi.  The FIRST pass draws the momenta (one Philox draw per pair
+// of sites) and sums 1/2 p^2, the LAST pass sums 1/2 p^2 of the final momenta.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_dense_epi_f(const ChainDev* __restrict__ chains, int64_t Np, int64_t Bp,
-                                                     int S, const float* __restrict__ part,
-                                                     const float* __restrict__ W32, int j, __bf16* __restrict__ Xl) {
+__global__ __launch_bounds__(EPI_THREADS) void k_dense_epi_f(const ChainDev* __restrict__ chains, int64_t Np,
+                                                             int64_t Bp, int S, const float* __restrict__ part,
+                                                             const float* __restrict__ W32, int j,
+                                                             __bf16* __restrict__ Xl) {
   const int b = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * EPI_SITES + 4 * threadIdx.x;
   const ChainDev& cd = chains[b];
   ChainState* st = cd.st;
   const int64_t o = (int64_t)b * Np + i;
   const int cur = st->cur;
-  const bool act = (i < cd.N);
   double kick_d = 0.0, drift_d = 0.0;
   pass_coeffs(cd, j, kick_d, drift_d);
   const float kick = (MODE == PASS_FORCE) ? 1.f : (float)kick_d;
   const float drift = (float)drift_d;
-  float* pmom = (float*)cd.p;
-  double kin = 0.0;
-  float psi_new = 0.f;
-  if (act) {
+  float* pmom = (float*)cd.p + i;
+  const f32x4 kw = sum_parts4(part, S, Bp * Np, o);
+  double kin[4] = {0.0, 0.0, 0.0, 0.0};
+  f32x4 psi_new = {0.f, 0.f, 0.f, 0.f};
+  if (i < cd.N) {
     const int in_buf = (MODE == PASS_FIRST || MODE == PASS_FORCE) ? cur : pass_in_buf(cur, j);
-    float v = ((const float*)cd.psi)[(int64_t)in_buf * cd.NP + i];
+    f32x4 v = ld_f4((const float*)cd.psi + (int64_t)in_buf * cd.NP + i);
     if ((MODE == PASS_FIRST || MODE == PASS_FORCE) && st->sign < 0) v = -v;
-    const float bsite = (cd.h_kind == 2) ? ((const float*)cd.b)[i] : (float)cd.b0;
-    const float F = __builtin_fmaf((float)cd.C, W32[o], sum_parts(part, S, Bp * Np, o)) + bsite;
-    float p;
+    const f32x4 w = ld_f4(W32 + o);
+    f32x4 bs;
+    if (cd.h_kind == 2) bs = ld_f4((const float*)cd.b + i);
+    else bs = f32x4{(float)cd.b0, (float)cd.b0, (float)cd.b0, (float)cd.b0};
+    f32x4 p = {0.f, 0.f, 0.f, 0.f};
     if (MODE == PASS_FIRST) {
       if (cd.p_given) {
-        p = pmom[i];
+        p = ld_f4(pmom);
       } else {
-        float z0, z1;
+        float z0, z1, z2, z3;
         normal_pair<float>(cd, (uint32_t)st->traj, TAG_MOM, i >> 1, z0, z1);
-        p = (i & 1) ? z1 : z0;
+        normal_pair<float>(cd, (uint32_t)st->traj, TAG_MOM, (i >> 1) + 1, z2, z3);
+        p = f32x4{z0, z1, z2, z3};
       }
-      kin = 0.5 * (double)p * (double)p;
-    } else if (MODE == PASS_FORCE) {
-      p = 0.f;
-    } else {
-      p = pmom[i];
+    } else if (MODE != PASS_FORCE) {
+      p = ld_f4(pmom);
     }
-    const float pn = __builtin_fmaf(kick, F, p);
-    if (MODE == PASS_LAST) {
-      kin = 0.5 * (double)pn * (double)pn;
-      if (cd.write_p_last) pmom[i] = pn;
-    } else {
-      pmom[i] = pn;
+    f32x4 pn = {0.f, 0.f, 0.f, 0.f};
+    const float C = (float)cd.C;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (i + e < cd.N) {
+        const float F = __builtin_fmaf(C, w[e], kw[e]) + bs[e];
+        pn[e] = __builtin_fmaf(kick, F, p[e]);
+        if (MODE == PASS_FIRST) kin[e] = 0.5 * (double)p[e] * (double)p[e];
+        if (MODE == PASS_LAST) kin[e] = 0.5 * (double)pn[e] * (double)pn[e];
+        if (MODE == PASS_FIRST || MODE == PASS_MIDDLE) psi_new[e] = __builtin_fmaf(drift, pn[e], v[e]);
+      }
     }
-    if (MODE == PASS_FIRST || MODE == PASS_MIDDLE) {
-      psi_new = __builtin_fmaf(drift, pn, v);
-      ((float*)cd.psi)[(int64_t)pass_out_buf(cur, j) * cd.NP + i] = psi_new;
-    }
+    if (MODE != PASS_LAST || cd.write_p_last) st_f4(pmom, pn);
+    if (MODE == PASS_FIRST || MODE == PASS_MIDDLE)
+      st_f4((float*)cd.psi + (int64_t)pass_out_buf(cur, j) * cd.NP + i, psi_new);
   }
-  if (MODE == PASS_FIRST || MODE == PASS_MIDDLE) {
-    __bf16 l0, l1, l2;
-    split_f32(psi_new, l0, l1, l2);
-    const int64_t ot = tiled(b, i, Np);
-    Xl[ot] = l0;
-    Xl[Bp * Np + ot] = l1;
-    Xl[2 * Bp * Np + ot] = l2;
-  }
+  if (MODE == PASS_FIRST || MODE == PASS_MIDDLE) store_limbs4(Xl, Bp * Np, b, i, Np, psi_new);
   if (MODE == PASS_FIRST || MODE == PASS_LAST) {
     uint32_t bad = 0u;
     u128 acc[NTERM];
 #pragma unroll
     for (int a = 0; a < NTERM; ++a) acc[a] = u128{0ull, 0ull};
     constexpr int a = (MODE == PASS_FIRST) ? T_K0 : T_K1;
-    acc[a] = to_fixed(quad_sum_lanes(kin), bad);
-    block_store_terms<4>(cd, acc, bad, a, a, MODE == PASS_FIRST ? CONTRIB_FIRST : CONTRIB_FINAL_KIN, blockIdx.x);
+    acc[a] = to_fixed(quad_sum(kin[0], kin[1], kin[2], kin[3]), bad);
+    block_store_terms<1>(cd, acc, bad, a, a, MODE == PASS_FIRST ? CONTRIB_FIRST : CONTRIB_FINAL_KIN, blockIdx.x);
   }
 }
 
 // FP64 action terms of the proposal (LAST) or of the accepted field (MEASURE)
 // from U64 = K psi; the block that finishes a chain last closes it (Metropolis
-// or measurement).  Grid: (site blocks of 256) x (chains).
+// or measurement).
 template <int MODE>
-__global__ __launch_bounds__(256) void k_dense_h(const ChainDev* __restrict__ chains, int64_t Np,
-                                                 const double* __restrict__ U64, int j) {
+__global__ __launch_bounds__(EPI_THREADS) void k_dense_h(const ChainDev* __restrict__ chains, int64_t Np,
+                                                         const double* __restrict__ U64, int j) {
   const int b = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * EPI_SITES + 4 * threadIdx.x;
   const ChainDev& cd = chains[b];
   ChainState* st = cd.st;
   const int cur = st->cur;
-  const bool act = (i < cd.N);
-  double h[4] = {0.0, 0.0, 0.0, 0.0};
-  if (act) {
+  double h[4][4] = {};  // [term][site]
+  if (i < cd.N) {
     const int buf = (MODE == PASS_MEASURE) ? cur : pass_in_buf(cur, j);
-    double v = (double)((const float*)cd.psi)[(int64_t)buf * cd.NP + i];
-    if (MODE == PASS_MEASURE && st->sign < 0) v = -v;
-    const double u = U64[(int64_t)b * Np + i] + cd.C * v;
-    double lc, th;
-    logcosh_tanh(cd.sqJ * u, lc, th);
-    double hpx = cd.hp0, bx = cd.b0;
-    if (cd.h_kind == 2) {
-      hpx = cd.hp[i];
-      bx = hpx / cd.sqJ;
+    f32x4 v4 = ld_f4((const float*)cd.psi + (int64_t)buf * cd.NP + i);
+    if (MODE == PASS_MEASURE && st->sign < 0) v4 = -v4;
+    const f64x4 ku = *reinterpret_cast<const f64x4*>(U64 + (int64_t)b * Np + i);
+    f64x4 hp4 = {cd.hp0, cd.hp0, cd.hp0, cd.hp0};
+    if (cd.h_kind == 2) hp4 = *reinterpret_cast<const f64x4*>(cd.hp + i);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (i + e < cd.N) {
+        const double v = (double)v4[e];
+        const double u = ku[e] + cd.C * v;
+        double lc, th;
+        logcosh_tanh(cd.sqJ * u, lc, th);
+        const double hpx = hp4[e];
+        const double bx = (cd.h_kind == 2) ? hpx / cd.sqJ : cd.b0;
+        h[0][e] = 0.5 * v * u - v * bx - lc;
+        h[1][e] = v;
+        h[2][e] = v * hpx;
+        h[3][e] = u * th;
+      }
     }
-    h[0] = 0.5 * v * u - v * bx - lc;
-    h[1] = v;
-    h[2] = v * hpx;
-    h[3] = u * th;
   }
   uint32_t bad = 0u;
   u128 acc[NTERM];
 #pragma unroll
   for (int a = 0; a < NTERM; ++a) acc[a] = u128{0ull, 0ull};
 #pragma unroll
-  for (int a = 0; a < 4; ++a) acc[T_S + a] = to_fixed(quad_sum_lanes(h[a]), bad);
+  for (int a = 0; a < 4; ++a) acc[T_S + a] = to_fixed(quad_sum(h[a][0], h[a][1], h[a][2], h[a][3]), bad);
   // the final kinetic energy was stored by the last force epilogue
-  block_store_terms<4>(cd, acc, bad, T_S, T_UT, CONTRIB_ACTION, blockIdx.x);
-  block_close<MODE == PASS_LAST, 4>(cd, st, MODE == PASS_LAST ? pass_in_buf(cur, j) : cur, blockIdx.x);
+  block_store_terms<1>(cd, acc, bad, T_S, T_UT, CONTRIB_ACTION, blockIdx.x);
+  block_close<MODE == PASS_LAST, 1>(cd, st, MODE == PASS_LAST ? pass_in_buf(cur, j) : cur, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ launch ---
@@ -707,33 +732,35 @@ hipError_t dense_gemm_f64(const double* K64, const ChainDev* chains, int j, int 
 }
 
 hipError_t dense_prep(const ChainDev* chains, int B, int64_t Np, int64_t Bp, __bf16* Xl, hipStream_t s) {
-  const int64_t n = (int64_t)B * Np;
-  k_dense_prep<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(chains, B, Np, Bp, Xl);
+  if (Np % EPI_SITES != 0) return hipErrorInvalidValue;
+  k_dense_prep<<<dim3((unsigned)(Np / EPI_SITES), (unsigned)B), EPI_THREADS, 0, s>>>(chains, Np, Bp, Xl);
   return hipGetLastError();
 }
 
 hipError_t dense_epi_w(const ChainDev* chains, int B, int64_t Np, int64_t Bp, int S, const float* part, int j,
                        float* W32, __bf16* Wl, hipStream_t s) {
-  const int64_t n = (int64_t)B * Np;
-  k_dense_epi_w<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(chains, B, Np, Bp, S, part, j, W32, Wl);
+  if (Np % EPI_SITES != 0) return hipErrorInvalidValue;
+  k_dense_epi_w<<<dim3((unsigned)(Np / EPI_SITES), (unsigned)B), EPI_THREADS, 0, s>>>(chains, Np, Bp, S, part, j,
+                                                                                      W32, Wl);
   return hipGetLastError();
 }
 
 hipError_t dense_epi_f(int mode, const ChainDev* chains, int B, int64_t Np, int64_t Bp, int S, const float* part,
                        const float* W32, int j, __bf16* Xl, hipStream_t s) {
-  dim3 grid((unsigned)(Np / 256), (unsigned)B);
+  if (Np % EPI_SITES != 0) return hipErrorInvalidValue;
+  dim3 grid((unsigned)(Np / EPI_SITES), (unsigned)B);
   switch (mode) {
     case PASS_FIRST:
-      k_dense_epi_f<PASS_FIRST><<<grid, 256, 0, s>>>(chains, Np, Bp, S, part, W32, j, Xl);
+      k_dense_epi_f<PASS_FIRST><<<grid, EPI_THREADS, 0, s>>>(chains, Np, Bp, S, part, W32, j, Xl);
       break;
     case PASS_MIDDLE:
-      k_dense_epi_f<PASS_MIDDLE><<<grid, 256, 0, s>>>(chains, Np, Bp, S, part, W32, j, Xl);
+      k_dense_epi_f<PASS_MIDDLE><<<grid, EPI_THREADS, 0, s>>>(chains, Np, Bp, S, part, W32, j, Xl);
       break;
     case PASS_LAST:
-      k_dense_epi_f<PASS_LAST><<<grid, 256, 0, s>>>(chains, Np, Bp, S, part, W32, j, Xl);
+      k_dense_epi_f<PASS_LAST><<<grid, EPI_THREADS, 0, s>>>(chains, Np, Bp, S, part, W32, j, Xl);
       break;
     case PASS_FORCE:
-      k_dense_epi_f<PASS_FORCE><<<grid, 256, 0, s>>>(chains, Np, Bp, S, part, W32, j, Xl);
+      k_dense_epi_f<PASS_FORCE><<<grid, EPI_THREADS, 0, s>>>(chains, Np, Bp, S, part, W32, j, Xl);
       break;
     default:
       return hipErrorInvalidValue;
@@ -742,9 +769,10 @@ hipError_t dense_epi_f(int mode, const ChainDev* chains, int B, int64_t Np, int6
 }
 
 hipError_t dense_h(int mode, const ChainDev* chains, int B, int64_t Np, const double* U64, int j, hipStream_t s) {
-  dim3 grid((unsigned)(Np / 256), (unsigned)B);
-  if (mode == PASS_LAST) k_dense_h<PASS_LAST><<<grid, 256, 0, s>>>(chains, Np, U64, j);
-  else k_dense_h<PASS_MEASURE><<<grid, 256, 0, s>>>(chains, Np, U64, j);
+  if (Np % EPI_SITES != 0) return hipErrorInvalidValue;
+  dim3 grid((unsigned)(Np / EPI_SITES), (unsigned)B);
+  if (mode == PASS_LAST) k_dense_h<PASS_LAST><<<grid, EPI_THREADS, 0, s>>>(chains, Np, U64, j);
+  else k_dense_h<PASS_MEASURE><<<grid, EPI_THREADS, 0, s>>>(chains, Np, U64, j);
   return hipGetLastError();
 }
 

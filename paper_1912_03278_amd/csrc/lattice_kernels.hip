@@ -181,13 +181,6 @@ __device__ __forceinline__ void h_terms(const ChainDev& cd, double v, double nb,
   h[3] = act ? u * th : 0.0;
 }
 
-// Site terms are summed per quad of four x-aligned sites (x = 4q .. 4q+3) as
-// (t0 + t1) + (t2 + t3) in FP64 and converted to fixed point once per quad.
-// Quads are the same in every tiling, so the totals stay tile-independent.
-__device__ __forceinline__ double quad_sum(double t0, double t1, double t2, double t3) {
-  return (t0 + t1) + (t2 + t3);
-}
-
 // Workgroups are dealt to the eight XCDs round-robin (block b runs on XCD b % 8),
 // each XCD with its own L2.  Neighbouring tiles read the same halo cache lines,
 // so each XCD takes a contiguous range of the tile table: block b works on tile
