@@ -54,7 +54,7 @@ def test_min_eig_infinite_range(ctx):
     assert abs(th + 1.0 / 500) < 1e-12 and res < 1e-9
 
 
-@pytest.mark.parametrize("N,h", [(300, None), (300, 0.07), (1000, "site")])
+@pytest.mark.parametrize("N,h", [(300, None), (299, None), (300, 0.07), (1000, "site")])
 def test_force_six_products(ctx, orc, N, h):
     from paper_1912_03278_amd import ihmc
     rng = np.random.default_rng(N)
@@ -82,7 +82,7 @@ def test_force_three_products_achieved_error(ctx, orc):
 
 
 @pytest.mark.parametrize("integ,n_md", [(0, 8), (1, 4)])
-@pytest.mark.parametrize("N,h", [(300, None), (500, "site")])
+@pytest.mark.parametrize("N,h", [(300, None), (500, "site"), (301, "site")])
 def test_one_trajectory(ctx, orc, integ, n_md, N, h):
     from paper_1912_03278_amd import ihmc
     rng = np.random.default_rng(N + integ)
