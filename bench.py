@@ -43,15 +43,15 @@ KERNEL_SOURCES = ("lattice_kernels.hip", "lattice_kernels.hpp", "chain_epilogue.
                   "ihmc_internal.hpp", "dense_kernels.hip", "dense_kernels.hpp")
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
-    "large_2d_middle": {"sources": "e540736aeaf6c97c", "tiles": "64x16", "sites": 1048576,
+    "large_2d_middle": {"sources": "884aa1d7441998f7", "tiles": "64x16", "sites": 1048576,
                         "fetch_kib": 4206.0, "write_kib": 8192.0},
-    "large_3d_middle": {"sources": "e540736aeaf6c97c", "tiles": "32x8x8", "sites": 2097152,
+    "large_3d_middle": {"sources": "884aa1d7441998f7", "tiles": "32x8x8", "sites": 2097152,
                         "fetch_kib": 9295.5, "write_kib": 16384.0},
-    "stream_2d_middle": {"sources": "e540736aeaf6c97c", "tiles": "64x16", "sites": 67108864,
+    "stream_2d_middle": {"sources": "884aa1d7441998f7", "tiles": "64x16", "sites": 67108864,
                          "fetch_kib": 263714.5, "write_kib": 524288.0},
-    "batched_middle": {"sources": "e540736aeaf6c97c", "tiles": "64x16", "sites": 28410923,
-                       "fetch_kib": 169419.9, "write_kib": 224484.9},
-    "dense_gemm_bf16": {"sources": "e540736aeaf6c97c", "fetch_kib": 73754.5, "write_kib": 16384.0},
+    "batched_middle": {"sources": "884aa1d7441998f7", "tiles": "64x16", "sites": 27910615,
+                       "fetch_kib": 166423.6, "write_kib": 220539.6},
+    "dense_gemm_bf16": {"sources": "884aa1d7441998f7", "fetch_kib": 73752.0, "write_kib": 16384.0},
 }
 
 
