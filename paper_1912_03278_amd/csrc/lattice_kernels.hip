@@ -484,19 +484,39 @@ __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict
     constexpr int NPP = (PZ + NH - 1) / NH;  // planes per thread
     static_assert(NH >= 1, "box row too long for one block");
     const int pair = threadIdx.x % NPAIR, h = threadIdx.x / NPAIR;
+    const int c = pair % NCH, r = pair / NCH;
+    const int pz0 = h * NPP;
+    T v[NPP][4];
     if (h < NH) {
-      const int c = pair % NCH, r = pair / NCH;
       const ChunkPos cp = chunk_pos(tl.x0 - 4 + 4 * c, L0, x_near);
       const int yy = rows_near ? wrap_near(tl.y0 + r - 2, L1) : wrap_any(tl.y0 + r - 2, L1);
       const gmem<T>* rowy = pin + row_offset(yy, pitch);
-      const int pz0 = h * NPP;
       int zz = planes_near ? wrap_near(tl.z0 + pz0 - 2, L2) : wrap_any(tl.z0 + pz0 - 2, L2);
-      T v[NPP][4];
 #pragma unroll
       for (int k = 0; k < NPP; ++k) {
         if (pz0 + k < PZ) load_chunk<T>(rowy + row_offset(zz, plane), cp, v[k]);
         zz = (zz + 1 == L2) ? 0 : zz + 1;
       }
+    }
+    // momenta of the first pass while the loads are in flight: one Philox draw
+    // per site pair.  With an even row length the pair of column x (even) is
+    // (x, x + 1), held by the neighbouring lane; over two planes the even lane
+    // draws the pair of plane k, the odd lane that of plane k + 1, and each
+    // passes its partner the partner's value.
+    if (MODE == PASS_FIRST && !cd.p_given && (L0 & 1) == 0) {
+      const bool even = (gx & 1) == 0;
+#pragma unroll
+      for (int k = 0; k < ZR; k += 2) {
+        const int64_t z = tl.z0 + k + (even ? 0 : 1);
+        const int64_t site = (gx & ~1) + (int64_t)L0 * (gy + (int64_t)L1 * z);
+        T z0, z1;
+        normal_pair<T>(cd, (uint32_t)traj, TAG_MOM, site >> 1, z0, z1);
+        const T other = __shfl_xor(even ? z1 : z0, 1, 64);
+        pcol[k] = even ? z0 : other;
+        pcol[k + 1] = even ? other : z1;
+      }
+    }
+    if (h < NH) {
 #pragma unroll
       for (int k = 0; k < NPP; ++k) {
         if (pz0 + k < PZ) {
@@ -583,7 +603,7 @@ __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict
         F = F + bcol[k];
         T p;
         if (MODE == PASS_FIRST) {
-          if (cd.p_given) {
+          if (cd.p_given || (L0 & 1) == 0) {
             p = pcol[k];
           } else {
             const int64_t site = gx + (int64_t)L0 * (gy + (int64_t)L1 * z);
