@@ -117,7 +117,12 @@ typedef struct {
  *   psi0        host, N values, or NULL: psi0 ~ N(0,1) from the TAG_INIT stream.
  *   replay_accept host, n_traj bytes, or NULL: force the accept decisions
  *               (test hook for comparing trajectories past a point where FP32
- *               and FP64 decisions could differ). */
+ *               and FP64 decisions could differ).
+ *   n_therm     thermalisation trajectories (>= 0; the paper leaves the length
+ *               open): the summary (acceptance, mean exp(-dH), non-finite
+ *               count) covers trajectories n_therm, n_therm + 1, ... only;
+ *               every trajectory is still recorded in the series.  0 (a
+ *               zero-initialised struct) counts them all. */
 typedef struct {
   int32_t n_md;
   int32_t n_traj;
@@ -125,7 +130,7 @@ typedef struct {
   int32_t integrator;
   int32_t flip_every;
   int32_t precision;
-  int32_t pad;
+  int32_t n_therm;
   uint64_t seed;
   uint64_t chain_id;
   const double* psi0;
@@ -178,6 +183,32 @@ int ihmc_chains_advance(ihmc_chains* chains, int32_t n_traj);
 int ihmc_chains_result(ihmc_chains* chains, int32_t i, ihmc_result* out);
 int ihmc_chains_destroy(ihmc_chains* chains);
 
+/* Checkpoint and resume of chain i (0 <= i < n).  The Philox streams are
+ * counter based (key = seed, counters = site pair, trajectory, chain_id,
+ * purpose), so a chain's state after t trajectories is its accepted field,
+ * S of that field in exact fixed point, the estimator sums, the sign, the
+ * counters and the series so far; a chain restored from it continues exactly
+ * (bit for bit) as the original would have.
+ *
+ * ihmc_chains_checkpoint waits for the chains' queued work, then writes the
+ * state into the caller's host buffer `buf` of *bytes bytes.  With buf NULL it
+ * only stores the size needed in *bytes.  A buffer smaller than that fails
+ * with IHMC_E_INVAL (and *bytes = the size needed).  The layout is private to
+ * this library version: a header with the chain's identity and state, the
+ * stored field (state precision, row pitch included), then the records.
+ *
+ * ihmc_chains_restore waits for queued work, then replaces chain i's state
+ * with the checkpoint in buf (bytes long).  Chain i must have been created
+ * with the same lattice and run parameters (dimensions, precision, couplings,
+ * field, C, n_md, traj_len, integrator, flip_every, seed, chain_id; n_traj may
+ * be larger, and must cover the trajectories already done).  A buffer that is
+ * not such a checkpoint, is truncated, or belongs to a chain with other
+ * parameters fails with IHMC_E_INVAL and leaves the chain unchanged.  The
+ * chain then continues at the checkpoint's trajectory index; further
+ * ihmc_chains_advance calls count against its capacity from there. */
+int ihmc_chains_checkpoint(ihmc_chains* chains, int32_t i, void* buf, uint64_t* bytes);
+int ihmc_chains_restore(ihmc_chains* chains, int32_t i, const void* buf, uint64_t bytes);
+
 /* One chain: create, advance run->n_traj, fetch, destroy.  Synchronous. */
 int ihmc_run_lattice(ihmc_ctx* ctx, const ihmc_lattice* lat, const ihmc_run* run, ihmc_result* out);
 /* n chains (arrays of n descriptors and n results).  Synchronous. */
@@ -204,6 +235,11 @@ int ihmc_dense_create(ihmc_ctx* ctx, const ihmc_dense* model, int32_t n, const i
 int ihmc_dense_advance(ihmc_dense_chains* chains, int32_t n_traj);
 /* Wait, then copy chain i's series and summary, as ihmc_chains_result. */
 int ihmc_dense_result(ihmc_dense_chains* chains, int32_t i, ihmc_result* out);
+/* Checkpoint and resume of dense chain i, as ihmc_chains_checkpoint and
+ * ihmc_chains_restore (the model, the products and the run parameters of the
+ * restoring chain must match; C must be the same number). */
+int ihmc_dense_checkpoint(ihmc_dense_chains* chains, int32_t i, void* buf, uint64_t* bytes);
+int ihmc_dense_restore(ihmc_dense_chains* chains, int32_t i, const void* buf, uint64_t bytes);
 /* The shift in use and the Lanczos estimate: out[0] = C, out[1] = theta,
  * out[2] = |r|, out[3] = Lanczos steps, out[4] = CG iterations (largest of
  * the solves). */

@@ -21,10 +21,11 @@ __device__ __forceinline__ void finalize_trajectory(const ChainDev& cd, ChainSta
   double dH = fixed_to_double(sub128(H_new, H_old));
   uint32_t flags = 0u;
   bool finite = (bad == 0u);
+  const bool counted = (t >= cd.n_therm);  // past thermalisation: enters the summary
   if (!finite) {
     dH = __builtin_nan("");
     flags |= REC_NONFINITE;
-    st->n_nonfinite += 1;
+    if (counted) st->n_nonfinite += 1;
   }
   if (finite && st->cur_bad) dH = -__builtin_inf();  // leaving a state of zero weight
   bool accept;
@@ -34,7 +35,7 @@ __device__ __forceinline__ void finalize_trajectory(const ChainDev& cd, ChainSta
     const double r = uniform_at(cd, (uint32_t)t, TAG_ACC);
     accept = finite && (dH <= 0.0 || r < exp(-dH));
   }
-  if (finite && !st->cur_bad) st->sum_exp_mdh += exp(-dH);
+  if (finite && !st->cur_bad && counted) st->sum_exp_mdh += exp(-dH);
   if (accept) {
     st->cur_bad = 0;
     st->S_lo = sum[T_S].lo;
@@ -44,7 +45,7 @@ __device__ __forceinline__ void finalize_trajectory(const ChainDev& cd, ChainSta
     st->sum_ut = fixed_to_double(sum[T_UT]);
     st->cur = last_buf;
     st->sign = 1;
-    st->n_acc += 1;
+    if (counted) st->n_acc += 1;
     flags |= REC_ACCEPT;
   }
   if (cd.flip_every > 0 && (t + 1) % cd.flip_every == 0) {

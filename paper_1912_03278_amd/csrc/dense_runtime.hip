@@ -188,6 +188,7 @@ struct DenseChains {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int enqueued = 0;
+  std::vector<int> base;  // per chain: trajectory index at enqueued = 0 (non-zero after a restore)
 
   void* dalloc(uint64_t bytes) {
     void* p = ctx->arena.alloc(bytes);
@@ -249,6 +250,7 @@ int DenseChains::build(const ihmc_dense& md, int32_t n, const ihmc_run* runs, in
     if (r.integrator != LEAPFROG && r.integrator != OMELYAN)
       return set_error(IHMC_E_INVAL, "chain %d: unknown integrator %d", i, r.integrator);
     if (r.flip_every < 0) return set_error(IHMC_E_INVAL, "chain %d: flip_every must be >= 0", i);
+    if (r.n_therm < 0) return set_error(IHMC_E_INVAL, "chain %d: n_therm must be >= 0", i);
     if (r.precision != IHMC_F32)
       return set_error(IHMC_E_UNSUPPORTED, "chain %d: dense chains keep FP32 state (precision 4)", i);
     if (r.n_md != r0.n_md || r.integrator != r0.integrator || r.traj_len != r0.traj_len)
@@ -326,6 +328,7 @@ int DenseChains::build(const ihmc_dense& md, int32_t n, const ihmc_run* runs, in
     HIPCHK(dense_field(ht, N, Np, md.beta, sqJ, hp, bfield, s), "field");
   }
   cd.resize(B);
+  base.assign(B, 0);
   for (int i = 0; i < B; ++i) {
     const ihmc_run& r = runs[i];
     ChainDev& c = cd[i];
@@ -352,6 +355,7 @@ int DenseChains::build(const ihmc_dense& md, int32_t n, const ihmc_run* runs, in
     c.b0 = h_kind == 1 ? c.hp0 / sqJ : 0.0;
     c.eps = r.traj_len / r.n_md;
     c.cap = r.n_traj;
+    c.n_therm = r.n_therm;
     c.precision = IHMC_F32;
     c.psi = dalloc(4 * 3 * (uint64_t)Np);
     c.p = dalloc(4 * (uint64_t)Np);
@@ -464,9 +468,9 @@ hipError_t DenseChains::enqueue_round(hipStream_t s) {
 int DenseChains::advance(int32_t n_traj) {
   if (n_traj < 0) return set_error(IHMC_E_INVAL, "n_traj must be >= 0");
   for (int i = 0; i < B; ++i)
-    if (enqueued + n_traj > cd[i].cap)
-      return set_error(IHMC_E_INVAL, "chain %d: %d trajectories exceed the capacity %d", i, enqueued + n_traj,
-                       cd[i].cap);
+    if (base[i] + enqueued + n_traj > cd[i].cap)
+      return set_error(IHMC_E_INVAL, "chain %d: %d trajectories exceed the capacity %d", i,
+                       base[i] + enqueued + n_traj, cd[i].cap);
   hipStream_t s = ctx->stream;
   if (n_traj == 0) return IHMC_OK;
   if (n_traj == 1 && !gexec) {
@@ -530,6 +534,26 @@ extern "C" int ihmc_dense_result(ihmc_dense_chains* ch, int32_t i, ihmc_result* 
   DenseChains& d = ch->impl;
   if (i < 0 || i >= d.B) return set_error(IHMC_E_INVAL, "chain index %d out of range", i);
   return result_from_device(d.ctx, d.cd[i], d.d_cd, i, out);
+}
+
+extern "C" int ihmc_dense_checkpoint(ihmc_dense_chains* ch, int32_t i, void* buf, uint64_t* bytes) {
+  if (!ch) return set_error(IHMC_E_INVAL, "chains is NULL");
+  CTX_OK(ch->impl.ctx);
+  DenseChains& d = ch->impl;
+  if (i < 0 || i >= d.B) return set_error(IHMC_E_INVAL, "chain index %d out of range", i);
+  return chain_checkpoint(d.ctx, d.cd[i], 0x100u + (uint64_t)d.nprod, buf, bytes);
+}
+
+extern "C" int ihmc_dense_restore(ihmc_dense_chains* ch, int32_t i, const void* buf, uint64_t bytes) {
+  if (!ch) return set_error(IHMC_E_INVAL, "chains is NULL");
+  CTX_OK(ch->impl.ctx);
+  DenseChains& d = ch->impl;
+  if (i < 0 || i >= d.B) return set_error(IHMC_E_INVAL, "chain index %d out of range", i);
+  int traj = 0;
+  int rc = chain_restore(d.ctx, d.cd[i], 0x100u + (uint64_t)d.nprod, buf, bytes, &traj);
+  if (rc) return rc;
+  d.base[i] = traj - d.enqueued;
+  return IHMC_OK;
 }
 
 extern "C" int ihmc_dense_info(ihmc_dense_chains* ch, double* out) {

@@ -65,6 +65,7 @@ struct ChainDev {
   int32_t precision;     // 4 or 8 (bytes of the state type)
   int32_t p_given;       // first pass reads p instead of drawing it (diagnostic)
   int32_t write_p_last;  // last pass stores the final momenta (diagnostic)
+  int32_t n_therm;       // trajectories before this index stay out of the summary counters
   void* psi;             // 3 * NP state values (three rotating buffers)
   void* p;               // NP state values
   const void* b;         // NP state values h'/sqrt(J') (per-site field) or null

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -273,6 +274,7 @@ void describe_chain(const ihmc_lattice& l, const ihmc_run& r, int flags, int cls
   c.precision = r.precision;
   c.p_given = (flags & BUILD_P_GIVEN) ? 1 : 0;
   c.write_p_last = (flags & BUILD_WRITE_P) ? 1 : 0;
+  c.n_therm = r.n_therm;
   c.tile_cls = cls;
   c.n_tiles = chain_tile_count(c);
 }
@@ -353,6 +355,7 @@ int validate(const ihmc_lattice& l, const ihmc_run& r, int idx) {
     return set_error(IHMC_E_INVAL, "chain %d: unknown integrator", idx);
   if (r.precision != 4 && r.precision != 8) return set_error(IHMC_E_INVAL, "chain %d: precision must be 4 or 8", idx);
   if (r.flip_every < 0) return set_error(IHMC_E_INVAL, "chain %d: flip_every must be >= 0", idx);
+  if (r.n_therm < 0) return set_error(IHMC_E_INVAL, "chain %d: n_therm must be >= 0", idx);
   return IHMC_OK;
 }
 
@@ -467,6 +470,7 @@ Chains::~Chains() {
 int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, int flags) {
   n = n_;
   cd.resize(n);
+  base.assign(n, 0);
   hipStream_t s = ctx->stream;
   std::vector<void*> temps;
   auto tmp_alloc = [&](uint64_t bytes) {
@@ -677,9 +681,9 @@ hipError_t Chains::enqueue_round(hipStream_t s) { return enqueue_round_plan(grou
 int Chains::advance(int32_t n_traj) {
   if (n_traj < 0) return set_error(IHMC_E_INVAL, "n_traj must be >= 0");
   for (int i = 0; i < n; ++i)
-    if (enqueued + n_traj > cd[i].cap)
-      return set_error(IHMC_E_INVAL, "chain %d: %d trajectories exceed the capacity %d", i, enqueued + n_traj,
-                       cd[i].cap);
+    if (base[i] + enqueued + n_traj > cd[i].cap)
+      return set_error(IHMC_E_INVAL, "chain %d: %d trajectories exceed the capacity %d", i,
+                       base[i] + enqueued + n_traj, cd[i].cap);
   hipStream_t s = ctx->stream;
   if (n_traj == 0) return IHMC_OK;
   if (n_traj == 1 && !gexec) {
@@ -698,6 +702,20 @@ int Chains::advance(int32_t n_traj) {
     for (int t = 0; t < n_traj; ++t) HIPCHK(hipGraphLaunch(gexec, s), "graph launch");
   }
   enqueued += n_traj;
+  return IHMC_OK;
+}
+
+int Chains::checkpoint(int32_t i, void* buf, uint64_t* bytes) {
+  if (i < 0 || i >= n) return set_error(IHMC_E_INVAL, "chain index %d out of range", i);
+  return chain_checkpoint(ctx, cd[i], 0, buf, bytes);
+}
+
+int Chains::restore(int32_t i, const void* buf, uint64_t bytes) {
+  if (i < 0 || i >= n) return set_error(IHMC_E_INVAL, "chain index %d out of range", i);
+  int traj = 0;
+  int rc = chain_restore(ctx, cd[i], 0, buf, bytes, &traj);
+  if (rc) return rc;
+  base[i] = traj - enqueued;
   return IHMC_OK;
 }
 
@@ -730,8 +748,9 @@ int result_from_device(ihmc_ctx* ctx, const ChainDev& c, const ChainDev* d_cd, i
     if (out->flipped) out->flipped[t] = (r.flags & REC_FLIP) ? 1 : 0;
   }
   out->n_traj_done = st.traj;
-  out->acceptance = st.traj ? (double)st.n_acc / st.traj : 0.0;
-  const int64_t nf = st.traj - st.n_nonfinite;
+  const int64_t counted = std::max(0, st.traj - c.n_therm);  // trajectories past thermalisation
+  out->acceptance = counted ? (double)st.n_acc / (double)counted : 0.0;
+  const int64_t nf = counted - st.n_nonfinite;
   out->mean_exp_minus_dH = nf > 0 ? st.sum_exp_mdh / (double)nf : 0.0;
   out->n_nonfinite = st.n_nonfinite;
   if (out->psi_final) {
@@ -744,6 +763,163 @@ int result_from_device(ihmc_ctx* ctx, const ChainDev& c, const ChainDev* d_cd, i
     if (e != hipSuccess) return hip_fail(ctx, e, "psi export");
     if (e2 != hipSuccess) return hip_fail(ctx, e2, "psi export sync");
   }
+  return IHMC_OK;
+}
+
+// ------------------------------------------------------ checkpoint / resume ---
+//
+// A chain's state between trajectories: the accepted field (buffer `cur`),
+// ChainState (S in fixed point, estimator sums, sign, counters, next
+// trajectory index) and the records so far.  Every random number is a Philox
+// draw at counters that name the trajectory, so this is all the state there is.
+
+namespace {
+constexpr char kCkptMagic[8] = {'I', 'H', 'M', 'C', 'C', 'K', 'P', 'T'};
+constexpr uint32_t kCkptVersion = 1;
+
+struct CkptHeader {
+  char magic[8];
+  uint32_t version, header_bytes;
+  // identity of the chain: everything its trajectories depend on
+  int32_t ndim, L0, L1, L2;
+  int64_t N, NP;
+  int32_t precision, n_pass, integrator, flip_every;
+  uint32_t chain_id, seed_lo, seed_hi;
+  int32_t h_kind;
+  double C, sqJ, Jp, b0, hp0, eps, c_m, c_e, c_v;
+  uint64_t field_hash;  // FNV-1a of the per-site h' (0 without one)
+  uint64_t variant;     // path-specific form of the force (dense: limb products)
+  // state
+  ChainState st;
+  int32_t n_rec, pad;
+};
+
+void fill_identity(const ChainDev& c, uint64_t field_hash, uint64_t variant, CkptHeader& h) {
+  h.ndim = c.ndim;
+  h.L0 = c.L0;
+  h.L1 = c.L1;
+  h.L2 = c.L2;
+  h.N = c.N;
+  h.NP = c.NP;
+  h.precision = c.precision;
+  h.n_pass = c.n_pass;
+  h.integrator = c.integrator;
+  h.flip_every = c.flip_every;
+  h.chain_id = c.chain_id;
+  h.seed_lo = c.seed_lo;
+  h.seed_hi = c.seed_hi;
+  h.h_kind = c.h_kind;
+  h.C = c.C;
+  h.sqJ = c.sqJ;
+  h.Jp = c.Jp;
+  h.b0 = c.b0;
+  h.hp0 = c.hp0;
+  h.eps = c.eps;
+  h.c_m = c.c_m;
+  h.c_e = c.c_e;
+  h.c_v = c.c_v;
+  h.field_hash = field_hash;
+  h.variant = variant;
+}
+
+// FNV-1a over the per-site FP64 h' of the chain (device array of NP values).
+int field_hash(ihmc_ctx* ctx, const ChainDev& c, uint64_t* out) {
+  *out = 0;
+  if (c.h_kind != 2 || !c.hp) return IHMC_OK;
+  std::vector<double> hp((size_t)c.NP);
+  HIPCHK(hipMemcpyAsync(hp.data(), c.hp, 8 * (size_t)c.NP, hipMemcpyDeviceToHost, ctx->stream), "field download");
+  HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
+  uint64_t h = 1469598103934665603ull;
+  const unsigned char* b = (const unsigned char*)hp.data();
+  for (size_t k = 0; k < hp.size() * 8; ++k) h = (h ^ b[k]) * 1099511628211ull;
+  *out = h;
+  return IHMC_OK;
+}
+}  // namespace
+
+int chain_checkpoint(ihmc_ctx* ctx, const ChainDev& c, uint64_t variant, void* buf, uint64_t* bytes) {
+  if (!bytes) return set_error(IHMC_E_INVAL, "bytes is NULL");
+  hipStream_t s = ctx->stream;
+  HIPCHK(hipStreamSynchronize(s), "sync");
+  ChainState st;
+  HIPCHK(hipMemcpy(&st, c.st, sizeof st, hipMemcpyDeviceToHost), "state download");
+  const int n_rec = std::max(0, std::min(st.traj, c.cap));
+  const uint64_t field = (uint64_t)c.NP * (uint64_t)c.precision;
+  const uint64_t need = sizeof(CkptHeader) + field + (uint64_t)n_rec * sizeof(TrajRecord);
+  if (!buf) {
+    *bytes = need;
+    return IHMC_OK;
+  }
+  if (*bytes < need) {
+    const uint64_t have = *bytes;
+    *bytes = need;
+    return set_error(IHMC_E_INVAL, "checkpoint buffer of %llu bytes, %llu needed", (unsigned long long)have,
+                     (unsigned long long)need);
+  }
+  CkptHeader h;
+  std::memset(&h, 0, sizeof h);
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.version = kCkptVersion;
+  h.header_bytes = sizeof h;
+  uint64_t fh = 0;
+  int rc = field_hash(ctx, c, &fh);
+  if (rc) return rc;
+  fill_identity(c, fh, variant, h);
+  h.st = st;
+  h.n_rec = n_rec;
+  char* out = (char*)buf;
+  std::memcpy(out, &h, sizeof h);
+  HIPCHK(hipMemcpyAsync(out + sizeof h, (const char*)c.psi + (uint64_t)st.cur * field, field, hipMemcpyDeviceToHost, s),
+         "field download");
+  if (n_rec)
+    HIPCHK(hipMemcpyAsync(out + sizeof h + field, c.rec, sizeof(TrajRecord) * (size_t)n_rec, hipMemcpyDeviceToHost, s),
+           "records download");
+  HIPCHK(hipStreamSynchronize(s), "sync");
+  *bytes = need;
+  return IHMC_OK;
+}
+
+int chain_restore(ihmc_ctx* ctx, const ChainDev& c, uint64_t variant, const void* buf, uint64_t bytes, int* traj) {
+  if (!buf) return set_error(IHMC_E_INVAL, "buf is NULL");
+  if (bytes < sizeof(CkptHeader)) return set_error(IHMC_E_INVAL, "not a checkpoint (%llu bytes)", (unsigned long long)bytes);
+  CkptHeader h;
+  std::memcpy(&h, buf, sizeof h);
+  if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != kCkptVersion || h.header_bytes != sizeof h)
+    return set_error(IHMC_E_INVAL, "not a checkpoint of this library version");
+  uint64_t fh = 0;
+  hipStream_t s = ctx->stream;
+  HIPCHK(hipStreamSynchronize(s), "sync");
+  int rc = field_hash(ctx, c, &fh);
+  if (rc) return rc;
+  CkptHeader mine;
+  std::memset(&mine, 0, sizeof mine);
+  fill_identity(c, fh, variant, mine);
+  // compare the identity fields (the span between the version words and the state)
+  const size_t id0 = offsetof(CkptHeader, ndim), id1 = offsetof(CkptHeader, st);
+  if (std::memcmp((const char*)&h + id0, (const char*)&mine + id0, id1 - id0) != 0)
+    return set_error(IHMC_E_INVAL, "checkpoint of a chain with other parameters");
+  const ChainState& st = h.st;
+  if (st.traj < 0 || st.cur < 0 || st.cur > 2 || (st.sign != 1 && st.sign != -1) || h.n_rec != st.traj)
+    return set_error(IHMC_E_INVAL, "checkpoint state is inconsistent");
+  if (st.traj > c.cap)
+    return set_error(IHMC_E_INVAL, "checkpoint after %d trajectories, the chain's capacity is %d", st.traj, c.cap);
+  const uint64_t field = (uint64_t)c.NP * (uint64_t)c.precision;
+  const uint64_t need = sizeof h + field + (uint64_t)h.n_rec * sizeof(TrajRecord);
+  if (bytes != need)
+    return set_error(IHMC_E_INVAL, "checkpoint of %llu bytes, %llu expected", (unsigned long long)bytes,
+                     (unsigned long long)need);
+  ChainState ns = st;
+  ns.cur = 0;  // the field goes to buffer 0
+  ns.done = 0u;
+  ns.bad = 0u;
+  const char* in = (const char*)buf;
+  HIPCHK(hipMemcpyAsync(c.psi, in + sizeof h, field, hipMemcpyHostToDevice, s), "field upload");
+  if (h.n_rec)
+    HIPCHK(hipMemcpyAsync(c.rec, in + sizeof h + field, sizeof(TrajRecord) * (size_t)h.n_rec, hipMemcpyHostToDevice, s),
+           "records upload");
+  HIPCHK(hipMemcpyAsync(c.st, &ns, sizeof ns, hipMemcpyHostToDevice, s), "state upload");
+  HIPCHK(hipStreamSynchronize(s), "sync");
+  *traj = st.traj;
   return IHMC_OK;
 }
 
@@ -791,6 +967,20 @@ extern "C" int ihmc_chains_result(ihmc_chains* ch, int32_t i, ihmc_result* out) 
   Chains* c = (Chains*)ch;
   CTX_OK(c->ctx);
   return c->result(i, out);
+}
+
+extern "C" int ihmc_chains_checkpoint(ihmc_chains* ch, int32_t i, void* buf, uint64_t* bytes) {
+  if (!ch) return set_error(IHMC_E_INVAL, "chains is NULL");
+  Chains* c = (Chains*)ch;
+  CTX_OK(c->ctx);
+  return c->checkpoint(i, buf, bytes);
+}
+
+extern "C" int ihmc_chains_restore(ihmc_chains* ch, int32_t i, const void* buf, uint64_t bytes) {
+  if (!ch) return set_error(IHMC_E_INVAL, "chains is NULL");
+  Chains* c = (Chains*)ch;
+  CTX_OK(c->ctx);
+  return c->restore(i, buf, bytes);
 }
 
 extern "C" int ihmc_chains_destroy(ihmc_chains* ch) {

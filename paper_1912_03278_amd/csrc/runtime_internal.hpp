@@ -26,6 +26,13 @@ hipError_t launch_export_psi(const ChainDev* d_cd, int ci, double* out, int64_t 
 hipError_t launch_export_field(const ChainDev* d_cd, int ci, double* out, const void* src, int64_t N, int precision,
                                hipStream_t s);
 int result_from_device(ihmc_ctx* ctx, const ChainDev& c, const ChainDev* d_cd, int ci, ihmc_result* out);
+// Checkpoint of one chain into a host buffer (buf NULL: size only), and its
+// restore into a chain with the same parameters (sets *traj to the
+// checkpoint's trajectory index).  `variant` names a path-specific form of the
+// force that must also match (0 for the lattice path).  Both wait for the
+// context stream.
+int chain_checkpoint(ihmc_ctx* ctx, const ChainDev& c, uint64_t variant, void* buf, uint64_t* bytes);
+int chain_restore(ihmc_ctx* ctx, const ChainDev& c, uint64_t variant, const void* buf, uint64_t bytes, int* traj);
 
 // First-fit sub-allocator over one device allocation (256-byte granules).
 struct Arena {
@@ -112,6 +119,7 @@ struct Chains {
   std::vector<hipStream_t> side;   // two per group: passes, and LAST passes
   std::vector<hipEvent_t> events;  // fork/join points of one round
   int enqueued = 0;
+  std::vector<int> base;  // per chain: trajectory index at enqueued = 0 (non-zero after a restore)
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
 
@@ -119,6 +127,8 @@ struct Chains {
   int build(int32_t n, const ihmc_lattice* lats, const ihmc_run* runs, int flags);
   hipError_t enqueue_round(hipStream_t s);
   int advance(int32_t n_traj);
+  int checkpoint(int32_t i, void* buf, uint64_t* bytes);
+  int restore(int32_t i, const void* buf, uint64_t bytes);
   int result(int32_t i, ihmc_result* out);
   ~Chains();
 };

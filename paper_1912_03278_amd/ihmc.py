@@ -33,7 +33,8 @@ EXPORTS = (
     "ihmc_run_dense", "ihmc_dense_force", "ihmc_min_eig", "ihmc_server_create", "ihmc_server_destroy",
     "ihmc_submit", "ihmc_poll", "ihmc_wait", "ihmc_fetch", "ihmc_cancel", "ihmc_server_stats",
     "ihmc_tile_shape", "ihmc_tune", "ihmc_tune_lookup", "ihmc_tune_pin", "ihmc_tune_save", "ihmc_tune_load",
-    "ihmc_tune_check",
+    "ihmc_tune_check", "ihmc_chains_checkpoint", "ihmc_chains_restore", "ihmc_dense_checkpoint",
+    "ihmc_dense_restore",
 )
 TUNE_RULE, TUNE_MEASURED, TUNE_PINNED = 0, 1, 2
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED, REQ_FAILED = 0, 1, 2, 3, 4
@@ -58,7 +59,7 @@ class _Dense(C.Structure):
 class _Run(C.Structure):
     _fields_ = [("n_md", C.c_int32), ("n_traj", C.c_int32), ("traj_len", C.c_double),
                 ("integrator", C.c_int32), ("flip_every", C.c_int32), ("precision", C.c_int32),
-                ("pad", C.c_int32), ("seed", C.c_uint64), ("chain_id", C.c_uint64),
+                ("n_therm", C.c_int32), ("seed", C.c_uint64), ("chain_id", C.c_uint64),
                 ("psi0", C.POINTER(C.c_double)), ("replay_accept", C.POINTER(C.c_uint8))]
 
 
@@ -106,6 +107,10 @@ def load():
     L.ihmc_chains_advance.argtypes = [vp, C.c_int32]
     L.ihmc_chains_result.argtypes = [vp, C.c_int32, C.POINTER(_Result)]
     L.ihmc_chains_destroy.argtypes = [vp]
+    L.ihmc_chains_checkpoint.argtypes = [vp, C.c_int32, vp, C.POINTER(C.c_uint64)]
+    L.ihmc_chains_restore.argtypes = [vp, C.c_int32, vp, C.c_uint64]
+    L.ihmc_dense_checkpoint.argtypes = [vp, C.c_int32, vp, C.POINTER(C.c_uint64)]
+    L.ihmc_dense_restore.argtypes = [vp, C.c_int32, vp, C.c_uint64]
     L.ihmc_run_lattice.argtypes = [vp, C.POINTER(_Lattice), C.POINTER(_Run), C.POINTER(_Result)]
     L.ihmc_run_batch.argtypes = [vp, C.c_int32, C.POINTER(_Lattice), C.POINTER(_Run), C.POINTER(_Result)]
     L.ihmc_force.argtypes = [vp, C.POINTER(_Lattice), C.c_int32, _DP, _DP]
@@ -253,11 +258,13 @@ class Run:
     chain_id: int = 0
     psi0: object = None
     replay_accept: object = None
+    n_therm: int = 0
 
     def _c(self, keep):
         s = _Run()
         s.n_md, s.n_traj, s.traj_len = int(self.n_md), int(self.n_traj), float(self.traj_len)
         s.integrator, s.flip_every, s.precision = int(self.integrator), int(self.flip_every), int(self.precision)
+        s.n_therm = int(self.n_therm)
         s.seed, s.chain_id = int(self.seed), int(self.chain_id)
         p0 = _f64(self.psi0)
         keep.append(p0)
@@ -473,6 +480,14 @@ class Context:
         return out
 
 
+def _checkpoint(fn, h, i):
+    n = C.c_uint64(0)
+    _check(fn(h, int(i), None, C.byref(n)))
+    buf = C.create_string_buffer(n.value)
+    _check(fn(h, int(i), buf, C.byref(n)))
+    return buf.raw[:n.value]
+
+
 class Chains:
     """Chains resident on the device; advance() enqueues trajectories asynchronously."""
 
@@ -495,6 +510,15 @@ class Chains:
         r, a = _result_struct(self.runs[i].n_traj, self.lats[i].N, want_psi)
         _check(load().ihmc_chains_result(self.h, int(i), C.byref(r)))
         return _result_dict(r, a)
+
+    def checkpoint(self, i):
+        """State of chain i after the queued trajectories, as bytes."""
+        return _checkpoint(load().ihmc_chains_checkpoint, self.h, i)
+
+    def restore(self, i, data):
+        """Continue chain i from a checkpoint of a chain with the same parameters."""
+        buf = C.create_string_buffer(bytes(data), len(data))
+        _check(load().ihmc_chains_restore(self.h, int(i), buf, len(data)))
 
     def groups(self):
         n = C.c_int32()
@@ -547,6 +571,15 @@ class DenseChains:
         r, a = _result_struct(self.runs[i].n_traj, self.model.N, want_psi)
         _check(load().ihmc_dense_result(self.h, int(i), C.byref(r)))
         return _result_dict(r, a)
+
+    def checkpoint(self, i):
+        """State of chain i after the queued trajectories, as bytes."""
+        return _checkpoint(load().ihmc_dense_checkpoint, self.h, i)
+
+    def restore(self, i, data):
+        """Continue chain i from a checkpoint of a chain of the same model and parameters."""
+        buf = C.create_string_buffer(bytes(data), len(data))
+        _check(load().ihmc_dense_restore(self.h, int(i), buf, len(data)))
 
     def info(self):
         out = np.zeros(5)
