@@ -101,6 +101,9 @@ def group_rows(chains, reps, modes=(1,)):
     rows = []
     for g in range(chains.groups()):
         info = chains.group_info(g)
+        if info["cls"] < 0:  # LDS-resident chains: whole trajectories per launch, no passes to time
+            rows.append(dict(ndim=info["ndim"], tiles="resident", chains=info["chains"], sites=info["sites"]))
+            continue
         shape = ihmc.tile_shape(info["ndim"], info["cls"])
         row = dict(ndim=info["ndim"], tiles="x".join(map(str, shape if info["ndim"] == 3 else shape[:2])),
                    chains=info["chains"], sites=info["sites"])
@@ -262,9 +265,10 @@ def bench_batched(args):
     # one launch group per tile class in use (all chains are FP32 2D)
     kern = group_rows(chains, args.timing_reps)
     for k in kern:
-        k["middle_GBs"] = round(20 * k["sites"] / (k["middle_us"] * 1e-6) / 1e9, 1)
-        k["middle_us"] = round(k["middle_us"], 2)
-    dom = max(kern, key=lambda k: k["sites"])
+        if "middle_us" in k:
+            k["middle_GBs"] = round(20 * k["sites"] / (k["middle_us"] * 1e-6) / 1e9, 1)
+            k["middle_us"] = round(k["middle_us"], 2)
+    dom = max((k for k in kern if "middle_us" in k), key=lambda k: k["sites"])
     achieved = 20 * dom["sites"] / (dom["middle_us"] * 1e-6) / 1e9
     copy_bytes = 512 << 20
     copy_gbs = 2 * copy_bytes / (ctx.copy_bandwidth(copy_bytes, reps=10) * 1e-6) / 1e9

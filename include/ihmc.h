@@ -165,6 +165,16 @@ void* ihmc_ctx_stream(ihmc_ctx* ctx);
 int ihmc_ctx_sync(ihmc_ctx* ctx);
 /* Bytes of the arena in use / in total. */
 int ihmc_ctx_memory(ihmc_ctx* ctx, uint64_t* used, uint64_t* total);
+/* Small chains run whole trajectories in one workgroup with the field, the
+ * momenta and w held in LDS (one launch per round, or per advance when every
+ * chain of a set is resident), instead of one launch per pass.  The per-site
+ * arithmetic and the grouping of the exact sums are those of the tiled
+ * passes, so results are bit-identical either way.  Chains created after this
+ * call with at most max_sites sites, and small enough for the LDS, run
+ * resident: max_sites < 0 (the default) admits every chain that fits, 0 none.
+ * *fp32_fit / *fp64_fit (may be NULL) receive the largest chains that fit
+ * without a per-site field (a per-site field takes a fifth array). */
+int ihmc_ctx_set_resident(ihmc_ctx* ctx, int64_t max_sites, int64_t* fp32_fit, int64_t* fp64_fit);
 const char* ihmc_last_error(void);
 
 /* ---- resident chains (the hot path) --------------------------------------- */

@@ -12,8 +12,9 @@ namespace ihmc {
 
 // Metropolis decision and record, run by one thread of the last block of a LAST
 // pass once the block has gathered the chain's accumulators (`sum`, `bad`).
-__device__ __forceinline__ void finalize_trajectory(const ChainDev& cd, ChainState* st, int last_buf,
-                                                    const u128* sum, uint32_t bad) {
+// Returns the record's flags (REC_ACCEPT, REC_FLIP, REC_NONFINITE).
+__device__ __forceinline__ uint32_t finalize_trajectory(const ChainDev& cd, ChainState* st, int last_buf,
+                                                        const u128* sum, uint32_t bad) {
   const int t = st->traj;
   const u128 S_old{st->S_lo, st->S_hi};
   const u128 H_old = add128(sum[T_K0], S_old);
@@ -81,6 +82,7 @@ __device__ __forceinline__ void finalize_trajectory(const ChainDev& cd, ChainSta
   st->traj = t + 1;
   __hip_atomic_store(&st->bad, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_store(&st->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return flags;
 }
 
 __device__ __forceinline__ void finalize_measure(ChainState* st, const u128* sum, uint32_t bad) {

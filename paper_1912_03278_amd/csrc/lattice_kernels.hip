@@ -660,6 +660,247 @@ __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict
   block_accumulate<MODE, 4>(cd, st, acc, bad, cur, j, tix);
 }
 
+// ---------------------------------------------------- LDS-resident chains ---
+//
+// One workgroup runs whole trajectories of one small chain (one Tile entry per
+// chain names it) with the accepted field, the working field, the momenta, w
+// and the per-site field held in LDS in logical site order: every pass of the
+// trajectory, its FP64 sums and the Metropolis step in one launch, with no
+// partial-sum table and no launch per pass.  The per-site arithmetic and the
+// grouping of the FP64 sums (x-aligned quads of sites; in 3D each column first
+// summed over an aligned 4-plane slab, in z order) are those of the tiled
+// passes, so a resident chain's trajectory is bit-identical to the tiled one.
+// n_traj = 0 measures S and the estimator sums of the accepted field (the
+// set-up pass) instead.
+constexpr int RES_THREADS = 256;
+// field arrays: under half of the 160 KiB LDS with the reduction scratch, so
+// two chains share a CU; 64 x 64 FP32 chains fit (without a per-site field)
+constexpr int RES_LDS_BYTES = 81408;
+
+int resident_max_sites(int precision, bool site_field) { return RES_LDS_BYTES / ((site_field ? 5 : 4) * precision); }
+
+template <typename T, int NDIM>
+__global__ __launch_bounds__(RES_THREADS) void lattice_resident(const ChainDev* __restrict__ chains,
+                                                                const Tile* __restrict__ tiles, int n_traj) {
+  __shared__ __align__(16) unsigned char lds[RES_LDS_BYTES];
+  __shared__ u128 sRed[RES_THREADS / 64][NTERM];
+  __shared__ uint32_t sBad[RES_THREADS / 64];
+  __shared__ int sSign, sTraj;
+  __shared__ uint32_t sFlags;
+  const ChainDev& cd = chains[tiles[blockIdx.x].chain];
+  ChainState* st = cd.st;
+  const int L0 = cd.L0, L1 = cd.L1, L2 = (NDIM == 3) ? cd.L2 : 1;
+  const int N = (int)cd.N;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool site_field = (cd.h_kind == 2);
+  T* sA = reinterpret_cast<T*>(lds);  // accepted field as stored (sign not applied)
+  T* sP = sA + N;                     // working field
+  T* sM = sP + N;                     // momenta
+  T* sW = sM + N;                     // w
+  T* sB = sW + N;                     // h'/sqrt(J') per site (site field only)
+  const int pitch = cd.pitch, plane = L0 * L1;
+  const int cur = st->cur;
+  gmem<T>* __restrict__ gpsi = (gmem<T>*)cd.psi + (int64_t)cur * cd.NP;
+  for (int i = tid; i < N; i += RES_THREADS) {
+    const int64_t g = (i % L0) + (int64_t)pitch * (i / L0);
+    sA[i] = gpsi[g];
+    if (site_field) sB[i] = ((const gmem<T>*)cd.b)[g];
+  }
+  const T b_uniform = (T)cd.b0;
+  const T Ct = (T)cd.C;
+  const T at = (T)cd.sqJ;
+
+  // periodic neighbours of logical site i = x + L0 (y + L1 z)
+  struct Nb {
+    int xm, xp, ym, yp, zm, zp;
+  };
+  auto nbrs = [&](int i, int x, int y, int z) {
+    Nb n;
+    n.xm = i + (x == 0 ? L0 - 1 : -1);
+    n.xp = i + (x == L0 - 1 ? 1 - L0 : 1);
+    n.ym = i + (y == 0 ? (L1 - 1) * L0 : -L0);
+    n.yp = i + (y == L1 - 1 ? -(L1 - 1) * L0 : L0);
+    n.zm = i, n.zp = i;
+    if (NDIM == 3) {
+      n.zm = i + (z == 0 ? (L2 - 1) * plane : -plane);
+      n.zp = i + (z == L2 - 1 ? -(L2 - 1) * plane : plane);
+    }
+    return n;
+  };
+  // FP64 sums of per-site terms into fixed point, grouped as in the tiled
+  // passes: per x-aligned quad (2D), per quad of columns each summed over an
+  // aligned 4-plane slab (3D).  term(i, x, y, z, out) fills the K terms
+  // listed in `which`; sites past the row end contribute zeros.
+  const int nq = (L0 + 3) / 4, ns = (NDIM == 3) ? (L2 + 3) / 4 : 1;
+  const int n_units = nq * L1 * ns;
+  auto unit_sums = [&](auto term, const int* which, int K, u128* acc, uint32_t& bad) {
+    for (int u = tid; u < n_units; u += RES_THREADS) {
+      const int q = u % nq, r = u / nq, y = r % L1, sl = r / L1;
+      double col[5][4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+#pragma unroll
+        for (int a = 0; a < 5; ++a) col[a][e] = 0.0;
+        const int x = 4 * q + e;
+        if (x >= L0) continue;
+        const int z0 = 4 * sl, z1 = (NDIM == 3) ? min(z0 + 4, L2) : 1;
+        for (int z = z0; z < z1; ++z) {
+          double v[5];
+          term(x + L0 * (y + L1 * z), x, y, z, v);
+          for (int a = 0; a < K; ++a) col[a][e] = col[a][e] + v[a];
+        }
+      }
+      for (int a = 0; a < K; ++a)
+        acc[which[a]] = add128(acc[which[a]], to_fixed(quad_sum(col[a][0], col[a][1], col[a][2], col[a][3]), bad));
+    }
+  };
+  // S-density, psi, psi h', u tanh(sqrt(J') u) of the field in sP (FP64)
+  auto action_terms = [&](int i, int x, int y, int z, double* v) {
+    const Nb n = nbrs(i, x, y, z);
+    double nb = ((double)sP[n.xm] + (double)sP[n.xp]) + ((double)sP[n.ym] + (double)sP[n.yp]);
+    if (NDIM == 3) nb = nb + ((double)sP[n.zm] + (double)sP[n.zp]);
+    double h[4];
+    h_terms(cd, (double)sP[i], nb, x + (int64_t)pitch * (y + (int64_t)L1 * z), true, h);
+    v[0] = h[0];
+    v[1] = h[1];
+    v[2] = h[2];
+    v[3] = h[3];
+  };
+  // the block's fixed-point totals, for thread 0
+  auto block_total = [&](const u128* acc, uint32_t bad, u128* sum) {
+#pragma unroll
+    for (int a = 0; a < NTERM; ++a) {
+      const u128 v = wave_sum128(acc[a]);
+      if (lane == 0) sRed[wave][a] = v;
+    }
+    const unsigned long long any = __ballot(bad != 0u);
+    if (lane == 0) sBad[wave] = any ? 1u : 0u;
+    __syncthreads();
+    uint32_t b = 0u;
+    if (tid == 0) {
+      for (int a = 0; a < NTERM; ++a) {
+        u128 v = sRed[0][a];
+        for (int w = 1; w < RES_THREADS / 64; ++w) v = add128(v, sRed[w][a]);
+        sum[a] = v;
+      }
+      for (int w = 0; w < RES_THREADS / 64; ++w) b |= sBad[w];
+    }
+    return b;
+  };
+  auto coords = [&](int i, int& x, int& y, int& z) {
+    x = i % L0;
+    const int r = i / L0;
+    y = r % L1;
+    z = r / L1;
+  };
+
+  if (n_traj == 0) {  // set-up: S and the estimator sums of the accepted field
+    const int sign = st->sign;
+    for (int i = tid; i < N; i += RES_THREADS) sP[i] = neg_if(sA[i], sign);
+    __syncthreads();
+    u128 acc[NTERM];
+    for (int a = 0; a < NTERM; ++a) acc[a] = u128{0ull, 0ull};
+    uint32_t bad = 0u;
+    const int which[4] = {T_S, T_PSI, T_PSIH, T_UT};
+    unit_sums(action_terms, which, 4, acc, bad);
+    u128 sum[NTERM];
+    const uint32_t b = block_total(acc, bad, sum);
+    if (tid == 0) finalize_measure(st, sum, b);
+    return;
+  }
+
+  for (int t = 0; t < n_traj; ++t) {
+    if (tid == 0) {
+      sSign = st->sign;
+      sTraj = st->traj;
+    }
+    __syncthreads();
+    const int sign = sSign;
+    const uint32_t traj = (uint32_t)sTraj;
+    // working field; fresh momenta, one Philox draw per site pair
+    for (int i = tid; i < N; i += RES_THREADS) sP[i] = neg_if(sA[i], sign);
+    for (int pr = tid; 2 * pr < N; pr += RES_THREADS) {
+      T z0, z1;
+      normal_pair<T>(cd, traj, TAG_MOM, pr, z0, z1);
+      sM[2 * pr] = z0;
+      if (2 * pr + 1 < N) sM[2 * pr + 1] = z1;
+    }
+    __syncthreads();
+    u128 acc[NTERM];
+    for (int a = 0; a < NTERM; ++a) acc[a] = u128{0ull, 0ull};
+    uint32_t bad = 0u;
+    {
+      const int which[1] = {T_K0};
+      unit_sums([&](int i, int, int, int, double* v) {
+        const double pd = (double)sM[i];
+        v[0] = 0.5 * pd * pd;
+      }, which, 1, acc, bad);
+    }
+    // kick-drift passes; the last one kicks only
+    for (int j = 0; j < cd.n_pass; ++j) {
+      for (int i = tid; i < N; i += RES_THREADS) {
+        int x, y, z;
+        coords(i, x, y, z);
+        const Nb n = nbrs(i, x, y, z);
+        const T c = sP[i];
+        T s = (sP[n.xm] + sP[n.xp]) + (sP[n.ym] + sP[n.yp]);
+        if (NDIM == 3) s = s + (sP[n.zm] + sP[n.zp]);
+        const T u = fma_t(Ct, c, s);
+        sW[i] = fma_t(at, tanh_state(at * u), -c);
+      }
+      __syncthreads();
+      double kick_d = 0.0, drift_d = 0.0;
+      pass_coeffs(cd, j, kick_d, drift_d);
+      const T kick = (T)kick_d, drift = (T)drift_d;
+      const bool last = (j == cd.n_pass - 1);
+      for (int i = tid; i < N; i += RES_THREADS) {
+        int x, y, z;
+        coords(i, x, y, z);
+        const Nb n = nbrs(i, x, y, z);
+        T sw = (sW[n.xm] + sW[n.xp]) + (sW[n.ym] + sW[n.yp]);
+        if (NDIM == 3) sw = sw + (sW[n.zm] + sW[n.zp]);
+        T F = fma_t(Ct, sW[i], sw);
+        F = F + (site_field ? sB[i] : b_uniform);
+        const T p = fma_t(kick, F, sM[i]);
+        sM[i] = p;
+        if (!last) sP[i] = fma_t(drift, p, sP[i]);
+      }
+      __syncthreads();
+    }
+    // final kinetic energy and the action terms of the proposal
+    {
+      const int which[5] = {T_K1, T_S, T_PSI, T_PSIH, T_UT};
+      unit_sums([&](int i, int x, int y, int z, double* v) {
+        const double pd = (double)sM[i];
+        v[0] = 0.5 * pd * pd;
+        action_terms(i, x, y, z, v + 1);
+      }, which, 5, acc, bad);
+    }
+    u128 sum[NTERM];
+    const uint32_t b = block_total(acc, bad, sum);
+    if (tid == 0) sFlags = finalize_trajectory(cd, st, cur, sum, b);
+    __syncthreads();
+    if (sFlags & REC_ACCEPT)
+      for (int i = tid; i < N; i += RES_THREADS) sA[i] = sP[i];
+    __syncthreads();
+  }
+  // the accepted field back to its buffer (finalize kept st->cur = cur)
+  for (int i = tid; i < N; i += RES_THREADS) gpsi[(i % L0) + (int64_t)pitch * (i / L0)] = sA[i];
+}
+
+hipError_t launch_lattice_resident(int precision, int ndim, const ChainDev* chains, const Tile* tiles, int n_chains,
+                                   int n_traj, hipStream_t s) {
+  if (n_chains <= 0) return hipSuccess;
+  if (precision == 4) {
+    if (ndim == 2) lattice_resident<float, 2><<<n_chains, RES_THREADS, 0, s>>>(chains, tiles, n_traj);
+    else lattice_resident<float, 3><<<n_chains, RES_THREADS, 0, s>>>(chains, tiles, n_traj);
+  } else {
+    if (ndim == 2) lattice_resident<double, 2><<<n_chains, RES_THREADS, 0, s>>>(chains, tiles, n_traj);
+    else lattice_resident<double, 3><<<n_chains, RES_THREADS, 0, s>>>(chains, tiles, n_traj);
+  }
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ launch ---
 
 template <typename T, int BX, int BY>
@@ -756,6 +997,10 @@ TileShape tile_shape(int precision, int ndim, int cls) {
 
 hipError_t launch_lattice_pass(int precision, int ndim, int cls, int mode, const ChainDev* chains,
                                const Tile* tiles, int n_tiles, int j, hipStream_t s) {
+  if (cls == RESIDENT_CLASS) {  // whole trajectories only; the set-up measurement is n_traj = 0
+    if (mode != PASS_MEASURE) return hipErrorInvalidValue;
+    return launch_lattice_resident(precision, ndim, chains, tiles, n_tiles, 0, s);
+  }
   if (precision == 4) {
     if (ndim == 2) {
       if (cls == 1) return launch_mode2v<float, 16, 16>(mode, chains, tiles, n_tiles, j, s);

@@ -24,6 +24,18 @@ int tile_class_count(int ndim);
 // and tile class.
 TileShape tile_shape(int precision, int ndim, int cls);
 
+// Chains small enough for one workgroup's LDS run whole trajectories per launch
+// (lattice_resident): their launch group has this tile class, and one Tile
+// entry per chain.
+constexpr int RESIDENT_CLASS = -1;
+// Largest chain (sites) of a state precision (4 or 8 bytes) that fits, with or
+// without a per-site field.
+int resident_max_sites(int precision, bool site_field);
+// n_traj trajectories of each of n_chains resident chains (tiles[b].chain is
+// block b's chain); n_traj = 0 measures S and the estimator sums instead.
+hipError_t launch_lattice_resident(int precision, int ndim, const ChainDev* chains, const Tile* tiles, int n_chains,
+                                   int n_traj, hipStream_t s);
+
 // Launch one pass of kind `mode` (pass index j of the trajectory) over n_tiles
 // consecutive entries of `tiles`; all tiles must belong to chains of the given
 // precision, dimension and tile class.

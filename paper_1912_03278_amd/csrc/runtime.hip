@@ -279,8 +279,18 @@ void describe_chain(const ihmc_lattice& l, const ihmc_run& r, int flags, int cls
   c.n_tiles = chain_tile_count(c);
 }
 
-// Tiles of one chain in the tile shape of its launch group.
+int choose_class(ihmc_ctx* ctx, const ihmc_lattice& l, int precision, int flags) {
+  const int64_t N = lattice_sites(l);
+  const bool site_field = !(l.h_len == 0 || l.h_len == 1);
+  const int64_t fit = resident_max_sites(precision, site_field);
+  const int64_t lim = ctx->resident_sites < 0 ? fit : std::min(fit, ctx->resident_sites);
+  if (flags == 0 && N <= lim) return RESIDENT_CLASS;
+  return ctx->tune.class_for(tile_key(l, precision));
+}
+
+// Tiles of one chain in the tile shape of its launch group (one per resident chain).
 uint32_t chain_tile_count(const ChainDev& c) {
+  if (c.tile_cls == RESIDENT_CLASS) return 1u;
   const TileShape ts = tile_shape(c.precision, c.ndim, c.tile_cls);
   const uint32_t nz = c.ndim == 3 ? (uint32_t)((c.L2 + ts.bz - 1) / ts.bz) : 1u;
   return nz * (uint32_t)((c.L1 + ts.by - 1) / ts.by) * (uint32_t)((c.L0 + ts.bx - 1) / ts.bx);
@@ -302,14 +312,19 @@ void plan_groups(const std::vector<ChainDev>& cd, const std::vector<int>& member
     g.cls = std::get<2>(kv.first);
     g.order = kv.second;
     std::stable_sort(g.order.begin(), g.order.end(), [&](int a, int b) { return cd[a].n_pass > cd[b].n_pass; });
-    const TileShape ts = tile_shape(g.prec, g.ndim, g.cls);
+    const bool resident = (g.cls == RESIDENT_CLASS);
+    const TileShape ts = resident ? TileShape{1, 1, 1} : tile_shape(g.prec, g.ndim, g.cls);
     g.tile_off = (int)tiles.size() - base;
     for (int ci : g.order) {
       const ChainDev& c = cd[ci];
       g.tile_begin.push_back((int)tiles.size() - base - g.tile_off);
-      for (int z = 0; z < c.L2; z += (g.ndim == 3 ? ts.bz : 1))
-        for (int y = 0; y < c.L1; y += ts.by)
-          for (int x = 0; x < c.L0; x += ts.bx) tiles.push_back(Tile{ci, x, y, z});
+      if (resident) {
+        tiles.push_back(Tile{ci, 0, 0, 0});
+      } else {
+        for (int z = 0; z < c.L2; z += (g.ndim == 3 ? ts.bz : 1))
+          for (int y = 0; y < c.L1; y += ts.by)
+            for (int x = 0; x < c.L0; x += ts.bx) tiles.push_back(Tile{ci, x, y, z});
+      }
       g.n_pass.push_back(c.n_pass);
     }
     g.tile_begin.push_back((int)tiles.size() - base - g.tile_off);
@@ -440,6 +455,14 @@ extern "C" int ihmc_ctx_sync(ihmc_ctx* c) {
   return e == hipSuccess ? IHMC_OK : hip_fail(c, e, "hipStreamSynchronize");
 }
 
+extern "C" int ihmc_ctx_set_resident(ihmc_ctx* c, int64_t max_sites, int64_t* fp32_fit, int64_t* fp64_fit) {
+  if (!c) return set_error(IHMC_E_INVAL, "ctx is NULL");
+  c->resident_sites = max_sites < 0 ? -1 : max_sites;
+  if (fp32_fit) *fp32_fit = resident_max_sites(4, false);
+  if (fp64_fit) *fp64_fit = resident_max_sites(8, false);
+  return IHMC_OK;
+}
+
 extern "C" int ihmc_ctx_memory(ihmc_ctx* c, uint64_t* used, uint64_t* total) {
   if (!c) return set_error(IHMC_E_INVAL, "ctx is NULL");
   if (used) *used = c->arena.used;
@@ -489,7 +512,7 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
     int rc = validate(l, r, i);
     if (rc) return rc;
     ChainDev& c = cd[i];
-    describe_chain(l, r, flags, ctx->tune.class_for(tile_key(l, r.precision)), c);
+    describe_chain(l, r, flags, choose_class(ctx, l, r.precision, flags), c);
     const int64_t N = c.N, NP = c.NP;
     const int64_t pb = r.precision;
     c.psi = dalloc(3 * NP * pb);
@@ -644,8 +667,16 @@ hipError_t enqueue_round_plan(const std::vector<Group>& groups, const Tile* d_ti
     const Group& g = groups[gi];
     hipStream_t gs = side[2 * gi], ls = side[2 * gi + 1];
     if ((e = hipStreamWaitEvent(gs, fork, 0)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(ls, fork, 0)) != hipSuccess) return e;
     const Tile* base = d_tiles + g.tile_off;
+    if (g.cls == RESIDENT_CLASS) {  // one launch runs the whole trajectory of every chain of the group
+      e = launch_lattice_resident(g.prec, g.ndim, d_cd, base, g.tile_begin.back(), 1, gs);
+      if (e != hipSuccess) return e;
+      hipEvent_t j1 = next_event();
+      if ((e = hipEventRecord(j1, gs)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(s, j1, 0)) != hipSuccess) return e;
+      continue;
+    }
+    if ((e = hipStreamWaitEvent(ls, fork, 0)) != hipSuccess) return e;
     e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_FIRST, d_cd, base, g.tile_begin.back(), 0, gs);
     if (e != hipSuccess) return e;
     const int nc = (int)g.order.size();
@@ -686,6 +717,15 @@ int Chains::advance(int32_t n_traj) {
                        base[i] + enqueued + n_traj, cd[i].cap);
   hipStream_t s = ctx->stream;
   if (n_traj == 0) return IHMC_OK;
+  bool all_resident = true;
+  for (auto& g : groups) all_resident = all_resident && g.cls == RESIDENT_CLASS;
+  if (all_resident) {  // every chain in LDS: one launch per group runs all n_traj trajectories
+    for (auto& g : groups)
+      HIPCHK(launch_lattice_resident(g.prec, g.ndim, d_cd, d_tiles + g.tile_off, g.tile_begin.back(), n_traj, s),
+             "resident launch");
+    enqueued += n_traj;
+    return IHMC_OK;
+  }
   if (n_traj == 1 && !gexec) {
     HIPCHK(enqueue_round(s), "round launch");
   } else {
@@ -1038,7 +1078,7 @@ extern "C" int ihmc_force(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t precis
   ihmc_run r = diag_run(precision);
   r.psi0 = psi;
   Chains* c = nullptr;
-  int rc = make_chains(ctx, 1, lat, &r, 0, &c);
+  int rc = make_chains(ctx, 1, lat, &r, BUILD_TILED, &c);  // the force pass is a tiled-kernel mode
   if (rc) return rc;
   hipStream_t s = ctx->stream;
   const Group& g = c->groups[0];
@@ -1208,6 +1248,8 @@ extern "C" int ihmc_chains_time_pass(ihmc_chains* ch, int32_t group, int32_t mod
     return set_error(IHMC_E_INVAL, "only FIRST, MIDDLE and LAST passes can be timed");
   if (reps < 1) return set_error(IHMC_E_INVAL, "reps must be >= 1");
   const Group& g = c->groups[group];
+  if (g.cls == RESIDENT_CLASS)
+    return set_error(IHMC_E_UNSUPPORTED, "group %d runs LDS-resident whole trajectories, not passes", group);
   for (int ci : g.order)
     if (mode == PASS_MIDDLE && c->cd[ci].n_pass < 3)
       return set_error(IHMC_E_INVAL, "chain %d has no middle pass", ci);

@@ -46,7 +46,7 @@ struct Arena {
   void release(void* p);
 };
 
-enum BuildFlags : int { BUILD_P_GIVEN = 1, BUILD_WRITE_P = 2 };
+enum BuildFlags : int { BUILD_P_GIVEN = 1, BUILD_WRITE_P = 2, BUILD_TILED = 4 };  // TILED: never LDS-resident
 
 // Tile classes of the lattice passes: the built-in rule (lattice_kernels.hip)
 // and the per-shape choices of the autotuner (tune.hip), keyed by what the
@@ -70,6 +70,10 @@ struct TuneTable {
   int class_for(const TileKey& k);
 };
 TileKey tile_key(const ihmc_lattice& l, int precision);
+// Launch class of a new chain: RESIDENT_CLASS when the context allows and the
+// chain fits one workgroup's LDS (and no diagnostic flag is set), else the
+// tuning table's tile class (or the built-in rule's).
+int choose_class(ihmc_ctx* ctx, const ihmc_lattice& l, int precision, int flags);
 // JSON form of the table; load merges (entries replace equal keys).
 int tune_save(TuneTable& t, const char* path);
 int tune_load(TuneTable& t, const char* path);
@@ -157,4 +161,5 @@ struct ihmc_ctx {
   void* user = nullptr;
   bool dead = false;
   ihmc::TuneTable tune;
+  int64_t resident_sites = -1;  // chains up to this many sites run LDS-resident (-1: as many as fit, 0: none)
 };

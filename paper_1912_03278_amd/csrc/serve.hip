@@ -498,7 +498,7 @@ extern "C" int ihmc_submit(ihmc_server* sv, const ihmc_lattice* lat, const ihmc_
   if (run->replay_accept && run->n_traj > 0) r->replay.assign(run->replay_accept, run->replay_accept + run->n_traj);
   r->run.psi0 = nullptr;
   r->run.replay_accept = r->replay.empty() ? nullptr : r->replay.data();
-  r->cls = sv->ctx->tune.class_for(tile_key(r->lat, r->run.precision));
+  r->cls = choose_class(sv->ctx, r->lat, r->run.precision, 0);
   r->need = request_bytes(r->lat, r->run, r->cls);
   std::lock_guard<std::mutex> lk(sv->mu);
   if (sv->dead) {

@@ -34,7 +34,7 @@ EXPORTS = (
     "ihmc_submit", "ihmc_poll", "ihmc_wait", "ihmc_fetch", "ihmc_cancel", "ihmc_server_stats",
     "ihmc_tile_shape", "ihmc_tune", "ihmc_tune_lookup", "ihmc_tune_pin", "ihmc_tune_save", "ihmc_tune_load",
     "ihmc_tune_check", "ihmc_chains_checkpoint", "ihmc_chains_restore", "ihmc_dense_checkpoint",
-    "ihmc_dense_restore",
+    "ihmc_dense_restore", "ihmc_ctx_set_resident",
 )
 TUNE_RULE, TUNE_MEASURED, TUNE_PINNED = 0, 1, 2
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED, REQ_FAILED = 0, 1, 2, 3, 4
@@ -102,6 +102,7 @@ def load():
     L.ihmc_ctx_stream.restype = vp
     L.ihmc_ctx_sync.argtypes = [vp]
     L.ihmc_ctx_memory.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+    L.ihmc_ctx_set_resident.argtypes = [vp, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.ihmc_last_error.restype = C.c_char_p
     L.ihmc_chains_create.argtypes = [vp, C.c_int32, C.POINTER(_Lattice), C.POINTER(_Run), pp]
     L.ihmc_chains_advance.argtypes = [vp, C.c_int32]
@@ -300,7 +301,7 @@ def _result_dict(r, arrays):
 class Context:
     """A device context: HIP stream plus an arena of device memory from torch."""
 
-    def __init__(self, device=0, arena_bytes=1 << 30, use_torch=True):
+    def __init__(self, device=0, arena_bytes=1 << 30, use_torch=True, resident=-1):
         L = load()
         self._keep = []
         if use_torch:
@@ -325,6 +326,17 @@ class Context:
         h = C.c_void_p()
         _check(L.ihmc_ctx_create(int(device), int(arena_bytes), af, ff, None, C.byref(h)))
         self.h = h
+        if resident != -1:
+            self.set_resident(resident)
+
+    def set_resident(self, max_sites=-1):
+        """Chains created afterwards with at most max_sites sites (and small enough
+        for one workgroup's LDS) run LDS-resident whole trajectories; -1 admits
+        every chain that fits, 0 none.  Returns the largest FP32 and FP64 chains
+        that fit (without a per-site field)."""
+        f32, f64 = C.c_int64(), C.c_int64()
+        _check(load().ihmc_ctx_set_resident(self.h, int(max_sites), C.byref(f32), C.byref(f64)))
+        return f32.value, f64.value
 
     def close(self):
         if getattr(self, "h", None):

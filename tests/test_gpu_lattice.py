@@ -19,10 +19,12 @@ def nrm(a, b):
     return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
 
 
-@pytest.fixture(scope="module")
-def ctx():
+@pytest.fixture(scope="module", params=["resident", "tiled"])
+def ctx(request):
+    """Every case twice: small chains as LDS-resident whole trajectories (the
+    default), and with that path switched off, on the tiled passes."""
     from paper_1912_03278_amd import ihmc
-    c = ihmc.Context(arena_bytes=2 << 30)
+    c = ihmc.Context(arena_bytes=2 << 30, resident=-1 if request.param == "resident" else 0)
     yield c
     c.close()
 

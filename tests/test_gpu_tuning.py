@@ -36,7 +36,7 @@ def test_every_tile_class_gives_bitwise_equal_chains(ih, k):
     lat, prec = lattices(ih)[k]
     nd = len(lat.L)
     run = ih.Run(n_md=7, n_traj=6, precision=prec, seed=5 + k, chain_id=k, flip_every=2)
-    with ih.Context(arena_bytes=256 << 20) as ctx:
+    with ih.Context(arena_bytes=256 << 20, resident=0) as ctx:
         outs = []
         for cls in range(ih.tile_class_count(nd)):
             ctx.pin_tile(lat, cls, prec)
@@ -58,7 +58,7 @@ def test_mixed_classes_in_one_batch_equal_alone(ih):
     lat_c = ih.Lattice((18, 18, 18), beta=0.22, C=6.1)
     lats = [lat_a, lat_b, lat_c, lat_a]
     runs = [ih.Run(n_md=5 + i, n_traj=4, seed=30 + i, chain_id=i) for i in range(4)]
-    with ih.Context(arena_bytes=256 << 20) as ctx:
+    with ih.Context(arena_bytes=256 << 20, resident=0) as ctx:
         ctx.pin_tile(lat_a, 0)
         ctx.pin_tile(lat_b, 2)
         ctx.pin_tile(lat_c, 1)
@@ -83,7 +83,7 @@ def test_tune_measures_pins_and_round_trips(ih, tmp_path, monkeypatch):
     pinned = ih.Lattice((100, 100), beta=0.44, C=4.1)
     path = tmp_path / "tiles.json"
     monkeypatch.setenv("IHMC_TUNE_CACHE", str(path))
-    with ih.Context(arena_bytes=1 << 30) as ctx:
+    with ih.Context(arena_bytes=1 << 30, resident=0) as ctx:
         ctx.pin_tile(pinned, 1)
         # h = scalar and h absent share a key (only a per-site field changes the pass)
         assert ctx.tune(shapes + [pinned, ih.Lattice((72, 72), beta=0.3, C=4.5)], reps=3) == 3
@@ -107,14 +107,14 @@ def test_tune_measures_pins_and_round_trips(ih, tmp_path, monkeypatch):
         chosen = {lat.L: ctx.tile_class(lat)["cls"] for lat in shapes}
     # the cache file was written by tune and is read by a new context
     assert path.exists() and ih.check_tuning(str(path)) == 4
-    with ih.Context(arena_bytes=64 << 20) as ctx2:
+    with ih.Context(arena_bytes=64 << 20, resident=0) as ctx2:
         for lat in shapes:
             assert ctx2.tile_class(lat)["cls"] == chosen[lat.L]
             assert ctx2.tile_class(lat)["source"] == ih.TUNE_MEASURED
         assert ctx2.tile_class(pinned)["source"] == ih.TUNE_PINNED
     # explicit save / load without the environment variable
     monkeypatch.delenv("IHMC_TUNE_CACHE")
-    with ih.Context(arena_bytes=64 << 20) as ctx3:
+    with ih.Context(arena_bytes=64 << 20, resident=0) as ctx3:
         assert ctx3.tile_class(shapes[0])["source"] == ih.TUNE_RULE
         ctx3.load_tuning(str(path))
         assert ctx3.tile_class(shapes[0])["cls"] == chosen[shapes[0].L]
@@ -125,7 +125,7 @@ def test_tune_measures_pins_and_round_trips(ih, tmp_path, monkeypatch):
 
 def test_tune_rejects_bad_input(ih, tmp_path, monkeypatch):
     monkeypatch.delenv("IHMC_TUNE_CACHE", raising=False)
-    with ih.Context(arena_bytes=64 << 20) as ctx:
+    with ih.Context(arena_bytes=64 << 20, resident=0) as ctx:
         with pytest.raises(ih.IhmcError):
             ctx.tune([ih.Lattice((16, 16), beta=0.44, C=3.9)])  # C <= 2d
         with pytest.raises(ih.IhmcError):
