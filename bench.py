@@ -136,7 +136,7 @@ def streaming_point(args, copy_gbs):
     import torch
     from paper_1912_03278_amd import ihmc, inputs
     L = 8192
-    ctx = ihmc.Context(device=0, arena_bytes=3 << 30)
+    ctx = ihmc.Context(device=0, arena_bytes=3 << 30, resident=args.resident_sites)
     lat = ihmc.Lattice((L, L), beta=inputs.BETA_C_2D, C=4.1)
     ch = ihmc.Chains(ctx, [lat], [ihmc.Run(n_md=20, n_traj=8, precision=ihmc.F32, seed=2, chain_id=2)])
     ch.advance(1)
@@ -170,7 +170,7 @@ def bench_small(args):
     from paper_1912_03278_amd import ihmc, inputs
     w = inputs.small()
     K, W = args.steps, args.warmup
-    ctx = ihmc.Context(device=0, arena_bytes=64 << 20)
+    ctx = ihmc.Context(device=0, arena_bytes=64 << 20, resident=args.resident_sites)
     lat = ihmc.Lattice(w["L"], beta=w["beta"], C=w["C"])
     ch = ihmc.Chains(ctx, [lat], [ihmc.Run(n_md=w["n_md"], n_traj=W + K, precision=ihmc.F64, seed=w["seed"])])
     ch.advance(W)
@@ -189,7 +189,8 @@ def bench_small(args):
         "steps": K, "warmup": W, "ms_per_step": 1000.0 * dt / K, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "small: one 2D 8x8 chain, beta=0.40, C=4.1, h=0, n_md=10, FP64 state; one step = "
-                               "one trajectory (latency-bound by construction)", "sites": N},
+                               "one trajectory (latency-bound by construction)", "sites": N,
+                   "resident": args.resident},
         "observables": {"beta_eps_mean": float(np.mean(r["beta_eps"][W:])), "m2c_mean": float(np.mean(r["m2c"][W:])),
                         "acceptance": r["acceptance"],
                         "exact_beta_eps": -0.4889282573, "exact_m2": 0.4320990786},
@@ -218,7 +219,7 @@ def bench_batched(args):
 
     ws = inputs.batched(n_chains=args.chains)
     K, W = args.steps, args.warmup
-    ctx = ihmc.Context(device=0, arena_bytes=6 << 30)
+    ctx = ihmc.Context(device=0, arena_bytes=6 << 30, resident=args.resident_sites)
     lats = [ihmc.Lattice(w["L"], beta=w["beta"], C=w["C"], h=w["h"]) for w in ws]
     runs = [ihmc.Run(n_md=w["n_md"], n_traj=W + K, precision=ihmc.F32, seed=w["seed"], chain_id=w["chain_id"])
             for w in ws]
@@ -279,7 +280,8 @@ def bench_batched(args):
         "config": {"workload": f"batched: {len(ws)} 2D tori, L log-uniform [16,256], beta U[0.30,0.55], "
                                "h_x ~ N(0,0.05^2) per site, n_md U{8..32}, C=4.1, FP32 state, FP64 H; "
                                "one step = one trajectory of every chain",
-                   "chains": len(ws), "sites": sum(int(math.prod(w["L"])) for w in ws), **tiles},
+                   "chains": len(ws), "sites": sum(int(math.prod(w["L"])) for w in ws), **tiles,
+                   "resident": args.resident},
         "roofline": {"bound": "hbm", "kernel": f"fused middle pass, 2D, per-site field, {dom['tiles']}-tile group "
                                                f"({dom['chains']} chains)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -312,7 +314,7 @@ def bench_dense(args):
     w = inputs.dense()
     K, W = args.steps, args.warmup
     N, B, n_md = w["K"].shape[0], w["n_chains"], w["n_md"]
-    ctx = ihmc.Context(device=0, arena_bytes=2 << 30)
+    ctx = ihmc.Context(device=0, arena_bytes=2 << 30, resident=args.resident_sites)
     runs = [ihmc.Run(n_md=n_md, n_traj=W + K, precision=ihmc.F32, seed=w["seed"], chain_id=i) for i in range(B)]
     t0 = time.perf_counter()
     chains = ihmc.DenseChains(ctx, ihmc.Dense(w["K"], beta=w["beta"]), runs, products=args.products)
@@ -392,7 +394,7 @@ def bench_serving(args):
     from paper_1912_03278_amd import ihmc, inputs
 
     reqs = inputs.serving(rate=args.rate, duration=args.serve_duration)
-    ctx = ihmc.Context(device=0, arena_bytes=12 << 30)
+    ctx = ihmc.Context(device=0, arena_bytes=12 << 30, resident=args.resident_sites)
     # tile classes of every request shape, chosen before the first arrival
     shapes = {}
     for r in reqs:
@@ -451,6 +453,7 @@ def bench_serving(args):
                                "U[0,0.1], C = 2d + 0.1, 50-1000 trajectories of 10-30 leap-frog steps, FP32 state, "
                                "FP64 H; one step = one completed request",
                    "requests": len(reqs), "offered_site_md_steps_per_s": sum(work) / args.serve_duration,
+                   "resident": args.resident,
                    **tiles},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "mean": float(lat.mean()), "max": float(lat.max())},
@@ -477,7 +480,7 @@ def bench_tau(args):
     pts3 = [dict(L=(L,) * 3, beta=inputs.BETA_3D, C=6.1) for L in (3, 4, 5, 6, 8, 10)]
     dcs = (0.05, 0.25, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0)
     ptsC = [dict(L=(15, 15), beta=inputs.BETA_C_2D, C=4.0 + dc) for dc in dcs]
-    ctx = ihmc.Context(device=0, arena_bytes=6 << 30)
+    ctx = ihmc.Context(device=0, arena_bytes=6 << 30, resident=args.resident_sites)
     pts = pts2 + pts3 + ptsC
     print(f"bench: tau_int scan, {len(pts)} points x {R} chains x {W + K} trajectories", file=sys.stderr,
           flush=True)
@@ -514,7 +517,7 @@ def bench_tau(args):
         "config": {"workload": f"tau_int scans at the critical coupling, h = 0, {R} replicas per point, "
                                f"{K} trajectories after {W}, n_md = floor(log N): 2D L 4..32 (C = 4.1), "
                                "3D L 3..10 (C = 6.1), 2D 15^2 with C - n from 0.05 to 4; one step = one "
-                               "trajectory of every chain", "chains": R * len(pts)},
+                               "trajectory of every chain", "chains": R * len(pts), "resident": args.resident},
         "tau_2d": {"points": rowfmt(r2, "L"), "fit": fits(r2, 2)},
         "tau_3d": {"points": rowfmt(r3, "L"), "fit": fits(r3, 3)},
         "tau_vs_C": {"points": rowfmt(rC, "C_minus_n"), "first_C_minus_n_above_plateau": c_crit},
@@ -542,12 +545,16 @@ def main():
     ap.add_argument("--no-streaming-point", action="store_true", help="large: skip the extra 8192^2 point")
     ap.add_argument("--timing-reps", type=int, default=100)
     ap.add_argument("--tau-chains", type=int, default=128, help="tau: replicas per scan point")
+    ap.add_argument("--resident", default="on", choices=["on", "off"],
+                    help="chains that fit one workgroup's LDS run whole trajectories per launch (on) or the "
+                         "tiled passes (off); results are bit-identical")
     ap.add_argument("--tiles", default="tuned", choices=["tuned", "rule"],
                     help="tile classes: autotuned per lattice shape before the run (default), or the built-in rule")
     args = ap.parse_args()
+    args.resident_sites = -1 if args.resident == "on" else 0
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU sharding is described in "
-              "DESIGN.md and is not implemented", file=sys.stderr)
+        print("bench.py: runs on one GPU only; sharding chains or a lattice over several GPUs is a design, "
+              "not implemented here", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched":
         args.steps = 10 if args.steps is None else args.steps
@@ -575,7 +582,7 @@ def main():
 
     ws = large_workload()
     K, W = args.steps, args.warmup
-    ctx = ihmc.Context(device=0, arena_bytes=2 << 30)
+    ctx = ihmc.Context(device=0, arena_bytes=2 << 30, resident=args.resident_sites)
     lats = [ihmc.Lattice(w["L"], beta=w["beta"], C=w["C"]) for w in ws]
     runs = [ihmc.Run(n_md=w["n_md"], n_traj=W + K, precision=ihmc.F32, seed=w["seed"], chain_id=w["chain_id"])
             for w in ws]
