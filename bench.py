@@ -43,15 +43,15 @@ KERNEL_SOURCES = ("lattice_kernels.hip", "lattice_kernels.hpp", "chain_epilogue.
                   "ihmc_internal.hpp", "dense_kernels.hip", "dense_kernels.hpp")
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
-    "large_2d_middle": {"sources": "884aa1d7441998f7", "tiles": "64x16", "sites": 1048576,
-                        "fetch_kib": 4206.0, "write_kib": 8192.0},
-    "large_3d_middle": {"sources": "884aa1d7441998f7", "tiles": "32x8x8", "sites": 2097152,
+    "large_2d_middle": {"sources": "1008d5e1fbd81d89", "tiles": "64x16", "sites": 1048576,
+                        "fetch_kib": 4199.0, "write_kib": 8192.0},
+    "large_3d_middle": {"sources": "1008d5e1fbd81d89", "tiles": "32x8x8", "sites": 2097152,
                         "fetch_kib": 9295.5, "write_kib": 16384.0},
-    "stream_2d_middle": {"sources": "884aa1d7441998f7", "tiles": "64x16", "sites": 67108864,
-                         "fetch_kib": 263714.5, "write_kib": 524288.0},
-    "batched_middle": {"sources": "884aa1d7441998f7", "tiles": "64x16", "sites": 27910615,
-                       "fetch_kib": 166423.6, "write_kib": 220539.6},
-    "dense_gemm_bf16": {"sources": "884aa1d7441998f7", "fetch_kib": 73752.0, "write_kib": 16384.0},
+    "stream_2d_middle": {"sources": "1008d5e1fbd81d89", "tiles": "64x16", "sites": 67108864,
+                         "fetch_kib": 263706.2, "write_kib": 524288.0},
+    "batched_middle": {"sources": "1008d5e1fbd81d89", "tiles": "64x16", "sites": 26410815,
+                       "fetch_kib": 157058.6, "write_kib": 208439.2},
+    "dense_gemm_bf16": {"sources": "1008d5e1fbd81d89", "fetch_kib": 73752.0, "write_kib": 16384.0},
 }
 
 
