@@ -719,10 +719,21 @@ int Chains::advance(int32_t n_traj) {
   if (n_traj == 0) return IHMC_OK;
   bool all_resident = true;
   for (auto& g : groups) all_resident = all_resident && g.cls == RESIDENT_CLASS;
-  if (all_resident) {  // every chain in LDS: one launch per group runs all n_traj trajectories
-    for (auto& g : groups)
-      HIPCHK(launch_lattice_resident(g.prec, g.ndim, d_cd, d_tiles + g.tile_off, g.tile_begin.back(), n_traj, s),
+  if (all_resident) {  // every chain in LDS: one launch per group runs all n_traj trajectories,
+                       // the groups side by side on their own streams
+    const bool fork = groups.size() > 1;
+    if (fork) HIPCHK(hipEventRecord(events[0], s), "fork");
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      const Group& g = groups[gi];
+      hipStream_t gs = fork ? side[2 * gi] : s;
+      if (fork) HIPCHK(hipStreamWaitEvent(gs, events[0], 0), "fork wait");
+      HIPCHK(launch_lattice_resident(g.prec, g.ndim, d_cd, d_tiles + g.tile_off, g.tile_begin.back(), n_traj, gs),
              "resident launch");
+      if (fork) {
+        HIPCHK(hipEventRecord(events[1 + gi], gs), "join");
+        HIPCHK(hipStreamWaitEvent(s, events[1 + gi], 0), "join wait");
+      }
+    }
     enqueued += n_traj;
     return IHMC_OK;
   }
