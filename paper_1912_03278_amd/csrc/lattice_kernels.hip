@@ -787,11 +787,32 @@ __global__ __launch_bounds__(RES_THREADS) void lattice_resident(const ChainDev* 
     }
     return b;
   };
-  auto coords = [&](int i, int& x, int& y, int& z) {
-    x = i % L0;
-    const int r = i / L0;
-    y = r % L1;
-    z = r / L1;
+  // The sites of a thread are tid, tid + NTHR, ...: their coordinates start
+  // from those of tid and advance by fixed steps with carries, which keeps
+  // integer division out of the pass loops.
+  struct Walk {
+    int x, y, z;
+  };
+  const int step_x = RES_THREADS % L0, step_r = RES_THREADS / L0;
+  const int step_y = step_r % L1, step_z = step_r / L1;
+  Walk w0;
+  w0.x = tid % L0;
+  w0.y = (tid / L0) % L1;
+  w0.z = (tid / L0) / L1;
+  auto advance_walk = [&](Walk& c) {
+    c.x += step_x;
+    int carry = 0;
+    if (c.x >= L0) {
+      c.x -= L0;
+      carry = 1;
+    }
+    c.y += step_y + carry;
+    carry = 0;
+    if (c.y >= L1) {
+      c.y -= L1;
+      carry = 1;
+    }
+    c.z += step_z + carry;
   };
 
   if (n_traj == 0) {  // set-up: S and the estimator sums of the accepted field
@@ -838,10 +859,9 @@ __global__ __launch_bounds__(RES_THREADS) void lattice_resident(const ChainDev* 
     }
     // kick-drift passes; the last one kicks only
     for (int j = 0; j < cd.n_pass; ++j) {
-      for (int i = tid; i < N; i += RES_THREADS) {
-        int x, y, z;
-        coords(i, x, y, z);
-        const Nb n = nbrs(i, x, y, z);
+      Walk cw = w0;
+      for (int i = tid; i < N; i += RES_THREADS, advance_walk(cw)) {
+        const Nb n = nbrs(i, cw.x, cw.y, cw.z);
         const T c = sP[i];
         T s = (sP[n.xm] + sP[n.xp]) + (sP[n.ym] + sP[n.yp]);
         if (NDIM == 3) s = s + (sP[n.zm] + sP[n.zp]);
@@ -853,10 +873,9 @@ __global__ __launch_bounds__(RES_THREADS) void lattice_resident(const ChainDev* 
       pass_coeffs(cd, j, kick_d, drift_d);
       const T kick = (T)kick_d, drift = (T)drift_d;
       const bool last = (j == cd.n_pass - 1);
-      for (int i = tid; i < N; i += RES_THREADS) {
-        int x, y, z;
-        coords(i, x, y, z);
-        const Nb n = nbrs(i, x, y, z);
+      Walk cu = w0;
+      for (int i = tid; i < N; i += RES_THREADS, advance_walk(cu)) {
+        const Nb n = nbrs(i, cu.x, cu.y, cu.z);
         T sw = (sW[n.xm] + sW[n.xp]) + (sW[n.ym] + sW[n.yp]);
         if (NDIM == 3) sw = sw + (sW[n.zm] + sW[n.zp]);
         T F = fma_t(Ct, sW[i], sw);
