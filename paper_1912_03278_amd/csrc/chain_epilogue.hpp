@@ -255,16 +255,17 @@ __device__ __forceinline__ double quad_sum_lanes(double t) {
 
 // Epilogue of a lattice pass: store the block's terms (FIRST: kinetic energy of
 // the fresh momenta; LAST: final kinetic energy and the action terms; MEASURE:
-// the action terms) and close the chain where this block completes it.
+// the action terms) and close the chain where this block completes it;
+// last_buf is the buffer holding the proposal (LAST).
 template <int MODE, int NW>
 __device__ __forceinline__ void block_accumulate(const ChainDev& cd, ChainState* st, const u128* acc, uint32_t bad,
-                                                 int cur, int j, int tix) {
+                                                 int last_buf, int tix) {
   constexpr int t_lo = (MODE == PASS_FIRST) ? T_K0 : ((MODE == PASS_MEASURE) ? T_S : T_K1);
   constexpr int t_hi = (MODE == PASS_FIRST) ? T_K0 : T_UT;
   constexpr int kind = (MODE == PASS_FIRST) ? CONTRIB_FIRST : ((MODE == PASS_MEASURE) ? CONTRIB_ACTION : CONTRIB_LAST);
   block_store_terms<NW>(cd, acc, bad, t_lo, t_hi, kind, tix);
   if (MODE == PASS_FIRST) return;
-  block_close<MODE == PASS_LAST, NW>(cd, st, pass_in_buf(cur, j), tix);
+  block_close<MODE == PASS_LAST, NW>(cd, st, last_buf, tix);
 }
 
 }  // namespace ihmc

@@ -66,7 +66,7 @@ struct ChainDev {
   int32_t p_given;       // first pass reads p instead of drawing it (diagnostic)
   int32_t write_p_last;  // last pass stores the final momenta (diagnostic)
   int32_t n_therm;       // trajectories before this index stay out of the summary counters
-  void* psi;             // 3 * NP state values (three rotating buffers)
+  void* psi;             // rotating field buffers of NP values: LAT_BUFFERS (lattice) or 3 (dense)
   void* p;               // NP state values
   const void* b;         // NP state values h'/sqrt(J') (per-site field) or null
   const double* hp;      // NP FP64 h' (per-site field) or null
@@ -113,7 +113,16 @@ inline __host__ __device__ void pass_coeffs(const ChainDev& cd, int j, double& k
   }
 }
 
-// Buffer read by pass j when the accepted field sits in buffer `cur`.
+// Field buffers of a lattice chain (four): the accepted field sits in buffer
+// `cur`; launch k of a trajectory (k = 0 the first pass; a launch may fuse two
+// leap-frog steps) reads lat_in_buf and writes lat_out_buf, cycling through the
+// three other buffers, so no launch writes the buffer it reads.
+constexpr int LAT_BUFFERS = 4;
+inline __host__ __device__ int lat_in_buf(int cur, int k) { return k == 0 ? cur : (cur + 1 + (k - 1) % 3) % 4; }
+inline __host__ __device__ int lat_out_buf(int cur, int k) { return (cur + 1 + k % 3) % 4; }
+
+// Dense chains (three buffers): buffer read by pass j when the accepted field
+// sits in buffer `cur`.
 inline __host__ __device__ int pass_in_buf(int cur, int j) {
   if (j == 0) return cur;
   return (j & 1) ? (cur + 1) % 3 : (cur + 2) % 3;

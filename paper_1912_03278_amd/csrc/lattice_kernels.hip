@@ -207,7 +207,8 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
 // before the LDS phases so their latency overlaps the stencil work.
 template <typename T, int BX, int BY, int MODE>
 __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __restrict__ chains,
-                                                              const Tile* __restrict__ tiles, int n_tiles, int j) {
+                                                              const Tile* __restrict__ tiles, int n_tiles, int j,
+                                                              int k) {
   constexpr int QX = BX / 4;
   constexpr int NT = QX * BY;
   constexpr int NWAVE = (NT + 63) / 64;
@@ -231,8 +232,8 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
   const int sign = st->sign;
   const int traj = st->traj;
   const bool from_cur = (MODE == PASS_FIRST || MODE == PASS_MEASURE || MODE == PASS_FORCE);
-  const int in_buf = from_cur ? cur : pass_in_buf(cur, j);
-  const int out_buf = pass_out_buf(cur, j);
+  const int in_buf = from_cur ? cur : lat_in_buf(cur, k);
+  const int out_buf = lat_out_buf(cur, k);
   const gmem<T>* __restrict__ pin = (const gmem<T>*)cd.psi + (int64_t)in_buf * NP;
   gmem<T>* __restrict__ pout = (gmem<T>*)cd.psi + (int64_t)out_buf * NP;
   gmem<T>* __restrict__ pmom = (gmem<T>*)cd.p;
@@ -406,7 +407,7 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
     for (int a = 0; a < 4; ++a) acc[T_S + a] = to_fixed(qs[T_S + a], bad);
   }
   const int tix = (tl.y0 / BY) * ((L0 + BX - 1) / BX) + tl.x0 / BX;  // tile index within the chain
-  block_accumulate<MODE, NWAVE>(cd, st, acc, bad, cur, j, tix);
+  block_accumulate<MODE, NWAVE>(cd, st, acc, bad, lat_in_buf(cur, k), tix);
 }
 
 // ------------------------------------------------------------ 3D, one phase ---
@@ -422,7 +423,8 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
 // ZR planes in z order, then per x-aligned quad of columns.
 template <typename T, int BX, int BY, int ZR, int MODE>
 __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict__ chains,
-                                                      const Tile* __restrict__ tiles, int n_tiles, int j) {
+                                                      const Tile* __restrict__ tiles, int n_tiles, int j,
+                                                              int k) {
   constexpr int RP = BX + 8;
   constexpr int NCH = RP / 4;  // 16-byte chunks per staged row
   constexpr int PR = BY + 4, PZ = ZR + 4;
@@ -444,8 +446,8 @@ __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict
   const int sign = st->sign;
   const int traj = st->traj;
   const bool from_cur = (MODE == PASS_FIRST || MODE == PASS_MEASURE || MODE == PASS_FORCE);
-  const int in_buf = from_cur ? cur : pass_in_buf(cur, j);
-  const int out_buf = pass_out_buf(cur, j);
+  const int in_buf = from_cur ? cur : lat_in_buf(cur, k);
+  const int out_buf = lat_out_buf(cur, k);
   const gmem<T>* __restrict__ pin = (const gmem<T>*)cd.psi + (int64_t)in_buf * NP;
   gmem<T>* __restrict__ pout = (gmem<T>*)cd.psi + (int64_t)out_buf * NP;
   gmem<T>* __restrict__ pmom = (gmem<T>*)cd.p;
@@ -657,7 +659,7 @@ __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict
 
   if (MODE == PASS_MIDDLE || MODE == PASS_FORCE) return;
   const int tix = ((tl.z0 / ZR) * ((L1 + BY - 1) / BY) + tl.y0 / BY) * ((L0 + BX - 1) / BX) + tl.x0 / BX;
-  block_accumulate<MODE, 4>(cd, st, acc, bad, cur, j, tix);
+  block_accumulate<MODE, 4>(cd, st, acc, bad, lat_in_buf(cur, k), tix);
 }
 
 // ---------------------------------------------------- LDS-resident chains ---
@@ -923,25 +925,25 @@ hipError_t launch_lattice_resident(int precision, int ndim, const ChainDev* chai
 // ------------------------------------------------------------------ launch ---
 
 template <typename T, int BX, int BY>
-static hipError_t launch_mode2v(int mode, const ChainDev* chains, const Tile* tiles, int n_tiles, int j,
+static hipError_t launch_mode2v(int mode, const ChainDev* chains, const Tile* tiles, int n_tiles, int j, int k,
                                 hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   dim3 grid(n_tiles), block(BX / 4 * BY);
   switch (mode) {
     case PASS_FIRST:
-      lattice_pass2v<T, BX, BY, PASS_FIRST><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
+      lattice_pass2v<T, BX, BY, PASS_FIRST><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j, k);
       break;
     case PASS_MIDDLE:
-      lattice_pass2v<T, BX, BY, PASS_MIDDLE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
+      lattice_pass2v<T, BX, BY, PASS_MIDDLE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j, k);
       break;
     case PASS_LAST:
-      lattice_pass2v<T, BX, BY, PASS_LAST><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
+      lattice_pass2v<T, BX, BY, PASS_LAST><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j, k);
       break;
     case PASS_MEASURE:
-      lattice_pass2v<T, BX, BY, PASS_MEASURE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
+      lattice_pass2v<T, BX, BY, PASS_MEASURE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j, k);
       break;
     case PASS_FORCE:
-      lattice_pass2v<T, BX, BY, PASS_FORCE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
+      lattice_pass2v<T, BX, BY, PASS_FORCE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j, k);
       break;
     default:
       return hipErrorInvalidValue;
@@ -950,25 +952,25 @@ static hipError_t launch_mode2v(int mode, const ChainDev* chains, const Tile* ti
 }
 
 template <typename T, int BX, int BY, int ZR>
-static hipError_t launch_mode3t(int mode, const ChainDev* chains, const Tile* tiles, int n_tiles, int j,
+static hipError_t launch_mode3t(int mode, const ChainDev* chains, const Tile* tiles, int n_tiles, int j, int k,
                                 hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   dim3 grid(n_tiles), block(256);
   switch (mode) {
     case PASS_FIRST:
-      lattice_pass3t<T, BX, BY, ZR, PASS_FIRST><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
+      lattice_pass3t<T, BX, BY, ZR, PASS_FIRST><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j, k);
       break;
     case PASS_MIDDLE:
-      lattice_pass3t<T, BX, BY, ZR, PASS_MIDDLE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
+      lattice_pass3t<T, BX, BY, ZR, PASS_MIDDLE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j, k);
       break;
     case PASS_LAST:
-      lattice_pass3t<T, BX, BY, ZR, PASS_LAST><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
+      lattice_pass3t<T, BX, BY, ZR, PASS_LAST><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j, k);
       break;
     case PASS_MEASURE:
-      lattice_pass3t<T, BX, BY, ZR, PASS_MEASURE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
+      lattice_pass3t<T, BX, BY, ZR, PASS_MEASURE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j, k);
       break;
     case PASS_FORCE:
-      lattice_pass3t<T, BX, BY, ZR, PASS_FORCE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j);
+      lattice_pass3t<T, BX, BY, ZR, PASS_FORCE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j, k);
       break;
     default:
       return hipErrorInvalidValue;
@@ -1015,34 +1017,34 @@ TileShape tile_shape(int precision, int ndim, int cls) {
 }
 
 hipError_t launch_lattice_pass(int precision, int ndim, int cls, int mode, const ChainDev* chains,
-                               const Tile* tiles, int n_tiles, int j, hipStream_t s) {
+                               const Tile* tiles, int n_tiles, int j, int k, hipStream_t s) {
   if (cls == RESIDENT_CLASS) {  // whole trajectories only; the set-up measurement is n_traj = 0
     if (mode != PASS_MEASURE) return hipErrorInvalidValue;
     return launch_lattice_resident(precision, ndim, chains, tiles, n_tiles, 0, s);
   }
   if (precision == 4) {
     if (ndim == 2) {
-      if (cls == 1) return launch_mode2v<float, 16, 16>(mode, chains, tiles, n_tiles, j, s);
-      if (cls == 2) return launch_mode2v<float, 32, 32>(mode, chains, tiles, n_tiles, j, s);
-      return launch_mode2v<float, IHMC_2D_BX, IHMC_2D_BY>(mode, chains, tiles, n_tiles, j, s);
+      if (cls == 1) return launch_mode2v<float, 16, 16>(mode, chains, tiles, n_tiles, j, k, s);
+      if (cls == 2) return launch_mode2v<float, 32, 32>(mode, chains, tiles, n_tiles, j, k, s);
+      return launch_mode2v<float, IHMC_2D_BX, IHMC_2D_BY>(mode, chains, tiles, n_tiles, j, k, s);
     }
     switch (cls) {
-      case 1: return launch_mode3t<float, 16, 16, 4>(mode, chains, tiles, n_tiles, j, s);
-      case 2: return launch_mode3t<float, 32, 8, 8>(mode, chains, tiles, n_tiles, j, s);
-      case 3: return launch_mode3t<float, 16, 16, 8>(mode, chains, tiles, n_tiles, j, s);
-      default: return launch_mode3t<float, 32, 8, 4>(mode, chains, tiles, n_tiles, j, s);
+      case 1: return launch_mode3t<float, 16, 16, 4>(mode, chains, tiles, n_tiles, j, k, s);
+      case 2: return launch_mode3t<float, 32, 8, 8>(mode, chains, tiles, n_tiles, j, k, s);
+      case 3: return launch_mode3t<float, 16, 16, 8>(mode, chains, tiles, n_tiles, j, k, s);
+      default: return launch_mode3t<float, 32, 8, 4>(mode, chains, tiles, n_tiles, j, k, s);
     }
   }
   if (ndim == 2) {
-    if (cls == 1) return launch_mode2v<double, 16, 16>(mode, chains, tiles, n_tiles, j, s);
-    if (cls == 2) return launch_mode2v<double, 32, 32>(mode, chains, tiles, n_tiles, j, s);
-    return launch_mode2v<double, IHMC_2D_BX, IHMC_2D_BY>(mode, chains, tiles, n_tiles, j, s);
+    if (cls == 1) return launch_mode2v<double, 16, 16>(mode, chains, tiles, n_tiles, j, k, s);
+    if (cls == 2) return launch_mode2v<double, 32, 32>(mode, chains, tiles, n_tiles, j, k, s);
+    return launch_mode2v<double, IHMC_2D_BX, IHMC_2D_BY>(mode, chains, tiles, n_tiles, j, k, s);
   }
   switch (cls) {
-    case 1: return launch_mode3t<double, 16, 16, 4>(mode, chains, tiles, n_tiles, j, s);
-    case 2: return launch_mode3t<double, 32, 8, 8>(mode, chains, tiles, n_tiles, j, s);
-    case 3: return launch_mode3t<double, 16, 16, 8>(mode, chains, tiles, n_tiles, j, s);
-    default: return launch_mode3t<double, 32, 8, 4>(mode, chains, tiles, n_tiles, j, s);
+    case 1: return launch_mode3t<double, 16, 16, 4>(mode, chains, tiles, n_tiles, j, k, s);
+    case 2: return launch_mode3t<double, 32, 8, 8>(mode, chains, tiles, n_tiles, j, k, s);
+    case 3: return launch_mode3t<double, 16, 16, 8>(mode, chains, tiles, n_tiles, j, k, s);
+    default: return launch_mode3t<double, 32, 8, 4>(mode, chains, tiles, n_tiles, j, k, s);
   }
 }
 

@@ -36,10 +36,11 @@ int resident_max_sites(int precision, bool site_field);
 hipError_t launch_lattice_resident(int precision, int ndim, const ChainDev* chains, const Tile* tiles, int n_chains,
                                    int n_traj, hipStream_t s);
 
-// Launch one pass of kind `mode` (pass index j of the trajectory) over n_tiles
+// Launch one pass of kind `mode` (pass index j of the trajectory, which sets
+// the kick and drift; launch index k, which sets the field buffers) over n_tiles
 // consecutive entries of `tiles`; all tiles must belong to chains of the given
 // precision, dimension and tile class.
 hipError_t launch_lattice_pass(int precision, int ndim, int cls, int mode, const ChainDev* chains,
-                               const Tile* tiles, int n_tiles, int j, hipStream_t s);
+                               const Tile* tiles, int n_tiles, int j, int k, hipStream_t s);
 
 }  // namespace ihmc

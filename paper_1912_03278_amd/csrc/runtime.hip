@@ -515,7 +515,7 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
     describe_chain(l, r, flags, choose_class(ctx, l, r.precision, flags), c);
     const int64_t N = c.N, NP = c.NP;
     const int64_t pb = r.precision;
-    c.psi = dalloc(3 * NP * pb);
+    c.psi = dalloc((uint64_t)LAT_BUFFERS * NP * pb);
     c.p = dalloc(NP * pb);
     c.rec = (TrajRecord*)dalloc(sizeof(TrajRecord) * (uint64_t)std::max(1, r.n_traj));
     c.st = (ChainState*)dalloc(sizeof(ChainState));
@@ -639,7 +639,7 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
     HIPCHK(hipGetLastError(), "k_init_psi");
   }
   for (auto& g : groups) {
-    HIPCHK(launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_MEASURE, d_cd, d_tiles + g.tile_off, g.tile_begin.back(), 0, s),
+    HIPCHK(launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_MEASURE, d_cd, d_tiles + g.tile_off, g.tile_begin.back(), 0, 0, s),
            "measure pass");
   }
   hipError_t e = hipStreamSynchronize(s);
@@ -677,7 +677,7 @@ hipError_t enqueue_round_plan(const std::vector<Group>& groups, const Tile* d_ti
       continue;
     }
     if ((e = hipStreamWaitEvent(ls, fork, 0)) != hipSuccess) return e;
-    e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_FIRST, d_cd, base, g.tile_begin.back(), 0, gs);
+    e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_FIRST, d_cd, base, g.tile_begin.back(), 0, 0, gs);
     if (e != hipSuccess) return e;
     const int nc = (int)g.order.size();
     for (int j = 1; j < g.max_pass; ++j) {
@@ -690,11 +690,11 @@ hipError_t enqueue_round_plan(const std::vector<Group>& groups, const Tile* d_ti
         if ((e = hipEventRecord(after_prev, gs)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(ls, after_prev, 0)) != hipSuccess) return e;
         const int t0 = g.tile_begin[mid_end], t1 = g.tile_begin[last_end];
-        e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_LAST, d_cd, base + t0, t1 - t0, j, ls);
+        e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_LAST, d_cd, base + t0, t1 - t0, j, j, ls);
         if (e != hipSuccess) return e;
       }
       if (mid_end > 0) {
-        e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_MIDDLE, d_cd, base, g.tile_begin[mid_end], j, gs);
+        e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_MIDDLE, d_cd, base, g.tile_begin[mid_end], j, j, gs);
         if (e != hipSuccess) return e;
       }
     }
@@ -950,7 +950,7 @@ int chain_restore(ihmc_ctx* ctx, const ChainDev& c, uint64_t variant, const void
   if (std::memcmp((const char*)&h + id0, (const char*)&mine + id0, id1 - id0) != 0)
     return set_error(IHMC_E_INVAL, "checkpoint of a chain with other parameters");
   const ChainState& st = h.st;
-  if (st.traj < 0 || st.cur < 0 || st.cur > 2 || (st.sign != 1 && st.sign != -1) || h.n_rec != st.traj)
+  if (st.traj < 0 || st.cur < 0 || st.cur >= LAT_BUFFERS || (st.sign != 1 && st.sign != -1) || h.n_rec != st.traj)
     return set_error(IHMC_E_INVAL, "checkpoint state is inconsistent");
   if (st.traj > c.cap)
     return set_error(IHMC_E_INVAL, "checkpoint after %d trajectories, the chain's capacity is %d", st.traj, c.cap);
@@ -1093,7 +1093,7 @@ extern "C" int ihmc_force(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t precis
   if (rc) return rc;
   hipStream_t s = ctx->stream;
   const Group& g = c->groups[0];
-  hipError_t e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_FORCE, c->d_cd, c->d_tiles, g.tile_begin.back(), 0, s);
+  hipError_t e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_FORCE, c->d_cd, c->d_tiles, g.tile_begin.back(), 0, 0, s);
   const int64_t N = c->cd[0].N;
   double* t = (double*)ctx->arena.alloc(8 * (uint64_t)N);
   if (e == hipSuccess && t) {
@@ -1270,10 +1270,10 @@ extern "C" int ihmc_chains_time_pass(ihmc_chains* ch, int32_t group, int32_t mod
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0), "event");
   HIPCHK(hipEventCreate(&e1), "event");
-  hipError_t e = launch_lattice_pass(g.prec, g.ndim, g.cls, mode, c->d_cd, c->d_tiles + g.tile_off, g.tile_begin.back(), 1, s);
+  hipError_t e = launch_lattice_pass(g.prec, g.ndim, g.cls, mode, c->d_cd, c->d_tiles + g.tile_off, g.tile_begin.back(), 1, 1, s);
   if (e == hipSuccess) e = hipEventRecord(e0, s);
   for (int r = 0; e == hipSuccess && r < reps; ++r)
-    e = launch_lattice_pass(g.prec, g.ndim, g.cls, mode, c->d_cd, c->d_tiles + g.tile_off, g.tile_begin.back(), 1, s);
+    e = launch_lattice_pass(g.prec, g.ndim, g.cls, mode, c->d_cd, c->d_tiles + g.tile_off, g.tile_begin.back(), 1, 1, s);
   if (e == hipSuccess) e = hipEventRecord(e1, s);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float ms = 0.f;
@@ -1358,7 +1358,7 @@ hipError_t launch_field_cg(ChainDev* d_cd, const int* which, int n, double* work
 hipError_t launch_measure(const std::vector<Group>& groups, const Tile* d_tiles, const ChainDev* d_cd, hipStream_t s) {
   for (auto& g : groups) {
     hipError_t e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_MEASURE, d_cd, d_tiles + g.tile_off,
-                                       g.tile_begin.back(), 0, s);
+                                       g.tile_begin.back(), 0, 0, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -66,7 +66,7 @@ static uint64_t request_bytes(const ihmc_lattice& l, const ihmc_run& r, int cls)
   const int64_t pitch = (l.L[0] + 3) & ~3;
   const int64_t NP = pitch * (N / l.L[0]);
   const uint64_t pb = (uint64_t)r.precision;
-  uint64_t b = r256(3 * NP * pb) + r256(NP * pb) + r256(sizeof(TrajRecord) * (uint64_t)std::max(1, r.n_traj)) +
+  uint64_t b = r256((uint64_t)LAT_BUFFERS * NP * pb) + r256(NP * pb) + r256(sizeof(TrajRecord) * (uint64_t)std::max(1, r.n_traj)) +
                r256(sizeof(ChainState)) + r256(8 * (uint64_t)N);
   if (r.replay_accept) b += r256((uint64_t)r.n_traj);
   if (l.h_len == N && N > 1) b += r256(8 * NP) + r256(NP * pb) + r256(8 * 4 * (uint64_t)N) + r256(8 * (uint64_t)N);
@@ -239,7 +239,7 @@ bool ihmc_server::admit_setup(std::vector<Request*>& fresh) {
       if (p) r->dev.push_back(p);
       return p;
     };
-    c.psi = dal(3 * c.NP * pb);
+    c.psi = dal((uint64_t)LAT_BUFFERS * c.NP * pb);
     c.p = dal(c.NP * pb);
     c.rec = (TrajRecord*)dal(sizeof(TrajRecord) * (uint64_t)std::max(1, r->run.n_traj));
     c.st = (ChainState*)dal(sizeof(ChainState));

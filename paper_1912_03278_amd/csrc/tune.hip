@@ -111,7 +111,7 @@ static int measure_key(ihmc_ctx* ctx, const TileKey& k, int64_t sites, int reps,
   const int64_t R = std::min(kTuneMaxReplicas, std::max<int64_t>(1, (sites + N / 2) / N));
   const int ncls = tile_class_count(k.ndim);
   const uint64_t pb = (uint64_t)k.prec;
-  const uint64_t fb = r256((4ull + (uint64_t)k.site_field) * (uint64_t)c0.NP * pb);
+  const uint64_t fb = r256(((uint64_t)LAT_BUFFERS + 1ull + (uint64_t)k.site_field) * (uint64_t)c0.NP * pb);
 
   std::vector<std::vector<Tile>> tl(ncls);
   for (int cls = 0; cls < ncls; ++cls) {
@@ -154,8 +154,8 @@ static int measure_key(ihmc_ctx* ctx, const TileKey& k, int64_t sites, int reps,
   for (int64_t q = 0; q < R; ++q) {
     char* f = fields + q * fb;
     cd[q].psi = f;
-    cd[q].p = f + 3 * c0.NP * pb;
-    cd[q].b = k.site_field ? (const void*)(f + 4 * c0.NP * pb) : nullptr;
+    cd[q].p = f + LAT_BUFFERS * c0.NP * pb;
+    cd[q].b = k.site_field ? (const void*)(f + (LAT_BUFFERS + 1) * c0.NP * pb) : nullptr;
     cd[q].st = st + q;
   }
   const int64_t nel = (int64_t)(R * fb / pb);
@@ -178,10 +178,10 @@ static int measure_key(ihmc_ctx* ctx, const TileKey& k, int64_t sites, int reps,
   for (int round = 0; round < 3; ++round) {
     for (int cls = 0; cls < ncls; ++cls) {
       const int nt = (int)tl[cls].size();
-      HIPCHK(launch_lattice_pass(k.prec, k.ndim, cls, PASS_MIDDLE, d_cd, d_tl[cls], nt, 1, s), "tune warm-up");
+      HIPCHK(launch_lattice_pass(k.prec, k.ndim, cls, PASS_MIDDLE, d_cd, d_tl[cls], nt, 1, 1, s), "tune warm-up");
       HIPCHK(hipEventRecord(rel.e0, s), "event record");
       for (int i = 0; i < reps; ++i)
-        HIPCHK(launch_lattice_pass(k.prec, k.ndim, cls, PASS_MIDDLE, d_cd, d_tl[cls], nt, 1, s), "tune pass");
+        HIPCHK(launch_lattice_pass(k.prec, k.ndim, cls, PASS_MIDDLE, d_cd, d_tl[cls], nt, 1, 1, s), "tune pass");
       HIPCHK(hipEventRecord(rel.e1, s), "event record");
       HIPCHK(hipEventSynchronize(rel.e1), "event sync");
       float ms = 0.f;
