@@ -95,8 +95,9 @@ def tune_tiles(ctx, lats, args, sites=0):
     return {"tile_classes": "autotuned", "tuned_shapes": n, "tune_s": round(dt, 2)}
 
 
-def group_rows(chains, reps, modes=(1,)):
-    """Per launch group: tile shape, sites and HIP-event time of the pass kinds."""
+def group_rows(chains, reps, modes=(1,), pair=False):
+    """Per launch group: tile shape, sites and HIP-event time of the pass kinds
+    (with pair: also the two-step launch of 2D groups, as pair_us)."""
     from paper_1912_03278_amd import ihmc
     rows = []
     for g in range(chains.groups()):
@@ -110,6 +111,8 @@ def group_rows(chains, reps, modes=(1,)):
         for m in modes:
             name = ("first_us", "middle_us", "last_us")[m]
             row[name] = chains.time_pass(g, mode=m, reps=reps if m == 1 else max(10, reps // 5))["us"]
+        if pair and info["ndim"] == 2:
+            row["pair_us"] = chains.time_pass(g, mode=ihmc.PAIR, reps=reps)["us"]
         rows.append(row)
     return rows
 
@@ -136,7 +139,7 @@ def streaming_point(args, copy_gbs):
     import torch
     from paper_1912_03278_amd import ihmc, inputs
     L = 8192
-    ctx = ihmc.Context(device=0, arena_bytes=3 << 30, resident=args.resident_sites)
+    ctx = ihmc.Context(device=0, arena_bytes=3 << 30, resident=args.resident_sites, fuse_steps=args.fuse_steps)
     lat = ihmc.Lattice((L, L), beta=inputs.BETA_C_2D, C=4.1)
     ch = ihmc.Chains(ctx, [lat], [ihmc.Run(n_md=20, n_traj=8, precision=ihmc.F32, seed=2, chain_id=2)])
     ch.advance(1)
@@ -170,7 +173,7 @@ def bench_small(args):
     from paper_1912_03278_amd import ihmc, inputs
     w = inputs.small()
     K, W = args.steps, args.warmup
-    ctx = ihmc.Context(device=0, arena_bytes=64 << 20, resident=args.resident_sites)
+    ctx = ihmc.Context(device=0, arena_bytes=64 << 20, resident=args.resident_sites, fuse_steps=args.fuse_steps)
     lat = ihmc.Lattice(w["L"], beta=w["beta"], C=w["C"])
     ch = ihmc.Chains(ctx, [lat], [ihmc.Run(n_md=w["n_md"], n_traj=W + K, precision=ihmc.F64, seed=w["seed"])])
     ch.advance(W)
@@ -190,7 +193,7 @@ def bench_small(args):
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "small: one 2D 8x8 chain, beta=0.40, C=4.1, h=0, n_md=10, FP64 state; one step = "
                                "one trajectory (latency-bound by construction)", "sites": N,
-                   "resident": args.resident},
+                   "resident": args.resident, "fuse_steps": args.fuse},
         "observables": {"beta_eps_mean": float(np.mean(r["beta_eps"][W:])), "m2c_mean": float(np.mean(r["m2c"][W:])),
                         "acceptance": r["acceptance"],
                         "exact_beta_eps": -0.4889282573, "exact_m2": 0.4320990786},
@@ -219,7 +222,7 @@ def bench_batched(args):
 
     ws = inputs.batched(n_chains=args.chains)
     K, W = args.steps, args.warmup
-    ctx = ihmc.Context(device=0, arena_bytes=6 << 30, resident=args.resident_sites)
+    ctx = ihmc.Context(device=0, arena_bytes=6 << 30, resident=args.resident_sites, fuse_steps=args.fuse_steps)
     lats = [ihmc.Lattice(w["L"], beta=w["beta"], C=w["C"], h=w["h"]) for w in ws]
     runs = [ihmc.Run(n_md=w["n_md"], n_traj=W + K, precision=ihmc.F32, seed=w["seed"], chain_id=w["chain_id"])
             for w in ws]
@@ -264,13 +267,17 @@ def bench_batched(args):
     acc = [chains.result(i, want_psi=False)["acceptance"] for i in range(0, len(ws), max(1, len(ws) // 64))]
 
     # one launch group per tile class in use (all chains are FP32 2D)
-    kern = group_rows(chains, args.timing_reps)
+    # (a pair launch moves the same 20 B per site as a one-step pass: psi, p and
+    # the field read once, p and psi written once)
+    kern = group_rows(chains, args.timing_reps, pair=args.fuse_steps)
     for k in kern:
-        if "middle_us" in k:
-            k["middle_GBs"] = round(20 * k["sites"] / (k["middle_us"] * 1e-6) / 1e9, 1)
-            k["middle_us"] = round(k["middle_us"], 2)
-    dom = max((k for k in kern if "middle_us" in k), key=lambda k: k["sites"])
-    achieved = 20 * dom["sites"] / (dom["middle_us"] * 1e-6) / 1e9
+        for name in ("middle", "pair"):
+            if f"{name}_us" in k:
+                k[f"{name}_GBs"] = round(20 * k["sites"] / (k[f"{name}_us"] * 1e-6) / 1e9, 1)
+                k[f"{name}_us"] = round(k[f"{name}_us"], 2)
+    key = "pair_us" if args.fuse_steps else "middle_us"
+    dom = max((k for k in kern if key in k), key=lambda k: k["sites"])
+    achieved = 20 * dom["sites"] / (dom[key] * 1e-6) / 1e9
     copy_bytes = 512 << 20
     copy_gbs = 2 * copy_bytes / (ctx.copy_bandwidth(copy_bytes, reps=10) * 1e-6) / 1e9
     line = {
@@ -281,13 +288,15 @@ def bench_batched(args):
                                "h_x ~ N(0,0.05^2) per site, n_md U{8..32}, C=4.1, FP32 state, FP64 H; "
                                "one step = one trajectory of every chain",
                    "chains": len(ws), "sites": sum(int(math.prod(w["L"])) for w in ws), **tiles,
-                   "resident": args.resident},
-        "roofline": {"bound": "hbm", "kernel": f"fused middle pass, 2D, per-site field, {dom['tiles']}-tile group "
+                   "resident": args.resident, "fuse_steps": args.fuse},
+        "roofline": {"bound": "hbm", "kernel": ("two-step " if args.fuse_steps else "") +
+                                               f"fused middle pass, 2D, per-site field, {dom['tiles']}-tile group "
                                                f"({dom['chains']} chains)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_bytes("batched_middle", sites=dom["sites"], tiles=dom["tiles"]),
-                     "bytes_per_launch": 20 * dom["sites"], "avg_launch_us": dom["middle_us"],
+                     "traffic": traffic_bytes("batched_pair" if args.fuse_steps else "batched_middle",
+                                              sites=dom["sites"], tiles=dom["tiles"]),
+                     "bytes_per_launch": 20 * dom["sites"], "avg_launch_us": dom[key],
                      "copy_kernel_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "kernels": kern,
         "plain": {"chains": len(sample), "value": (plain_work / plain_time) if plain_time > 0 else None,
@@ -314,7 +323,7 @@ def bench_dense(args):
     w = inputs.dense()
     K, W = args.steps, args.warmup
     N, B, n_md = w["K"].shape[0], w["n_chains"], w["n_md"]
-    ctx = ihmc.Context(device=0, arena_bytes=2 << 30, resident=args.resident_sites)
+    ctx = ihmc.Context(device=0, arena_bytes=2 << 30, resident=args.resident_sites, fuse_steps=args.fuse_steps)
     runs = [ihmc.Run(n_md=n_md, n_traj=W + K, precision=ihmc.F32, seed=w["seed"], chain_id=i) for i in range(B)]
     t0 = time.perf_counter()
     chains = ihmc.DenseChains(ctx, ihmc.Dense(w["K"], beta=w["beta"]), runs, products=args.products)
@@ -394,7 +403,7 @@ def bench_serving(args):
     from paper_1912_03278_amd import ihmc, inputs
 
     reqs = inputs.serving(rate=args.rate, duration=args.serve_duration)
-    ctx = ihmc.Context(device=0, arena_bytes=12 << 30, resident=args.resident_sites)
+    ctx = ihmc.Context(device=0, arena_bytes=12 << 30, resident=args.resident_sites, fuse_steps=args.fuse_steps)
     # tile classes of every request shape, chosen before the first arrival
     shapes = {}
     for r in reqs:
@@ -453,7 +462,7 @@ def bench_serving(args):
                                "U[0,0.1], C = 2d + 0.1, 50-1000 trajectories of 10-30 leap-frog steps, FP32 state, "
                                "FP64 H; one step = one completed request",
                    "requests": len(reqs), "offered_site_md_steps_per_s": sum(work) / args.serve_duration,
-                   "resident": args.resident,
+                   "resident": args.resident, "fuse_steps": args.fuse,
                    **tiles},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "mean": float(lat.mean()), "max": float(lat.max())},
@@ -480,7 +489,7 @@ def bench_tau(args):
     pts3 = [dict(L=(L,) * 3, beta=inputs.BETA_3D, C=6.1) for L in (3, 4, 5, 6, 8, 10)]
     dcs = (0.05, 0.25, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0)
     ptsC = [dict(L=(15, 15), beta=inputs.BETA_C_2D, C=4.0 + dc) for dc in dcs]
-    ctx = ihmc.Context(device=0, arena_bytes=6 << 30, resident=args.resident_sites)
+    ctx = ihmc.Context(device=0, arena_bytes=6 << 30, resident=args.resident_sites, fuse_steps=args.fuse_steps)
     pts = pts2 + pts3 + ptsC
     print(f"bench: tau_int scan, {len(pts)} points x {R} chains x {W + K} trajectories", file=sys.stderr,
           flush=True)
@@ -517,7 +526,8 @@ def bench_tau(args):
         "config": {"workload": f"tau_int scans at the critical coupling, h = 0, {R} replicas per point, "
                                f"{K} trajectories after {W}, n_md = floor(log N): 2D L 4..32 (C = 4.1), "
                                "3D L 3..10 (C = 6.1), 2D 15^2 with C - n from 0.05 to 4; one step = one "
-                               "trajectory of every chain", "chains": R * len(pts), "resident": args.resident},
+                               "trajectory of every chain", "chains": R * len(pts), "resident": args.resident,
+                   "fuse_steps": args.fuse},
         "tau_2d": {"points": rowfmt(r2, "L"), "fit": fits(r2, 2)},
         "tau_3d": {"points": rowfmt(r3, "L"), "fit": fits(r3, 3)},
         "tau_vs_C": {"points": rowfmt(rC, "C_minus_n"), "first_C_minus_n_above_plateau": c_crit},
@@ -548,10 +558,14 @@ def main():
     ap.add_argument("--resident", default="on", choices=["on", "off"],
                     help="chains that fit one workgroup's LDS run whole trajectories per launch (on) or the "
                          "tiled passes (off); results are bit-identical")
+    ap.add_argument("--fuse", default="on", choices=["on", "off"],
+                    help="2D chains on the tiled passes run two middle leap-frog steps per launch (on) or one "
+                         "(off); results are bit-identical")
     ap.add_argument("--tiles", default="tuned", choices=["tuned", "rule"],
                     help="tile classes: autotuned per lattice shape before the run (default), or the built-in rule")
     args = ap.parse_args()
     args.resident_sites = -1 if args.resident == "on" else 0
+    args.fuse_steps = args.fuse == "on"
     if args.gpus != 1:
         print("bench.py: runs on one GPU only; sharding chains or a lattice over several GPUs is a design, "
               "not implemented here", file=sys.stderr)
@@ -582,7 +596,7 @@ def main():
 
     ws = large_workload()
     K, W = args.steps, args.warmup
-    ctx = ihmc.Context(device=0, arena_bytes=2 << 30, resident=args.resident_sites)
+    ctx = ihmc.Context(device=0, arena_bytes=2 << 30, resident=args.resident_sites, fuse_steps=args.fuse_steps)
     lats = [ihmc.Lattice(w["L"], beta=w["beta"], C=w["C"]) for w in ws]
     runs = [ihmc.Run(n_md=w["n_md"], n_traj=W + K, precision=ihmc.F32, seed=w["seed"], chain_id=w["chain_id"])
             for w in ws]
@@ -614,18 +628,31 @@ def main():
 
     # ---- roofline of the dominant kernel: HIP-event timing of each fused pass kind
     # groups are ordered (precision, ndim, tile class): the 2D chain, then the 3D one
-    kern = group_rows(chains, args.timing_reps, modes=(1, 0, 2))
+    # per group, the launch kind that carries most of its middle steps: the
+    # two-step launch of a fused 2D group (plus one single step for an odd
+    # number of middle steps), else the one-step pass; both move 16 B per site
+    kern = group_rows(chains, args.timing_reps, modes=(1, 0, 2), pair=args.fuse_steps)
     for g, k in enumerate(kern):
-        k["middle_share_us"] = (ws[g]["n_md"] - 1) * k["middle_us"]
+        n_mid = ws[g]["n_md"] - 1
+        if "pair_us" in k:
+            k["kind"], k["kind_us"] = "two-step middle pass", k["pair_us"]
+            k["middle_share_us"] = (n_mid // 2) * k["pair_us"] + (n_mid % 2) * k["middle_us"]
+        else:
+            k["kind"], k["kind_us"] = "middle pass", k["middle_us"]
+            k["middle_share_us"] = n_mid * k["middle_us"]
     dom = max(kern, key=lambda k: k["middle_share_us"])
     bytes_per_launch = BYTES_MIDDLE_F32 * dom["sites"]
-    achieved = bytes_per_launch / (dom["middle_us"] * 1e-6) / 1e9
+    achieved = bytes_per_launch / (dom["kind_us"] * 1e-6) / 1e9
+    dom_kind, dom_us = dom["kind"], dom["kind_us"]
     for k in kern:
-        k["middle_GBs"] = round(BYTES_MIDDLE_F32 * k["sites"] / (k["middle_us"] * 1e-6) / 1e9, 1)
-        k["middle_us"] = round(k["middle_us"], 3)
+        for name in ("middle", "pair"):
+            if f"{name}_us" in k:
+                k[f"{name}_GBs"] = round(BYTES_MIDDLE_F32 * k["sites"] / (k[f"{name}_us"] * 1e-6) / 1e9, 1)
+                k[f"{name}_us"] = round(k[f"{name}_us"], 3)
         k["first_us"] = round(k["first_us"], 3)
         k["last_us"] = round(k["last_us"], 3)
-        del k["middle_share_us"]
+        for name in ("middle_share_us", "kind", "kind_us"):
+            del k[name]
 
     copy_bytes = 512 << 20
     copy_us = ctx.copy_bandwidth(copy_bytes, reps=10)
@@ -649,19 +676,21 @@ def main():
                         "state, FP64 H/dH/Metropolis; one step = one trajectory of both chains",
             "sites": sum(int(math.prod(w["L"])) for w in ws),
             "md_steps_per_trajectory": ws[0]["n_md"],
+            "fuse_steps": args.fuse,
             **tiles,
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": f"fused middle pass, {dom['ndim']}D",
+            "kernel": f"fused {dom_kind}, {dom['ndim']}D",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_bytes("large_3d_middle" if dom["ndim"] == 3 else "large_2d_middle",
+            "traffic": traffic_bytes("large_3d_middle" if dom["ndim"] == 3 else
+                                     ("large_2d_pair" if dom_kind.startswith("two") else "large_2d_middle"),
                                      sites=dom["sites"], tiles=dom["tiles"]),
             "bytes_per_launch": bytes_per_launch,
-            "avg_launch_us": round(dom["middle_us"], 3),
+            "avg_launch_us": round(dom_us, 3),
             "copy_kernel_GBs": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4),
         },

@@ -175,6 +175,13 @@ int ihmc_ctx_memory(ihmc_ctx* ctx, uint64_t* used, uint64_t* total);
  * *fp32_fit / *fp64_fit (may be NULL) receive the largest chains that fit
  * without a per-site field (a per-site field takes a fifth array). */
 int ihmc_ctx_set_resident(ihmc_ctx* ctx, int64_t max_sites, int64_t* fp32_fit, int64_t* fp64_fit);
+/* 2D chains on the tiled passes run their middle leap-frog steps two per
+ * launch (on != 0, the default): the first step is evaluated on the tile plus
+ * a 2-wide ring, the second on the tile, with the field read and written once
+ * per pair.  The per-site arithmetic is that of one step per launch, so
+ * results are bit-identical either way.  Applies to chain sets created after
+ * the call, to the serving rounds that follow it, and to tuning. */
+int ihmc_ctx_set_step_fusion(ihmc_ctx* ctx, int32_t on);
 const char* ihmc_last_error(void);
 
 /* ---- resident chains (the hot path) --------------------------------------- */
@@ -351,8 +358,9 @@ int ihmc_chains_groups(ihmc_chains* chains, int32_t* n_groups);
 /* Launch group `group` (0 <= group < n_groups): out[0..5] = state precision,
  * ndim, tile class (see ihmc_tile_shape), chains, lattice sites, tiles. */
 int ihmc_chains_group_info(ihmc_chains* chains, int32_t group, int64_t* out);
-/* Time the fused pass kind `mode` (0 = first, 1 = middle, 2 = last) of launch
- * group `group`: one warm-up launch, then `reps` launches bracketed by HIP
+/* Time the fused pass kind `mode` (0 = first, 1 = middle, 2 = last, 5 = two
+ * middle steps in one launch, 2D groups whose chains have at least two middle
+ * steps) of launch group `group`: one warm-up launch, then `reps` launches bracketed by HIP
  * events on the context stream.  Returns the mean duration per launch in
  * microseconds and the lattice sites one launch covers.  The repeated passes
  * overwrite the chains' momenta and field buffers (and a last pass closes a
@@ -392,7 +400,8 @@ int ihmc_copy_bandwidth(ihmc_ctx* ctx, uint64_t bytes, int32_t reps, double* avg
  * not NULL) = number of classes of ndim (out may be NULL to ask only that). */
 int ihmc_tile_shape(int32_t ndim, int32_t cls, int32_t* out, int32_t* n_classes);
 /* Autotune: for each distinct key among lats[0..n) (state precision
- * precision[i]), time the middle pass of every tile class and keep the fastest
+ * precision[i]), time the middle steps of every tile class (two per launch in 2D
+ * when step fusion is on, see ihmc_ctx_set_step_fusion) and keep the fastest
  * in the table (the built-in rule's class stays unless another is over 3 % faster).  A measurement
  * runs on the context stream over replicas of the lattice with synthetic
  * fields, about `sites` sites in all (at most 65536 replicas): the working set
@@ -402,7 +411,7 @@ int ihmc_tile_shape(int32_t ndim, int32_t cls, int32_t* out, int32_t* n_classes)
  * will run together); the value is clamped to [2^20, 2^26].  Per class, `reps`
  * launches (0: 10, or 4 above 2^23 sites) after a warm-up, in three rounds
  * interleaved across the classes, keeping the least mean.  The arena must hold
- * the replicas (4 state fields, 5 with a per-site field, each replica) for the
+ * the replicas (6 state fields, 7 with a per-site field, each replica) for the
  * duration of one key.  Keys with a measured entry are skipped unless flags has
  * IHMC_TUNE_FORCE; pinned keys are always skipped.  Synchronous; *n_measured
  * (may be NULL) = keys measured.  Existing chains keep their classes. */

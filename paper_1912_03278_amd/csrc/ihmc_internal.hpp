@@ -121,6 +121,16 @@ constexpr int LAT_BUFFERS = 4;
 inline __host__ __device__ int lat_in_buf(int cur, int k) { return k == 0 ? cur : (cur + 1 + (k - 1) % 3) % 4; }
 inline __host__ __device__ int lat_out_buf(int cur, int k) { return (cur + 1 + k % 3) % 4; }
 
+// Momentum buffers of a lattice chain (two).  In 2D, launch k >= 1 reads
+// buffer lat_p_in(k) and writes lat_p_out(k): a launch that fuses two steps
+// reads the momenta of neighbouring tiles, so it must not write the buffer it
+// reads.  The first pass, the last pass and the force pass use buffer 0 (where
+// given momenta are read and final ones exported); 3D passes update buffer 0
+// in place.
+constexpr int LAT_P_BUFFERS = 2;
+inline __host__ __device__ int lat_p_in(int k) { return k == 0 ? 0 : (k - 1) & 1; }
+inline __host__ __device__ int lat_p_out(int k) { return k & 1; }
+
 // Dense chains (three buffers): buffer read by pass j when the accepted field
 // sits in buffer `cur`.
 inline __host__ __device__ int pass_in_buf(int cur, int j) {

@@ -7,7 +7,8 @@
 
 namespace ihmc {
 
-enum PassMode : int { PASS_FIRST = 0, PASS_MIDDLE = 1, PASS_LAST = 2, PASS_MEASURE = 3, PASS_FORCE = 4 };
+// PASS_PAIR: the middle steps j and j + 1 in one launch (2D tile classes only).
+enum PassMode : int { PASS_FIRST = 0, PASS_MIDDLE = 1, PASS_LAST = 2, PASS_MEASURE = 3, PASS_FORCE = 4, PASS_PAIR = 5 };
 
 struct TileShape {
   int bx, by, bz;

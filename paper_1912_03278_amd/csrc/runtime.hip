@@ -300,7 +300,7 @@ uint32_t chain_tile_count(const ChainDev& c) {
 // `members` (indices into cd), each sorted by pass count (descending), and
 // their tiles appended to `tiles` (group tile offsets relative to its start).
 void plan_groups(const std::vector<ChainDev>& cd, const std::vector<int>& members, std::vector<Group>& groups,
-                 std::vector<Tile>& tiles) {
+                 std::vector<Tile>& tiles, bool fuse_steps) {
   const int base = (int)tiles.size();
   std::map<std::tuple<int, int, int>, std::vector<int>> byk;
   for (int i : members)
@@ -313,6 +313,7 @@ void plan_groups(const std::vector<ChainDev>& cd, const std::vector<int>& member
     g.order = kv.second;
     std::stable_sort(g.order.begin(), g.order.end(), [&](int a, int b) { return cd[a].n_pass > cd[b].n_pass; });
     const bool resident = (g.cls == RESIDENT_CLASS);
+    g.pair = fuse_steps && g.ndim == 2 && !resident;
     const TileShape ts = resident ? TileShape{1, 1, 1} : tile_shape(g.prec, g.ndim, g.cls);
     g.tile_off = (int)tiles.size() - base;
     for (int ci : g.order) {
@@ -463,6 +464,12 @@ extern "C" int ihmc_ctx_set_resident(ihmc_ctx* c, int64_t max_sites, int64_t* fp
   return IHMC_OK;
 }
 
+extern "C" int ihmc_ctx_set_step_fusion(ihmc_ctx* c, int32_t on) {
+  if (!c) return set_error(IHMC_E_INVAL, "ctx is NULL");
+  c->fuse_steps = on ? 1 : 0;
+  return IHMC_OK;
+}
+
 extern "C" int ihmc_ctx_memory(ihmc_ctx* c, uint64_t* used, uint64_t* total) {
   if (!c) return set_error(IHMC_E_INVAL, "ctx is NULL");
   if (used) *used = c->arena.used;
@@ -516,7 +523,7 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
     const int64_t N = c.N, NP = c.NP;
     const int64_t pb = r.precision;
     c.psi = dalloc((uint64_t)LAT_BUFFERS * NP * pb);
-    c.p = dalloc(NP * pb);
+    c.p = dalloc((uint64_t)LAT_P_BUFFERS * NP * pb);
     c.rec = (TrajRecord*)dalloc(sizeof(TrajRecord) * (uint64_t)std::max(1, r.n_traj));
     c.st = (ChainState*)dalloc(sizeof(ChainState));
     void* pblk = dalloc(partials_bytes(c.n_tiles));
@@ -556,7 +563,7 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
   {
     std::vector<int> members(n);
     for (int i = 0; i < n; ++i) members[i] = i;
-    plan_groups(cd, members, groups, all_tiles);
+    plan_groups(cd, members, groups, all_tiles, ctx->fuse_steps != 0);
   }
   // streams and events of the per-round fork/join (default priority)
   {
@@ -680,7 +687,46 @@ hipError_t enqueue_round_plan(const std::vector<Group>& groups, const Tile* d_ti
     e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_FIRST, d_cd, base, g.tile_begin.back(), 0, 0, gs);
     if (e != hipSuccess) return e;
     const int nc = (int)g.order.size();
-    for (int j = 1; j < g.max_pass; ++j) {
+    if (g.pair) {
+      // Middle steps in pairs (1, 2), (3, 4), ...: launch k = 1 + (j - 1) / 2
+      // runs the pair starting at odd j, or step j alone where it is a chain's
+      // last middle step; the last pass of a chain ending at pass j is launch
+      // 1 + j / 2.  Per odd j, in chain order (descending pass count): pairs
+      // for the chains with passes after j + 1, the single step for those
+      // ending at j + 1, LAST(j) for those ending at j.
+      for (int j = 1; j < g.max_pass; j += 2) {
+        const int k = 1 + (j - 1) / 2;
+        int pair_end = 0;
+        while (pair_end < nc && g.n_pass[pair_end] - 1 > j + 1) ++pair_end;
+        int single_end = pair_end;
+        while (single_end < nc && g.n_pass[single_end] - 1 == j + 1) ++single_end;
+        int last_end = single_end;
+        while (last_end < nc && g.n_pass[last_end] - 1 == j) ++last_end;
+        if (last_end > single_end) {
+          hipEvent_t after_prev = next_event();
+          if ((e = hipEventRecord(after_prev, gs)) != hipSuccess) return e;
+          if ((e = hipStreamWaitEvent(ls, after_prev, 0)) != hipSuccess) return e;
+          const int t0 = g.tile_begin[single_end], t1 = g.tile_begin[last_end];
+          e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_LAST, d_cd, base + t0, t1 - t0, j, k, ls);
+          if (e != hipSuccess) return e;
+        }
+        if (single_end > pair_end) {
+          const int t0 = g.tile_begin[pair_end], t1 = g.tile_begin[single_end];
+          e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_MIDDLE, d_cd, base + t0, t1 - t0, j, k, gs);
+          if (e != hipSuccess) return e;
+          hipEvent_t after_single = next_event();
+          if ((e = hipEventRecord(after_single, gs)) != hipSuccess) return e;
+          if ((e = hipStreamWaitEvent(ls, after_single, 0)) != hipSuccess) return e;
+          e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_LAST, d_cd, base + t0, t1 - t0, j + 1, k + 1, ls);
+          if (e != hipSuccess) return e;
+        }
+        if (pair_end > 0) {
+          e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_PAIR, d_cd, base, g.tile_begin[pair_end], j, k, gs);
+          if (e != hipSuccess) return e;
+        }
+      }
+    }
+    for (int j = 1; !g.pair && j < g.max_pass; ++j) {
       int mid_end = 0;
       while (mid_end < nc && g.n_pass[mid_end] - 1 > j) ++mid_end;
       int last_end = mid_end;
@@ -1255,15 +1301,20 @@ extern "C" int ihmc_chains_time_pass(ihmc_chains* ch, int32_t group, int32_t mod
   ihmc_ctx* ctx = c->ctx;
   CTX_OK(ctx);
   if (group < 0 || group >= (int32_t)c->groups.size()) return set_error(IHMC_E_INVAL, "group out of range");
-  if (mode != PASS_FIRST && mode != PASS_MIDDLE && mode != PASS_LAST)
-    return set_error(IHMC_E_INVAL, "only FIRST, MIDDLE and LAST passes can be timed");
+  if (mode != PASS_FIRST && mode != PASS_MIDDLE && mode != PASS_LAST && mode != PASS_PAIR)
+    return set_error(IHMC_E_INVAL, "only FIRST, MIDDLE, LAST and PAIR passes can be timed");
   if (reps < 1) return set_error(IHMC_E_INVAL, "reps must be >= 1");
   const Group& g = c->groups[group];
   if (g.cls == RESIDENT_CLASS)
     return set_error(IHMC_E_UNSUPPORTED, "group %d runs LDS-resident whole trajectories, not passes", group);
-  for (int ci : g.order)
+  if (mode == PASS_PAIR && g.ndim != 2)
+    return set_error(IHMC_E_UNSUPPORTED, "group %d: two-step launches are 2D only", group);
+  for (int ci : g.order) {
     if (mode == PASS_MIDDLE && c->cd[ci].n_pass < 3)
       return set_error(IHMC_E_INVAL, "chain %d has no middle pass", ci);
+    if (mode == PASS_PAIR && c->cd[ci].n_pass < 4)
+      return set_error(IHMC_E_INVAL, "chain %d has fewer than two middle steps", ci);
+  }
   int64_t nsite = 0;
   for (int ci : g.order) nsite += c->cd[ci].N;
   hipStream_t s = ctx->stream;

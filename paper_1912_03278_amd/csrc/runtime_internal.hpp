@@ -81,6 +81,7 @@ int tune_load(TuneTable& t, const char* path);
 // Chains of equal state precision and dimension share launches.
 struct Group {
   int prec = 4, ndim = 2, cls = 0;
+  bool pair = false;            // middle steps two per launch (PASS_PAIR)
   std::vector<int> order;       // chain indices, sorted by pass count (descending)
   std::vector<int> n_pass;      // pass count per position in `order`
   std::vector<int> tile_begin;  // first tile of each position, relative to tile_off; size+1
@@ -95,8 +96,9 @@ int64_t lattice_sites(const ihmc_lattice& l);
 // Descriptor of one chain whose passes use tile class `cls` (no device memory).
 void describe_chain(const ihmc_lattice& l, const ihmc_run& r, int flags, int cls, ChainDev& c);
 uint32_t chain_tile_count(const ChainDev& c);
+// fuse_steps: 2D tiled groups run their middle steps two per launch.
 void plan_groups(const std::vector<ChainDev>& cd, const std::vector<int>& members, std::vector<Group>& groups,
-                 std::vector<Tile>& tiles);
+                 std::vector<Tile>& tiles, bool fuse_steps);
 size_t round_events(const std::vector<Group>& groups);
 // One trajectory of every chain of the plan: FIRST over all tiles of a group,
 // then MIDDLE / LAST per pass index; groups on side streams (two per group).
@@ -162,4 +164,5 @@ struct ihmc_ctx {
   bool dead = false;
   ihmc::TuneTable tune;
   int64_t resident_sites = -1;  // chains up to this many sites run LDS-resident (-1: as many as fit, 0: none)
+  int32_t fuse_steps = 1;       // 2D tiled chains run two middle steps per launch
 };

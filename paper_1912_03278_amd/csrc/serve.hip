@@ -66,8 +66,9 @@ static uint64_t request_bytes(const ihmc_lattice& l, const ihmc_run& r, int cls)
   const int64_t pitch = (l.L[0] + 3) & ~3;
   const int64_t NP = pitch * (N / l.L[0]);
   const uint64_t pb = (uint64_t)r.precision;
-  uint64_t b = r256((uint64_t)LAT_BUFFERS * NP * pb) + r256(NP * pb) + r256(sizeof(TrajRecord) * (uint64_t)std::max(1, r.n_traj)) +
-               r256(sizeof(ChainState)) + r256(8 * (uint64_t)N);
+  uint64_t b = r256((uint64_t)LAT_BUFFERS * NP * pb) + r256((uint64_t)LAT_P_BUFFERS * NP * pb) +
+               r256(sizeof(TrajRecord) * (uint64_t)std::max(1, r.n_traj)) + r256(sizeof(ChainState)) +
+               r256(8 * (uint64_t)N);
   if (r.replay_accept) b += r256((uint64_t)r.n_traj);
   if (l.h_len == N && N > 1) b += r256(8 * NP) + r256(NP * pb) + r256(8 * 4 * (uint64_t)N) + r256(8 * (uint64_t)N);
   ChainDev c;
@@ -240,7 +241,7 @@ bool ihmc_server::admit_setup(std::vector<Request*>& fresh) {
       return p;
     };
     c.psi = dal((uint64_t)LAT_BUFFERS * c.NP * pb);
-    c.p = dal(c.NP * pb);
+    c.p = dal((uint64_t)LAT_P_BUFFERS * c.NP * pb);
     c.rec = (TrajRecord*)dal(sizeof(TrajRecord) * (uint64_t)std::max(1, r->run.n_traj));
     c.st = (ChainState*)dal(sizeof(ChainState));
     void* pblk = dal(partials_bytes(c.n_tiles));
@@ -310,7 +311,7 @@ bool ihmc_server::admit_setup(std::vector<Request*>& fresh) {
     for (Request* r : ok) slots.push_back(r->slot);
     std::vector<Group> g;
     std::vector<Tile> tiles;
-    plan_groups(cd_host, slots, g, tiles);
+    plan_groups(cd_host, slots, g, tiles, ctx->fuse_steps != 0);
     if (!ensure_tiles(tiles.size())) {
       e = hipErrorOutOfMemory;
     } else {
@@ -361,7 +362,7 @@ bool ihmc_server::run_round() {
   if (slots.empty()) return true;
   std::vector<Group> g;
   std::vector<Tile> tiles;
-  plan_groups(cd_host, slots, g, tiles);
+  plan_groups(cd_host, slots, g, tiles, ctx->fuse_steps != 0);
   const auto t_start = std::chrono::steady_clock::now();
   hipError_t e = hipSuccess;
   if (!ensure_tiles(tiles.size()) || !ensure_streams(g.size(), round_events(g))) e = hipErrorOutOfMemory;

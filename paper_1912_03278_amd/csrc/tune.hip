@@ -83,7 +83,8 @@ constexpr int64_t kTuneMinSites = int64_t(1) << 20;  // a launch this large fill
 constexpr int64_t kTuneMaxSites = int64_t(1) << 26;
 constexpr int64_t kTuneMaxReplicas = 65536;
 
-// Middle-pass nanoseconds per site of every class of key k: replicas of the
+// Nanoseconds per site and middle step of every class of key k (timed on the
+// two-step launch for 2D when the context fuses steps): replicas of the
 // lattice, each with its own fields, `sites` sites in all (the working set the
 // choice is for: whether it streams from HBM or stays in the last-level cache
 // decides which tile is fastest), one launch over all their tiles.
@@ -111,7 +112,8 @@ static int measure_key(ihmc_ctx* ctx, const TileKey& k, int64_t sites, int reps,
   const int64_t R = std::min(kTuneMaxReplicas, std::max<int64_t>(1, (sites + N / 2) / N));
   const int ncls = tile_class_count(k.ndim);
   const uint64_t pb = (uint64_t)k.prec;
-  const uint64_t fb = r256(((uint64_t)LAT_BUFFERS + 1ull + (uint64_t)k.site_field) * (uint64_t)c0.NP * pb);
+  const uint64_t fb =
+      r256(((uint64_t)LAT_BUFFERS + (uint64_t)LAT_P_BUFFERS + (uint64_t)k.site_field) * (uint64_t)c0.NP * pb);
 
   std::vector<std::vector<Tile>> tl(ncls);
   for (int cls = 0; cls < ncls; ++cls) {
@@ -155,7 +157,7 @@ static int measure_key(ihmc_ctx* ctx, const TileKey& k, int64_t sites, int reps,
     char* f = fields + q * fb;
     cd[q].psi = f;
     cd[q].p = f + LAT_BUFFERS * c0.NP * pb;
-    cd[q].b = k.site_field ? (const void*)(f + (LAT_BUFFERS + 1) * c0.NP * pb) : nullptr;
+    cd[q].b = k.site_field ? (const void*)(f + (LAT_BUFFERS + LAT_P_BUFFERS) * c0.NP * pb) : nullptr;
     cd[q].st = st + q;
   }
   const int64_t nel = (int64_t)(R * fb / pb);
@@ -175,18 +177,21 @@ static int measure_key(ihmc_ctx* ctx, const TileKey& k, int64_t sites, int reps,
   // three interleaved rounds over the classes; the minimum of the round means
   double best[kMaxTileClasses];
   for (int cls = 0; cls < kMaxTileClasses; ++cls) best[cls] = NAN;
+  const bool pair = (k.ndim == 2) && ctx->fuse_steps;
+  const int mode = pair ? PASS_PAIR : PASS_MIDDLE;
+  const double steps = pair ? 2.0 : 1.0;
   for (int round = 0; round < 3; ++round) {
     for (int cls = 0; cls < ncls; ++cls) {
       const int nt = (int)tl[cls].size();
-      HIPCHK(launch_lattice_pass(k.prec, k.ndim, cls, PASS_MIDDLE, d_cd, d_tl[cls], nt, 1, 1, s), "tune warm-up");
+      HIPCHK(launch_lattice_pass(k.prec, k.ndim, cls, mode, d_cd, d_tl[cls], nt, 1, 1, s), "tune warm-up");
       HIPCHK(hipEventRecord(rel.e0, s), "event record");
       for (int i = 0; i < reps; ++i)
-        HIPCHK(launch_lattice_pass(k.prec, k.ndim, cls, PASS_MIDDLE, d_cd, d_tl[cls], nt, 1, 1, s), "tune pass");
+        HIPCHK(launch_lattice_pass(k.prec, k.ndim, cls, mode, d_cd, d_tl[cls], nt, 1, 1, s), "tune pass");
       HIPCHK(hipEventRecord(rel.e1, s), "event record");
       HIPCHK(hipEventSynchronize(rel.e1), "event sync");
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, rel.e0, rel.e1), "event time");
-      const double v = 1e6 * (double)ms / reps / (double)(R * N);
+      const double v = 1e6 * (double)ms / reps / (double)(R * N) / steps;
       if (!(best[cls] <= v)) best[cls] = v;
     }
   }

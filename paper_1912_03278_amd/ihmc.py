@@ -21,6 +21,7 @@ STATUS = {-1: "IHMC_E_INVAL", -2: "IHMC_E_NOMEM", -3: "IHMC_E_AGAIN", -4: "IHMC_
           -5: "IHMC_E_CANCELLED", -6: "IHMC_E_UNSUPPORTED"}
 F32, F64 = 4, 8
 LEAPFROG, OMELYAN = 0, 1
+FIRST, MIDDLE, LAST, PAIR = 0, 1, 2, 5  # pass kinds of Chains.time_pass
 TAG_INIT, TAG_MOM, TAG_ACC, TAG_FLIP = 1, 2, 3, 4
 
 EXPORTS = (
@@ -34,7 +35,7 @@ EXPORTS = (
     "ihmc_submit", "ihmc_poll", "ihmc_wait", "ihmc_fetch", "ihmc_cancel", "ihmc_server_stats",
     "ihmc_tile_shape", "ihmc_tune", "ihmc_tune_lookup", "ihmc_tune_pin", "ihmc_tune_save", "ihmc_tune_load",
     "ihmc_tune_check", "ihmc_chains_checkpoint", "ihmc_chains_restore", "ihmc_dense_checkpoint",
-    "ihmc_dense_restore", "ihmc_ctx_set_resident",
+    "ihmc_dense_restore", "ihmc_ctx_set_resident", "ihmc_ctx_set_step_fusion",
 )
 TUNE_RULE, TUNE_MEASURED, TUNE_PINNED = 0, 1, 2
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED, REQ_FAILED = 0, 1, 2, 3, 4
@@ -103,6 +104,7 @@ def load():
     L.ihmc_ctx_sync.argtypes = [vp]
     L.ihmc_ctx_memory.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
     L.ihmc_ctx_set_resident.argtypes = [vp, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    L.ihmc_ctx_set_step_fusion.argtypes = [vp, C.c_int32]
     L.ihmc_last_error.restype = C.c_char_p
     L.ihmc_chains_create.argtypes = [vp, C.c_int32, C.POINTER(_Lattice), C.POINTER(_Run), pp]
     L.ihmc_chains_advance.argtypes = [vp, C.c_int32]
@@ -301,7 +303,7 @@ def _result_dict(r, arrays):
 class Context:
     """A device context: HIP stream plus an arena of device memory from torch."""
 
-    def __init__(self, device=0, arena_bytes=1 << 30, use_torch=True, resident=-1):
+    def __init__(self, device=0, arena_bytes=1 << 30, use_torch=True, resident=-1, fuse_steps=True):
         L = load()
         self._keep = []
         if use_torch:
@@ -328,6 +330,8 @@ class Context:
         self.h = h
         if resident != -1:
             self.set_resident(resident)
+        if not fuse_steps:
+            self.set_step_fusion(False)
 
     def set_resident(self, max_sites=-1):
         """Chains created afterwards with at most max_sites sites (and small enough
@@ -337,6 +341,11 @@ class Context:
         f32, f64 = C.c_int64(), C.c_int64()
         _check(load().ihmc_ctx_set_resident(self.h, int(max_sites), C.byref(f32), C.byref(f64)))
         return f32.value, f64.value
+
+    def set_step_fusion(self, on=True):
+        """2D chains on the tiled passes run their middle steps two per launch
+        (bit-identical results); applies to chain sets created afterwards."""
+        _check(load().ihmc_ctx_set_step_fusion(self.h, 1 if on else 0))
 
     def close(self):
         if getattr(self, "h", None):
@@ -544,7 +553,8 @@ class Chains:
         return dict(zip(("precision", "ndim", "cls", "chains", "sites", "tiles"), (int(v) for v in out)))
 
     def time_pass(self, group, mode=1, reps=50):
-        """Mean duration (us) of one fused pass launch of a group, timed with HIP events."""
+        """Mean duration (us) of one fused pass launch of a group, timed with HIP events
+        (mode 0 first, 1 middle, 2 last, PAIR = two middle steps, 2D only)."""
         us, sites, nd, pr = C.c_double(), C.c_int64(), C.c_int32(), C.c_int32()
         _check(load().ihmc_chains_time_pass(self.h, int(group), int(mode), int(reps), C.byref(us),
                                             C.byref(sites), C.byref(nd), C.byref(pr)))
