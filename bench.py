@@ -6,12 +6,14 @@ Hamiltonian reductions, J = 1, h = 0, 20 leap-frog steps per unit trajectory:
   * 2D 1024 x 1024 torus at beta_c = ln(1 + sqrt 2)/2, C = 4.1;
   * 3D 128^3 torus at beta = 0.2216544, C = 6.1.
 Seeded Gaussian initial fields (Philox).  One step = one HMC trajectory of both
-chains (21 fused passes each, Metropolis on the device); the metric is
-site-MD-steps/s = (sites x MD steps) per second over the timed steps.
+chains (21 fused passes each, Metropolis on the device; the 2D chain's middle
+steps run two per launch unless --fuse off); the metric is site-MD-steps/s =
+(sites x MD steps) per second over the timed steps.
 
 Besides the throughput line it reports the roofline of the dominant kernel (the
-fused middle pass: 16 bytes of state per site, HIP-event timed on the library's
-stream) and the FP64 CPU oracle timed on a bounded sample of the same workload.
+fused middle pass, one or two steps per launch: 16 bytes of state per site and
+launch, HIP-event timed on the library's stream) and the FP64 CPU oracle timed
+on a bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -43,15 +45,21 @@ KERNEL_SOURCES = ("lattice_kernels.hip", "lattice_kernels.hpp", "chain_epilogue.
                   "ihmc_internal.hpp", "dense_kernels.hip", "dense_kernels.hpp")
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
-    "large_2d_middle": {"sources": "1008d5e1fbd81d89", "tiles": "64x16", "sites": 1048576,
-                        "fetch_kib": 4199.0, "write_kib": 8192.0},
-    "large_3d_middle": {"sources": "1008d5e1fbd81d89", "tiles": "32x8x8", "sites": 2097152,
-                        "fetch_kib": 9295.5, "write_kib": 16384.0},
-    "stream_2d_middle": {"sources": "1008d5e1fbd81d89", "tiles": "64x16", "sites": 67108864,
-                         "fetch_kib": 263706.2, "write_kib": 524288.0},
-    "batched_middle": {"sources": "1008d5e1fbd81d89", "tiles": "64x16", "sites": 26410815,
-                       "fetch_kib": 157058.6, "write_kib": 208439.2},
-    "dense_gemm_bf16": {"sources": "1008d5e1fbd81d89", "fetch_kib": 73752.0, "write_kib": 16384.0},
+    "large_2d_middle": {"sources": "194ab5651bd7ffb9", "tiles": "64x16", "sites": 1048576,
+                        "fetch_kib": 4207.0, "write_kib": 8192.0},
+    "large_2d_pair": {"sources": "194ab5651bd7ffb9", "tiles": "64x16", "sites": 1048576,
+                      "fetch_kib": 4353.5, "write_kib": 8192.0},
+    "large_3d_middle": {"sources": "194ab5651bd7ffb9", "tiles": "32x8x8", "sites": 2097152,
+                        "fetch_kib": 9300.0, "write_kib": 16384.0},
+    "stream_2d_middle": {"sources": "194ab5651bd7ffb9", "tiles": "64x16", "sites": 67108864,
+                         "fetch_kib": 263726.7, "write_kib": 524288.0},
+    "stream_2d_pair": {"sources": "194ab5651bd7ffb9", "tiles": "64x16", "sites": 67108864,
+                       "fetch_kib": 265260.4, "write_kib": 524288.0},
+    "batched_middle": {"sources": "194ab5651bd7ffb9", "tiles": "64x16", "sites": 27859003,
+                       "fetch_kib": 165575.8, "write_kib": 219679.1},
+    "batched_pair": {"sources": "194ab5651bd7ffb9", "tiles": "64x16", "sites": 27859003,
+                     "fetch_kib": 165705.1, "write_kib": 219995.7},
+    "dense_gemm_bf16": {"sources": "194ab5651bd7ffb9", "fetch_kib": 73752.0, "write_kib": 16384.0},
 }
 
 
@@ -151,17 +159,23 @@ def streaming_point(args, copy_gbs):
     dt = time.perf_counter() - t0
     acc = ch.result(0, want_psi=False)["acceptance"]
     mid = ch.time_pass(0, mode=1, reps=max(5, args.timing_reps // 5))
+    pair = ch.time_pass(0, mode=ihmc.PAIR, reps=max(5, args.timing_reps // 5)) if args.fuse_steps else None
     ch.close()
     ctx.close()
     gbs = BYTES_MIDDLE_F32 * mid["sites"] / (mid["us"] * 1e-6) / 1e9
     print(f"bench: streaming point 8192^2 middle pass {mid['us']:.1f} us = {gbs:.0f} GB/s", file=sys.stderr,
           flush=True)
+    extra = {}
+    if pair:
+        pgbs = BYTES_MIDDLE_F32 * pair["sites"] / (pair["us"] * 1e-6) / 1e9
+        extra = {"two_step_pass_us": round(pair["us"], 2), "two_step_achieved_GBs": round(pgbs, 1),
+                 "two_step_traffic": traffic_bytes("stream_2d_pair", sites=pair["sites"])}
     return {"label": "extra point, not the configured workload: one 2D 8192^2 chain at beta_c, FP32, n_md=20",
             "site_md_steps_per_s": 4 * L * L * 20 / dt, "acceptance": acc,
             "middle_pass_us": round(mid["us"], 2), "bytes_per_launch": BYTES_MIDDLE_F32 * mid["sites"],
             "traffic": traffic_bytes("stream_2d_middle", sites=mid["sites"]),
             "achieved_GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
-            "frac_of_copy": round(gbs / copy_gbs, 4)}
+            "frac_of_copy": round(gbs / copy_gbs, 4), **extra}
 
 
 def bench_small(args):
