@@ -125,18 +125,25 @@ def group_rows(chains, reps, modes=(1,), pair=False):
     return rows
 
 
-def cpu_baseline(chains):
-    """The FP64 oracle, single-threaded, one trajectory of each chain."""
+def cpu_baseline(chains, min_seconds=10.0, max_traj=8):
+    """The FP64 oracle, single-threaded: one trajectory of each chain, repeated
+    as whole chains of k trajectories until about min_seconds of CPU work
+    (k <= max_traj)."""
     import oracle
-    t_total, work = 0.0, 0
-    for w in chains:
-        lat = oracle.Lattice(w["L"], beta=w["beta"], C=w["C"])
-        t0 = time.perf_counter()
-        oracle.run(lat, 1, w["n_md"], seed=w["seed"], chain_id=w["chain_id"])
-        t_total += time.perf_counter() - t0
-        work += int(math.prod(w["L"])) * w["n_md"]
+    t_total, work, k = 0.0, 0, 1
+    while True:
+        for w in chains:
+            lat = oracle.Lattice(w["L"], beta=w["beta"], C=w["C"])
+            t0 = time.perf_counter()
+            oracle.run(lat, k, w["n_md"], seed=w["seed"], chain_id=w["chain_id"])
+            t_total += time.perf_counter() - t0
+            work += k * int(math.prod(w["L"])) * w["n_md"]
+        if t_total >= min_seconds or k >= max_traj:
+            break
+        k = min(max_traj, max(1, math.ceil((min_seconds - t_total) * k / t_total)))
+    n = work // sum(int(math.prod(w["L"])) * w["n_md"] for w in chains)
     return dict(value=work / t_total, unit="site-MD-steps/s", cores=1, kind="oracle",
-                sample="one trajectory (20 MD steps) of the 1024^2 and the 128^3 chain, FP64, "
+                sample=f"{n} trajectories (20 MD steps each) of the 1024^2 and of the 128^3 chain, FP64, "
                        f"{t_total:.1f} s on one host core")
 
 
