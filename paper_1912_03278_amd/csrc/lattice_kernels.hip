@@ -616,19 +616,23 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v_pair(const ChainDe
 
 // ------------------------------------------------------------ 3D, one phase ---
 //
-// A block owns a BX x BY x ZR box, one x-y column per thread, ZR sites deep.
-// psi on the box plus its 2-wide halo is staged in LDS in one phase, in
-// aligned 4-element chunks (rows of RP = BX + 8 values with lattice x at
-// x - x0 + 4, as in 2D), so every load of the block is in flight at once; w on
-// the box plus its 1-wide halo follows in quads (the outermost quad of a row is
-// unused), then each thread updates its column plane by plane.  The column's
-// momenta and field values are fetched before the staging.  Sums of the FP64
-// terms follow the same order as in every other tiling: per column over the
-// ZR planes in z order, then per x-aligned quad of columns.
+// A block owns a BX x BY x ZR box, one thread per x-y column and aligned
+// 4-plane slab (256 threads per slab: the LDS a box stages allows four boxes
+// per CU, so an 8-plane box runs eight waves rather than four, to hide the
+// latency of a chain too small to fill the GPU).  psi on the box plus its
+// 2-wide halo is staged in LDS in one phase, in aligned 4-element chunks (rows
+// of RP = BX + 8 values with lattice x at x - x0 + 4, as in 2D), so every load
+// of the block is in flight at once; w on the box plus its 1-wide halo follows
+// in quads (the outermost quad of a row is unused), then each thread updates
+// its column's slab plane by plane.  The momenta and field values of the slab
+// are fetched before the staging.  Sums of the FP64 terms follow the same
+// order as in every other tiling: per column over each 4-plane slab in z order,
+// then per x-aligned quad of columns.
 template <typename T, int BX, int BY, int ZR, int MODE>
-__global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict__ chains,
-                                                      const Tile* __restrict__ tiles, int n_tiles, int j,
-                                                              int k) {
+__global__ __launch_bounds__(64 * ZR) void lattice_pass3t(const ChainDev* __restrict__ chains,
+                                                          const Tile* __restrict__ tiles, int n_tiles, int j,
+                                                          int k) {
+  constexpr int NT = 64 * ZR;  // 256 threads per 4-plane slab
   constexpr int RP = BX + 8;
   constexpr int NCH = RP / 4;  // 16-byte chunks per staged row
   constexpr int PR = BY + 4, PZ = ZR + 4;
@@ -636,7 +640,7 @@ __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict
   constexpr int PPL = PR * RP, WPL = WR * RP;
   constexpr bool kHasW = (MODE != PASS_MEASURE);
   constexpr bool kH64 = (MODE == PASS_LAST || MODE == PASS_MEASURE);
-  static_assert(BX * BY == 256 && BX % 4 == 0, "one column per thread");
+  static_assert(BX * BY == 256 && BX % 4 == 0 && ZR % 4 == 0, "one column and slab per thread");
   __shared__ __align__(16) T sP[PZ * PPL];
   __shared__ __align__(16) T sW[kHasW ? WZ * WPL : 4];
 
@@ -660,22 +664,24 @@ __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict
   const gmem<T>* __restrict__ bsite = (const gmem<T>*)cd.b;
   const bool site_field = (cd.h_kind == 2);
 
-  // ---- the column's momenta and field values
-  const int lx = threadIdx.x % BX, ly = threadIdx.x / BX;
+  // ---- the momenta and field values of the thread's column and slab (planes
+  // kz0 .. kz0 + 3 of the box)
+  const int kz0 = 4 * (threadIdx.x / 256);
+  const int lx = threadIdx.x % BX, ly = (threadIdx.x % 256) / BX;
   const int gx = tl.x0 + lx, gy = tl.y0 + ly;
   const bool act = (gx < L0) && (gy < L1);
   const int64_t col = gx + (int64_t)pitch * gy;
   constexpr bool kLoadP = (MODE == PASS_MIDDLE || MODE == PASS_LAST || MODE == PASS_FIRST);
   const bool load_p = kLoadP && act && (MODE != PASS_FIRST || cd.p_given);
   const bool load_b = kHasW && act && site_field;
-  T pcol[ZR], bcol[ZR];
+  T pcol[4], bcol[4];
 #pragma unroll
-  for (int k = 0; k < ZR; ++k) {
+  for (int k = 0; k < 4; ++k) {
     pcol[k] = (T)0;
     bcol[k] = b_uniform;
-    if (tl.z0 + k < z_end) {
-      if (load_p) pcol[k] = pmom[col + plane * (tl.z0 + k)];
-      if (load_b) bcol[k] = bsite[col + plane * (tl.z0 + k)];
+    if (tl.z0 + kz0 + k < z_end) {
+      if (load_p) pcol[k] = pmom[col + plane * (tl.z0 + kz0 + k)];
+      if (load_b) bcol[k] = bsite[col + plane * (tl.z0 + kz0 + k)];
     }
   }
 
@@ -686,7 +692,7 @@ __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict
   const bool rows_near = (L1 > BY), planes_near = (L2 > ZR), x_near = (L0 > BX + 2);
   {
     constexpr int NPAIR = NCH * PR;
-    constexpr int NH = 256 / NPAIR;
+    constexpr int NH = NT / NPAIR;
     constexpr int NPP = (PZ + NH - 1) / NH;  // planes per thread
     static_assert(NH >= 1, "box row too long for one block");
     const int pair = threadIdx.x % NPAIR, h = threadIdx.x / NPAIR;
@@ -712,8 +718,8 @@ __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict
     if (MODE == PASS_FIRST && !cd.p_given && (L0 & 1) == 0) {
       const bool even = (gx & 1) == 0;
 #pragma unroll
-      for (int k = 0; k < ZR; k += 2) {
-        const int64_t z = tl.z0 + k + (even ? 0 : 1);
+      for (int k = 0; k < 4; k += 2) {
+        const int64_t z = tl.z0 + kz0 + k + (even ? 0 : 1);
         const int64_t site = (gx & ~1) + (int64_t)L0 * (gy + (int64_t)L1 * z);
         T z0, z1;
         normal_pair<T>(cd, (uint32_t)traj, TAG_MOM, site >> 1, z0, z1);
@@ -744,7 +750,7 @@ __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict
   // thread t computes chunk column t % NCH of the w rows t / NCH + RG k
   if (kHasW) {
     constexpr int NWROW = WZ * WR;
-    constexpr int RG = 256 / NCH;
+    constexpr int RG = NT / NCH;
     constexpr int NIT = (NWROW + RG - 1) / RG;
     const int c = threadIdx.x % NCH, rg = threadIdx.x / NCH;
 #pragma unroll
@@ -794,7 +800,8 @@ __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict
   }
 
 #pragma unroll
-  for (int k = 0; k < ZR; ++k) {
+  for (int kk = 0; kk < 4; ++kk) {
+    const int k = kz0 + kk;  // plane of the box
     const int z = tl.z0 + k;
     if (z < z_end) {
       const int64_t idx = col + plane * z;
@@ -806,11 +813,11 @@ __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict
         T sw = (sW[q - 1] + sW[q + 1]) + (sW[q - RP] + sW[q + RP]);
         sw = sw + (sW[q - WPL] + sW[q + WPL]);
         T F = fma_t(Ct, sW[q], sw);
-        F = F + bcol[k];
+        F = F + bcol[kk];
         T p;
         if (MODE == PASS_FIRST) {
           if (cd.p_given || (L0 & 1) == 0) {
-            p = pcol[k];
+            p = pcol[kk];
           } else {
             const int64_t site = gx + (int64_t)L0 * (gy + (int64_t)L1 * z);
             T z0, z1;
@@ -822,7 +829,7 @@ __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict
         } else if (MODE == PASS_FORCE) {
           p = (T)0;
         } else {
-          p = pcol[k];
+          p = pcol[kk];
         }
         const T pn = fma_t(kick, F, p);
         if (MODE == PASS_FIRST || MODE == PASS_MIDDLE) {
@@ -863,7 +870,7 @@ __global__ __launch_bounds__(256) void lattice_pass3t(const ChainDev* __restrict
 
   if (MODE == PASS_MIDDLE || MODE == PASS_FORCE) return;
   const int tix = ((tl.z0 / ZR) * ((L1 + BY - 1) / BY) + tl.y0 / BY) * ((L0 + BX - 1) / BX) + tl.x0 / BX;
-  block_accumulate<MODE, 4>(cd, st, acc, bad, lat_in_buf(cur, k), tix);
+  block_accumulate<MODE, NT / 64>(cd, st, acc, bad, lat_in_buf(cur, k), tix);
 }
 
 // ---------------------------------------------------- LDS-resident chains ---
@@ -1162,7 +1169,7 @@ template <typename T, int BX, int BY, int ZR>
 static hipError_t launch_mode3t(int mode, const ChainDev* chains, const Tile* tiles, int n_tiles, int j, int k,
                                 hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  dim3 grid(n_tiles), block(256);
+  dim3 grid(n_tiles), block(64 * ZR);
   switch (mode) {
     case PASS_FIRST:
       lattice_pass3t<T, BX, BY, ZR, PASS_FIRST><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j, k);
