@@ -432,10 +432,12 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
 // come from the buffer of launch k - 1 while the pair writes that of launch k,
 // so no block reads momenta another block of the launch writes.
 //
-// One thread per quad of four consecutive x: its tile quad (first-step momenta
-// kept in registers for the second step) and at most one quad of the 2-wide
-// ring (rows -2, -1, BY, BY+1 over the whole staged width, and the outer
-// chunks of the tile rows).
+// Threads work on quads of four consecutive x: TPQ = 1 gives each thread its
+// tile quad (first-step momenta kept in registers for the second step) and at
+// most one quad of the 2-wide ring (rows -2, -1, BY, BY+1 over the whole
+// staged width, and the outer chunks of the tile rows); TPQ = 2 runs twice the
+// threads, the first half on the tile quads and the second on the ring, so a
+// launch of few tiles has more waves to hide latency with.
 
 // w = sqrt(J') tanh(sqrt(J') u) - psi on the quad in chunk c of w-row wr, from
 // psi in row wr + 1 of the staged rows (both arrays of pitch RP); the
@@ -486,18 +488,19 @@ __device__ __forceinline__ void pair_kick_drift(T* __restrict__ sP, const T* __r
   st4<T>(sP + pc, pv);
 }
 
-template <typename T, int BX, int BY>
-__global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v_pair(const ChainDev* __restrict__ chains,
-                                                                   const Tile* __restrict__ tiles, int n_tiles,
-                                                                   int j, int k) {
+template <typename T, int BX, int BY, int TPQ>
+__global__ __launch_bounds__(BX / 4 * BY * TPQ) void lattice_pass2v_pair(const ChainDev* __restrict__ chains,
+                                                                         const Tile* __restrict__ tiles,
+                                                                         int n_tiles, int j, int k) {
   constexpr int QX = BX / 4;
-  constexpr int NT = QX * BY;
+  constexpr int NQ = QX * BY;  // tile quads
+  constexpr int NT = NQ * TPQ;
   constexpr int RP = BX + 8;  // staged x in [-4, BX+4)
   constexpr int NCH = RP / 4;
   constexpr int PR = BY + 8;  // psi rows y in [-4, BY+4)
   constexpr int WR = BY + 6;  // w rows y in [-3, BY+3)
   constexpr int NRING = 4 * NCH + 2 * BY;
-  static_assert(BX % 4 == 0 && NT % 64 == 0 && NRING <= NT, "tile shape");
+  static_assert(BX % 4 == 0 && NQ % 64 == 0 && NRING <= NQ && (TPQ == 1 || TPQ == 2), "tile shape");
   __shared__ __align__(16) T sP[PR * RP];
   __shared__ __align__(16) T sW[WR * RP];
 
@@ -519,19 +522,22 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v_pair(const ChainDe
   auto lat_row = [&](int y) { return rows_near ? wrap_near(y0 + y, L1) : wrap_any(y0 + y, L1); };
 
   const int t = threadIdx.x;
-  const int qx = t % QX, qy = t / QX;
+  const bool has_quad = (TPQ == 1) || t < NQ;
+  const int tq = t % NQ;
+  const int qx = tq % QX, qy = tq / QX;
   const int gx = tl.x0 + 4 * qx, gy = y0 + qy;
-  const bool quad_ok = (gx < L0) && (gy < L1);
+  const bool quad_ok = has_quad && (gx < L0) && (gy < L1);
 
   // ---- the thread's ring quad: row ry of the tile frame, chunk rc of the staged width
-  const bool has_ring = t < NRING;
+  const int rt = (TPQ == 1) ? t : t - NQ;  // ring quad index
+  const bool has_ring = rt >= 0 && rt < NRING;
   int ry = 0, rc = 0;
-  if (t < 4 * NCH) {
-    const int ri = t / NCH;
+  if (has_ring && rt < 4 * NCH) {
+    const int ri = rt / NCH;
     ry = ri < 2 ? ri - 2 : BY + ri - 2;
-    rc = t % NCH;
-  } else {
-    const int r2 = t - 4 * NCH;
+    rc = rt % NCH;
+  } else if (has_ring) {
+    const int r2 = rt - 4 * NCH;
     ry = r2 >> 1;
     rc = (r2 & 1) ? NCH - 1 : 0;
   }
@@ -543,13 +549,16 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v_pair(const ChainDe
   for (int e = 0; e < 4; ++e) {
     bq[e] = b_uniform;
     br[e] = b_uniform;
+    pq[e] = (T)0;
     pr[e] = (T)0;
   }
   {
-    const ChunkPos cq = chunk_pos(gx, L0, x_near);
-    const uint64_t oq = row_offset(lat_row(qy), pitch);
-    load_chunk<T>(pmi + oq, cq, pq);
-    if (site_field) load_chunk<T>(bfield + oq, cq, bq);
+    if (has_quad) {
+      const ChunkPos cq = chunk_pos(gx, L0, x_near);
+      const uint64_t oq = row_offset(lat_row(qy), pitch);
+      load_chunk<T>(pmi + oq, cq, pq);
+      if (site_field) load_chunk<T>(bfield + oq, cq, bq);
+    }
     if (has_ring) {
       const ChunkPos cr = chunk_pos(tl.x0 - 4 + 4 * rc, L0, x_near);
       const uint64_t orr = row_offset(lat_row(ry), pitch);
@@ -595,7 +604,7 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v_pair(const ChainDe
   // kick and drift on the tile (momenta kept) and on the ring; each thread
   // overwrites only the psi of its own quads, which no other thread reads now
   T pa[4], va[4];
-  pair_kick_drift<T, RP>(sP, sW, qy + 3, qx + 1, Ct, kick1, drift1, pq, bq, pa, va);
+  if (has_quad) pair_kick_drift<T, RP>(sP, sW, qy + 3, qx + 1, Ct, kick1, drift1, pq, bq, pa, va);
   if (has_ring) {
     T pn[4], pv[4];
     pair_kick_drift<T, RP>(sP, sW, ry + 3, rc, Ct, kick1, drift1, pr, br, pn, pv);
@@ -605,6 +614,7 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v_pair(const ChainDe
   // ---- step j + 1: w on the rows y in [-1, BY+1), then kick and drift on the tile
   for (int i = t; i < (BY + 2) * NCH; i += NT) pair_w_quad<T, RP>(sP, sW, 2 + i / NCH, i % NCH, Ct, at);
   lds_barrier();
+  if (!has_quad) return;
   T pn[4], pv[4];
   pair_kick_drift<T, RP>(sP, sW, qy + 3, qx + 1, Ct, kick2, drift2, pa, bq, pn, pv);
   if (quad_ok) {
@@ -1135,6 +1145,10 @@ hipError_t launch_lattice_resident(int precision, int ndim, const ChainDev* chai
 
 // ------------------------------------------------------------------ launch ---
 
+// Threads that give every SIMD of the MI355X eight waves: 256 CUs x 4 SIMDs x
+// 8 waves x 64 lanes.
+constexpr int64_t kFillThreads = 256 * 4 * 8 * 64;
+
 template <typename T, int BX, int BY>
 static hipError_t launch_mode2v(int mode, const ChainDev* chains, const Tile* tiles, int n_tiles, int j, int k,
                                 hipStream_t s) {
@@ -1157,7 +1171,13 @@ static hipError_t launch_mode2v(int mode, const ChainDev* chains, const Tile* ti
       lattice_pass2v<T, BX, BY, PASS_FORCE><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j, k);
       break;
     case PASS_PAIR:
-      lattice_pass2v_pair<T, BX, BY><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j, k);
+      // a launch too small to give every SIMD eight waves with one thread per
+      // tile quad takes two threads per quad (the ring on its own threads);
+      // a large one keeps one, which leaves each thread more work in flight
+      if ((int64_t)n_tiles * block.x < kFillThreads)
+        lattice_pass2v_pair<T, BX, BY, 2><<<grid, dim3(2 * block.x), 0, s>>>(chains, tiles, n_tiles, j, k);
+      else
+        lattice_pass2v_pair<T, BX, BY, 1><<<grid, block, 0, s>>>(chains, tiles, n_tiles, j, k);
       break;
     default:
       return hipErrorInvalidValue;

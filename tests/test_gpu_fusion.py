@@ -142,3 +142,16 @@ def test_time_pair(ctxs):
     with pytest.raises(ihmc.IhmcError):
         cube.time_pass(0, mode=ihmc.PAIR, reps=1)  # 3D stays one step per launch
     cube.close()
+
+
+def test_large_launch_one_thread_per_quad(ctxs):
+    """A launch of more tiles than give every SIMD eight waves keeps one thread
+    per tile quad; smaller launches (every case above) take two.  Both must
+    equal one step per launch."""
+    from paper_1912_03278_amd import ihmc
+    lat = ihmc.Lattice((2048, 1040), beta=0.44, C=4.1, h=0.01)  # 2080 tiles of 64 x 16
+    for ctx in ctxs:
+        ctx.pin_tile(lat, 0)
+    run = ihmc.Run(n_md=5, n_traj=3, seed=9, chain_id=3)
+    a, b = run_both(ctxs, [lat], [run], 3)
+    same(a[0], b[0])
