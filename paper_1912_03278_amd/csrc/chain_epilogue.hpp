@@ -105,7 +105,7 @@ __device__ __forceinline__ void finalize_measure(ChainState* st, const u128* sum
 // action terms).  Stores and loads of the table are agent-scope (coherent across
 // the XCDs' L2 caches); a full wait for outstanding memory operations precedes
 // every counter increment, so a closer that sees the final count also sees every
-// entry counted.  Tiles are counted in groups of PGROUP: the block that completes
+// entry counted.  Tiles are counted in groups (part_group): the block that completes
 // a group sums the group's entries (integer sums: exact, in any order), and the
 // block that completes the last group closes the chain.  No two blocks ever add
 // into the same memory, so large chains do not serialise on a few cache lines.
@@ -206,14 +206,15 @@ __device__ __forceinline__ void block_close(const ChainDev& cd, ChainState* st, 
   __shared__ uint32_t sFlag, sLast;
   const int a_lo = kTraj ? T_K0 : T_S;
   const uint32_t wmask = kTraj ? 7u : 4u;
-  const int g = tix / PGROUP;
-  const int ng = (int)((cd.n_tiles + PGROUP - 1) / PGROUP);
-  const int gs = min(PGROUP, (int)cd.n_tiles - g * PGROUP);
+  const int pg = part_group(cd.n_tiles);
+  const int g = tix / pg;
+  const int ng = (int)part_groups(cd.n_tiles);
+  const int gs = min(pg, (int)cd.n_tiles - g * pg);
   if (threadIdx.x == 0) sLast = count_done(&cd.gcnt[g], (uint32_t)gs) ? 1u : 0u;
   __syncthreads();
   if (!sLast) return;
   // this block completed group g
-  gather_entries<NW>(cd.part + (int64_t)g * PGROUP * NPART * 2, gs, a_lo, T_UT, wmask, sSum, &sFlag);
+  gather_entries<NW>(cd.part + (int64_t)g * pg * NPART * 2, gs, a_lo, T_UT, wmask, sSum, &sFlag);
   if (ng > 1) {
     if (threadIdx.x == 0) {
       __hip_atomic_store(&cd.gcnt[g], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -23,7 +23,13 @@ enum Term : int {
   NTERM = 6
 };
 constexpr int NPART = NTERM + 1;  // entries per tile of the partial-sum table (terms + flag words)
-constexpr int PGROUP = 64;        // tiles per group of the two-level close
+// Tiles per group of the two-level close: 64, or 32 for chains of more than
+// 256 tiles (smaller groups complete, and are summed, while the chain's other
+// blocks still run; a chain of at most 64 tiles closes in one level).
+inline __host__ __device__ int part_group(uint32_t n_tiles) { return n_tiles > 256u ? 32 : 64; }
+inline __host__ __device__ uint64_t part_groups(uint32_t n_tiles) {
+  return (n_tiles + (uint64_t)part_group(n_tiles) - 1) / (uint64_t)part_group(n_tiles);
+}
 
 // Record written after every trajectory (64 bytes).
 struct TrajRecord {
@@ -74,13 +80,13 @@ struct ChainDev {
   const uint8_t* replay; // forced decisions (test hook) or null
   ChainState* st;
   uint64_t* part;   // n_tiles x NPART fixed-point entries (block sums of the current trajectory)
-  uint64_t* gsum;   // ceil(n_tiles / PGROUP) x NPART group sums
-  uint32_t* gcnt;   // ceil(n_tiles / PGROUP) tile counters, zero between passes
+  uint64_t* gsum;   // part_groups(n_tiles) x NPART group sums
+  uint32_t* gcnt;   // part_groups(n_tiles) tile counters, zero between passes
 };
 
 // Bytes of a chain's partial-sum table, group sums and group counters.
 inline __host__ __device__ uint64_t partials_bytes(uint32_t n_tiles) {
-  const uint64_t ng = (n_tiles + PGROUP - 1) / PGROUP;
+  const uint64_t ng = part_groups(n_tiles);
   return ((uint64_t)n_tiles * NPART * 16 + 255) / 256 * 256 + (ng * NPART * 16 + 255) / 256 * 256 +
          (ng * 4 + 255) / 256 * 256;
 }

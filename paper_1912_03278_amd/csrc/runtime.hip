@@ -1416,7 +1416,7 @@ hipError_t launch_measure(const std::vector<Group>& groups, const Tile* d_tiles,
 }
 hipError_t setup_partials(ChainDev& c, void* block, hipStream_t s) {
   char* b = (char*)block;
-  const uint64_t ng = (c.n_tiles + PGROUP - 1) / PGROUP;
+  const uint64_t ng = part_groups(c.n_tiles);
   c.part = (uint64_t*)b;
   b += ((uint64_t)c.n_tiles * NPART * 16 + 255) / 256 * 256;
   c.gsum = (uint64_t*)b;
