@@ -45,21 +45,21 @@ KERNEL_SOURCES = ("lattice_kernels.hip", "lattice_kernels.hpp", "chain_epilogue.
                   "ihmc_internal.hpp", "dense_kernels.hip", "dense_kernels.hpp")
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
-    "large_2d_middle": {"sources": "a02fb57884fb3756", "tiles": "64x16", "sites": 1048576,
+    "large_2d_middle": {"sources": "66f8655e97e84fb0", "tiles": "64x16", "sites": 1048576,
                         "fetch_kib": 4207.0, "write_kib": 8192.0},
-    "large_2d_pair": {"sources": "a02fb57884fb3756", "tiles": "64x16", "sites": 1048576,
-                      "fetch_kib": 4353.5, "write_kib": 8192.0},
-    "large_3d_middle": {"sources": "a02fb57884fb3756", "tiles": "32x8x8", "sites": 2097152,
-                        "fetch_kib": 9277.5, "write_kib": 16384.0},
-    "stream_2d_middle": {"sources": "a02fb57884fb3756", "tiles": "64x16", "sites": 67108864,
-                         "fetch_kib": 263727.9, "write_kib": 524288.0},
-    "stream_2d_pair": {"sources": "a02fb57884fb3756", "tiles": "64x16", "sites": 67108864,
-                       "fetch_kib": 265072.1, "write_kib": 524288.0},
-    "batched_middle": {"sources": "a02fb57884fb3756", "tiles": "64x16", "sites": 29479149,
-                       "fetch_kib": 175195.9, "write_kib": 232411.7},
-    "batched_pair": {"sources": "a02fb57884fb3756", "tiles": "64x16", "sites": 29479149,
-                     "fetch_kib": 175327.8, "write_kib": 232811.5},
-    "dense_gemm_bf16": {"sources": "a02fb57884fb3756", "fetch_kib": 73752.0, "write_kib": 16384.0},
+    "large_2d_pair": {"sources": "66f8655e97e84fb0", "tiles": "64x16", "sites": 1048576,
+                      "fetch_kib": 4351.5, "write_kib": 8192.0},
+    "large_3d_middle": {"sources": "66f8655e97e84fb0", "tiles": "32x8x8", "sites": 2097152,
+                        "fetch_kib": 9279.0, "write_kib": 16384.0},
+    "stream_2d_middle": {"sources": "66f8655e97e84fb0", "tiles": "64x16", "sites": 67108864,
+                         "fetch_kib": 263722.5, "write_kib": 524288.0},
+    "stream_2d_pair": {"sources": "66f8655e97e84fb0", "tiles": "64x16", "sites": 67108864,
+                       "fetch_kib": 265019.0, "write_kib": 524288.0},
+    "batched_middle": {"sources": "66f8655e97e84fb0", "tiles": "64x16", "sites": 28951602,
+                       "fetch_kib": 172033.4, "write_kib": 228216.2},
+    "batched_pair": {"sources": "66f8655e97e84fb0", "tiles": "64x16", "sites": 28951602,
+                     "fetch_kib": 172163.2, "write_kib": 228627.3},
+    "dense_gemm_bf16": {"sources": "66f8655e97e84fb0", "fetch_kib": 73752.0, "write_kib": 16384.0},
 }
 
 
