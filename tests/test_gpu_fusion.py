@@ -155,3 +155,4 @@ def test_large_launch_one_thread_per_quad(ctxs):
     run = ihmc.Run(n_md=5, n_traj=3, seed=9, chain_id=3)
     a, b = run_both(ctxs, [lat], [run], 3)
     same(a[0], b[0])
+    assert a[0]["n_traj_done"] == 3 and np.all(np.isfinite(a[0]["dH"]))

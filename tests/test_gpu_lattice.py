@@ -261,3 +261,30 @@ def test_arena_exhaustion_reports_nomem():
         small.run_lattice(glat((256, 256), 0.4, 4.1), ihmc.Run(n_md=4, n_traj=2))
     assert e.value.code == -2
     small.close()
+
+
+# Chains of many tiles close through the two-level partial-sum table: groups of
+# 64 tiles up to 256 tiles, of 32 above (the last group ragged in each case).
+MULTI_GROUP = [
+    ("2d_95_tiles", (300, 300), 0.44, 4.1, None),        # 5 x 19 tiles of 64 x 16: groups of 64
+    ("2d_330_tiles", (1030, 300), 0.44, 4.1, "site"),    # 33 x 10 tiles of 32 x 32: groups of 32
+    ("3d_270_tiles", (130, 48, 40), 0.22, 6.1, 0.05),    # 9 x 3 x 10 boxes of 16 x 16 x 4: groups of 32
+]
+
+
+@pytest.mark.parametrize("case", MULTI_GROUP, ids=[c[0] for c in MULTI_GROUP])
+def test_multi_group_close_matches_oracle(ctx, orc, case):
+    from paper_1912_03278_amd import ihmc
+    L, beta, C, h, psi = _case(case, 3)
+    lat = glat(L, beta, C, h)
+    ch = ihmc.Chains(ctx, [lat], [ihmc.Run(n_md=3, n_traj=1, precision=8)])
+    info = ch.group_info(0)
+    ch.close()
+    assert info["tiles"] == {"2d_95_tiles": 95, "2d_330_tiles": 330, "3d_270_tiles": 270}[case[0]], info
+    run = ihmc.Run(n_md=3, n_traj=1, precision=8, seed=7, chain_id=1, psi0=psi, replay_accept=[1])
+    g = ctx.run_lattice(lat, run)
+    r = orc.run(olat(orc, L, beta, C, h), 1, 3, seed=7, chain_id=1, psi0=psi, replay_accept=[1])
+    assert nrm(g["psi_final"], r.psi_final) < 1e-12
+    for k in ("H_old", "H_new"):
+        assert abs(g[k][0] - getattr(r, k)[0]) <= 1e-12 * abs(getattr(r, k)[0]), k
+    assert abs(g["dH"][0] - r.dH[0]) <= 4e-12 * abs(r.H_old[0]) + 1e-9
