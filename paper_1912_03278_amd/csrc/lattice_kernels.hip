@@ -17,6 +17,8 @@
 //             decision (Sec. 3) and writes the trajectory record;
 //   MEASURE - FP64 action and estimator sums of the accepted field (set-up);
 //   FORCE   - writes F itself (diagnostic; same arithmetic as the other passes).
+// In 2D two MIDDLE steps can also run as one launch (lattice_pass2v_pair, the
+// launch kind PASS_PAIR), with the per-site arithmetic of two passes.
 //
 // Memory layout: rows padded to `pitch` (a multiple of 4 elements), so a thread
 // of the 2D kernel moves its four sites with 16-byte vector accesses.  Sums are
@@ -1215,7 +1217,8 @@ static hipError_t launch_mode3t(int mode, const ChainDev* chains, const Tile* ti
 // 2D tiles: 64 x 16 (256 threads) for rows of 48 sites or more, 32 x 32 (256
 // threads) where that wastes less of the last tile of a row, 16 x 16 (64
 // threads) for small lattices.  3D boxes: 32 x 8 (or 16 x 16 by the same rule)
-// in the plane, 4 planes deep, or 8 where that adds no padding planes.
+// in the plane, 4 planes deep, or 8 where that adds no padding planes (256
+// threads per 4-plane slab).
 #ifndef IHMC_2D_BX
 #define IHMC_2D_BX 64
 #define IHMC_2D_BY 16
