@@ -45,21 +45,21 @@ KERNEL_SOURCES = ("lattice_kernels.hip", "lattice_kernels.hpp", "chain_epilogue.
                   "ihmc_internal.hpp", "dense_kernels.hip", "dense_kernels.hpp")
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
-    "large_2d_middle": {"sources": "66f8655e97e84fb0", "tiles": "64x16", "sites": 1048576,
+    "large_2d_middle": {"sources": "cddb2c4eb8c0d5af", "tiles": "64x16", "sites": 1048576,
                         "fetch_kib": 4207.0, "write_kib": 8192.0},
-    "large_2d_pair": {"sources": "66f8655e97e84fb0", "tiles": "64x16", "sites": 1048576,
+    "large_2d_pair": {"sources": "cddb2c4eb8c0d5af", "tiles": "64x16", "sites": 1048576,
                       "fetch_kib": 4351.5, "write_kib": 8192.0},
-    "large_3d_middle": {"sources": "66f8655e97e84fb0", "tiles": "32x8x8", "sites": 2097152,
+    "large_3d_middle": {"sources": "cddb2c4eb8c0d5af", "tiles": "32x8x8", "sites": 2097152,
                         "fetch_kib": 9279.0, "write_kib": 16384.0},
-    "stream_2d_middle": {"sources": "66f8655e97e84fb0", "tiles": "64x16", "sites": 67108864,
-                         "fetch_kib": 263722.5, "write_kib": 524288.0},
-    "stream_2d_pair": {"sources": "66f8655e97e84fb0", "tiles": "64x16", "sites": 67108864,
-                       "fetch_kib": 265019.0, "write_kib": 524288.0},
-    "batched_middle": {"sources": "66f8655e97e84fb0", "tiles": "64x16", "sites": 28951602,
-                       "fetch_kib": 172033.4, "write_kib": 228216.2},
-    "batched_pair": {"sources": "66f8655e97e84fb0", "tiles": "64x16", "sites": 28951602,
-                     "fetch_kib": 172163.2, "write_kib": 228627.3},
-    "dense_gemm_bf16": {"sources": "66f8655e97e84fb0", "fetch_kib": 73752.0, "write_kib": 16384.0},
+    "stream_2d_middle": {"sources": "cddb2c4eb8c0d5af", "tiles": "64x16", "sites": 67108864,
+                         "fetch_kib": 263719.8, "write_kib": 524288.0},
+    "stream_2d_pair": {"sources": "cddb2c4eb8c0d5af", "tiles": "64x16", "sites": 67108864,
+                       "fetch_kib": 265040.3, "write_kib": 524288.0},
+    "batched_middle": {"sources": "cddb2c4eb8c0d5af", "tiles": "64x16", "sites": 29379987,
+                       "fetch_kib": 174561.7, "write_kib": 231563.0},
+    "batched_pair": {"sources": "cddb2c4eb8c0d5af", "tiles": "64x16", "sites": 29379987,
+                     "fetch_kib": 174705.1, "write_kib": 231957.4},
+    "dense_gemm_bf16": {"sources": "cddb2c4eb8c0d5af", "fetch_kib": 73752.0, "write_kib": 16384.0},
 }
 
 
