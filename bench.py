@@ -723,7 +723,7 @@ def main():
     if not args.no_streaming_point:
         line["extra_streaming_point"] = streaming_point(args, copy_gbs)
     if not args.no_cpu_baseline:
-        print("bench: timing the CPU oracle on a one-trajectory sample", file=sys.stderr, flush=True)
+        print("bench: timing the CPU oracle on whole trajectories of both chains (about 10 s)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(ws)
     else:
         line["cpu_baseline"] = None
