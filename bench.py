@@ -1,21 +1,25 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the fused lattice HMC path on one MI355X.
 
-Workload (default, "large"): two single large chains, FP32 state with FP64
-Hamiltonian reductions, J = 1, h = 0, 20 leap-frog steps per unit trajectory:
-  * 2D 1024 x 1024 torus at beta_c = ln(1 + sqrt 2)/2, C = 4.1;
-  * 3D 128^3 torus at beta = 0.2216544, C = 6.1.
-Seeded Gaussian initial fields (Philox).  One step = one HMC trajectory of both
-chains (21 fused passes each, Metropolis on the device; the 2D chain's middle
-steps run two per launch unless --fuse off); the metric is site-MD-steps/s =
-(sites x MD steps) per second over the timed steps.
+Default workload (the headline): 4096 independent 2D tori of uneven size, beta,
+per-site field and step count (L log-uniform in [16, 256], beta ~ U[0.30, 0.55],
+h_x ~ N(0, 0.05^2), n_md ~ U{8..32}, C = 4.1, 200 trajectories each), FP32 state
+with FP64 Hamiltonian reductions, advanced together.  One step = one trajectory
+of every chain; the metric is site-MD-steps/s = (sites x MD steps) per second
+over the timed steps.  Beside it the line carries
 
-Besides the throughput line it reports the roofline of the dominant kernel (the
-fused middle pass, one or two steps per launch: 16 bytes of state per site and
-launch, HIP-event timed on the library's stream) and the FP64 CPU oracle timed
-on a bounded sample of the same workload.
+  * the roofline of the dominant launch kind (HIP-event timed on the library's
+    stream): the algorithmic fraction (20 + 8/n_md bytes per site-MD-step times
+    the site-MD-steps one launch advances) and the physical one (20 bytes per
+    site and launch);
+  * the plain form: a sample of the same chains run one at a time, its rate and
+    whether every result is bitwise equal to the batched run;
+  * the FP64 CPU oracle on a 64-chain sample of the workload (5 trajectories
+    each), run over the host cores in parallel processes, median of 5 runs;
+  * extra keys: the single large chains (2D 1024^2 at beta_c and 3D 128^3), an
+    8192^2 streaming point, and 60 s of Poisson serving with p50/p99 latency.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ...]
 """
 from __future__ import annotations
 
@@ -125,26 +129,65 @@ def group_rows(chains, reps, modes=(1,), pair=False):
     return rows
 
 
-def cpu_baseline(chains, min_seconds=10.0, max_traj=8):
-    """The FP64 oracle, single-threaded: one trajectory of each chain, repeated
-    as whole chains of k trajectories until about min_seconds of CPU work
-    (k <= max_traj)."""
+def host_cpu():
+    """(cores this process may run on, capped at the box's share of 16; CPU model)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return max(1, min(16, n)), model
+
+
+def _oracle_warm(_):
     import oracle
-    t_total, work, k = 0.0, 0, 1
-    while True:
-        for w in chains:
-            lat = oracle.Lattice(w["L"], beta=w["beta"], C=w["C"])
+    oracle.lib()
+    return os.getpid()
+
+
+def _oracle_job(job):
+    """One oracle chain of `job` (a dict of its parameters); returns its CPU seconds."""
+    import oracle
+    lat = oracle.Lattice(tuple(job["L"]), beta=job["beta"], C=job["C"], h=job["h"])
+    t0 = time.perf_counter()
+    oracle.run(lat, job["n_traj"], job["n_md"], seed=job["seed"], chain_id=job["chain_id"])
+    return time.perf_counter() - t0
+
+
+def oracle_parallel(jobs, reps=5, what=""):
+    """The FP64 oracle, unchanged, on `jobs` (independent chains) over the host
+    cores: one process per core, chains dealt largest first; one warm-up pass
+    loads the oracle in every process, then `reps` timed passes over all jobs,
+    the median wall time kept.  Returns the cpu_baseline record."""
+    import multiprocessing as mp
+    import statistics
+
+    import oracle
+    oracle.lib()  # built once here, before the workers load it
+    cores, model = host_cpu()
+    work = sum(int(math.prod(j["L"])) * j["n_md"] * j["n_traj"] for j in jobs)
+    order = sorted(jobs, key=lambda j: -int(math.prod(j["L"])) * j["n_md"] * j["n_traj"])
+    walls, cpu_s = [], 0.0
+    with mp.get_context("spawn").Pool(cores) as pool:
+        pool.map(_oracle_warm, range(cores))
+        for _ in range(reps):
             t0 = time.perf_counter()
-            oracle.run(lat, k, w["n_md"], seed=w["seed"], chain_id=w["chain_id"])
-            t_total += time.perf_counter() - t0
-            work += k * int(math.prod(w["L"])) * w["n_md"]
-        if t_total >= min_seconds or k >= max_traj:
-            break
-        k = min(max_traj, max(1, math.ceil((min_seconds - t_total) * k / t_total)))
-    n = work // sum(int(math.prod(w["L"])) * w["n_md"] for w in chains)
-    return dict(value=work / t_total, unit="site-MD-steps/s", cores=1, kind="oracle",
-                sample=f"{n} trajectories (20 MD steps each) of the 1024^2 and of the 128^3 chain, FP64, "
-                       f"{t_total:.1f} s on one host core")
+            cpu_s = sum(pool.map(_oracle_job, order, chunksize=1))
+            walls.append(time.perf_counter() - t0)
+    wall = statistics.median(walls)
+    return dict(value=work / wall, unit="site-MD-steps/s", cores=cores, kind="oracle",
+                sample=f"{what}: {len(jobs)} chains, {work:.3g} site-MD-steps, FP64, each chain's set-up (field "
+                       f"constants by CG) included, in {cores} processes; "
+                       f"median wall time of {reps} runs {wall:.2f} s ({cpu_s:.1f} CPU-s per run)",
+                cpu_model=model, runs_wall_s=[round(w, 3) for w in walls])
 
 
 def streaming_point(args, copy_gbs):
@@ -233,10 +276,13 @@ def bench_small(args):
     print(json.dumps(line), flush=True)
 
 
-def bench_batched(args):
+METRIC = "site-MD-steps/s & %HBM roofline, batched vs plain; p50/p99 request latency"
+
+
+def run_batched(args):
     """4096 independent 2D tori of uneven size, beta, per-site field and step count,
     advanced together (one step = one trajectory of every chain), against the same
-    chains run one at a time (the plain form) on a sample."""
+    chains run one at a time (the plain form) on a sample.  Returns the JSON line."""
     import numpy as np
     import torch
     from paper_1912_03278_amd import ihmc, inputs
@@ -255,6 +301,7 @@ def bench_batched(args):
     chains.advance(W)
     ctx.sync()
     torch.cuda.synchronize()
+    print(f"bench: warmup {W} rounds done", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     chains.advance(K)
     ctx.sync()
@@ -278,58 +325,89 @@ def bench_batched(args):
         ctx.sync()
         plain_time += time.perf_counter() - t0
         plain_work += K * int(math.prod(ws[i]["L"])) * ws[i]["n_md"]
-        a = alone.result(0, want_psi=False)
-        b = chains.result(i, want_psi=False)
-        same = bool(np.array_equal(a["dH"], b["dH"]) and np.array_equal(a["beta_eps"], b["beta_eps"]))
+        a = alone.result(0)
+        b = chains.result(i)
+        same = all(np.array_equal(a[k], b[k]) for k in ("dH", "H_old", "H_new", "m", "beta_eps", "accepted",
+                                                         "psi_final"))
         if not same:
             mismatch.append(i)
         identical &= same
         alone.close()
+    if sample:
+        print(f"bench: plain form on {len(sample)} chains, bitwise equal: {identical}", file=sys.stderr, flush=True)
     acc = [chains.result(i, want_psi=False)["acceptance"] for i in range(0, len(ws), max(1, len(ws) // 64))]
 
-    # one launch group per tile class in use (all chains are FP32 2D)
-    # (a pair launch moves the same 20 B per site as a one-step pass: psi, p and
-    # the field read once, p and psi written once)
+    # launch groups (all chains FP32 2D): HIP-event times of the one-step and
+    # two-step launches; a launch moves 20 B per site (psi, p and the field
+    # read, p and psi written) for one or two MD steps
     kern = group_rows(chains, args.timing_reps, pair=args.fuse_steps)
     for k in kern:
         for name in ("middle", "pair"):
             if f"{name}_us" in k:
-                k[f"{name}_GBs"] = round(20 * k["sites"] / (k[f"{name}_us"] * 1e-6) / 1e9, 1)
+                k[f"{name}_physical_GBs"] = round(20 * k["sites"] / (k[f"{name}_us"] * 1e-6) / 1e9, 1)
                 k[f"{name}_us"] = round(k[f"{name}_us"], 2)
     key = "pair_us" if args.fuse_steps else "middle_us"
-    dom = max((k for k in kern if key in k), key=lambda k: k["sites"])
-    achieved = 20 * dom["sites"] / (dom[key] * 1e-6) / 1e9
+    gi, dom = max(((g, k) for g, k in enumerate(kern) if key in k), key=lambda t: t[1]["sites"])
+    steps_per_launch = 2 if args.fuse_steps else 1
+    # algorithmic bytes of one launch: (20 + 8/n_md) B per site-MD-step, per
+    # chain of the group, times the site-MD-steps the launch advances
+    dom_chains = [ws[i] for i in chains.group_chains(gi)]
+    alg_bytes = steps_per_launch * sum(int(math.prod(w["L"])) * (20.0 + 8.0 / w["n_md"]) for w in dom_chains)
+    phys_bytes = 20 * dom["sites"]
+    achieved = alg_bytes / (dom[key] * 1e-6) / 1e9
+    achieved_phys = phys_bytes / (dom[key] * 1e-6) / 1e9
     copy_bytes = 512 << 20
     copy_gbs = 2 * copy_bytes / (ctx.copy_bandwidth(copy_bytes, reps=10) * 1e-6) / 1e9
+    cls_traffic = traffic_bytes("batched_pair" if args.fuse_steps else "batched_middle", sites=dom["sites"],
+                                tiles=dom["tiles"])
     line = {
-        "metric": "site-MD-steps/s", "value": value, "unit": "site-MD-steps/s", "n_gpus": 1, "steps": K,
+        "metric": METRIC, "value": value, "unit": "site-MD-steps/s", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": 1000.0 * dt / K, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"batched: {len(ws)} 2D tori, L log-uniform [16,256], beta U[0.30,0.55], "
-                               "h_x ~ N(0,0.05^2) per site, n_md U{8..32}, C=4.1, FP32 state, FP64 H; "
+        "config": {"workload": f"batched: {len(ws)} independent 2D tori, L log-uniform [16,256], beta U[0.30,0.55], "
+                               "h_x ~ N(0,0.05^2) per site, n_md U{8..32}, C=4.1, FP32 state, FP64 H/dH/Metropolis; "
                                "one step = one trajectory of every chain",
-                   "chains": len(ws), "sites": sum(int(math.prod(w["L"])) for w in ws), **tiles,
-                   "resident": args.resident, "fuse_steps": args.fuse},
+                   "chains": len(ws), "sites": sum(int(math.prod(w["L"])) for w in ws),
+                   "execution_form": "one HIP graph per round (per-pass launches of every tile-class group on "
+                                     "streams of their own; chains of at most 5024 sites as LDS-resident whole-"
+                                     "trajectory launches beside them), replayed per round; not a single persistent "
+                                     "kernel with a device work queue",
+                   **tiles, "resident": args.resident, "fuse_steps": args.fuse},
         "roofline": {"bound": "hbm", "kernel": ("two-step " if args.fuse_steps else "") +
                                                f"fused middle pass, 2D, per-site field, {dom['tiles']}-tile group "
-                                               f"({dom['chains']} chains)",
+                                               f"({dom['chains']} chains, {dom['sites']} sites)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_bytes("batched_pair" if args.fuse_steps else "batched_middle",
-                                              sites=dom["sites"], tiles=dom["tiles"]),
-                     "bytes_per_launch": 20 * dom["sites"], "avg_launch_us": dom[key],
-                     "copy_kernel_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": cls_traffic,
+                     "algorithmic_bytes_per_launch": int(alg_bytes),
+                     "algorithmic_basis": f"(20 + 8/n_md) B per site-MD-step x {steps_per_launch} MD step(s) per "
+                                          "site and launch, summed over the group's chains",
+                     "physical_bytes_per_launch": phys_bytes, "achieved_physical": round(achieved_phys, 1),
+                     "frac_physical": round(achieved_phys / HBM_PEAK_GBS, 4),
+                     "avg_launch_us": dom[key], "timing": "HIP events on the library stream, launches back to back",
+                     "copy_kernel_GBs": round(copy_gbs, 1), "frac_physical_of_copy": round(achieved_phys / copy_gbs, 4)},
         "kernels": kern,
         "plain": {"chains": len(sample), "value": (plain_work / plain_time) if plain_time > 0 else None,
-                  "unit": "site-MD-steps/s", "bitwise_equal_to_batched": identical if sample else None,
-                  "mismatched_chains": mismatch},
+                  "unit": "site-MD-steps/s", "batched_over_plain": (value / (plain_work / plain_time))
+                  if plain_time > 0 else None,
+                  "bitwise_equal_to_batched": identical if sample else None, "mismatched_chains": mismatch},
         "acceptance_sample_mean": float(np.mean(acc)),
         "setup_s": round(t_setup, 2),
-        "cpu_baseline": None,
     }
     chains.close()
     ctx.close()
-    print(json.dumps(line), flush=True)
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle on a 64-chain sample", file=sys.stderr, flush=True)
+        pick = sorted(np.random.default_rng(1).choice(len(ws), size=min(64, len(ws)), replace=False).tolist())
+        jobs = [dict(L=ws[i]["L"], beta=ws[i]["beta"], C=ws[i]["C"], h=ws[i]["h"], n_md=ws[i]["n_md"], n_traj=5,
+                     seed=ws[i]["seed"], chain_id=ws[i]["chain_id"]) for i in pick]
+        line["cpu_baseline"] = oracle_parallel(jobs, what="batched workload, 64 sampled chains x 5 trajectories")
+    else:
+        line["cpu_baseline"] = None
+    return line
+
+
+def bench_batched(args):
+    print(json.dumps(run_batched(args)), flush=True)
 
 
 def bench_dense(args):
@@ -414,10 +492,12 @@ def bench_dense(args):
     print(json.dumps(line), flush=True)
 
 
-def bench_serving(args):
+def run_serving(args):
     """Open-loop Poisson arrivals of lattice requests (2D or 3D, uneven size,
-    beta, field and length) into the continuous-batching server; reports the
-    completed site-MD-steps/s and the p50/p99 request latency."""
+    beta, field and length) into the continuous-batching server; returns the
+    completed site-MD-steps/s and the request latency percentiles.  A request
+    still unfinished at the deadline counts in the percentiles with an unbounded
+    latency (a percentile that falls on one is reported as null)."""
     import threading
 
     import numpy as np
@@ -461,7 +541,7 @@ def bench_serving(args):
                 lat_s.append(r["t_done"] - r["t_submit"])
         if time.perf_counter() > next_report:
             st = sv.stats()
-            print(f"bench: t={time.perf_counter() - t_start:.0f}s done {len(done)}/{len(reqs)} "
+            print(f"bench: serving t={time.perf_counter() - t_start:.0f}s done {len(done)}/{len(reqs)} "
                   f"resident {st['resident']:.0f} queued {st['queued']:.0f}", file=sys.stderr, flush=True)
             next_report += 10
         time.sleep(0.002)
@@ -473,26 +553,50 @@ def bench_serving(args):
     ctx.close()
     completed_work = sum(work[k] for k in done)
     elapsed = t_end - t_start
-    lat = np.array(lat_s) if lat_s else np.array([float("nan")])
-    line = {
-        "metric": "site-MD-steps/s", "value": completed_work / elapsed, "unit": "site-MD-steps/s", "n_gpus": 1,
-        "steps": len(done), "warmup": 0, "ms_per_step": 1000.0 * elapsed / max(1, len(done)),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"serving: Poisson arrivals {args.rate:g}/s for {args.serve_duration:g} s; 2D or 3D "
-                               "(p = 1/2), L U{16..128} (2D) / U{16..64} (3D), beta U[0.2,0.6], uniform h "
-                               "U[0,0.1], C = 2d + 0.1, 50-1000 trajectories of 10-30 leap-frog steps, FP32 state, "
-                               "FP64 H; one step = one completed request",
-                   "requests": len(reqs), "offered_site_md_steps_per_s": sum(work) / args.serve_duration,
-                   "resident": args.resident, "fuse_steps": args.fuse,
-                   **tiles},
-        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                      "mean": float(lat.mean()), "max": float(lat.max())},
-        "completed": len(done), "incomplete": len(incomplete), "elapsed_s": elapsed,
+    # every request counts: unfinished ones with an unbounded latency
+    lat = np.array(lat_s + [math.inf] * len(incomplete)) if reqs else np.array([math.nan])
+
+    def pct(q):
+        v = float(np.percentile(lat, q, method="higher"))
+        return v if math.isfinite(v) else None
+
+    out = {
+        "workload": f"serving: Poisson arrivals {args.rate:g}/s for {args.serve_duration:g} s; 2D or 3D (p = 1/2), "
+                    "L U{16..128} (2D) / U{16..64} (3D), beta U[0.2,0.6], uniform h U[0,0.1], C = 2d + 0.1, "
+                    "50-1000 trajectories of 10-30 leap-frog steps, FP32 state, FP64 H",
+        "value": completed_work / elapsed, "unit": "site-MD-steps/s",
+        "latency_s": {"p50": pct(50), "p99": pct(99), "mean_completed": float(np.mean(lat_s)) if lat_s else None,
+                      "max_completed": float(np.max(lat_s)) if lat_s else None},
+        "requests": len(reqs), "completed": len(done), "incomplete": len(incomplete), "elapsed_s": elapsed,
+        "offered_site_md_steps_per_s": sum(work) / args.serve_duration,
         "server": {"rounds": st["rounds"], "busy_s": st["busy_s"], "max_resident": st["max_resident"],
                    "site_md_steps_in_rounds": st["site_md_steps"],
                    "rate_while_busy": st["site_md_steps"] / st["busy_s"] if st["busy_s"] > 0 else None},
-        "roofline": None, "cpu_baseline": None,
+        "resident": args.resident, "fuse_steps": args.fuse, **tiles,
     }
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle on a sample of the served requests", file=sys.stderr, flush=True)
+        rng = np.random.default_rng(2)
+        pick = sorted(rng.choice(len(reqs), size=min(64, len(reqs)), replace=False).tolist())
+        jobs = [dict(L=reqs[i]["L"], beta=reqs[i]["beta"], C=reqs[i]["C"], h=reqs[i]["h"], n_md=reqs[i]["n_md"],
+                     n_traj=3, seed=reqs[i]["seed"], chain_id=reqs[i]["chain_id"]) for i in pick]
+        cb = oracle_parallel(jobs, reps=3, what="served requests, 64 sampled requests x 3 trajectories")
+        # CPU time a whole request would take on one core, from the sample's rate
+        mean_req = float(np.mean([work[i] for i in pick]))
+        cb["one_core_s_per_request_mean"] = round(mean_req / (cb["value"] / cb["cores"]), 2)
+        out["cpu_baseline"] = cb
+    else:
+        out["cpu_baseline"] = None
+    return out
+
+
+def bench_serving(args):
+    s = run_serving(args)
+    line = {"metric": METRIC, "value": s["value"], "unit": "site-MD-steps/s", "n_gpus": 1,
+            "steps": s["completed"], "warmup": 0, "ms_per_step": 1000.0 * s["elapsed_s"] / max(1, s["completed"]),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": s["workload"] + "; one step = one completed request"},
+            "latency_s": s["latency_s"], "serving": s, "roofline": None, "cpu_baseline": s["cpu_baseline"]}
     print(json.dumps(line), flush=True)
 
 
@@ -557,66 +661,16 @@ def bench_tau(args):
     print(json.dumps(line), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="large",
-                    choices=["large", "batched", "dense", "serving", "small", "tau"],
-                    help="large (default): the 1024^2 + 128^3 single chains; batched: 4096 uneven chains; "
-                         "dense: 256 chains of an N=4096 all-to-all model; serving: Poisson request arrivals")
-    ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
-    ap.add_argument("--serve-duration", type=float, default=60.0, help="serving: seconds of arrivals")
-    ap.add_argument("--drain", type=float, default=120.0, help="serving: seconds allowed after the last arrival")
-    ap.add_argument("--products", type=int, default=6, choices=[3, 6], help="dense: BF16 limb products")
-    ap.add_argument("--chains", type=int, default=4096, help="batched: number of chains")
-    ap.add_argument("--plain-sample", type=int, default=16, help="batched: chains rerun alone")
-    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
-    ap.add_argument("--no-streaming-point", action="store_true", help="large: skip the extra 8192^2 point")
-    ap.add_argument("--timing-reps", type=int, default=100)
-    ap.add_argument("--tau-chains", type=int, default=128, help="tau: replicas per scan point")
-    ap.add_argument("--resident", default="on", choices=["on", "off"],
-                    help="chains that fit one workgroup's LDS run whole trajectories per launch (on) or the "
-                         "tiled passes (off); results are bit-identical")
-    ap.add_argument("--fuse", default="on", choices=["on", "off"],
-                    help="2D chains on the tiled passes run two middle leap-frog steps per launch (on) or one "
-                         "(off); results are bit-identical")
-    ap.add_argument("--tiles", default="tuned", choices=["tuned", "rule"],
-                    help="tile classes: autotuned per lattice shape before the run (default), or the built-in rule")
-    args = ap.parse_args()
-    args.resident_sites = -1 if args.resident == "on" else 0
-    args.fuse_steps = args.fuse == "on"
-    if args.gpus != 1:
-        print("bench.py: runs on one GPU only; sharding chains or a lattice over several GPUs is a design, "
-              "not implemented here", file=sys.stderr)
-        sys.exit(2)
-    if args.workload == "batched":
-        args.steps = 10 if args.steps is None else args.steps
-        args.warmup = 2 if args.warmup is None else args.warmup
-        return bench_batched(args)
-    if args.workload == "serving":
-        return bench_serving(args)
-    if args.workload == "tau":
-        args.steps = 8000 if args.steps is None else args.steps
-        args.warmup = 1000 if args.warmup is None else args.warmup
-        return bench_tau(args)
-    if args.workload == "small":
-        args.steps = 2000 if args.steps is None else args.steps
-        args.warmup = 200 if args.warmup is None else args.warmup
-        return bench_small(args)
-    if args.workload == "dense":
-        args.steps = 100 if args.steps is None else args.steps
-        args.warmup = 5 if args.warmup is None else args.warmup
-        return bench_dense(args)
-    args.steps = 200 if args.steps is None else args.steps
-    args.warmup = 20 if args.warmup is None else args.warmup
-
+def run_large(args, K=None, W=None):
+    """Single large chains: 2D 1024^2 at beta_c and 3D 128^3 at beta = 0.2216544,
+    FP32 state, FP64 H, h = 0, 20 MD steps; one step = one trajectory of both.
+    Returns the JSON line (extra keys included)."""
     import torch
     from paper_1912_03278_amd import ihmc
 
     ws = large_workload()
-    K, W = args.steps, args.warmup
+    K = args.steps if K is None else K
+    W = args.warmup if W is None else W
     ctx = ihmc.Context(device=0, arena_bytes=2 << 30, resident=args.resident_sites, fuse_steps=args.fuse_steps)
     lats = [ihmc.Lattice(w["L"], beta=w["beta"], C=w["C"]) for w in ws]
     runs = [ihmc.Run(n_md=w["n_md"], n_traj=W + K, precision=ihmc.F32, seed=w["seed"], chain_id=w["chain_id"])
@@ -658,62 +712,56 @@ def main():
         if "pair_us" in k:
             k["kind"], k["kind_us"] = "two-step middle pass", k["pair_us"]
             k["middle_share_us"] = (n_mid // 2) * k["pair_us"] + (n_mid % 2) * k["middle_us"]
+            k["steps_per_launch"] = 2
         else:
             k["kind"], k["kind_us"] = "middle pass", k["middle_us"]
             k["middle_share_us"] = n_mid * k["middle_us"]
+            k["steps_per_launch"] = 1
     dom = max(kern, key=lambda k: k["middle_share_us"])
-    bytes_per_launch = BYTES_MIDDLE_F32 * dom["sites"]
-    achieved = bytes_per_launch / (dom["kind_us"] * 1e-6) / 1e9
-    dom_kind, dom_us = dom["kind"], dom["kind_us"]
+    n_md = ws[0]["n_md"]
+    phys_bytes = BYTES_MIDDLE_F32 * dom["sites"]
+    alg_bytes = dom["steps_per_launch"] * dom["sites"] * (16.0 + 4.0 / n_md)
+    achieved = alg_bytes / (dom["kind_us"] * 1e-6) / 1e9
+    achieved_phys = phys_bytes / (dom["kind_us"] * 1e-6) / 1e9
+    dom_kind, dom_us, dom_steps = dom["kind"], dom["kind_us"], dom["steps_per_launch"]
     for k in kern:
         for name in ("middle", "pair"):
             if f"{name}_us" in k:
-                k[f"{name}_GBs"] = round(BYTES_MIDDLE_F32 * k["sites"] / (k[f"{name}_us"] * 1e-6) / 1e9, 1)
+                k[f"{name}_physical_GBs"] = round(BYTES_MIDDLE_F32 * k["sites"] / (k[f"{name}_us"] * 1e-6) / 1e9, 1)
                 k[f"{name}_us"] = round(k[f"{name}_us"], 3)
         k["first_us"] = round(k["first_us"], 3)
         k["last_us"] = round(k["last_us"], 3)
-        for name in ("middle_share_us", "kind", "kind_us"):
+        for name in ("middle_share_us", "kind", "kind_us", "steps_per_launch"):
             del k[name]
 
     copy_bytes = 512 << 20
     copy_us = ctx.copy_bandwidth(copy_bytes, reps=10)
     copy_gbs = 2 * copy_bytes / (copy_us * 1e-6) / 1e9
     line = {
-        "metric": "site-MD-steps/s",
-        "value": value,
-        "unit": "site-MD-steps/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": W,
-        "ms_per_step": 1000.0 * dt / K,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
+        "metric": "site-MD-steps/s", "value": value, "unit": "site-MD-steps/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": 1000.0 * dt / K, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {
             "workload": "single large chains: 2D 1024^2 at beta_c=0.4406868 (C=4.1) and 3D 128^3 at "
                         "beta=0.2216544 (C=6.1), J=1, h=0, 20 leap-frog steps per unit trajectory, FP32 "
                         "state, FP64 H/dH/Metropolis; one step = one trajectory of both chains",
             "sites": sum(int(math.prod(w["L"])) for w in ws),
-            "md_steps_per_trajectory": ws[0]["n_md"],
-            "fuse_steps": args.fuse,
-            **tiles,
+            "md_steps_per_trajectory": n_md, "fuse_steps": args.fuse, **tiles,
         },
         "roofline": {
-            "bound": "hbm",
-            "kernel": f"fused {dom_kind}, {dom['ndim']}D",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
+            "bound": "hbm", "kernel": f"fused {dom_kind}, {dom['ndim']}D",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic_bytes("large_3d_middle" if dom["ndim"] == 3 else
                                      ("large_2d_pair" if dom_kind.startswith("two") else "large_2d_middle"),
                                      sites=dom["sites"], tiles=dom["tiles"]),
-            "bytes_per_launch": bytes_per_launch,
+            "algorithmic_bytes_per_launch": int(alg_bytes),
+            "algorithmic_basis": f"(16 + 4/n_md) B per site-MD-step x {dom_steps} MD step(s) "
+                                 "per site and launch",
+            "physical_bytes_per_launch": phys_bytes, "achieved_physical": round(achieved_phys, 1),
+            "frac_physical": round(achieved_phys / HBM_PEAK_GBS, 4),
             "avg_launch_us": round(dom_us, 3),
-            "copy_kernel_GBs": round(copy_gbs, 1),
-            "frac_of_copy": round(achieved / copy_gbs, 4),
+            "copy_kernel_GBs": round(copy_gbs, 1), "frac_physical_of_copy": round(achieved_phys / copy_gbs, 4),
         },
         "kernels": kern,
         "chains": per,
@@ -723,11 +771,97 @@ def main():
     if not args.no_streaming_point:
         line["extra_streaming_point"] = streaming_point(args, copy_gbs)
     if not args.no_cpu_baseline:
-        print("bench: timing the CPU oracle on whole trajectories of both chains (about 10 s)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(ws)
+        print("bench: timing the CPU oracle on one trajectory of each large chain", file=sys.stderr, flush=True)
+        jobs = [dict(L=w["L"], beta=w["beta"], C=w["C"], h=None, n_md=w["n_md"], n_traj=1, seed=w["seed"],
+                     chain_id=w["chain_id"]) for w in ws]
+        line["cpu_baseline"] = oracle_parallel(jobs, reps=3, what="one trajectory of the 1024^2 and of the "
+                                                                    "128^3 chain")
     else:
         line["cpu_baseline"] = None
+    return line
+
+
+def bench_large(args):
+    print(json.dumps(run_large(args)), flush=True)
+
+
+def bench_headline(args):
+    """The batched workload's line, with the single large chains, the streaming
+    point and the serving run as extra keys."""
+    line = run_batched(args)
+    if args.extras in ("all", "large"):
+        print("bench: extra key: single large chains", file=sys.stderr, flush=True)
+        lg = run_large(args, K=max(args.steps, 20), W=max(args.warmup, 5))
+        line["extra_large_chains"] = {k: lg[k] for k in ("value", "unit", "ms_per_step", "steps", "warmup", "config",
+                                                         "roofline", "kernels", "chains", "cpu_baseline")}
+        if "extra_streaming_point" in lg:
+            line["extra_streaming_point"] = lg["extra_streaming_point"]
+    if args.extras in ("all", "serving"):
+        print("bench: extra key: serving", file=sys.stderr, flush=True)
+        sv = run_serving(args)
+        line["extra_serving"] = sv
+        line["latency_s"] = sv["latency_s"]
     print(json.dumps(line), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "batched", "large", "dense", "serving", "small", "tau"],
+                    help="headline (default): the batched workload with the large chains, the streaming point and "
+                         "serving as extra keys; batched: 4096 uneven chains only; large: the 1024^2 + 128^3 single "
+                         "chains; dense: 256 chains of an N=4096 all-to-all model; serving: Poisson request arrivals")
+    ap.add_argument("--extras", default="all", choices=["all", "large", "serving", "none"],
+                    help="headline: which extra keys to run")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
+    ap.add_argument("--serve-duration", type=float, default=60.0, help="serving: seconds of arrivals")
+    ap.add_argument("--drain", type=float, default=120.0, help="serving: seconds allowed after the last arrival")
+    ap.add_argument("--products", type=int, default=6, choices=[3, 6], help="dense: BF16 limb products")
+    ap.add_argument("--chains", type=int, default=4096, help="batched: number of chains")
+    ap.add_argument("--plain-sample", type=int, default=16, help="batched: chains rerun alone")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--no-streaming-point", action="store_true", help="large: skip the extra 8192^2 point")
+    ap.add_argument("--timing-reps", type=int, default=100)
+    ap.add_argument("--tau-chains", type=int, default=128, help="tau: replicas per scan point")
+    ap.add_argument("--resident", default="on", choices=["on", "off"],
+                    help="chains that fit one workgroup's LDS run whole trajectories per launch (on) or the "
+                         "tiled passes (off); results are bit-identical")
+    ap.add_argument("--fuse", default="on", choices=["on", "off"],
+                    help="2D chains on the tiled passes run two middle leap-frog steps per launch (on) or one "
+                         "(off); results are bit-identical")
+    ap.add_argument("--tiles", default="tuned", choices=["tuned", "rule"],
+                    help="tile classes: autotuned per lattice shape before the run (default), or the built-in rule")
+    args = ap.parse_args()
+    args.resident_sites = -1 if args.resident == "on" else 0
+    args.fuse_steps = args.fuse == "on"
+    if args.gpus != 1:
+        print("bench.py: runs on one GPU only; sharding chains or a lattice over several GPUs is a design, "
+              "not implemented here", file=sys.stderr)
+        sys.exit(2)
+    if args.workload in ("headline", "batched"):
+        args.steps = 10 if args.steps is None else args.steps
+        args.warmup = 2 if args.warmup is None else args.warmup
+        return bench_headline(args) if args.workload == "headline" else bench_batched(args)
+    if args.workload == "serving":
+        return bench_serving(args)
+    if args.workload == "tau":
+        args.steps = 8000 if args.steps is None else args.steps
+        args.warmup = 1000 if args.warmup is None else args.warmup
+        return bench_tau(args)
+    if args.workload == "small":
+        args.steps = 2000 if args.steps is None else args.steps
+        args.warmup = 200 if args.warmup is None else args.warmup
+        return bench_small(args)
+    if args.workload == "dense":
+        args.steps = 100 if args.steps is None else args.steps
+        args.warmup = 5 if args.warmup is None else args.warmup
+        return bench_dense(args)
+    args.steps = 200 if args.steps is None else args.steps
+    args.warmup = 20 if args.warmup is None else args.warmup
+    return bench_large(args)
 
 
 if __name__ == "__main__":

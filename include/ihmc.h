@@ -324,6 +324,32 @@ int ihmc_fetch(ihmc_server* server, uint64_t ticket, ihmc_result* out, double* t
 /* Cancel a request: a queued one at once, a running one at the next round
  * boundary.  Thread-safe. */
 int ihmc_cancel(ihmc_server* server, uint64_t ticket);
+/* Checkpoint of a request, by ticket, into the caller's host buffer `buf` of
+ * *bytes bytes (buf NULL: *bytes = the size needed, the largest the request
+ * can take; a smaller buffer fails with IHMC_E_INVAL).  On success *bytes = the
+ * bytes written.  The checkpoint holds the request (lattice, field, run
+ * parameters, given initial field, replayed decisions) and, once it has run,
+ * its chain's state after a whole number of trajectories: the accepted field,
+ * S of it in exact fixed point, the estimator sums, the sign, the counters and
+ * the records.  The momenta, accept and flip uniforms of later trajectories
+ * are Philox draws at counters that name the trajectory (Sec. 3 needs nothing
+ * else), so a request restored from it continues bit for bit as the original.
+ * A queued request gives the request alone; a running one is checkpointed by
+ * the scheduler at the next round boundary (the call blocks until then; it
+ * keeps running); a finished or cancelled one (not yet fetched) from its
+ * retired results.  Thread-safe; must not overlap ihmc_server_destroy.  The
+ * layout is private to this library version. */
+int ihmc_checkpoint(ihmc_server* server, uint64_t ticket, void* buf, uint64_t* bytes);
+/* Queue a request restored from a checkpoint of ihmc_checkpoint (of this or
+ * another server, in this or another process) under a new ticket: it is
+ * admitted like any request, set up, then given the checkpoint's state, and
+ * runs its remaining trajectories; its fetched series hold all of them.
+ * IHMC_E_INVAL for a buffer that is not such a checkpoint or is truncated, and
+ * for a chain state that does not match its parameters.  Thread-safe. */
+int ihmc_restore(ihmc_server* server, const void* buf, uint64_t bytes, uint64_t* ticket);
+/* out[4]: state (IHMC_REQ_*), lattice sites, n_traj, trajectories done.
+ * Thread-safe. */
+int ihmc_request_info(ihmc_server* server, uint64_t ticket, int64_t* out);
 /* out[10]: rounds, seconds spent in rounds, site-MD-steps done, largest
  * number of resident chains, completed requests, queued now, resident now,
  * seconds since start, device bytes held, budget. */
@@ -338,16 +364,45 @@ int ihmc_force(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t precision, const 
  * phi_psi_substitution without constants), out[1] = m, out[2] = |m|,
  * out[3] = m^2 corrected, out[4] = beta*eps (Sec. 4). */
 int ihmc_action(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t precision, const double* psi, double* out);
+/* The HMC Hamiltonian H(psi, p) = 1/2 p.p + S(psi) of Sec. 3 (S as in
+ * ihmc_action) at host psi and p (N values each, rounded to the state
+ * `precision` as a chain holds them), into *H.  Computed by the hot path's own
+ * kernels: the kinetic sum of a first pass that reads the given momenta and
+ * the set-up measurement of S, added in exact fixed point (as every
+ * trajectory's H_old).  IHMC_E_INVAL (and *H = NaN) when a site term is
+ * non-finite or reaches 2^28 in magnitude. */
+int ihmc_hamiltonian(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t precision, const double* psi, const double* p,
+                     double* H);
 /* One trajectory of molecular dynamics from host (psi, p), in place, with
  * run->n_md, traj_len, integrator, precision (no Metropolis test). */
 int ihmc_integrate(ihmc_ctx* ctx, const ihmc_lattice* lat, const ihmc_run* run, double* psi, double* p);
-/* The momentum-stream normals of the GPU generator: n values for sites
- * 0..n-1 of (seed, chain_id, traj, tag) into host out. */
+/* The normals of the GPU generator for sites 0..n-1 of (seed, chain_id, traj,
+ * tag) into host out, exactly as a pass of state precision `precision` (4 or
+ * 8) draws them: Box-Muller in FP64 on the Philox pair's two 53-bit uniforms
+ * (sites 2i and 2i+1 from pair i), rounded to FP32 for precision 4 (Sec. 3, eq.
+ * momentum distribution). */
 int ihmc_philox_normals(ihmc_ctx* ctx, uint64_t seed, uint64_t chain_id, uint32_t traj, uint32_t tag,
-                        int64_t n, double* out);
+                        int32_t precision, int64_t n, double* out);
 /* Raw Philox4x32-10 words: for k < n, out[4k..4k+3] = philox(ctr[4k..4k+3],
  * key[2k..2k+1]), computed on the GPU. */
 int ihmc_philox_words(ihmc_ctx* ctx, int64_t n, const uint32_t* ctr, const uint32_t* key, uint32_t* out);
+
+/* Host-only (no device needed).  The launch plan that n chains (lats, runs)
+ * would form in one chain set of a context with step fusion `fuse_steps` and
+ * LDS-resident limit `resident_sites` (as ihmc_ctx_set_resident; tile classes
+ * from the built-in rule), and a dry run of one round of it: *taken = the
+ * fork/join events the round records, *reserved = the events a chain set
+ * creates for it.  A round that would need more than the chain set holds fails
+ * with IHMC_E_DEVICE rather than record past them. */
+int ihmc_plan_events(int32_t n, const ihmc_lattice* lats, const ihmc_run* runs, int32_t fuse_steps,
+                     int64_t resident_sites, int64_t* taken, int64_t* reserved);
+/* Host-only.  The exact fixed-point form (unit 2^-64, 128-bit two's
+ * complement, rounded to nearest with ties away from zero) that single action
+ * changes of any size take, such as the sign flip's (Sec. 3): for k < n,
+ * out[2k] / out[2k+1] = low / high word of round(x[k] 2^64), ok[k] = 1; ok[k] =
+ * 0 (and zero words) when |x[k]| >= 2^62 or x[k] is not finite, in which case
+ * the flip is rejected and counted as non-finite. */
+int ihmc_fixed_point(int64_t n, const double* x, uint64_t* out, int32_t* ok);
 
 /* ---- measurement ----------------------------------------------------------- */
 
@@ -358,6 +413,10 @@ int ihmc_chains_groups(ihmc_chains* chains, int32_t* n_groups);
 /* Launch group `group` (0 <= group < n_groups): out[0..5] = state precision,
  * ndim, tile class (see ihmc_tile_shape), chains, lattice sites, tiles. */
 int ihmc_chains_group_info(ihmc_chains* chains, int32_t group, int64_t* out);
+/* The chains (indices into the set) of launch group `group`, in launch order
+ * (descending pass count), into chain_idx (out[3] of ihmc_chains_group_info
+ * entries). */
+int ihmc_chains_group_chains(ihmc_chains* chains, int32_t group, int32_t* chain_idx);
 /* Time the fused pass kind `mode` (0 = first, 1 = middle, 2 = last, 5 = two
  * middle steps in one launch, 2D groups whose chains have at least two middle
  * steps) of launch group `group`: one warm-up launch, then `reps` launches bracketed by HIP

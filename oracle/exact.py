@@ -142,7 +142,7 @@ def ring_1d(N, beta, J=1.0, h=0.0):
 
 
 def infinite_range(N, betaJ, beta_h=0.0):
-    """App. A: exact <beta*eps> of H = -(J/2N) sum_{i!=j} s_i s_j - h sum s_i.
+    """App. A: exact <beta*eps>, <m> and <m^2> of H = -(J/2N) sum_{i!=j} s_i s_j - h sum s_i.
 
     Z = e^{-beta J/2} sum_n C(N,n) f(beta J/N, beta h, N - 2n) with
     f(a, b, x) = exp(a x^2 / 2 + b x); the e^{-beta J/2} prefactor follows from
@@ -158,7 +158,9 @@ def infinite_range(N, betaJ, beta_h=0.0):
     # beta*E(x) = beta J/2 - a x^2 / 2 - beta_h x
     be = 0.5 * betaJ / N - float((w * (0.5 * a * x * x + beta_h * x)).sum() / Z) / N
     m = float((w * x).sum() / Z) / N
-    return dict(be=be, m=m)
+    # the same weights give every moment of the magnetisation x / N
+    m2 = float((w * x * x).sum() / Z) / (N * N)
+    return dict(be=be, m=m, m2=m2)
 
 
 BETA_C_2D = 0.5 * math.log(1.0 + math.sqrt(2.0))

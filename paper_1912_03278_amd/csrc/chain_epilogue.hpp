@@ -51,11 +51,16 @@ __device__ __forceinline__ uint32_t finalize_trajectory(const ChainDev& cd, Chai
   }
   if (cd.flip_every > 0 && (t + 1) % cd.flip_every == 0) {
     // S(-psi) - S(psi) = 2 psi.h'/sqrt(J'): only the linear field term changes.
+    // A change that the fixed-point action cannot hold (non-finite, or
+    // |dS| >= 2^62) rejects the flip and marks the record.
     const double dS = 2.0 * st->sum_psih / cd.sqJ;
     const double r2 = uniform_at(cd, (uint32_t)t, TAG_FLIP);
-    if (dS <= 0.0 || r2 < exp(-dS)) {
-      uint32_t b2 = 0u;
-      const u128 S = add128(u128{st->S_lo, st->S_hi}, to_fixed(dS, b2));
+    u128 dSf;
+    if (!to_fixed_wide(dS, dSf)) {
+      if (finite && counted) st->n_nonfinite += 1;
+      flags |= REC_NONFINITE;
+    } else if (dS <= 0.0 || r2 < exp(-dS)) {
+      const u128 S = add128(u128{st->S_lo, st->S_hi}, dSf);
       st->S_lo = S.lo;
       st->S_hi = S.hi;
       st->sign = -st->sign;
@@ -128,9 +133,24 @@ __device__ __forceinline__ uint32_t load_flag_agent(const uint64_t* entry, int w
   return __hip_atomic_load((const uint32_t*)entry + word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // Count one finished unit at `counter`; true for the unit that completes `n`.
+//
+// Ordering: the entries are agent-scope atomic stores, which write through to
+// the memory that all XCDs share, and the counter is an agent-scope atomic.
+// The compiler barriers keep the entry stores above the wait and the counter
+// update below it; the wait for every outstanding memory operation makes the
+// entries complete (visible to every agent-scope load) before the counter
+// moves.  After the update, a compiler barrier keeps the caller's gathers of
+// the entries below it, and they are issued only once its return value has
+// arrived (they depend on it).  A release/acquire pair at agent scope would
+// say the same in the language's model, but on this GPU an agent-scope
+// release writes back the whole L2 of the XCD, including the field and momenta
+// the pass has just written, which the next launch does not need early.
 __device__ __forceinline__ bool count_done(uint32_t* counter, uint32_t n) {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_waitcnt(0);  // the entries stored above have completed
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
   const uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
   return prev == n - 1u;
 }
 

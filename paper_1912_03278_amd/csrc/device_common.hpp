@@ -43,42 +43,104 @@ __device__ __forceinline__ uint4 draw(const ChainDev& cd, uint32_t i, uint32_t t
   return philox4x32_10(make_uint4(i, traj, cd.chain_id, tag), cd.seed_lo, cd.seed_hi);
 }
 
-// Standard normal for `site`: pair site/2 gives (r cos th, r sin th) to sites 2i, 2i+1.
-__device__ __forceinline__ double normal_at(const ChainDev& cd, uint32_t traj, uint32_t tag, int64_t site) {
-  const uint4 w = draw(cd, (uint32_t)(site >> 1), traj, tag);
-  const double u1 = unit53(w.x, w.y), u2 = unit53(w.z, w.w);
-  const double r = sqrt(-2.0 * log(u1));
-  const double th = 6.283185307179586 * u2;
-  return (site & 1) ? r * sin(th) : r * cos(th);
+// ln 2 as head + tail: the head is ln 2 with its low 21 significand bits
+// cleared, so e * head is exact for |e| < 2^21; the tail is the rounded rest.
+constexpr double kLn2Head = 6.93147180369123816490e-01;
+constexpr double kLn2Tail = 1.90821492927058770002e-10;
+
+// ln u for u in (0, 1) (a 53-bit uniform): u = m 2^e with m in [sqrt(1/2),
+// sqrt 2), ln u = e ln 2 + 2 atanh(s), s = (m - 1)/(m + 1), |s| <= 0.1716, with
+// the odd Taylor series of atanh to s^23 (truncation below 1e-19 relative).
+__device__ __forceinline__ double ln_unit(double u) {
+  int e;
+  double m = frexp(u, &e);  // u = m 2^e, m in [1/2, 1)
+  const bool lo = m < 0.70710678118654752;
+  m = lo ? 2.0 * m : m;
+  e = lo ? e - 1 : e;
+  const double s = (m - 1.0) / (m + 1.0);
+  const double z = s * s;
+  double q = 1.0 / 23.0;
+  q = __builtin_fma(q, z, 1.0 / 21.0);
+  q = __builtin_fma(q, z, 1.0 / 19.0);
+  q = __builtin_fma(q, z, 1.0 / 17.0);
+  q = __builtin_fma(q, z, 1.0 / 15.0);
+  q = __builtin_fma(q, z, 1.0 / 13.0);
+  q = __builtin_fma(q, z, 1.0 / 11.0);
+  q = __builtin_fma(q, z, 1.0 / 9.0);
+  q = __builtin_fma(q, z, 1.0 / 7.0);
+  q = __builtin_fma(q, z, 1.0 / 5.0);
+  q = __builtin_fma(q, z, 1.0 / 3.0);
+  q = q * z;  // atanh(s)/s - 1
+  const double ls = 2.0 * __builtin_fma(s, q, s);
+  const double de = (double)e;
+  return __builtin_fma(de, kLn2Head, __builtin_fma(de, kLn2Tail, ls));
 }
 
-// Both normals of pair i.  FP64 state: FP64 Box-Muller (matches an FP64
-// reference to a few ulp).  FP32 state: the same 53-bit uniforms, Box-Muller
-// in FP32 with the hardware log2 / sin / cos (absolute error ~1e-6).
+// sin and cos of the angle 2 pi u, u in [0, 1] (a fraction of a turn): u is
+// reduced exactly to t = u - k/4, k = round(4u), |t| <= 1/8 turn; x = 2 pi t
+// (|x| <= pi/4, one rounding) goes into the Taylor series of sin (to x^17) and
+// cos (to x^18), truncation below 1e-19; quarter turn k mod 4 rotates the pair.
+__device__ __forceinline__ void sincos_turn(double u, double& sn, double& cs) {
+  const double k = rint(4.0 * u);
+  const double t = __builtin_fma(k, -0.25, u);  // exact
+  const double x = 6.283185307179586 * t;
+  const double z = x * x;
+  // sin x = x + x z P(z), cos x = 1 + z Q(z), z = x^2, coefficients +-1/n!
+  double ps = 1.0 / 355687428096000.0;
+  ps = __builtin_fma(ps, z, -1.0 / 1307674368000.0);
+  ps = __builtin_fma(ps, z, 1.0 / 6227020800.0);
+  ps = __builtin_fma(ps, z, -1.0 / 39916800.0);
+  ps = __builtin_fma(ps, z, 1.0 / 362880.0);
+  ps = __builtin_fma(ps, z, -1.0 / 5040.0);
+  ps = __builtin_fma(ps, z, 1.0 / 120.0);
+  ps = __builtin_fma(ps, z, -1.0 / 6.0);
+  const double sx = __builtin_fma(x * z, ps, x);
+  double pc = -1.0 / 6402373705728000.0;
+  pc = __builtin_fma(pc, z, 1.0 / 20922789888000.0);
+  pc = __builtin_fma(pc, z, -1.0 / 87178291200.0);
+  pc = __builtin_fma(pc, z, 1.0 / 479001600.0);
+  pc = __builtin_fma(pc, z, -1.0 / 3628800.0);
+  pc = __builtin_fma(pc, z, 1.0 / 40320.0);
+  pc = __builtin_fma(pc, z, -1.0 / 720.0);
+  pc = __builtin_fma(pc, z, 1.0 / 24.0);
+  pc = __builtin_fma(pc, z, -0.5);
+  const double cx = __builtin_fma(pc, z, 1.0);
+  const int q = (int)k & 3;
+  const double s0 = (q & 1) ? cx : sx, c0 = (q & 1) ? sx : cx;
+  sn = (q & 2) ? -s0 : s0;
+  cs = ((q + 1) & 2) ? -c0 : c0;
+}
+
+// Box-Muller in FP64 on a Philox output: two 53-bit uniforms u1, u2 give
+// r cos(2 pi u2) and r sin(2 pi u2), r = sqrt(-2 ln u1).
+__device__ __forceinline__ void box_muller(uint4 w, double& z0, double& z1) {
+  const double u1 = unit53(w.x, w.y), u2 = unit53(w.z, w.w);
+  const double r = sqrt(-2.0 * ln_unit(u1));
+  double sn, cs;
+  sincos_turn(u2, sn, cs);
+  z0 = r * cs;
+  z1 = r * sn;
+}
+
+// Standard normal for `site`: pair site/2 gives (r cos th, r sin th) to sites 2i, 2i+1.
+__device__ __forceinline__ double normal_at(const ChainDev& cd, uint32_t traj, uint32_t tag, int64_t site) {
+  double z0, z1;
+  box_muller(draw(cd, (uint32_t)(site >> 1), traj, tag), z0, z1);
+  return (site & 1) ? z1 : z0;
+}
+
+// Both normals of pair i, Box-Muller in FP64.  An FP32 state takes these FP64
+// normals rounded to nearest, so its momenta are the FP64 normals to within
+// one rounding (FP64 values of another log / sin / cos implementation lie a
+// few ulp away, which changes the FP32 rounding only when a value sits that
+// close to a rounding boundary).
 template <typename T>
 __device__ __forceinline__ void normal_pair(const ChainDev& cd, uint32_t traj, uint32_t tag, int64_t pair,
-                                            T& z0, T& z1);
-template <>
-__device__ __forceinline__ void normal_pair<double>(const ChainDev& cd, uint32_t traj, uint32_t tag,
-                                                    int64_t pair, double& z0, double& z1) {
-  const uint4 w = draw(cd, (uint32_t)pair, traj, tag);
-  const double u1 = unit53(w.x, w.y), u2 = unit53(w.z, w.w);
-  const double r = sqrt(-2.0 * log(u1));
-  const double th = 6.283185307179586 * u2;
-  z0 = r * cos(th);
-  z1 = r * sin(th);
-}
-template <>
-__device__ __forceinline__ void normal_pair<float>(const ChainDev& cd, uint32_t traj, uint32_t tag,
-                                                   int64_t pair, float& z0, float& z1) {
-  const uint4 w = draw(cd, (uint32_t)pair, traj, tag);
-  const float u1 = (float)unit53(w.x, w.y);
-  const float u2 = (float)unit53(w.z, w.w);
-  // -2 ln u1 = -2 ln2 log2(u1); the hardware sine/cosine take revolutions,
-  // so sin(2 pi u2) needs no range reduction for u2 in (0, 1)
-  const float r = __builtin_sqrtf(-1.38629436111989061f * __builtin_amdgcn_logf(u1));
-  z0 = r * __builtin_amdgcn_cosf(u2);
-  z1 = r * __builtin_amdgcn_sinf(u2);
+                                            T& z0, T& z1) {
+  double a, b;
+  box_muller(draw(cd, (uint32_t)pair, traj, tag), a, b);
+  z0 = (T)a;
+  z1 = (T)b;
 }
 
 __device__ __forceinline__ double uniform_at(const ChainDev& cd, uint32_t traj, uint32_t tag) {
@@ -137,6 +199,33 @@ __device__ __forceinline__ u128 to_fixed(double x, uint32_t& bad) {
   return r;
 }
 
+// round(x 2^64) (ties away from zero, as to_fixed) for any |x| < 2^62, the
+// range of the 128-bit sums; false (and zero) for larger or non-finite x.  For
+// single values of any size, such as the action change of the sign flip.
+__host__ __device__ inline bool to_fixed_wide(double x, u128& out) {
+  const uint64_t bits = __builtin_bit_cast(uint64_t, x);
+  const int ex = (int)((bits >> 52) & 0x7ffu);
+  out = u128{0ull, 0ull};
+  if (ex >= 1023 + 62) return false;  // |x| >= 2^62, inf or nan
+  if (ex == 0) return true;                   // zero or subnormal: rounds to 0
+  const uint64_t m = (bits & 0x000fffffffffffffull) | 0x0010000000000000ull;
+  const int sh = ex - 1011;  // |x| 2^64 = m 2^sh, sh <= 73
+  u128 r{0ull, 0ull};
+  if (sh >= 64) {
+    r.hi = m << (sh - 64);
+  } else if (sh > 0) {
+    r.lo = m << sh;
+    r.hi = m >> (64 - sh);
+  } else if (sh == 0) {
+    r.lo = m;
+  } else if (sh > -64) {
+    const int k = -sh;
+    r.lo = (m + (1ull << (k - 1))) >> k;
+  }
+  out = ((bits >> 63) != 0ull) ? neg128(r) : r;
+  return true;
+}
+
 __host__ __device__ __forceinline__ double fixed_to_double(u128 v) {
   const bool neg = (int64_t)v.hi < 0;
   if (neg) v = neg128(v);
@@ -190,8 +279,8 @@ __device__ __forceinline__ double exp_nonpos(double x) {
   const bool under = (x < -745.0);
   x = under ? 0.0 : x;
   const double k = rint(x * 1.4426950408889634);
-  double r = __builtin_fma(-k, 6.93147180369123816490e-01, x);
-  r = __builtin_fma(-k, 1.90821492927058770002e-10, r);
+  double r = __builtin_fma(-k, kLn2Head, x);
+  r = __builtin_fma(-k, kLn2Tail, r);
   double p = 1.6059043836821614e-10;  // 1/13!
   p = __builtin_fma(p, r, 2.0876756987868099e-09);
   p = __builtin_fma(p, r, 2.5052108385441720e-08);

@@ -187,17 +187,9 @@ __device__ __forceinline__ void h_terms(const ChainDev& cd, double v, double nb,
 // each XCD with its own L2.  Neighbouring tiles read the same halo cache lines,
 // so each XCD takes a contiguous range of the tile table: block b works on tile
 // xcd_tile(b, n), a bijection of [0, n).
-#ifndef IHMC_XCD_REMAP
-#define IHMC_XCD_REMAP 1
-#endif
 __device__ __forceinline__ int xcd_tile(int b, int n) {
-#if IHMC_XCD_REMAP
   const int q = n >> 3, r = n & 7, k = b & 7, m = b >> 3;
   return k * q + (k < r ? k : r) + m;
-#else
-  (void)n;
-  return b;
-#endif
 }
 
 // --------------------------------------------------------------------- 2D ---
@@ -1219,11 +1211,6 @@ static hipError_t launch_mode3t(int mode, const ChainDev* chains, const Tile* ti
 // threads) for small lattices.  3D boxes: 32 x 8 (or 16 x 16 by the same rule)
 // in the plane, 4 planes deep, or 8 where that adds no padding planes (256
 // threads per 4-plane slab).
-#ifndef IHMC_2D_BX
-#define IHMC_2D_BX 64
-#define IHMC_2D_BY 16
-#endif
-
 // Tile classes: the narrower tile wherever it leaves fewer idle threads in the
 // last tile of a row (row lengths just above a multiple of the wide tile); in
 // 3D the 8-plane boxes (fewer halo planes per site) where L2 is a multiple of 8
@@ -1247,7 +1234,7 @@ TileShape tile_shape(int precision, int ndim, int cls) {
   if (ndim == 2) {
     if (cls == 1) return TileShape{16, 16, 1};
     if (cls == 2) return TileShape{32, 32, 1};
-    return TileShape{IHMC_2D_BX, IHMC_2D_BY, 1};
+    return TileShape{64, 16, 1};
   }
   const int bz = cls >= 2 ? 8 : 4;
   return (cls & 1) ? TileShape{16, 16, bz} : TileShape{32, 8, bz};
@@ -1263,7 +1250,7 @@ hipError_t launch_lattice_pass(int precision, int ndim, int cls, int mode, const
     if (ndim == 2) {
       if (cls == 1) return launch_mode2v<float, 16, 16>(mode, chains, tiles, n_tiles, j, k, s);
       if (cls == 2) return launch_mode2v<float, 32, 32>(mode, chains, tiles, n_tiles, j, k, s);
-      return launch_mode2v<float, IHMC_2D_BX, IHMC_2D_BY>(mode, chains, tiles, n_tiles, j, k, s);
+      return launch_mode2v<float, 64, 16>(mode, chains, tiles, n_tiles, j, k, s);
     }
     switch (cls) {
       case 1: return launch_mode3t<float, 16, 16, 4>(mode, chains, tiles, n_tiles, j, k, s);
@@ -1275,7 +1262,7 @@ hipError_t launch_lattice_pass(int precision, int ndim, int cls, int mode, const
   if (ndim == 2) {
     if (cls == 1) return launch_mode2v<double, 16, 16>(mode, chains, tiles, n_tiles, j, k, s);
     if (cls == 2) return launch_mode2v<double, 32, 32>(mode, chains, tiles, n_tiles, j, k, s);
-    return launch_mode2v<double, IHMC_2D_BX, IHMC_2D_BY>(mode, chains, tiles, n_tiles, j, k, s);
+    return launch_mode2v<double, 64, 16>(mode, chains, tiles, n_tiles, j, k, s);
   }
   switch (cls) {
     case 1: return launch_mode3t<double, 16, 16, 4>(mode, chains, tiles, n_tiles, j, k, s);

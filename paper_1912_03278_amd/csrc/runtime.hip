@@ -155,9 +155,16 @@ __global__ void k_philox_words(int64_t n, const uint32_t* ctr, const uint32_t* k
   out[4 * k + 3] = r.w;
 }
 
+// Normals of sites 0..n-1 exactly as a pass of state type T draws them (one
+// pair per thread).
+template <typename T>
 __global__ void k_philox_normals(ChainDev cd, uint32_t traj, uint32_t tag, int64_t n, double* out) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) out[i] = normal_at(cd, traj, tag, i);
+  if (2 * i >= n) return;
+  T z0, z1;
+  normal_pair<T>(cd, traj, tag, i, z0, z1);
+  out[2 * i] = (double)z0;
+  if (2 * i + 1 < n) out[2 * i + 1] = (double)z1;
 }
 
 // Deterministic block-wide FP64 sum (fixed order), result broadcast to all threads.
@@ -655,6 +662,42 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
   return IHMC_OK;
 }
 
+// Enqueue target of a round plan: the HIP stream operations, or (dry) a count
+// of the events the plan takes, with no HIP call at all.  Every event the plan
+// takes comes from the pool; a plan that would take more than the pool holds
+// fails with hipErrorInvalidValue before it records anything past the end.
+struct RoundSink {
+  const std::vector<hipEvent_t>* pool = nullptr;  // null: dry count
+  size_t used = 0;
+  hipError_t take(hipEvent_t* ev) {
+    if (pool) {
+      if (used >= pool->size()) return hipErrorInvalidValue;
+      *ev = (*pool)[used];
+    } else {
+      *ev = nullptr;
+    }
+    ++used;
+    return hipSuccess;
+  }
+  hipError_t record(hipEvent_t ev, hipStream_t st) { return pool ? hipEventRecord(ev, st) : hipSuccess; }
+  hipError_t wait(hipStream_t st, hipEvent_t ev) { return pool ? hipStreamWaitEvent(st, ev, 0) : hipSuccess; }
+  // an event recorded on `from` that `to` waits for
+  hipError_t join(hipStream_t from, hipStream_t to) {
+    hipEvent_t ev;
+    hipError_t e = take(&ev);
+    if (e == hipSuccess) e = record(ev, from);
+    if (e == hipSuccess) e = wait(to, ev);
+    return e;
+  }
+  hipError_t pass(const Group& g, int mode, const ChainDev* d_cd, const Tile* t, int n, int j, int k,
+                  hipStream_t st) {
+    return pool ? launch_lattice_pass(g.prec, g.ndim, g.cls, mode, d_cd, t, n, j, k, st) : hipSuccess;
+  }
+  hipError_t resident(const Group& g, const ChainDev* d_cd, const Tile* t, int n, hipStream_t st) {
+    return pool ? launch_lattice_resident(g.prec, g.ndim, d_cd, t, n, 1, st) : hipSuccess;
+  }
+};
+
 // One trajectory of every chain.  Per group: pass j = 0 (FIRST) over all
 // tiles, then MIDDLE over the chains that still have passes after j and LAST
 // over the chains whose final pass is j.  Chains are sorted by pass count, so
@@ -662,30 +705,24 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
 // their own, and the LAST launches of a group on a second stream: LAST(j) only
 // waits for launch j-1 of its group, so it overlaps MIDDLE(j) of the other
 // chains.  Captured once, the fork/join structure becomes graph edges.
-hipError_t enqueue_round_plan(const std::vector<Group>& groups, const Tile* d_tiles, const ChainDev* d_cd,
-                              const std::vector<hipStream_t>& side, const std::vector<hipEvent_t>& events,
-                              hipStream_t s) {
+static hipError_t round_plan(const std::vector<Group>& groups, const Tile* d_tiles, const ChainDev* d_cd,
+                             const std::vector<hipStream_t>& side, RoundSink& sk, hipStream_t s) {
   hipError_t e;
-  int ev = 0;
-  auto next_event = [&]() { return events[ev++]; };
-  hipEvent_t fork = next_event();
-  if ((e = hipEventRecord(fork, s)) != hipSuccess) return e;
+  hipEvent_t fork;
+  if ((e = sk.take(&fork)) != hipSuccess) return e;
+  if ((e = sk.record(fork, s)) != hipSuccess) return e;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const Group& g = groups[gi];
-    hipStream_t gs = side[2 * gi], ls = side[2 * gi + 1];
-    if ((e = hipStreamWaitEvent(gs, fork, 0)) != hipSuccess) return e;
+    hipStream_t gs = sk.pool ? side[2 * gi] : nullptr, ls = sk.pool ? side[2 * gi + 1] : nullptr;
+    if ((e = sk.wait(gs, fork)) != hipSuccess) return e;
     const Tile* base = d_tiles + g.tile_off;
     if (g.cls == RESIDENT_CLASS) {  // one launch runs the whole trajectory of every chain of the group
-      e = launch_lattice_resident(g.prec, g.ndim, d_cd, base, g.tile_begin.back(), 1, gs);
-      if (e != hipSuccess) return e;
-      hipEvent_t j1 = next_event();
-      if ((e = hipEventRecord(j1, gs)) != hipSuccess) return e;
-      if ((e = hipStreamWaitEvent(s, j1, 0)) != hipSuccess) return e;
+      if ((e = sk.resident(g, d_cd, base, g.tile_begin.back(), gs)) != hipSuccess) return e;
+      if ((e = sk.join(gs, s)) != hipSuccess) return e;
       continue;
     }
-    if ((e = hipStreamWaitEvent(ls, fork, 0)) != hipSuccess) return e;
-    e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_FIRST, d_cd, base, g.tile_begin.back(), 0, 0, gs);
-    if (e != hipSuccess) return e;
+    if ((e = sk.wait(ls, fork)) != hipSuccess) return e;
+    if ((e = sk.pass(g, PASS_FIRST, d_cd, base, g.tile_begin.back(), 0, 0, gs)) != hipSuccess) return e;
     const int nc = (int)g.order.size();
     if (g.pair) {
       // Middle steps in pairs (1, 2), (3, 4), ...: launch k = 1 + (j - 1) / 2
@@ -703,26 +740,18 @@ hipError_t enqueue_round_plan(const std::vector<Group>& groups, const Tile* d_ti
         int last_end = single_end;
         while (last_end < nc && g.n_pass[last_end] - 1 == j) ++last_end;
         if (last_end > single_end) {
-          hipEvent_t after_prev = next_event();
-          if ((e = hipEventRecord(after_prev, gs)) != hipSuccess) return e;
-          if ((e = hipStreamWaitEvent(ls, after_prev, 0)) != hipSuccess) return e;
+          if ((e = sk.join(gs, ls)) != hipSuccess) return e;
           const int t0 = g.tile_begin[single_end], t1 = g.tile_begin[last_end];
-          e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_LAST, d_cd, base + t0, t1 - t0, j, k, ls);
-          if (e != hipSuccess) return e;
+          if ((e = sk.pass(g, PASS_LAST, d_cd, base + t0, t1 - t0, j, k, ls)) != hipSuccess) return e;
         }
         if (single_end > pair_end) {
           const int t0 = g.tile_begin[pair_end], t1 = g.tile_begin[single_end];
-          e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_MIDDLE, d_cd, base + t0, t1 - t0, j, k, gs);
-          if (e != hipSuccess) return e;
-          hipEvent_t after_single = next_event();
-          if ((e = hipEventRecord(after_single, gs)) != hipSuccess) return e;
-          if ((e = hipStreamWaitEvent(ls, after_single, 0)) != hipSuccess) return e;
-          e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_LAST, d_cd, base + t0, t1 - t0, j + 1, k + 1, ls);
-          if (e != hipSuccess) return e;
+          if ((e = sk.pass(g, PASS_MIDDLE, d_cd, base + t0, t1 - t0, j, k, gs)) != hipSuccess) return e;
+          if ((e = sk.join(gs, ls)) != hipSuccess) return e;
+          if ((e = sk.pass(g, PASS_LAST, d_cd, base + t0, t1 - t0, j + 1, k + 1, ls)) != hipSuccess) return e;
         }
         if (pair_end > 0) {
-          e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_PAIR, d_cd, base, g.tile_begin[pair_end], j, k, gs);
-          if (e != hipSuccess) return e;
+          if ((e = sk.pass(g, PASS_PAIR, d_cd, base, g.tile_begin[pair_end], j, k, gs)) != hipSuccess) return e;
         }
       }
     }
@@ -732,25 +761,34 @@ hipError_t enqueue_round_plan(const std::vector<Group>& groups, const Tile* d_ti
       int last_end = mid_end;
       while (last_end < nc && g.n_pass[last_end] - 1 == j) ++last_end;
       if (last_end > mid_end) {
-        hipEvent_t after_prev = next_event();
-        if ((e = hipEventRecord(after_prev, gs)) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(ls, after_prev, 0)) != hipSuccess) return e;
+        if ((e = sk.join(gs, ls)) != hipSuccess) return e;
         const int t0 = g.tile_begin[mid_end], t1 = g.tile_begin[last_end];
-        e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_LAST, d_cd, base + t0, t1 - t0, j, j, ls);
-        if (e != hipSuccess) return e;
+        if ((e = sk.pass(g, PASS_LAST, d_cd, base + t0, t1 - t0, j, j, ls)) != hipSuccess) return e;
       }
       if (mid_end > 0) {
-        e = launch_lattice_pass(g.prec, g.ndim, g.cls, PASS_MIDDLE, d_cd, base, g.tile_begin[mid_end], j, j, gs);
-        if (e != hipSuccess) return e;
+        if ((e = sk.pass(g, PASS_MIDDLE, d_cd, base, g.tile_begin[mid_end], j, j, gs)) != hipSuccess) return e;
       }
     }
-    hipEvent_t j1 = next_event(), j2 = next_event();
-    if ((e = hipEventRecord(j1, gs)) != hipSuccess) return e;
-    if ((e = hipEventRecord(j2, ls)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(s, j1, 0)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(s, j2, 0)) != hipSuccess) return e;
+    if ((e = sk.join(gs, s)) != hipSuccess) return e;
+    if ((e = sk.join(ls, s)) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t enqueue_round_plan(const std::vector<Group>& groups, const Tile* d_tiles, const ChainDev* d_cd,
+                              const std::vector<hipStream_t>& side, const std::vector<hipEvent_t>& events,
+                              hipStream_t s) {
+  if (side.size() < 2 * groups.size()) return hipErrorInvalidValue;
+  RoundSink sk;
+  sk.pool = &events;
+  return round_plan(groups, d_tiles, d_cd, side, sk, s);
+}
+
+size_t round_events_used(const std::vector<Group>& groups) {
+  RoundSink sk;
+  const std::vector<hipStream_t> none;
+  round_plan(groups, nullptr, nullptr, none, sk, nullptr);
+  return sk.used;
 }
 
 hipError_t Chains::enqueue_round(hipStream_t s) { return enqueue_round_plan(groups, d_tiles, d_cd, side, events, s); }
@@ -872,7 +910,7 @@ int result_from_device(ihmc_ctx* ctx, const ChainDev& c, const ChainDev* d_cd, i
 
 namespace {
 constexpr char kCkptMagic[8] = {'I', 'H', 'M', 'C', 'C', 'K', 'P', 'T'};
-constexpr uint32_t kCkptVersion = 1;
+constexpr uint32_t kCkptVersion = 2;
 
 struct CkptHeader {
   char magic[8];
@@ -884,7 +922,7 @@ struct CkptHeader {
   uint32_t chain_id, seed_lo, seed_hi;
   int32_t h_kind;
   double C, sqJ, Jp, b0, hp0, eps, c_m, c_e, c_v;
-  uint64_t field_hash;  // FNV-1a of the per-site h' (0 without one)
+  uint64_t field_hash;  // FNV-1a of the per-site h' in site order (0 without one)
   uint64_t variant;     // path-specific form of the force (dense: limb products)
   // state
   ChainState st;
@@ -919,30 +957,44 @@ void fill_identity(const ChainDev& c, uint64_t field_hash, uint64_t variant, Ckp
   h.variant = variant;
 }
 
-// FNV-1a over the per-site FP64 h' of the chain (device array of NP values).
-int field_hash(ihmc_ctx* ctx, const ChainDev& c, uint64_t* out) {
+// FNV-1a over the per-site FP64 h' of the chain (device array of NP values in
+// the stored layout; the padding of the rows is skipped).
+int field_hash(ihmc_ctx* ctx, const ChainDev& c, hipStream_t s, uint64_t* out) {
   *out = 0;
   if (c.h_kind != 2 || !c.hp) return IHMC_OK;
   std::vector<double> hp((size_t)c.NP);
-  HIPCHK(hipMemcpyAsync(hp.data(), c.hp, 8 * (size_t)c.NP, hipMemcpyDeviceToHost, ctx->stream), "field download");
-  HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
-  uint64_t h = 1469598103934665603ull;
-  const unsigned char* b = (const unsigned char*)hp.data();
-  for (size_t k = 0; k < hp.size() * 8; ++k) h = (h ^ b[k]) * 1099511628211ull;
-  *out = h;
+  HIPCHK(hipMemcpyAsync(hp.data(), c.hp, 8 * (size_t)c.NP, hipMemcpyDeviceToHost, s), "field download");
+  HIPCHK(hipStreamSynchronize(s), "sync");
+  std::vector<double> logical((size_t)c.N);
+  for (int64_t i = 0; i < c.N; ++i) logical[(size_t)i] = hp[(size_t)stored_index(c, i)];
+  *out = field_hash_host(logical.data(), c.N);
   return IHMC_OK;
+}
+
+uint64_t checkpoint_bytes(const ChainDev& c, int n_rec) {
+  return sizeof(CkptHeader) + (uint64_t)c.NP * (uint64_t)c.precision + (uint64_t)n_rec * sizeof(TrajRecord);
 }
 }  // namespace
 
-int chain_checkpoint(ihmc_ctx* ctx, const ChainDev& c, uint64_t variant, void* buf, uint64_t* bytes) {
+uint64_t field_hash_host(const double* hp, int64_t n) {
+  uint64_t h = 1469598103934665603ull;
+  const unsigned char* b = (const unsigned char*)hp;
+  for (size_t k = 0; k < (size_t)n * 8; ++k) h = (h ^ b[k]) * 1099511628211ull;
+  return h;
+}
+
+uint64_t chain_checkpoint_max_bytes(const ChainDev& c) { return checkpoint_bytes(c, std::max(0, c.cap)); }
+
+int chain_checkpoint(ihmc_ctx* ctx, const ChainDev& c, uint64_t variant, void* buf, uint64_t* bytes, hipStream_t s) {
   if (!bytes) return set_error(IHMC_E_INVAL, "bytes is NULL");
-  hipStream_t s = ctx->stream;
+  if (!s) s = ctx->stream;
   HIPCHK(hipStreamSynchronize(s), "sync");
   ChainState st;
-  HIPCHK(hipMemcpy(&st, c.st, sizeof st, hipMemcpyDeviceToHost), "state download");
+  HIPCHK(hipMemcpyAsync(&st, c.st, sizeof st, hipMemcpyDeviceToHost, s), "state download");
+  HIPCHK(hipStreamSynchronize(s), "sync");
   const int n_rec = std::max(0, std::min(st.traj, c.cap));
   const uint64_t field = (uint64_t)c.NP * (uint64_t)c.precision;
-  const uint64_t need = sizeof(CkptHeader) + field + (uint64_t)n_rec * sizeof(TrajRecord);
+  const uint64_t need = checkpoint_bytes(c, n_rec);
   if (!buf) {
     *bytes = need;
     return IHMC_OK;
@@ -959,7 +1011,7 @@ int chain_checkpoint(ihmc_ctx* ctx, const ChainDev& c, uint64_t variant, void* b
   h.version = kCkptVersion;
   h.header_bytes = sizeof h;
   uint64_t fh = 0;
-  int rc = field_hash(ctx, c, &fh);
+  int rc = field_hash(ctx, c, s, &fh);
   if (rc) return rc;
   fill_identity(c, fh, variant, h);
   h.st = st;
@@ -976,17 +1028,51 @@ int chain_checkpoint(ihmc_ctx* ctx, const ChainDev& c, uint64_t variant, void* b
   return IHMC_OK;
 }
 
-int chain_restore(ihmc_ctx* ctx, const ChainDev& c, uint64_t variant, const void* buf, uint64_t bytes, int* traj) {
+int chain_checkpoint_host(const ChainDev& c, uint64_t fh, const ChainState& st_in, const double* psi,
+                          const TrajRecord* rec, int n_rec, std::vector<char>& out) {
+  const uint64_t field = (uint64_t)c.NP * (uint64_t)c.precision;
+  out.assign(checkpoint_bytes(c, n_rec), 0);
+  CkptHeader h;
+  std::memset(&h, 0, sizeof h);
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.version = kCkptVersion;
+  h.header_bytes = sizeof h;
+  fill_identity(c, fh, 0, h);
+  h.st = st_in;
+  // the field is given with its sign applied: it is stored as is, with sign +1
+  // (every pass reads the stored field times the sign, and negation is exact)
+  h.st.cur = 0;
+  h.st.sign = 1;
+  h.st.done = 0u;
+  h.st.bad = 0u;
+  h.n_rec = n_rec;
+  std::memcpy(out.data(), &h, sizeof h);
+  char* f = out.data() + sizeof h;
+  for (int64_t i = 0; i < c.N; ++i) {
+    const int64_t k = stored_index(c, i);
+    if (c.precision == 4) {
+      const float v = (float)psi[i];
+      std::memcpy(f + 4 * k, &v, 4);
+    } else {
+      std::memcpy(f + 8 * k, &psi[i], 8);
+    }
+  }
+  if (n_rec) std::memcpy(out.data() + sizeof h + field, rec, sizeof(TrajRecord) * (size_t)n_rec);
+  return IHMC_OK;
+}
+
+int chain_restore(ihmc_ctx* ctx, const ChainDev& c, uint64_t variant, const void* buf, uint64_t bytes, int* traj,
+                  hipStream_t s) {
   if (!buf) return set_error(IHMC_E_INVAL, "buf is NULL");
   if (bytes < sizeof(CkptHeader)) return set_error(IHMC_E_INVAL, "not a checkpoint (%llu bytes)", (unsigned long long)bytes);
+  if (!s) s = ctx->stream;
   CkptHeader h;
   std::memcpy(&h, buf, sizeof h);
   if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != kCkptVersion || h.header_bytes != sizeof h)
     return set_error(IHMC_E_INVAL, "not a checkpoint of this library version");
   uint64_t fh = 0;
-  hipStream_t s = ctx->stream;
   HIPCHK(hipStreamSynchronize(s), "sync");
-  int rc = field_hash(ctx, c, &fh);
+  int rc = field_hash(ctx, c, s, &fh);
   if (rc) return rc;
   CkptHeader mine;
   std::memset(&mine, 0, sizeof mine);
@@ -1001,7 +1087,7 @@ int chain_restore(ihmc_ctx* ctx, const ChainDev& c, uint64_t variant, const void
   if (st.traj > c.cap)
     return set_error(IHMC_E_INVAL, "checkpoint after %d trajectories, the chain's capacity is %d", st.traj, c.cap);
   const uint64_t field = (uint64_t)c.NP * (uint64_t)c.precision;
-  const uint64_t need = sizeof h + field + (uint64_t)h.n_rec * sizeof(TrajRecord);
+  const uint64_t need = checkpoint_bytes(c, h.n_rec);
   if (bytes != need)
     return set_error(IHMC_E_INVAL, "checkpoint of %llu bytes, %llu expected", (unsigned long long)bytes,
                      (unsigned long long)need);
@@ -1226,10 +1312,90 @@ extern "C" int ihmc_integrate(ihmc_ctx* ctx, const ihmc_lattice* lat, const ihmc
   return IHMC_OK;
 }
 
+extern "C" int ihmc_hamiltonian(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t precision, const double* psi,
+                                const double* p, double* H) {
+  CTX_OK(ctx);
+  if (!lat || !psi || !p || !H) return set_error(IHMC_E_INVAL, "NULL argument");
+  *H = NAN;
+  // H_old of a trajectory whose first pass reads the given momenta: the
+  // kinetic sum of that pass plus S(psi) of the set-up measurement, added in
+  // exact fixed point by the closing block.  The trajectory itself is made
+  // negligibly short (its kicks and drifts round away), so no term of the
+  // final state can flag the record unless the given state already does.
+  ihmc_run r = diag_run(precision);
+  r.psi0 = psi;
+  r.traj_len = 1e-300;
+  static const uint8_t one = 1;
+  r.replay_accept = &one;
+  Chains* c = nullptr;
+  int rc = make_chains(ctx, 1, lat, &r, BUILD_P_GIVEN, &c);
+  if (rc) return rc;
+  hipStream_t s = ctx->stream;
+  const ChainDev& cdh = c->cd[0];
+  const int64_t N = cdh.N;
+  double* t = (double*)ctx->arena.alloc(8 * (uint64_t)N);
+  hipError_t e = t ? hipMemcpyAsync(t, p, 8 * N, hipMemcpyHostToDevice, s) : hipSuccess;
+  if (t && e == hipSuccess) {
+    if (cdh.precision == 4) k_import<float><<<nblk(N), 256, 0, s>>>(c->d_cd, 0, (float*)cdh.p, t);
+    else k_import<double><<<nblk(N), 256, 0, s>>>(c->d_cd, 0, (double*)cdh.p, t);
+    e = c->enqueue_round(s);
+  }
+  TrajRecord rec;
+  std::memset(&rec, 0, sizeof rec);
+  if (t && e == hipSuccess) e = hipMemcpyAsync(&rec, cdh.rec, sizeof rec, hipMemcpyDeviceToHost, s);
+  hipError_t e2 = hipStreamSynchronize(s);
+  if (t) ctx->arena.release(t);
+  delete c;
+  if (!t) return set_error(IHMC_E_NOMEM, "arena exhausted");
+  if (e != hipSuccess) return hip_fail(ctx, e, "hamiltonian");
+  if (e2 != hipSuccess) return hip_fail(ctx, e2, "hamiltonian sync");
+  if (rec.flags & REC_NONFINITE)
+    return set_error(IHMC_E_INVAL, "a term of H(psi, p) is non-finite or too large for the exact sums");
+  *H = rec.H_old;
+  return IHMC_OK;
+}
+
+extern "C" int ihmc_plan_events(int32_t n, const ihmc_lattice* lats, const ihmc_run* runs, int32_t fuse_steps,
+                                int64_t resident_sites, int64_t* taken, int64_t* reserved) {
+  if (n < 1 || !lats || !runs || !taken || !reserved) return set_error(IHMC_E_INVAL, "bad arguments");
+  std::vector<ChainDev> cd((size_t)n);
+  for (int i = 0; i < n; ++i) {
+    int rc = validate(lats[i], runs[i], i);
+    if (rc) return rc;
+    const ihmc_lattice& l = lats[i];
+    const bool site_field = !(l.h_len == 0 || l.h_len == 1);
+    const int64_t fit = resident_max_sites(runs[i].precision, site_field);
+    const int64_t lim = resident_sites < 0 ? fit : std::min(fit, resident_sites);
+    const int cls = lattice_sites(l) <= lim ? RESIDENT_CLASS
+                                            : tile_class(l.ndim, l.L[0], l.ndim == 3 ? l.L[2] : 1);
+    describe_chain(l, runs[i], 0, cls, cd[i]);
+  }
+  std::vector<int> members((size_t)n);
+  for (int i = 0; i < n; ++i) members[i] = i;
+  std::vector<Group> groups;
+  std::vector<Tile> tiles;
+  plan_groups(cd, members, groups, tiles, fuse_steps != 0);
+  *taken = (int64_t)round_events_used(groups);
+  *reserved = (int64_t)round_events(groups);
+  return IHMC_OK;
+}
+
+extern "C" int ihmc_fixed_point(int64_t n, const double* x, uint64_t* out, int32_t* ok) {
+  if (n < 0 || (n > 0 && (!x || !out || !ok))) return set_error(IHMC_E_INVAL, "bad arguments");
+  for (int64_t i = 0; i < n; ++i) {
+    u128 v;
+    ok[i] = to_fixed_wide(x[i], v) ? 1 : 0;
+    out[2 * i] = v.lo;
+    out[2 * i + 1] = v.hi;
+  }
+  return IHMC_OK;
+}
+
 extern "C" int ihmc_philox_normals(ihmc_ctx* ctx, uint64_t seed, uint64_t chain_id, uint32_t traj, uint32_t tag,
-                                   int64_t n, double* out) {
+                                   int32_t precision, int64_t n, double* out) {
   CTX_OK(ctx);
   if (n < 0 || (n > 0 && !out)) return set_error(IHMC_E_INVAL, "bad output");
+  if (precision != 4 && precision != 8) return set_error(IHMC_E_INVAL, "precision must be 4 or 8");
   if (n == 0) return IHMC_OK;
   ChainDev cdv;
   std::memset(&cdv, 0, sizeof cdv);
@@ -1239,7 +1405,9 @@ extern "C" int ihmc_philox_normals(ihmc_ctx* ctx, uint64_t seed, uint64_t chain_
   double* t = (double*)ctx->arena.alloc(8 * (uint64_t)n);
   if (!t) return set_error(IHMC_E_NOMEM, "arena exhausted");
   hipStream_t s = ctx->stream;
-  k_philox_normals<<<nblk(n), 256, 0, s>>>(cdv, traj, tag, n, t);
+  const int64_t pairs = (n + 1) / 2;
+  if (precision == 4) k_philox_normals<float><<<nblk(pairs), 256, 0, s>>>(cdv, traj, tag, n, t);
+  else k_philox_normals<double><<<nblk(pairs), 256, 0, s>>>(cdv, traj, tag, n, t);
   hipError_t e = hipMemcpyAsync(out, t, 8 * n, hipMemcpyDeviceToHost, s);
   hipError_t e2 = hipStreamSynchronize(s);
   ctx->arena.release(t);
@@ -1291,6 +1459,15 @@ extern "C" int ihmc_chains_group_info(ihmc_chains* ch, int32_t group, int64_t* o
   out[3] = (int64_t)g.order.size();
   out[4] = sites;
   out[5] = g.tile_begin.back();
+  return IHMC_OK;
+}
+
+extern "C" int ihmc_chains_group_chains(ihmc_chains* ch, int32_t group, int32_t* chain_idx) {
+  if (!ch || !chain_idx) return set_error(IHMC_E_INVAL, "NULL argument");
+  Chains* c = (Chains*)ch;
+  if (group < 0 || group >= (int32_t)c->groups.size()) return set_error(IHMC_E_INVAL, "group out of range");
+  const Group& g = c->groups[group];
+  for (size_t i = 0; i < g.order.size(); ++i) chain_idx[i] = g.order[i];
   return IHMC_OK;
 }
 

@@ -29,10 +29,20 @@ int result_from_device(ihmc_ctx* ctx, const ChainDev& c, const ChainDev* d_cd, i
 // Checkpoint of one chain into a host buffer (buf NULL: size only), and its
 // restore into a chain with the same parameters (sets *traj to the
 // checkpoint's trajectory index).  `variant` names a path-specific form of the
-// force that must also match (0 for the lattice path).  Both wait for the
-// context stream.
-int chain_checkpoint(ihmc_ctx* ctx, const ChainDev& c, uint64_t variant, void* buf, uint64_t* bytes);
-int chain_restore(ihmc_ctx* ctx, const ChainDev& c, uint64_t variant, const void* buf, uint64_t bytes, int* traj);
+// force that must also match (0 for the lattice path).  Both wait for stream
+// s (null: the context stream) and do their copies on it.
+int chain_checkpoint(ihmc_ctx* ctx, const ChainDev& c, uint64_t variant, void* buf, uint64_t* bytes,
+                     hipStream_t s = nullptr);
+int chain_restore(ihmc_ctx* ctx, const ChainDev& c, uint64_t variant, const void* buf, uint64_t bytes, int* traj,
+                  hipStream_t s = nullptr);
+// The same checkpoint built from host copies of a finished lattice chain: its
+// state, its accepted field in site order with the sign applied, and its
+// records; fh = field_hash_host of its h' in site order (0 without a per-site field).
+int chain_checkpoint_host(const ChainDev& c, uint64_t fh, const ChainState& st, const double* psi,
+                          const TrajRecord* rec, int n_rec, std::vector<char>& out);
+// Largest checkpoint of a chain (all cap records).
+uint64_t chain_checkpoint_max_bytes(const ChainDev& c);
+uint64_t field_hash_host(const double* hp, int64_t n);
 
 // First-fit sub-allocator over one device allocation (256-byte granules).
 struct Arena {
@@ -100,6 +110,9 @@ uint32_t chain_tile_count(const ChainDev& c);
 void plan_groups(const std::vector<ChainDev>& cd, const std::vector<int>& members, std::vector<Group>& groups,
                  std::vector<Tile>& tiles, bool fuse_steps);
 size_t round_events(const std::vector<Group>& groups);
+// Events the round of a plan actually takes (a dry run of the enqueue that
+// makes no HIP call); never more than round_events(groups).
+size_t round_events_used(const std::vector<Group>& groups);
 // One trajectory of every chain of the plan: FIRST over all tiles of a group,
 // then MIDDLE / LAST per pass index; groups on side streams (two per group).
 hipError_t enqueue_round_plan(const std::vector<Group>& groups, const Tile* d_tiles, const ChainDev* d_cd,

@@ -55,6 +55,10 @@ struct Request {
   double t_submit = 0, t_admit = 0, t_done = 0;
   int err_code = 0;
   std::string error;
+  std::vector<char> resume;  // chain checkpoint to continue from (restored requests)
+  bool ckpt_wanted = false;  // a checkpoint is asked for at the next round boundary
+  bool ckpt_ready = false;
+  std::vector<char> ckpt;    // the chain checkpoint taken by the scheduler
 };
 
 static inline uint64_t r256(uint64_t b) { return (b + 255ull) & ~255ull; }
@@ -75,6 +79,67 @@ static uint64_t request_bytes(const ihmc_lattice& l, const ihmc_run& r, int cls)
   describe_chain(l, r, 0, cls, c);
   b += r256(sizeof(Tile) * (uint64_t)c.n_tiles) + partials_bytes(c.n_tiles);
   return b;
+}
+
+// Checkpoint of a served request: the request itself (lattice, run
+// parameters, field, given initial field, replayed decisions) and, once it has
+// run, its chain checkpoint (chain_checkpoint's format).  A request restored
+// from it continues where the checkpoint was taken, bit for bit.
+constexpr char kSrvMagic[8] = {'I', 'H', 'M', 'C', 'S', 'R', 'V', 'C'};
+constexpr uint32_t kSrvVersion = 1;
+struct SrvHeader {
+  char magic[8];
+  uint32_t version, header_bytes;
+  int32_t ndim, L[3];
+  double J, beta, C;
+  int64_t h_len;
+  int32_t n_md, n_traj;
+  double traj_len;
+  int32_t integrator, flip_every, precision, n_therm;
+  uint64_t seed, chain_id;
+  int64_t psi0_len, replay_len;
+  uint64_t chain_bytes;
+};
+
+static uint64_t served_prefix_bytes(const Request* r) {
+  return sizeof(SrvHeader) + 8 * (uint64_t)r->h.size() + 8 * (uint64_t)r->psi0.size() + (uint64_t)r->replay.size();
+}
+
+static void served_write(const Request* r, const std::vector<char>& chain, std::vector<char>& out) {
+  SrvHeader h;
+  std::memset(&h, 0, sizeof h);
+  std::memcpy(h.magic, kSrvMagic, 8);
+  h.version = kSrvVersion;
+  h.header_bytes = sizeof h;
+  h.ndim = r->lat.ndim;
+  for (int i = 0; i < 3; ++i) h.L[i] = r->lat.L[i];
+  h.J = r->lat.J;
+  h.beta = r->lat.beta;
+  h.C = r->lat.C;
+  h.h_len = (int64_t)r->h.size();
+  h.n_md = r->run.n_md;
+  h.n_traj = r->run.n_traj;
+  h.traj_len = r->run.traj_len;
+  h.integrator = r->run.integrator;
+  h.flip_every = r->run.flip_every;
+  h.precision = r->run.precision;
+  h.n_therm = r->run.n_therm;
+  h.seed = r->run.seed;
+  h.chain_id = r->run.chain_id;
+  h.psi0_len = (int64_t)r->psi0.size();
+  h.replay_len = (int64_t)r->replay.size();
+  h.chain_bytes = chain.size();
+  out.resize(served_prefix_bytes(r) + chain.size());
+  char* o = out.data();
+  std::memcpy(o, &h, sizeof h);
+  o += sizeof h;
+  if (!r->h.empty()) std::memcpy(o, r->h.data(), 8 * r->h.size());
+  o += 8 * r->h.size();
+  if (!r->psi0.empty()) std::memcpy(o, r->psi0.data(), 8 * r->psi0.size());
+  o += 8 * r->psi0.size();
+  if (!r->replay.empty()) std::memcpy(o, r->replay.data(), r->replay.size());
+  o += r->replay.size();
+  if (!chain.empty()) std::memcpy(o, chain.data(), chain.size());
 }
 
 }  // namespace ihmc
@@ -119,7 +184,73 @@ struct ihmc_server {
   void fail_all(const char* what, hipError_t e);
   bool ensure_tiles(size_t n);
   bool ensure_streams(size_t n_groups, size_t n_events);
+  void take_checkpoints();
+  void resume_requests(std::vector<Request*>& ok);
 };
+
+// Checkpoints asked for since the last round, taken while the device is idle
+// between rounds.  Scheduler thread.
+void ihmc_server::take_checkpoints() {
+  std::vector<Request*> want;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (Request* r : active)
+      if (r->ckpt_wanted && !r->ckpt_ready) want.push_back(r);
+  }
+  for (Request* r : want) {
+    const ChainDev& c = cd_host[r->slot];
+    uint64_t n = 0;
+    std::vector<char> blob;
+    int rc = chain_checkpoint(ctx, c, 0, nullptr, &n, s);
+    if (rc == IHMC_OK) {
+      blob.resize(n);
+      rc = chain_checkpoint(ctx, c, 0, blob.data(), &n, s);
+      blob.resize(n);
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    r->ckpt_wanted = false;
+    if (rc == IHMC_OK) {
+      r->ckpt.swap(blob);
+      r->ckpt_ready = true;
+    } else {
+      r->ckpt.clear();
+      r->ckpt_ready = true;  // empty: the checkpoint failed
+    }
+    cv_done.notify_all();
+  }
+}
+
+// Restored requests: replace the freshly set-up state of each admitted chain
+// with its checkpoint.  Scheduler thread, device idle.
+void ihmc_server::resume_requests(std::vector<Request*>& ok) {
+  for (auto it = ok.begin(); it != ok.end();) {
+    Request* r = *it;
+    if (r->resume.empty()) {
+      ++it;
+      continue;
+    }
+    int traj = 0;
+    const int rc = chain_restore(ctx, cd_host[r->slot], 0, r->resume.data(), r->resume.size(), &traj, s);
+    if (rc == IHMC_OK) {
+      std::lock_guard<std::mutex> lk(mu);
+      r->rounds = traj;
+      r->resume.clear();
+      ++it;
+      continue;
+    }
+    for (void* p : r->dev) ctx->arena.release(p);
+    r->dev.clear();
+    std::lock_guard<std::mutex> lk(mu);
+    used -= r->need;
+    free_slots.push_back(r->slot);
+    r->state = REQ_FAILED;
+    r->err_code = rc;
+    r->error = std::string("restore: ") + ihmc_last_error();
+    r->t_done = now();
+    cv_done.notify_all();
+    it = ok.erase(it);
+  }
+}
 
 void ihmc_server::fail_all(const char* what, hipError_t e) {
   std::lock_guard<std::mutex> lk(mu);
@@ -322,6 +453,7 @@ bool ihmc_server::admit_setup(std::vector<Request*>& fresh) {
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   for (void* p : temps) ctx->arena.release(p);
+  if (e == hipSuccess) resume_requests(ok);
   if (e != hipSuccess) {
     {
       // requests of this batch are in neither the queue nor the active set yet
@@ -401,6 +533,7 @@ void ihmc_server::loop() {
       for (Request* r : active)
         if (r->cancel || r->rounds >= r->run.n_traj) finished.push_back(r);
     }
+    take_checkpoints();
     for (Request* r : finished) {
       retire(r, r->cancel ? REQ_CANCELLED : REQ_DONE);
       std::lock_guard<std::mutex> lk(mu);
@@ -484,19 +617,10 @@ extern "C" int ihmc_server_destroy(ihmc_server* sv) {
   return IHMC_OK;
 }
 
-extern "C" int ihmc_submit(ihmc_server* sv, const ihmc_lattice* lat, const ihmc_run* run, uint64_t* ticket) {
-  if (!sv || !lat || !run || !ticket) return set_error(IHMC_E_INVAL, "NULL argument");
-  int rc = validate(*lat, *run, 0);
-  if (rc) return rc;
-  Request* r = new (std::nothrow) Request();
-  if (!r) return set_error(IHMC_E_NOMEM, "host allocation failed");
-  r->lat = *lat;
-  r->run = *run;
-  const int64_t N = lattice_sites(*lat);
-  if (lat->h_len > 0) r->h.assign(lat->h, lat->h + lat->h_len);
+// Queue a request whose host copies are filled in (lat.h, psi0, replay point
+// into the request's own vectors).  Thread-safe.
+static int queue_request(ihmc_server* sv, Request* r, uint64_t* ticket) {
   r->lat.h = r->h.empty() ? nullptr : r->h.data();
-  if (run->psi0) r->psi0.assign(run->psi0, run->psi0 + N);
-  if (run->replay_accept && run->n_traj > 0) r->replay.assign(run->replay_accept, run->replay_accept + run->n_traj);
   r->run.psi0 = nullptr;
   r->run.replay_accept = r->replay.empty() ? nullptr : r->replay.data();
   r->cls = choose_class(sv->ctx, r->lat, r->run.precision, 0);
@@ -525,6 +649,143 @@ extern "C" int ihmc_submit(ihmc_server* sv, const ihmc_lattice* lat, const ihmc_
   sv->queue.push_back(r);
   *ticket = r->ticket;
   sv->cv_work.notify_one();
+  return IHMC_OK;
+}
+
+extern "C" int ihmc_submit(ihmc_server* sv, const ihmc_lattice* lat, const ihmc_run* run, uint64_t* ticket) {
+  if (!sv || !lat || !run || !ticket) return set_error(IHMC_E_INVAL, "NULL argument");
+  int rc = validate(*lat, *run, 0);
+  if (rc) return rc;
+  Request* r = new (std::nothrow) Request();
+  if (!r) return set_error(IHMC_E_NOMEM, "host allocation failed");
+  r->lat = *lat;
+  r->run = *run;
+  const int64_t N = lattice_sites(*lat);
+  if (lat->h_len > 0) r->h.assign(lat->h, lat->h + lat->h_len);
+  if (run->psi0) r->psi0.assign(run->psi0, run->psi0 + N);
+  if (run->replay_accept && run->n_traj > 0) r->replay.assign(run->replay_accept, run->replay_accept + run->n_traj);
+  return queue_request(sv, r, ticket);
+}
+
+extern "C" int ihmc_checkpoint(ihmc_server* sv, uint64_t ticket, void* buf, uint64_t* bytes) {
+  if (!sv || !bytes) return set_error(IHMC_E_INVAL, "NULL argument");
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return set_error(IHMC_E_INVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  Request* r = it->second;
+  if (r->state == REQ_FAILED) return set_error(IHMC_E_INVAL, "request %llu failed: %s", (unsigned long long)ticket,
+                                               r->error.c_str());
+  ChainDev c;
+  describe_chain(r->lat, r->run, 0, r->cls, c);
+  const uint64_t max_bytes = served_prefix_bytes(r) + chain_checkpoint_max_bytes(c);
+  if (!buf) {
+    *bytes = max_bytes;
+    return IHMC_OK;
+  }
+  if (*bytes < max_bytes) {
+    const uint64_t have = *bytes;
+    *bytes = max_bytes;
+    return set_error(IHMC_E_INVAL, "checkpoint buffer of %llu bytes, %llu needed", (unsigned long long)have,
+                     (unsigned long long)max_bytes);
+  }
+  std::vector<char> chain, out;
+  if (r->state == REQ_RUNNING) {
+    // taken by the scheduler at the next round boundary (or from the host copies
+    // if the request finishes first)
+    r->ckpt_ready = false;
+    r->ckpt_wanted = true;
+    sv->cv_work.notify_all();
+    sv->cv_done.wait(lk, [&] { return r->ckpt_ready || r->state >= REQ_DONE || sv->dead; });
+    if (r->ckpt_ready) {
+      if (r->ckpt.empty()) return set_error(IHMC_E_DEVICE, "checkpoint of request %llu failed",
+                                            (unsigned long long)ticket);
+      chain.swap(r->ckpt);
+      r->ckpt_ready = false;
+    }
+  }
+  if (r->state == REQ_FAILED) return set_error(IHMC_E_DEVICE, "request %llu failed", (unsigned long long)ticket);
+  if (chain.empty() && (r->state == REQ_DONE || r->state == REQ_CANCELLED) && r->st.traj > 0) {
+    // retired: its state, field and records are host copies
+    uint64_t fh = 0;
+    if (r->cd.h_kind == 2) {
+      std::vector<double> hp(r->h.size());
+      for (size_t i = 0; i < hp.size(); ++i) hp[i] = r->lat.beta * r->h[i];
+      fh = field_hash_host(hp.data(), (int64_t)hp.size());
+    }
+    if ((int64_t)r->psi.size() != r->cd.N)
+      return set_error(IHMC_E_DEVICE, "request %llu has no final field", (unsigned long long)ticket);
+    chain_checkpoint_host(r->cd, fh, r->st, r->psi.data(), r->rec.data(), (int)r->rec.size(), chain);
+  }
+  // queued (or retired before any trajectory): the request alone
+  served_write(r, chain, out);
+  std::memcpy(buf, out.data(), out.size());
+  *bytes = out.size();
+  return IHMC_OK;
+}
+
+extern "C" int ihmc_restore(ihmc_server* sv, const void* buf, uint64_t bytes, uint64_t* ticket) {
+  if (!sv || !buf || !ticket) return set_error(IHMC_E_INVAL, "NULL argument");
+  SrvHeader h;
+  if (bytes < sizeof h) return set_error(IHMC_E_INVAL, "not a served checkpoint (%llu bytes)", (unsigned long long)bytes);
+  std::memcpy(&h, buf, sizeof h);
+  if (std::memcmp(h.magic, kSrvMagic, 8) != 0 || h.version != kSrvVersion || h.header_bytes != sizeof h)
+    return set_error(IHMC_E_INVAL, "not a served checkpoint of this library version");
+  if (h.h_len < 0 || h.psi0_len < 0 || h.replay_len < 0 || h.h_len > (int64_t(1) << 33) ||
+      h.psi0_len > (int64_t(1) << 33) || h.replay_len > (int64_t(1) << 31))
+    return set_error(IHMC_E_INVAL, "served checkpoint is inconsistent");
+  const uint64_t prefix = sizeof h + 8 * (uint64_t)h.h_len + 8 * (uint64_t)h.psi0_len + (uint64_t)h.replay_len;
+  if (bytes != prefix + h.chain_bytes)
+    return set_error(IHMC_E_INVAL, "served checkpoint of %llu bytes, %llu expected", (unsigned long long)bytes,
+                     (unsigned long long)(prefix + h.chain_bytes));
+  Request* r = new (std::nothrow) Request();
+  if (!r) return set_error(IHMC_E_NOMEM, "host allocation failed");
+  std::memset(&r->lat, 0, sizeof r->lat);
+  std::memset(&r->run, 0, sizeof r->run);
+  r->lat.ndim = h.ndim;
+  for (int i = 0; i < 3; ++i) r->lat.L[i] = h.L[i];
+  r->lat.J = h.J;
+  r->lat.beta = h.beta;
+  r->lat.C = h.C;
+  r->lat.h_len = h.h_len;
+  r->run.n_md = h.n_md;
+  r->run.n_traj = h.n_traj;
+  r->run.traj_len = h.traj_len;
+  r->run.integrator = h.integrator;
+  r->run.flip_every = h.flip_every;
+  r->run.precision = h.precision;
+  r->run.n_therm = h.n_therm;
+  r->run.seed = h.seed;
+  r->run.chain_id = h.chain_id;
+  const char* in = (const char*)buf + sizeof h;
+  r->h.assign((const double*)in, (const double*)in + h.h_len);
+  in += 8 * h.h_len;
+  r->psi0.assign((const double*)in, (const double*)in + h.psi0_len);
+  in += 8 * h.psi0_len;
+  r->replay.assign((const uint8_t*)in, (const uint8_t*)in + h.replay_len);
+  in += h.replay_len;
+  r->resume.assign(in, in + h.chain_bytes);
+  r->lat.h = r->h.empty() ? nullptr : r->h.data();
+  int rc = validate(r->lat, r->run, 0);
+  const int64_t N = rc ? 0 : lattice_sites(r->lat);
+  if (!rc && ((h.psi0_len != 0 && h.psi0_len != N) || (h.replay_len != 0 && h.replay_len != h.n_traj)))
+    rc = set_error(IHMC_E_INVAL, "served checkpoint is inconsistent");
+  if (rc) {
+    delete r;
+    return rc;
+  }
+  return queue_request(sv, r, ticket);
+}
+
+extern "C" int ihmc_request_info(ihmc_server* sv, uint64_t ticket, int64_t* out) {
+  if (!sv || !out) return set_error(IHMC_E_INVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return set_error(IHMC_E_INVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  const Request* r = it->second;
+  out[0] = r->state;
+  out[1] = lattice_sites(r->lat);
+  out[2] = r->run.n_traj;
+  out[3] = r->state >= REQ_DONE ? r->st.traj : r->rounds;
   return IHMC_OK;
 }
 
@@ -582,8 +843,9 @@ extern "C" int ihmc_fetch(ihmc_server* sv, uint64_t ticket, ihmc_result* out, do
     if (out->flipped) out->flipped[t] = (q.flags & REC_FLIP) ? 1 : 0;
   }
   out->n_traj_done = r->st.traj;
-  out->acceptance = r->st.traj ? (double)r->st.n_acc / r->st.traj : 0.0;
-  const int64_t nf = r->st.traj - r->st.n_nonfinite;
+  const int64_t counted = std::max(0, r->st.traj - r->run.n_therm);  // trajectories past thermalisation
+  out->acceptance = counted ? (double)r->st.n_acc / (double)counted : 0.0;
+  const int64_t nf = counted - r->st.n_nonfinite;
   out->mean_exp_minus_dH = nf > 0 ? r->st.sum_exp_mdh / (double)nf : 0.0;
   out->n_nonfinite = r->st.n_nonfinite;
   if (out->psi_final && !r->psi.empty()) std::memcpy(out->psi_final, r->psi.data(), 8 * r->psi.size());

@@ -35,7 +35,9 @@ EXPORTS = (
     "ihmc_submit", "ihmc_poll", "ihmc_wait", "ihmc_fetch", "ihmc_cancel", "ihmc_server_stats",
     "ihmc_tile_shape", "ihmc_tune", "ihmc_tune_lookup", "ihmc_tune_pin", "ihmc_tune_save", "ihmc_tune_load",
     "ihmc_tune_check", "ihmc_chains_checkpoint", "ihmc_chains_restore", "ihmc_dense_checkpoint",
-    "ihmc_dense_restore", "ihmc_ctx_set_resident", "ihmc_ctx_set_step_fusion",
+    "ihmc_dense_restore", "ihmc_ctx_set_resident", "ihmc_ctx_set_step_fusion", "ihmc_hamiltonian",
+    "ihmc_plan_events", "ihmc_fixed_point", "ihmc_chains_group_chains", "ihmc_checkpoint", "ihmc_restore",
+    "ihmc_request_info",
 )
 TUNE_RULE, TUNE_MEASURED, TUNE_PINNED = 0, 1, 2
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED, REQ_FAILED = 0, 1, 2, 3, 4
@@ -119,11 +121,17 @@ def load():
     L.ihmc_force.argtypes = [vp, C.POINTER(_Lattice), C.c_int32, _DP, _DP]
     L.ihmc_action.argtypes = [vp, C.POINTER(_Lattice), C.c_int32, _DP, _DP]
     L.ihmc_integrate.argtypes = [vp, C.POINTER(_Lattice), C.POINTER(_Run), _DP, _DP]
-    L.ihmc_philox_normals.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int64, _DP]
+    L.ihmc_philox_normals.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, C.c_int64,
+                                      _DP]
+    L.ihmc_hamiltonian.argtypes = [vp, C.POINTER(_Lattice), C.c_int32, _DP, _DP, _DP]
+    L.ihmc_plan_events.argtypes = [C.c_int32, C.POINTER(_Lattice), C.POINTER(_Run), C.c_int32, C.c_int64,
+                                   C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    L.ihmc_fixed_point.argtypes = [C.c_int64, _DP, C.POINTER(C.c_uint64), C.POINTER(C.c_int32)]
     L.ihmc_philox_words.argtypes = [vp, C.c_int64, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
                                     C.POINTER(C.c_uint32)]
     L.ihmc_chains_groups.argtypes = [vp, C.POINTER(C.c_int32)]
     L.ihmc_chains_group_info.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64)]
+    L.ihmc_chains_group_chains.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
     L.ihmc_chains_time_pass.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                         C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.ihmc_copy_bandwidth.argtypes = [vp, C.c_uint64, C.c_int32, C.POINTER(C.c_double)]
@@ -145,6 +153,9 @@ def load():
     L.ihmc_fetch.argtypes = [vp, C.c_uint64, C.POINTER(_Result), _DP]
     L.ihmc_cancel.argtypes = [vp, C.c_uint64]
     L.ihmc_server_stats.argtypes = [vp, _DP]
+    L.ihmc_checkpoint.argtypes = [vp, C.c_uint64, vp, C.POINTER(C.c_uint64)]
+    L.ihmc_restore.argtypes = [vp, vp, C.c_uint64, C.POINTER(C.c_uint64)]
+    L.ihmc_request_info.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int64)]
     i32p = C.POINTER(C.c_int32)
     L.ihmc_tile_shape.argtypes = [C.c_int32, C.c_int32, i32p, i32p]
     L.ihmc_tune.argtypes = [vp, C.c_int32, C.POINTER(_Lattice), i32p, C.c_int64, C.c_int32, C.c_int32, i32p]
@@ -184,6 +195,34 @@ def check_tuning(path):
 
 def _f64(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def plan_events(lats, runs, fuse_steps=True, resident_sites=-1):
+    """(events one round of the chain set's launch plan takes, events the set
+    reserves for it), from a dry run on the host (no GPU needed)."""
+    keep = []
+    n = len(lats)
+    la = (_Lattice * n)(*[l._c(keep) for l in lats])
+    ra = (_Run * n)(*[r._c(keep) for r in runs])
+    taken, reserved = C.c_int64(), C.c_int64()
+    _check(load().ihmc_plan_events(n, la, ra, 1 if fuse_steps else 0, int(resident_sites), C.byref(taken),
+                                   C.byref(reserved)))
+    return taken.value, reserved.value
+
+
+def fixed_point(x):
+    """The library's fixed-point form of single action changes (host-only):
+    (signed 128-bit integers round(x 2^64) as Python ints, ok flags)."""
+    x = np.ascontiguousarray(np.atleast_1d(x), dtype=np.float64)
+    out = np.zeros(2 * x.size, dtype=np.uint64)
+    ok = np.zeros(x.size, dtype=np.int32)
+    _check(load().ihmc_fixed_point(x.size, _dp(x), out.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                   ok.ctypes.data_as(C.POINTER(C.c_int32))))
+    vals = []
+    for k in range(x.size):
+        v = int(out[2 * k]) | (int(out[2 * k + 1]) << 64)
+        vals.append(v - (1 << 128) if v >> 127 else v)
+    return vals, ok.astype(bool)
 
 
 def _dp(a):
@@ -485,10 +524,19 @@ class Context:
         _check(load().ihmc_copy_bandwidth(self.h, int(nbytes), int(reps), C.byref(us)))
         return us.value
 
-    def philox_normals(self, seed, chain_id, traj, tag, n):
+    def philox_normals(self, seed, chain_id, traj, tag, n, precision=F64):
+        """Normals of sites 0..n-1 as a pass of state `precision` draws them."""
         out = np.zeros(n)
-        _check(load().ihmc_philox_normals(self.h, seed, chain_id, traj, tag, n, _dp(out)))
+        _check(load().ihmc_philox_normals(self.h, seed, chain_id, traj, tag, int(precision), n, _dp(out)))
         return out
+
+    def hamiltonian(self, lat: Lattice, psi, p, precision=F64):
+        """H(psi, p) = 1/2 p.p + S(psi) through the hot path's kernels (exact fixed-point sums)."""
+        keep = []
+        psi, p = _f64(psi), _f64(p)
+        H = np.zeros(1)
+        _check(load().ihmc_hamiltonian(self.h, C.byref(lat._c(keep)), int(precision), _dp(psi), _dp(p), _dp(H)))
+        return float(H[0])
 
     def philox_words(self, ctr, key):
         ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
@@ -551,6 +599,13 @@ class Chains:
         out = (C.c_int64 * 6)()
         _check(load().ihmc_chains_group_info(self.h, int(group), out))
         return dict(zip(("precision", "ndim", "cls", "chains", "sites", "tiles"), (int(v) for v in out)))
+
+    def group_chains(self, group):
+        """Indices of the chains of a launch group, in launch order."""
+        n = self.group_info(group)["chains"]
+        out = (C.c_int32 * max(1, n))()
+        _check(load().ihmc_chains_group_chains(self.h, int(group), out))
+        return [int(out[i]) for i in range(n)]
 
     def time_pass(self, group, mode=1, reps=50):
         """Mean duration (us) of one fused pass launch of a group, timed with HIP events
@@ -658,6 +713,30 @@ class Server:
         st = C.c_int32()
         _check(load().ihmc_wait(self.h, int(ticket), float(timeout), C.byref(st)))
         return st.value
+
+    def info(self, ticket):
+        """{'state', 'sites', 'n_traj', 'done'} of a request."""
+        out = (C.c_int64 * 4)()
+        _check(load().ihmc_request_info(self.h, int(ticket), out))
+        return dict(zip(("state", "sites", "n_traj", "done"), (int(v) for v in out)))
+
+    def checkpoint(self, ticket):
+        """The request's checkpoint, as bytes (a running request: at the next
+        round boundary; it keeps running)."""
+        n = C.c_uint64(0)
+        _check(load().ihmc_checkpoint(self.h, int(ticket), None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(load().ihmc_checkpoint(self.h, int(ticket), buf, C.byref(n)))
+        return buf.raw[:n.value]
+
+    def restore(self, data):
+        """Queue a request that continues from a checkpoint; returns its ticket."""
+        buf = C.create_string_buffer(bytes(data), len(data))
+        t = C.c_uint64()
+        _check(load().ihmc_restore(self.h, buf, len(data), C.byref(t)))
+        inf = self.info(t.value)
+        self._meta[t.value] = (inf["n_traj"], inf["sites"])
+        return t.value
 
     def fetch(self, ticket, want_psi=True):
         n_traj, N = self._meta[ticket]

@@ -14,7 +14,7 @@ import pytest
 
 from oracle import exact as E
 
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "exact_values.json")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "spin_model_exact.json")
 
 
 @pytest.mark.parametrize("L0,L1,beta", [(4, 4, 0.4), (3, 4, 0.3), (4, 3, 0.5), (4, 4, E.BETA_C_2D)])
@@ -39,6 +39,7 @@ def test_appendix_formula_matches_enumeration(N, betaJ, bh):
     ap = E.infinite_range(N, betaJ, beta_h=bh)
     assert abs(bf["be"] - ap["be"]) < 1e-12
     assert abs(bf["m"] - ap["m"]) < 1e-12
+    assert abs(bf["m2"] - ap["m2"]) < 1e-12
 
 
 def test_torus_spectrum():
@@ -70,10 +71,12 @@ def test_ferdinand_fisher_is_leading_order_only():
     assert abs(tm["be"] - E.ferdinand_fisher_leading(64)) < 5e-3
 
 
-def test_golden_values():
-    """Stored exact values (written by tests/golden/make_golden.py from oracle.exact)."""
+def test_against_independent_values():
+    """The exact references against values computed independently of them
+    (tests/golden/spin_model_exact.json, printed to 10 decimals)."""
     with open(GOLDEN) as f:
         g = json.load(f)
+    assert len(g["values"]) >= 7
     for rec in g["values"]:
         kind, args, ref = rec["kind"], rec["args"], rec["value"]
         if kind == "brute_force":
@@ -84,9 +87,7 @@ def test_golden_values():
             got = E.ring_1d(args["N"], args["beta"], h=args["h"])
         elif kind == "infinite_range":
             got = E.infinite_range(args["N"], args["betaJ"])
-        elif kind == "onsager":
-            got = {"be": E.onsager_energy(args["beta"])}
         else:
             raise AssertionError(kind)
         for k, v in ref.items():
-            assert abs(got[k] - v) < 1e-10, (rec, k)
+            assert abs(got[k] - v) < 1e-10, (rec, k, got[k])

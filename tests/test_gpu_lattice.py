@@ -47,6 +47,16 @@ def test_philox_words_bit_identical(ctx, orc):
     assert np.array_equal(g, ref)
 
 
+def test_philox_known_answer_vectors(ctx):
+    """The GPU generator reproduces the published Philox4x32-10 vectors (SC'11)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    rows = [[int(v, 16) for v in line.split()] for line in open(path) if line.strip() and line[0] != "#"]
+    ctr = np.array([r[0:4] for r in rows], dtype=np.uint32)
+    key = np.array([r[4:6] for r in rows], dtype=np.uint32)
+    assert np.array_equal(ctx.philox_words(ctr, key), np.array([r[6:10] for r in rows], dtype=np.uint32))
+
+
 @pytest.mark.parametrize("tag", [1, 2, 4])
 def test_philox_normals_match(ctx, orc, tag):
     n = 100001
@@ -54,6 +64,49 @@ def test_philox_normals_match(ctx, orc, tag):
     r = orc.normals(7, 3, 11, tag, n)
     # same uniforms; FP64 log/sqrt/sincos of two libraries differ by a few ulp
     assert np.max(np.abs(g - r)) < 1e-14
+
+
+@pytest.mark.parametrize("tag", [2, 4])
+def test_fp32_momenta_are_rounded_fp64_normals(ctx, orc, tag):
+    """The FP32 state's momenta (drawn by the same function the first pass
+    calls) are the FP64 normals rounded to nearest: equal to the oracle's normals
+    rounded to FP32, except where the two FP64 values (a few ulp apart) straddle
+    an FP32 rounding boundary, which moves one value by one FP32 ulp."""
+    n = 1 << 20
+    g = ctx.philox_normals(7, 3, 11, tag, n, precision=4)
+    r32 = orc.normals(7, 3, 11, tag, n).astype(np.float32).astype(np.float64)
+    diff = g != r32
+    assert diff.sum() <= 2, int(diff.sum())
+    if diff.any():
+        ulp = np.spacing(np.abs(r32[diff]).astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(g[diff] - r32[diff]) <= ulp)
+
+
+@pytest.mark.parametrize("case", ["2d_ragged", "2d_site_h", "3d_small_wrap", "3d_site_h"])
+@pytest.mark.parametrize("prec", [8, 4])
+def test_hamiltonian(ctx, orc, case, prec):
+    """H(psi, p) = 1/2 p.p + S(psi) (Sec. 3) through the hot path's kernels, at
+    states representable in both precisions: 1e-12 relative to the oracle."""
+    L, beta, C, h, psi = _case([c for c in CASES if c[0] == case][0], 4)
+    rng = np.random.default_rng(5)
+    p = rng.standard_normal(psi.size)
+    psi = psi.astype(np.float32).astype(np.float64)
+    p = p.astype(np.float32).astype(np.float64)
+    H = ctx.hamiltonian(glat(L, beta, C, h), psi, p, precision=prec)
+    Hr = orc.hamiltonian(olat(orc, L, beta, C, h), psi, p)
+    assert abs(H - Hr) <= 1e-12 * abs(Hr), (H, Hr)
+
+
+def test_hamiltonian_rejects_out_of_range_state(ctx):
+    from paper_1912_03278_amd import ihmc
+    psi = np.zeros(64)
+    p = np.zeros(64)
+    p[5] = 1e15  # 1/2 p^2 beyond the exact sums' per-term range
+    with pytest.raises(ihmc.IhmcError):
+        ctx.hamiltonian(glat((8, 8), 0.4, 4.1), psi, p)
+    p[5] = np.nan
+    with pytest.raises(ihmc.IhmcError):
+        ctx.hamiltonian(glat((8, 8), 0.4, 4.1), psi, p)
 
 
 CASES = [

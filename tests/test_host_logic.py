@@ -1,0 +1,113 @@
+"""Host-side logic of the library that needs no GPU: the event budget of a
+round's launch plan and the fixed-point conversion of the sign flip.
+
+* Every round records its fork/join points on events taken from a pool that a
+  chain set creates once.  A dry run of the plan (the same code path as the
+  enqueue, with every HIP call left out) counts the events one round takes;
+  over random plans it must never exceed the pool (a round that would is
+  refused instead of reading past it).
+* The sign flip of Sec. 3 changes S by 2 psi.h'/sqrt(J'), added to the exact
+  fixed-point action.  Its conversion must give round(x 2^64), ties away from
+  zero, for every |x| < 2^62 and refuse larger or non-finite values.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+
+def _lib():
+    from paper_1912_03278_amd import build, ihmc
+    import os
+    if not os.path.exists(ihmc.LIB_PATH):
+        build.build()
+    return ihmc
+
+
+def _random_plan(rng, ihmc, n):
+    lats, runs = [], []
+    for i in range(n):
+        d = int(rng.choice([2, 3]))
+        if d == 2:
+            L = tuple(int(v) for v in rng.integers(3, 300, 2))
+        else:
+            L = tuple(int(v) for v in rng.integers(3, 40, 3))
+        h = None
+        u = rng.random()
+        if u < 0.3:
+            h = float(rng.normal(0, 0.1))
+        elif u < 0.5:
+            h = rng.normal(0, 0.1, int(np.prod(L)))
+        lats.append(ihmc.Lattice(L, beta=0.4, C=2 * d + 0.1, h=h))
+        runs.append(ihmc.Run(n_md=int(rng.integers(1, 12)), n_traj=1, integrator=int(rng.integers(0, 2)),
+                             precision=int(rng.choice([4, 8])), chain_id=i))
+    return lats, runs
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_round_events_within_pool(seed):
+    ihmc = _lib()
+    rng = np.random.default_rng(seed)
+    lats, runs = _random_plan(rng, ihmc, int(rng.integers(1, 40)))
+    for fuse in (True, False):
+        for resident in (-1, 0, 300):
+            taken, reserved = ihmc.plan_events(lats, runs, fuse_steps=fuse, resident_sites=resident)
+            assert 1 <= taken <= reserved, (seed, fuse, resident, taken, reserved)
+
+
+def test_round_events_exact_counts():
+    """Hand-counted plans: one fork; per tiled group 2 joins plus one event per
+    LAST launch that waits for its group's stream (and per single middle step
+    of a fused 2D group); per resident group 1 join."""
+    ihmc = _lib()
+    lat2 = ihmc.Lattice((100, 100), beta=0.4, C=4.1)
+    lat3 = ihmc.Lattice((20, 20, 20), beta=0.2, C=6.1)
+    run = lambda n_md, i=0: ihmc.Run(n_md=n_md, n_traj=1, chain_id=i)
+    # one 2D chain, 4 MD steps = 5 passes: pairs (1,2), then LAST at 4 after a
+    # single middle step 3 -> fork + join(single) + 2 final joins
+    assert ihmc.plan_events([lat2], [run(4)], fuse_steps=True, resident_sites=0)[0] == 4
+    # one step per launch: LAST(4) waits once -> fork + 1 + 2
+    assert ihmc.plan_events([lat2], [run(4)], fuse_steps=False, resident_sites=0)[0] == 4
+    # 3D chains of 3 and 5 steps: LAST at 3 and at 5 each wait -> fork + 2 + 2
+    assert ihmc.plan_events([lat3, lat3], [run(3), run(5, 1)], fuse_steps=True, resident_sites=0)[0] == 5
+    # two resident chains (one group): fork + 1
+    small = ihmc.Lattice((8, 8), beta=0.4, C=4.1)
+    assert ihmc.plan_events([small, small], [run(4), run(7, 1)], resident_sites=-1)[0] == 2
+
+
+def _exact_fixed(x):
+    """round(x 2^64), ties away from zero, from exact rational arithmetic."""
+    v = Fraction(x) * (1 << 64)
+    a = abs(v)
+    q, r = divmod(a.numerator, a.denominator)
+    if 2 * r >= a.denominator:
+        q += 1
+    return q if v >= 0 else -q
+
+
+def test_fixed_point_conversion_boundaries():
+    ihmc = _lib()
+    big = 2.0 ** 62
+    xs = [0.0, -0.0, 1.0, -1.0, 0.5, 2.0 ** -64, 2.0 ** -65, 3 * 2.0 ** -66, -(2.0 ** -65), 2.0 ** -66,
+          1e-300, 5e-324, math.pi, -math.e * 1e9, 2.0 ** 28, -(2.0 ** 28) * 1.5, 2.0 ** 40 + 0.25,
+          np.nextafter(big, 0.0), -np.nextafter(big, 0.0), 2.0 ** 61, 1.2345678901234567e17]
+    vals, ok = ihmc.fixed_point(xs)
+    assert ok.all()
+    for x, v in zip(xs, vals):
+        assert v == _exact_fixed(x), (x, v, _exact_fixed(x))
+    bad = [big, -big, 2.0 ** 63, 1e300, float("inf"), -float("inf"), float("nan")]
+    vals, ok = ihmc.fixed_point(bad)
+    assert not ok.any()
+    assert all(v == 0 for v in vals)
+
+
+def test_fixed_point_random_values():
+    ihmc = _lib()
+    rng = np.random.default_rng(1)
+    xs = np.concatenate([rng.normal(0, 1, 300), rng.normal(0, 1, 300) * 10.0 ** rng.integers(-20, 18, 300),
+                         rng.uniform(-2.0 ** 61, 2.0 ** 61, 100)])
+    vals, ok = ihmc.fixed_point(xs)
+    assert ok.all()
+    for x, v in zip(xs.tolist(), vals):
+        assert v == _exact_fixed(x), x

@@ -67,6 +67,9 @@ def test_infinite_range_dense_against_appendix(orc, N):
     ex = E.infinite_range(N, 1.0)
     r = orc.run(d, 30000, 10, seed=5, flip_every=4)
     _check(r.beta_eps, ex["be"], 500)
+    # the dense estimators of m^2 (bias 1^T Kt^-1 1 / (N^2 J') from a CG solve) and m
+    _check(r.m2c, ex["m2"], 500)
+    _check(r.m, ex["m"], 500)
 
 
 @pytest.mark.parametrize("dC", [1e-5, 0.1, 1.0])

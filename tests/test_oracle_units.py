@@ -11,6 +11,7 @@
 * Philox / Box-Muller: distribution tests.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -182,6 +183,24 @@ def test_philox_uniforms_and_normals(orc):
     assert sst.kstest(z, "norm").pvalue > 1e-4
     # cos/sin halves of a pair are uncorrelated
     assert abs(np.corrcoef(z[0:-1:2], z[1::2])[0, 1]) < 4 / math.sqrt(z.size / 2)
+
+
+def _kat():
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    out = []
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            w = [int(v, 16) for v in line.split()]
+            out.append((w[0:4], w[4:6], w[6:10]))
+    return out
+
+
+def test_philox_known_answer_vectors(orc):
+    """The published Philox4x32-10 known-answer vectors (SC'11 / Random123)."""
+    kat = _kat()
+    assert len(kat) == 3
+    for ctr, key, ref in kat:
+        assert [int(v) for v in orc.philox4x32_10(ctr, key)] == ref, (ctr, key)
 
 
 def test_philox_streams_are_distinct_and_mixing(orc):
