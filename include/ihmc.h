@@ -360,6 +360,22 @@ int ihmc_server_stats(ihmc_server* server, double* out);
 /* F = -dS/dpsi at the host field psi (N values) into host F (N values), with
  * the state rounded to `precision` (Sec. 3 equations of motion). */
 int ihmc_force(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t precision, const double* psi, double* F);
+/* Allocation-free variant of ihmc_force, for callers that cannot allocate
+ * device memory (code under HIP stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc): F = -dS/dpsi of the device field `psi` into the
+ * device array `F`, both N values of the state `precision` (4: float, 8:
+ * double) in site order, caller-owned, enqueued on `stream` (a hipStream_t;
+ * NULL: the context stream) and not waited for.  The lattice may carry no
+ * field or a uniform one (h_len 0 or 1; a per-site field is
+ * IHMC_E_UNSUPPORTED).  It allocates nothing: the chain descriptor, tile table
+ * and padded field staging live in a fixed 32 MiB device array per GPU (a
+ * lattice whose staging exceeds it, about 3.9M FP32 or 1.9M FP64 sites, is
+ * IHMC_E_INVAL).  Every call on one GPU uses that GPU's array, which keeps the
+ * last call's contents: calls that overlap on one GPU (other streams, other
+ * host threads, other contexts of the device) race and must be serialised by
+ * the caller.  Same force pass and bits as ihmc_force. */
+int ihmc_force_noalloc(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t precision, const void* psi, void* F,
+                       void* stream);
 /* Action and estimators of a host field psi: out[0] = S(psi) (FP64, eq.
  * phi_psi_substitution without constants), out[1] = m, out[2] = |m|,
  * out[3] = m^2 corrected, out[4] = beta*eps (Sec. 4). */

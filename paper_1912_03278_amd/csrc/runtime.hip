@@ -428,6 +428,14 @@ extern "C" int ihmc_ctx_create(int32_t device, uint64_t arena_bytes, ihmc_alloc_
     delete c;
     return hip_fail(nullptr, e, "hipStreamCreate");
   }
+  // the allocation-free entry point's scratch on this device
+  {
+    const int rc = noalloc_scratch_init(device, &c->scratch);
+    if (rc) {
+      ihmc_ctx_destroy(c);
+      return rc;
+    }
+  }
   // tile classes chosen earlier, when a cache file is named and present
   const char* cache = std::getenv("IHMC_TUNE_CACHE");
   if (cache && *cache) {

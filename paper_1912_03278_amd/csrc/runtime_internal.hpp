@@ -178,4 +178,11 @@ struct ihmc_ctx {
   ihmc::TuneTable tune;
   int64_t resident_sites = -1;  // chains up to this many sites run LDS-resident (-1: as many as fit, 0: none)
   int32_t fuse_steps = 1;       // 2D tiled chains run two middle steps per launch
+  void* scratch = nullptr;      // this device's scratch of the allocation-free entry point
 };
+
+namespace ihmc {
+// Device address of the allocation-free entry point's scratch array on
+// `device` (the current device), looked up once per device (noalloc.hip).
+int noalloc_scratch_init(int device, void** out);
+}  // namespace ihmc

@@ -37,7 +37,7 @@ EXPORTS = (
     "ihmc_tune_check", "ihmc_chains_checkpoint", "ihmc_chains_restore", "ihmc_dense_checkpoint",
     "ihmc_dense_restore", "ihmc_ctx_set_resident", "ihmc_ctx_set_step_fusion", "ihmc_hamiltonian",
     "ihmc_plan_events", "ihmc_fixed_point", "ihmc_chains_group_chains", "ihmc_checkpoint", "ihmc_restore",
-    "ihmc_request_info",
+    "ihmc_request_info", "ihmc_force_noalloc",
 )
 TUNE_RULE, TUNE_MEASURED, TUNE_PINNED = 0, 1, 2
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED, REQ_FAILED = 0, 1, 2, 3, 4
@@ -119,6 +119,7 @@ def load():
     L.ihmc_run_lattice.argtypes = [vp, C.POINTER(_Lattice), C.POINTER(_Run), C.POINTER(_Result)]
     L.ihmc_run_batch.argtypes = [vp, C.c_int32, C.POINTER(_Lattice), C.POINTER(_Run), C.POINTER(_Result)]
     L.ihmc_force.argtypes = [vp, C.POINTER(_Lattice), C.c_int32, _DP, _DP]
+    L.ihmc_force_noalloc.argtypes = [vp, C.POINTER(_Lattice), C.c_int32, vp, vp, vp]
     L.ihmc_action.argtypes = [vp, C.POINTER(_Lattice), C.c_int32, _DP, _DP]
     L.ihmc_integrate.argtypes = [vp, C.POINTER(_Lattice), C.POINTER(_Run), _DP, _DP]
     L.ihmc_philox_normals.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, C.c_int64,
@@ -475,6 +476,14 @@ class Context:
         F = np.zeros_like(psi)
         _check(load().ihmc_force(self.h, C.byref(lat._c(keep)), int(precision), _dp(psi), _dp(F)))
         return F
+
+    def force_noalloc(self, lat: Lattice, psi_ptr, F_ptr, precision=F32, stream=None):
+        """Allocation-free force on caller-owned device arrays (raw device
+        pointers of N state-precision values each), enqueued on `stream` (raw
+        hipStream_t; None or 0: the context stream); not synchronised."""
+        keep = []
+        _check(load().ihmc_force_noalloc(self.h, C.byref(lat._c(keep)), int(precision), C.c_void_p(psi_ptr),
+                                         C.c_void_p(F_ptr), None if stream is None else C.c_void_p(stream)))
 
     def action(self, lat: Lattice, psi, precision=F32):
         keep = []
