@@ -93,6 +93,11 @@ def lib():
         L.orc_constants.argtypes = [lp, dnp, dp]
         L.orc_run_lattice.argtypes = [lp, C.POINTER(_Run), C.POINTER(_Result)]
         L.orc_run_dense.argtypes = [dnp, C.POINTER(_Run), C.POINTER(_Result)]
+        L.orc_phi_force.argtypes = [lp, dnp, dp, dp]
+        L.orc_phi_action.argtypes = [lp, dnp, dp, dp]
+        L.orc_phi_start.argtypes = [lp, dnp, C.POINTER(_Run), dp]
+        L.orc_phi_md.argtypes = [lp, dnp, C.c_int32, C.c_double, dp, dp]
+        L.orc_run_phi.argtypes = [lp, dnp, C.POINTER(_Run), C.POINTER(_Result)]
         _lib = L
     return _lib
 
@@ -244,6 +249,57 @@ def constants(model):
     return tuple(out.tolist())
 
 
+# ---- the inverse (phi) formulation, eq. cosh_in_exponent (Sec. 2)
+
+PHI_ACTION_KEYS = ("S", "m", "abs_m", "m2c", "beta_eps")
+
+
+def phi_force(model, phi):
+    """-dS/dphi = -Kt^-1 phi / J' + tanh(h' + phi) (one CG solve)."""
+    phi = _f64(phi)
+    F = np.empty_like(phi)
+    a, d, keep = _model(model)
+    if lib().orc_phi_force(a, d, _dp(phi), _dp(F)):
+        raise ValueError("invalid model")
+    return F
+
+
+def phi_action(model, phi):
+    """S(phi) and the spin estimators given phi (dict)."""
+    phi = _f64(phi)
+    out = np.empty(5)
+    a, d, keep = _model(model)
+    if lib().orc_phi_action(a, d, _dp(phi), _dp(out)):
+        raise ValueError("invalid model")
+    return dict(zip(PHI_ACTION_KEYS, out.tolist()))
+
+
+def phi_start(model, seed=0, chain_id=0, psi0=None):
+    """The phi chain's starting field sqrt(J') Kt psi0 - h' (psi0 from TAG_INIT unless given)."""
+    r = _Run()
+    r.seed, r.chain_id = int(seed), int(chain_id)
+    p0 = _f64(psi0)
+    r.psi0 = _dp(p0)
+    out = np.empty(model.N)
+    a, d, keep = _model(model)
+    if lib().orc_phi_start(a, d, C.byref(r), _dp(out)):
+        raise ValueError("invalid model")
+    return out
+
+
+def phi_md(model, phi, p, n_md, traj_len=1.0):
+    """One leap-frog trajectory in phi; returns new (phi, p) copies."""
+    phi, p = _f64(phi).copy(), _f64(p).copy()
+    a, d, keep = _model(model)
+    if lib().orc_phi_md(a, d, int(n_md), float(traj_len), _dp(phi), _dp(p)):
+        raise ValueError("invalid model")
+    return phi, p
+
+
+def phi_hamiltonian(model, phi, p):
+    return 0.5 * float(np.dot(p, p)) + phi_action(model, phi)["S"]
+
+
 @dataclass
 class RunResult:
     dH: np.ndarray
@@ -262,8 +318,12 @@ class RunResult:
 
 
 def run(model, n_traj, n_md, traj_len=1.0, seed=0, chain_id=0, psi0=None,
-        replay_accept=None, flip_every=0, integrator=LEAPFROG) -> RunResult:
-    """A full HMC chain (Sec. 3), recording the estimators after each trajectory."""
+        replay_accept=None, flip_every=0, integrator=LEAPFROG, form="psi") -> RunResult:
+    """A full HMC chain (Sec. 3), recording the estimators after each trajectory.
+    form "psi": the substituted field (eq. phi_psi_substitution), psi0 the
+    starting psi; form "phi": the inverse formulation (eq. cosh_in_exponent,
+    leap-frog only, no flips), psi0 then the starting phi (None: the TAG_INIT
+    psi0 mapped by phi = sqrt(J') Kt psi0 - h'); psi_final holds the final phi."""
     N = model.N
     out = {k: np.zeros(n_traj) for k in ("dH", "m", "abs_m", "m2c", "beta_eps", "H_old", "H_new")}
     acc = np.zeros(n_traj, dtype=np.uint8)
@@ -284,8 +344,11 @@ def run(model, n_traj, n_md, traj_len=1.0, seed=0, chain_id=0, psi0=None,
     res.flipped = flp.ctypes.data_as(C.POINTER(C.c_uint8))
     res.psi_final = _dp(psi_final)
     a, d, keep = _model(model)
-    rc = lib().orc_run_lattice(a, C.byref(r), C.byref(res)) if a is not None else \
-        lib().orc_run_dense(d, C.byref(r), C.byref(res))
+    if form == "phi":
+        rc = lib().orc_run_phi(a, d, C.byref(r), C.byref(res))
+    else:
+        rc = lib().orc_run_lattice(a, C.byref(r), C.byref(res)) if a is not None else \
+            lib().orc_run_dense(d, C.byref(r), C.byref(res))
     if rc:
         raise ValueError("invalid model or run parameters")
     return RunResult(accepted=acc, flipped=flp, psi_final=psi_final, acceptance=res.acceptance,

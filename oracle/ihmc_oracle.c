@@ -483,6 +483,152 @@ static int hmc(const model* M, const orc_run* R, orc_result* out) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* The inverse (phi) formulation, before the substitution: eq.               */
+/* cosh_in_exponent gives the phi-dependent action                           */
+/*     S(phi) = 1/(2J') phi.Kt^-1 phi - sum_i log cosh(h'_i + phi_i),        */
+/* whose force -dS/dphi = -Kt^-1 phi / J' + tanh(h' + phi) needs the solve   */
+/* Kt x = phi (CG, to a relative residual of 1e-15) at every evaluation.     */
+/* Observables are the exact expectations given phi: the spins are then      */
+/* independent with E[s_i | phi] = t_i = tanh(h'_i + phi_i) (eq.             */
+/* did_HS_trafo with phi held fixed), so m = sum t / N,                      */
+/* m^2 = ((sum t)^2 - sum t^2 + N) / N^2 and                                 */
+/* beta eps = (-1/2 J' (t.K t - sum_i K_ii t_i^2 + sum_i K_ii) - h'.t) / N. */
+
+typedef struct { double S, sum_t, sum_t2, sum_ht, tKt; } phi_parts;
+
+static phi_parts phi_action(const model* M, const double* phi, double* x) {
+    const int64_t N = M->N;
+    double* t = M->scratch[3];
+    double* Kt = M->scratch[2];
+    cg_solve(M, phi, x);
+    nsum S = {0, 0}, st = {0, 0}, st2 = {0, 0}, sht = {0, 0}, q = {0, 0};
+    for (int64_t i = 0; i < N; ++i) {
+        const double a = phi[i] + (M->hp ? M->hp[i] : 0.0);
+        ns_add(&S, 0.5 * phi[i] * x[i] / M->Jp);
+        ns_add(&S, -logcosh(a));
+        t[i] = tanh(a);
+        ns_add(&st, t[i]);
+        ns_add(&st2, t[i] * t[i]);
+        if (M->hp) ns_add(&sht, M->hp[i] * t[i]);
+    }
+    /* t.K t with K = Kt - C 1 (the diagonal of K itself handled below) */
+    apply_Kt(M, t, Kt);
+    for (int64_t i = 0; i < N; ++i) {
+        double kii = M->dense ? M->K[i * N + i] : 0.0;
+        ns_add(&q, t[i] * (Kt[i] - M->C * t[i]) - kii * t[i] * t[i] + kii);
+    }
+    phi_parts r = { ns_val(&S), ns_val(&st), ns_val(&st2), ns_val(&sht), ns_val(&q) };
+    return r;
+}
+
+static observables phi_estimators(const model* M, const phi_parts* a) {
+    const double N = (double)M->N;
+    observables o;
+    o.m = a->sum_t / N;
+    o.abs_m = fabs(o.m);
+    o.m2c = (a->sum_t * a->sum_t - a->sum_t2 + N) / (N * N);
+    o.beta_eps = (-0.5 * M->Jp * a->tKt - a->sum_ht) / N;
+    return o;
+}
+
+static void phi_force(const model* M, const double* phi, double* F) {
+    const int64_t N = M->N;
+    double* x = M->scratch[2];
+    cg_solve(M, phi, x);
+    for (int64_t i = 0; i < N; ++i)
+        F[i] = -x[i] / M->Jp + tanh(phi[i] + (M->hp ? M->hp[i] : 0.0));
+}
+
+/* Leap-frog (kick-drift-kick) in phi, as md() does in psi. */
+static void phi_md(const model* M, int n_md, double tau, double* phi, double* p) {
+    const int64_t N = M->N;
+    const double eps = tau / n_md;
+    double* F = M->scratch[1];
+    phi_force(M, phi, F);
+    for (int64_t i = 0; i < N; ++i) p[i] += 0.5 * eps * F[i];
+    for (int k = 1; k <= n_md; ++k) {
+        for (int64_t i = 0; i < N; ++i) phi[i] += eps * p[i];
+        phi_force(M, phi, F);
+        const double kick = (k < n_md) ? eps : 0.5 * eps;
+        for (int64_t i = 0; i < N; ++i) p[i] += kick * F[i];
+    }
+}
+
+/* The starting field: phi0 given, or phi0 = sqrt(J') Kt psi0 - h' with psi0
+ * ~ N(0,1) from the TAG_INIT stream (the substitution that links the forms). */
+static void phi_start(const model* M, const orc_run* R, const double* phi0, double* phi) {
+    const int64_t N = M->N;
+    if (phi0) {
+        memcpy(phi, phi0, sizeof(double) * N);
+        return;
+    }
+    double* psi = M->scratch[3];
+    orc_normals(R->seed, R->chain_id, 0u, ORC_TAG_INIT, N, psi);
+    apply_Kt(M, psi, phi);
+    for (int64_t i = 0; i < N; ++i) phi[i] = M->sqJ * phi[i] - (M->hp ? M->hp[i] : 0.0);
+}
+
+static int hmc_phi(const model* M, const orc_run* R, orc_result* out) {
+    const int64_t N = M->N;
+    if (R->n_md < 1 || R->n_traj < 0 || !(R->traj_len > 0) || R->flip_every != 0 || R->integrator != ORC_LEAPFROG)
+        return -1;
+    double* phi = (double*)malloc(sizeof(double) * N);
+    double* trial = (double*)malloc(sizeof(double) * N);
+    double* p = (double*)malloc(sizeof(double) * N);
+    double* x = (double*)malloc(sizeof(double) * N);
+    phi_start(M, R, R->psi0, phi);
+    phi_parts cur = phi_action(M, phi, x);
+    observables ocur = phi_estimators(M, &cur);
+    int64_t n_acc = 0, n_nonfinite = 0;
+    nsum emdh = {0, 0};
+    for (int32_t t = 0; t < R->n_traj; ++t) {
+        orc_normals(R->seed, R->chain_id, (uint32_t)t, ORC_TAG_MOM, N, p);
+        const double H_old = kinetic(p, N) + cur.S;
+        memcpy(trial, phi, sizeof(double) * N);
+        phi_md(M, R->n_md, R->traj_len, trial, p);
+        phi_parts nw = phi_action(M, trial, x);
+        const double H_new = kinetic(p, N) + nw.S;
+        const double dH = H_new - H_old;
+        const int finite = isfinite(dH);
+        int acc;
+        if (!finite) ++n_nonfinite;
+        if (R->replay_accept) {
+            acc = R->replay_accept[t] != 0;
+        } else {
+            const double r = orc_uniform(R->seed, R->chain_id, (uint32_t)t, ORC_TAG_ACC);
+            acc = finite && (dH <= 0.0 || r < exp(-dH));
+        }
+        if (finite) ns_add(&emdh, exp(-dH));
+        if (acc) {
+            double* tmp = phi; phi = trial; trial = tmp;
+            cur = nw;
+            ocur = phi_estimators(M, &cur);
+            ++n_acc;
+        }
+        if (out) {
+            if (out->dH) out->dH[t] = dH;
+            if (out->H_old) out->H_old[t] = H_old;
+            if (out->H_new) out->H_new[t] = H_new;
+            if (out->accepted) out->accepted[t] = (uint8_t)acc;
+            if (out->flipped) out->flipped[t] = 0;
+            if (out->m) out->m[t] = ocur.m;
+            if (out->abs_m) out->abs_m[t] = ocur.abs_m;
+            if (out->m2c) out->m2c[t] = ocur.m2c;
+            if (out->beta_eps) out->beta_eps[t] = ocur.beta_eps;
+        }
+    }
+    if (out) {
+        if (out->psi_final) memcpy(out->psi_final, phi, sizeof(double) * N);
+        out->acceptance = R->n_traj ? (double)n_acc / R->n_traj : 0.0;
+        int64_t nf = R->n_traj - n_nonfinite;
+        out->mean_exp_minus_dH = nf ? ns_val(&emdh) / (double)nf : 0.0;
+        out->n_nonfinite = n_nonfinite;
+    }
+    free(phi); free(trial); free(p); free(x);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Exported entry points.                                                    */
 
 static int64_t lattice_sites(const orc_lattice* lat) {
@@ -594,6 +740,53 @@ int orc_run_dense(const orc_dense* d, const orc_run* run, orc_result* res) {
     model M;
     if (dense_model(&M, d)) { model_free(&M); return -1; }
     int rc = hmc(&M, run, res);
+    model_free(&M);
+    return rc;
+}
+
+/* The inverse (phi) formulation: force, action with the observables, the
+ * starting field and whole chains (leap-frog only, no sign flip). */
+int orc_phi_force(const orc_lattice* lat, const orc_dense* d, const double* phi, double* F) {
+    model M;
+    if (with_model(lat, d, &M)) { model_free(&M); return -1; }
+    phi_force(&M, phi, F);
+    model_free(&M);
+    return 0;
+}
+
+/* out[0] = S(phi), out[1] = m, out[2] = |m|, out[3] = m^2, out[4] = beta*eps. */
+int orc_phi_action(const orc_lattice* lat, const orc_dense* d, const double* phi, double* out) {
+    model M;
+    if (with_model(lat, d, &M)) { model_free(&M); return -1; }
+    double* x = (double*)malloc(sizeof(double) * M.N);
+    phi_parts a = phi_action(&M, phi, x);
+    observables o = phi_estimators(&M, &a);
+    out[0] = a.S; out[1] = o.m; out[2] = o.abs_m; out[3] = o.m2c; out[4] = o.beta_eps;
+    free(x);
+    model_free(&M);
+    return 0;
+}
+
+int orc_phi_start(const orc_lattice* lat, const orc_dense* d, const orc_run* run, double* phi) {
+    model M;
+    if (with_model(lat, d, &M)) { model_free(&M); return -1; }
+    phi_start(&M, run, run->psi0, phi);
+    model_free(&M);
+    return 0;
+}
+
+int orc_phi_md(const orc_lattice* lat, const orc_dense* d, int32_t n_md, double traj_len, double* phi, double* p) {
+    model M;
+    if (with_model(lat, d, &M) || n_md < 1) { model_free(&M); return -1; }
+    phi_md(&M, n_md, traj_len, phi, p);
+    model_free(&M);
+    return 0;
+}
+
+int orc_run_phi(const orc_lattice* lat, const orc_dense* d, const orc_run* run, orc_result* res) {
+    model M;
+    if (with_model(lat, d, &M)) { model_free(&M); return -1; }
+    int rc = hmc_phi(&M, run, res);
     model_free(&M);
     return rc;
 }
