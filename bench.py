@@ -600,6 +600,73 @@ def bench_serving(args):
     print(json.dumps(line), flush=True)
 
 
+def run_phi_ab(args, K=20, W=2):
+    """The paper's substitution measured (Sec. 2): the same chains run in the
+    inverse formulation (eq. cosh_in_exponent, a CG solve of Kt per force
+    evaluation) and in the substituted psi form (eq. phi_psi_substitution), both
+    FP64 and LDS-resident, one workgroup per chain: 512 2D 32^2 tori at beta_c
+    (C = 4.1) and 512 3D 11^3 tori at beta = 0.2216544 (C = 6.1), h = 0,
+    n_md = 10.  Returns site-MD-steps/s of each form and their ratio, CG
+    iterations per force evaluation, acceptance, and <beta*eps> over the timed
+    trajectories (from the same start; far too few to thermalise at these
+    couplings, so the two forms' values are not comparable)."""
+    import numpy as np
+    import torch
+    from paper_1912_03278_amd import ihmc, inputs
+
+    pts = [((32, 32), inputs.BETA_C_2D, 4.1), ((11, 11, 11), inputs.BETA_3D, 6.1)]
+    R = args.phi_chains
+    lats, specs = [], []
+    for L, beta, C in pts:
+        for r in range(R):
+            lats.append(ihmc.Lattice(L, beta=beta, C=C))
+            specs.append((L, beta, C))
+    n_md = 10
+    out = {"workload": f"{R} 2D 32^2 tori at beta_c (C=4.1) and {R} 3D 11^3 tori at beta=0.2216544 (C=6.1), "
+                       f"h=0, n_md={n_md}, FP64 state, LDS-resident (one workgroup per chain); one step = one "
+                       "trajectory of every chain", "steps": K, "warmup": W}
+    work = sum(int(math.prod(L)) * n_md for L, _, _ in specs)
+    for name, form in (("psi", ihmc.FORM_PSI), ("phi", ihmc.FORM_PHI)):
+        ctx = ihmc.Context(device=0, arena_bytes=1 << 30)
+        runs = [ihmc.Run(n_md=n_md, n_traj=W + K, precision=ihmc.F64, seed=21, chain_id=i, form=form)
+                for i in range(len(lats))]
+        ch = ihmc.Chains(ctx, lats, runs)
+        ch.advance(W)
+        ctx.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch.advance(K)
+        ctx.sync()
+        dt = time.perf_counter() - t0
+        res = [ch.result(i, want_psi=False) for i in range(len(lats))]
+        ch.close()
+        ctx.close()
+        be = {}
+        for k, (L, _, _) in enumerate(pts):
+            vals = np.array([r["beta_eps"][W:] for r in res[k * R:(k + 1) * R]])
+            be["x".join(map(str, L))] = [float(vals.mean()), float(vals.mean(axis=1).std() / math.sqrt(R))]
+        row = {"value": K * work / dt, "unit": "site-MD-steps/s", "ms_per_step": 1000.0 * dt / K,
+               "acceptance": float(np.mean([r["acceptance"] for r in res])),
+               "beta_eps_mean_err_unthermalised": be}
+        if form == ihmc.FORM_PHI:
+            cg = sum(r["cg_iterations"] for r in res)
+            row["cg_iterations_per_force"] = cg / (len(res) * (W + K) * (n_md + 1))
+        out[name] = row
+        print(f"bench: {name} form {row['value']:.3g} site-MD-steps/s", file=sys.stderr, flush=True)
+    out["psi_over_phi"] = out["psi"]["value"] / out["phi"]["value"]
+    return out
+
+
+def bench_phi(args):
+    ab = run_phi_ab(args, K=args.steps, W=args.warmup)
+    line = {"metric": "site-MD-steps/s", "value": ab["psi"]["value"], "unit": "site-MD-steps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ab["psi"]["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "phi/psi A/B: " + ab["workload"]}, "phi_form_ab": ab, "roofline": None,
+            "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+
+
 def bench_tau(args):
     """Critical slowing down measured on the batched engine (Sec. 4): tau_int of
     |m| against N at the critical coupling in 2D and 3D, with the paper's fits
@@ -796,6 +863,9 @@ def bench_headline(args):
                                                          "roofline", "kernels", "chains", "cpu_baseline")}
         if "extra_streaming_point" in lg:
             line["extra_streaming_point"] = lg["extra_streaming_point"]
+    if args.extras in ("all", "phi"):
+        print("bench: extra key: phi/psi form A/B", file=sys.stderr, flush=True)
+        line["extra_phi_form_ab"] = run_phi_ab(args)
     if args.extras in ("all", "serving"):
         print("bench: extra key: serving", file=sys.stderr, flush=True)
         sv = run_serving(args)
@@ -810,11 +880,11 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "batched", "large", "dense", "serving", "small", "tau"],
+                    choices=["headline", "batched", "large", "dense", "serving", "small", "tau", "phi"],
                     help="headline (default): the batched workload with the large chains, the streaming point and "
                          "serving as extra keys; batched: 4096 uneven chains only; large: the 1024^2 + 128^3 single "
                          "chains; dense: 256 chains of an N=4096 all-to-all model; serving: Poisson request arrivals")
-    ap.add_argument("--extras", default="all", choices=["all", "large", "serving", "none"],
+    ap.add_argument("--extras", default="all", choices=["all", "large", "serving", "phi", "none"],
                     help="headline: which extra keys to run")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
     ap.add_argument("--serve-duration", type=float, default=60.0, help="serving: seconds of arrivals")
@@ -826,6 +896,7 @@ def main():
     ap.add_argument("--no-streaming-point", action="store_true", help="large: skip the extra 8192^2 point")
     ap.add_argument("--timing-reps", type=int, default=100)
     ap.add_argument("--tau-chains", type=int, default=128, help="tau: replicas per scan point")
+    ap.add_argument("--phi-chains", type=int, default=512, help="phi: chains per lattice shape of the A/B")
     ap.add_argument("--resident", default="on", choices=["on", "off"],
                     help="chains that fit one workgroup's LDS run whole trajectories per launch (on) or the "
                          "tiled passes (off); results are bit-identical")
@@ -847,6 +918,10 @@ def main():
         return bench_headline(args) if args.workload == "headline" else bench_batched(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "phi":
+        args.steps = 20 if args.steps is None else args.steps
+        args.warmup = 2 if args.warmup is None else args.warmup
+        return bench_phi(args)
     if args.workload == "tau":
         args.steps = 8000 if args.steps is None else args.steps
         args.warmup = 1000 if args.warmup is None else args.warmup

@@ -53,6 +53,12 @@ extern "C" {
 #define IHMC_LEAPFROG 0 /* kick-drift-kick leap-frog (Sec. 3) */
 #define IHMC_OMELYAN 1  /* second-order minimum-norm integrator, named in Sec. 3 */
 
+/* The field a chain samples (Sec. 2): */
+#define IHMC_FORM_PSI 0 /* psi of eq. phi_psi_substitution: no inverse of Kt (the hot path) */
+#define IHMC_FORM_PHI 1 /* phi of eq. cosh_in_exponent: a CG solve of Kt per force evaluation;
+                           the A/B baseline of the substitution (FP64 leap-frog lattice chains of
+                           at most 1453 sites, 1272 with a per-site field; no flips) */
+
 #define IHMC_TAG_INIT 1u /* Philox stream tags (counter word 3) */
 #define IHMC_TAG_MOM 2u
 #define IHMC_TAG_ACC 3u
@@ -122,7 +128,13 @@ typedef struct {
  *               open): the summary (acceptance, mean exp(-dH), non-finite
  *               count) covers trajectories n_therm, n_therm + 1, ... only;
  *               every trajectory is still recorded in the series.  0 (a
- *               zero-initialised struct) counts them all. */
+ *               zero-initialised struct) counts them all.
+ *   form        IHMC_FORM_PSI (0) or IHMC_FORM_PHI.  In the phi form, psi0 is
+ *               the starting phi (NULL: phi0 = sqrt(J') Kt psi0 - h' with psi0
+ *               the TAG_INIT normals, the substitution that links the forms),
+ *               psi_final the final phi, and the records hold the spin
+ *               expectations given phi (m = mean tanh(h' + phi), m^2 and beta*eps
+ *               likewise, no bias correction needed). */
 typedef struct {
   int32_t n_md;
   int32_t n_traj;
@@ -135,6 +147,8 @@ typedef struct {
   uint64_t chain_id;
   const double* psi0;
   const uint8_t* replay_accept;
+  int32_t form;
+  int32_t reserved;
 } ihmc_run;
 
 /* Per-chain results.  Series are indexed by trajectory; after trajectory t
@@ -149,6 +163,7 @@ typedef struct {
   double mean_exp_minus_dH; /* over trajectories with finite dH */
   int64_t n_nonfinite;      /* trajectories with a non-finite or out-of-range H term */
   int64_t n_traj_done;
+  int64_t cg_iterations;    /* phi form: CG iterations of the set-up and all trajectories (0 for psi) */
 } ihmc_result;
 
 /* ---- context ------------------------------------------------------------ */

@@ -13,8 +13,12 @@ namespace ihmc {
 // Metropolis decision and record, run by one thread of the last block of a LAST
 // pass once the block has gathered the chain's accumulators (`sum`, `bad`).
 // Returns the record's flags (REC_ACCEPT, REC_FLIP, REC_NONFINITE).
+//
+// In the phi form the estimator slots hold the sums of t = tanh(h' + phi):
+// T_PSI sum t, T_PSIH sum h' t, T_UT t.K t, and `t2` is sum t^2 of the
+// proposal; the records then hold the spin expectations given phi.
 __device__ __forceinline__ uint32_t finalize_trajectory(const ChainDev& cd, ChainState* st, int last_buf,
-                                                        const u128* sum, uint32_t bad) {
+                                                        const u128* sum, uint32_t bad, double t2 = 0.0) {
   const int t = st->traj;
   const u128 S_old{st->S_lo, st->S_hi};
   const u128 H_old = add128(sum[T_K0], S_old);
@@ -44,6 +48,7 @@ __device__ __forceinline__ uint32_t finalize_trajectory(const ChainDev& cd, Chai
     st->sum_psi = fixed_to_double(sum[T_PSI]);
     st->sum_psih = fixed_to_double(sum[T_PSIH]);
     st->sum_ut = fixed_to_double(sum[T_UT]);
+    st->sum_t2 = t2;
     st->cur = last_buf;
     st->sign = 1;
     if (counted) st->n_acc += 1;
@@ -75,11 +80,19 @@ __device__ __forceinline__ uint32_t finalize_trajectory(const ChainDev& cd, Chai
     rec.dH = dH;
     rec.H_old = fixed_to_double(H_old);
     rec.H_new = fixed_to_double(H_new);
-    rec.m = (st->sum_psi / cd.sqJ - cd.c_m / cd.Jp) / N;
-    rec.abs_m = fabs(rec.m);
-    rec.m2c = rec.m * rec.m - cd.c_v / (N * N * cd.Jp);
-    rec.beta_eps = 0.5 * cd.C * cd.Jp + cd.c_e / (2.0 * N * cd.Jp) - st->sum_psih / (2.0 * N * cd.sqJ) -
-                   cd.sqJ / (2.0 * N) * st->sum_ut;
+    if (cd.form == FORM_PHI) {
+      // E[s_i | phi] = t_i, spins independent given phi
+      rec.m = st->sum_psi / N;
+      rec.abs_m = fabs(rec.m);
+      rec.m2c = (st->sum_psi * st->sum_psi - st->sum_t2 + N) / (N * N);
+      rec.beta_eps = (-0.5 * cd.Jp * st->sum_ut - st->sum_psih) / N;
+    } else {
+      rec.m = (st->sum_psi / cd.sqJ - cd.c_m / cd.Jp) / N;
+      rec.abs_m = fabs(rec.m);
+      rec.m2c = rec.m * rec.m - cd.c_v / (N * N * cd.Jp);
+      rec.beta_eps = 0.5 * cd.C * cd.Jp + cd.c_e / (2.0 * N * cd.Jp) - st->sum_psih / (2.0 * N * cd.sqJ) -
+                     cd.sqJ / (2.0 * N) * st->sum_ut;
+    }
     rec.flags = flags;
     rec.pad = 0u;
     cd.rec[t] = rec;
@@ -90,8 +103,9 @@ __device__ __forceinline__ uint32_t finalize_trajectory(const ChainDev& cd, Chai
   return flags;
 }
 
-__device__ __forceinline__ void finalize_measure(ChainState* st, const u128* sum, uint32_t bad) {
+__device__ __forceinline__ void finalize_measure(ChainState* st, const u128* sum, uint32_t bad, double t2 = 0.0) {
   st->cur_bad = bad ? 1 : 0;
+  st->sum_t2 = t2;
   st->S_lo = sum[T_S].lo;
   st->S_hi = sum[T_S].hi;
   st->sum_psi = fixed_to_double(sum[T_PSI]);

@@ -253,6 +253,7 @@ int DenseChains::build(const ihmc_dense& md, int32_t n, const ihmc_run* runs, in
     if (r.n_therm < 0) return set_error(IHMC_E_INVAL, "chain %d: n_therm must be >= 0", i);
     if (r.precision != IHMC_F32)
       return set_error(IHMC_E_UNSUPPORTED, "chain %d: dense chains keep FP32 state (precision 4)", i);
+    if (r.form != 0) return set_error(IHMC_E_UNSUPPORTED, "chain %d: dense chains run the psi form only", i);
     if (r.n_md != r0.n_md || r.integrator != r0.integrator || r.traj_len != r0.traj_len)
       return set_error(IHMC_E_INVAL, "chain %d: n_md, integrator and traj_len must agree across dense chains", i);
   }

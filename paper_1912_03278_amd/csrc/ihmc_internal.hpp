@@ -9,6 +9,11 @@ enum : uint32_t { TAG_INIT = 1u, TAG_MOM = 2u, TAG_ACC = 3u, TAG_FLIP = 4u };
 
 enum Integrator : int32_t { LEAPFROG = 0, OMELYAN = 1 };
 
+// Field of the chain: psi of the substituted action (eq. phi_psi_substitution,
+// the hot path) or phi of the inverse formulation (eq. cosh_in_exponent, whose
+// force needs a linear solve per evaluation; the A/B baseline).
+enum Form : int32_t { FORM_PSI = 0, FORM_PHI = 1 };
+
 // Omelyan-Mryglod-Folk second-order minimum-norm parameter.
 constexpr double kOmelyanLambda = 0.1931833275037836;
 
@@ -51,6 +56,8 @@ struct ChainState {
   int32_t cur_bad;  // the accepted field itself has such a term (e.g. a NaN start)
   int64_t n_acc, n_nonfinite;
   double sum_exp_mdh;
+  double sum_t2;  // phi form: sum of tanh^2(h' + phi) of phi_cur
+  int64_t n_cg;   // phi form: CG iterations so far
 };
 
 // Immutable per-chain parameters (FP64 constants; kernels round what they need).
@@ -72,6 +79,7 @@ struct ChainDev {
   int32_t p_given;       // first pass reads p instead of drawing it (diagnostic)
   int32_t write_p_last;  // last pass stores the final momenta (diagnostic)
   int32_t n_therm;       // trajectories before this index stay out of the summary counters
+  int32_t form;          // FORM_PSI or FORM_PHI
   void* psi;             // rotating field buffers of NP values: LAT_BUFFERS (lattice) or 3 (dense)
   void* p;               // NP state values
   const void* b;         // NP state values h'/sqrt(J') (per-site field) or null

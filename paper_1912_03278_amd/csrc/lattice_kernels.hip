@@ -1242,8 +1242,9 @@ TileShape tile_shape(int precision, int ndim, int cls) {
 
 hipError_t launch_lattice_pass(int precision, int ndim, int cls, int mode, const ChainDev* chains,
                                const Tile* tiles, int n_tiles, int j, int k, hipStream_t s) {
-  if (cls == RESIDENT_CLASS) {  // whole trajectories only; the set-up measurement is n_traj = 0
+  if (cls == RESIDENT_CLASS || cls == RESIDENT_PHI_CLASS) {  // whole trajectories only; set-up is n_traj = 0
     if (mode != PASS_MEASURE) return hipErrorInvalidValue;
+    if (cls == RESIDENT_PHI_CLASS) return launch_lattice_resident_phi(ndim, chains, tiles, n_tiles, 0, s);
     return launch_lattice_resident(precision, ndim, chains, tiles, n_tiles, 0, s);
   }
   if (precision == 4) {

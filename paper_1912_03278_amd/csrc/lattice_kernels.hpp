@@ -29,6 +29,13 @@ TileShape tile_shape(int precision, int ndim, int cls);
 // (lattice_resident): their launch group has this tile class, and one Tile
 // entry per chain.
 constexpr int RESIDENT_CLASS = -1;
+// Chains of the inverse (phi) formulation run whole trajectories per launch
+// too (lattice_resident_phi, FP64): their own launch group.
+constexpr int RESIDENT_PHI_CLASS = -2;
+// Largest phi-form chain (sites) that fits one workgroup's LDS.
+int resident_phi_max_sites(bool site_field);
+hipError_t launch_lattice_resident_phi(int ndim, const ChainDev* chains, const Tile* tiles, int n_chains, int n_traj,
+                                       hipStream_t s);
 // Largest chain (sites) of a state precision (4 or 8 bytes) that fits, with or
 // without a per-site field.
 int resident_max_sites(int precision, bool site_field);

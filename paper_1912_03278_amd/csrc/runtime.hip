@@ -111,6 +111,30 @@ __global__ void k_init_psi(const ChainDev* cds, int ci, const double* psi0) {
   psi[stored_index(cd, i)] = psi0 ? (T)psi0[i] : (T)normal_at(cd, 0u, TAG_INIT, i);
 }
 
+// Starting field of a phi-form chain without a given one: the substitution
+// phi0 = sqrt(J') Kt psi0 - h' (Sec. 2) of the TAG_INIT normals psi0 that a
+// psi-form chain of the same seed starts from (FP64 state).
+__global__ void k_init_phi(const ChainDev* cds, int ci) {
+  const ChainDev& cd = cds[ci];
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= cd.N) return;
+  const int L0 = cd.L0, L1 = cd.L1, L2 = cd.L2;
+  const int x = (int)(i % L0), y = (int)((i / L0) % L1), z = (int)(i / ((int64_t)L0 * L1));
+  auto at = [&](int a, int b, int c) { return normal_at(cd, 0u, TAG_INIT, a + (int64_t)L0 * (b + (int64_t)L1 * c)); };
+  double u = cd.C * at(x, y, z);
+  u += at((x + 1) % L0, y, z);
+  u += at((x + L0 - 1) % L0, y, z);
+  u += at(x, (y + 1) % L1, z);
+  u += at(x, (y + L1 - 1) % L1, z);
+  if (cd.ndim == 3) {
+    u += at(x, y, (z + 1) % L2);
+    u += at(x, y, (z + L2 - 1) % L2);
+  }
+  const int64_t k = stored_index(cd, i);
+  const double hp = cd.h_kind == 2 ? cd.hp[k] : cd.hp0;
+  ((double*)cd.psi)[k] = cd.sqJ * u - hp;
+}
+
 // Logical <-> stored layout of one field (p or F).
 template <typename T>
 __global__ void k_import(const ChainDev* cds, int ci, T* dst, const double* src) {
@@ -282,22 +306,25 @@ void describe_chain(const ihmc_lattice& l, const ihmc_run& r, int flags, int cls
   c.p_given = (flags & BUILD_P_GIVEN) ? 1 : 0;
   c.write_p_last = (flags & BUILD_WRITE_P) ? 1 : 0;
   c.n_therm = r.n_therm;
+  c.form = r.form;
   c.tile_cls = cls;
   c.n_tiles = chain_tile_count(c);
 }
 
-int choose_class(ihmc_ctx* ctx, const ihmc_lattice& l, int precision, int flags) {
+int choose_class(ihmc_ctx* ctx, const ihmc_lattice& l, int precision, int flags, int form) {
+  if (form == FORM_PHI) return RESIDENT_PHI_CLASS;
   const int64_t N = lattice_sites(l);
   const bool site_field = !(l.h_len == 0 || l.h_len == 1);
   const int64_t fit = resident_max_sites(precision, site_field);
   const int64_t lim = ctx->resident_sites < 0 ? fit : std::min(fit, ctx->resident_sites);
+  (void)flags;
   if (flags == 0 && N <= lim) return RESIDENT_CLASS;
   return ctx->tune.class_for(tile_key(l, precision));
 }
 
 // Tiles of one chain in the tile shape of its launch group (one per resident chain).
 uint32_t chain_tile_count(const ChainDev& c) {
-  if (c.tile_cls == RESIDENT_CLASS) return 1u;
+  if (c.tile_cls < 0) return 1u;  // LDS-resident: one workgroup per chain
   const TileShape ts = tile_shape(c.precision, c.ndim, c.tile_cls);
   const uint32_t nz = c.ndim == 3 ? (uint32_t)((c.L2 + ts.bz - 1) / ts.bz) : 1u;
   return nz * (uint32_t)((c.L1 + ts.by - 1) / ts.by) * (uint32_t)((c.L0 + ts.bx - 1) / ts.bx);
@@ -319,7 +346,7 @@ void plan_groups(const std::vector<ChainDev>& cd, const std::vector<int>& member
     g.cls = std::get<2>(kv.first);
     g.order = kv.second;
     std::stable_sort(g.order.begin(), g.order.end(), [&](int a, int b) { return cd[a].n_pass > cd[b].n_pass; });
-    const bool resident = (g.cls == RESIDENT_CLASS);
+    const bool resident = (g.cls < 0);
     g.pair = fuse_steps && g.ndim == 2 && !resident;
     const TileShape ts = resident ? TileShape{1, 1, 1} : tile_shape(g.prec, g.ndim, g.cls);
     g.tile_off = (int)tiles.size() - base;
@@ -379,6 +406,15 @@ int validate(const ihmc_lattice& l, const ihmc_run& r, int idx) {
   if (r.precision != 4 && r.precision != 8) return set_error(IHMC_E_INVAL, "chain %d: precision must be 4 or 8", idx);
   if (r.flip_every < 0) return set_error(IHMC_E_INVAL, "chain %d: flip_every must be >= 0", idx);
   if (r.n_therm < 0) return set_error(IHMC_E_INVAL, "chain %d: n_therm must be >= 0", idx);
+  if (r.form != FORM_PSI && r.form != FORM_PHI) return set_error(IHMC_E_INVAL, "chain %d: unknown form", idx);
+  if (r.form == FORM_PHI) {
+    if (r.precision != 8 || r.integrator != LEAPFROG || r.flip_every != 0)
+      return set_error(IHMC_E_UNSUPPORTED, "chain %d: the phi form runs FP64 leap-frog chains without flips", idx);
+    const bool site_field = !(l.h_len == 0 || l.h_len == 1);
+    if (N > resident_phi_max_sites(site_field))
+      return set_error(IHMC_E_UNSUPPORTED, "chain %d: the phi form takes chains of at most %d sites", idx,
+                       resident_phi_max_sites(site_field));
+  }
   return IHMC_OK;
 }
 
@@ -534,7 +570,7 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
     int rc = validate(l, r, i);
     if (rc) return rc;
     ChainDev& c = cd[i];
-    describe_chain(l, r, flags, choose_class(ctx, l, r.precision, flags), c);
+    describe_chain(l, r, flags, choose_class(ctx, l, r.precision, flags, r.form), c);
     const int64_t N = c.N, NP = c.NP;
     const int64_t pb = r.precision;
     c.psi = dalloc((uint64_t)LAT_BUFFERS * NP * pb);
@@ -656,7 +692,8 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
       HIPCHK(hipMemcpyAsync(t, r.psi0, 8 * N, hipMemcpyHostToDevice, s), "psi0 upload");
       src = t;
     }
-    if (cd[i].precision == 4) k_init_psi<float><<<nblk(N), 256, 0, s>>>(d_cd, i, src);
+    if (cd[i].form == FORM_PHI && !src) k_init_phi<<<nblk(N), 256, 0, s>>>(d_cd, i);
+    else if (cd[i].precision == 4) k_init_psi<float><<<nblk(N), 256, 0, s>>>(d_cd, i, src);
     else k_init_psi<double><<<nblk(N), 256, 0, s>>>(d_cd, i, src);
     HIPCHK(hipGetLastError(), "k_init_psi");
   }
@@ -668,6 +705,14 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
   cleanup();
   if (e != hipSuccess) return hip_fail(ctx, e, "chain set-up");
   return IHMC_OK;
+}
+
+// One launch running n_traj whole trajectories (0: the set-up measurement) of
+// every chain of an LDS-resident group.
+hipError_t launch_resident_group(const Group& g, const ChainDev* d_cd, const Tile* t, int n, int n_traj,
+                                 hipStream_t s) {
+  if (g.cls == RESIDENT_PHI_CLASS) return launch_lattice_resident_phi(g.ndim, d_cd, t, n, n_traj, s);
+  return launch_lattice_resident(g.prec, g.ndim, d_cd, t, n, n_traj, s);
 }
 
 // Enqueue target of a round plan: the HIP stream operations, or (dry) a count
@@ -702,7 +747,7 @@ struct RoundSink {
     return pool ? launch_lattice_pass(g.prec, g.ndim, g.cls, mode, d_cd, t, n, j, k, st) : hipSuccess;
   }
   hipError_t resident(const Group& g, const ChainDev* d_cd, const Tile* t, int n, hipStream_t st) {
-    return pool ? launch_lattice_resident(g.prec, g.ndim, d_cd, t, n, 1, st) : hipSuccess;
+    return pool ? launch_resident_group(g, d_cd, t, n, 1, st) : hipSuccess;
   }
 };
 
@@ -724,7 +769,7 @@ static hipError_t round_plan(const std::vector<Group>& groups, const Tile* d_til
     hipStream_t gs = sk.pool ? side[2 * gi] : nullptr, ls = sk.pool ? side[2 * gi + 1] : nullptr;
     if ((e = sk.wait(gs, fork)) != hipSuccess) return e;
     const Tile* base = d_tiles + g.tile_off;
-    if (g.cls == RESIDENT_CLASS) {  // one launch runs the whole trajectory of every chain of the group
+    if (g.cls < 0) {  // one launch runs the whole trajectory of every chain of the group
       if ((e = sk.resident(g, d_cd, base, g.tile_begin.back(), gs)) != hipSuccess) return e;
       if ((e = sk.join(gs, s)) != hipSuccess) return e;
       continue;
@@ -810,7 +855,7 @@ int Chains::advance(int32_t n_traj) {
   hipStream_t s = ctx->stream;
   if (n_traj == 0) return IHMC_OK;
   bool all_resident = true;
-  for (auto& g : groups) all_resident = all_resident && g.cls == RESIDENT_CLASS;
+  for (auto& g : groups) all_resident = all_resident && g.cls < 0;
   if (all_resident) {  // every chain in LDS: one launch per group runs all n_traj trajectories,
                        // the groups side by side on their own streams
     const bool fork = groups.size() > 1;
@@ -819,7 +864,7 @@ int Chains::advance(int32_t n_traj) {
       const Group& g = groups[gi];
       hipStream_t gs = fork ? side[2 * gi] : s;
       if (fork) HIPCHK(hipStreamWaitEvent(gs, events[0], 0), "fork wait");
-      HIPCHK(launch_lattice_resident(g.prec, g.ndim, d_cd, d_tiles + g.tile_off, g.tile_begin.back(), n_traj, gs),
+      HIPCHK(launch_resident_group(g, d_cd, d_tiles + g.tile_off, g.tile_begin.back(), n_traj, gs),
              "resident launch");
       if (fork) {
         HIPCHK(hipEventRecord(events[1 + gi], gs), "join");
@@ -896,6 +941,7 @@ int result_from_device(ihmc_ctx* ctx, const ChainDev& c, const ChainDev* d_cd, i
   const int64_t nf = counted - st.n_nonfinite;
   out->mean_exp_minus_dH = nf > 0 ? st.sum_exp_mdh / (double)nf : 0.0;
   out->n_nonfinite = st.n_nonfinite;
+  out->cg_iterations = st.n_cg;
   if (out->psi_final) {
     double* t = (double*)ctx->arena.alloc(8 * (uint64_t)c.N);
     if (!t) return set_error(IHMC_E_NOMEM, "arena exhausted (export)");
@@ -928,7 +974,7 @@ struct CkptHeader {
   int64_t N, NP;
   int32_t precision, n_pass, integrator, flip_every;
   uint32_t chain_id, seed_lo, seed_hi;
-  int32_t h_kind;
+  int32_t h_kind, form, pad0;
   double C, sqJ, Jp, b0, hp0, eps, c_m, c_e, c_v;
   uint64_t field_hash;  // FNV-1a of the per-site h' in site order (0 without one)
   uint64_t variant;     // path-specific form of the force (dense: limb products)
@@ -952,6 +998,7 @@ void fill_identity(const ChainDev& c, uint64_t field_hash, uint64_t variant, Ckp
   h.seed_lo = c.seed_lo;
   h.seed_hi = c.seed_hi;
   h.h_kind = c.h_kind;
+  h.form = c.form;
   h.C = c.C;
   h.sqJ = c.sqJ;
   h.Jp = c.Jp;
@@ -1374,8 +1421,9 @@ extern "C" int ihmc_plan_events(int32_t n, const ihmc_lattice* lats, const ihmc_
     const bool site_field = !(l.h_len == 0 || l.h_len == 1);
     const int64_t fit = resident_max_sites(runs[i].precision, site_field);
     const int64_t lim = resident_sites < 0 ? fit : std::min(fit, resident_sites);
-    const int cls = lattice_sites(l) <= lim ? RESIDENT_CLASS
-                                            : tile_class(l.ndim, l.L[0], l.ndim == 3 ? l.L[2] : 1);
+    const int cls = runs[i].form == FORM_PHI ? RESIDENT_PHI_CLASS
+                    : lattice_sites(l) <= lim ? RESIDENT_CLASS
+                                              : tile_class(l.ndim, l.L[0], l.ndim == 3 ? l.L[2] : 1);
     describe_chain(l, runs[i], 0, cls, cd[i]);
   }
   std::vector<int> members((size_t)n);
@@ -1490,7 +1538,7 @@ extern "C" int ihmc_chains_time_pass(ihmc_chains* ch, int32_t group, int32_t mod
     return set_error(IHMC_E_INVAL, "only FIRST, MIDDLE, LAST and PAIR passes can be timed");
   if (reps < 1) return set_error(IHMC_E_INVAL, "reps must be >= 1");
   const Group& g = c->groups[group];
-  if (g.cls == RESIDENT_CLASS)
+  if (g.cls < 0)
     return set_error(IHMC_E_UNSUPPORTED, "group %d runs LDS-resident whole trajectories, not passes", group);
   if (mode == PASS_PAIR && g.ndim != 2)
     return set_error(IHMC_E_UNSUPPORTED, "group %d: two-step launches are 2D only", group);

@@ -83,7 +83,7 @@ TileKey tile_key(const ihmc_lattice& l, int precision);
 // Launch class of a new chain: RESIDENT_CLASS when the context allows and the
 // chain fits one workgroup's LDS (and no diagnostic flag is set), else the
 // tuning table's tile class (or the built-in rule's).
-int choose_class(ihmc_ctx* ctx, const ihmc_lattice& l, int precision, int flags);
+int choose_class(ihmc_ctx* ctx, const ihmc_lattice& l, int precision, int flags, int form = 0);
 // JSON form of the table; load merges (entries replace equal keys).
 int tune_save(TuneTable& t, const char* path);
 int tune_load(TuneTable& t, const char* path);
@@ -126,6 +126,8 @@ hipError_t launch_field_setup(const ChainDev* d_cd, int ci, const double* h, dou
 hipError_t launch_field_cg(ChainDev* d_cd, const int* which, int n, double* work, const int64_t* woff,
                            hipStream_t s);
 hipError_t launch_measure(const std::vector<Group>& groups, const Tile* d_tiles, const ChainDev* d_cd, hipStream_t s);
+hipError_t launch_resident_group(const Group& g, const ChainDev* d_cd, const Tile* t, int n, int n_traj,
+                                 hipStream_t s);
 
 struct Chains {
   ihmc_ctx* ctx = nullptr;

@@ -21,6 +21,7 @@ STATUS = {-1: "IHMC_E_INVAL", -2: "IHMC_E_NOMEM", -3: "IHMC_E_AGAIN", -4: "IHMC_
           -5: "IHMC_E_CANCELLED", -6: "IHMC_E_UNSUPPORTED"}
 F32, F64 = 4, 8
 LEAPFROG, OMELYAN = 0, 1
+FORM_PSI, FORM_PHI = 0, 1  # the substituted field (the hot path) / the inverse formulation (A/B baseline)
 FIRST, MIDDLE, LAST, PAIR = 0, 1, 2, 5  # pass kinds of Chains.time_pass
 TAG_INIT, TAG_MOM, TAG_ACC, TAG_FLIP = 1, 2, 3, 4
 
@@ -63,7 +64,8 @@ class _Run(C.Structure):
     _fields_ = [("n_md", C.c_int32), ("n_traj", C.c_int32), ("traj_len", C.c_double),
                 ("integrator", C.c_int32), ("flip_every", C.c_int32), ("precision", C.c_int32),
                 ("n_therm", C.c_int32), ("seed", C.c_uint64), ("chain_id", C.c_uint64),
-                ("psi0", C.POINTER(C.c_double)), ("replay_accept", C.POINTER(C.c_uint8))]
+                ("psi0", C.POINTER(C.c_double)), ("replay_accept", C.POINTER(C.c_uint8)),
+                ("form", C.c_int32), ("reserved", C.c_int32)]
 
 
 _DP = C.POINTER(C.c_double)
@@ -74,7 +76,7 @@ class _Result(C.Structure):
     _fields_ = [("dH", _DP), ("H_old", _DP), ("H_new", _DP), ("m", _DP), ("abs_m", _DP), ("m2c", _DP),
                 ("beta_eps", _DP), ("accepted", _U8), ("flipped", _U8), ("psi_final", _DP),
                 ("acceptance", C.c_double), ("mean_exp_minus_dH", C.c_double),
-                ("n_nonfinite", C.c_int64), ("n_traj_done", C.c_int64)]
+                ("n_nonfinite", C.c_int64), ("n_traj_done", C.c_int64), ("cg_iterations", C.c_int64)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_uint64, C.c_void_p)
@@ -302,12 +304,14 @@ class Run:
     psi0: object = None
     replay_accept: object = None
     n_therm: int = 0
+    form: int = FORM_PSI
 
     def _c(self, keep):
         s = _Run()
         s.n_md, s.n_traj, s.traj_len = int(self.n_md), int(self.n_traj), float(self.traj_len)
         s.integrator, s.flip_every, s.precision = int(self.integrator), int(self.flip_every), int(self.precision)
         s.n_therm = int(self.n_therm)
+        s.form = int(self.form)
         s.seed, s.chain_id = int(self.seed), int(self.chain_id)
         p0 = _f64(self.psi0)
         keep.append(p0)
@@ -336,7 +340,8 @@ def _result_struct(n_traj, N, want_psi=True):
 def _result_dict(r, arrays):
     out = dict(arrays)
     out.update(acceptance=r.acceptance, mean_exp_minus_dH=r.mean_exp_minus_dH,
-               n_nonfinite=int(r.n_nonfinite), n_traj_done=int(r.n_traj_done))
+               n_nonfinite=int(r.n_nonfinite), n_traj_done=int(r.n_traj_done),
+               cg_iterations=int(r.cg_iterations))
     return out
 
 
