@@ -667,6 +667,62 @@ def bench_phi(args):
     print(json.dumps(line), flush=True)
 
 
+def run_mh_compare(args, sweeps=None):
+    """Sec. 4's cost comparison on this GPU: one HMC trajectory against one
+    Metropolis-Hastings sweep (checkerboard, N spin proposals) of the same
+    single chain, per N_step = floor(ln N) leap-frog steps (the paper finds
+    T_HMC ~ 4 N_step T_MH on its CPU code).  Single chains at the critical
+    couplings, h = 0: 2D L = 64 .. 2048 at beta_c, 3D L = 16 .. 128 at
+    beta = 0.2216544; HMC FP32 state on the tiled passes (no LDS-resident
+    path), graph-replayed trajectories; MH int8 spins, graph-replayed sweeps
+    timed with HIP events."""
+    import torch
+    from paper_1912_03278_amd import ihmc, inputs
+
+    pts = [((L, L), inputs.BETA_C_2D, 4.1) for L in (64, 256, 1024, 2048)] + \
+          [((L,) * 3, inputs.BETA_3D, 6.1) for L in (16, 32, 64, 128)]
+    rows = []
+    ctx = ihmc.Context(device=0, arena_bytes=2 << 30, resident=0, fuse_steps=args.fuse_steps)
+    for L, beta, C in pts:
+        N = int(math.prod(L))
+        n_step = int(math.floor(math.log(N)))
+        lat = ihmc.Lattice(L, beta=beta, C=C)
+        n_sw = sweeps or max(20, min(400, int(4e8 // N)))
+        ctx.mh_run(lat, 5, seed=1)  # warm-up (module load, graph)
+        mh = ctx.mh_run(lat, n_sw, seed=1)
+        t_mh = mh["seconds"] / n_sw
+        K = max(10, min(200, int(4e7 // (N * n_step))))
+        ch = ihmc.Chains(ctx, [lat], [ihmc.Run(n_md=n_step, n_traj=K + 3, precision=ihmc.F32, seed=1)])
+        ch.advance(3)
+        ctx.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch.advance(K)
+        ctx.sync()
+        t_hmc = (time.perf_counter() - t0) / K
+        acc = ch.result(0, want_psi=False)["acceptance"]
+        ch.close()
+        rows.append({"lattice": "x".join(map(str, L)), "N": N, "n_step": n_step, "T_MH_us": round(1e6 * t_mh, 2),
+                     "T_HMC_us": round(1e6 * t_hmc, 2), "T_HMC_over_Nstep_T_MH": round(t_hmc / (n_step * t_mh), 3),
+                     "mh_acceptance": round(mh["acceptance"], 4), "hmc_acceptance": round(acc, 4),
+                     "mh_spin_flips_per_s": N / t_mh})
+        print(f"bench: {rows[-1]['lattice']}: T_HMC {rows[-1]['T_HMC_us']} us, T_MH {rows[-1]['T_MH_us']} us, "
+              f"ratio/N_step {rows[-1]['T_HMC_over_Nstep_T_MH']}", file=sys.stderr, flush=True)
+    ctx.close()
+    return {"workload": "one chain per lattice, h = 0, critical couplings; HMC with N_step = floor(ln N), FP32 "
+                        "state; MH checkerboard sweeps of int8 spins", "points": rows}
+
+
+def bench_mh(args):
+    cmp = run_mh_compare(args)
+    line = {"metric": "T_HMC / (N_step T_MH)", "value": cmp["points"][-1]["T_HMC_over_Nstep_T_MH"],
+            "unit": "ratio", "n_gpus": 1, "steps": None, "warmup": None, "ms_per_step": None,
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32/int8",
+            "data": "synthetic", "config": {"workload": "HMC vs Metropolis-Hastings: " + cmp["workload"]},
+            "mh_compare": cmp, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+
+
 def bench_tau(args):
     """Critical slowing down measured on the batched engine (Sec. 4): tau_int of
     |m| against N at the critical coupling in 2D and 3D, with the paper's fits
@@ -866,6 +922,9 @@ def bench_headline(args):
     if args.extras in ("all", "phi"):
         print("bench: extra key: phi/psi form A/B", file=sys.stderr, flush=True)
         line["extra_phi_form_ab"] = run_phi_ab(args)
+    if args.extras in ("all", "mh"):
+        print("bench: extra key: HMC trajectory against Metropolis-Hastings sweep", file=sys.stderr, flush=True)
+        line["extra_mh_compare"] = run_mh_compare(args)
     if args.extras in ("all", "serving"):
         print("bench: extra key: serving", file=sys.stderr, flush=True)
         sv = run_serving(args)
@@ -880,11 +939,11 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "batched", "large", "dense", "serving", "small", "tau", "phi"],
+                    choices=["headline", "batched", "large", "dense", "serving", "small", "tau", "phi", "mh"],
                     help="headline (default): the batched workload with the large chains, the streaming point and "
                          "serving as extra keys; batched: 4096 uneven chains only; large: the 1024^2 + 128^3 single "
                          "chains; dense: 256 chains of an N=4096 all-to-all model; serving: Poisson request arrivals")
-    ap.add_argument("--extras", default="all", choices=["all", "large", "serving", "phi", "none"],
+    ap.add_argument("--extras", default="all", choices=["all", "large", "serving", "phi", "mh", "none"],
                     help="headline: which extra keys to run")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
     ap.add_argument("--serve-duration", type=float, default=60.0, help="serving: seconds of arrivals")
@@ -918,6 +977,8 @@ def main():
         return bench_headline(args) if args.workload == "headline" else bench_batched(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "mh":
+        return bench_mh(args)
     if args.workload == "phi":
         args.steps = 20 if args.steps is None else args.steps
         args.warmup = 2 if args.warmup is None else args.warmup

@@ -370,6 +370,24 @@ int ihmc_request_info(ihmc_server* server, uint64_t ticket, int64_t* out);
  * seconds since start, device bytes held, budget. */
 int ihmc_server_stats(ihmc_server* server, double* out);
 
+/* ---- the comparison method: local Metropolis-Hastings ---------------------- */
+
+/* n_sweeps sweeps of single-spin Metropolis-Hastings on the spins of a
+ * periodic lattice (the method the paper compares HMC with, Sec. 4), on the
+ * GPU.  A sweep proposes every spin once in checkerboard order (sites of even
+ * parity x + y + z, then odd: independent updates, which needs every extent
+ * even); flipping s_i changes the energy by dE = 2 s_i (J sum_nb s_j + h) and
+ * is accepted iff dE <= 0 or u < exp(-beta dE), u the 53-bit uniform of the
+ * Philox counter (site, sweep, chain_id, tag 5).  Start: spins0 (host, N int8
+ * values of sign +-1) or, if NULL, s_i = +1 iff the uniform of (site, 0,
+ * chain_id, tag 6) is below 1/2.  h_len must be 0 or 1 (IHMC_E_UNSUPPORTED
+ * for a per-site field); C is not used.  Outputs (host, may be NULL): m and
+ * beta_eps per sweep (n_sweeps each; beta*eps = beta H(s) / N), spins_final (N
+ * int8), stats[0] = acceptance, stats[1] = GPU seconds of the sweeps (HIP
+ * events around them).  Synchronous. */
+int ihmc_mh_run(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t n_sweeps, uint64_t seed, uint64_t chain_id,
+                const int8_t* spins0, double* m, double* beta_eps, int8_t* spins_final, double* stats);
+
 /* ---- diagnostics (same kernels as the hot path) --------------------------- */
 
 /* F = -dS/dpsi at the host field psi (N values) into host F (N values), with

@@ -27,7 +27,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ihmc_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle_ihmc.so")
 
-TAG_INIT, TAG_MOM, TAG_ACC, TAG_FLIP = 1, 2, 3, 4
+TAG_INIT, TAG_MOM, TAG_ACC, TAG_FLIP, TAG_MH, TAG_MH_INIT = 1, 2, 3, 4, 5, 6
 LEAPFROG, OMELYAN = 0, 1
 
 
@@ -98,6 +98,8 @@ def lib():
         L.orc_phi_start.argtypes = [lp, dnp, C.POINTER(_Run), dp]
         L.orc_phi_md.argtypes = [lp, dnp, C.c_int32, C.c_double, dp, dp]
         L.orc_run_phi.argtypes = [lp, dnp, C.POINTER(_Run), C.POINTER(_Result)]
+        i8p = C.POINTER(C.c_int8)
+        L.orc_mh_run.argtypes = [lp, C.c_int32, C.c_uint64, C.c_uint64, i8p, dp, dp, i8p, dp]
         _lib = L
     return _lib
 
@@ -298,6 +300,25 @@ def phi_md(model, phi, p, n_md, traj_len=1.0):
 
 def phi_hamiltonian(model, phi, p):
     return 0.5 * float(np.dot(p, p)) + phi_action(model, phi)["S"]
+
+
+def mh_run(lat, n_sweeps, seed=0, chain_id=0, spins0=None):
+    """Checkerboard single-spin Metropolis-Hastings (the comparison method of
+    Sec. 4) on an even-extent periodic lattice with h = 0 or uniform: returns
+    dict(m, beta_eps (per sweep), spins (final, int8), acceptance)."""
+    s, keep = lat._c()
+    N = lat.N
+    m, be = np.zeros(n_sweeps), np.zeros(n_sweeps)
+    fin = np.zeros(N, dtype=np.int8)
+    s0 = None if spins0 is None else np.ascontiguousarray(spins0, dtype=np.int8)
+    acc = C.c_double()
+    i8p = C.POINTER(C.c_int8)
+    rc = lib().orc_mh_run(C.byref(s), int(n_sweeps), int(seed), int(chain_id),
+                          None if s0 is None else s0.ctypes.data_as(i8p), _dp(m), _dp(be),
+                          fin.ctypes.data_as(i8p), C.byref(acc))
+    if rc:
+        raise ValueError("invalid lattice for checkerboard Metropolis-Hastings")
+    return dict(m=m, beta_eps=be, spins=fin, acceptance=acc.value)
 
 
 @dataclass

@@ -52,6 +52,8 @@
 #define ORC_TAG_MOM 2u
 #define ORC_TAG_ACC 3u
 #define ORC_TAG_FLIP 4u
+#define ORC_TAG_MH 5u
+#define ORC_TAG_MH_INIT 6u
 
 #define ORC_LEAPFROG 0
 #define ORC_OMELYAN 1
@@ -789,4 +791,86 @@ int orc_run_phi(const orc_lattice* lat, const orc_dense* d, const orc_run* run, 
     int rc = hmc_phi(&M, run, res);
     model_free(&M);
     return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Local Metropolis-Hastings on the spins, the comparison method of Sec. 4. */
+/* A sweep proposes every spin once: first the sites of even parity          */
+/* x + y + z, then the odd ones (on a lattice of even extents no two sites   */
+/* of one parity are neighbours, so each half is a set of independent       */
+/* single-site updates).  Flipping s_i changes the energy by                */
+/* dE = 2 s_i (J sum_nb s_j + h); the flip is accepted iff dE <= 0 or       */
+/* u < exp(-beta dE), u the 53-bit uniform of counter (i, sweep, chain,      */
+/* TAG_MH).  Start: s_i = +1 iff the uniform of (i, 0, chain, TAG_MH_INIT)   */
+/* is below 1/2.  After every sweep: m = sum s / N and                      */
+/* beta eps = beta (-J sum_i sum_mu s_i s_{i+mu} - h sum s) / N.            */
+
+static int mh_sum_nb(const int8_t* s, const int* L, int ndim, int x, int y, int z) {
+    const int L0 = L[0], L1 = L[1], L2 = ndim > 2 ? L[2] : 1;
+    int acc = 0;
+    acc += s[(x + 1) % L0 + (int64_t)L0 * (y + (int64_t)L1 * z)];
+    acc += s[(x + L0 - 1) % L0 + (int64_t)L0 * (y + (int64_t)L1 * z)];
+    acc += s[x + (int64_t)L0 * ((y + 1) % L1 + (int64_t)L1 * z)];
+    acc += s[x + (int64_t)L0 * ((y + L1 - 1) % L1 + (int64_t)L1 * z)];
+    if (ndim > 2) {
+        acc += s[x + (int64_t)L0 * (y + (int64_t)L1 * ((z + 1) % L2))];
+        acc += s[x + (int64_t)L0 * (y + (int64_t)L1 * ((z + L2 - 1) % L2))];
+    }
+    return acc;
+}
+
+int orc_mh_run(const orc_lattice* lat, int32_t n_sweeps, uint64_t seed, uint64_t chain, const int8_t* spins0,
+               double* m, double* beta_eps, int8_t* spins_final, double* acceptance) {
+    if (lat->ndim < 2 || lat->ndim > 3 || n_sweeps < 0) return -1;
+    if (lat->h_len != 0 && lat->h_len != 1) return -1;
+    for (int i = 0; i < lat->ndim; ++i)
+        if (lat->L[i] < 2 || lat->L[i] % 2) return -1;
+    const int ndim = lat->ndim;
+    const int L[3] = {lat->L[0], lat->L[1], ndim > 2 ? lat->L[2] : 1};
+    const int64_t N = (int64_t)L[0] * L[1] * L[2];
+    const double J = lat->J, beta = lat->beta, h = lat->h_len ? lat->h[0] : 0.0;
+    int8_t* s = (int8_t*)malloc((size_t)N);
+    for (int64_t i = 0; i < N; ++i) {
+        if (spins0) {
+            s[i] = spins0[i] > 0 ? 1 : -1;
+        } else {
+            uint32_t w[4];
+            draw4(seed, (uint32_t)i, 0u, chain, ORC_TAG_MH_INIT, w);
+            s[i] = u53(w[0], w[1]) < 0.5 ? 1 : -1;
+        }
+    }
+    int64_t accepted = 0;
+    for (int32_t t = 0; t < n_sweeps; ++t) {
+        for (int color = 0; color < 2; ++color)
+            for (int z = 0; z < L[2]; ++z)
+                for (int y = 0; y < L[1]; ++y)
+                    for (int x = 0; x < L[0]; ++x) {
+                        if (((x + y + z) & 1) != color) continue;
+                        const int64_t i = x + (int64_t)L[0] * (y + (int64_t)L[1] * z);
+                        const int sum = mh_sum_nb(s, L, ndim, x, y, z);
+                        const double dE = 2.0 * s[i] * (J * sum + h);
+                        uint32_t w[4];
+                        draw4(seed, (uint32_t)i, (uint32_t)t, chain, ORC_TAG_MH, w);
+                        if (dE <= 0.0 || u53(w[0], w[1]) < exp(-beta * dE)) {
+                            s[i] = (int8_t)(-s[i]);
+                            ++accepted;
+                        }
+                    }
+        int64_t ssum = 0, bsum = 0;
+        for (int z = 0; z < L[2]; ++z)
+            for (int y = 0; y < L[1]; ++y)
+                for (int x = 0; x < L[0]; ++x) {
+                    const int64_t i = x + (int64_t)L[0] * (y + (int64_t)L[1] * z);
+                    ssum += s[i];
+                    bsum += s[i] * s[(x + 1) % L[0] + (int64_t)L[0] * (y + (int64_t)L[1] * z)];
+                    bsum += s[i] * s[x + (int64_t)L[0] * ((y + 1) % L[1] + (int64_t)L[1] * z)];
+                    if (ndim > 2) bsum += s[i] * s[x + (int64_t)L[0] * (y + (int64_t)L[1] * ((z + 1) % L[2]))];
+                }
+        if (m) m[t] = (double)ssum / (double)N;
+        if (beta_eps) beta_eps[t] = beta * (-J * (double)bsum - h * (double)ssum) / (double)N;
+    }
+    if (spins_final) memcpy(spins_final, s, (size_t)N);
+    if (acceptance) *acceptance = n_sweeps ? (double)accepted / ((double)N * n_sweeps) : 0.0;
+    free(s);
+    return 0;
 }

@@ -38,7 +38,7 @@ EXPORTS = (
     "ihmc_tune_check", "ihmc_chains_checkpoint", "ihmc_chains_restore", "ihmc_dense_checkpoint",
     "ihmc_dense_restore", "ihmc_ctx_set_resident", "ihmc_ctx_set_step_fusion", "ihmc_hamiltonian",
     "ihmc_plan_events", "ihmc_fixed_point", "ihmc_chains_group_chains", "ihmc_checkpoint", "ihmc_restore",
-    "ihmc_request_info", "ihmc_force_noalloc",
+    "ihmc_request_info", "ihmc_force_noalloc", "ihmc_mh_run",
 )
 TUNE_RULE, TUNE_MEASURED, TUNE_PINNED = 0, 1, 2
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED, REQ_FAILED = 0, 1, 2, 3, 4
@@ -122,6 +122,8 @@ def load():
     L.ihmc_run_batch.argtypes = [vp, C.c_int32, C.POINTER(_Lattice), C.POINTER(_Run), C.POINTER(_Result)]
     L.ihmc_force.argtypes = [vp, C.POINTER(_Lattice), C.c_int32, _DP, _DP]
     L.ihmc_force_noalloc.argtypes = [vp, C.POINTER(_Lattice), C.c_int32, vp, vp, vp]
+    i8p = C.POINTER(C.c_int8)
+    L.ihmc_mh_run.argtypes = [vp, C.POINTER(_Lattice), C.c_int32, C.c_uint64, C.c_uint64, i8p, _DP, _DP, i8p, _DP]
     L.ihmc_action.argtypes = [vp, C.POINTER(_Lattice), C.c_int32, _DP, _DP]
     L.ihmc_integrate.argtypes = [vp, C.POINTER(_Lattice), C.POINTER(_Run), _DP, _DP]
     L.ihmc_philox_normals.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, C.c_int64,
@@ -531,6 +533,22 @@ class Context:
         th, rs, st = C.c_double(), C.c_double(), C.c_int32()
         _check(load().ihmc_min_eig(self.h, _dp(K), K.shape[0], C.byref(th), C.byref(rs), C.byref(st)))
         return th.value, rs.value, st.value
+
+    def mh_run(self, lat: Lattice, n_sweeps, seed=0, chain_id=0, spins0=None):
+        """Checkerboard single-spin Metropolis-Hastings on the GPU: dict(m, beta_eps
+        (per sweep), spins (final, int8), acceptance, seconds (GPU time of the sweeps))."""
+        keep = []
+        N = lat.N
+        m, be = np.zeros(max(1, n_sweeps)), np.zeros(max(1, n_sweeps))
+        fin = np.zeros(N, dtype=np.int8)
+        st = np.zeros(2)
+        i8p = C.POINTER(C.c_int8)
+        s0 = None if spins0 is None else np.ascontiguousarray(spins0, dtype=np.int8)
+        _check(load().ihmc_mh_run(self.h, C.byref(lat._c(keep)), int(n_sweeps), int(seed), int(chain_id),
+                                  None if s0 is None else s0.ctypes.data_as(i8p), _dp(m), _dp(be),
+                                  fin.ctypes.data_as(i8p), _dp(st)))
+        return dict(m=m[:n_sweeps], beta_eps=be[:n_sweeps], spins=fin, acceptance=float(st[0]),
+                    seconds=float(st[1]))
 
     def copy_bandwidth(self, nbytes, reps=20):
         """Mean microseconds of one plain device copy of nbytes (2 * nbytes of traffic)."""
