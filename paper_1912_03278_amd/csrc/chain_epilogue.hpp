@@ -195,6 +195,13 @@ __device__ __forceinline__ void gather_entries(const uint64_t* base, int count, 
   __syncthreads();
 }
 
+// Terms of four x-aligned sites held by four consecutive lanes, summed as
+// (t0 + t1) + (t2 + t3) in FP64; every lane of the quad gets the identical value.
+__device__ __forceinline__ double quad_sum_all(double t) {
+  t = t + __shfl_xor(t, 1, 64);
+  return t + __shfl_xor(t, 2, 64);
+}
+
 // Flag words a pass stores, by kind of contribution.
 enum : int { CONTRIB_FIRST = 0, CONTRIB_FINAL_KIN = 1, CONTRIB_ACTION = 2, CONTRIB_LAST = 3 };
 
@@ -224,6 +231,49 @@ __device__ __forceinline__ void block_store_terms(const ChainDev& cd, const u128
     }
     uint32_t anyb = 0u;
     for (int w = 0; w < NW; ++w) anyb |= sBadA[w];
+    uint64_t* fe = part_entry(base, tix, NTERM);
+    if (kind == CONTRIB_FIRST) store_flag_agent(fe, 0, anyb);
+    if (kind == CONTRIB_FINAL_KIN || kind == CONTRIB_LAST) store_flag_agent(fe, 1, anyb);
+    if (kind == CONTRIB_ACTION || kind == CONTRIB_LAST) store_flag_agent(fe, 2, anyb);
+  }
+}
+
+// As block_store_terms, for accumulators dealt over the lanes of each quad:
+// the pass's terms t0 .. t0 + nterms - 1 in rank order, rank 4k + j held by
+// lane j (mod 4) of every quad in accR[k] (the quad's four lanes hold the same
+// FP64 sums, so each converts a different term to fixed point).  The sums over
+// the lanes of one residue are the terms' block sums, as before.
+template <int NW, int NR>
+__device__ __forceinline__ void block_store_ranks(const ChainDev& cd, const u128 (&accR)[NR], uint32_t bad, int t0,
+                                                  int nterms, int kind, int tix) {
+  __shared__ u128 sRedR[NW][NTERM];
+  __shared__ uint32_t sBadR[NW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    u128 v = accR[k];
+#pragma unroll
+    for (int off = 4; off < 64; off <<= 1) {
+      u128 o;
+      o.lo = __shfl_xor(v.lo, off, 64);
+      o.hi = __shfl_xor(v.hi, off, 64);
+      v = add128(v, o);
+    }
+    const int r = 4 * k + lane;
+    if (lane < 4 && r < nterms) sRedR[wave][t0 + r] = v;
+  }
+  const unsigned long long any_bad = __ballot(bad != 0u);
+  if (lane == 0) sBadR[wave] = any_bad ? 1u : 0u;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t* base = cd.part;
+    for (int a = t0; a < t0 + nterms; ++a) {
+      u128 v = sRedR[0][a];
+      for (int w = 1; w < NW; ++w) v = add128(v, sRedR[w][a]);
+      store_u128_agent(part_entry(base, tix, a), v);
+    }
+    uint32_t anyb = 0u;
+    for (int w = 0; w < NW; ++w) anyb |= sBadR[w];
     uint64_t* fe = part_entry(base, tix, NTERM);
     if (kind == CONTRIB_FIRST) store_flag_agent(fe, 0, anyb);
     if (kind == CONTRIB_FINAL_KIN || kind == CONTRIB_LAST) store_flag_agent(fe, 1, anyb);
@@ -299,6 +349,18 @@ __device__ __forceinline__ void block_accumulate(const ChainDev& cd, ChainState*
   constexpr int t_hi = (MODE == PASS_FIRST) ? T_K0 : T_UT;
   constexpr int kind = (MODE == PASS_FIRST) ? CONTRIB_FIRST : ((MODE == PASS_MEASURE) ? CONTRIB_ACTION : CONTRIB_LAST);
   block_store_terms<NW>(cd, acc, bad, t_lo, t_hi, kind, tix);
+  if (MODE == PASS_FIRST) return;
+  block_close<MODE == PASS_LAST, NW>(cd, st, last_buf, tix);
+}
+
+// The same with accumulators dealt over the lanes of each quad (block_store_ranks).
+template <int MODE, int NW, int NR>
+__device__ __forceinline__ void block_accumulate_ranks(const ChainDev& cd, ChainState* st, const u128 (&accR)[NR],
+                                                       uint32_t bad, int last_buf, int tix) {
+  constexpr int t_lo = (MODE == PASS_FIRST) ? T_K0 : ((MODE == PASS_MEASURE) ? T_S : T_K1);
+  constexpr int t_hi = (MODE == PASS_FIRST) ? T_K0 : T_UT;
+  constexpr int kind = (MODE == PASS_FIRST) ? CONTRIB_FIRST : ((MODE == PASS_MEASURE) ? CONTRIB_ACTION : CONTRIB_LAST);
+  block_store_ranks<NW, NR>(cd, accR, bad, t_lo, t_hi - t_lo + 1, kind, tix);
   if (MODE == PASS_FIRST) return;
   block_close<MODE == PASS_LAST, NW>(cd, st, last_buf, tix);
 }

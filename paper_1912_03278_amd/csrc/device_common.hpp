@@ -318,11 +318,34 @@ __device__ __forceinline__ double log1p_unit(double e) {
   return off + 2.0 * __builtin_fma(s, q, s);
 }
 
+// Both quotients, s = num/den of the log1p series and (1 - e)/(1 + e), come
+// from the one reciprocal q = 1/((1 + e) den): s = num (1 + e) q and
+// 1/(1 + e) = den q (a few ulp each, instead of two divisions).
 __device__ __forceinline__ void logcosh_tanh(double y, double& lc, double& t) {
   const double a = fabs(y);
   const double e = exp_nonpos(-2.0 * a);
-  lc = (a - 0.6931471805599453) + log1p_unit(e);
-  t = copysign((1.0 - e) / (1.0 + e), y);
+  const bool hi = (e > 0.41421356237309503);
+  const double num = hi ? e - 1.0 : e;
+  const double den = hi ? e + 3.0 : 2.0 + e;
+  const double g = 1.0 + e;
+  const double q = 1.0 / (g * den);
+  const double s = (num * g) * q;
+  const double z = s * s;
+  double p = 1.0 / 23.0;
+  p = __builtin_fma(p, z, 1.0 / 21.0);
+  p = __builtin_fma(p, z, 1.0 / 19.0);
+  p = __builtin_fma(p, z, 1.0 / 17.0);
+  p = __builtin_fma(p, z, 1.0 / 15.0);
+  p = __builtin_fma(p, z, 1.0 / 13.0);
+  p = __builtin_fma(p, z, 1.0 / 11.0);
+  p = __builtin_fma(p, z, 1.0 / 9.0);
+  p = __builtin_fma(p, z, 1.0 / 7.0);
+  p = __builtin_fma(p, z, 1.0 / 5.0);
+  p = __builtin_fma(p, z, 1.0 / 3.0);
+  p = p * z;  // atanh(s)/s - 1
+  const double l1p = (hi ? 0.6931471805599453 : 0.0) + 2.0 * __builtin_fma(s, p, s);
+  lc = (a - 0.6931471805599453) + l1p;
+  t = copysign((1.0 - e) * (den * q), y);
 }
 
 template <typename T>

@@ -791,17 +791,22 @@ __global__ __launch_bounds__(64 * ZR) void lattice_pass3t(const ChainDev* __rest
 
   // FP64 terms are summed per column over each aligned 4-plane slab (in z
   // order), then per x-aligned quad of columns, and converted to fixed point
-  // once per slab and quad: the same grouping for every box depth.
+  // once per slab and quad: the same grouping for every box depth.  The quad's
+  // four lanes hold the same sums and deal the conversions: the pass's terms
+  // T0 .. T0 + NU - 1 in rank order, rank 4k + j converted by lane j into accR[k].
   static_assert(ZR % 4 == 0, "boxes are whole 4-plane slabs");
   constexpr bool kAcc = (MODE == PASS_FIRST || MODE == PASS_LAST || MODE == PASS_MEASURE);
+  constexpr int T0 = (MODE == PASS_FIRST) ? T_K0 : ((MODE == PASS_MEASURE) ? T_S : T_K1);
+  constexpr int NU = (MODE == PASS_FIRST) ? 1 : ((MODE == PASS_MEASURE) ? 4 : 5);
+  constexpr int NR = (NU + 3) / 4;
+  const int ql = threadIdx.x & 3;
   uint32_t bad = 0u;
   double hs[NTERM];
-  u128 acc[NTERM];
+  u128 accR[NR];
 #pragma unroll
-  for (int a = 0; a < NTERM; ++a) {
-    hs[a] = 0.0;
-    acc[a] = u128{0ull, 0ull};
-  }
+  for (int a = 0; a < NTERM; ++a) hs[a] = 0.0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) accR[r] = u128{0ull, 0ull};
 
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
@@ -860,21 +865,26 @@ __global__ __launch_bounds__(64 * ZR) void lattice_pass3t(const ChainDev* __rest
     }
     // end of a slab: every lane takes part (the quad sums shuffle across the wave)
     if (kAcc && (k & 3) == 3) {
+      double qv[NU];
 #pragma unroll
-      for (int a = 0; a < NTERM; ++a) {
-        const bool used = (MODE == PASS_FIRST && a == T_K0) || (MODE == PASS_LAST && a == T_K1) ||
-                          (kH64 && a >= T_S && a < T_S + 4);
-        if (used) {
-          acc[a] = add128(acc[a], to_fixed(quad_sum_lanes(hs[a]), bad));
-          hs[a] = 0.0;
-        }
+      for (int r = 0; r < NU; ++r) {
+        qv[r] = quad_sum_all(hs[T0 + r]);
+        hs[T0 + r] = 0.0;
+      }
+#pragma unroll
+      for (int kr = 0; kr < NR; ++kr) {
+        double x = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (4 * kr + j < NU) x = (ql == j) ? qv[4 * kr + j] : x;
+        accR[kr] = add128(accR[kr], to_fixed(x, bad));
       }
     }
   }
 
   if (MODE == PASS_MIDDLE || MODE == PASS_FORCE) return;
   const int tix = ((tl.z0 / ZR) * ((L1 + BY - 1) / BY) + tl.y0 / BY) * ((L0 + BX - 1) / BX) + tl.x0 / BX;
-  block_accumulate<MODE, NT / 64>(cd, st, acc, bad, lat_in_buf(cur, k), tix);
+  block_accumulate_ranks<MODE, NT / 64, NR>(cd, st, accR, bad, lat_in_buf(cur, k), tix);
 }
 
 // ---------------------------------------------------- LDS-resident chains ---
