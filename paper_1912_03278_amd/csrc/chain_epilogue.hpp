@@ -19,9 +19,18 @@ namespace ihmc {
 // proposal; the records then hold the spin expectations given phi.
 __device__ __forceinline__ uint32_t finalize_trajectory(const ChainDev& cd, ChainState* st, int last_buf,
                                                         const u128* sum, uint32_t bad, double t2 = 0.0) {
+  // Every field of the state that the step reads is loaded up front (one round
+  // trip of independent loads rather than a chain of dependent ones) and the
+  // changed ones are stored at the end.
   const int t = st->traj;
-  const u128 S_old{st->S_lo, st->S_hi};
-  const u128 H_old = add128(sum[T_K0], S_old);
+  u128 S{st->S_lo, st->S_hi};
+  int cur_bad = st->cur_bad;
+  int cur = st->cur, sign = st->sign;
+  double sum_psi = st->sum_psi, sum_psih = st->sum_psih, sum_ut = st->sum_ut, sum_t2 = st->sum_t2;
+  int64_t n_acc = st->n_acc, n_nonfinite = st->n_nonfinite;
+  double sum_exp_mdh = st->sum_exp_mdh;
+
+  const u128 H_old = add128(sum[T_K0], S);
   const u128 H_new = add128(sum[T_K1], sum[T_S]);
   double dH = fixed_to_double(sub128(H_new, H_old));
   uint32_t flags = 0u;
@@ -30,9 +39,9 @@ __device__ __forceinline__ uint32_t finalize_trajectory(const ChainDev& cd, Chai
   if (!finite) {
     dH = __builtin_nan("");
     flags |= REC_NONFINITE;
-    if (counted) st->n_nonfinite += 1;
+    if (counted) n_nonfinite += 1;
   }
-  if (finite && st->cur_bad) dH = -__builtin_inf();  // leaving a state of zero weight
+  if (finite && cur_bad) dH = -__builtin_inf();  // leaving a state of zero weight
   bool accept;
   if (cd.replay && t < cd.cap) {
     accept = cd.replay[t] != 0;
@@ -40,37 +49,34 @@ __device__ __forceinline__ uint32_t finalize_trajectory(const ChainDev& cd, Chai
     const double r = uniform_at(cd, (uint32_t)t, TAG_ACC);
     accept = finite && (dH <= 0.0 || r < exp(-dH));
   }
-  if (finite && !st->cur_bad && counted) st->sum_exp_mdh += exp(-dH);
+  if (finite && !cur_bad && counted) sum_exp_mdh += exp(-dH);
   if (accept) {
-    st->cur_bad = 0;
-    st->S_lo = sum[T_S].lo;
-    st->S_hi = sum[T_S].hi;
-    st->sum_psi = fixed_to_double(sum[T_PSI]);
-    st->sum_psih = fixed_to_double(sum[T_PSIH]);
-    st->sum_ut = fixed_to_double(sum[T_UT]);
-    st->sum_t2 = t2;
-    st->cur = last_buf;
-    st->sign = 1;
-    if (counted) st->n_acc += 1;
+    cur_bad = 0;
+    S = sum[T_S];
+    sum_psi = fixed_to_double(sum[T_PSI]);
+    sum_psih = fixed_to_double(sum[T_PSIH]);
+    sum_ut = fixed_to_double(sum[T_UT]);
+    sum_t2 = t2;
+    cur = last_buf;
+    sign = 1;
+    if (counted) n_acc += 1;
     flags |= REC_ACCEPT;
   }
   if (cd.flip_every > 0 && (t + 1) % cd.flip_every == 0) {
     // S(-psi) - S(psi) = 2 psi.h'/sqrt(J'): only the linear field term changes.
     // A change that the fixed-point action cannot hold (non-finite, or
     // |dS| >= 2^62) rejects the flip and marks the record.
-    const double dS = 2.0 * st->sum_psih / cd.sqJ;
+    const double dS = 2.0 * sum_psih / cd.sqJ;
     const double r2 = uniform_at(cd, (uint32_t)t, TAG_FLIP);
     u128 dSf;
     if (!to_fixed_wide(dS, dSf)) {
-      if (finite && counted) st->n_nonfinite += 1;
+      if (finite && counted) n_nonfinite += 1;
       flags |= REC_NONFINITE;
     } else if (dS <= 0.0 || r2 < exp(-dS)) {
-      const u128 S = add128(u128{st->S_lo, st->S_hi}, dSf);
-      st->S_lo = S.lo;
-      st->S_hi = S.hi;
-      st->sign = -st->sign;
-      st->sum_psi = -st->sum_psi;
-      st->sum_psih = -st->sum_psih;
+      S = add128(S, dSf);
+      sign = -sign;
+      sum_psi = -sum_psi;
+      sum_psih = -sum_psih;
       flags |= REC_FLIP;
     }
   }
@@ -82,21 +88,33 @@ __device__ __forceinline__ uint32_t finalize_trajectory(const ChainDev& cd, Chai
     rec.H_new = fixed_to_double(H_new);
     if (cd.form == FORM_PHI) {
       // E[s_i | phi] = t_i, spins independent given phi
-      rec.m = st->sum_psi / N;
+      rec.m = sum_psi / N;
       rec.abs_m = fabs(rec.m);
-      rec.m2c = (st->sum_psi * st->sum_psi - st->sum_t2 + N) / (N * N);
-      rec.beta_eps = (-0.5 * cd.Jp * st->sum_ut - st->sum_psih) / N;
+      rec.m2c = (sum_psi * sum_psi - sum_t2 + N) / (N * N);
+      rec.beta_eps = (-0.5 * cd.Jp * sum_ut - sum_psih) / N;
     } else {
-      rec.m = (st->sum_psi / cd.sqJ - cd.c_m / cd.Jp) / N;
+      rec.m = (sum_psi / cd.sqJ - cd.c_m / cd.Jp) / N;
       rec.abs_m = fabs(rec.m);
       rec.m2c = rec.m * rec.m - cd.c_v / (N * N * cd.Jp);
-      rec.beta_eps = 0.5 * cd.C * cd.Jp + cd.c_e / (2.0 * N * cd.Jp) - st->sum_psih / (2.0 * N * cd.sqJ) -
-                     cd.sqJ / (2.0 * N) * st->sum_ut;
+      rec.beta_eps = 0.5 * cd.C * cd.Jp + cd.c_e / (2.0 * N * cd.Jp) - sum_psih / (2.0 * N * cd.sqJ) -
+                     cd.sqJ / (2.0 * N) * sum_ut;
     }
     rec.flags = flags;
     rec.pad = 0u;
     cd.rec[t] = rec;
   }
+  st->S_lo = S.lo;
+  st->S_hi = S.hi;
+  st->cur_bad = cur_bad;
+  st->cur = cur;
+  st->sign = sign;
+  st->sum_psi = sum_psi;
+  st->sum_psih = sum_psih;
+  st->sum_ut = sum_ut;
+  st->sum_t2 = sum_t2;
+  st->n_acc = n_acc;
+  st->n_nonfinite = n_nonfinite;
+  st->sum_exp_mdh = sum_exp_mdh;
   st->traj = t + 1;
   __hip_atomic_store(&st->bad, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_store(&st->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -198,8 +216,8 @@ __device__ __forceinline__ void gather_entries(const uint64_t* base, int count, 
 // Terms of four x-aligned sites held by four consecutive lanes, summed as
 // (t0 + t1) + (t2 + t3) in FP64; every lane of the quad gets the identical value.
 __device__ __forceinline__ double quad_sum_all(double t) {
-  t = t + __shfl_xor(t, 1, 64);
-  return t + __shfl_xor(t, 2, 64);
+  t = t + dpp_f64<DPP_QUAD_XOR1>(t);
+  return t + dpp_f64<DPP_QUAD_XOR2>(t);
 }
 
 // Flag words a pass stores, by kind of contribution.
@@ -252,8 +270,11 @@ __device__ __forceinline__ void block_store_ranks(const ChainDev& cd, const u128
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
     u128 v = accR[k];
+    // the four lanes of each residue within a row (DPP), then across rows
+    v = add128(v, dpp_u128<DPP_ROW_ROR4>(v));
+    v = add128(v, dpp_u128<DPP_ROW_ROR8>(v));
 #pragma unroll
-    for (int off = 4; off < 64; off <<= 1) {
+    for (int off = 16; off < 64; off <<= 1) {
       u128 o;
       o.lo = __shfl_xor(v.lo, off, 64);
       o.hi = __shfl_xor(v.hi, off, 64);
@@ -327,15 +348,6 @@ __device__ __forceinline__ void block_close(const ChainDev& cd, ChainState* st, 
 // Quads are the same in every tiling, so the totals stay tile-independent.
 __device__ __forceinline__ double quad_sum(double t0, double t1, double t2, double t3) {
   return (t0 + t1) + (t2 + t3);
-}
-
-// Terms of four x-aligned sites held by four consecutive lanes, summed as
-// (t0 + t1) + (t2 + t3) in FP64 (FP addition is commutative, so every lane of
-// the quad forms the identical value; lane 4q keeps it, the other three give 0).
-__device__ __forceinline__ double quad_sum_lanes(double t) {
-  t = t + __shfl_xor(t, 1, 64);
-  t = t + __shfl_xor(t, 2, 64);
-  return ((threadIdx.x & 3) == 0) ? t : 0.0;
 }
 
 // Epilogue of a lattice pass: store the block's terms (FIRST: kinetic energy of

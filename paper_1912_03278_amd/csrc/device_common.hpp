@@ -233,15 +233,49 @@ __host__ __device__ __forceinline__ double fixed_to_double(u128 v) {
   return neg ? -m : m;
 }
 
+// Cross-lane moves within rows of 16 lanes by DPP (a modifier of a VALU
+// operation: no LDS round trip, unlike a shuffle).  CTRL is the DPP control
+// word; every source lane named below lies in the destination's row.
+constexpr int DPP_QUAD_XOR1 = 0xB1;         // quad_perm [1,0,3,2]: lane l ^ 1
+constexpr int DPP_QUAD_XOR2 = 0x4E;         // quad_perm [2,3,0,1]: lane l ^ 2
+constexpr int DPP_ROW_MIRROR = 0x140;       // lane 15 - l of the row
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;  // lane 7 - l of the half-row
+constexpr int DPP_ROW_ROR4 = 0x124;         // lane l - 4 of the row, rotating
+constexpr int DPP_ROW_ROR8 = 0x128;         // lane l - 8 of the row, rotating
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+  return (uint64_t)dpp_u32<CTRL>((uint32_t)v) | ((uint64_t)dpp_u32<CTRL>((uint32_t)(v >> 32)) << 32);
+}
+template <int CTRL>
+__device__ __forceinline__ u128 dpp_u128(u128 v) {
+  return u128{dpp_u64<CTRL>(v.lo), dpp_u64<CTRL>(v.hi)};
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  return __longlong_as_double((long long)dpp_u64<CTRL>((uint64_t)__double_as_longlong(v)));
+}
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
+  return (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l) |
+         ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l) << 32);
+}
+
+// Sum over the 64 lanes of the wave, the same value in every lane; the whole
+// wave must be active.  Within each row by DPP (quads, half-rows, rows), then
+// the four row sums read out.  Integer sums: the order does not matter.
 __device__ __forceinline__ u128 wave_sum128(u128 v) {
+  v = add128(v, dpp_u128<DPP_QUAD_XOR1>(v));
+  v = add128(v, dpp_u128<DPP_QUAD_XOR2>(v));
+  v = add128(v, dpp_u128<DPP_ROW_HALF_MIRROR>(v));
+  v = add128(v, dpp_u128<DPP_ROW_MIRROR>(v));  // every lane holds its row's sum
+  u128 r[4];
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    u128 o;
-    o.lo = __shfl_xor(v.lo, off, 64);
-    o.hi = __shfl_xor(v.hi, off, 64);
-    v = add128(v, o);
-  }
-  return v;
+  for (int q = 0; q < 4; ++q) r[q] = u128{readlane_u64(v.lo, 16 * q), readlane_u64(v.hi, 16 * q)};
+  return add128(add128(r[0], r[1]), add128(r[2], r[3]));
 }
 
 // Workgroup barrier that orders LDS accesses only.  The full __syncthreads

@@ -28,10 +28,13 @@ def lattices(ih):
         (ih.Lattice((20, 12, 9), beta=0.25, C=6.1, h=rng.normal(0, 0.05, 20 * 12 * 9)), ih.F32),
         (ih.Lattice((36, 20), beta=0.44, C=4.1), ih.F64),
         (ih.Lattice((18, 9, 11), beta=0.22, C=6.1), ih.F64),
+        # over 1024 boxes in the 8-plane classes (the pipelined middle pass),
+        # ragged in every direction, rows not whole vector chunks, per-site field
+        (ih.Lattice((258, 100, 80), beta=0.22, C=6.1, h=rng.normal(0, 0.05, 258 * 100 * 80)), ih.F32),
     ]
 
 
-@pytest.mark.parametrize("k", range(8))
+@pytest.mark.parametrize("k", range(9))
 def test_every_tile_class_gives_bitwise_equal_chains(ih, k):
     lat, prec = lattices(ih)[k]
     nd = len(lat.L)
