@@ -40,6 +40,15 @@ __device__ __forceinline__ int wrap_any(int v, int L) {
   return r >= L ? r - L : r;
 }
 
+// The chain-state words a tiled pass reads at its start (accepted buffer,
+// sign, trajectory index) do not change during the launch: only the block that
+// closes the chain writes them, after every block of the launch has read them.
+// They are read through the constant address space, so with scalar loads, and
+// the buffer addresses derived from them stay in scalar registers.
+__device__ __forceinline__ int32_t state_word(const int32_t* p) {
+  return *(const __attribute__((address_space(4))) int32_t*)p;
+}
+
 template <typename T>
 __device__ __forceinline__ T neg_if(T v, int sign) {
   return sign < 0 ? -v : v;
@@ -222,9 +231,9 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
   ChainState* st = cd.st;
   const int L0 = cd.L0, L1 = cd.L1, pitch = cd.pitch;
   const int64_t NP = cd.NP;
-  const int cur = st->cur;
-  const int sign = st->sign;
-  const int traj = st->traj;
+  const int cur = state_word(&st->cur);
+  const int sign = state_word(&st->sign);
+  const int traj = state_word(&st->traj);
   const bool from_cur = (MODE == PASS_FIRST || MODE == PASS_MEASURE || MODE == PASS_FORCE);
   const int in_buf = from_cur ? cur : lat_in_buf(cur, k);
   const int out_buf = lat_out_buf(cur, k);
@@ -503,7 +512,7 @@ __global__ __launch_bounds__(BX / 4 * BY * TPQ) void lattice_pass2v_pair(const C
   const ChainState* st = cd.st;
   const int L0 = cd.L0, L1 = cd.L1, pitch = cd.pitch;
   const int64_t NP = cd.NP;
-  const int cur = st->cur;
+  const int cur = state_word(&st->cur);
   const gmem<T>* __restrict__ pin = (const gmem<T>*)cd.psi + (int64_t)lat_in_buf(cur, k) * NP;
   gmem<T>* __restrict__ pout = (gmem<T>*)cd.psi + (int64_t)lat_out_buf(cur, k) * NP;
   const gmem<T>* __restrict__ pmi = (const gmem<T>*)cd.p + (int64_t)lat_p_in(k) * NP;
@@ -654,9 +663,9 @@ __global__ __launch_bounds__(64 * ZR) void lattice_pass3t(const ChainDev* __rest
   const int L0 = cd.L0, L1 = cd.L1, L2 = cd.L2, pitch = cd.pitch;
   const int64_t NP = cd.NP;
   const int64_t plane = (int64_t)pitch * L1;
-  const int cur = st->cur;
-  const int sign = st->sign;
-  const int traj = st->traj;
+  const int cur = state_word(&st->cur);
+  const int sign = state_word(&st->sign);
+  const int traj = state_word(&st->traj);
   const bool from_cur = (MODE == PASS_FIRST || MODE == PASS_MEASURE || MODE == PASS_FORCE);
   const int in_buf = from_cur ? cur : lat_in_buf(cur, k);
   const int out_buf = lat_out_buf(cur, k);
