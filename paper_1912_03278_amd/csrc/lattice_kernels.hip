@@ -201,6 +201,16 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return k * q + (k < r ? k : r) + m;
 }
 
+// A LAST launch may cover chains whose trajectories end at different passes
+// (j < 0): each block then takes its chain's own last pass j = n_pass - 1 and
+// the launch index of that pass under the round's step plan (k != 0: the
+// middle steps ran two per launch, so the last pass is launch j / 2 + 1;
+// otherwise launch j).
+__device__ __forceinline__ void chain_last_pass(const ChainDev& cd, int& j, int& k) {
+  j = cd.n_pass - 1;
+  k = k ? j / 2 + 1 : j;
+}
+
 // --------------------------------------------------------------------- 2D ---
 //
 // Tile BX x BY, one thread per quad of four consecutive x (NT = BX/4 * BY).
@@ -231,6 +241,7 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
   ChainState* st = cd.st;
   const int L0 = cd.L0, L1 = cd.L1, pitch = cd.pitch;
   const int64_t NP = cd.NP;
+  if (MODE == PASS_LAST && j < 0) chain_last_pass(cd, j, k);
   const int cur = state_word(&st->cur);
   const int sign = state_word(&st->sign);
   const int traj = state_word(&st->traj);
@@ -660,6 +671,7 @@ __global__ __launch_bounds__(64 * ZR) void lattice_pass3t(const ChainDev* __rest
   const Tile tl = tiles[xcd_tile(blockIdx.x, n_tiles)];
   const ChainDev& cd = chains[tl.chain];
   ChainState* st = cd.st;
+  if (MODE == PASS_LAST && j < 0) chain_last_pass(cd, j, k);
   const int L0 = cd.L0, L1 = cd.L1, L2 = cd.L2, pitch = cd.pitch;
   const int64_t NP = cd.NP;
   const int64_t plane = (int64_t)pitch * L1;

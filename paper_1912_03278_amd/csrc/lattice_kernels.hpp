@@ -47,7 +47,9 @@ hipError_t launch_lattice_resident(int precision, int ndim, const ChainDev* chai
 // Launch one pass of kind `mode` (pass index j of the trajectory, which sets
 // the kick and drift; launch index k, which sets the field buffers) over n_tiles
 // consecutive entries of `tiles`; all tiles must belong to chains of the given
-// precision, dimension and tile class.
+// precision, dimension and tile class.  A LAST launch with j < 0 runs every
+// chain's own last pass (j = n_pass - 1), with its launch index j / 2 + 1 when
+// k != 0 (middle steps two per launch) or j when k == 0.
 hipError_t launch_lattice_pass(int precision, int ndim, int cls, int mode, const ChainDev* chains,
                                const Tile* tiles, int n_tiles, int j, int k, hipStream_t s);
 

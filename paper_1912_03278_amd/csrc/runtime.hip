@@ -368,12 +368,8 @@ void plan_groups(const std::vector<ChainDev>& cd, const std::vector<int>& member
   }
 }
 
-// Events one round of the plan needs.
-size_t round_events(const std::vector<Group>& groups) {
-  size_t n = 1;
-  for (auto& g : groups) n += (size_t)g.max_pass + 2;
-  return n;
-}
+// Events one round of the plan needs: the fork, and one join per group.
+size_t round_events(const std::vector<Group>& groups) { return 1 + groups.size(); }
 
 // ------------------------------------------------------------ validation ---
 
@@ -619,7 +615,7 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
   // streams and events of the per-round fork/join (default priority)
   {
     const size_t n_ev = round_events(groups);
-    for (size_t k = 0; k < 2 * groups.size(); ++k) {
+    for (size_t k = 0; k < groups.size(); ++k) {
       hipStream_t st = nullptr;
       HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "side stream");
       side.push_back(st);
@@ -766,7 +762,7 @@ static hipError_t round_plan(const std::vector<Group>& groups, const Tile* d_til
   if ((e = sk.record(fork, s)) != hipSuccess) return e;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const Group& g = groups[gi];
-    hipStream_t gs = sk.pool ? side[2 * gi] : nullptr, ls = sk.pool ? side[2 * gi + 1] : nullptr;
+    hipStream_t gs = sk.pool ? side[gi] : nullptr;
     if ((e = sk.wait(gs, fork)) != hipSuccess) return e;
     const Tile* base = d_tiles + g.tile_off;
     if (g.cls < 0) {  // one launch runs the whole trajectory of every chain of the group
@@ -774,34 +770,23 @@ static hipError_t round_plan(const std::vector<Group>& groups, const Tile* d_til
       if ((e = sk.join(gs, s)) != hipSuccess) return e;
       continue;
     }
-    if ((e = sk.wait(ls, fork)) != hipSuccess) return e;
     if ((e = sk.pass(g, PASS_FIRST, d_cd, base, g.tile_begin.back(), 0, 0, gs)) != hipSuccess) return e;
     const int nc = (int)g.order.size();
     if (g.pair) {
       // Middle steps in pairs (1, 2), (3, 4), ...: launch k = 1 + (j - 1) / 2
       // runs the pair starting at odd j, or step j alone where it is a chain's
-      // last middle step; the last pass of a chain ending at pass j is launch
-      // 1 + j / 2.  Per odd j, in chain order (descending pass count): pairs
-      // for the chains with passes after j + 1, the single step for those
-      // ending at j + 1, LAST(j) for those ending at j.
+      // last middle step.  Per odd j, in chain order (descending pass count):
+      // pairs for the chains with passes after j + 1, the single step for those
+      // ending at j + 1.
       for (int j = 1; j < g.max_pass; j += 2) {
         const int k = 1 + (j - 1) / 2;
         int pair_end = 0;
         while (pair_end < nc && g.n_pass[pair_end] - 1 > j + 1) ++pair_end;
         int single_end = pair_end;
         while (single_end < nc && g.n_pass[single_end] - 1 == j + 1) ++single_end;
-        int last_end = single_end;
-        while (last_end < nc && g.n_pass[last_end] - 1 == j) ++last_end;
-        if (last_end > single_end) {
-          if ((e = sk.join(gs, ls)) != hipSuccess) return e;
-          const int t0 = g.tile_begin[single_end], t1 = g.tile_begin[last_end];
-          if ((e = sk.pass(g, PASS_LAST, d_cd, base + t0, t1 - t0, j, k, ls)) != hipSuccess) return e;
-        }
         if (single_end > pair_end) {
           const int t0 = g.tile_begin[pair_end], t1 = g.tile_begin[single_end];
           if ((e = sk.pass(g, PASS_MIDDLE, d_cd, base + t0, t1 - t0, j, k, gs)) != hipSuccess) return e;
-          if ((e = sk.join(gs, ls)) != hipSuccess) return e;
-          if ((e = sk.pass(g, PASS_LAST, d_cd, base + t0, t1 - t0, j + 1, k + 1, ls)) != hipSuccess) return e;
         }
         if (pair_end > 0) {
           if ((e = sk.pass(g, PASS_PAIR, d_cd, base, g.tile_begin[pair_end], j, k, gs)) != hipSuccess) return e;
@@ -811,19 +796,15 @@ static hipError_t round_plan(const std::vector<Group>& groups, const Tile* d_til
     for (int j = 1; !g.pair && j < g.max_pass; ++j) {
       int mid_end = 0;
       while (mid_end < nc && g.n_pass[mid_end] - 1 > j) ++mid_end;
-      int last_end = mid_end;
-      while (last_end < nc && g.n_pass[last_end] - 1 == j) ++last_end;
-      if (last_end > mid_end) {
-        if ((e = sk.join(gs, ls)) != hipSuccess) return e;
-        const int t0 = g.tile_begin[mid_end], t1 = g.tile_begin[last_end];
-        if ((e = sk.pass(g, PASS_LAST, d_cd, base + t0, t1 - t0, j, j, ls)) != hipSuccess) return e;
-      }
       if (mid_end > 0) {
         if ((e = sk.pass(g, PASS_MIDDLE, d_cd, base, g.tile_begin[mid_end], j, j, gs)) != hipSuccess) return e;
       }
     }
+    // the last pass of every chain of the group in one launch, each chain at
+    // its own pass and buffers: no launch of the round waits on another stream
+    if ((e = sk.pass(g, PASS_LAST, d_cd, base, g.tile_begin.back(), -1, g.pair ? 1 : 0, gs)) != hipSuccess)
+      return e;
     if ((e = sk.join(gs, s)) != hipSuccess) return e;
-    if ((e = sk.join(ls, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -831,7 +812,7 @@ static hipError_t round_plan(const std::vector<Group>& groups, const Tile* d_til
 hipError_t enqueue_round_plan(const std::vector<Group>& groups, const Tile* d_tiles, const ChainDev* d_cd,
                               const std::vector<hipStream_t>& side, const std::vector<hipEvent_t>& events,
                               hipStream_t s) {
-  if (side.size() < 2 * groups.size()) return hipErrorInvalidValue;
+  if (side.size() < groups.size()) return hipErrorInvalidValue;
   RoundSink sk;
   sk.pool = &events;
   return round_plan(groups, d_tiles, d_cd, side, sk, s);
@@ -862,7 +843,7 @@ int Chains::advance(int32_t n_traj) {
     if (fork) HIPCHK(hipEventRecord(events[0], s), "fork");
     for (size_t gi = 0; gi < groups.size(); ++gi) {
       const Group& g = groups[gi];
-      hipStream_t gs = fork ? side[2 * gi] : s;
+      hipStream_t gs = fork ? side[gi] : s;
       if (fork) HIPCHK(hipStreamWaitEvent(gs, events[0], 0), "fork wait");
       HIPCHK(launch_resident_group(g, d_cd, d_tiles + g.tile_off, g.tile_begin.back(), n_traj, gs),
              "resident launch");

@@ -114,7 +114,8 @@ size_t round_events(const std::vector<Group>& groups);
 // makes no HIP call); never more than round_events(groups).
 size_t round_events_used(const std::vector<Group>& groups);
 // One trajectory of every chain of the plan: FIRST over all tiles of a group,
-// then MIDDLE / LAST per pass index; groups on side streams (two per group).
+// then the middle steps per pass index, then one LAST launch that runs every
+// chain's own last pass; each group on a side stream of its own.
 hipError_t enqueue_round_plan(const std::vector<Group>& groups, const Tile* d_tiles, const ChainDev* d_cd,
                               const std::vector<hipStream_t>& side, const std::vector<hipEvent_t>& events,
                               hipStream_t s);
@@ -137,7 +138,7 @@ struct Chains {
   Tile* d_tiles = nullptr;
   std::vector<Group> groups;
   std::vector<void*> allocs;
-  std::vector<hipStream_t> side;   // two per group: passes, and LAST passes
+  std::vector<hipStream_t> side;   // one per launch group
   std::vector<hipEvent_t> events;  // fork/join points of one round
   int enqueued = 0;
   std::vector<int> base;  // per chain: trajectory index at enqueued = 0 (non-zero after a restore)

@@ -293,7 +293,7 @@ bool ihmc_server::ensure_tiles(size_t n) {
 }
 
 bool ihmc_server::ensure_streams(size_t n_groups, size_t n_events) {
-  while (side.size() < 2 * n_groups) {
+  while (side.size() < n_groups) {
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return false;
     side.push_back(st);

@@ -57,23 +57,24 @@ def test_round_events_within_pool(seed):
 
 
 def test_round_events_exact_counts():
-    """Hand-counted plans: one fork; per tiled group 2 joins plus one event per
-    LAST launch that waits for its group's stream (and per single middle step
-    of a fused 2D group); per resident group 1 join."""
+    """Hand-counted plans: one fork, then one join per launch group (every
+    launch of a tiled group, its last passes included, runs on the group's own
+    stream; a resident group is one launch)."""
     ihmc = _lib()
     lat2 = ihmc.Lattice((100, 100), beta=0.4, C=4.1)
     lat3 = ihmc.Lattice((20, 20, 20), beta=0.2, C=6.1)
     run = lambda n_md, i=0: ihmc.Run(n_md=n_md, n_traj=1, chain_id=i)
-    # one 2D chain, 4 MD steps = 5 passes: pairs (1,2), then LAST at 4 after a
-    # single middle step 3 -> fork + join(single) + 2 final joins
-    assert ihmc.plan_events([lat2], [run(4)], fuse_steps=True, resident_sites=0)[0] == 4
-    # one step per launch: LAST(4) waits once -> fork + 1 + 2
-    assert ihmc.plan_events([lat2], [run(4)], fuse_steps=False, resident_sites=0)[0] == 4
-    # 3D chains of 3 and 5 steps: LAST at 3 and at 5 each wait -> fork + 2 + 2
-    assert ihmc.plan_events([lat3, lat3], [run(3), run(5, 1)], fuse_steps=True, resident_sites=0)[0] == 5
+    # one 2D chain, 4 MD steps = 5 passes: FIRST, pair (1,2), single 3, LAST -> fork + join
+    assert ihmc.plan_events([lat2], [run(4)], fuse_steps=True, resident_sites=0)[0] == 2
+    # one step per launch
+    assert ihmc.plan_events([lat2], [run(4)], fuse_steps=False, resident_sites=0)[0] == 2
+    # 3D chains of 3 and 5 steps share a group and its one LAST launch
+    assert ihmc.plan_events([lat3, lat3], [run(3), run(5, 1)], fuse_steps=True, resident_sites=0)[0] == 2
     # two resident chains (one group): fork + 1
     small = ihmc.Lattice((8, 8), beta=0.4, C=4.1)
     assert ihmc.plan_events([small, small], [run(4), run(7, 1)], resident_sites=-1)[0] == 2
+    # a 2D group, a 3D group and a resident group: fork + 3
+    assert ihmc.plan_events([lat2, lat3, small], [run(4), run(3, 1), run(5, 2)], resident_sites=300)[0] == 4
 
 
 def _exact_fixed(x):
