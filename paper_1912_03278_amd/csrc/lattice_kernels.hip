@@ -446,6 +446,10 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
 // come from the buffer of launch k - 1 while the pair writes that of launch k,
 // so no block reads momenta another block of the launch writes.
 //
+// A chain whose last middle step is step j (n_pass - 1 = j + 1) takes step j
+// only: its blocks store the first step's tile results, which are those of the
+// one-step pass, and skip the second.
+//
 // Threads work on quads of four consecutive x: TPQ = 1 gives each thread its
 // tile quad (first-step momenta kept in registers for the second step) and at
 // most one quad of the 2-wide ring (rows -2, -1, BY, BY+1 over the whole
@@ -619,6 +623,16 @@ __global__ __launch_bounds__(BX / 4 * BY * TPQ) void lattice_pass2v_pair(const C
   // overwrites only the psi of its own quads, which no other thread reads now
   T pa[4], va[4];
   if (has_quad) pair_kick_drift<T, RP>(sP, sW, qy + 3, qx + 1, Ct, kick1, drift1, pq, bq, pa, va);
+  if (cd.n_pass - 1 == j + 1) {
+    // the chain's last middle step is step j: its results are those of the
+    // one-step pass, stored to the same buffers, and the block ends here
+    if (quad_ok) {
+      const int64_t base = gx + (int64_t)pitch * gy;
+      st4g<T>(pmo + base, pa);
+      st4g<T>(pout + base, va);
+    }
+    return;
+  }
   if (has_ring) {
     T pn[4], pv[4];
     pair_kick_drift<T, RP>(sP, sW, ry + 3, rc, Ct, kick1, drift1, pr, br, pn, pv);

@@ -774,22 +774,15 @@ static hipError_t round_plan(const std::vector<Group>& groups, const Tile* d_til
     const int nc = (int)g.order.size();
     if (g.pair) {
       // Middle steps in pairs (1, 2), (3, 4), ...: launch k = 1 + (j - 1) / 2
-      // runs the pair starting at odd j, or step j alone where it is a chain's
-      // last middle step.  Per odd j, in chain order (descending pass count):
-      // pairs for the chains with passes after j + 1, the single step for those
-      // ending at j + 1.
+      // runs the pair starting at odd j over the chains with passes after j
+      // (chain order is descending pass count); a chain whose last middle step
+      // is j (its last pass is j + 1) takes step j alone in the same launch.
       for (int j = 1; j < g.max_pass; j += 2) {
         const int k = 1 + (j - 1) / 2;
-        int pair_end = 0;
-        while (pair_end < nc && g.n_pass[pair_end] - 1 > j + 1) ++pair_end;
-        int single_end = pair_end;
-        while (single_end < nc && g.n_pass[single_end] - 1 == j + 1) ++single_end;
-        if (single_end > pair_end) {
-          const int t0 = g.tile_begin[pair_end], t1 = g.tile_begin[single_end];
-          if ((e = sk.pass(g, PASS_MIDDLE, d_cd, base + t0, t1 - t0, j, k, gs)) != hipSuccess) return e;
-        }
-        if (pair_end > 0) {
-          if ((e = sk.pass(g, PASS_PAIR, d_cd, base, g.tile_begin[pair_end], j, k, gs)) != hipSuccess) return e;
+        int end = 0;
+        while (end < nc && g.n_pass[end] - 1 > j) ++end;
+        if (end > 0) {
+          if ((e = sk.pass(g, PASS_PAIR, d_cd, base, g.tile_begin[end], j, k, gs)) != hipSuccess) return e;
         }
       }
     }
