@@ -217,7 +217,8 @@ __device__ __forceinline__ void chain_last_pass(const ChainDev& cd, int& j, int&
 // LDS rows have pitch RP = BX + 8 with lattice x at index x - x0 + 4, so the
 // psi halo [x0-2, x0+BX+2) sits inside one 16-byte aligned row and global and
 // LDS traffic moves in aligned quads.  p and the per-site field are fetched
-// before the LDS phases so their latency overlaps the stencil work.
+// after the staging, so their latency overlaps the barrier and the stencil
+// work without holding up the staging.
 template <typename T, int BX, int BY, int MODE>
 __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __restrict__ chains,
                                                               const Tile* __restrict__ tiles, int n_tiles, int j,
@@ -262,15 +263,10 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
   const bool quad_ok = (gx < L0) && (gy < L1);  // the quad's first site is a lattice site
   const int64_t base = gx + (int64_t)pitch * gy;  // gx + 3 < pitch when quad_ok
 
-  // ---- prefetch p and the field of the quad
   T pq[4] = {(T)0, (T)0, (T)0, (T)0};
   T bq[4];
   const T b_uniform = (T)cd.b0;
   bq[0] = bq[1] = bq[2] = bq[3] = b_uniform;
-  if (quad_ok) {
-    if (MODE == PASS_MIDDLE || MODE == PASS_LAST || (MODE == PASS_FIRST && cd.p_given)) ld4g<T>(pmi + base, pq);
-    if (kHasW && site_field) ld4g<T>((const gmem<T>*)cd.b + base, bq);
-  }
 
   // ---- stage psi on the tile plus its halo, in aligned 4-element chunks:
   // a chunk inside [0, L0) is one vector load, a chunk crossing the periodic
@@ -305,6 +301,13 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
         }
       }
     }
+  }
+  // p and the field of the quad, issued after the staged rows' LDS stores
+  // (loads complete in issue order: issued earlier, they would hold up the
+  // wait for the staged values); their latency overlaps the barrier and w
+  if (quad_ok) {
+    if (MODE == PASS_MIDDLE || MODE == PASS_LAST || (MODE == PASS_FIRST && cd.p_given)) ld4g<T>(pmi + base, pq);
+    if (kHasW && site_field) ld4g<T>((const gmem<T>*)cd.b + base, bq);
   }
   lds_barrier();
 
@@ -560,7 +563,29 @@ __global__ __launch_bounds__(BX / 4 * BY * TPQ) void lattice_pass2v_pair(const C
     rc = (r2 & 1) ? NCH - 1 : 0;
   }
 
-  // ---- momenta and field of both quads, fetched before the LDS phases
+  // ---- stage psi on the tile plus its 4-wide halo, as in the one-step kernel.
+  // The momenta and field loads are issued after the staged rows' LDS stores:
+  // loads complete in issue order, so issued before them they would hold up
+  // the wait for the staged values; issued here, their latency overlaps the
+  // barrier and the first w, and the kick is their first use
+  constexpr int RG = NT / NCH;
+  constexpr int NRPT = (PR + RG - 1) / RG;
+  const int sc = t % NCH, srg = t / NCH;
+  T v[NRPT][4];
+  if (srg < RG) {
+    const ChunkPos cp = chunk_pos(tl.x0 - 4 + 4 * sc, L0, x_near);
+#pragma unroll
+    for (int q = 0; q < NRPT; ++q) {
+      const int r = srg + RG * q;
+      if (r < PR) load_chunk<T>(pin + row_offset(lat_row(r - 4), pitch), cp, v[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < NRPT; ++q) {
+      const int r = srg + RG * q;
+      if (r < PR) st4<T>(sP + r * RP + 4 * sc, v[q]);
+    }
+  }
+  // ---- momenta and field of both quads, first needed by the kick
   T pq[4], bq[4], pr[4], br[4];
   const T b_uniform = (T)cd.b0;
 #pragma unroll
@@ -585,26 +610,6 @@ __global__ __launch_bounds__(BX / 4 * BY * TPQ) void lattice_pass2v_pair(const C
     }
   }
 
-  // ---- stage psi on the tile plus its 4-wide halo, as in the one-step kernel
-  {
-    constexpr int RG = NT / NCH;
-    constexpr int NRPT = (PR + RG - 1) / RG;
-    const int c = t % NCH, rg = t / NCH;
-    if (rg < RG) {
-      const ChunkPos cp = chunk_pos(tl.x0 - 4 + 4 * c, L0, x_near);
-      T v[NRPT][4];
-#pragma unroll
-      for (int q = 0; q < NRPT; ++q) {
-        const int r = rg + RG * q;
-        if (r < PR) load_chunk<T>(pin + row_offset(lat_row(r - 4), pitch), cp, v[q]);
-      }
-#pragma unroll
-      for (int q = 0; q < NRPT; ++q) {
-        const int r = rg + RG * q;
-        if (r < PR) st4<T>(sP + r * RP + 4 * c, v[q]);
-      }
-    }
-  }
   lds_barrier();
 
   const T Ct = (T)cd.C;
@@ -667,7 +672,7 @@ __global__ __launch_bounds__(BX / 4 * BY * TPQ) void lattice_pass2v_pair(const C
 // order as in every other tiling: per column over each 4-plane slab in z order,
 // then per x-aligned quad of columns.
 template <typename T, int BX, int BY, int ZR, int MODE>
-__global__ __launch_bounds__(64 * ZR) void lattice_pass3t(const ChainDev* __restrict__ chains,
+__global__ __launch_bounds__(64 * ZR, 8) void lattice_pass3t(const ChainDev* __restrict__ chains,
                                                           const Tile* __restrict__ tiles, int n_tiles, int j,
                                                           int k) {
   constexpr int NT = 64 * ZR;  // 256 threads per 4-plane slab
