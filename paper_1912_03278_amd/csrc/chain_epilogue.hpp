@@ -343,9 +343,11 @@ __device__ __forceinline__ void block_close(const ChainDev& cd, ChainState* st, 
 }
 
 // Site terms are summed per quad of four x-aligned sites (x = 4q .. 4q+3; in the dense
-// path, site indices 4q .. 4q+3) as
-// (t0 + t1) + (t2 + t3) in FP64 and converted to fixed point once per quad.
-// Quads are the same in every tiling, so the totals stay tile-independent.
+// path, site indices 4q .. 4q+3) as (t0 + t1) + (t2 + t3) in FP64; 2D lattice
+// passes then sum four consecutive quads (16 x-aligned sites) the same way, 3D
+// ones the quads of a column's 4-plane slab, before one conversion to fixed
+// point.  The groups are the same in every tiling, so the totals stay
+// tile-independent.
 __device__ __forceinline__ double quad_sum(double t0, double t1, double t2, double t3) {
   return (t0 + t1) + (t2 + t3);
 }

@@ -417,17 +417,30 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
   }
 
   if (MODE == PASS_MIDDLE || MODE == PASS_FORCE) return;
-  u128 acc[NTERM];
+  // Terms of 16 x-aligned sites: lanes 4m .. 4m+3 hold four consecutive quads
+  // of one tile row (tile widths are multiples of 16), summed in FP64 as
+  // (q0 + q1) + (q2 + q3) into every lane of the group; the group's lanes then
+  // convert different terms to fixed point: the pass's terms T0 .. T0 + NU - 1
+  // in rank order, rank 4r + j by lane j into accR[r].
+  constexpr int T0 = (MODE == PASS_FIRST) ? T_K0 : ((MODE == PASS_MEASURE) ? T_S : T_K1);
+  constexpr int NU = (MODE == PASS_FIRST) ? 1 : ((MODE == PASS_MEASURE) ? 4 : 5);
+  constexpr int NR = (NU + 3) / 4;
+  static_assert(QX % 4 == 0, "rows of whole 16-site groups");
+  const int gl = threadIdx.x & 3;
+  double gv[NU];
 #pragma unroll
-  for (int a = 0; a < NTERM; ++a) acc[a] = u128{0ull, 0ull};
-  if (MODE == PASS_FIRST) acc[T_K0] = to_fixed(qs[T_K0], bad);
-  if (MODE == PASS_LAST) acc[T_K1] = to_fixed(qs[T_K1], bad);
-  if (kH64) {
+  for (int r = 0; r < NU; ++r) gv[r] = quad_sum_all(qs[T0 + r]);
+  u128 accR[NR];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) acc[T_S + a] = to_fixed(qs[T_S + a], bad);
+  for (int r = 0; r < NR; ++r) {
+    double x = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+      if (4 * r + jj < NU) x = (gl == jj) ? gv[4 * r + jj] : x;
+    accR[r] = to_fixed(x, bad);
   }
   const int tix = (tl.y0 / BY) * ((L0 + BX - 1) / BX) + tl.x0 / BX;  // tile index within the chain
-  block_accumulate<MODE, NWAVE>(cd, st, acc, bad, lat_in_buf(cur, k), tix);
+  block_accumulate_ranks<MODE, NWAVE, NR>(cd, st, accR, bad, lat_in_buf(cur, k), tix);
 }
 
 // ------------------------------------------------------------ 2D, two steps ---
@@ -934,9 +947,10 @@ __global__ __launch_bounds__(64 * ZR, 8) void lattice_pass3t(const ChainDev* __r
 // and the per-site field held in LDS in logical site order: every pass of the
 // trajectory, its FP64 sums and the Metropolis step in one launch, with no
 // partial-sum table and no launch per pass.  The per-site arithmetic and the
-// grouping of the FP64 sums (x-aligned quads of sites; in 3D each column first
-// summed over an aligned 4-plane slab, in z order) are those of the tiled
-// passes, so a resident chain's trajectory is bit-identical to the tiled one.
+// grouping of the FP64 sums (in 2D 16 x-aligned sites as four quads; in 3D
+// x-aligned quads of columns, each column first summed over an aligned 4-plane
+// slab, in z order) are those of the tiled passes, so a resident chain's
+// trajectory is bit-identical to the tiled one.
 // n_traj = 0 measures S and the estimator sums of the accepted field (the
 // set-up pass) instead.
 constexpr int RES_THREADS = 256;
@@ -995,30 +1009,48 @@ __global__ __launch_bounds__(RES_THREADS) void lattice_resident(const ChainDev* 
     return n;
   };
   // FP64 sums of per-site terms into fixed point, grouped as in the tiled
-  // passes: per x-aligned quad (2D), per quad of columns each summed over an
-  // aligned 4-plane slab (3D).  term(i, x, y, z, out) fills the K terms
-  // listed in `which`; sites past the row end contribute zeros.
-  const int nq = (L0 + 3) / 4, ns = (NDIM == 3) ? (L2 + 3) / 4 : 1;
+  // passes: per 16 x-aligned sites, as (q0 + q1) + (q2 + q3) of their quads
+  // (2D); per quad of columns each summed over an aligned 4-plane slab (3D).
+  // term(i, x, y, z, out) fills the K terms listed in `which`; sites past the
+  // row end contribute zeros.
+  constexpr int UQ = (NDIM == 2) ? 4 : 1;  // quads per unit
+  const int nq = (L0 + 4 * UQ - 1) / (4 * UQ), ns = (NDIM == 3) ? (L2 + 3) / 4 : 1;
   const int n_units = nq * L1 * ns;
   auto unit_sums = [&](auto term, const int* which, int K, u128* acc, uint32_t& bad) {
     for (int u = tid; u < n_units; u += RES_THREADS) {
       const int q = u % nq, r = u / nq, y = r % L1, sl = r / L1;
-      double col[5][4];
+      // unit total (q0 + q1) + (q2 + q3) over its quads, built as the quads come
+      double first[5], total[5];
+#pragma unroll 1
+      for (int g = 0; g < UQ; ++g) {
+        double col[5][4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < 4; ++e) {
 #pragma unroll
-        for (int a = 0; a < 5; ++a) col[a][e] = 0.0;
-        const int x = 4 * q + e;
-        if (x >= L0) continue;
-        const int z0 = 4 * sl, z1 = (NDIM == 3) ? min(z0 + 4, L2) : 1;
-        for (int z = z0; z < z1; ++z) {
-          double v[5];
-          term(x + L0 * (y + L1 * z), x, y, z, v);
-          for (int a = 0; a < K; ++a) col[a][e] = col[a][e] + v[a];
+          for (int a = 0; a < 5; ++a) col[a][e] = 0.0;
+          const int x = 4 * (UQ * q + g) + e;
+          if (x >= L0) continue;
+          const int z0 = 4 * sl, z1 = (NDIM == 3) ? min(z0 + 4, L2) : 1;
+          for (int z = z0; z < z1; ++z) {
+            double v[5];
+            term(x + L0 * (y + L1 * z), x, y, z, v);
+            for (int a = 0; a < K; ++a) col[a][e] = col[a][e] + v[a];
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+          const double qv = quad_sum(col[a][0], col[a][1], col[a][2], col[a][3]);
+          if (UQ == 1) {
+            total[a] = qv;
+          } else if ((g & 1) == 0) {
+            first[a] = qv;
+          } else {
+            const double pr = first[a] + qv;
+            total[a] = (g == 1) ? pr : total[a] + pr;
+          }
         }
       }
-      for (int a = 0; a < K; ++a)
-        acc[which[a]] = add128(acc[which[a]], to_fixed(quad_sum(col[a][0], col[a][1], col[a][2], col[a][3]), bad));
+      for (int a = 0; a < K; ++a) acc[which[a]] = add128(acc[which[a]], to_fixed(total[a], bad));
     }
   };
   // S-density, psi, psi h', u tanh(sqrt(J') u) of the field in sP (FP64)
