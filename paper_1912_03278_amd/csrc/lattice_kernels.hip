@@ -960,8 +960,20 @@ constexpr int RES_LDS_BYTES = 81408;
 
 int resident_max_sites(int precision, bool site_field) { return RES_LDS_BYTES / ((site_field ? 5 : 4) * precision); }
 
+// LDS a launch reserves beyond the kernel's own when it runs beside tiled
+// passes: enough that a CU holds one resident chain instead of two, so the
+// other half of the CU's LDS stays with the tiled blocks (as many of them fit
+// there as without it).
+constexpr int RES_SOLO_LDS_PAD = 1024;
+static_assert(2 * (RES_LDS_BYTES + RES_SOLO_LDS_PAD) > 160 * 1024, "one resident chain per CU");
+
+// Two workgroups per CU also need the registers of two waves per SIMD (at most
+// 256 per lane): left to itself the compiler spends more on the Metropolis
+// step and the FP64 draws, which run once per trajectory, and the CU then
+// holds one chain.  The bound keeps two, at the price of a few spilled FP64
+// constants reloaded at the trajectory's end.
 template <typename T, int NDIM>
-__global__ __launch_bounds__(RES_THREADS) void lattice_resident(const ChainDev* __restrict__ chains,
+__global__ __launch_bounds__(RES_THREADS, 2) void lattice_resident(const ChainDev* __restrict__ chains,
                                                                 const Tile* __restrict__ tiles, int n_traj) {
   __shared__ __align__(16) unsigned char lds[RES_LDS_BYTES];
   __shared__ u128 sRed[RES_THREADS / 64][NTERM];
@@ -1207,14 +1219,16 @@ __global__ __launch_bounds__(RES_THREADS) void lattice_resident(const ChainDev* 
 }
 
 hipError_t launch_lattice_resident(int precision, int ndim, const ChainDev* chains, const Tile* tiles, int n_chains,
-                                   int n_traj, hipStream_t s) {
+                                   int n_traj, int per_cu, hipStream_t s) {
   if (n_chains <= 0) return hipSuccess;
+  if (per_cu != 1 && per_cu != 2) return hipErrorInvalidValue;
+  const size_t pad = per_cu == 1 ? RES_SOLO_LDS_PAD : 0;
   if (precision == 4) {
-    if (ndim == 2) lattice_resident<float, 2><<<n_chains, RES_THREADS, 0, s>>>(chains, tiles, n_traj);
-    else lattice_resident<float, 3><<<n_chains, RES_THREADS, 0, s>>>(chains, tiles, n_traj);
+    if (ndim == 2) lattice_resident<float, 2><<<n_chains, RES_THREADS, pad, s>>>(chains, tiles, n_traj);
+    else lattice_resident<float, 3><<<n_chains, RES_THREADS, pad, s>>>(chains, tiles, n_traj);
   } else {
-    if (ndim == 2) lattice_resident<double, 2><<<n_chains, RES_THREADS, 0, s>>>(chains, tiles, n_traj);
-    else lattice_resident<double, 3><<<n_chains, RES_THREADS, 0, s>>>(chains, tiles, n_traj);
+    if (ndim == 2) lattice_resident<double, 2><<<n_chains, RES_THREADS, pad, s>>>(chains, tiles, n_traj);
+    else lattice_resident<double, 3><<<n_chains, RES_THREADS, pad, s>>>(chains, tiles, n_traj);
   }
   return hipGetLastError();
 }
@@ -1327,7 +1341,7 @@ hipError_t launch_lattice_pass(int precision, int ndim, int cls, int mode, const
   if (cls == RESIDENT_CLASS || cls == RESIDENT_PHI_CLASS) {  // whole trajectories only; set-up is n_traj = 0
     if (mode != PASS_MEASURE) return hipErrorInvalidValue;
     if (cls == RESIDENT_PHI_CLASS) return launch_lattice_resident_phi(ndim, chains, tiles, n_tiles, 0, s);
-    return launch_lattice_resident(precision, ndim, chains, tiles, n_tiles, 0, s);
+    return launch_lattice_resident(precision, ndim, chains, tiles, n_tiles, 0, 2, s);
   }
   if (precision == 4) {
     if (ndim == 2) {

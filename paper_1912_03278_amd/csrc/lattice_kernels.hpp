@@ -41,8 +41,11 @@ hipError_t launch_lattice_resident_phi(int ndim, const ChainDev* chains, const T
 int resident_max_sites(int precision, bool site_field);
 // n_traj trajectories of each of n_chains resident chains (tiles[b].chain is
 // block b's chain); n_traj = 0 measures S and the estimator sums instead.
+// per_cu: chains a CU may hold at once, 2 (the kernel's LDS and register
+// budget) or 1 (the launch runs beside tiled passes, which keep the rest of
+// the CU's LDS).
 hipError_t launch_lattice_resident(int precision, int ndim, const ChainDev* chains, const Tile* tiles, int n_chains,
-                                   int n_traj, hipStream_t s);
+                                   int n_traj, int per_cu, hipStream_t s);
 
 // Launch one pass of kind `mode` (pass index j of the trajectory, which sets
 // the kick and drift; launch index k, which sets the field buffers) over n_tiles

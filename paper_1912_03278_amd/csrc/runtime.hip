@@ -704,11 +704,11 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
 }
 
 // One launch running n_traj whole trajectories (0: the set-up measurement) of
-// every chain of an LDS-resident group.
+// every chain of an LDS-resident group; per_cu as in launch_lattice_resident.
 hipError_t launch_resident_group(const Group& g, const ChainDev* d_cd, const Tile* t, int n, int n_traj,
-                                 hipStream_t s) {
+                                 int per_cu, hipStream_t s) {
   if (g.cls == RESIDENT_PHI_CLASS) return launch_lattice_resident_phi(g.ndim, d_cd, t, n, n_traj, s);
-  return launch_lattice_resident(g.prec, g.ndim, d_cd, t, n, n_traj, s);
+  return launch_lattice_resident(g.prec, g.ndim, d_cd, t, n, n_traj, per_cu, s);
 }
 
 // Enqueue target of a round plan: the HIP stream operations, or (dry) a count
@@ -742,8 +742,8 @@ struct RoundSink {
                   hipStream_t st) {
     return pool ? launch_lattice_pass(g.prec, g.ndim, g.cls, mode, d_cd, t, n, j, k, st) : hipSuccess;
   }
-  hipError_t resident(const Group& g, const ChainDev* d_cd, const Tile* t, int n, hipStream_t st) {
-    return pool ? launch_resident_group(g, d_cd, t, n, 1, st) : hipSuccess;
+  hipError_t resident(const Group& g, const ChainDev* d_cd, const Tile* t, int n, int per_cu, hipStream_t st) {
+    return pool ? launch_resident_group(g, d_cd, t, n, 1, per_cu, st) : hipSuccess;
   }
 };
 
@@ -760,13 +760,17 @@ static hipError_t round_plan(const std::vector<Group>& groups, const Tile* d_til
   hipEvent_t fork;
   if ((e = sk.take(&fork)) != hipSuccess) return e;
   if ((e = sk.record(fork, s)) != hipSuccess) return e;
+  // resident launches beside tiled groups leave half of each CU to their passes
+  bool tiled = false;
+  for (const Group& g : groups) tiled = tiled || g.cls >= 0;
+  const int res_per_cu = tiled ? 1 : 2;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const Group& g = groups[gi];
     hipStream_t gs = sk.pool ? side[gi] : nullptr;
     if ((e = sk.wait(gs, fork)) != hipSuccess) return e;
     const Tile* base = d_tiles + g.tile_off;
     if (g.cls < 0) {  // one launch runs the whole trajectory of every chain of the group
-      if ((e = sk.resident(g, d_cd, base, g.tile_begin.back(), gs)) != hipSuccess) return e;
+      if ((e = sk.resident(g, d_cd, base, g.tile_begin.back(), res_per_cu, gs)) != hipSuccess) return e;
       if ((e = sk.join(gs, s)) != hipSuccess) return e;
       continue;
     }
@@ -838,7 +842,7 @@ int Chains::advance(int32_t n_traj) {
       const Group& g = groups[gi];
       hipStream_t gs = fork ? side[gi] : s;
       if (fork) HIPCHK(hipStreamWaitEvent(gs, events[0], 0), "fork wait");
-      HIPCHK(launch_resident_group(g, d_cd, d_tiles + g.tile_off, g.tile_begin.back(), n_traj, gs),
+      HIPCHK(launch_resident_group(g, d_cd, d_tiles + g.tile_off, g.tile_begin.back(), n_traj, 2, gs),
              "resident launch");
       if (fork) {
         HIPCHK(hipEventRecord(events[1 + gi], gs), "join");

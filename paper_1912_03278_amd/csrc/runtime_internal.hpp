@@ -128,7 +128,7 @@ hipError_t launch_field_cg(ChainDev* d_cd, const int* which, int n, double* work
                            hipStream_t s);
 hipError_t launch_measure(const std::vector<Group>& groups, const Tile* d_tiles, const ChainDev* d_cd, hipStream_t s);
 hipError_t launch_resident_group(const Group& g, const ChainDev* d_cd, const Tile* t, int n, int n_traj,
-                                 hipStream_t s);
+                                 int per_cu, hipStream_t s);
 
 struct Chains {
   ihmc_ctx* ctx = nullptr;
