@@ -17,7 +17,9 @@ over the timed steps.  Beside it the line carries
   * the FP64 CPU oracle on a 64-chain sample of the workload (5 trajectories
     each), run over the host cores in parallel processes, median of 5 runs;
   * extra keys: the single large chains (2D 1024^2 at beta_c and 3D 128^3), an
-    8192^2 streaming point, and 60 s of Poisson serving with p50/p99 latency.
+    8192^2 streaming point, the psi/phi form A/B, HMC against Metropolis-Hastings,
+    the dense all-to-all workload (N = 4096, 256 chains, MFMA roofline) and 60 s
+    of Poisson serving with p50/p99 latency.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ...]
 """
@@ -419,7 +421,63 @@ def bench_batched(args):
     print(json.dumps(run_batched(args)), flush=True)
 
 
+_DENSE_MODEL = {}
+
+
+def _oracle_dense_job(job):
+    """One oracle chain of the dense workload's model (built once per process
+    from the same seeded generator); returns its CPU seconds."""
+    import oracle
+    from paper_1912_03278_amd import inputs
+    if "w" not in _DENSE_MODEL:
+        _DENSE_MODEL["w"] = inputs.dense()
+    w = _DENSE_MODEL["w"]
+    t0 = time.perf_counter()
+    oracle.run(oracle.Dense(w["K"], beta=w["beta"], C=job["C"]), job["n_traj"], w["n_md"], seed=w["seed"],
+               chain_id=job["chain_id"])
+    return time.perf_counter() - t0
+
+
+def _oracle_dense_warm(_):
+    from paper_1912_03278_amd import inputs
+    import oracle
+    oracle.lib()
+    if "w" not in _DENSE_MODEL:
+        _DENSE_MODEL["w"] = inputs.dense()
+    return os.getpid()
+
+
+def oracle_dense_parallel(C, n_md, N, reps=3, n_traj=1):
+    """The FP64 oracle on one trajectory of each of `cores` chains of the dense
+    model, one process per core; median wall time of `reps` passes."""
+    import multiprocessing as mp
+    import statistics
+
+    import oracle
+    oracle.lib()
+    cores, model = host_cpu()
+    jobs = [dict(C=C, n_traj=n_traj, chain_id=i) for i in range(cores)]
+    work = len(jobs) * n_traj * N * n_md
+    walls, cpu_s = [], 0.0
+    with mp.get_context("spawn").Pool(cores) as pool:
+        pool.map(_oracle_dense_warm, range(cores))
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            cpu_s = sum(pool.map(_oracle_dense_job, jobs, chunksize=1))
+            walls.append(time.perf_counter() - t0)
+    wall = statistics.median(walls)
+    return dict(value=work / wall, unit="site-MD-steps/s", cores=cores, kind="oracle",
+                sample=f"dense workload, {len(jobs)} chains x {n_traj} trajectory of the N={N} model: "
+                       f"{work:.3g} site-MD-steps, FP64, each chain's set-up (CG constants) included, in {cores} "
+                       f"processes; median wall time of {reps} runs {wall:.2f} s ({cpu_s:.1f} CPU-s per run)",
+                cpu_model=model, runs_wall_s=[round(x, 3) for x in walls])
+
+
 def bench_dense(args):
+    print(json.dumps(run_dense(args)), flush=True)
+
+
+def run_dense(args):
     """256 chains of one dense all-to-all model (N = 4096, K_ij ~ N(0, 1/N), h = 0,
     beta = 1, C from Lanczos), 16 leap-frog steps per trajectory; one step = one
     trajectory of every chain.  Both K~ applications of a force evaluation are
@@ -485,20 +543,11 @@ def bench_dense(args):
     chains.close()
     ctx.close()
     if not args.no_cpu_baseline:
-        print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        import oracle
-        t_cpu, work = 0.0, 0
-        for i in range(2):
-            t1 = time.perf_counter()
-            oracle.run(oracle.Dense(w["K"], beta=w["beta"], C=info["C"]), 2, n_md, seed=w["seed"], chain_id=i)
-            t_cpu += time.perf_counter() - t1
-            work += 2 * N * n_md
-        line["cpu_baseline"] = dict(value=work / t_cpu, unit="site-MD-steps/s", cores=1, kind="oracle",
-                                    sample=f"2 chains x 2 trajectories of the N={N} dense model, FP64, set-up "
-                                           f"(CG constants) included, {t_cpu:.1f} s on one host core")
+        print("bench: timing the CPU oracle on a sample of the dense chains", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = oracle_dense_parallel(info["C"], n_md, N)
     else:
         line["cpu_baseline"] = None
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def run_serving(args):
@@ -719,7 +768,58 @@ def run_mh_compare(args, sweeps=None):
               f"ratio/N_step {rows[-1]['T_HMC_over_Nstep_T_MH']}", file=sys.stderr, flush=True)
     ctx.close()
     return {"workload": "one chain per lattice, h = 0, critical couplings; HMC with N_step = floor(ln N), FP32 "
-                        "state; MH checkerboard sweeps of int8 spins", "points": rows}
+                        "state; MH checkerboard sweeps of int8 spins", "points": rows,
+            "dense": run_mh_compare_dense(args)}
+
+
+def run_mh_compare_dense(args):
+    """The same comparison on the dense workload's all-to-all model (N = 4096,
+    K_ij ~ N(0, 1/N), beta = 1, 256 chains): where every site has N - 1
+    neighbours (Sec. 5 expects HMC to close the gap there).  HMC: the dense
+    chains with N_step = floor(ln N) leap-frog steps (BF16-limb GEMMs over all
+    chains); MH: sequential sweeps, one workgroup per chain, local fields
+    carried in FP64.  T_MH from the GPU time of two launches of different sweep
+    counts (their difference removes the set-up of the fields)."""
+    import numpy as np
+    import torch
+    from paper_1912_03278_amd import ihmc, inputs
+
+    w = inputs.dense()
+    K, beta, B = w["K"], w["beta"], w["n_chains"]
+    N = K.shape[0]
+    n_step = int(math.floor(math.log(N)))
+    ctx = ihmc.Context(device=0, arena_bytes=2 << 30)
+    model = ihmc.Dense(K, beta=beta, C=-1.0)
+    ctx.dense_mh_run(model, B, 1, seed=1)  # warm-up
+    a = ctx.dense_mh_run(model, B, 2, seed=1)
+    b = ctx.dense_mh_run(model, B, 6, seed=1)
+    t_mh = (b["seconds"] - a["seconds"]) / 4
+    Kt = 20
+    ch = ihmc.DenseChains(ctx, model, [ihmc.Run(n_md=n_step, n_traj=Kt + 3, precision=ihmc.F32, seed=w["seed"],
+                                                chain_id=i) for i in range(B)], products=args.products)
+    ch.advance(3)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ch.advance(Kt)
+    ctx.sync()
+    t_hmc = (time.perf_counter() - t0) / Kt
+    acc = float(np.mean([ch.result(i, want_psi=False)["acceptance"] for i in range(B)]))
+    ch.close()
+    ctx.close()
+    np_ = 512 * (-(-N // 512))
+    k_bytes = float(N) * np_ * 8 * B  # every row of K streamed by every chain's workgroup per sweep
+    out = {"model": f"dense all-to-all N={N}, K_ij ~ N(0,1/N), beta={beta:g}, h=0, {B} chains", "N": N,
+           "chains": B, "n_step": n_step, "T_MH_us": round(1e6 * t_mh, 1), "T_HMC_us": round(1e6 * t_hmc, 1),
+           "T_HMC_over_Nstep_T_MH": round(t_hmc / (n_step * t_mh), 3),
+           "mh_acceptance": round(float(np.mean(b["acceptance"])), 4), "hmc_acceptance": round(acc, 4),
+           "mh_spin_flips_per_s": N * B / t_mh,
+           "mh_K_row_bytes_per_s": k_bytes / t_mh,
+           "mh_bound": "each chain's workgroup streams all of K once per sweep (rows read ahead of the decisions); "
+                       "one barrier per proposal"}
+    print(f"bench: dense N={N}: T_HMC {out['T_HMC_us']} us, T_MH {out['T_MH_us']} us, ratio/N_step "
+          f"{out['T_HMC_over_Nstep_T_MH']}", file=sys.stderr, flush=True)
+    return out
 
 
 def bench_mh(args):
@@ -934,6 +1034,13 @@ def bench_headline(args):
     if args.extras in ("all", "mh"):
         print("bench: extra key: HMC trajectory against Metropolis-Hastings sweep", file=sys.stderr, flush=True)
         line["extra_mh_compare"] = run_mh_compare(args)
+    if args.extras in ("all", "dense"):
+        print("bench: extra key: dense all-to-all chains", file=sys.stderr, flush=True)
+        dargs = argparse.Namespace(**vars(args))
+        dargs.steps, dargs.warmup = 100, 5
+        dn = run_dense(dargs)
+        line["extra_dense"] = {k: dn[k] for k in ("value", "unit", "ms_per_step", "steps", "warmup", "dtype", "config",
+                                                  "roofline", "kernels", "acceptance_mean", "cpu_baseline")}
     if args.extras in ("all", "serving"):
         print("bench: extra key: serving", file=sys.stderr, flush=True)
         sv = run_serving(args)
@@ -952,7 +1059,7 @@ def main():
                     help="headline (default): the batched workload with the large chains, the streaming point and "
                          "serving as extra keys; batched: 4096 uneven chains only; large: the 1024^2 + 128^3 single "
                          "chains; dense: 256 chains of an N=4096 all-to-all model; serving: Poisson request arrivals")
-    ap.add_argument("--extras", default="all", choices=["all", "large", "serving", "phi", "mh", "none"],
+    ap.add_argument("--extras", default="all", choices=["all", "large", "dense", "serving", "phi", "mh", "none"],
                     help="headline: which extra keys to run")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
     ap.add_argument("--serve-duration", type=float, default=60.0, help="serving: seconds of arrivals")

@@ -388,6 +388,33 @@ int ihmc_server_stats(ihmc_server* server, double* out);
 int ihmc_mh_run(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t n_sweeps, uint64_t seed, uint64_t chain_id,
                 const int8_t* spins0, double* m, double* beta_eps, int8_t* spins_final, double* stats);
 
+/* Single-spin Metropolis-Hastings with an explicit coupling matrix (the
+ * all-to-all models of Sec. 2 and App. A; Sec. 5 expects the gap between HMC
+ * and local updates to shrink as every site gains neighbours), n_chains
+ * independent chains on the GPU, one workgroup each.  Every spin couples to
+ * every other, so a sweep proposes the spins one after another in site order
+ * i = 0 .. N-1: flipping s_i changes H(s) = -1/2 J s^T K s - h.s by
+ * dE = 2 s_i (J sum_{j != i} K_ij s_j + h_i), accepted iff dE <= 0 or
+ * u < exp(-beta dE), u the 53-bit uniform of the Philox counter (site, sweep,
+ * chain_id + c, tag 5).  The local fields are carried from flip to flip in
+ * FP64 (not re-summed), so they differ from a fresh sum by rounding only.
+ *   model       K (host, N x N row-major, exactly symmetric, finite), J, beta
+ *               (finite, >= 0), h/h_len (0, 1 or N values); C is not used.
+ *               1 <= N <= 4096.
+ *   spins0      host, n_chains x N int8 (sign taken), or NULL: s_i = +1 iff the
+ *               uniform of (site, 0, chain, tag 6) is below 1/2.
+ *   m, beta_eps host, n_chains x n_sweeps each (chain-major), or NULL: after
+ *               every sweep m = sum s / N and beta*eps = beta H(s) / N (the full
+ *               quadratic form, diagonal included).
+ *   spins_final host, n_chains x N int8, or NULL.
+ *   acceptance  host, n_chains (accepted flips / (N n_sweeps)), or NULL.
+ *   seconds     host, one value: GPU time of the sweeps' launch, or NULL.
+ * IHMC_E_INVAL for an invalid model or sizes, IHMC_E_NOMEM when the arena
+ * cannot hold K (N x N FP64, rows padded to a multiple of 512).  Synchronous. */
+int ihmc_dense_mh_run(ihmc_ctx* ctx, const ihmc_dense* model, int32_t n_chains, int32_t n_sweeps, uint64_t seed,
+                      uint64_t chain_id, const int8_t* spins0, double* m, double* beta_eps, int8_t* spins_final,
+                      double* acceptance, double* seconds);
+
 /* ---- diagnostics (same kernels as the hot path) --------------------------- */
 
 /* F = -dS/dpsi at the host field psi (N values) into host F (N values), with

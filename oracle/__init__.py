@@ -100,6 +100,7 @@ def lib():
         L.orc_run_phi.argtypes = [lp, dnp, C.POINTER(_Run), C.POINTER(_Result)]
         i8p = C.POINTER(C.c_int8)
         L.orc_mh_run.argtypes = [lp, C.c_int32, C.c_uint64, C.c_uint64, i8p, dp, dp, i8p, dp]
+        L.orc_dense_mh_run.argtypes = [dnp, C.c_int32, C.c_uint64, C.c_uint64, i8p, dp, dp, i8p, dp]
         _lib = L
     return _lib
 
@@ -318,6 +319,26 @@ def mh_run(lat, n_sweeps, seed=0, chain_id=0, spins0=None):
                           fin.ctypes.data_as(i8p), C.byref(acc))
     if rc:
         raise ValueError("invalid lattice for checkerboard Metropolis-Hastings")
+    return dict(m=m, beta_eps=be, spins=fin, acceptance=acc.value)
+
+
+def dense_mh_run(model, n_sweeps, seed=0, chain_id=0, spins0=None):
+    """Sequential single-spin Metropolis-Hastings with an explicit coupling
+    matrix (sites in order 0 .. N-1, the local field summed afresh for every
+    proposal): returns dict(m, beta_eps (per sweep), spins (final, int8),
+    acceptance)."""
+    s, keep = model._c()
+    N = model.N
+    m, be = np.zeros(n_sweeps), np.zeros(n_sweeps)
+    fin = np.zeros(N, dtype=np.int8)
+    s0 = None if spins0 is None else np.ascontiguousarray(spins0, dtype=np.int8)
+    acc = C.c_double()
+    i8p = C.POINTER(C.c_int8)
+    rc = lib().orc_dense_mh_run(C.byref(s), int(n_sweeps), int(seed), int(chain_id),
+                                None if s0 is None else s0.ctypes.data_as(i8p), _dp(m), _dp(be),
+                                fin.ctypes.data_as(i8p), C.byref(acc))
+    if rc:
+        raise ValueError("invalid model for dense Metropolis-Hastings")
     return dict(m=m, beta_eps=be, spins=fin, acceptance=acc.value)
 
 

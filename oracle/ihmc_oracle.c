@@ -38,6 +38,10 @@
  *                         - sqrt(J')/(2N) (Kt psi).tanh(sqrt(J') Kt psi)
  *              (eqs. formula_for_m and formula_for_e written for a general
  *              field; they reduce to the printed forms for constant h)
+ *   phi form   the inverse formulation of eq. cosh_in_exponent  [Sec. 2]
+ *   MH         single-spin Metropolis-Hastings on the spins, checkerboard
+ *              sweeps on a lattice and sequential sweeps with an explicit
+ *              coupling matrix (the comparison method)  [Secs. 4, 5]
  *
  * Randomness: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by the
  * 64-bit seed, counter = (pair index, trajectory, chain id, tag); two 53-bit
@@ -871,6 +875,69 @@ int orc_mh_run(const orc_lattice* lat, int32_t n_sweeps, uint64_t seed, uint64_t
     }
     if (spins_final) memcpy(spins_final, s, (size_t)N);
     if (acceptance) *acceptance = n_sweeps ? (double)accepted / ((double)N * n_sweeps) : 0.0;
+    free(s);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Single-spin Metropolis-Hastings with an explicit coupling matrix (the     */
+/* comparison method of Sec. 4 on the all-to-all models of Sec. 2 / App. A). */
+/* Every spin couples to every other, so no two sites can be updated         */
+/* independently: a sweep proposes the spins one after another in site       */
+/* order i = 0 .. N-1.  Flipping s_i changes H(s) = -1/2 J s^T K s - h.s by  */
+/* dE = 2 s_i (J sum_{j != i} K_ij s_j + h_i) (the diagonal term K_ii s_i^2   */
+/* does not change); the flip is accepted iff dE <= 0 or u < exp(-beta dE),  */
+/* u the 53-bit uniform of counter (i, sweep, chain, TAG_MH).  The local      */
+/* field is summed afresh for every proposal.  Start as in the lattice       */
+/* version.  After every sweep: m = sum s / N and                            */
+/* beta eps = beta H(s) / N with the full quadratic form (diagonal included). */
+
+int orc_dense_mh_run(const orc_dense* d, int32_t n_sweeps, uint64_t seed, uint64_t chain, const int8_t* spins0,
+                     double* m, double* beta_eps, int8_t* spins_final, double* acceptance) {
+    if (!d || d->N < 1 || !d->K || n_sweeps < 0) return -1;
+    if (d->h_len != 0 && d->h_len != 1 && d->h_len != d->N) return -1;
+    if (d->h_len && !d->h) return -1;
+    const int64_t N = d->N;
+    const double J = d->J, beta = d->beta;
+    int8_t* s = (int8_t*)malloc((size_t)N);
+    for (int64_t i = 0; i < N; ++i) {
+        if (spins0) {
+            s[i] = spins0[i] > 0 ? 1 : -1;
+        } else {
+            uint32_t w[4];
+            draw4(seed, (uint32_t)i, 0u, chain, ORC_TAG_MH_INIT, w);
+            s[i] = u53(w[0], w[1]) < 0.5 ? 1 : -1;
+        }
+    }
+    int64_t accepted = 0;
+    for (int32_t t = 0; t < n_sweeps; ++t) {
+        for (int64_t i = 0; i < N; ++i) {
+            nsum fs = {0.0, 0.0};
+            for (int64_t j = 0; j < N; ++j)
+                if (j != i) ns_add(&fs, d->K[i * N + j] * s[j]);
+            const double f = ns_val(&fs);
+            const double hi = d->h_len == 0 ? 0.0 : (d->h_len == 1 ? d->h[0] : d->h[i]);
+            const double dE = 2.0 * s[i] * (J * f + hi);
+            uint32_t w[4];
+            draw4(seed, (uint32_t)i, (uint32_t)t, chain, ORC_TAG_MH, w);
+            if (dE <= 0.0 || u53(w[0], w[1]) < exp(-beta * dE)) {
+                s[i] = (int8_t)(-s[i]);
+                ++accepted;
+            }
+        }
+        nsum quad = {0.0, 0.0}, field = {0.0, 0.0};
+        int64_t ssum = 0;
+        for (int64_t i = 0; i < N; ++i) {
+            ssum += s[i];
+            for (int64_t j = 0; j < N; ++j) ns_add(&quad, d->K[i * N + j] * s[i] * s[j]);
+            const double hi = d->h_len == 0 ? 0.0 : (d->h_len == 1 ? d->h[0] : d->h[i]);
+            ns_add(&field, hi * s[i]);
+        }
+        if (m) m[t] = (double)ssum / (double)N;
+        if (beta_eps) beta_eps[t] = beta * (-0.5 * J * ns_val(&quad) - ns_val(&field)) / (double)N;
+    }
+    if (spins_final) memcpy(spins_final, s, (size_t)N);
+    if (acceptance) *acceptance = (n_sweeps && N) ? (double)accepted / ((double)N * n_sweeps) : 0.0;
     free(s);
     return 0;
 }

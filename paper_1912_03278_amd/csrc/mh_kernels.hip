@@ -14,6 +14,14 @@
 // sweep's slot.  Spins are int8 in site order.  One sweep's three launches are
 // captured into a HIP graph and replayed; the sweep index lives in device
 // memory.
+//
+// With an explicit coupling matrix (the all-to-all models of Sec. 2 and
+// App. A) every spin couples to every other, so the spins of a chain are
+// proposed one after another in site order.  A chain is one workgroup that
+// keeps the local fields f_j = sum_{k != j} K_jk s_k of its sites in
+// registers; a flip of s_i adds 2 s_i K_ij to every f_j (the rows of K are
+// streamed ahead of the decisions, since which row comes next never depends
+// on them), and the owner of site i takes the decision from its own f_i.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -145,6 +153,189 @@ __global__ void k_mh_clear(long long* acc, int64_t n, int* sweep, unsigned long 
   }
 }
 
+
+// ----------------------------------------------------------------- dense ---
+
+struct DenseMhParams {
+  int32_t N, Np;  // sites; row pitch of the padded K (multiple of the block size)
+  int32_t h_kind; // 0: none, 1: uniform, 2: per site
+  uint32_t seed_lo, seed_hi, chain0;
+  double J, beta, h0;
+};
+
+constexpr int DMH_THREADS = 512;
+
+__device__ __forceinline__ double dmh_uniform(const DenseMhParams& q, uint32_t chain, uint32_t i, uint32_t t,
+                                              uint32_t tag) {
+  const uint4 w = philox4x32_10(make_uint4(i, t, chain, tag), q.seed_lo, q.seed_hi);
+  return unit53(w.x, w.y);
+}
+
+// Sum of one double per thread over the block, in a fixed order (waves by
+// shuffle-free LDS tree), so the result does not depend on timing.
+__device__ __forceinline__ double dmh_block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = DMH_THREADS / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// One workgroup per chain, n_sweeps sweeps.  Thread t owns the sites
+// j = t + DMH_THREADS r, r < R (f, s and the sweep's uniforms in registers).
+// Rows of K (padded to Np columns and N + 8 rows with zeros) are loaded D
+// steps ahead into a register ring.  Per site i: the owner decides and writes the new spin (or 0)
+// into an LDS slot, one barrier, then every thread applies the flip to its
+// fields.  The slot alternates between two words: the write for site i + 2
+// happens after the barrier of site i + 1, which every thread passes only
+// after reading the slot of site i.
+// rec[(c * n_sweeps + t) * 3 + {0, 1, 2}] = sum s, s^T K s, sum h s after sweep t.
+template <int R, int D>
+__global__ __launch_bounds__(DMH_THREADS, 1) void k_dense_mh(DenseMhParams q, const double* __restrict__ K,
+                                                            const double* __restrict__ hsite,
+                                                            const int8_t* __restrict__ spins0,
+                                                            int8_t* __restrict__ spins, int n_sweeps,
+                                                            double* __restrict__ rec,
+                                                            unsigned long long* __restrict__ n_acc) {
+  static_assert(DMH_THREADS % D == 0, "ring depth divides the block");
+  __shared__ int8_t sS[R * DMH_THREADS];
+  __shared__ double sh[DMH_THREADS];
+  __shared__ int slot[2];
+  const int c = blockIdx.x;
+  const uint32_t chain = q.chain0 + (uint32_t)c;
+  const int t = threadIdx.x;
+  const int N = q.N;
+  const int64_t Np = q.Np;
+
+  // start spins: given, or +1 iff the uniform of (i, 0, chain, TAG_MH_INIT) < 1/2
+  int s[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = t + DMH_THREADS * r;
+    int v = 0;
+    if (j < N) {
+      if (spins0)
+        v = spins0[(int64_t)c * N + j] > 0 ? 1 : -1;
+      else
+        v = dmh_uniform(q, chain, (uint32_t)j, 0u, TAG_MH_INIT) < 0.5 ? 1 : -1;
+    }
+    s[r] = v;
+    sS[j] = (int8_t)v;
+  }
+  double hv[R], f[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = t + DMH_THREADS * r;
+    hv[r] = (j < N) ? (q.h_kind == 2 ? hsite[j] : q.h0) : 0.0;
+    f[r] = 0.0;
+  }
+  __syncthreads();
+  // f_j = sum_{k != j} K_kj s_k over the rows k (K is symmetric)
+  for (int k = 0; k < N; ++k) {
+    const double sk = (double)sS[k];
+    const double* row = K + (int64_t)k * Np;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = t + DMH_THREADS * r;
+      if (j != k) f[r] = __builtin_fma(row[j], sk, f[r]);
+    }
+  }
+  unsigned long long acc = 0ull;
+
+  for (int ts = 0; ts < n_sweeps; ++ts) {
+    double u[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = t + DMH_THREADS * r;
+      u[r] = (j < N) ? dmh_uniform(q, chain, (uint32_t)j, (uint32_t)ts, TAG_MH) : 0.0;
+    }
+    // ring of the next D rows
+    double kb[D][R];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const double* rowp = K + (int64_t)d * Np + t;
+#pragma unroll
+      for (int r = 0; r < R; ++r) kb[d][r] = rowp[DMH_THREADS * r];
+    }
+
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      for (int tt0 = 0; tt0 < DMH_THREADS; tt0 += D) {
+        if (r * DMH_THREADS + tt0 >= N) break;  // uniform over the block
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const int i = r * DMH_THREADS + tt0 + d;
+          if (i < N) {
+            if (t == tt0 + d) {
+              // owner of site i: register r
+              const int si = s[r];
+              const double dE = 2.0 * (double)si * (q.J * f[r] + hv[r]);
+              const bool flip = (dE <= 0.0) || (u[r] < exp_nonpos(-q.beta * dE));
+              if (flip) {
+                s[r] = -si;
+                ++acc;
+              }
+              slot[i & 1] = flip ? -si : 0;
+            }
+            lds_barrier();
+            const int v = slot[i & 1];
+            if (v != 0) {
+              const double dv = 2.0 * (double)v;
+#pragma unroll
+              for (int rr = 0; rr < R; ++rr) {
+                const int j = t + DMH_THREADS * rr;
+                if (j != i) f[rr] = __builtin_fma(kb[d][rr], dv, f[rr]);
+              }
+            }
+            // refill this ring entry with row i + D (rows N .. N + D - 1 are zeros)
+            const double* rowp = K + (int64_t)(i + D) * Np + t;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) kb[d][rr] = rowp[DMH_THREADS * rr];
+          }
+        }
+      }
+    }
+    // measurement of the sweep: sum s, s^T K s = sum_j s_j (f_j + K_jj s_j), sum h s
+    double ss = 0.0, qf = 0.0, hs = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = t + DMH_THREADS * r;
+      const double sv = (double)s[r];
+      const double kd = (j < N) ? K[(int64_t)j * Np + j] : 0.0;
+      ss += sv;
+      qf += sv * f[r] + kd * (sv * sv);
+      hs += hv[r] * sv;
+    }
+    ss = dmh_block_sum(ss, sh);
+    qf = dmh_block_sum(qf, sh);
+    hs = dmh_block_sum(hs, sh);
+    if (t == 0) {
+      double* o = rec + ((int64_t)c * n_sweeps + ts) * 3;
+      o[0] = ss;
+      o[1] = qf;
+      o[2] = hs;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = t + DMH_THREADS * r;
+    if (j < N) spins[(int64_t)c * N + j] = (int8_t)s[r];
+  }
+  // accepted flips of the chain
+  const double a = dmh_block_sum((double)acc, sh);
+  if (t == 0) n_acc[c] = (unsigned long long)a;
+}
+
+template <int R, int D>
+static void launch_dense_mh(int n_chains, hipStream_t st, const DenseMhParams& q, const double* K, const double* h,
+                            const int8_t* s0, int8_t* s, int n_sweeps, double* rec, unsigned long long* n_acc) {
+  k_dense_mh<R, D><<<n_chains, DMH_THREADS, 0, st>>>(q, K, h, s0, s, n_sweeps, rec, n_acc);
+}
+
 }  // namespace ihmc
 
 using namespace ihmc;
@@ -247,5 +438,106 @@ extern "C" int ihmc_mh_run(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t n_swe
     stats[0] = n_sweeps ? (double)h_nacc / ((double)q.N * n_sweeps) : 0.0;
     stats[1] = 1e-3 * (double)ms;
   }
+  return IHMC_OK;
+}
+
+extern "C" int ihmc_dense_mh_run(ihmc_ctx* ctx, const ihmc_dense* model, int32_t n_chains, int32_t n_sweeps,
+                                 uint64_t seed, uint64_t chain_id, const int8_t* spins0, double* m, double* beta_eps,
+                                 int8_t* spins_final, double* acceptance, double* seconds) {
+  CTX_OK(ctx);
+  if (!model) return set_error(IHMC_E_INVAL, "model is NULL");
+  const int64_t N = model->N;
+  if (N < 1 || N > 4096) return set_error(IHMC_E_INVAL, "dense Metropolis-Hastings: N must be in [1, 4096]");
+  if (!model->K) return set_error(IHMC_E_INVAL, "dense: K is NULL");
+  if (n_chains < 1 || n_chains > 65535) return set_error(IHMC_E_INVAL, "n_chains must be in [1, 65535]");
+  if (n_sweeps < 0) return set_error(IHMC_E_INVAL, "n_sweeps must be >= 0");
+  if (!(model->beta >= 0.0) || !std::isfinite(model->beta) || !std::isfinite(model->J))
+    return set_error(IHMC_E_INVAL, "beta must be finite and >= 0, J finite");
+  if (!(model->h_len == 0 || model->h_len == 1 || model->h_len == N))
+    return set_error(IHMC_E_INVAL, "dense: h_len must be 0, 1 or N");
+  if (model->h_len > 0 && !model->h) return set_error(IHMC_E_INVAL, "dense: h is NULL");
+  for (int64_t i = 0; i < model->h_len; ++i)
+    if (!std::isfinite(model->h[i])) return set_error(IHMC_E_INVAL, "dense: h[%lld] is not finite", (long long)i);
+  for (int64_t i = 0; i < N * N; ++i)
+    if (!std::isfinite(model->K[i])) return set_error(IHMC_E_INVAL, "dense: K has a non-finite entry");
+  // the fields are updated from rows of K in place of its columns
+  for (int64_t i = 0; i < N; ++i)
+    for (int64_t k = i + 1; k < N; ++k)
+      if (model->K[i * N + k] != model->K[k * N + i])
+        return set_error(IHMC_E_INVAL, "dense Metropolis-Hastings: K must be exactly symmetric (entry %lld, %lld)",
+                         (long long)i, (long long)k);
+  // sites per thread; the read-ahead depth shrinks as R grows (registers)
+  const int R = N <= DMH_THREADS ? 1 : N <= 2 * DMH_THREADS ? 2 : N <= 4 * DMH_THREADS ? 4 : 8;
+  DenseMhParams q;
+  std::memset(&q, 0, sizeof q);
+  q.N = (int32_t)N;
+  q.Np = R * DMH_THREADS;
+  q.h_kind = model->h_len == 0 ? 0 : (model->h_len == 1 ? 1 : 2);
+  q.seed_lo = (uint32_t)seed;
+  q.seed_hi = (uint32_t)(seed >> 32);
+  q.chain0 = (uint32_t)chain_id;
+  q.J = model->J;
+  q.beta = model->beta;
+  q.h0 = model->h_len == 1 ? model->h[0] : 0.0;
+  const uint64_t kbytes = 8ull * (uint64_t)(N + 8) * (uint64_t)q.Np;  // 8 zero rows for the read-ahead
+  const uint64_t hbytes = q.h_kind == 2 ? 8ull * (uint64_t)N : 0;
+  const uint64_t sbytes = (uint64_t)n_chains * (uint64_t)N;
+  const uint64_t rbytes = 24ull * (uint64_t)n_chains * (uint64_t)std::max(1, n_sweeps);
+  const uint64_t abytes = 8ull * (uint64_t)n_chains;
+  auto up = [](uint64_t b) { return (b + 255) & ~uint64_t(255); };
+  const uint64_t total = up(kbytes) + up(hbytes) + 2 * up(sbytes) + up(rbytes) + up(abytes);
+  char* blk = (char*)ctx->arena.alloc(total);
+  if (!blk) return set_error(IHMC_E_NOMEM, "arena exhausted");
+  double* dK = (double*)blk;
+  double* dh = (double*)(blk + up(kbytes));
+  int8_t* ds = (int8_t*)(blk + up(kbytes) + up(hbytes));
+  int8_t* ds0 = spins0 ? ds + up(sbytes) : nullptr;
+  double* rec = (double*)(blk + up(kbytes) + up(hbytes) + 2 * up(sbytes));
+  unsigned long long* nacc = (unsigned long long*)(blk + up(kbytes) + up(hbytes) + 2 * up(sbytes) + up(rbytes));
+  hipStream_t st = ctx->stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMemsetAsync(dK, 0, kbytes, st);
+  // rows of K at pitch Np, zero padded
+  if (e == hipSuccess)
+    e = hipMemcpy2DAsync(dK, 8 * (size_t)q.Np, model->K, 8 * (size_t)N, 8 * (size_t)N, (size_t)N,
+                         hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && hbytes) e = hipMemcpyAsync(dh, model->h, hbytes, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && ds0) e = hipMemcpyAsync(ds0, spins0, sbytes, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipEventRecord(e0, st);
+  if (e == hipSuccess) {
+    switch (R) {
+      case 1: launch_dense_mh<1, 8>(n_chains, st, q, dK, dh, ds0, ds, n_sweeps, rec, nacc); break;
+      case 2: launch_dense_mh<2, 8>(n_chains, st, q, dK, dh, ds0, ds, n_sweeps, rec, nacc); break;
+      case 4: launch_dense_mh<4, 8>(n_chains, st, q, dK, dh, ds0, ds, n_sweeps, rec, nacc); break;
+      default: launch_dense_mh<8, 2>(n_chains, st, q, dK, dh, ds0, ds, n_sweeps, rec, nacc); break;
+    }
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  std::vector<double> h_rec(3 * (size_t)n_chains * (size_t)std::max(0, n_sweeps));
+  std::vector<unsigned long long> h_acc((size_t)n_chains);
+  if (e == hipSuccess && !h_rec.empty())
+    e = hipMemcpyAsync(h_rec.data(), rec, 8 * h_rec.size(), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(h_acc.data(), nacc, 8 * h_acc.size(), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && spins_final) e = hipMemcpyAsync(spins_final, ds, sbytes, hipMemcpyDeviceToHost, st);
+  hipError_t es = hipStreamSynchronize(st);
+  float ms = 0.f;
+  if (e == hipSuccess && es == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  ctx->arena.release(blk);
+  if (e != hipSuccess) return hip_fail(ctx, e, "dense Metropolis-Hastings");
+  if (es != hipSuccess) return hip_fail(ctx, es, "dense Metropolis-Hastings sync");
+  for (int32_t c = 0; c < n_chains; ++c) {
+    for (int32_t t = 0; t < n_sweeps; ++t) {
+      const double* o = &h_rec[3 * ((size_t)c * n_sweeps + t)];
+      if (m) m[(size_t)c * n_sweeps + t] = o[0] / (double)N;
+      if (beta_eps) beta_eps[(size_t)c * n_sweeps + t] = q.beta * (-0.5 * q.J * o[1] - o[2]) / (double)N;
+    }
+    if (acceptance) acceptance[c] = n_sweeps ? (double)h_acc[c] / ((double)N * n_sweeps) : 0.0;
+  }
+  if (seconds) *seconds = 1e-3 * (double)ms;
   return IHMC_OK;
 }

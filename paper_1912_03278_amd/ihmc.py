@@ -38,7 +38,7 @@ EXPORTS = (
     "ihmc_tune_check", "ihmc_chains_checkpoint", "ihmc_chains_restore", "ihmc_dense_checkpoint",
     "ihmc_dense_restore", "ihmc_ctx_set_resident", "ihmc_ctx_set_step_fusion", "ihmc_hamiltonian",
     "ihmc_plan_events", "ihmc_fixed_point", "ihmc_chains_group_chains", "ihmc_checkpoint", "ihmc_restore",
-    "ihmc_request_info", "ihmc_force_noalloc", "ihmc_mh_run",
+    "ihmc_request_info", "ihmc_force_noalloc", "ihmc_mh_run", "ihmc_dense_mh_run",
 )
 TUNE_RULE, TUNE_MEASURED, TUNE_PINNED = 0, 1, 2
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED, REQ_FAILED = 0, 1, 2, 3, 4
@@ -124,6 +124,8 @@ def load():
     L.ihmc_force_noalloc.argtypes = [vp, C.POINTER(_Lattice), C.c_int32, vp, vp, vp]
     i8p = C.POINTER(C.c_int8)
     L.ihmc_mh_run.argtypes = [vp, C.POINTER(_Lattice), C.c_int32, C.c_uint64, C.c_uint64, i8p, _DP, _DP, i8p, _DP]
+    L.ihmc_dense_mh_run.argtypes = [vp, C.POINTER(_Dense), C.c_int32, C.c_int32, C.c_uint64, C.c_uint64, i8p, _DP,
+                                    _DP, i8p, _DP, _DP]
     L.ihmc_action.argtypes = [vp, C.POINTER(_Lattice), C.c_int32, _DP, _DP]
     L.ihmc_integrate.argtypes = [vp, C.POINTER(_Lattice), C.POINTER(_Run), _DP, _DP]
     L.ihmc_philox_normals.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, C.c_int64,
@@ -549,6 +551,30 @@ class Context:
                                   fin.ctypes.data_as(i8p), _dp(st)))
         return dict(m=m[:n_sweeps], beta_eps=be[:n_sweeps], spins=fin, acceptance=float(st[0]),
                     seconds=float(st[1]))
+
+    def dense_mh_run(self, model: "Dense", n_chains, n_sweeps, seed=0, chain_id=0, spins0=None):
+        """Sequential single-spin Metropolis-Hastings with an explicit coupling
+        matrix on the GPU, chains chain_id .. chain_id + n_chains - 1: dict(m,
+        beta_eps (n_chains x n_sweeps), spins (n_chains x N, int8), acceptance
+        (per chain), seconds (GPU time of the launch))."""
+        keep = []
+        N = model.N
+        m = np.zeros((n_chains, max(1, n_sweeps)))
+        be = np.zeros((n_chains, max(1, n_sweeps)))
+        fin = np.zeros((n_chains, N), dtype=np.int8)
+        acc = np.zeros(n_chains)
+        sec = np.zeros(1)
+        i8p = C.POINTER(C.c_int8)
+        s0 = None
+        if spins0 is not None:
+            s0 = np.ascontiguousarray(np.broadcast_to(np.asarray(spins0, dtype=np.int8), (n_chains, N)))
+        _check(load().ihmc_dense_mh_run(self.h, C.byref(model._c(keep)), int(n_chains), int(n_sweeps), int(seed),
+                                        int(chain_id), None if s0 is None else s0.ctypes.data_as(i8p), _dp(m),
+                                        _dp(be), fin.ctypes.data_as(i8p), _dp(acc), _dp(sec)))
+        if n_sweeps == 0:
+            m, be = m[:, :0], be[:, :0]
+        return dict(m=np.ascontiguousarray(m), beta_eps=np.ascontiguousarray(be), spins=fin, acceptance=acc,
+                    seconds=float(sec[0]))
 
     def copy_bandwidth(self, nbytes, reps=20):
         """Mean microseconds of one plain device copy of nbytes (2 * nbytes of traffic)."""

@@ -51,3 +51,73 @@ def test_mh_refusals(ctx):
             ctx.mh_run(lat, 3)
     r = ctx.mh_run(ihmc.Lattice((4, 4), beta=0.4, C=4.1), 0)
     assert r["m"].size == 0 and r["seconds"] == 0.0
+
+
+# ---- sequential sweeps with an explicit coupling matrix
+
+def _sym(rng, N, diag):
+    A = rng.standard_normal((N, N)) / np.sqrt(N)
+    K = 0.5 * (A + A.T)  # exactly symmetric
+    np.fill_diagonal(K, diag * rng.standard_normal(N) if diag else 0.0)
+    return K
+
+
+@pytest.mark.parametrize("N,beta,hk,diag,given", [(100, 1.0, "none", False, False), (512, 1.2, "uniform", True, False),
+                                                  (777, 0.9, "site", False, True), (1500, 1.0, "none", True, False),
+                                                  (2049, 0.7, "site", True, False), (4096, 1.0, "none", False, False),
+                                                  (4096, 0.8, "uniform", False, True)])
+def test_dense_mh_equal_to_oracle(ctx, orc, N, beta, hk, diag, given):
+    """Three chains of sequential sweeps against the oracle's (which sums every
+    local field afresh): the same spins after the last sweep and the same m and
+    acceptance, bit for bit; beta*eps to 1e-12 (the GPU's fields are carried
+    from flip to flip, so H differs by rounding).  Sizes span one to eight
+    sites per thread with ragged last rows."""
+    from paper_1912_03278_amd import ihmc
+    rng = np.random.default_rng(N)
+    K = _sym(rng, N, 0.5 if diag else 0.0)
+    h = None if hk == "none" else (np.array([0.05]) if hk == "uniform" else 0.1 * rng.standard_normal(N))
+    n_chains, n_sweeps = 3, (4 if N > 2000 else 8)
+    s0 = np.where(rng.random((n_chains, N)) < 0.6, 1, -1).astype(np.int8) if given else None
+    g = ctx.dense_mh_run(ihmc.Dense(K, beta=beta, C=0.0, h=h), n_chains, n_sweeps, seed=9, chain_id=5, spins0=s0)
+    for c in range(n_chains):
+        r = orc.dense_mh_run(orc.Dense(K, beta=beta, C=0.0, h=h), n_sweeps, seed=9, chain_id=5 + c,
+                             spins0=None if s0 is None else s0[c])
+        assert np.array_equal(g["spins"][c], r["spins"]), (N, c)
+        assert np.array_equal(g["m"][c], r["m"]), (N, c)
+        assert np.max(np.abs(g["beta_eps"][c] - r["beta_eps"])) < 1e-12, (N, c)
+        assert g["acceptance"][c] == r["acceptance"]
+    assert g["seconds"] > 0.0
+
+
+def test_dense_mh_infinite_range_statistics(ctx):
+    """App. A's model at beta J = 1 (N = 10) and a spin-glass matrix with a
+    per-site field (N = 8): the GPU chains' m, m^2 and beta*eps average to the
+    enumeration (4 sigma; the error from the spread of the 16 independent chains'
+    means)."""
+    from paper_1912_03278_amd import ihmc
+    from oracle import exact as E
+    rng = np.random.default_rng(21)
+    cases = [(E.infinite_range_K(10), 1.0, None), (_sym(rng, 8, 0.3), 1.1, 0.2 * rng.standard_normal(8))]
+    for K, beta, h in cases:
+        ex = E.brute_force(K, beta, h=0.0 if h is None else h)
+        g = ctx.dense_mh_run(ihmc.Dense(K, beta=beta, C=0.0, h=h), 16, 20000, seed=3)
+        for key, series in (("be", g["beta_eps"]), ("m", g["m"]), ("m2", g["m"] ** 2)):
+            means = series[:, 100:].mean(axis=1)
+            err = means.std(ddof=1) / np.sqrt(means.size)
+            assert abs(means.mean() - ex[key]) < 4 * err, (key, means.mean(), err, ex[key])
+
+
+def test_dense_mh_refusals(ctx):
+    from paper_1912_03278_amd import ihmc
+    rng = np.random.default_rng(4)
+    K = _sym(rng, 16, 0.0)
+    Kb = K.copy()
+    Kb[2, 5] = np.nextafter(Kb[2, 5], 1.0)  # no longer exactly symmetric
+    bad = [(ihmc.Dense(Kb, beta=1.0, C=0.0), 1), (ihmc.Dense(K, beta=1.0, C=0.0, h=np.zeros(5)), 1),
+           (ihmc.Dense(K, beta=-1.0, C=0.0), 1), (ihmc.Dense(K, beta=1.0, C=0.0), 0),
+           (ihmc.Dense(_sym(rng, 4097, 0.0), beta=1.0, C=0.0), 1)]
+    for model, nc in bad:
+        with pytest.raises(ihmc.IhmcError):
+            ctx.dense_mh_run(model, nc, 2)
+    r = ctx.dense_mh_run(ihmc.Dense(K, beta=1.0, C=0.0), 2, 0)
+    assert r["m"].shape == (2, 0)
