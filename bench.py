@@ -117,7 +117,8 @@ def tune_tiles(ctx, lats, args, sites=0):
 
 def group_rows(chains, reps, modes=(1,), pair=False):
     """Per launch group: tile shape, sites and HIP-event time of the pass kinds
-    (with pair: also the two-step launch of 2D groups, as pair_us)."""
+    (with pair: also the two-step launch of the groups that have one, as
+    pair_us)."""
     from paper_1912_03278_amd import ihmc
     rows = []
     for g in range(chains.groups()):
@@ -131,8 +132,11 @@ def group_rows(chains, reps, modes=(1,), pair=False):
         for m in modes:
             name = ("first_us", "middle_us", "last_us")[m]
             row[name] = chains.time_pass(g, mode=m, reps=reps if m == 1 else max(10, reps // 5))["us"]
-        if pair and info["ndim"] == 2:
-            row["pair_us"] = chains.time_pass(g, mode=ihmc.PAIR, reps=reps)["us"]
+        if pair:
+            try:  # groups without two-step launches refuse the mode
+                row["pair_us"] = chains.time_pass(g, mode=ihmc.PAIR, reps=reps)["us"]
+            except ihmc.IhmcError:
+                pass
         rows.append(row)
     return rows
 
@@ -984,8 +988,8 @@ def run_large(args, K=None, W=None):
             "bound": "hbm", "kernel": f"fused {dom_kind}, {dom['ndim']}D",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_bytes("large_3d_middle" if dom["ndim"] == 3 else
-                                     ("large_2d_pair" if dom_kind.startswith("two") else "large_2d_middle"),
+            "traffic": traffic_bytes(("large_3d_" if dom["ndim"] == 3 else "large_2d_") +
+                                     ("pair" if dom_kind.startswith("two") else "middle"),
                                      sites=dom["sites"], tiles=dom["tiles"]),
             "algorithmic_bytes_per_launch": int(alg_bytes),
             "algorithmic_basis": f"(16 + 4/n_md) B per site-MD-step x {dom_steps} MD step(s) "
