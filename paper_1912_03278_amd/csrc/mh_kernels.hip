@@ -234,7 +234,9 @@ __global__ __launch_bounds__(DMH_THREADS, 1) void k_dense_mh(DenseMhParams q, co
     f[r] = 0.0;
   }
   __syncthreads();
-  // f_j = sum_{k != j} K_kj s_k over the rows k (K is symmetric)
+  // f_j = sum_{k != j} K_kj s_k over the rows k (K is symmetric); unrolled so
+  // that several rows' loads are in flight
+#pragma unroll 8
   for (int k = 0; k < N; ++k) {
     const double sk = (double)sS[k];
     const double* row = K + (int64_t)k * Np;
