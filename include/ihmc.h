@@ -396,8 +396,10 @@ int ihmc_mh_run(ihmc_ctx* ctx, const ihmc_lattice* lat, int32_t n_sweeps, uint64
  * i = 0 .. N-1: flipping s_i changes H(s) = -1/2 J s^T K s - h.s by
  * dE = 2 s_i (J sum_{j != i} K_ij s_j + h_i), accepted iff dE <= 0 or
  * u < exp(-beta dE), u the 53-bit uniform of the Philox counter (site, sweep,
- * chain_id + c, tag 5).  The local fields are carried from flip to flip in
- * FP64 (not re-summed), so they differ from a fresh sum by rounding only.
+ * chain_id + c, tag 5), evaluated as dE < -ln(u) / beta.  The local fields
+ * are carried from flip to flip in FP64 (not re-summed), so they differ from
+ * a fresh sum by rounding only; a decision can differ from one taken with
+ * exact arithmetic only where u and exp(-beta dE) agree to rounding.
  *   model       K (host, N x N row-major, exactly symmetric, finite), J, beta
  *               (finite, >= 0), h/h_len (0, 1 or N values); C is not used.
  *               1 <= N <= 4096.

@@ -19,9 +19,10 @@
 // App. A) every spin couples to every other, so the spins of a chain are
 // proposed one after another in site order.  A chain is one workgroup that
 // keeps the local fields f_j = sum_{k != j} K_jk s_k of its sites in
-// registers; a flip of s_i adds 2 s_i K_ij to every f_j (the rows of K are
-// streamed ahead of the decisions, since which row comes next never depends
-// on them), and the owner of site i takes the decision from its own f_i.
+// registers; a flip of s_i adds 2 s_i K_ij to every f_j.  The proposals run in
+// blocks of 64 sites on the wave that holds the block (no barrier between
+// them), and the block's flips reach the other fields afterwards, from the
+// flipped rows of K only (delayed updates).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -185,31 +186,50 @@ __device__ __forceinline__ double dmh_block_sum(double v, double* sh) {
   return r;
 }
 
-// One workgroup per chain, n_sweeps sweeps.  Thread t owns the sites
-// j = t + DMH_THREADS r, r < R (f, s and the sweep's uniforms in registers).
-// Rows of K (padded to Np columns and N + 8 rows with zeros) are loaded D
-// steps ahead into a register ring.  Per site i: the owner decides and writes the new spin (or 0)
-// into an LDS slot, one barrier, then every thread applies the flip to its
-// fields.  The slot alternates between two words: the write for site i + 2
-// happens after the barrier of site i + 1, which every thread passes only
-// after reading the slot of site i.
+// One workgroup per chain, n_sweeps sweeps, with the spins proposed in blocks
+// of 64 consecutive sites and the fields updated late (delayed updates).
+// Thread t owns the sites j = t + DMH_THREADS r, r < R: lane j % 64 of wave
+// (j % DMH_THREADS) / 64, register r, so the 64 sites of block n are the lanes
+// of wave n % 8 in register n / 8.  Per block:
+//   A  that wave runs the block's proposals in order: lane k decides from its
+//      own field, the decision is broadcast within the wave (no barrier), and a
+//      flip of s_k adds 2 s_k K_kl to the fields of the block's other lanes
+//      from the block's 64 x 64 diagonal part of K, staged in LDS;
+//   B  one barrier, then every thread adds the block's flips to the fields of
+//      its other sites from the flipped rows of K only (a compacted list, rows
+//      read four or eight at a time), while the next diagonal block is staged;
+//      a barrier.
+// Every field takes the flips in increasing site order, the order of a
+// sweep, so it holds the same FP64 value as when each flip is applied at
+// once.  The test u < exp(-beta dE) is taken as dE < -ln(u) / beta with the
+// threshold computed for every site before the sweep (off the proposals'
+// dependent chain); the two differ only where u and exp(-beta dE) agree to
+// rounding.
 // rec[(c * n_sweeps + t) * 3 + {0, 1, 2}] = sum s, s^T K s, sum h s after sweep t.
-template <int R, int D>
+constexpr int DMH_BLK = 64;
+
+template <int R>
 __global__ __launch_bounds__(DMH_THREADS, 1) void k_dense_mh(DenseMhParams q, const double* __restrict__ K,
                                                             const double* __restrict__ hsite,
                                                             const int8_t* __restrict__ spins0,
                                                             int8_t* __restrict__ spins, int n_sweeps,
                                                             double* __restrict__ rec,
                                                             unsigned long long* __restrict__ n_acc) {
-  static_assert(DMH_THREADS % D == 0, "ring depth divides the block");
+  constexpr int NW = DMH_THREADS / 64;
+  constexpr int DMH_Q = R >= 8 ? 4 : 8;  // flipped rows read at once (R values each, in registers)
+  static_assert(DMH_THREADS % 64 == 0 && DMH_BLK == 64, "one block per wave");
+  __shared__ double sKd[2][DMH_BLK * DMH_BLK];
+  __shared__ int sList[2][DMH_BLK];  // flipped block-local sites, increasing
+  __shared__ int sNew[2][DMH_BLK];   // their new spins
+  __shared__ int sCount[2];
   __shared__ int8_t sS[R * DMH_THREADS];
   __shared__ double sh[DMH_THREADS];
-  __shared__ int slot[2];
   const int c = blockIdx.x;
   const uint32_t chain = q.chain0 + (uint32_t)c;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int N = q.N;
   const int64_t Np = q.Np;
+  const int NB = (N + DMH_BLK - 1) / DMH_BLK;
 
   // start spins: given, or +1 iff the uniform of (i, 0, chain, TAG_MH_INIT) < 1/2
   int s[R];
@@ -248,57 +268,94 @@ __global__ __launch_bounds__(DMH_THREADS, 1) void k_dense_mh(DenseMhParams q, co
   }
   unsigned long long acc = 0ull;
 
+  // the diagonal 64 x 64 part of K of block n, 8 values per thread
+  auto diag_load = [&](int n, double (&v)[DMH_BLK * DMH_BLK / DMH_THREADS]) {
+#pragma unroll
+    for (int m = 0; m < DMH_BLK * DMH_BLK / DMH_THREADS; ++m) {
+      const int e = t + DMH_THREADS * m, a = e >> 6, b = e & 63;
+      v[m] = K[(int64_t)(DMH_BLK * n + a) * Np + DMH_BLK * n + b];
+    }
+  };
+  auto diag_store = [&](int buf, const double (&v)[DMH_BLK * DMH_BLK / DMH_THREADS]) {
+#pragma unroll
+    for (int m = 0; m < DMH_BLK * DMH_BLK / DMH_THREADS; ++m) sKd[buf][t + DMH_THREADS * m] = v[m];
+  };
+
   for (int ts = 0; ts < n_sweeps; ++ts) {
-    double u[R];
+    // acceptance thresholds of the owned sites: accept iff dE < -ln(u)/beta
+    double thr[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int j = t + DMH_THREADS * r;
-      u[r] = (j < N) ? dmh_uniform(q, chain, (uint32_t)j, (uint32_t)ts, TAG_MH) : 0.0;
+      const double u = (j < N) ? dmh_uniform(q, chain, (uint32_t)j, (uint32_t)ts, TAG_MH) : 0.5;
+      thr[r] = -ln_unit(u) / q.beta;  // +inf for beta = 0: every proposal is taken
     }
-    // ring of the next D rows
-    double kb[D][R];
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const double* rowp = K + (int64_t)d * Np + t;
-#pragma unroll
-      for (int r = 0; r < R; ++r) kb[d][r] = rowp[DMH_THREADS * r];
+    {
+      double v[DMH_BLK * DMH_BLK / DMH_THREADS];
+      diag_load(0, v);
+      diag_store(0, v);
     }
-
+    __syncthreads();
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      for (int tt0 = 0; tt0 < DMH_THREADS; tt0 += D) {
-        if (r * DMH_THREADS + tt0 >= N) break;  // uniform over the block
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-          const int i = r * DMH_THREADS + tt0 + d;
-          if (i < N) {
-            if (t == tt0 + d) {
-              // owner of site i: register r
-              const int si = s[r];
-              const double dE = 2.0 * (double)si * (q.J * f[r] + hv[r]);
-              const bool flip = (dE <= 0.0) || (u[r] < exp_nonpos(-q.beta * dE));
-              if (flip) {
-                s[r] = -si;
-                ++acc;
-              }
-              slot[i & 1] = flip ? -si : 0;
+      for (int w = 0; w < NW; ++w) {
+        const int n = NW * r + w;  // block n: wave w, register r
+        if (n >= NB) break;        // uniform over the workgroup
+        const int buf = n & 1;
+        // ---- A: the block's proposals, in order, on wave w
+        if (wave == w) {
+          const int kmax = min(DMH_BLK, N - DMH_BLK * n);
+          double fl = f[r];
+          int sl = s[r];
+          for (int k = 0; k < kmax; ++k) {
+            const double dE = 2.0 * (double)sl * (q.J * fl + hv[r]);
+            const int take = __builtin_amdgcn_readlane((dE <= 0.0 || dE < thr[r]) ? 1 : 0, k);
+            if (take) {
+              const int sk = -__builtin_amdgcn_readlane(sl, k);  // the new spin of site k
+              if (lane == k)
+                sl = sk;
+              else
+                fl = __builtin_fma(sKd[buf][k * DMH_BLK + lane], 2.0 * (double)sk, fl);
             }
-            lds_barrier();
-            const int v = slot[i & 1];
-            if (v != 0) {
-              const double dv = 2.0 * (double)v;
+          }
+          const bool flipped = (lane < kmax) && (sl != s[r]);
+          const unsigned long long mask = __ballot(flipped);
+          if (flipped) {
+            const int idx = __popcll(mask & ((1ull << lane) - 1ull));
+            sList[buf][idx] = lane;
+            sNew[buf][idx] = sl;
+          }
+          if (lane == 0) sCount[buf] = __popcll(mask);
+          acc += flipped ? 1ull : 0ull;
+          f[r] = fl;
+          s[r] = sl;
+        }
+        __syncthreads();
+        // ---- B: the block's flips into every other field; the next diagonal block staged
+        double v[DMH_BLK * DMH_BLK / DMH_THREADS];
+        if (n + 1 < NB) diag_load(n + 1, v);
+        const int cnt = sCount[buf];
+        for (int q0 = 0; q0 < cnt; q0 += DMH_Q) {
+          double kr[DMH_Q][R];
 #pragma unroll
-              for (int rr = 0; rr < R; ++rr) {
-                const int j = t + DMH_THREADS * rr;
-                if (j != i) f[rr] = __builtin_fma(kb[d][rr], dv, f[rr]);
-              }
+          for (int qq = 0; qq < DMH_Q; ++qq) {
+            const int k = (q0 + qq < cnt) ? sList[buf][q0 + qq] : sList[buf][q0];
+            const double* row = K + (int64_t)(DMH_BLK * n + k) * Np + t;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) kr[qq][rr] = row[DMH_THREADS * rr];
+          }
+#pragma unroll
+          for (int qq = 0; qq < DMH_Q; ++qq) {
+            if (q0 + qq < cnt) {
+              const double dv = 2.0 * (double)sNew[buf][q0 + qq];
+#pragma unroll
+              for (int rr = 0; rr < R; ++rr)
+                if (rr != r || wave != w) f[rr] = __builtin_fma(kr[qq][rr], dv, f[rr]);
             }
-            // refill this ring entry with row i + D (rows N .. N + D - 1 are zeros)
-            const double* rowp = K + (int64_t)(i + D) * Np + t;
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) kb[d][rr] = rowp[DMH_THREADS * rr];
           }
         }
+        if (n + 1 < NB) diag_store(buf ^ 1, v);
+        __syncthreads();
       }
     }
     // measurement of the sweep: sum s, s^T K s = sum_j s_j (f_j + K_jj s_j), sum h s
@@ -332,10 +389,10 @@ __global__ __launch_bounds__(DMH_THREADS, 1) void k_dense_mh(DenseMhParams q, co
   if (t == 0) n_acc[c] = (unsigned long long)a;
 }
 
-template <int R, int D>
+template <int R>
 static void launch_dense_mh(int n_chains, hipStream_t st, const DenseMhParams& q, const double* K, const double* h,
                             const int8_t* s0, int8_t* s, int n_sweeps, double* rec, unsigned long long* n_acc) {
-  k_dense_mh<R, D><<<n_chains, DMH_THREADS, 0, st>>>(q, K, h, s0, s, n_sweeps, rec, n_acc);
+  k_dense_mh<R><<<n_chains, DMH_THREADS, 0, st>>>(q, K, h, s0, s, n_sweeps, rec, n_acc);
 }
 
 }  // namespace ihmc
@@ -468,7 +525,7 @@ extern "C" int ihmc_dense_mh_run(ihmc_ctx* ctx, const ihmc_dense* model, int32_t
       if (model->K[i * N + k] != model->K[k * N + i])
         return set_error(IHMC_E_INVAL, "dense Metropolis-Hastings: K must be exactly symmetric (entry %lld, %lld)",
                          (long long)i, (long long)k);
-  // sites per thread; the read-ahead depth shrinks as R grows (registers)
+  // sites per thread
   const int R = N <= DMH_THREADS ? 1 : N <= 2 * DMH_THREADS ? 2 : N <= 4 * DMH_THREADS ? 4 : 8;
   DenseMhParams q;
   std::memset(&q, 0, sizeof q);
@@ -481,7 +538,9 @@ extern "C" int ihmc_dense_mh_run(ihmc_ctx* ctx, const ihmc_dense* model, int32_t
   q.J = model->J;
   q.beta = model->beta;
   q.h0 = model->h_len == 1 ? model->h[0] : 0.0;
-  const uint64_t kbytes = 8ull * (uint64_t)(N + 8) * (uint64_t)q.Np;  // 8 zero rows for the read-ahead
+  // rows padded with zeros to whole 64-site blocks (the diagonal blocks staged)
+  const uint64_t krows = (uint64_t)((N + DMH_BLK - 1) / DMH_BLK) * DMH_BLK;
+  const uint64_t kbytes = 8ull * krows * (uint64_t)q.Np;
   const uint64_t hbytes = q.h_kind == 2 ? 8ull * (uint64_t)N : 0;
   const uint64_t sbytes = (uint64_t)n_chains * (uint64_t)N;
   const uint64_t rbytes = 24ull * (uint64_t)n_chains * (uint64_t)std::max(1, n_sweeps);
@@ -510,10 +569,10 @@ extern "C" int ihmc_dense_mh_run(ihmc_ctx* ctx, const ihmc_dense* model, int32_t
   if (e == hipSuccess) e = hipEventRecord(e0, st);
   if (e == hipSuccess) {
     switch (R) {
-      case 1: launch_dense_mh<1, 8>(n_chains, st, q, dK, dh, ds0, ds, n_sweeps, rec, nacc); break;
-      case 2: launch_dense_mh<2, 8>(n_chains, st, q, dK, dh, ds0, ds, n_sweeps, rec, nacc); break;
-      case 4: launch_dense_mh<4, 8>(n_chains, st, q, dK, dh, ds0, ds, n_sweeps, rec, nacc); break;
-      default: launch_dense_mh<8, 2>(n_chains, st, q, dK, dh, ds0, ds, n_sweeps, rec, nacc); break;
+      case 1: launch_dense_mh<1>(n_chains, st, q, dK, dh, ds0, ds, n_sweeps, rec, nacc); break;
+      case 2: launch_dense_mh<2>(n_chains, st, q, dK, dh, ds0, ds, n_sweeps, rec, nacc); break;
+      case 4: launch_dense_mh<4>(n_chains, st, q, dK, dh, ds0, ds, n_sweeps, rec, nacc); break;
+      default: launch_dense_mh<8>(n_chains, st, q, dK, dh, ds0, ds, n_sweeps, rec, nacc); break;
     }
     e = hipGetLastError();
   }
