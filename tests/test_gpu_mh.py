@@ -62,7 +62,9 @@ def _sym(rng, N, diag):
     return K
 
 
-@pytest.mark.parametrize("N,beta,hk,diag,given", [(100, 1.0, "none", False, False), (512, 1.2, "uniform", True, False),
+@pytest.mark.parametrize("N,beta,hk,diag,given", [(1, 0.7, "uniform", True, False), (64, 1.1, "site", False, False),
+                                                  (65, 0.9, "none", True, True), (100, 1.0, "none", False, False),
+                                                  (513, 1.0, "site", False, False), (512, 1.2, "uniform", True, False),
                                                   (777, 0.9, "site", False, True), (1500, 1.0, "none", True, False),
                                                   (2049, 0.7, "site", True, False), (4096, 1.0, "none", False, False),
                                                   (4096, 0.8, "uniform", False, True)])
@@ -71,10 +73,11 @@ def test_dense_mh_equal_to_oracle(ctx, orc, N, beta, hk, diag, given):
     local field afresh): the same spins after the last sweep and the same m and
     acceptance, bit for bit; beta*eps to 1e-12 (the GPU's fields are carried
     from flip to flip, so H differs by rounding).  Sizes span one to eight
-    sites per thread with ragged last rows."""
+    sites per thread, one site, one whole 64-site block and partial last
+    blocks."""
     from paper_1912_03278_amd import ihmc
     rng = np.random.default_rng(N)
-    K = _sym(rng, N, 0.5 if diag else 0.0)
+    K = _sym(rng, N, 0.5 if diag else 0.0) if N > 1 else np.array([[0.3 if diag else 0.0]])
     h = None if hk == "none" else (np.array([0.05]) if hk == "uniform" else 0.1 * rng.standard_normal(N))
     n_chains, n_sweeps = 3, (4 if N > 2000 else 8)
     s0 = np.where(rng.random((n_chains, N)) < 0.6, 1, -1).astype(np.int8) if given else None
