@@ -362,7 +362,8 @@ int ihmc_checkpoint(ihmc_server* server, uint64_t ticket, void* buf, uint64_t* b
  * IHMC_E_INVAL for a buffer that is not such a checkpoint or is truncated, and
  * for a chain state that does not match its parameters.  Thread-safe. */
 int ihmc_restore(ihmc_server* server, const void* buf, uint64_t bytes, uint64_t* ticket);
-/* out[4]: state (IHMC_REQ_*), lattice sites, n_traj, trajectories done.
+/* out[4]: state (IHMC_REQ_*), lattice sites, n_traj, trajectories done or
+ * enqueued (the server enqueues a round while the previous one runs).
  * Thread-safe. */
 int ihmc_request_info(ihmc_server* server, uint64_t ticket, int64_t* out);
 /* out[10]: rounds, seconds spent in rounds, site-MD-steps done, largest

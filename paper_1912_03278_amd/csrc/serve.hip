@@ -11,7 +11,10 @@
 // on the device between rounds.  A chain's arithmetic depends only on its own
 // parameters (fixed-point sums, per-site work independent of the tile and of
 // the other chains in a launch), so a served result is bit-identical to the
-// same request run alone.
+// same request run alone.  A round is enqueued while the previous one still
+// runs (the host's per-request trajectory counts advance at enqueue); the
+// set-up of admitted requests, retirement and checkpoints wait for the rounds
+// in flight.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -164,8 +167,18 @@ struct ihmc_server {
   std::vector<ChainDev> cd_host;  // slot table
   std::vector<int> free_slots;
   Tile* d_tiles = nullptr;
-  Tile* h_tiles = nullptr;  // pinned staging of the tile table
+  Tile* h_tiles = nullptr;  // pinned staging of the tile table (set-up of admitted chains)
   size_t tile_cap = 0;
+  // the rounds' tile tables, two of each: a round is enqueued while the one
+  // before it still runs, so its table goes to the other buffer; copy_ev[b]
+  // marks the upload from rh_tiles[b], which the host waits for before it
+  // writes that staging buffer again
+  Tile* rd_tiles[2] = {nullptr, nullptr};
+  Tile* rh_tiles[2] = {nullptr, nullptr};
+  hipEvent_t copy_ev[2] = {nullptr, nullptr};
+  bool copy_pending[2] = {false, false};
+  size_t rtile_cap = 0;
+  int round_buf = 0;
   double* d_export = nullptr;
   int64_t export_cap = 0;
   // statistics
@@ -183,6 +196,7 @@ struct ihmc_server {
   void retire(Request* r, int32_t final_state);
   void fail_all(const char* what, hipError_t e);
   bool ensure_tiles(size_t n);
+  bool ensure_round_tiles(size_t n);
   bool ensure_streams(size_t n_groups, size_t n_events);
   void take_checkpoints();
   void resume_requests(std::vector<Request*>& ok);
@@ -292,6 +306,33 @@ bool ihmc_server::ensure_tiles(size_t n) {
   return true;
 }
 
+// Both round tile tables with room for n tiles.  Growing them waits for the
+// rounds in flight, which read the old ones.
+bool ihmc_server::ensure_round_tiles(size_t n) {
+  if (n <= rtile_cap) return true;
+  if (hipStreamSynchronize(s) != hipSuccess) return false;
+  const size_t cap = std::max<size_t>(n, 2 * rtile_cap);
+  for (int b = 0; b < 2; ++b) {
+    if (rd_tiles[b]) ctx->arena.release(rd_tiles[b]);
+    if (rh_tiles[b]) hipHostFree(rh_tiles[b]);
+    rd_tiles[b] = nullptr;
+    rh_tiles[b] = nullptr;
+    copy_pending[b] = false;
+  }
+  rtile_cap = 0;
+  for (int b = 0; b < 2; ++b) {
+    if (!copy_ev[b] && hipEventCreateWithFlags(&copy_ev[b], hipEventDisableTiming) != hipSuccess) return false;
+    rd_tiles[b] = (Tile*)ctx->arena.alloc(sizeof(Tile) * cap);
+    if (!rd_tiles[b]) return false;
+    if (hipHostMalloc((void**)&rh_tiles[b], sizeof(Tile) * cap, 0) != hipSuccess) {
+      rh_tiles[b] = nullptr;
+      return false;
+    }
+  }
+  rtile_cap = cap;
+  return true;
+}
+
 bool ihmc_server::ensure_streams(size_t n_groups, size_t n_events) {
   while (side.size() < n_groups) {
     hipStream_t st = nullptr;
@@ -361,8 +402,10 @@ bool ihmc_server::admit_setup(std::vector<Request*>& fresh) {
   std::vector<int> cg_slots;
   std::vector<int64_t> cg_off;
   int64_t cg_total = 0;
-  hipError_t e = hipSuccess;
+  // the set-up runs with the device idle: the round in flight finishes first
+  hipError_t e = hipStreamSynchronize(s);
   for (Request* r : fresh) {
+    if (e != hipSuccess) break;
     ChainDev& c = r->cd;
     describe_chain(r->lat, r->run, 0, r->cls, c);
     const uint64_t pb = (uint64_t)c.precision;
@@ -495,23 +538,31 @@ bool ihmc_server::run_round() {
   std::vector<Group> g;
   std::vector<Tile> tiles;
   plan_groups(cd_host, slots, g, tiles, ctx->fuse_steps != 0);
-  const auto t_start = std::chrono::steady_clock::now();
+  // The round is enqueued without waiting for it: the host plans and submits
+  // the next round while this one runs (every request advances by exactly one
+  // trajectory per round, so the host's counts do not need the device).  Only
+  // retirement, admission and checkpoints wait for the rounds in flight.
+  const int b = round_buf;
+  round_buf ^= 1;
   hipError_t e = hipSuccess;
-  if (!ensure_tiles(tiles.size()) || !ensure_streams(g.size(), round_events(g))) e = hipErrorOutOfMemory;
-  if (e == hipSuccess) {
-    std::memcpy(h_tiles, tiles.data(), sizeof(Tile) * tiles.size());
-    e = hipMemcpyAsync(d_tiles, h_tiles, sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, s);
+  if (!ensure_round_tiles(tiles.size()) || !ensure_streams(g.size(), round_events(g))) e = hipErrorOutOfMemory;
+  if (e == hipSuccess && copy_pending[b]) {
+    e = hipEventSynchronize(copy_ev[b]);  // the upload two rounds back has read rh_tiles[b]
+    copy_pending[b] = false;
   }
-  if (e == hipSuccess) e = enqueue_round_plan(g, d_tiles, d_cd, side, events, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) {
+    std::memcpy(rh_tiles[b], tiles.data(), sizeof(Tile) * tiles.size());
+    e = hipMemcpyAsync(rd_tiles[b], rh_tiles[b], sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, s);
+  }
+  if (e == hipSuccess) e = hipEventRecord(copy_ev[b], s);
+  if (e == hipSuccess) copy_pending[b] = true;
+  if (e == hipSuccess) e = enqueue_round_plan(g, rd_tiles[b], d_cd, side, events, s);
   if (e != hipSuccess) {
     fail_all("round", e);
     return false;
   }
-  const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   std::lock_guard<std::mutex> lk(mu);
   ++rounds;
-  busy_s += dt;
   site_steps += work;
   for (Request* r : active)
     if (!r->cancel && r->rounds < r->run.n_traj) ++r->rounds;
@@ -521,6 +572,7 @@ bool ihmc_server::run_round() {
 void ihmc_server::loop() {
   hipSetDevice(ctx->device);
   for (;;) {
+    const auto t_iter = std::chrono::steady_clock::now();
     std::vector<Request*> fresh, finished;
     bool quit = false;
     {
@@ -559,6 +611,11 @@ void ihmc_server::loop() {
     }
     if (!fresh.empty() && !admit_setup(fresh)) return;
     if (!run_round()) return;
+    // busy time: the iterations that had resident chains (set-up, retirement and
+    // the waits for rounds in flight included)
+    const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_iter).count();
+    std::lock_guard<std::mutex> lk(mu);
+    busy_s += dt;
   }
 }
 
@@ -611,6 +668,11 @@ extern "C" int ihmc_server_destroy(ihmc_server* sv) {
   if (sv->s) hipStreamDestroy(sv->s);
   if (sv->d_tiles) sv->ctx->arena.release(sv->d_tiles);
   if (sv->h_tiles) hipHostFree(sv->h_tiles);
+  for (int b = 0; b < 2; ++b) {
+    if (sv->rd_tiles[b]) sv->ctx->arena.release(sv->rd_tiles[b]);
+    if (sv->rh_tiles[b]) hipHostFree(sv->rh_tiles[b]);
+    if (sv->copy_ev[b]) hipEventDestroy(sv->copy_ev[b]);
+  }
   if (sv->d_export) sv->ctx->arena.release(sv->d_export);
   if (sv->d_cd) sv->ctx->arena.release(sv->d_cd);
   delete sv;
