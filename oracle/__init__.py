@@ -54,7 +54,7 @@ class _Dense(C.Structure):
 
 class _Run(C.Structure):
     _fields_ = [("n_md", C.c_int32), ("traj_len", C.c_double), ("n_traj", C.c_int32),
-                ("flip_every", C.c_int32), ("integrator", C.c_int32), ("pad", C.c_int32),
+                ("flip_every", C.c_int32), ("integrator", C.c_int32), ("form", C.c_int32),
                 ("seed", C.c_uint64), ("chain_id", C.c_uint64),
                 ("psi0", C.POINTER(C.c_double)), ("replay_accept", C.POINTER(C.c_uint8))]
 
@@ -91,6 +91,9 @@ def lib():
         L.orc_hamiltonian.argtypes = [lp, dnp, dp, dp, dp]
         L.orc_md.argtypes = [lp, dnp, C.c_int32, C.c_double, C.c_int32, dp, dp]
         L.orc_constants.argtypes = [lp, dnp, dp]
+        L.orc_shifted_force.argtypes = [lp, dnp, dp, dp]
+        L.orc_shifted_action.argtypes = [lp, dnp, dp, dp]
+        L.orc_shifted_md.argtypes = [lp, dnp, C.c_int32, C.c_double, C.c_int32, dp, dp]
         L.orc_run_lattice.argtypes = [lp, C.POINTER(_Run), C.POINTER(_Result)]
         L.orc_run_dense.argtypes = [dnp, C.POINTER(_Run), C.POINTER(_Result)]
         L.orc_phi_force.argtypes = [lp, dnp, dp, dp]
@@ -192,6 +195,15 @@ def uniform(seed, chain, traj, tag):
     return lib().orc_uniform(seed, chain, traj, tag)
 
 
+FORMS = {"psi": 0, "shifted": 2}
+
+
+def _shifted(form):
+    if form not in FORMS:
+        raise ValueError("form must be 'psi' or 'shifted'")
+    return form == "shifted"
+
+
 def apply_Kt(model, psi):
     psi = _f64(psi)
     u = np.empty_like(psi)
@@ -203,11 +215,13 @@ def apply_Kt(model, psi):
     return u
 
 
-def force(model, psi):
+def force(model, psi, form="psi"):
+    """F = -dS/dpsi; form "shifted": the action with h' inside the log cosh."""
     psi = _f64(psi)
     F = np.empty_like(psi)
     a, d, keep = _model(model)
-    if lib().orc_force(a, d, _dp(psi), _dp(F)):
+    fn = lib().orc_shifted_force if _shifted(form) else lib().orc_force
+    if fn(a, d, _dp(psi), _dp(F)):
         raise ValueError("invalid model")
     return F
 
@@ -215,12 +229,14 @@ def force(model, psi):
 ACTION_KEYS = ("S", "m", "abs_m", "m2c", "beta_eps", "sum_psi", "sum_psih", "sum_ut")
 
 
-def action(model, psi):
-    """S(psi) and the per-configuration estimators (dict)."""
+def action(model, psi, form="psi"):
+    """S(psi) and the per-configuration estimators (dict).  For the shifted
+    form sum_ut holds sum y tanh(y), y = sqrt(J') Kt psi + h'."""
     psi = _f64(psi)
     out = np.empty(8)
     a, d, keep = _model(model)
-    if lib().orc_action(a, d, _dp(psi), _dp(out)):
+    fn = lib().orc_shifted_action if _shifted(form) else lib().orc_action
+    if fn(a, d, _dp(psi), _dp(out)):
         raise ValueError("invalid model")
     return dict(zip(ACTION_KEYS, out.tolist()))
 
@@ -234,11 +250,12 @@ def hamiltonian(model, psi, p):
     return H.value
 
 
-def md(model, psi, p, n_md, traj_len=1.0, integrator=LEAPFROG):
+def md(model, psi, p, n_md, traj_len=1.0, integrator=LEAPFROG, form="psi"):
     """Integrate one trajectory; returns new (psi, p) copies."""
     psi, p = _f64(psi).copy(), _f64(p).copy()
     a, d, keep = _model(model)
-    if lib().orc_md(a, d, int(n_md), float(traj_len), int(integrator), _dp(psi), _dp(p)):
+    fn = lib().orc_shifted_md if _shifted(form) else lib().orc_md
+    if fn(a, d, int(n_md), float(traj_len), int(integrator), _dp(psi), _dp(p)):
         raise ValueError("invalid model")
     return psi, p
 
@@ -365,7 +382,9 @@ def run(model, n_traj, n_md, traj_len=1.0, seed=0, chain_id=0, psi0=None,
     form "psi": the substituted field (eq. phi_psi_substitution), psi0 the
     starting psi; form "phi": the inverse formulation (eq. cosh_in_exponent,
     leap-frog only, no flips), psi0 then the starting phi (None: the TAG_INIT
-    psi0 mapped by phi = sqrt(J') Kt psi0 - h'); psi_final holds the final phi."""
+    psi0 mapped by phi = sqrt(J') Kt psi0 - h'); psi_final holds the final phi;
+    form "shifted": the substitution phi = sqrt(J') Kt psi (h' inside the log
+    cosh; flips only at h = 0)."""
     N = model.N
     out = {k: np.zeros(n_traj) for k in ("dH", "m", "abs_m", "m2c", "beta_eps", "H_old", "H_new")}
     acc = np.zeros(n_traj, dtype=np.uint8)
@@ -375,6 +394,8 @@ def run(model, n_traj, n_md, traj_len=1.0, seed=0, chain_id=0, psi0=None,
     r.n_md, r.traj_len, r.n_traj = int(n_md), float(traj_len), int(n_traj)
     r.flip_every, r.integrator = int(flip_every), int(integrator)
     r.seed, r.chain_id = int(seed), int(chain_id)
+    if form != "phi":
+        r.form = FORMS[form] if form in FORMS else -1
     p0 = _f64(psi0)
     r.psi0 = _dp(p0)
     ra = None if replay_accept is None else np.ascontiguousarray(replay_accept, dtype=np.uint8)

@@ -38,6 +38,10 @@
  *                         - sqrt(J')/(2N) (Kt psi).tanh(sqrt(J') Kt psi)
  *              (eqs. formula_for_m and formula_for_e written for a general
  *              field; they reduce to the printed forms for constant h)
+ *   shifted    the substitution phi = sqrt(J') Kt psi in eq. did_HS_trafo
+ *              (field inside the log cosh, no linear term), with the paper's
+ *              estimators carried over by psi -> psi + Kt^-1 h'/sqrt(J')
+ *                                                [Sec. 2, eqs. did_HS_trafo, phi_psi_substitution]
  *   phi form   the inverse formulation of eq. cosh_in_exponent  [Sec. 2]
  *   MH         single-spin Metropolis-Hastings on the spins, checkerboard
  *              sweeps on a lattice and sequential sweeps with an explicit
@@ -51,6 +55,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+#define ORC_FORM_PSI 0
+#define ORC_FORM_SHIFTED 2
 
 #define ORC_TAG_INIT 1u
 #define ORC_TAG_MOM 2u
@@ -87,7 +94,7 @@ typedef struct {
     int32_t n_traj;        /* trajectories */
     int32_t flip_every;    /* 0: no sign-flip proposals */
     int32_t integrator;    /* ORC_LEAPFROG | ORC_OMELYAN */
-    int32_t pad;
+    int32_t form;          /* ORC_FORM_PSI (0) | ORC_FORM_SHIFTED (2) */
     uint64_t seed;         /* Philox key */
     uint64_t chain_id;     /* Philox counter word 2 (low 32 bits used) */
     const double* psi0;    /* NULL: psi0 ~ N(0,1) from the TAG_INIT stream */
@@ -187,6 +194,7 @@ typedef struct {
     double c_m;           /* 1^T Kt^-1 h' */
     double c_e;           /* h'^T Kt^-1 h' */
     double c_v;           /* 1^T Kt^-1 1 */
+    int shifted;          /* the h'-inside-log-cosh form (see action) */
     double* scratch[4];   /* work vectors of length N */
 } model;
 
@@ -325,7 +333,13 @@ static double logcosh(double y) {
     return a + log1p(exp(-2.0 * a)) - 0.6931471805599453;
 }
 
-/* S(psi) and the observable partial sums.  `u` receives Kt psi. */
+/* S(psi) and the observable partial sums.  `u` receives Kt psi.
+ *
+ * The shifted form substitutes phi = sqrt(J') Kt psi in eq. did_HS_trafo
+ * instead of phi = sqrt(J') Kt psi - h' (eq. phi_psi_substitution); both are
+ * exact.  The field then sits inside the log cosh and the linear term drops:
+ *     S(psi) = 1/2 psi.Kt psi - sum_i log cosh(sqrt(J') (Kt psi)_i + h'_i).
+ * For such a model sum_ut holds sum_i y_i tanh(y_i), y = sqrt(J') Kt psi + h'. */
 typedef struct { double S, sum_psi, sum_psih, sum_ut; } action_parts;
 
 static action_parts action(const model* M, const double* psi, double* u) {
@@ -333,27 +347,39 @@ static action_parts action(const model* M, const double* psi, double* u) {
     apply_Kt(M, psi, u);
     nsum S = {0, 0}, sp = {0, 0}, sph = {0, 0}, sut = {0, 0};
     for (int64_t i = 0; i < N; ++i) {
-        double y = M->sqJ * u[i];
+        const double hpi = M->hp ? M->hp[i] : 0.0;
         ns_add(&S, 0.5 * psi[i] * u[i]);
-        if (M->b) ns_add(&S, -psi[i] * M->b[i]);
-        ns_add(&S, -logcosh(y));
         ns_add(&sp, psi[i]);
-        if (M->hp) ns_add(&sph, psi[i] * M->hp[i]);
-        ns_add(&sut, u[i] * tanh(y));
+        if (M->hp) ns_add(&sph, psi[i] * hpi);
+        if (M->shifted) {
+            double y = M->sqJ * u[i] + hpi;
+            ns_add(&S, -logcosh(y));
+            ns_add(&sut, y * tanh(y));
+        } else {
+            double y = M->sqJ * u[i];
+            if (M->b) ns_add(&S, -psi[i] * M->b[i]);
+            ns_add(&S, -logcosh(y));
+            ns_add(&sut, u[i] * tanh(y));
+        }
     }
     action_parts a = { ns_val(&S), ns_val(&sp), ns_val(&sph), ns_val(&sut) };
     return a;
 }
 
-/* F = -dS/dpsi = Kt (sqrt(J') tanh(sqrt(J') Kt psi) - psi) + h'/sqrt(J'). */
+/* F = -dS/dpsi = Kt (sqrt(J') tanh(sqrt(J') Kt psi) - psi) + h'/sqrt(J');
+ * shifted form: F = Kt (sqrt(J') tanh(sqrt(J') Kt psi + h') - psi). */
 static void force(const model* M, const double* psi, double* F) {
     const int64_t N = M->N;
     double* u = M->scratch[2];
     double* w = M->scratch[3];
     apply_Kt(M, psi, u);
-    for (int64_t i = 0; i < N; ++i) w[i] = M->sqJ * tanh(M->sqJ * u[i]) - psi[i];
+    for (int64_t i = 0; i < N; ++i) {
+        double y = M->sqJ * u[i];
+        if (M->shifted && M->hp) y += M->hp[i];
+        w[i] = M->sqJ * tanh(y) - psi[i];
+    }
     apply_Kt(M, w, F);
-    if (M->b)
+    if (M->b && !M->shifted)
         for (int64_t i = 0; i < N; ++i) F[i] += M->b[i];
 }
 
@@ -369,12 +395,21 @@ typedef struct { double m, abs_m, m2c, beta_eps; } observables;
 static observables estimators(const model* M, const action_parts* a) {
     const double N = (double)M->N;
     observables o;
-    o.m = (a->sum_psi / M->sqJ - M->c_m / M->Jp) / N;
+    if (M->shifted) {
+        /* The paper's estimators at psi + Kt^-1 h'/sqrt(J'), the point of the
+         * substituted field that carries the same phi: the Kt^-1 terms cancel,
+         * m = sum psi / (N sqrt(J')) and
+         * beta*eps = C J'/2 - psi.h'/(2 N sqrt(J')) - sum_i y_i tanh(y_i) / (2N). */
+        o.m = a->sum_psi / M->sqJ / N;
+        o.beta_eps = 0.5 * M->C * M->Jp - a->sum_psih / (2.0 * N * M->sqJ) - a->sum_ut / (2.0 * N);
+    } else {
+        o.m = (a->sum_psi / M->sqJ - M->c_m / M->Jp) / N;
+        o.beta_eps = 0.5 * M->C * M->Jp + M->c_e / (2.0 * N * M->Jp)
+                   - a->sum_psih / (2.0 * N * M->sqJ)
+                   - M->sqJ / (2.0 * N) * a->sum_ut;
+    }
     o.abs_m = fabs(o.m);
     o.m2c = o.m * o.m - M->c_v / (N * N * M->Jp);
-    o.beta_eps = 0.5 * M->C * M->Jp + M->c_e / (2.0 * N * M->Jp)
-               - a->sum_psih / (2.0 * N * M->sqJ)
-               - M->sqJ / (2.0 * N) * a->sum_ut;
     return o;
 }
 
@@ -412,9 +447,15 @@ static void md(const model* M, int n_md, double tau, int integrator, double* psi
     }
 }
 
-static int hmc(const model* M, const orc_run* R, orc_result* out) {
-    const int64_t N = M->N;
+static int hmc(const model* M0, const orc_run* R, orc_result* out) {
+    const int64_t N = M0->N;
     if (R->n_md < 1 || R->n_traj < 0 || !(R->traj_len > 0)) return -1;
+    if (R->form != ORC_FORM_PSI && R->form != ORC_FORM_SHIFTED) return -1;
+    model Mf = *M0;
+    Mf.shifted = R->form == ORC_FORM_SHIFTED;
+    const model* M = &Mf;
+    /* psi -> -psi leaves the shifted action unchanged only at h = 0. */
+    if (M->shifted && M->hp && R->flip_every > 0) return -1;
     double* psi = (double*)malloc(sizeof(double) * N);
     double* trial = (double*)malloc(sizeof(double) * N);
     double* p = (double*)malloc(sizeof(double) * N);
@@ -734,6 +775,37 @@ int orc_constants(const orc_lattice* lat, const orc_dense* d, double* out) {
     return 0;
 }
 
+/* The same three with the shifted form (h' inside the log cosh). */
+int orc_shifted_force(const orc_lattice* lat, const orc_dense* d, const double* psi, double* F) {
+    model M;
+    if (with_model(lat, d, &M)) { model_free(&M); return -1; }
+    M.shifted = 1;
+    force(&M, psi, F);
+    model_free(&M);
+    return 0;
+}
+int orc_shifted_action(const orc_lattice* lat, const orc_dense* d, const double* psi, double* out) {
+    model M;
+    if (with_model(lat, d, &M)) { model_free(&M); return -1; }
+    M.shifted = 1;
+    double* u = (double*)malloc(sizeof(double) * M.N);
+    action_parts a = action(&M, psi, u);
+    observables o = estimators(&M, &a);
+    out[0] = a.S; out[1] = o.m; out[2] = o.abs_m; out[3] = o.m2c; out[4] = o.beta_eps;
+    out[5] = a.sum_psi; out[6] = a.sum_psih; out[7] = a.sum_ut;
+    free(u);
+    model_free(&M);
+    return 0;
+}
+int orc_shifted_md(const orc_lattice* lat, const orc_dense* d, int32_t n_md, double traj_len,
+                   int32_t integrator, double* psi, double* p) {
+    model M;
+    if (with_model(lat, d, &M) || n_md < 1) { model_free(&M); return -1; }
+    M.shifted = 1;
+    md(&M, n_md, traj_len, integrator, psi, p);
+    model_free(&M);
+    return 0;
+}
 int orc_run_lattice(const orc_lattice* lat, const orc_run* run, orc_result* res) {
     model M;
     if (lattice_model(&M, lat)) { model_free(&M); return -1; }
