@@ -58,6 +58,13 @@ extern "C" {
 #define IHMC_FORM_PHI 1 /* phi of eq. cosh_in_exponent: a CG solve of Kt per force evaluation;
                            the A/B baseline of the substitution (FP64 leap-frog lattice chains of
                            at most 1453 sites, 1272 with a per-site field; no flips) */
+#define IHMC_FORM_SHIFTED 2 /* psi of the substitution phi = sqrt(J') Kt psi in eq. did_HS_trafo:
+                           S = 1/2 psi.Kt psi - sum log cosh(sqrt(J') (Kt psi)_i + h'), no linear
+                           term; the same fused passes (lattice chains with h = 0 or a uniform
+                           field; flips only at h = 0).  psi differs from the paper's by the
+                           constant Kt^-1 h'/sqrt(J'); the records hold the paper's estimators at
+                           that translate: m = sum psi/(N sqrt(J')), beta*eps = C J'/2
+                           - psi.h'/(2N sqrt(J')) - sum y tanh(y)/(2N), y = sqrt(J') Kt psi + h' */
 
 #define IHMC_TAG_INIT 1u /* Philox stream tags (counter word 3) */
 #define IHMC_TAG_MOM 2u
@@ -134,7 +141,11 @@ typedef struct {
  *               the TAG_INIT normals, the substitution that links the forms),
  *               psi_final the final phi, and the records hold the spin
  *               expectations given phi (m = mean tanh(h' + phi), m^2 and beta*eps
- *               likewise, no bias correction needed). */
+ *               likewise, no bias correction needed).  IHMC_FORM_SHIFTED: psi0
+ *               is the starting psi of that form (NULL: the TAG_INIT normals);
+ *               a per-site field, or flips at h != 0, give IHMC_E_UNSUPPORTED /
+ *               IHMC_E_INVAL; dense chains and the server take IHMC_FORM_PSI
+ *               only. */
 typedef struct {
   int32_t n_md;
   int32_t n_traj;

@@ -92,6 +92,13 @@ __device__ __forceinline__ uint32_t finalize_trajectory(const ChainDev& cd, Chai
       rec.abs_m = fabs(rec.m);
       rec.m2c = (sum_psi * sum_psi - sum_t2 + N) / (N * N);
       rec.beta_eps = (-0.5 * cd.Jp * sum_ut - sum_psih) / N;
+    } else if (cd.form == FORM_SHIFTED) {
+      // the paper's estimators at psi + Kt^-1 h'/sqrt(J'): no Kt^-1 terms;
+      // sum_ut holds sum y tanh(y), y = sqrt(J') u + h'
+      rec.m = sum_psi / cd.sqJ / N;
+      rec.abs_m = fabs(rec.m);
+      rec.m2c = rec.m * rec.m - cd.c_v / (N * N * cd.Jp);
+      rec.beta_eps = 0.5 * cd.C * cd.Jp - sum_psih / (2.0 * N * cd.sqJ) - sum_ut / (2.0 * N);
     } else {
       rec.m = (sum_psi / cd.sqJ - cd.c_m / cd.Jp) / N;
       rec.abs_m = fabs(rec.m);

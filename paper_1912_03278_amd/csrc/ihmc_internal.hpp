@@ -10,9 +10,11 @@ enum : uint32_t { TAG_INIT = 1u, TAG_MOM = 2u, TAG_ACC = 3u, TAG_FLIP = 4u };
 enum Integrator : int32_t { LEAPFROG = 0, OMELYAN = 1 };
 
 // Field of the chain: psi of the substituted action (eq. phi_psi_substitution,
-// the hot path) or phi of the inverse formulation (eq. cosh_in_exponent, whose
-// force needs a linear solve per evaluation; the A/B baseline).
-enum Form : int32_t { FORM_PSI = 0, FORM_PHI = 1 };
+// the hot path), phi of the inverse formulation (eq. cosh_in_exponent, whose
+// force needs a linear solve per evaluation; the A/B baseline), or psi of the
+// substitution phi = sqrt(J') Kt psi in eq. did_HS_trafo (h' inside the log
+// cosh, no linear term; the same passes with hw != 0 and b0 = 0).
+enum Form : int32_t { FORM_PSI = 0, FORM_PHI = 1, FORM_SHIFTED = 2 };
 
 // Omelyan-Mryglod-Folk second-order minimum-norm parameter.
 constexpr double kOmelyanLambda = 0.1931833275037836;
@@ -74,6 +76,7 @@ struct ChainDev {
   uint32_t chain_id, n_tiles, seed_lo, seed_hi;
   double C, sqJ, Jp, b0, hp0, eps;
   double c_m, c_e, c_v;  // 1^T Kt^-1 h', h'^T Kt^-1 h', 1^T Kt^-1 1
+  double hw;             // h' inside the log cosh: the uniform field of a shifted-form chain, else 0
   int32_t cap;           // capacity of the record series
   int32_t precision;     // 4 or 8 (bytes of the state type)
   int32_t p_given;       // first pass reads p instead of drawing it (diagnostic)

@@ -174,13 +174,16 @@ __device__ __forceinline__ void st4<double>(double* __restrict__ p, const double
 //   h[1]  psi
 //   h[2]  psi h'
 //   h[3]  u tanh(sqrt(J') u)
+// or, in the shifted form (b0 = 0, hw = h'), with y = sqrt(J') u + h':
+//   h[0] = 1/2 psi u - log cosh(y),  h[3] = y tanh(y).
 // `act` = the site belongs to the lattice (a quad may reach into the row
 // padding, a column into the plane padding): inactive sites give exact zeros.
 __device__ __forceinline__ void h_terms(const ChainDev& cd, double v, double nb, int64_t idx, bool act,
                                         double (&h)[4]) {
   const double u = cd.C * v + nb;
+  const double y = __builtin_fma(cd.sqJ, u, cd.hw);
   double lc, th;
-  logcosh_tanh(cd.sqJ * u, lc, th);
+  logcosh_tanh(y, lc, th);
   double hpx = cd.hp0, bx = cd.b0;
   if (cd.h_kind == 2) {
     hpx = cd.hp[idx];
@@ -189,7 +192,7 @@ __device__ __forceinline__ void h_terms(const ChainDev& cd, double v, double nb,
   h[0] = act ? 0.5 * v * u - v * bx - lc : 0.0;
   h[1] = act ? v : 0.0;
   h[2] = act ? v * hpx : 0.0;
-  h[3] = act ? u * th : 0.0;
+  h[3] = act ? (cd.form == FORM_SHIFTED ? y : u) * th : 0.0;
 }
 
 // Workgroups are dealt to the eight XCDs round-robin (block b runs on XCD b % 8),
@@ -312,7 +315,7 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
   lds_barrier();
 
   const T Ct = (T)cd.C;
-  const T at = (T)cd.sqJ;
+  const T at = (T)cd.sqJ, hw = (T)cd.hw;
 
   // ---- w on the rows y in [-1, BY], in quads over x in [-4, BX+4): the
   // outermost quads hold unused values (their stencil reaches past the staged
@@ -332,7 +335,7 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
         const T xp = (e == 3) ? rgt : cv[e + 1];
         const T s = (xm + xp) + (up[e] + dn[e]);
         const T u = fma_t(Ct, cv[e], s);
-        w[e] = fma_t(at, tanh_state(at * u), -cv[e]);
+        w[e] = fma_t(at, tanh_state(fma_t(at, u, hw)), -cv[e]);
       }
       st4<T>(sW + wy * RP + 4 * c, w);
     }
@@ -478,7 +481,7 @@ __global__ __launch_bounds__(BX / 4 * BY) void lattice_pass2v(const ChainDev* __
 // expression of the one-step kernel.
 template <typename T, int RP>
 __device__ __forceinline__ void pair_w_quad(const T* __restrict__ sP, T* __restrict__ sW, int wr, int c, T Ct,
-                                            T at) {
+                                            T at, T hw) {
   const int pc = (wr + 1) * RP + 4 * c;
   T cv[4], up[4], dn[4], w[4];
   ld4<T>(sP + pc, cv);
@@ -491,7 +494,7 @@ __device__ __forceinline__ void pair_w_quad(const T* __restrict__ sP, T* __restr
     const T xp = (e == 3) ? rgt : cv[e + 1];
     const T s = (xm + xp) + (up[e] + dn[e]);
     const T u = fma_t(Ct, cv[e], s);
-    w[e] = fma_t(at, tanh_state(at * u), -cv[e]);
+    w[e] = fma_t(at, tanh_state(fma_t(at, u, hw)), -cv[e]);
   }
   st4<T>(sW + wr * RP + 4 * c, w);
 }
@@ -626,7 +629,7 @@ __global__ __launch_bounds__(BX / 4 * BY * TPQ) void lattice_pass2v_pair(const C
   lds_barrier();
 
   const T Ct = (T)cd.C;
-  const T at = (T)cd.sqJ;
+  const T at = (T)cd.sqJ, hw = (T)cd.hw;
   double kick_d = 0.0, drift_d = 0.0;
   pass_coeffs(cd, j, kick_d, drift_d);
   const T kick1 = (T)kick_d, drift1 = (T)drift_d;
@@ -635,7 +638,7 @@ __global__ __launch_bounds__(BX / 4 * BY * TPQ) void lattice_pass2v_pair(const C
 
   // ---- step j: w on the rows y in [-3, BY+3) (w-row y + 3), all chunks (the
   // outermost quad of each row holds an unused value)
-  for (int i = t; i < WR * NCH; i += NT) pair_w_quad<T, RP>(sP, sW, i / NCH, i % NCH, Ct, at);
+  for (int i = t; i < WR * NCH; i += NT) pair_w_quad<T, RP>(sP, sW, i / NCH, i % NCH, Ct, at, hw);
   lds_barrier();
   // kick and drift on the tile (momenta kept) and on the ring; each thread
   // overwrites only the psi of its own quads, which no other thread reads now
@@ -658,7 +661,7 @@ __global__ __launch_bounds__(BX / 4 * BY * TPQ) void lattice_pass2v_pair(const C
   lds_barrier();
 
   // ---- step j + 1: w on the rows y in [-1, BY+1), then kick and drift on the tile
-  for (int i = t; i < (BY + 2) * NCH; i += NT) pair_w_quad<T, RP>(sP, sW, 2 + i / NCH, i % NCH, Ct, at);
+  for (int i = t; i < (BY + 2) * NCH; i += NT) pair_w_quad<T, RP>(sP, sW, 2 + i / NCH, i % NCH, Ct, at, hw);
   lds_barrier();
   if (!has_quad) return;
   T pn[4], pv[4];
@@ -801,7 +804,7 @@ __global__ __launch_bounds__(64 * ZR, 8) void lattice_pass3t(const ChainDev* __r
   lds_barrier();
 
   const T Ct = (T)cd.C;
-  const T at = (T)cd.sqJ;
+  const T at = (T)cd.sqJ, hw = (T)cd.hw;
 
   // ---- w on the box plus its 1-wide halo, in quads over x in [-4, BX+4):
   // thread t computes chunk column t % NCH of the w rows t / NCH + RG k
@@ -830,7 +833,7 @@ __global__ __launch_bounds__(64 * ZR, 8) void lattice_pass3t(const ChainDev* __r
         T sum = (xm + xp) + (up[e] + dn[e]);
         sum = sum + (zm[e] + zp[e]);
         const T u = fma_t(Ct, cv[e], sum);
-        w[e] = fma_t(at, tanh_state(at * u), -cv[e]);
+        w[e] = fma_t(at, tanh_state(fma_t(at, u, hw)), -cv[e]);
       }
       st4<T>(sW + wz * WPL + wy * RP + 4 * c, w);
     }
@@ -1001,7 +1004,7 @@ __global__ __launch_bounds__(RES_THREADS, 2) void lattice_resident(const ChainDe
   }
   const T b_uniform = (T)cd.b0;
   const T Ct = (T)cd.C;
-  const T at = (T)cd.sqJ;
+  const T at = (T)cd.sqJ, hw = (T)cd.hw;
 
   // periodic neighbours of logical site i = x + L0 (y + L1 z)
   struct Nb {
@@ -1177,7 +1180,7 @@ __global__ __launch_bounds__(RES_THREADS, 2) void lattice_resident(const ChainDe
         T s = (sP[n.xm] + sP[n.xp]) + (sP[n.ym] + sP[n.yp]);
         if (NDIM == 3) s = s + (sP[n.zm] + sP[n.zp]);
         const T u = fma_t(Ct, c, s);
-        sW[i] = fma_t(at, tanh_state(at * u), -c);
+        sW[i] = fma_t(at, tanh_state(fma_t(at, u, hw)), -c);
       }
       __syncthreads();
       double kick_d = 0.0, drift_d = 0.0;

@@ -307,6 +307,15 @@ void describe_chain(const ihmc_lattice& l, const ihmc_run& r, int flags, int cls
   c.write_p_last = (flags & BUILD_WRITE_P) ? 1 : 0;
   c.n_therm = r.n_therm;
   c.form = r.form;
+  c.hw = 0.0;
+  if (r.form == FORM_SHIFTED) {
+    // h' moves inside the log cosh; the linear term and the Kt^-1 constants of
+    // the estimators drop (h' itself stays for the psi.h' estimator sum)
+    c.hw = c.hp0;
+    c.b0 = 0.0;
+    c.c_m = 0.0;
+    c.c_e = 0.0;
+  }
   c.tile_cls = cls;
   c.n_tiles = chain_tile_count(c);
 }
@@ -402,7 +411,14 @@ int validate(const ihmc_lattice& l, const ihmc_run& r, int idx) {
   if (r.precision != 4 && r.precision != 8) return set_error(IHMC_E_INVAL, "chain %d: precision must be 4 or 8", idx);
   if (r.flip_every < 0) return set_error(IHMC_E_INVAL, "chain %d: flip_every must be >= 0", idx);
   if (r.n_therm < 0) return set_error(IHMC_E_INVAL, "chain %d: n_therm must be >= 0", idx);
-  if (r.form != FORM_PSI && r.form != FORM_PHI) return set_error(IHMC_E_INVAL, "chain %d: unknown form", idx);
+  if (r.form != FORM_PSI && r.form != FORM_PHI && r.form != FORM_SHIFTED)
+    return set_error(IHMC_E_INVAL, "chain %d: unknown form", idx);
+  if (r.form == FORM_SHIFTED) {
+    if (l.h_len > 1)
+      return set_error(IHMC_E_UNSUPPORTED, "chain %d: the shifted form takes h = 0 or a uniform field", idx);
+    if (r.flip_every > 0 && l.h_len == 1 && l.h[0] != 0.0)
+      return set_error(IHMC_E_INVAL, "chain %d: psi -> -psi is no symmetry of the shifted form at h != 0", idx);
+  }
   if (r.form == FORM_PHI) {
     if (r.precision != 8 || r.integrator != LEAPFROG || r.flip_every != 0)
       return set_error(IHMC_E_UNSUPPORTED, "chain %d: the phi form runs FP64 leap-frog chains without flips", idx);

@@ -22,6 +22,7 @@ STATUS = {-1: "IHMC_E_INVAL", -2: "IHMC_E_NOMEM", -3: "IHMC_E_AGAIN", -4: "IHMC_
 F32, F64 = 4, 8
 LEAPFROG, OMELYAN = 0, 1
 FORM_PSI, FORM_PHI = 0, 1  # the substituted field (the hot path) / the inverse formulation (A/B baseline)
+FORM_SHIFTED = 2  # the substitution phi = sqrt(J') Kt psi: h' inside the log cosh
 FIRST, MIDDLE, LAST, PAIR = 0, 1, 2, 5  # pass kinds of Chains.time_pass
 TAG_INIT, TAG_MOM, TAG_ACC, TAG_FLIP = 1, 2, 3, 4
 

@@ -1,0 +1,157 @@
+"""GPU parity of the shifted form (IHMC_FORM_SHIFTED: h' inside the log cosh,
+no linear term) against the FP64 oracle, on the same fused passes as the paper's
+form: LDS-resident whole trajectories, tiled passes with two leap-frog steps per
+launch, and tiled passes with one.
+
+Tolerances as for the paper's form: one trajectory from identical inputs
+(psi0, Philox momenta) 1e-12 normwise in FP64 and 1e-5 in FP32; FP64 chains
+take the oracle's accept decisions.  Properties checked on the GPU alone: at
+h = 0 the two forms give the same chain (bitwise, flips included, beta*eps to
+rounding), and with a uniform field a shifted chain started at
+psi0 - Kt^-1 h'/sqrt(J') takes the paper-form chain's decisions with the same
+observables.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def nrm(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.fixture(scope="module", params=["resident", "tiled_pairs", "tiled_single"])
+def ctx(request):
+    from paper_1912_03278_amd import ihmc
+    kw = dict(arena_bytes=1 << 30)
+    if request.param == "resident":
+        kw["resident"] = -1
+    else:
+        kw["resident"] = 0
+        kw["fuse_steps"] = request.param == "tiled_pairs"
+    c = ihmc.Context(**kw)
+    yield c
+    c.close()
+
+
+CASES = [
+    ("2d_ragged_h0", (70, 19), 0.44, 4.1, None),
+    ("2d_uniform", (64, 32), 0.35, 4.3, 0.07),
+    ("2d_small_wrap", (8, 8), 0.40, 4.1, 0.1),
+    ("2d_tiles_ragged", (130, 35), 0.44, 4.1, -0.02),
+    ("3d_ragged", (67, 9, 6), 0.22, 6.1, 0.05),
+    ("3d_small_wrap", (5, 3, 7), 0.3, 6.5, 0.1),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("prec,integ", [(8, 0), (4, 0), (8, 1), (4, 1)])
+def test_one_trajectory(ctx, orc, case, prec, integ):
+    from paper_1912_03278_amd import ihmc
+    name, L, beta, C, h = case
+    N = int(np.prod(L))
+    psi = np.random.default_rng(2).standard_normal(N)
+    n_md = 7 if integ == 0 else 4
+    run = ihmc.Run(n_md=n_md, n_traj=1, precision=prec, integrator=integ, seed=5, chain_id=2,
+                   psi0=psi, replay_accept=[1], form=ihmc.FORM_SHIFTED)
+    g = ctx.run_lattice(ihmc.Lattice(L, beta=beta, C=C, h=h), run)
+    psi_ref0 = psi.astype(np.float32).astype(np.float64) if prec == 4 else psi
+    r = orc.run(orc.Lattice(L, beta=beta, C=C, h=h), 1, n_md, seed=5, chain_id=2, psi0=psi_ref0,
+                replay_accept=[1], integrator=integ, form="shifted")
+    tol = 1e-12 if prec == 8 else 1e-5
+    assert nrm(g["psi_final"], r.psi_final) < tol
+    for k in ("H_old", "H_new"):
+        assert abs(g[k][0] - getattr(r, k)[0]) <= tol * abs(getattr(r, k)[0]), k
+    for k in ("m", "m2c", "beta_eps"):
+        assert abs(g[k][0] - getattr(r, k)[0]) <= tol * max(1.0, abs(getattr(r, k)[0])), k
+
+
+@pytest.mark.parametrize("L,h", [((16, 12), 0.05), ((6, 5, 7), 0.08)])
+def test_fp64_chain_takes_the_oracles_decisions(ctx, orc, L, h):
+    from paper_1912_03278_amd import ihmc
+    beta, C = (0.42, 4.1) if len(L) == 2 else (0.22, 6.1)
+    g = ctx.run_lattice(ihmc.Lattice(L, beta=beta, C=C, h=h),
+                        ihmc.Run(n_md=8, n_traj=300, precision=8, seed=7, chain_id=4, form=ihmc.FORM_SHIFTED))
+    r = orc.run(orc.Lattice(L, beta=beta, C=C, h=h), 300, 8, seed=7, chain_id=4, form="shifted")
+    # The kernels form y = sqrt(J') u + h' with one rounding (FMA), the oracle
+    # with two; such one-ulp differences grow along the chaotic MD flow (from
+    # 1e-14 in the first trajectories to about 1e-7 after 300 on the 3D case)
+    # while every decision stays the oracle's.
+    assert np.array_equal(g["accepted"], r.accepted) and 0.5 < r.acceptance < 1.0
+    assert np.max(np.abs(g["dH"][:50] - r.dH[:50])) < 1e-9
+    assert np.max(np.abs(g["dH"] - r.dH)) < 1e-6
+    for k in ("m", "m2c", "beta_eps"):
+        assert np.max(np.abs(g[k][:50] - getattr(r, k)[:50])) < 1e-9, k
+        assert np.max(np.abs(g[k] - getattr(r, k))) < 1e-6, k
+    assert nrm(g["psi_final"], r.psi_final) < 1e-6
+
+
+@pytest.mark.parametrize("prec", [8, 4])
+def test_zero_field_equals_paper_form(ctx, prec):
+    from paper_1912_03278_amd import ihmc
+    lat = ihmc.Lattice((40, 24), beta=0.44, C=4.1)
+    out = []
+    for form in (ihmc.FORM_PSI, ihmc.FORM_SHIFTED):
+        out.append(ctx.run_lattice(lat, ihmc.Run(n_md=7, n_traj=30, precision=prec, seed=3, chain_id=1,
+                                                 flip_every=4, form=form)))
+    a, b = out
+    for k in ("dH", "accepted", "flipped", "psi_final", "m", "m2c"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.max(np.abs(a["beta_eps"] - b["beta_eps"])) < 1e-13
+    assert b["flipped"].sum() > 0
+
+
+@pytest.mark.parametrize("L", [(48, 40), (12, 10, 9)])
+def test_translate_of_the_paper_form(ctx, L):
+    """psi_paper = psi_shifted + h'/(sqrt(J') (n0 + C)) for a uniform field
+    (Kt 1 = (n0 + C) 1 on the periodic lattice, eq. hKh_for_constant_h)."""
+    from paper_1912_03278_amd import ihmc
+    beta, C, h = (0.44, 4.1, 0.03) if len(L) == 2 else (0.22, 6.1, 0.04)
+    N = int(np.prod(L))
+    lat = ihmc.Lattice(L, beta=beta, C=C, h=h)
+    delta = beta * h / (math.sqrt(beta) * (2 * len(L) + C))
+    psi0 = np.random.default_rng(8).standard_normal(N)
+    a = ctx.run_lattice(lat, ihmc.Run(n_md=8, n_traj=40, precision=8, seed=6, chain_id=2, psi0=psi0))
+    b = ctx.run_lattice(lat, ihmc.Run(n_md=8, n_traj=40, precision=8, seed=6, chain_id=2, psi0=psi0 - delta,
+                                      form=ihmc.FORM_SHIFTED))
+    assert np.array_equal(a["accepted"], b["accepted"]) and a["acceptance"] > 0.5
+    assert np.max(np.abs(a["dH"] - b["dH"])) < 1e-8
+    for k in ("m", "m2c", "beta_eps"):
+        assert np.max(np.abs(a[k] - b[k])) < 1e-10, k
+    assert np.max(np.abs(a["psi_final"] - (b["psi_final"] + delta))) < 1e-10
+
+
+def test_mixed_forms_in_one_set_equal_alone(ctx):
+    """Paper-form and shifted chains of one shape share launch groups; each
+    chain's series equal those of the chain run alone, bitwise."""
+    from paper_1912_03278_amd import ihmc
+    lats = [ihmc.Lattice((48, 40), beta=0.44, C=4.1, h=0.02 * (i + 1)) for i in range(4)]
+    lats.append(ihmc.Lattice((12, 10, 9), beta=0.22, C=6.1, h=0.03))
+    runs = [ihmc.Run(n_md=6 + i, n_traj=5, seed=4, chain_id=i, precision=4 if i % 2 else 8,
+                     form=ihmc.FORM_SHIFTED if i in (1, 2, 4) else ihmc.FORM_PSI) for i in range(5)]
+    ch = ihmc.Chains(ctx, lats, runs)
+    ch.advance(5)
+    mixed = [ch.result(i) for i in range(5)]
+    ch.close()
+    for i in range(5):
+        alone = ctx.run_lattice(lats[i], runs[i])
+        for k in ("dH", "accepted", "psi_final", "m", "m2c", "beta_eps"):
+            assert np.array_equal(mixed[i][k], alone[k]), (i, k)
+
+
+def test_refusals(ctx):
+    from paper_1912_03278_amd import ihmc
+    site = ihmc.Lattice((16, 16), beta=0.4, C=4.1, h=np.full(256, 0.01))
+    with pytest.raises(ihmc.IhmcError):
+        ctx.run_lattice(site, ihmc.Run(n_md=4, n_traj=1, form=ihmc.FORM_SHIFTED))
+    uni = ihmc.Lattice((16, 16), beta=0.4, C=4.1, h=0.01)
+    with pytest.raises(ihmc.IhmcError):
+        ctx.run_lattice(uni, ihmc.Run(n_md=4, n_traj=2, flip_every=1, form=ihmc.FORM_SHIFTED))
+    with pytest.raises(ihmc.IhmcError):
+        ctx.run_lattice(uni, ihmc.Run(n_md=4, n_traj=1, form=3))
+    K = np.ones((8, 8)) - np.eye(8)
+    with pytest.raises(ihmc.IhmcError):
+        ctx.run_dense(ihmc.Dense(K / 8, beta=0.5, C=1.2), [ihmc.Run(n_md=4, n_traj=1, form=ihmc.FORM_SHIFTED)])
