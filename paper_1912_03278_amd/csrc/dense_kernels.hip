@@ -515,7 +515,9 @@ __global__ __launch_bounds__(EPI_THREADS) void k_dense_prep(const ChainDev* __re
   store_limbs4(Xl, Bp * Np, b, i, Np, v);
 }
 
-// After U = K Psi: w = sqrt(J') tanh(sqrt(J') (U + C psi)) - psi  -> W (FP32 and limbs).
+// After U = K Psi: w = sqrt(J') tanh(sqrt(J') (U + C psi) + hw) - psi  -> W (FP32 and
+// limbs); hw = h' in the shifted form (per site: sqrt(J') times the stored
+// h'/sqrt(J')), else 0.
 __global__ __launch_bounds__(EPI_THREADS) void k_dense_epi_w(const ChainDev* __restrict__ chains, int64_t Np,
                                                              int64_t Bp, int S, const float* __restrict__ part, int j,
                                                              float* __restrict__ W32, __bf16* __restrict__ Wl) {
@@ -531,11 +533,21 @@ __global__ __launch_bounds__(EPI_THREADS) void k_dense_epi_w(const ChainDev* __r
     f32x4 v = ld_f4((const float*)cd.psi + (int64_t)buf * cd.NP + i);
     if (j == 0 && st->sign < 0) v = -v;
     const float a = (float)cd.sqJ, C = (float)cd.C;
+    f32x4 hw = {0.f, 0.f, 0.f, 0.f};
+    if (cd.form == FORM_SHIFTED) {
+      if (cd.h_kind == 2) {
+        const f32x4 b4 = ld_f4((const float*)cd.b + i);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) hw[e] = a * b4[e];
+      } else {
+        hw = f32x4{(float)cd.hw, (float)cd.hw, (float)cd.hw, (float)cd.hw};
+      }
+    }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       if (i + e < cd.N) {
         const float u = __builtin_fmaf(C, v[e], ku[e]);
-        w[e] = __builtin_fmaf(a, tanh_state(a * u), -v[e]);
+        w[e] = __builtin_fmaf(a, tanh_state(__builtin_fmaf(a, u, hw[e])), -v[e]);
       }
     }
   }
@@ -570,9 +582,11 @@ __global__ __launch_bounds__(EPI_THREADS) void k_dense_epi_f(const ChainDev* __r
     f32x4 v = ld_f4((const float*)cd.psi + (int64_t)in_buf * cd.NP + i);
     if ((MODE == PASS_FIRST || MODE == PASS_FORCE) && st->sign < 0) v = -v;
     const f32x4 w = ld_f4(W32 + o);
-    f32x4 bs;
-    if (cd.h_kind == 2) bs = ld_f4((const float*)cd.b + i);
-    else bs = f32x4{(float)cd.b0, (float)cd.b0, (float)cd.b0, (float)cd.b0};
+    f32x4 bs = {0.f, 0.f, 0.f, 0.f};  // the shifted form has no linear term
+    if (cd.form != FORM_SHIFTED) {
+      if (cd.h_kind == 2) bs = ld_f4((const float*)cd.b + i);
+      else bs = f32x4{(float)cd.b0, (float)cd.b0, (float)cd.b0, (float)cd.b0};
+    }
     f32x4 p = {0.f, 0.f, 0.f, 0.f};
     if (MODE == PASS_FIRST) {
       if (cd.p_given) {
@@ -638,14 +652,17 @@ __global__ __launch_bounds__(EPI_THREADS) void k_dense_h(const ChainDev* __restr
       if (i + e < cd.N) {
         const double v = (double)v4[e];
         const double u = ku[e] + cd.C * v;
-        double lc, th;
-        logcosh_tanh(cd.sqJ * u, lc, th);
         const double hpx = hp4[e];
-        const double bx = (cd.h_kind == 2) ? hpx / cd.sqJ : cd.b0;
+        const bool shifted = cd.form == FORM_SHIFTED;
+        // shifted form: y = sqrt(J') u + h', no linear term, h[3] = y tanh(y)
+        const double y = __builtin_fma(cd.sqJ, u, shifted ? hpx : 0.0);
+        double lc, th;
+        logcosh_tanh(y, lc, th);
+        const double bx = shifted ? 0.0 : ((cd.h_kind == 2) ? hpx / cd.sqJ : cd.b0);
         h[0][e] = 0.5 * v * u - v * bx - lc;
         h[1][e] = v;
         h[2][e] = v * hpx;
-        h[3][e] = u * th;
+        h[3][e] = (shifted ? y : u) * th;
       }
     }
   }

@@ -241,6 +241,8 @@ int DenseChains::build(const ihmc_dense& md, int32_t n, const ihmc_run* runs, in
   Np = round_up(N, 256);
   Bp = round_up(B, 128);
   const ihmc_run& r0 = runs[0];
+  bool field_nonzero = false;
+  for (int64_t k = 0; k < md.h_len && !field_nonzero; ++k) field_nonzero = md.h[k] != 0.0;
   for (int i = 0; i < n; ++i) {
     const ihmc_run& r = runs[i];
     if (r.n_md < 1) return set_error(IHMC_E_INVAL, "chain %d: n_md must be >= 1", i);
@@ -253,7 +255,10 @@ int DenseChains::build(const ihmc_dense& md, int32_t n, const ihmc_run* runs, in
     if (r.n_therm < 0) return set_error(IHMC_E_INVAL, "chain %d: n_therm must be >= 0", i);
     if (r.precision != IHMC_F32)
       return set_error(IHMC_E_UNSUPPORTED, "chain %d: dense chains keep FP32 state (precision 4)", i);
-    if (r.form != 0) return set_error(IHMC_E_UNSUPPORTED, "chain %d: dense chains run the psi form only", i);
+    if (r.form != FORM_PSI && r.form != FORM_SHIFTED)
+      return set_error(IHMC_E_UNSUPPORTED, "chain %d: dense chains run the psi or the shifted form", i);
+    if (r.form == FORM_SHIFTED && r.flip_every > 0 && field_nonzero)
+      return set_error(IHMC_E_INVAL, "chain %d: psi -> -psi is no symmetry of the shifted form at h != 0", i);
     if (r.n_md != r0.n_md || r.integrator != r0.integrator || r.traj_len != r0.traj_len)
       return set_error(IHMC_E_INVAL, "chain %d: n_md, integrator and traj_len must agree across dense chains", i);
   }
@@ -354,6 +359,11 @@ int DenseChains::build(const ihmc_dense& md, int32_t n, const ihmc_run* runs, in
     c.sqJ = sqJ;
     c.hp0 = h_kind == 1 ? md.beta * md.h[0] : 0.0;
     c.b0 = h_kind == 1 ? c.hp0 / sqJ : 0.0;
+    c.form = r.form;
+    if (r.form == FORM_SHIFTED) {  // h' inside the log cosh, no linear term
+      c.hw = c.hp0;
+      c.b0 = 0.0;
+    }
     c.eps = r.traj_len / r.n_md;
     c.cap = r.n_traj;
     c.n_therm = r.n_therm;
@@ -417,6 +427,7 @@ int DenseChains::build(const ihmc_dense& md, int32_t n, const ihmc_run* runs, in
         c.c_m = hd[1];
         c.c_e = hd[2];
       }
+      if (c.form == FORM_SHIFTED) c.c_m = c.c_e = 0.0;  // the estimators need no Kt^-1 h' terms
     }
   }
   d_cd = (ChainDev*)dalloc(sizeof(ChainDev) * (uint64_t)B);

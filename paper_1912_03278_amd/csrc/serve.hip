@@ -718,7 +718,7 @@ extern "C" int ihmc_submit(ihmc_server* sv, const ihmc_lattice* lat, const ihmc_
   if (!sv || !lat || !run || !ticket) return set_error(IHMC_E_INVAL, "NULL argument");
   int rc = validate(*lat, *run, 0);
   if (rc) return rc;
-  if (run->form != 0) return set_error(IHMC_E_UNSUPPORTED, "the server runs psi-form chains only");
+  if (run->form == FORM_PHI) return set_error(IHMC_E_UNSUPPORTED, "the server runs psi-form or shifted-form chains");
   Request* r = new (std::nothrow) Request();
   if (!r) return set_error(IHMC_E_NOMEM, "host allocation failed");
   r->lat = *lat;
@@ -829,7 +829,8 @@ extern "C" int ihmc_restore(ihmc_server* sv, const void* buf, uint64_t bytes, ui
   r->resume.assign(in, in + h.chain_bytes);
   r->lat.h = r->h.empty() ? nullptr : r->h.data();
   int rc = validate(r->lat, r->run, 0);
-  if (!rc && r->run.form != 0) rc = set_error(IHMC_E_UNSUPPORTED, "the server runs psi-form chains only");
+  if (!rc && r->run.form == FORM_PHI)
+    rc = set_error(IHMC_E_UNSUPPORTED, "the server runs psi-form or shifted-form chains");
   const int64_t N = rc ? 0 : lattice_sites(r->lat);
   if (!rc && ((h.psi0_len != 0 && h.psi0_len != N) || (h.replay_len != 0 && h.replay_len != h.n_traj)))
     rc = set_error(IHMC_E_INVAL, "served checkpoint is inconsistent");

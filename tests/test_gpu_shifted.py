@@ -4,8 +4,9 @@ form: LDS-resident whole trajectories, tiled passes with two leap-frog steps per
 launch, and tiled passes with one.
 
 Tolerances as for the paper's form: one trajectory from identical inputs
-(psi0, Philox momenta) 1e-12 normwise in FP64 and 1e-5 in FP32; FP64 chains
-take the oracle's accept decisions.  Properties checked on the GPU alone: at
+(psi0, Philox momenta) 1e-12 normwise in FP64 and 1e-5 in FP32 (dense chains,
+FP32 state, any field: 1e-5); FP64 chains take the oracle's accept decisions;
+served shifted requests equal the same chains alone bit for bit.  Properties checked on the GPU alone: at
 h = 0 the two forms give the same chain (bitwise, flips included, beta*eps to
 rounding), and with a uniform field a shifted chain started at
 psi0 - Kt^-1 h'/sqrt(J') takes the paper-form chain's decisions with the same
@@ -142,6 +143,81 @@ def test_mixed_forms_in_one_set_equal_alone(ctx):
             assert np.array_equal(mixed[i][k], alone[k]), (i, k)
 
 
+def _rand_K(N, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.normal(0.0, 1.0 / np.sqrt(N), (N, N))
+    K = np.triu(A, 1)
+    return K + K.T
+
+
+@pytest.mark.parametrize("integ,n_md", [(0, 8), (1, 4)])
+@pytest.mark.parametrize("N,h", [(300, 0.05), (500, "site"), (301, None)])
+def test_dense_one_trajectory(ctx, orc, integ, n_md, N, h):
+    """Dense chains (BF16-limb GEMMs, FP32 state): any field, 1e-5 as for the paper's form."""
+    from paper_1912_03278_amd import ihmc
+    rng = np.random.default_rng(N + 7 * integ)
+    K = _rand_K(N, 3)
+    C = -np.linalg.eigvalsh(K)[0] + 0.1
+    hv = rng.normal(0, 0.1, N) if h == "site" else h
+    B = 4
+    psi0 = [rng.standard_normal(N) for _ in range(B)]
+    runs = [ihmc.Run(n_md=n_md, n_traj=1, integrator=integ, seed=7, chain_id=10 + i, psi0=psi0[i],
+                     replay_accept=[1], form=ihmc.FORM_SHIFTED if i != 2 else ihmc.FORM_PSI) for i in range(B)]
+    g = ctx.run_dense(ihmc.Dense(K, beta=0.9, C=C, h=hv), runs)
+    for i in range(B):
+        r = orc.run(orc.Dense(K, beta=0.9, C=C, h=hv), 1, n_md, seed=7, chain_id=10 + i,
+                    psi0=psi0[i].astype(np.float32).astype(np.float64), replay_accept=[1], integrator=integ,
+                    form="shifted" if i != 2 else "psi")
+        assert nrm(g[i]["psi_final"], r.psi_final) < 1e-5, (i, nrm(g[i]["psi_final"], r.psi_final))
+        for k in ("H_old", "H_new"):
+            assert abs(g[i][k][0] - getattr(r, k)[0]) <= 1e-5 * abs(getattr(r, k)[0]), (i, k)
+        for k in ("m", "m2c", "beta_eps"):
+            assert abs(g[i][k][0] - getattr(r, k)[0]) <= 1e-5 * max(1.0, abs(getattr(r, k)[0])), (i, k)
+
+
+def test_dense_shifted_alone_equals_mixed_bitwise(ctx):
+    from paper_1912_03278_amd import ihmc
+    N = 300
+    model = ihmc.Dense(_rand_K(N, 6), beta=0.8, C=2.2, h=0.04)
+    runs = [ihmc.Run(n_md=5, n_traj=6, seed=9, chain_id=i, form=ihmc.FORM_SHIFTED if i % 3 else ihmc.FORM_PSI)
+            for i in range(40)]
+    both = ctx.run_dense(model, runs)
+    for i in (1, 3, 38):
+        alone = ctx.run_dense(model, [runs[i]])[0]
+        for k in ("dH", "beta_eps", "psi_final"):
+            assert np.array_equal(both[i][k], alone[k]), (i, k)
+
+
+def test_served_shifted_requests_equal_alone(ctx):
+    """Served shifted and paper-form requests (2D/3D, FP32/FP64, fields) equal the same
+    chains run alone, bit for bit."""
+    import time
+    from paper_1912_03278_amd import ihmc
+    reqs = []
+    for i in range(12):
+        L = (24 + 4 * i, 20) if i % 3 else (8, 6, 5 + i)
+        lat = ihmc.Lattice(L, beta=0.4 if len(L) == 2 else 0.22, C=4.1 if len(L) == 2 else 6.1,
+                           h=0.02 * (i % 4) if i % 4 else None)
+        reqs.append((lat, ihmc.Run(n_md=4 + i % 5, n_traj=6, seed=3, chain_id=i, precision=8 if i % 2 else 4,
+                                   integrator=i % 2 if i % 4 == 3 else 0, flip_every=2 if i % 4 == 0 else 0,
+                                   form=ihmc.FORM_SHIFTED if i % 4 != 1 else ihmc.FORM_PSI)))
+    sv = ihmc.Server(ctx, budget_bytes=4 << 20, max_active=6)
+    tickets = []
+    for k, (lat, run) in enumerate(reqs):
+        tickets.append(sv.submit(lat, run))
+        if k % 4 == 3:
+            time.sleep(0.01)
+    served = []
+    for t in tickets:
+        assert sv.wait(t, 120.0) == ihmc.REQ_DONE
+        served.append(sv.fetch(t))
+    sv.close()
+    for (lat, run), g in zip(reqs, served):
+        alone = ctx.run_lattice(lat, run)
+        for k in ("dH", "m", "beta_eps", "psi_final", "accepted", "flipped"):
+            assert np.array_equal(g[k], alone[k]), (lat.L, k)
+
+
 def test_refusals(ctx):
     from paper_1912_03278_amd import ihmc
     site = ihmc.Lattice((16, 16), beta=0.4, C=4.1, h=np.full(256, 0.01))
@@ -152,6 +228,14 @@ def test_refusals(ctx):
         ctx.run_lattice(uni, ihmc.Run(n_md=4, n_traj=2, flip_every=1, form=ihmc.FORM_SHIFTED))
     with pytest.raises(ihmc.IhmcError):
         ctx.run_lattice(uni, ihmc.Run(n_md=4, n_traj=1, form=3))
-    K = np.ones((8, 8)) - np.eye(8)
+    K = (np.ones((8, 8)) - np.eye(8)) / 8
+    with pytest.raises(ihmc.IhmcError):  # flips at h != 0 in the shifted form
+        ctx.run_dense(ihmc.Dense(K, beta=0.5, C=1.2, h=0.1),
+                      [ihmc.Run(n_md=4, n_traj=2, flip_every=1, form=ihmc.FORM_SHIFTED)])
     with pytest.raises(ihmc.IhmcError):
-        ctx.run_dense(ihmc.Dense(K / 8, beta=0.5, C=1.2), [ihmc.Run(n_md=4, n_traj=1, form=ihmc.FORM_SHIFTED)])
+        ctx.run_dense(ihmc.Dense(K, beta=0.5, C=1.2), [ihmc.Run(n_md=4, n_traj=1, form=ihmc.FORM_PHI)])
+    ctx.run_dense(ihmc.Dense(K, beta=0.5, C=1.2), [ihmc.Run(n_md=4, n_traj=2, flip_every=1, form=ihmc.FORM_SHIFTED)])
+    sv = ihmc.Server(ctx, budget_bytes=1 << 20, max_active=2)
+    with pytest.raises(ihmc.IhmcError):
+        sv.submit(ihmc.Lattice((16, 16), beta=0.4, C=4.1), ihmc.Run(n_md=4, n_traj=1, precision=8, form=ihmc.FORM_PHI))
+    sv.close()
