@@ -218,6 +218,41 @@ def test_served_shifted_requests_equal_alone(ctx):
             assert np.array_equal(g[k], alone[k]), (lat.L, k)
 
 
+@pytest.mark.parametrize("dense", [False, True])
+def test_checkpoint_resume_and_form_mismatch(ctx, dense):
+    """A shifted chain resumed from a checkpoint continues bit for bit; the
+    checkpoint does not restore into a paper-form chain of the same model."""
+    from paper_1912_03278_amd import ihmc
+    if dense:
+        model = ihmc.Dense(_rand_K(200, 2), beta=0.8, C=2.3, h=np.random.default_rng(1).normal(0, 0.1, 200))
+    else:
+        model = ihmc.Lattice((24, 20), beta=0.42, C=4.1, h=0.04)
+
+    def make(run):
+        return ihmc.DenseChains(ctx, model, [run]) if dense else ihmc.Chains(ctx, [model], [run])
+
+    run = ihmc.Run(n_md=6, n_traj=10, seed=12, chain_id=3, form=ihmc.FORM_SHIFTED)
+    ref = make(run)
+    ref.advance(10)
+    want = ref.result(0)
+    ref.close()
+    a = make(run)
+    a.advance(4)
+    blob = a.checkpoint(0)
+    a.close()
+    b = make(run)
+    b.restore(0, blob)
+    b.advance(6)
+    got = b.result(0)
+    b.close()
+    for k in ("dH", "accepted", "m", "m2c", "beta_eps", "psi_final"):
+        assert np.array_equal(got[k], want[k]), k
+    other = make(ihmc.Run(n_md=6, n_traj=10, seed=12, chain_id=3, form=ihmc.FORM_PSI))
+    with pytest.raises(ihmc.IhmcError):
+        other.restore(0, blob)
+    other.close()
+
+
 def test_refusals(ctx):
     from paper_1912_03278_amd import ihmc
     site = ihmc.Lattice((16, 16), beta=0.4, C=4.1, h=np.full(256, 0.01))
