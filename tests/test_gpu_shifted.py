@@ -70,6 +70,28 @@ def test_one_trajectory(ctx, orc, case, prec, integ):
         assert abs(g[k][0] - getattr(r, k)[0]) <= tol * max(1.0, abs(getattr(r, k)[0])), k
 
 
+@pytest.mark.parametrize("prec", [8, 4])
+@pytest.mark.parametrize("L", [(40, 24), (9, 8, 7)])
+def test_integrate_arbitrary_momenta(ctx, orc, prec, L):
+    """ihmc_integrate with a shifted-form run follows the oracle's shifted MD."""
+    from paper_1912_03278_amd import ihmc
+    rng = np.random.default_rng(4)
+    N = int(np.prod(L))
+    beta, C = (0.45, 4.1) if len(L) == 2 else (0.22, 6.1)
+    psi, p = rng.standard_normal(N), rng.standard_normal(N)
+    if prec == 4:
+        psi = psi.astype(np.float32).astype(np.float64)
+        p = p.astype(np.float32).astype(np.float64)
+    run = ihmc.Run(n_md=9, n_traj=1, precision=prec, form=ihmc.FORM_SHIFTED)
+    gpsi, gp = ctx.integrate(ihmc.Lattice(L, beta=beta, C=C, h=0.06), run, psi, p)
+    rpsi, rp = orc.md(orc.Lattice(L, beta=beta, C=C, h=0.06), psi, p, 9, form="shifted")
+    tol = 1e-12 if prec == 8 else 1e-5
+    assert nrm(gpsi, rpsi) < tol and nrm(gp, rp) < tol
+    # and differs from the paper form's dynamics from the same point
+    ppsi, _ = ctx.integrate(ihmc.Lattice(L, beta=beta, C=C, h=0.06), ihmc.Run(n_md=9, n_traj=1, precision=prec), psi, p)
+    assert nrm(ppsi, rpsi) > 1e-3
+
+
 @pytest.mark.parametrize("L,h", [((16, 12), 0.05), ((6, 5, 7), 0.08)])
 def test_fp64_chain_takes_the_oracles_decisions(ctx, orc, L, h):
     from paper_1912_03278_amd import ihmc
