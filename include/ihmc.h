@@ -60,8 +60,11 @@ extern "C" {
                            at most 1453 sites, 1272 with a per-site field; no flips) */
 #define IHMC_FORM_SHIFTED 2 /* psi of the substitution phi = sqrt(J') Kt psi in eq. did_HS_trafo:
                            S = 1/2 psi.Kt psi - sum log cosh(sqrt(J') (Kt psi)_i + h'), no linear
-                           term; the same fused passes (lattice chains with h = 0 or a uniform
-                           field, dense chains with any field; flips only at h = 0).  psi differs from the paper's by the
+                           term; the same fused passes (flips only at h = 0).  A lattice chain
+                           with a per-site field runs as a paper-form chain in coordinates
+                           translated by Kt^-1 h'/sqrt(J') (one CG solve at set-up; HMC with
+                           unit mass commutes with translations); its results are reported in
+                           its own coordinates (psi, and H offset by h'.Kt^-1 h'/(2J')).  psi differs from the paper's by the
                            constant Kt^-1 h'/sqrt(J'); the records hold the paper's estimators at
                            that translate: m = sum psi/(N sqrt(J')), beta*eps = C J'/2
                            - psi.h'/(2N sqrt(J')) - sum y tanh(y)/(2N), y = sqrt(J') Kt psi + h' */
@@ -143,9 +146,9 @@ typedef struct {
  *               expectations given phi (m = mean tanh(h' + phi), m^2 and beta*eps
  *               likewise, no bias correction needed).  IHMC_FORM_SHIFTED: psi0
  *               is the starting psi of that form (NULL: the TAG_INIT normals);
- *               flips at h != 0 give IHMC_E_INVAL, a per-site field on a
- *               lattice IHMC_E_UNSUPPORTED (dense chains take any field); the
- *               server runs psi and shifted chains, not phi ones. */
+ *               flips at h != 0 give IHMC_E_INVAL; the server runs psi chains
+ *               and shifted chains with h = 0 or a uniform field (a per-site
+ *               field there: IHMC_E_UNSUPPORTED), not phi ones. */
 typedef struct {
   int32_t n_md;
   int32_t n_traj;

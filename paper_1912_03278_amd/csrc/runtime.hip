@@ -102,13 +102,23 @@ __global__ void k_field_setup(const ChainDev* cds, int ci, const double* h, doub
   ((T*)cd.b)[k] = (T)(hp / cd.sqJ);
 }
 
+// Starting field: psi0 (logical layout) or the TAG_INIT normals, plus `shift`
+// (logical layout, or null) before the rounding to the state type.
 template <typename T>
-__global__ void k_init_psi(const ChainDev* cds, int ci, const double* psi0) {
+__global__ void k_init_psi(const ChainDev* cds, int ci, const double* psi0, const double* shift) {
   const ChainDev& cd = cds[ci];
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= cd.N) return;
   T* psi = (T*)cd.psi;
-  psi[stored_index(cd, i)] = psi0 ? (T)psi0[i] : (T)normal_at(cd, 0u, TAG_INIT, i);
+  double v = psi0 ? psi0[i] : normal_at(cd, 0u, TAG_INIT, i);
+  if (shift) v += shift[i];
+  psi[stored_index(cd, i)] = (T)v;
+}
+
+// x /= s over n values (the translation of a shifted-form chain from Kt^-1 h').
+__global__ void k_scale(double* x, int64_t n, double s) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] /= s;
 }
 
 // Starting field of a phi-form chain without a given one: the substitution
@@ -308,7 +318,11 @@ void describe_chain(const ihmc_lattice& l, const ihmc_run& r, int flags, int cls
   c.n_therm = r.n_therm;
   c.form = r.form;
   c.hw = 0.0;
-  if (r.form == FORM_SHIFTED) {
+  if (r.form == FORM_SHIFTED && c.h_kind == 2) {
+    // a per-site field: the chain runs as a paper-form chain in coordinates
+    // translated by Kt^-1 h'/sqrt(J') (set up by Chains::build)
+    c.form = FORM_PSI;
+  } else if (r.form == FORM_SHIFTED) {
     // h' moves inside the log cosh; the linear term and the Kt^-1 constants of
     // the estimators drop (h' itself stays for the psi.h' estimator sum)
     c.hw = c.hp0;
@@ -413,11 +427,10 @@ int validate(const ihmc_lattice& l, const ihmc_run& r, int idx) {
   if (r.n_therm < 0) return set_error(IHMC_E_INVAL, "chain %d: n_therm must be >= 0", idx);
   if (r.form != FORM_PSI && r.form != FORM_PHI && r.form != FORM_SHIFTED)
     return set_error(IHMC_E_INVAL, "chain %d: unknown form", idx);
-  if (r.form == FORM_SHIFTED) {
-    if (l.h_len > 1)
-      return set_error(IHMC_E_UNSUPPORTED, "chain %d: the shifted form takes h = 0 or a uniform field", idx);
-    if (r.flip_every > 0 && l.h_len == 1 && l.h[0] != 0.0)
-      return set_error(IHMC_E_INVAL, "chain %d: psi -> -psi is no symmetry of the shifted form at h != 0", idx);
+  if (r.form == FORM_SHIFTED && r.flip_every > 0) {
+    bool field = false;
+    for (int64_t k = 0; k < l.h_len && !field; ++k) field = l.h[k] != 0.0;
+    if (field) return set_error(IHMC_E_INVAL, "chain %d: psi -> -psi is no symmetry of the shifted form at h != 0", idx);
   }
   if (r.form == FORM_PHI) {
     if (r.precision != 8 || r.integrator != LEAPFROG || r.flip_every != 0)
@@ -563,6 +576,8 @@ Chains::~Chains() {
 int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, int flags) {
   n = n_;
   cd.resize(n);
+  delta.assign(n, std::vector<double>());
+  s_offset.assign(n, 0.0);
   base.assign(n, 0);
   hipStream_t s = ctx->stream;
   std::vector<void*> temps;
@@ -667,6 +682,7 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
   }
 
   // ---- per-site field constants by CG (one block per chain)
+  std::vector<double*> shift(n, nullptr);
   std::vector<int> cg_idx;
   std::vector<int64_t> cg_off;
   int64_t cg_total = 0;
@@ -688,6 +704,14 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
     HIPCHK(hipMemcpyAsync(doff, cg_off.data(), sizeof(int64_t) * cg_off.size(), hipMemcpyHostToDevice, s), "cg off");
     k_field_cg<<<(unsigned)cg_idx.size(), 256, 0, s>>>(d_cd, didx, work, doff);
     HIPCHK(hipGetLastError(), "k_field_cg");
+    // shifted-form chains with this field: delta = Kt^-1 h' / sqrt(J') (the CG's x)
+    for (size_t j = 0; j < cg_idx.size(); ++j) {
+      const int i = cg_idx[j];
+      if (runs[i].form != FORM_SHIFTED) continue;
+      shift[i] = work + cg_off[j];
+      k_scale<<<nblk(cd[i].N), 256, 0, s>>>(shift[i], cd[i].N, cd[i].sqJ);
+      HIPCHK(hipGetLastError(), "k_scale");
+    }
   }
 
   // ---- initial field and its action
@@ -705,8 +729,8 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
       src = t;
     }
     if (cd[i].form == FORM_PHI && !src) k_init_phi<<<nblk(N), 256, 0, s>>>(d_cd, i);
-    else if (cd[i].precision == 4) k_init_psi<float><<<nblk(N), 256, 0, s>>>(d_cd, i, src);
-    else k_init_psi<double><<<nblk(N), 256, 0, s>>>(d_cd, i, src);
+    else if (cd[i].precision == 4) k_init_psi<float><<<nblk(N), 256, 0, s>>>(d_cd, i, src, shift[i]);
+    else k_init_psi<double><<<nblk(N), 256, 0, s>>>(d_cd, i, src, shift[i]);
     HIPCHK(hipGetLastError(), "k_init_psi");
   }
   for (auto& g : groups) {
@@ -714,6 +738,15 @@ int Chains::build(int32_t n_, const ihmc_lattice* lats, const ihmc_run* runs, in
            "measure pass");
   }
   hipError_t e = hipStreamSynchronize(s);
+  // translated chains: delta and the action offset h'.Kt^-1 h'/(2J') on the host
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    if (!shift[i]) continue;
+    delta[i].resize((size_t)cd[i].N);
+    e = hipMemcpy(delta[i].data(), shift[i], 8 * (uint64_t)cd[i].N, hipMemcpyDeviceToHost);
+    double ce = 0.0;
+    if (e == hipSuccess) e = hipMemcpy(&ce, &d_cd[i].c_e, sizeof ce, hipMemcpyDeviceToHost);
+    s_offset[i] = ce / (2.0 * cd[i].Jp);
+  }
   cleanup();
   if (e != hipSuccess) return hip_fail(ctx, e, "chain set-up");
   return IHMC_OK;
@@ -889,13 +922,13 @@ int Chains::advance(int32_t n_traj) {
 
 int Chains::checkpoint(int32_t i, void* buf, uint64_t* bytes) {
   if (i < 0 || i >= n) return set_error(IHMC_E_INVAL, "chain index %d out of range", i);
-  return chain_checkpoint(ctx, cd[i], 0, buf, bytes);
+  return chain_checkpoint(ctx, cd[i], delta[i].empty() ? 0 : 1, buf, bytes);
 }
 
 int Chains::restore(int32_t i, const void* buf, uint64_t bytes) {
   if (i < 0 || i >= n) return set_error(IHMC_E_INVAL, "chain index %d out of range", i);
   int traj = 0;
-  int rc = chain_restore(ctx, cd[i], 0, buf, bytes, &traj);
+  int rc = chain_restore(ctx, cd[i], delta[i].empty() ? 0 : 1, buf, bytes, &traj);
   if (rc) return rc;
   base[i] = traj - enqueued;
   return IHMC_OK;
@@ -903,7 +936,17 @@ int Chains::restore(int32_t i, const void* buf, uint64_t bytes) {
 
 int Chains::result(int32_t i, ihmc_result* out) {
   if (i < 0 || i >= n) return set_error(IHMC_E_INVAL, "chain index %d out of range", i);
-  return result_from_device(ctx, cd[i], d_cd, i, out);
+  int rc = result_from_device(ctx, cd[i], d_cd, i, out);
+  if (rc || delta[i].empty()) return rc;
+  // a translated shifted-form chain: its field and action in its own coordinates
+  const int64_t done = std::min<int64_t>(out->n_traj_done, cd[i].cap);
+  for (int64_t t = 0; t < done; ++t) {
+    if (out->H_old) out->H_old[t] += s_offset[i];
+    if (out->H_new) out->H_new[t] += s_offset[i];
+  }
+  if (out->psi_final)
+    for (int64_t k = 0; k < cd[i].N; ++k) out->psi_final[k] -= delta[i][(size_t)k];
+  return IHMC_OK;
 }
 
 // Series and summary of chain ci of a device chain table (shared by the lattice
@@ -1346,6 +1389,8 @@ extern "C" int ihmc_integrate(ihmc_ctx* ctx, const ihmc_lattice* lat, const ihmc
       e = hipMemcpyAsync(psi, t, 8 * N, hipMemcpyDeviceToHost, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && !c->delta[0].empty())  // a translated shifted-form chain
+      for (int64_t k = 0; k < N; ++k) psi[k] -= c->delta[0][(size_t)k];
     if (e == hipSuccess) {
       if (cdh.precision == 4) k_export<float><<<nblk(N), 256, 0, s>>>(c->d_cd, 0, t, (const float*)cdh.p);
       else k_export<double><<<nblk(N), 256, 0, s>>>(c->d_cd, 0, t, (const double*)cdh.p);
@@ -1618,8 +1663,8 @@ extern "C" int ihmc_copy_bandwidth(ihmc_ctx* ctx, uint64_t bytes, int32_t reps, 
 
 namespace ihmc {
 hipError_t launch_init_psi(const ChainDev* d_cd, int ci, const double* psi0, int64_t N, int precision, hipStream_t s) {
-  if (precision == 4) k_init_psi<float><<<nblk(N), 256, 0, s>>>(d_cd, ci, psi0);
-  else k_init_psi<double><<<nblk(N), 256, 0, s>>>(d_cd, ci, psi0);
+  if (precision == 4) k_init_psi<float><<<nblk(N), 256, 0, s>>>(d_cd, ci, psi0, nullptr);
+  else k_init_psi<double><<<nblk(N), 256, 0, s>>>(d_cd, ci, psi0, nullptr);
   return hipGetLastError();
 }
 hipError_t launch_field_setup(const ChainDev* d_cd, int ci, const double* h, double beta, int64_t N, int precision,

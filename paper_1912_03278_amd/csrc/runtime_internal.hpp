@@ -142,6 +142,13 @@ struct Chains {
   std::vector<hipEvent_t> events;  // fork/join points of one round
   int enqueued = 0;
   std::vector<int> base;  // per chain: trajectory index at enqueued = 0 (non-zero after a restore)
+  // A shifted-form chain with a per-site field runs as a paper-form chain in
+  // coordinates translated by delta = Kt^-1 h'/sqrt(J'): HMC with unit mass
+  // commutes with translations, and the two actions differ by the constant
+  // h'.Kt^-1 h'/(2J').  Per chain: delta (logical layout) and that offset, or
+  // an empty vector and 0.
+  std::vector<std::vector<double>> delta;
+  std::vector<double> s_offset;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
 

@@ -719,6 +719,8 @@ extern "C" int ihmc_submit(ihmc_server* sv, const ihmc_lattice* lat, const ihmc_
   int rc = validate(*lat, *run, 0);
   if (rc) return rc;
   if (run->form == FORM_PHI) return set_error(IHMC_E_UNSUPPORTED, "the server runs psi-form or shifted-form chains");
+  if (run->form == FORM_SHIFTED && lat->h_len > 1)
+    return set_error(IHMC_E_UNSUPPORTED, "served shifted-form requests take h = 0 or a uniform field");
   Request* r = new (std::nothrow) Request();
   if (!r) return set_error(IHMC_E_NOMEM, "host allocation failed");
   r->lat = *lat;
@@ -831,6 +833,8 @@ extern "C" int ihmc_restore(ihmc_server* sv, const void* buf, uint64_t bytes, ui
   int rc = validate(r->lat, r->run, 0);
   if (!rc && r->run.form == FORM_PHI)
     rc = set_error(IHMC_E_UNSUPPORTED, "the server runs psi-form or shifted-form chains");
+  if (!rc && r->run.form == FORM_SHIFTED && r->lat.h_len > 1)
+    rc = set_error(IHMC_E_UNSUPPORTED, "served shifted-form requests take h = 0 or a uniform field");
   const int64_t N = rc ? 0 : lattice_sites(r->lat);
   if (!rc && ((h.psi0_len != 0 && h.psi0_len != N) || (h.replay_len != 0 && h.replay_len != h.n_traj)))
     rc = set_error(IHMC_E_INVAL, "served checkpoint is inconsistent");

@@ -45,6 +45,8 @@ CASES = [
     ("2d_tiles_ragged", (130, 35), 0.44, 4.1, -0.02),
     ("3d_ragged", (67, 9, 6), 0.22, 6.1, 0.05),
     ("3d_small_wrap", (5, 3, 7), 0.3, 6.5, 0.1),
+    ("2d_site_h", (33, 17), 0.5, 4.1, "site"),
+    ("3d_site_h", (20, 6, 9), 0.25, 6.1, "site"),
 ]
 
 
@@ -54,6 +56,8 @@ def test_one_trajectory(ctx, orc, case, prec, integ):
     from paper_1912_03278_amd import ihmc
     name, L, beta, C, h = case
     N = int(np.prod(L))
+    if isinstance(h, str):
+        h = np.random.default_rng(11).normal(0, 0.2, N)
     psi = np.random.default_rng(2).standard_normal(N)
     n_md = 7 if integ == 0 else 4
     run = ihmc.Run(n_md=n_md, n_traj=1, precision=prec, integrator=integ, seed=5, chain_id=2,
@@ -71,8 +75,8 @@ def test_one_trajectory(ctx, orc, case, prec, integ):
 
 
 @pytest.mark.parametrize("prec", [8, 4])
-@pytest.mark.parametrize("L", [(40, 24), (9, 8, 7)])
-def test_integrate_arbitrary_momenta(ctx, orc, prec, L):
+@pytest.mark.parametrize("L,site", [((40, 24), False), ((9, 8, 7), False), ((30, 22), True)])
+def test_integrate_arbitrary_momenta(ctx, orc, prec, L, site):
     """ihmc_integrate with a shifted-form run follows the oracle's shifted MD."""
     from paper_1912_03278_amd import ihmc
     rng = np.random.default_rng(4)
@@ -82,20 +86,23 @@ def test_integrate_arbitrary_momenta(ctx, orc, prec, L):
     if prec == 4:
         psi = psi.astype(np.float32).astype(np.float64)
         p = p.astype(np.float32).astype(np.float64)
+    h = rng.normal(0, 0.1, N) if site else 0.06
     run = ihmc.Run(n_md=9, n_traj=1, precision=prec, form=ihmc.FORM_SHIFTED)
-    gpsi, gp = ctx.integrate(ihmc.Lattice(L, beta=beta, C=C, h=0.06), run, psi, p)
-    rpsi, rp = orc.md(orc.Lattice(L, beta=beta, C=C, h=0.06), psi, p, 9, form="shifted")
+    gpsi, gp = ctx.integrate(ihmc.Lattice(L, beta=beta, C=C, h=h), run, psi, p)
+    rpsi, rp = orc.md(orc.Lattice(L, beta=beta, C=C, h=h), psi, p, 9, form="shifted")
     tol = 1e-12 if prec == 8 else 1e-5
     assert nrm(gpsi, rpsi) < tol and nrm(gp, rp) < tol
     # and differs from the paper form's dynamics from the same point
-    ppsi, _ = ctx.integrate(ihmc.Lattice(L, beta=beta, C=C, h=0.06), ihmc.Run(n_md=9, n_traj=1, precision=prec), psi, p)
+    ppsi, _ = ctx.integrate(ihmc.Lattice(L, beta=beta, C=C, h=h), ihmc.Run(n_md=9, n_traj=1, precision=prec), psi, p)
     assert nrm(ppsi, rpsi) > 1e-3
 
 
-@pytest.mark.parametrize("L,h", [((16, 12), 0.05), ((6, 5, 7), 0.08)])
+@pytest.mark.parametrize("L,h", [((16, 12), 0.05), ((6, 5, 7), 0.08), ((14, 10), "site")])
 def test_fp64_chain_takes_the_oracles_decisions(ctx, orc, L, h):
     from paper_1912_03278_amd import ihmc
     beta, C = (0.42, 4.1) if len(L) == 2 else (0.22, 6.1)
+    if isinstance(h, str):
+        h = np.random.default_rng(12).normal(0, 0.1, int(np.prod(L)))
     g = ctx.run_lattice(ihmc.Lattice(L, beta=beta, C=C, h=h),
                         ihmc.Run(n_md=8, n_traj=300, precision=8, seed=7, chain_id=4, form=ihmc.FORM_SHIFTED))
     r = orc.run(orc.Lattice(L, beta=beta, C=C, h=h), 300, 8, seed=7, chain_id=4, form="shifted")
@@ -153,13 +160,14 @@ def test_mixed_forms_in_one_set_equal_alone(ctx):
     from paper_1912_03278_amd import ihmc
     lats = [ihmc.Lattice((48, 40), beta=0.44, C=4.1, h=0.02 * (i + 1)) for i in range(4)]
     lats.append(ihmc.Lattice((12, 10, 9), beta=0.22, C=6.1, h=0.03))
+    lats.append(ihmc.Lattice((48, 40), beta=0.44, C=4.1, h=np.random.default_rng(3).normal(0, 0.05, 1920)))
     runs = [ihmc.Run(n_md=6 + i, n_traj=5, seed=4, chain_id=i, precision=4 if i % 2 else 8,
-                     form=ihmc.FORM_SHIFTED if i in (1, 2, 4) else ihmc.FORM_PSI) for i in range(5)]
+                     form=ihmc.FORM_SHIFTED if i in (1, 2, 4, 5) else ihmc.FORM_PSI) for i in range(6)]
     ch = ihmc.Chains(ctx, lats, runs)
     ch.advance(5)
-    mixed = [ch.result(i) for i in range(5)]
+    mixed = [ch.result(i) for i in range(6)]
     ch.close()
-    for i in range(5):
+    for i in range(6):
         alone = ctx.run_lattice(lats[i], runs[i])
         for k in ("dH", "accepted", "psi_final", "m", "m2c", "beta_eps"):
             assert np.array_equal(mixed[i][k], alone[k]), (i, k)
@@ -240,15 +248,16 @@ def test_served_shifted_requests_equal_alone(ctx):
             assert np.array_equal(g[k], alone[k]), (lat.L, k)
 
 
-@pytest.mark.parametrize("dense", [False, True])
-def test_checkpoint_resume_and_form_mismatch(ctx, dense):
+@pytest.mark.parametrize("dense,site", [(False, False), (False, True), (True, False)])
+def test_checkpoint_resume_and_form_mismatch(ctx, dense, site):
     """A shifted chain resumed from a checkpoint continues bit for bit; the
     checkpoint does not restore into a paper-form chain of the same model."""
     from paper_1912_03278_amd import ihmc
     if dense:
         model = ihmc.Dense(_rand_K(200, 2), beta=0.8, C=2.3, h=np.random.default_rng(1).normal(0, 0.1, 200))
     else:
-        model = ihmc.Lattice((24, 20), beta=0.42, C=4.1, h=0.04)
+        model = ihmc.Lattice((24, 20), beta=0.42, C=4.1,
+                             h=np.random.default_rng(5).normal(0, 0.05, 480) if site else 0.04)
 
     def make(run):
         return ihmc.DenseChains(ctx, model, [run]) if dense else ihmc.Chains(ctx, [model], [run])
@@ -278,8 +287,12 @@ def test_checkpoint_resume_and_form_mismatch(ctx, dense):
 def test_refusals(ctx):
     from paper_1912_03278_amd import ihmc
     site = ihmc.Lattice((16, 16), beta=0.4, C=4.1, h=np.full(256, 0.01))
-    with pytest.raises(ihmc.IhmcError):
-        ctx.run_lattice(site, ihmc.Run(n_md=4, n_traj=1, form=ihmc.FORM_SHIFTED))
+    with pytest.raises(ihmc.IhmcError):  # flips with a nonzero per-site field
+        ctx.run_lattice(site, ihmc.Run(n_md=4, n_traj=2, flip_every=1, form=ihmc.FORM_SHIFTED))
+    sv = ihmc.Server(ctx, budget_bytes=1 << 20, max_active=2)
+    with pytest.raises(ihmc.IhmcError):  # served requests: h = 0 or uniform only
+        sv.submit(site, ihmc.Run(n_md=4, n_traj=1, form=ihmc.FORM_SHIFTED))
+    sv.close()
     uni = ihmc.Lattice((16, 16), beta=0.4, C=4.1, h=0.01)
     with pytest.raises(ihmc.IhmcError):
         ctx.run_lattice(uni, ihmc.Run(n_md=4, n_traj=2, flip_every=1, form=ihmc.FORM_SHIFTED))
