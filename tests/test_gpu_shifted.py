@@ -45,6 +45,8 @@ CASES = [
     ("2d_tiles_ragged", (130, 35), 0.44, 4.1, -0.02),
     ("3d_ragged", (67, 9, 6), 0.22, 6.1, 0.05),
     ("3d_small_wrap", (5, 3, 7), 0.3, 6.5, 0.1),
+    ("2d_smallest", (3, 3), 0.4, 4.1, 0.1),
+    ("3d_smallest", (3, 3, 3), 0.2, 6.1, "site"),
     ("2d_site_h", (33, 17), 0.5, 4.1, "site"),
     ("3d_site_h", (20, 6, 9), 0.25, 6.1, "site"),
 ]
@@ -282,6 +284,17 @@ def test_checkpoint_resume_and_form_mismatch(ctx, dense, site):
     with pytest.raises(ihmc.IhmcError):
         other.restore(0, blob)
     other.close()
+
+
+def test_no_trajectories(ctx):
+    """n_traj = 0: empty series, the summary of nothing, the starting field back."""
+    from paper_1912_03278_amd import ihmc
+    psi0 = np.random.default_rng(1).standard_normal(120)
+    for h in (0.05, np.random.default_rng(2).normal(0, 0.1, 120)):
+        g = ctx.run_lattice(ihmc.Lattice((12, 10), beta=0.4, C=4.1, h=h),
+                            ihmc.Run(n_md=5, n_traj=0, precision=8, psi0=psi0, form=ihmc.FORM_SHIFTED))
+        assert g["n_traj_done"] == 0 and g["acceptance"] == 0.0 and len(g["dH"]) == 0
+        assert np.max(np.abs(g["psi_final"] - psi0)) < 1e-14
 
 
 def test_refusals(ctx):
