@@ -286,6 +286,25 @@ def test_checkpoint_resume_and_form_mismatch(ctx, dense, site):
     other.close()
 
 
+@pytest.mark.parametrize("h", ["uniform", "site"])
+def test_fp32_statistics_4x4(ctx, h):
+    """FP32 shifted-form chains are exact HMC: 4x4 at beta 0.4 against enumeration (4 sigma),
+    a uniform field (in-cosh operand) and a per-site one (translated coordinates)."""
+    from paper_1912_03278_amd import ihmc
+    from oracle import exact as E
+    from oracle import stats as S
+    hv = 0.1 if h == "uniform" else np.random.default_rng(6).normal(0.05, 0.1, 16)
+    ex = E.brute_force(E.torus_adjacency((4, 4)), 0.4, h=hv)
+    g = ctx.run_lattice(ihmc.Lattice((4, 4), beta=0.4, C=4.1, h=hv),
+                        ihmc.Run(n_md=10, n_traj=30000, precision=4, seed=3, form=ihmc.FORM_SHIFTED),
+                        want_psi=False)
+    for k, ref in (("beta_eps", ex["be"]), ("m", ex["m"]), ("m2c", ex["m2"])):
+        st = S.gamma_method(g[k][500:])
+        assert abs(st["mean"] - ref) < 4 * st["err"], (k, st, ref)
+    st = S.gamma_method(np.exp(-g["dH"][500:]))
+    assert abs(st["mean"] - 1) < 4 * st["err"]
+
+
 def test_no_trajectories(ctx):
     """n_traj = 0: empty series, the summary of nothing, the starting field back."""
     from paper_1912_03278_amd import ihmc
