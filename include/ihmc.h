@@ -146,9 +146,8 @@ typedef struct {
  *               expectations given phi (m = mean tanh(h' + phi), m^2 and beta*eps
  *               likewise, no bias correction needed).  IHMC_FORM_SHIFTED: psi0
  *               is the starting psi of that form (NULL: the TAG_INIT normals);
- *               flips at h != 0 give IHMC_E_INVAL; the server runs psi chains
- *               and shifted chains with h = 0 or a uniform field (a per-site
- *               field there: IHMC_E_UNSUPPORTED), not phi ones. */
+ *               flips at h != 0 give IHMC_E_INVAL; the server runs psi and
+ *               shifted chains (any field), not phi ones. */
 typedef struct {
   int32_t n_md;
   int32_t n_traj;
@@ -357,7 +356,7 @@ int ihmc_cancel(ihmc_server* server, uint64_t ticket);
  * *bytes bytes (buf NULL: *bytes = the size needed, the largest the request
  * can take; a smaller buffer fails with IHMC_E_INVAL).  On success *bytes = the
  * bytes written.  The checkpoint holds the request (lattice, field, run
- * parameters, given initial field, replayed decisions) and, once it has run,
+ * parameters with the form, given initial field, replayed decisions) and, once it has run,
  * its chain's state after a whole number of trajectories: the accepted field,
  * S of it in exact fixed point, the estimator sums, the sign, the counters and
  * the records.  The momenta, accept and flip uniforms of later trajectories

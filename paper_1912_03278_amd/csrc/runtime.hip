@@ -1662,9 +1662,14 @@ extern "C" int ihmc_copy_bandwidth(ihmc_ctx* ctx, uint64_t bytes, int32_t reps, 
 }
 
 namespace ihmc {
-hipError_t launch_init_psi(const ChainDev* d_cd, int ci, const double* psi0, int64_t N, int precision, hipStream_t s) {
-  if (precision == 4) k_init_psi<float><<<nblk(N), 256, 0, s>>>(d_cd, ci, psi0, nullptr);
-  else k_init_psi<double><<<nblk(N), 256, 0, s>>>(d_cd, ci, psi0, nullptr);
+hipError_t launch_init_psi(const ChainDev* d_cd, int ci, const double* psi0, int64_t N, int precision, hipStream_t s,
+                           const double* shift) {
+  if (precision == 4) k_init_psi<float><<<nblk(N), 256, 0, s>>>(d_cd, ci, psi0, shift);
+  else k_init_psi<double><<<nblk(N), 256, 0, s>>>(d_cd, ci, psi0, shift);
+  return hipGetLastError();
+}
+hipError_t launch_scale(double* x, int64_t n, double by, hipStream_t s) {
+  k_scale<<<nblk(n), 256, 0, s>>>(x, n, by);
   return hipGetLastError();
 }
 hipError_t launch_field_setup(const ChainDev* d_cd, int ci, const double* h, double beta, int64_t N, int precision,

@@ -17,7 +17,9 @@ int set_error(int code, const char* fmt, ...);
 int hip_fail(ihmc_ctx* ctx, hipError_t e, const char* where);
 
 // Set-up launchers shared by the lattice and dense runtimes (runtime.hip).
-hipError_t launch_init_psi(const ChainDev* d_cd, int ci, const double* psi0, int64_t N, int precision, hipStream_t s);
+hipError_t launch_init_psi(const ChainDev* d_cd, int ci, const double* psi0, int64_t N, int precision, hipStream_t s,
+                           const double* shift = nullptr);
+hipError_t launch_scale(double* x, int64_t n, double by, hipStream_t s);  // x /= by
 hipError_t launch_zero_state(ChainState* st, hipStream_t s);
 // Point c.part / c.gsum / c.gcnt into `block` (partials_bytes(c.n_tiles) bytes)
 // and clear the group counters.

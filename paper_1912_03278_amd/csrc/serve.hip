@@ -62,6 +62,12 @@ struct Request {
   bool ckpt_wanted = false;  // a checkpoint is asked for at the next round boundary
   bool ckpt_ready = false;
   std::vector<char> ckpt;    // the chain checkpoint taken by the scheduler
+  // A shifted-form request with a per-site field runs in coordinates
+  // translated by delta = Kt^-1 h'/sqrt(J') (as a chain set does): delta in the
+  // logical layout and the action offset h'.Kt^-1 h'/(2J'), applied at fetch.
+  std::vector<double> delta;
+  double s_off = 0.0;
+  const double* dshift = nullptr;  // device delta during the set-up
 };
 
 static inline uint64_t r256(uint64_t b) { return (b + 255ull) & ~255ull; }
@@ -89,7 +95,7 @@ static uint64_t request_bytes(const ihmc_lattice& l, const ihmc_run& r, int cls)
 // run, its chain checkpoint (chain_checkpoint's format).  A request restored
 // from it continues where the checkpoint was taken, bit for bit.
 constexpr char kSrvMagic[8] = {'I', 'H', 'M', 'C', 'S', 'R', 'V', 'C'};
-constexpr uint32_t kSrvVersion = 1;
+constexpr uint32_t kSrvVersion = 2;  // 2: the run's form
 struct SrvHeader {
   char magic[8];
   uint32_t version, header_bytes;
@@ -102,6 +108,7 @@ struct SrvHeader {
   uint64_t seed, chain_id;
   int64_t psi0_len, replay_len;
   uint64_t chain_bytes;
+  int32_t form, pad;
 };
 
 static uint64_t served_prefix_bytes(const Request* r) {
@@ -127,6 +134,7 @@ static void served_write(const Request* r, const std::vector<char>& chain, std::
   h.flip_every = r->run.flip_every;
   h.precision = r->run.precision;
   h.n_therm = r->run.n_therm;
+  h.form = r->run.form;
   h.seed = r->run.seed;
   h.chain_id = r->run.chain_id;
   h.psi0_len = (int64_t)r->psi0.size();
@@ -458,6 +466,7 @@ bool ihmc_server::admit_setup(std::vector<Request*>& fresh) {
       cg_off.push_back(cg_total);
       cg_total += 4 * c.N;
     }
+    const bool translated = r->run.form == FORM_SHIFTED && c.h_kind == 2;
     if (e == hipSuccess) {
       const double* src = nullptr;
       if (!r->psi0.empty()) {
@@ -466,7 +475,9 @@ bool ihmc_server::admit_setup(std::vector<Request*>& fresh) {
         if (e == hipSuccess) e = hipMemcpyAsync(t, r->psi0.data(), 8 * c.N, hipMemcpyHostToDevice, s);
         src = t;
       }
-      if (e == hipSuccess) e = launch_init_psi(d_cd, r->slot, src, c.N, c.precision, s);
+      // a translated request's field starts after the CG below, with delta added
+      if (e == hipSuccess && !translated) e = launch_init_psi(d_cd, r->slot, src, c.N, c.precision, s);
+      if (translated) r->dshift = src;  // the staged psi0 (or null), for the later start
     }
     if (e != hipSuccess) break;
     ok.push_back(r);
@@ -479,6 +490,18 @@ bool ihmc_server::admit_setup(std::vector<Request*>& fresh) {
     if (e == hipSuccess) e = hipMemcpyAsync(which, cg_slots.data(), sizeof(int) * cg_slots.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(woff, cg_off.data(), sizeof(int64_t) * cg_off.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_field_cg(d_cd, which, (int)cg_slots.size(), work, woff, s);
+    // translated requests: delta = x / sqrt(J') (x = Kt^-1 h' of the CG), then
+    // the starting field psi0 + delta, as a chain set starts it
+    for (Request* r : ok) {
+      if (e != hipSuccess) break;
+      if (!(r->run.form == FORM_SHIFTED && r->cd.h_kind == 2)) continue;
+      size_t j = 0;
+      while (j < cg_slots.size() && cg_slots[j] != r->slot) ++j;
+      double* x = work + cg_off[j];
+      e = launch_scale(x, r->cd.N, r->cd.sqJ, s);
+      if (e == hipSuccess) e = launch_init_psi(d_cd, r->slot, r->dshift, r->cd.N, r->cd.precision, s, x);
+      r->dshift = x;
+    }
   }
   if (e == hipSuccess && !ok.empty()) {
     std::vector<int> slots;
@@ -495,6 +518,16 @@ bool ihmc_server::admit_setup(std::vector<Request*>& fresh) {
     }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  for (Request* r : ok) {  // translated requests: delta and the action offset to the host
+    if (e != hipSuccess) break;
+    if (!(r->run.form == FORM_SHIFTED && r->cd.h_kind == 2)) continue;
+    r->delta.resize((size_t)r->cd.N);
+    e = hipMemcpy(r->delta.data(), r->dshift, 8 * (uint64_t)r->cd.N, hipMemcpyDeviceToHost);
+    double ce = 0.0;
+    if (e == hipSuccess) e = hipMemcpy(&ce, &d_cd[r->slot].c_e, sizeof ce, hipMemcpyDeviceToHost);
+    r->s_off = ce / (2.0 * r->cd.Jp);
+    r->dshift = nullptr;
+  }
   for (void* p : temps) ctx->arena.release(p);
   if (e == hipSuccess) resume_requests(ok);
   if (e != hipSuccess) {
@@ -719,8 +752,6 @@ extern "C" int ihmc_submit(ihmc_server* sv, const ihmc_lattice* lat, const ihmc_
   int rc = validate(*lat, *run, 0);
   if (rc) return rc;
   if (run->form == FORM_PHI) return set_error(IHMC_E_UNSUPPORTED, "the server runs psi-form or shifted-form chains");
-  if (run->form == FORM_SHIFTED && lat->h_len > 1)
-    return set_error(IHMC_E_UNSUPPORTED, "served shifted-form requests take h = 0 or a uniform field");
   Request* r = new (std::nothrow) Request();
   if (!r) return set_error(IHMC_E_NOMEM, "host allocation failed");
   r->lat = *lat;
@@ -819,6 +850,7 @@ extern "C" int ihmc_restore(ihmc_server* sv, const void* buf, uint64_t bytes, ui
   r->run.flip_every = h.flip_every;
   r->run.precision = h.precision;
   r->run.n_therm = h.n_therm;
+  r->run.form = h.form;
   r->run.seed = h.seed;
   r->run.chain_id = h.chain_id;
   const char* in = (const char*)buf + sizeof h;
@@ -833,8 +865,6 @@ extern "C" int ihmc_restore(ihmc_server* sv, const void* buf, uint64_t bytes, ui
   int rc = validate(r->lat, r->run, 0);
   if (!rc && r->run.form == FORM_PHI)
     rc = set_error(IHMC_E_UNSUPPORTED, "the server runs psi-form or shifted-form chains");
-  if (!rc && r->run.form == FORM_SHIFTED && r->lat.h_len > 1)
-    rc = set_error(IHMC_E_UNSUPPORTED, "served shifted-form requests take h = 0 or a uniform field");
   const int64_t N = rc ? 0 : lattice_sites(r->lat);
   if (!rc && ((h.psi0_len != 0 && h.psi0_len != N) || (h.replay_len != 0 && h.replay_len != h.n_traj)))
     rc = set_error(IHMC_E_INVAL, "served checkpoint is inconsistent");
@@ -902,8 +932,8 @@ extern "C" int ihmc_fetch(ihmc_server* sv, uint64_t ticket, ihmc_result* out, do
   for (int t = 0; t < done; ++t) {
     const TrajRecord& q = r->rec[t];
     if (out->dH) out->dH[t] = q.dH;
-    if (out->H_old) out->H_old[t] = q.H_old;
-    if (out->H_new) out->H_new[t] = q.H_new;
+    if (out->H_old) out->H_old[t] = q.H_old + r->s_off;
+    if (out->H_new) out->H_new[t] = q.H_new + r->s_off;
     if (out->m) out->m[t] = q.m;
     if (out->abs_m) out->abs_m[t] = q.abs_m;
     if (out->m2c) out->m2c[t] = q.m2c;
@@ -918,7 +948,11 @@ extern "C" int ihmc_fetch(ihmc_server* sv, uint64_t ticket, ihmc_result* out, do
   out->mean_exp_minus_dH = nf > 0 ? r->st.sum_exp_mdh / (double)nf : 0.0;
   out->n_nonfinite = r->st.n_nonfinite;
   out->cg_iterations = r->st.n_cg;
-  if (out->psi_final && !r->psi.empty()) std::memcpy(out->psi_final, r->psi.data(), 8 * r->psi.size());
+  if (out->psi_final && !r->psi.empty()) {
+    std::memcpy(out->psi_final, r->psi.data(), 8 * r->psi.size());
+    if (r->delta.size() == r->psi.size())  // a translated request: back to its own coordinates
+      for (size_t k = 0; k < r->psi.size(); ++k) out->psi_final[k] -= r->delta[k];
+  }
   delete r;
   return rc;
 }

@@ -242,7 +242,8 @@ def _same(a, b, keys=("dH", "H_old", "H_new", "m", "abs_m", "m2c", "beta_eps", "
     assert a["acceptance"] == b["acceptance"]
 
 
-@pytest.mark.parametrize("case", ["2d_tiled_site_field", "3d_flips_f64", "2d_resident_omelyan"])
+@pytest.mark.parametrize("case", ["2d_tiled_site_field", "3d_flips_f64", "2d_resident_omelyan",
+                                  "2d_shifted_site_field", "3d_shifted_uniform"])
 def test_checkpoint_running_request_and_resume_elsewhere(ctx, case):
     """Kill-and-resume by ticket: checkpoint a running request, cancel it (as a
     killed server would lose it), restore the checkpoint into another server on
@@ -256,9 +257,15 @@ def test_checkpoint_running_request_and_resume_elsewhere(ctx, case):
     elif case == "3d_flips_f64":
         lat = ihmc.Lattice((20, 18, 21), beta=0.25, C=6.1, h=0.03)
         run = ihmc.Run(n_md=5, n_traj=40, precision=ihmc.F64, seed=5, chain_id=2, flip_every=3)
-    else:
+    elif case == "2d_resident_omelyan":
         lat = ihmc.Lattice((30, 30), beta=0.44, C=4.1)
         run = ihmc.Run(n_md=3, n_traj=400, precision=ihmc.F32, seed=5, chain_id=3, integrator=ihmc.OMELYAN)
+    elif case == "2d_shifted_site_field":  # the shifted form's per-site field: translated coordinates
+        lat = ihmc.Lattice((72, 64), beta=0.42, C=4.1, h=rng.normal(0, 0.05, 72 * 64))
+        run = ihmc.Run(n_md=6, n_traj=40, precision=ihmc.F64, seed=5, chain_id=4, form=ihmc.FORM_SHIFTED)
+    else:
+        lat = ihmc.Lattice((18, 16, 20), beta=0.24, C=6.1, h=0.04)
+        run = ihmc.Run(n_md=5, n_traj=40, precision=ihmc.F32, seed=5, chain_id=5, form=ihmc.FORM_SHIFTED)
     whole = ctx.run_lattice(lat, run)
     sv = ihmc.Server(ctx, budget_bytes=64 << 20, max_active=4)
     t = sv.submit(lat, run)

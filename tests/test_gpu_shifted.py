@@ -221,19 +221,23 @@ def test_dense_shifted_alone_equals_mixed_bitwise(ctx):
 
 
 def test_served_shifted_requests_equal_alone(ctx):
-    """Served shifted and paper-form requests (2D/3D, FP32/FP64, fields) equal the same
-    chains run alone, bit for bit."""
+    """Served shifted and paper-form requests (2D/3D, FP32/FP64, uniform and per-site
+    fields, flips at h = 0, Omelyan) equal the same chains run alone, bit for bit."""
     import time
     from paper_1912_03278_amd import ihmc
     reqs = []
-    for i in range(12):
+    rng = np.random.default_rng(9)
+    for i in range(14):
         L = (24 + 4 * i, 20) if i % 3 else (8, 6, 5 + i)
-        lat = ihmc.Lattice(L, beta=0.4 if len(L) == 2 else 0.22, C=4.1 if len(L) == 2 else 6.1,
-                           h=0.02 * (i % 4) if i % 4 else None)
+        h = 0.02 * (i % 4) if i % 4 else None
+        if i >= 12:  # per-site fields: translated coordinates
+            L = (70 + 10 * i, 40)
+            h = rng.normal(0, 0.05, L[0] * L[1])
+        lat = ihmc.Lattice(L, beta=0.4 if len(L) == 2 else 0.22, C=4.1 if len(L) == 2 else 6.1, h=h)
         reqs.append((lat, ihmc.Run(n_md=4 + i % 5, n_traj=6, seed=3, chain_id=i, precision=8 if i % 2 else 4,
-                                   integrator=i % 2 if i % 4 == 3 else 0, flip_every=2 if i % 4 == 0 else 0,
+                                   integrator=i % 2 if i % 4 == 3 else 0, flip_every=2 if i % 4 == 0 and i < 12 else 0,
                                    form=ihmc.FORM_SHIFTED if i % 4 != 1 else ihmc.FORM_PSI)))
-    sv = ihmc.Server(ctx, budget_bytes=4 << 20, max_active=6)
+    sv = ihmc.Server(ctx, budget_bytes=8 << 20, max_active=6)
     tickets = []
     for k, (lat, run) in enumerate(reqs):
         tickets.append(sv.submit(lat, run))
@@ -246,7 +250,7 @@ def test_served_shifted_requests_equal_alone(ctx):
     sv.close()
     for (lat, run), g in zip(reqs, served):
         alone = ctx.run_lattice(lat, run)
-        for k in ("dH", "m", "beta_eps", "psi_final", "accepted", "flipped"):
+        for k in ("dH", "H_old", "H_new", "m", "beta_eps", "psi_final", "accepted", "flipped"):
             assert np.array_equal(g[k], alone[k]), (lat.L, k)
 
 
@@ -322,8 +326,8 @@ def test_refusals(ctx):
     with pytest.raises(ihmc.IhmcError):  # flips with a nonzero per-site field
         ctx.run_lattice(site, ihmc.Run(n_md=4, n_traj=2, flip_every=1, form=ihmc.FORM_SHIFTED))
     sv = ihmc.Server(ctx, budget_bytes=1 << 20, max_active=2)
-    with pytest.raises(ihmc.IhmcError):  # served requests: h = 0 or uniform only
-        sv.submit(site, ihmc.Run(n_md=4, n_traj=1, form=ihmc.FORM_SHIFTED))
+    with pytest.raises(ihmc.IhmcError):  # flips at h != 0, served
+        sv.submit(site, ihmc.Run(n_md=4, n_traj=2, flip_every=1, form=ihmc.FORM_SHIFTED))
     sv.close()
     uni = ihmc.Lattice((16, 16), beta=0.4, C=4.1, h=0.01)
     with pytest.raises(ihmc.IhmcError):
